@@ -1,0 +1,159 @@
+/*
+ * cutbddc: BDDC-preconditioned conjugate gradients for unfitted (cut-cell)
+ * Q1 finite elements on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Badia, F. Verdugo, "Robust and scalable domain decomposition
+ * solvers for unfitted finite element methods" (arXiv:1703.06323).
+ *   - Problem: find u in V-bar with A-bar u = b, A-bar = sum_e A_e (Sect. 2.2),
+ *     strong Dirichlet data on the mesh-aligned boundary (Sect. 5.1).
+ *   - Domain: Omega = {phi > 0}, phi(x) = min_i(|x - c_i| - r_i) on the unit
+ *     cube (level-set geometry, Sect. 2.1); background mesh of N^3 cells.
+ *   - Subdomains: aggregation of active cells in uniform s^3 blocks (Sect. 2.1).
+ *   - Preconditioner: M = I0 A0^-1 I0^T + Q A~^-1 Q^T, Q = E W (eq. bddc),
+ *     coarse DOFs = object means (eq. coarse-dofs), BDDC(cef) or BDDC(ce),
+ *     topological (eq. weighting) or stiffness (eq. alge-weighting) weights,
+ *     standard objects (Sect. 3.2) or variant 1 (cut coarse edges split,
+ *     Sect. 4.4).
+ *   - Solver: PCG with |r|_2 < rtol |b|_2 (Sect. 5.1).
+ *
+ * Conventions for every entry point:
+ *   - Return value: CB_OK (0) on success, a negative CB_ERR_* code on
+ *     failure; cb_last_error() then gives a message (thread-local).  No
+ *     exception crosses this interface and no entry point exits the process.
+ *   - Pointers named *_dev are device pointers (HBM) owned by the caller; the
+ *     library never frees or keeps them after the call returns.  Host inputs
+ *     are copied before the call returns.
+ *   - All device work runs on the HIP stream given to cb_setup; calls that
+ *     return host values synchronise that stream.
+ *   - Grid layouts: cells are numbered i + N (j + N k), grid nodes
+ *     I + (N+1)(J + (N+1) K) with x fastest.  DOF vectors hold the active
+ *     interior nodes in ascending node order (cb_info.n_dof entries).
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CUTBDDC_H
+#define CUTBDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum cb_status {
+  CB_OK = 0,
+  CB_ERR_ARG = -1,             /* invalid argument (sizes, options, NaN/<=0 kappa)     */
+  CB_ERR_SINGULAR = -2,        /* an active component touches no Dirichlet node        */
+  CB_ERR_NOT_SPD = -3,         /* a local or coarse Cholesky met a non-positive pivot  */
+  CB_ERR_NO_CONVERGENCE = -4,  /* max_iter reached; best iterate returned              */
+  CB_ERR_DEVICE = -5,          /* a HIP runtime call failed                            */
+  CB_ERR_STATE = -6,           /* call out of order (e.g. solve before factor)         */
+  CB_ERR_OOM = -7              /* device allocation failed                             */
+};
+
+enum cb_weighting { CB_W_CARDINALITY = 0, CB_W_STIFFNESS = 1 };
+enum cb_objects { CB_OBJ_CEF = 0, CB_OBJ_CE = 1 };
+enum cb_variant { CB_CV_STANDARD = 0, CB_CV_V1 = 1 };
+enum cb_precision { CB_FP64 = 0, CB_FP32_LOCAL = 1 };
+
+typedef struct {
+  int32_t n_cells;             /* N: background cells per axis on [0,1]^3, h = 1/N       */
+  int32_t sub_cells;           /* s: subdomain block size in cells; must divide N        */
+  int32_t n_balls;             /* number of balls removed from the cube (may be 0)       */
+  const double* ball_centres;  /* host, [n_balls * 3] (x, y, z per ball)                  */
+  const double* ball_radii;    /* host, [n_balls], > 0                                    */
+  const double* kappa;         /* host, [N^3] per-cell conductivity > 0, or NULL (= 1)    */
+  int32_t weighting;           /* cb_weighting                                            */
+  int32_t objects;             /* cb_objects                                              */
+  int32_t coarse_variant;      /* cb_variant                                              */
+  int32_t local_precision;     /* cb_precision: subdomain factor/solves in FP64 or FP32   */
+  int32_t full_elements;       /* test flag: integrate every active cell as uncut         */
+} cb_problem;
+
+typedef struct {
+  int64_t n_dof;               /* active interior nodes (unknowns)                        */
+  int64_t n_active;            /* active cells                                            */
+  int64_t n_cut;               /* cut cells                                               */
+  int32_t n_sub;               /* subdomains (m^3, empty blocks included)                 */
+  int32_t n_coarse;            /* coarse DOFs                                             */
+  int32_t n_objects;           /* interface objects (selected or not)                     */
+  int32_t n_iface;             /* interface DOFs                                          */
+  int32_t max_local_dofs;      /* largest n_omega                                         */
+  int32_t max_coarse_per_sub;  /* largest number of coarse DOFs touching one subdomain    */
+  int32_t n_fp64_fallbacks;    /* FP32-local subdomains refactored in FP64                */
+  int32_t factored;            /* 1 once cb_factor succeeded                              */
+  double t_integrate_ms;       /* last phase times (HIP events + host clock)              */
+  double t_topology_ms;
+  double t_factor_ms;
+  double t_solve_ms;
+} cb_info;
+
+typedef struct cb_ctx cb_ctx;
+
+/* Classify cells and integrate cut cells (Sect. 2.1-2.2), number DOFs,
+ * build subdomains, objects and coarse DOFs (Sect. 3.1-3.2, 4.4).
+ * `stream` is a hipStream_t (NULL = default stream).  On success *out owns
+ * all device buffers of the problem; release it with cb_destroy.
+ * Errors: CB_ERR_ARG (N < 1, s does not divide N, bad option, radius <= 0,
+ * kappa <= 0 or not finite), CB_ERR_SINGULAR (floating active component),
+ * CB_ERR_DEVICE / CB_ERR_OOM. */
+int cb_setup(const cb_problem* p, void* stream, cb_ctx** out);
+
+/* Sub-assemble the local Neumann matrices (Sect. 3.1), compute weights
+ * (eq. weighting / eq. alge-weighting), factor the local Dirichlet and
+ * constrained Neumann problems, the coarse basis and the coarse matrix
+ * (Sect. 3.3-3.4).  Errors: CB_ERR_STATE, CB_ERR_NOT_SPD, CB_ERR_DEVICE. */
+int cb_factor(cb_ctx* c);
+
+/* b = M_cut f (Q1 source with nodal values f on all (N+1)^3 grid nodes,
+ * f_nodes_dev == NULL means f = 1), then PCG with M from x0 = 0 until
+ * |r|_2 < rtol |b|_2 (Sect. 5.1).  u_dev: [n_dof] device output.
+ * *iters = operator applies, *final_relres = |r|/|b| of the recursive
+ * residual.  CB_ERR_NO_CONVERGENCE leaves the last iterate in u_dev. */
+int cb_solve(cb_ctx* c, const double* f_nodes_dev, double* u_dev, double rtol,
+             int32_t max_iter, int32_t* iters, double* final_relres);
+
+/* Same PCG for an explicit right-hand side b_dev: [n_dof] (adjoint solves). */
+int cb_solve_rhs(cb_ctx* c, const double* b_dev, double* u_dev, double rtol,
+                 int32_t max_iter, int32_t* iters, double* final_relres);
+
+/* Adjoint contraction for J(u) with dJ/du = A-bar lambda and kappa = exp(theta):
+ * dJ_dtheta_dev[e] = -kappa_e lambda_e^T K_e u_e (per cell, 0 if inactive),
+ * dJ_df_dev = M_cut^T lambda over all grid nodes.  Inputs [n_dof]. */
+int cb_grad(cb_ctx* c, const double* u_dev, const double* lam_dev,
+            double* dJ_dtheta_dev, double* dJ_df_dev);
+
+/* Building blocks exposed for parity testing.  All vectors [n_dof], device. */
+int cb_apply_operator(cb_ctx* c, const double* x_dev, double* y_dev);       /* y = A-bar x  */
+int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev); /* z = M r      */
+int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev);           /* b = M_cut f  */
+
+int cb_query(const cb_ctx* c, cb_info* out);
+
+/* Host copies of the integer data of the discretisation (bit-exact parity).
+ * Each output pointer may be NULL; sizes come from cb_query / cb_export_sizes.
+ *  cell_status [N^3]      0 inactive, 1 cut, 2 interior
+ *  cell_count  [N^3]      kept points per cell
+ *  dof_node    [n_dof]    grid node of each DOF
+ *  card        [n_dof]    |S(xi)|: number of subdomains containing the DOF
+ *  obj_ptr     [n_objects+1], obj_dofs [n_iface]: DOFs per object (ascending)
+ *  obj_type    [n_objects] 0 corner, 1 edge, 2 face
+ *  coarse_of_obj [n_objects] coarse id or -1 */
+int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_count,
+                       int64_t* dof_node, int32_t* card, int64_t* obj_ptr,
+                       int64_t* obj_dofs, int8_t* obj_type, int32_t* coarse_of_obj);
+
+/* Cut-cell reference matrices (kappa = 1, h = 1), host copies, packed upper
+ * triangles row by row (36 values each), cut cells in ascending cell order:
+ * K [n_cut*36], M [n_cut*36], cut_cells [n_cut]. */
+int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_cells);
+
+/* Dense coarse matrix A_c [n_coarse^2] (row-major, host) after cb_factor. */
+int cb_export_coarse(const cb_ctx* c, double* Ac);
+
+const char* cb_last_error(void);
+void cb_destroy(cb_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUTBDDC_H */

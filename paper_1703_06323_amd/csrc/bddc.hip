@@ -1,0 +1,506 @@
+// BDDC kernels (paper Sect. 3.1-3.4 and 4.3): sub-assembly of the local
+// Neumann matrices, weights, coarse basis, coarse matrix assembly and the
+// pieces of the preconditioner apply M r.
+//
+// Local layout per subdomain omega (padded to NIp + NGp rows): interior DOFs
+// first (rows [0, nI)), interface DOFs at rows [NIp, NIp + nG); padding rows
+// carry the identity.  The constrained Neumann problem is posed on the
+// augmented matrix K = A_omega + C^T R C with R = diag(rho_lambda),
+// rho_lambda = sum of A_omega's diagonal over lambda: on the constraint
+// subspace C v = 0 it equals A_omega, so its constrained inverse is that of
+// A_omega.  K is Jacobi scaled before the Cholesky factorisation.
+//
+// With L the Cholesky factor of K ([I; G] ordering), L_II factors A_II and
+// L_GG the Schur complement K_S = S_A + C^T R C of K on the interface
+// (S_A the Schur complement of A_omega).  The apply uses
+//   P   = A_II^{-1}                          (Dirichlet solves, E and I0 A0^-1 I0^T)
+//   G   = K_S^{-1} C^T,  S_c = C G,  Phi = G S_c^{-1}   (coarse basis on the interface)
+//   Kt  = K_S^{-1} - Phi G^T                  (constrained Neumann solve on the interface)
+//   A_c^omega = Phi^T S_A Phi = S_c^{-1} - R  (local coarse matrix)
+#include "bddc.h"
+
+#pragma clang fp contract(off)
+
+namespace cutbddc {
+namespace {
+
+__constant__ double c_Kref_b[64];
+
+// Kernel 1: per subdomain, unscaled diagonal of A_omega, rho per coarse
+// object, Jacobi scaling, and the scaled padded matrix K.
+template <typename T>
+__global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat,
+                                                             double* diagA_G, double* Dscale) {
+  extern __shared__ double smem[];
+  const int w = blockIdx.x;
+  const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
+  double* diag = smem;              // [nt]
+  double* Ds = smem + nt;           // [nt]
+  double* rho = smem + 2 * nt;      // [NCp]
+  double* cnt = rho + NCp;          // [NCp]
+  const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
+  const int s = g.s, m = g.N / g.s, N = g.N;
+  const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
+  const int64_t N1 = N + 1;
+  const int s1 = s + 1;
+  const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
+  T* K = Kmat + (int64_t)w * nt * nt;
+  const int tid = threadIdx.x;
+
+  auto row_node = [&](int r) -> int64_t {
+    if (r < NIp) return r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+    const int j = r - NIp;
+    return j < nG ? sd.G_idx[(int64_t)w * NGp + j] : -1;
+  };
+  // phase 0: diagonal of A_omega
+  for (int r = tid; r < nt; r += 256) {
+    const int64_t n = row_node(r);
+    double d = 0.0;
+    if (n >= 0) {
+      const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
+      const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
+      for (int u = 0; u < 8; ++u) {
+        const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+        if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+        const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
+        const int32_t info = g.cellinfo[c];
+        if (info == CELL_INACTIVE) continue;
+        const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+        const double kaa = info == CELL_UNCUT ? c_Kref_b[a * 9] : g.Kc[(int64_t)info * PACK36 + pack_index(a, a)];
+        d += g.kappa[c] * g.h * kaa;
+      }
+    }
+    diag[r] = d;
+    if (r >= NIp) diagA_G[(int64_t)w * NGp + (r - NIp)] = d;
+  }
+  __syncthreads();
+  // phase 1: rho_t = sum of the diagonal over object t, |t|
+  for (int t = tid; t < NCp; t += 256) {
+    double sr = 0.0, sc = 0.0;
+    if (t < nC)
+      for (int j = 0; j < nG; ++j)
+        if (sd.G_obj[(int64_t)w * NGp + j] == t) {
+          sr += diag[NIp + j];
+          sc += 1.0;
+        }
+    rho[t] = sr;
+    cnt[t] = sc;
+  }
+  __syncthreads();
+  for (int r = tid; r < nt; r += 256) {
+    const int64_t n = row_node(r);
+    double dk = diag[r];
+    if (r >= NIp && n >= 0) {
+      const int t = sd.G_obj[(int64_t)w * NGp + (r - NIp)];
+      if (t >= 0) dk += rho[t] / (cnt[t] * cnt[t]);
+    }
+    Ds[r] = n >= 0 ? 1.0 / sqrt(dk) : 1.0;
+    Dscale[(int64_t)w * nt + r] = Ds[r];
+  }
+  __syncthreads();
+  // phase 2: zero, then write scaled entries (row r owned by one thread)
+  for (int64_t e = tid; e < (int64_t)nt * nt; e += 256) K[e] = T(0);
+  __syncthreads();
+  for (int r = tid; r < nt; r += 256) {
+    const int64_t n = row_node(r);
+    T* Kr = K + (int64_t)r * nt;
+    if (n < 0) {
+      Kr[r] = T(1);
+      continue;
+    }
+    const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
+    const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
+    for (int u = 0; u < 8; ++u) {
+      const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+      if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+      const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
+      const int32_t info = g.cellinfo[c];
+      if (info == CELL_INACTIVE) continue;
+      const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+      const double sc = g.kappa[c] * g.h;
+      for (int b = 0; b < 8; ++b) {
+        const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
+        const int col = loc[bx + s1 * (by + s1 * bz)];
+        if (col < 0) continue;
+        const double kab = info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
+        Kr[col] = (T)((double)Kr[col] + sc * kab * Ds[r] * Ds[col]);
+      }
+    }
+    if (r >= NIp) {
+      const int t = sd.G_obj[(int64_t)w * NGp + (r - NIp)];
+      if (t >= 0) {
+        const double add = rho[t] / (cnt[t] * cnt[t]);
+        for (int j = 0; j < nG; ++j)
+          if (sd.G_obj[(int64_t)w * NGp + j] == t)
+            Kr[NIp + j] = (T)((double)Kr[NIp + j] + add * Ds[r] * Ds[NIp + j]);
+      }
+    }
+  }
+}
+
+// Kernel 2: weights per interface DOF, summed over its subdomains in
+// ascending order: stiffness A^w_xx / sum A^w'_xx, or 1/|S(x)|.
+__global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_ptr,
+                               const int32_t* __restrict__ if_sub, const int32_t* __restrict__ if_slot,
+                               int NGp, const double* __restrict__ diagA_G, int stiffness,
+                               double* __restrict__ Dw) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_iface) return;
+  const int64_t b = if_ptr[q], e = if_ptr[q + 1];
+  double tot = 0.0;
+  for (int64_t z = b; z < e; ++z) tot += diagA_G[(int64_t)if_sub[z] * NGp + if_slot[z]];
+  for (int64_t z = b; z < e; ++z) {
+    const int64_t k = (int64_t)if_sub[z] * NGp + if_slot[z];
+    Dw[k] = stiffness ? diagA_G[k] / tot : 1.0 / (double)(e - b);
+  }
+}
+
+// Kernel 3: per subdomain, from KS = K_S^{-1} (full, unscaled, FP64):
+// G = KS C^T, S_c = C G, S_c^{-1}, Phi = G S_c^{-1}, A_c^w = S_c^{-1} - R.
+__global__ __launch_bounds__(256) void coarse_local_kernel(SubDev sd, const double* __restrict__ KS,
+                                                           const double* __restrict__ diagA_G,
+                                                           double* __restrict__ Gm, double* __restrict__ Phi,
+                                                           double* __restrict__ AcLoc, int* info) {
+  extern __shared__ double smem[];
+  const int w = blockIdx.x;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  const int nG = sd.nG[w], nC = sd.nC[w];
+  double* Sc = smem;                  // [NCp*NCp]
+  double* rho = Sc + NCp * NCp;       // [NCp]
+  double* cnt = rho + NCp;            // [NCp]
+  const int tid = threadIdx.x;
+  const int* obj = sd.G_obj + (int64_t)w * NGp;
+  const double* ks = KS + (int64_t)w * NGp * NGp;
+  double* g = Gm + (int64_t)w * NGp * NCp;
+  double* phi = Phi + (int64_t)w * NGp * NCp;
+  for (int t = tid; t < NCp; t += 256) {
+    double sr = 0.0, sc = 0.0;
+    if (t < nC)
+      for (int j = 0; j < nG; ++j)
+        if (obj[j] == t) {
+          sr += diagA_G[(int64_t)w * NGp + j];
+          sc += 1.0;
+        }
+    rho[t] = sr;
+    cnt[t] = sc;
+  }
+  // G[i][t] = (1/|t|) sum_{j in t} KS[i][j]  (rows i owned by one thread)
+  for (int i = tid; i < NGp; i += 256)
+    for (int t = 0; t < NCp; ++t) g[(int64_t)i * NCp + t] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < NGp; i += 256) {
+    if (i >= nG) continue;
+    for (int j = 0; j < nG; ++j) {
+      const int t = obj[j];
+      if (t >= 0) g[(int64_t)i * NCp + t] += ks[(int64_t)i * NGp + j];
+    }
+    for (int t = 0; t < nC; ++t) g[(int64_t)i * NCp + t] /= cnt[t];
+  }
+  __syncthreads();
+  // S_c[t][u] = (1/|t|) sum_{j in t} G[j][u]
+  for (int e = tid; e < NCp * NCp; e += 256) Sc[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < NCp * NCp; e += 256) {
+    const int t = e / NCp, u = e % NCp;
+    if (t >= nC || u >= nC) {
+      if (t == u) Sc[e] = 1.0;
+      continue;
+    }
+    double acc = 0.0;
+    for (int j = 0; j < nG; ++j)
+      if (obj[j] == t) acc += g[(int64_t)j * NCp + u];
+    Sc[e] = acc / cnt[t];
+  }
+  __syncthreads();
+  // in-place Gauss-Jordan inverse of the SPD matrix S_c (no pivoting needed)
+  __shared__ double piv;
+  for (int k = 0; k < NCp; ++k) {
+    if (tid == 0) {
+      double p = Sc[k * NCp + k];
+      if (!(p > 0.0) && info) atomicMax(info, 1);
+      piv = (p > 0.0) ? p : 1.0;
+    }
+    __syncthreads();
+    const double p = piv;
+    // row k scaled
+    for (int j = tid; j < NCp; j += 256)
+      if (j != k) Sc[k * NCp + j] /= p;
+    __syncthreads();
+    for (int e = tid; e < NCp * NCp; e += 256) {
+      const int i = e / NCp, j = e % NCp;
+      if (i == k || j == k) continue;
+      Sc[e] -= Sc[i * NCp + k] * Sc[k * NCp + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < NCp; i += 256)
+      if (i != k) Sc[i * NCp + k] = -Sc[i * NCp + k] / p;
+    __syncthreads();
+    if (tid == 0) Sc[k * NCp + k] = 1.0 / p;
+    __syncthreads();
+  }
+  // Phi = G S_c^{-1}
+  for (int i = tid; i < NGp; i += 256)
+    for (int u = 0; u < NCp; ++u) {
+      double acc = 0.0;
+      if (i < nG && u < nC)
+        for (int t = 0; t < nC; ++t) acc += g[(int64_t)i * NCp + t] * Sc[t * NCp + u];
+      phi[(int64_t)i * NCp + u] = acc;
+    }
+  // A_c^w = S_c^{-1} - R (restricted to the nC x nC block)
+  for (int e = tid; e < NCp * NCp; e += 256) {
+    const int t = e / NCp, u = e % NCp;
+    double v = 0.0;
+    if (t < nC && u < nC) v = Sc[e] - (t == u ? rho[t] : 0.0);
+    AcLoc[(int64_t)w * NCp * NCp + e] = v;
+  }
+}
+
+// Kernel 4: coarse matrix row c = sum over the subdomains touching coarse
+// DOF c (ascending) of the matching row of A_c^w.
+__global__ void coarse_assemble_kernel(int nc, int ldc, const int64_t* __restrict__ cs_ptr,
+                                       const int32_t* __restrict__ cs_sub, const int32_t* __restrict__ cs_row,
+                                       SubDev sd, const double* __restrict__ AcLoc, double* __restrict__ Ac) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ldc) return;
+  double* row = Ac + (int64_t)c * ldc;   // zero-filled by the caller
+  if (c >= nc) {
+    row[c] = 1.0;
+    return;
+  }
+  const int NCp = sd.NCp;
+  for (int64_t z = cs_ptr[c]; z < cs_ptr[c + 1]; ++z) {
+    const int w = cs_sub[z], t = cs_row[z];
+    const int nC = sd.nC[w];
+    const double* src = AcLoc + ((int64_t)w * NCp + t) * NCp;
+    const int32_t* ids = sd.C_ids + (int64_t)w * NCp;
+    for (int u = 0; u < nC; ++u) row[ids[u]] += src[u];
+  }
+}
+
+// ---- apply ----------------------------------------------------------------
+
+// out[node(I_idx)] = P_w * (a - b)[I_idx]  (b may be null), per subdomain.
+// One workgroup per (subdomain, row chunk); each wave reduces one row at a time.
+template <typename TM>
+__global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM* __restrict__ P,
+                                                             const double* __restrict__ a,
+                                                             const double* __restrict__ b,
+                                                             double* __restrict__ out, int rows_per_block) {
+  extern __shared__ double xs[];
+  const int w = blockIdx.y;
+  const int NIp = sd.NIp;
+  const int nI = sd.nI[w];
+  const int64_t* idx = sd.I_idx + (int64_t)w * NIp;
+  for (int j = threadIdx.x; j < NIp; j += 256) {
+    double v = 0.0;
+    if (j < nI) {
+      const int64_t n = idx[j];
+      v = a[n] - (b ? b[n] : 0.0);
+    }
+    xs[j] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(nI, r0 + rows_per_block);
+  const TM* Pw = P + (int64_t)w * NIp * NIp;
+  for (int r = r0 + wv; r < r1; r += 4) {
+    const TM* row = Pw + (int64_t)r * NIp;
+    double acc = 0.0;
+    for (int j = lane; j < nI; j += 64) acc += (double)row[j] * xs[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) out[idx[r]] = acc;
+  }
+}
+
+// z_w = Kt_w g_w with g_w[j] = Dw[j] (r - t)[G_idx[j]]; cloc_w = Phi_w^T g_w.
+template <typename TM>
+__global__ __launch_bounds__(256) void apply_neumann_kernel(SubDev sd, const TM* __restrict__ Kt,
+                                                            const double* __restrict__ Phi,
+                                                            const double* __restrict__ Dw,
+                                                            const double* __restrict__ r,
+                                                            const double* __restrict__ t,
+                                                            double* __restrict__ z, double* __restrict__ cloc,
+                                                            int rows_per_block) {
+  extern __shared__ double gs[];
+  const int w = blockIdx.y;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  const int nG = sd.nG[w], nC = sd.nC[w];
+  const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
+  for (int j = threadIdx.x; j < NGp; j += 256) {
+    double v = 0.0;
+    if (j < nG) {
+      const int64_t n = idx[j];
+      v = Dw[(int64_t)w * NGp + j] * (r[n] - t[n]);
+    }
+    gs[j] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(nG, r0 + rows_per_block);
+  const TM* Kw = Kt + (int64_t)w * NGp * NGp;
+  for (int i = r0 + wv; i < r1; i += 4) {
+    const TM* row = Kw + (int64_t)i * NGp;
+    double acc = 0.0;
+    for (int j = lane; j < nG; j += 64) acc += (double)row[j] * gs[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) z[(int64_t)w * NGp + i] = acc;
+  }
+  if (blockIdx.x == 0) {
+    const double* ph = Phi + (int64_t)w * NGp * NCp;
+    for (int u = threadIdx.x; u < NCp; u += 256) {
+      double acc = 0.0;
+      if (u < nC)
+        for (int j = 0; j < nG; ++j) acc += ph[(int64_t)j * NCp + u] * gs[j];
+      cloc[(int64_t)w * NCp + u] = acc;
+    }
+  }
+}
+
+__global__ void coarse_rhs_kernel(int nc, const int64_t* __restrict__ cs_ptr, const int32_t* __restrict__ cs_sub,
+                                  const int32_t* __restrict__ cs_row, int NCp, const double* __restrict__ cloc,
+                                  double* __restrict__ c) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  double acc = 0.0;
+  for (int64_t z = cs_ptr[q]; z < cs_ptr[q + 1]; ++z) acc += cloc[(int64_t)cs_sub[z] * NCp + cs_row[z]];
+  c[q] = acc;
+}
+
+// y = A x for one dense n x n matrix (ld), one wave per row.
+__global__ __launch_bounds__(256) void gemv_kernel(int n, int ld, const double* __restrict__ A,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  const double* row = A + (int64_t)r * ld;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += row[j] * x[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[r] = acc;
+}
+
+// u~_w[j] = z_w[j] + sum_t Phi_w[j][t] u_c[C_ids[t]]  (in place in z)
+__global__ __launch_bounds__(256) void add_coarse_kernel(SubDev sd, const double* __restrict__ Phi,
+                                                         const double* __restrict__ uc, double* __restrict__ z) {
+  extern __shared__ double ul[];
+  const int w = blockIdx.x;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  const int nG = sd.nG[w], nC = sd.nC[w];
+  for (int t = threadIdx.x; t < NCp; t += 256) ul[t] = t < nC ? uc[sd.C_ids[(int64_t)w * NCp + t]] : 0.0;
+  __syncthreads();
+  const double* ph = Phi + (int64_t)w * NGp * NCp;
+  for (int j = threadIdx.x; j < nG; j += 256) {
+    double acc = z[(int64_t)w * NGp + j];
+    for (int t = 0; t < nC; ++t) acc += ph[(int64_t)j * NCp + t] * ul[t];
+    z[(int64_t)w * NGp + j] = acc;
+  }
+}
+
+// u_G[node] = sum over the DOF's subdomains (ascending) of Dw u~_w.
+__global__ void iface_average_kernel(int64_t n_iface, const int64_t* __restrict__ iface_node,
+                                     const int64_t* __restrict__ if_ptr, const int32_t* __restrict__ if_sub,
+                                     const int32_t* __restrict__ if_slot, int NGp,
+                                     const double* __restrict__ Dw, const double* __restrict__ z,
+                                     double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_iface) return;
+  double acc = 0.0;
+  for (int64_t e = if_ptr[q]; e < if_ptr[q + 1]; ++e) {
+    const int64_t k = (int64_t)if_sub[e] * NGp + if_slot[e];
+    acc += Dw[k] * z[k];
+  }
+  out[iface_node[q]] = acc;
+}
+
+}  // namespace
+
+void bddc_set_reference(const double* Kref) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_Kref_b), Kref, 64 * sizeof(double));
+}
+
+template <typename T>
+void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
+                           double* diagA_G, double* Dscale) {
+  const int nt = sd.NIp + sd.NGp;
+  const size_t sh = (size_t)(2 * nt + 2 * sd.NCp) * sizeof(double);
+  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(256), sh, st, sd, g, K, diagA_G, Dscale);
+}
+template void launch_assemble_local<double>(hipStream_t, const SubDev&, const GridDev&, int, double*,
+                                            double*, double*);
+template void launch_assemble_local<float>(hipStream_t, const SubDev&, const GridDev&, int, float*,
+                                           double*, double*);
+
+void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
+                    const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw) {
+  if (n_iface <= 0) return;
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((n_iface + 255) / 256)), dim3(256), 0, st, n_iface,
+                     if_ptr, if_sub, if_slot, NGp, diagA_G, stiffness, Dw);
+}
+
+void launch_coarse_local(hipStream_t st, const SubDev& sd, int ns, const double* KS,
+                         const double* diagA_G, double* G, double* Phi, double* AcLoc, int* info) {
+  const size_t sh = (size_t)(sd.NCp * sd.NCp + 2 * sd.NCp) * sizeof(double);
+  hipLaunchKernelGGL(coarse_local_kernel, dim3(ns), dim3(256), sh, st, sd, KS, diagA_G, G, Phi, AcLoc,
+                     info);
+}
+
+void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,
+                            const int32_t* cs_row, const SubDev& sd, const double* AcLoc, double* Ac) {
+  hipLaunchKernelGGL(coarse_assemble_kernel, dim3((ldc + 63) / 64), dim3(64), 0, st, nc, ldc, cs_ptr, cs_sub,
+                     cs_row, sd, AcLoc, Ac);
+}
+
+template <typename TM>
+void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
+                           const double* b, double* out) {
+  const int rpb = 64;
+  dim3 grid((sd.NIp + rpb - 1) / rpb, ns);
+  hipLaunchKernelGGL(apply_interior_kernel<TM>, grid, dim3(256), sd.NIp * sizeof(double), st, sd, P, a, b,
+                     out, rpb);
+}
+template void launch_apply_interior<double>(hipStream_t, const SubDev&, int, const double*, const double*,
+                                            const double*, double*);
+template void launch_apply_interior<float>(hipStream_t, const SubDev&, int, const float*, const double*,
+                                           const double*, double*);
+
+template <typename TM>
+void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
+                          const double* Dw, const double* r, const double* t, double* z, double* cloc) {
+  const int rpb = 64;
+  dim3 grid((sd.NGp + rpb - 1) / rpb, ns);
+  hipLaunchKernelGGL(apply_neumann_kernel<TM>, grid, dim3(256), sd.NGp * sizeof(double), st, sd, Kt, Phi,
+                     Dw, r, t, z, cloc, rpb);
+}
+template void launch_apply_neumann<double>(hipStream_t, const SubDev&, int, const double*, const double*,
+                                           const double*, const double*, const double*, double*, double*);
+template void launch_apply_neumann<float>(hipStream_t, const SubDev&, int, const float*, const double*,
+                                          const double*, const double*, const double*, double*, double*);
+
+void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int32_t* cs_sub,
+                       const int32_t* cs_row, int NCp, const double* cloc, double* c) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(coarse_rhs_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, nc, cs_ptr, cs_sub, cs_row,
+                     NCp, cloc, c);
+}
+
+void launch_gemv(hipStream_t st, int n, int ld, const double* A, const double* x, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gemv_kernel, dim3((n + 3) / 4), dim3(256), 0, st, n, ld, A, x, y);
+}
+
+void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,
+                       double* z) {
+  hipLaunchKernelGGL(add_coarse_kernel, dim3(ns), dim3(256), sd.NCp * sizeof(double), st, sd, Phi, uc, z);
+}
+
+void launch_iface_average(hipStream_t st, int64_t n_iface, const int64_t* iface_node, const int64_t* if_ptr,
+                          const int32_t* if_sub, const int32_t* if_slot, int NGp, const double* Dw,
+                          const double* z, double* out) {
+  if (n_iface <= 0) return;
+  hipLaunchKernelGGL(iface_average_kernel, dim3((unsigned)((n_iface + 255) / 256)), dim3(256), 0, st,
+                     n_iface, iface_node, if_ptr, if_sub, if_slot, NGp, Dw, z, out);
+}
+
+}  // namespace cutbddc

@@ -1,0 +1,43 @@
+// Batched dense linear algebra (MFMA) used by the subdomain and coarse
+// factorisations.  All matrices are row-major; `s*` arguments are element
+// strides between consecutive matrices of a batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cutbddc {
+
+enum GemmMode {
+  GEMM_LOWER = 1,        // only output tiles/elements on or below the diagonal
+  GEMM_KFROM_DIAG = 2,   // K loop starts at max(row0, col0) (op(A) upper-zero in K)
+  GEMM_KTO_DIAG = 4      // K loop ends at row0 + 64 (op(A) lower triangular)
+};
+
+constexpr int CHOL_BLOCK = 32;
+
+// C = alpha op(A) op(B) + beta C; TA/TB = 0 plain, 1 transposed storage.
+template <typename T>
+void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
+          int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
+          int batch, int mode);
+
+// In-place lower Cholesky of n x n matrices (n a multiple of CHOL_BLOCK).
+// Linv receives the inverses of the diagonal tiles: sL >= (n/32)*32*32.
+template <typename T>
+void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv, int64_t sL,
+              int* info);
+
+// Y = inverse of the lower-triangular diagonal block [off, off+nb) of L,
+// using the diagonal-tile inverses written by cholesky().
+template <typename T>
+void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY);
+
+// out = D sym(lower(in)) D, full storage.
+template <typename T, typename TO>
+void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* out, int64_t ldo,
+                      int64_t sO, const double* D, int64_t sD, int nb, int batch);
+
+}  // namespace cutbddc

@@ -1,0 +1,319 @@
+// Batched dense linear algebra on CDNA4 matrix cores (MFMA), FP64 and FP32.
+//
+// Used for the subdomain Dirichlet and constrained-Neumann factorisations and
+// the coarse matrix: blocked right-looking Cholesky with 32-wide panels, a
+// triangular inverse by block forward substitution, and the product
+// Y^T Y that turns the inverse factor into the inverse.  Every kernel takes a
+// batch of equally sized, row-major matrices (stride between matrices) and
+// runs one workgroup per (tile, matrix), so the same code factors one large
+// coarse matrix or thousands of subdomain matrices.
+//
+// GEMM tile: 64 x 64 outputs per 256-thread workgroup, four 64-wide waves in
+// a 2 x 2 arrangement, each wave owning 2 x 2 MFMA 16x16 blocks; the K loop
+// stages 64 x 16 / 16 x 64 operand tiles in LDS.
+#include "dense.h"
+
+#include <hip/hip_runtime.h>
+
+namespace cutbddc {
+namespace {
+
+constexpr int TM = 64;    // output tile rows
+constexpr int TN = 64;    // output tile cols
+constexpr int KT = 16;    // K per LDS stage
+constexpr int BLK = 32;   // Cholesky panel width
+
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+  typedef double __attribute__((ext_vector_type(4))) type;
+  __device__ static type mfma(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Acc<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
+  __device__ static type mfma(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C
+//   TA = 0: A(i,k) = A[i*lda + k];  TA = 1: A(i,k) = A[k*lda + i]
+//   TB = 0: B(k,j) = B[k*ldb + j];  TB = 1: B(k,j) = B[j*ldb + k]
+template <typename T, int TA, int TB>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
+                                                   int64_t lda, int64_t sA, const T* __restrict__ B,
+                                                   int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
+                                                   int64_t sC, int mode) {
+  __shared__ T As[TM][KT + 1];
+  __shared__ T Bs[KT][TN + 1];
+  const int row0 = blockIdx.y * TM;
+  const int col0 = blockIdx.x * TN;
+  const int64_t bz = blockIdx.z;
+  if ((mode & GEMM_LOWER) && col0 > row0 + TM - 1) return;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  int kbeg = 0, kend = K;
+  if (mode & GEMM_KFROM_DIAG) kbeg = (max(row0, col0) / KT) * KT;
+  if (mode & GEMM_KTO_DIAG) kend = min(K, row0 + TM);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  typename Acc<T>::type acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    // stage A tile (TM x KT)
+    for (int e = tid; e < TM * KT; e += 256) {
+      int i, k;
+      if (TA == 0) { i = e / KT; k = e % KT; } else { k = e / TM; i = e % TM; }
+      const int gi = row0 + i, gk = k0 + k;
+      T v = 0;
+      if (gi < M && gk < kend) v = TA == 0 ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi];
+      As[i][k] = v;
+    }
+    for (int e = tid; e < KT * TN; e += 256) {
+      int k, j;
+      if (TB == 0) { k = e / TN; j = e % TN; } else { j = e / KT; k = e % KT; }
+      const int gj = col0 + j, gk = k0 + k;
+      T v = 0;
+      if (gj < N && gk < kend) v = TB == 0 ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk];
+      Bs[k][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const T a = As[wr * 32 + mi * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+          const T b = Bs[kk + (lane >> 4)][wc * 32 + ni * 16 + (lane & 15)];
+          acc[mi][ni] = Acc<T>::mfma(a, b, acc[mi][ni]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wr * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int gj = col0 + wc * 32 + ni * 16 + (lane & 15);
+        if (gi >= M || gj >= N) continue;
+        if ((mode & GEMM_LOWER) && gj > gi) continue;
+        T* c = C + (int64_t)gi * ldc + gj;
+        const T r = alpha * acc[mi][ni][v];
+        *c = (beta == T(0)) ? r : r + beta * (*c);
+      }
+}
+
+// Cholesky of the BLK x BLK diagonal tile at (k0, k0) of each matrix, in LDS.
+// Writes L (lower, upper part of the tile zeroed) and L^{-1} into
+// Linv[bz][tile][BLK*BLK].  A non-positive or non-finite pivot sets
+// info[bz] (first failing global row + 1) and is replaced by 1 so that the
+// factorisation continues without NaNs.
+template <typename T>
+__global__ __launch_bounds__(256) void potrf_tile_kernel(T* A, int64_t lda, int64_t sA, int k0,
+                                                         T* Linv, int64_t sL, int* info) {
+  __shared__ T L[BLK][BLK + 1];
+  __shared__ T X[BLK][BLK + 1];
+  const int64_t bz = blockIdx.x;
+  T* a = A + bz * sA + (int64_t)k0 * lda + k0;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BLK * BLK; e += 256) L[e / BLK][e % BLK] = a[(int64_t)(e / BLK) * lda + e % BLK];
+  __syncthreads();
+  for (int j = 0; j < BLK; ++j) {
+    if (tid == 0) {
+      T d = L[j][j];
+      if (!(d > T(0)) || !(d < T(3.0e38))) {
+        if (info && info[bz] == 0) info[bz] = k0 + j + 1;
+        d = T(1);
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const T piv = L[j][j];
+    for (int i = j + 1 + tid; i < BLK; i += 256) L[i][j] /= piv;
+    __syncthreads();
+    for (int e = tid; e < BLK * BLK; e += 256) {
+      const int i = e / BLK, l = e % BLK;
+      if (i > j && l > j && l <= i) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular tile: one column per thread
+  if (tid < BLK) {
+    const int c = tid;
+    for (int i = 0; i < BLK; ++i) {
+      T s = (i == c) ? T(1) : T(0);
+      for (int k = c; k < i; ++k) s -= L[i][k] * X[k][c];
+      X[i][c] = (i < c) ? T(0) : s / L[i][i];
+    }
+  }
+  __syncthreads();
+  T* li = Linv + bz * sL + (int64_t)(k0 / BLK) * BLK * BLK;
+  for (int e = tid; e < BLK * BLK; e += 256) {
+    const int i = e / BLK, l = e % BLK;
+    a[(int64_t)i * lda + l] = (l <= i) ? L[i][l] : T(0);
+    li[e] = X[i][l];
+  }
+}
+
+// Panel solve: rows r in [k0+BLK, n) of columns [k0, k0+BLK):
+// X = A_panel * L_kk^{-T}.  One workgroup per 64 rows.
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_panel_kernel(T* A, int64_t lda, int64_t sA, int n, int k0,
+                                                         const T* Linv, int64_t sL) {
+  __shared__ T P[64][BLK + 1];
+  __shared__ T Li[BLK][BLK + 1];
+  const int64_t bz = blockIdx.y;
+  const int r0 = k0 + BLK + blockIdx.x * 64;
+  T* a = A + bz * sA;
+  const T* li = Linv + bz * sL + (int64_t)(k0 / BLK) * BLK * BLK;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * BLK; e += 256) {
+    const int r = e / BLK, c = e % BLK;
+    P[r][c] = (r0 + r < n) ? a[(int64_t)(r0 + r) * lda + k0 + c] : T(0);
+  }
+  for (int e = tid; e < BLK * BLK; e += 256) Li[e / BLK][e % BLK] = li[e];
+  __syncthreads();
+  for (int e = tid; e < 64 * BLK; e += 256) {
+    const int r = e / BLK, j = e % BLK;
+    if (r0 + r >= n) continue;
+    T s = 0;
+    for (int c = 0; c <= j; ++c) s += P[r][c] * Li[j][c];
+    a[(int64_t)(r0 + r) * lda + k0 + j] = s;
+  }
+}
+
+// Copies the diagonal Linv tile into Y's diagonal block and zeroes the rest
+// of Y's block row to the right of it (Y is built in place block by block).
+template <typename T>
+__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int nb,
+                                                             int i0, const T* Linv, int64_t sL,
+                                                             int tile) {
+  const int64_t bz = blockIdx.x;
+  T* y = Y + bz * sY;
+  const T* li = Linv + bz * sL + (int64_t)tile * BLK * BLK;
+  for (int e = threadIdx.x; e < BLK * nb; e += 256) {
+    const int r = e / nb, c = e % nb;
+    if (c < i0) continue;
+    T v = 0;
+    if (c < i0 + BLK) v = li[r * BLK + (c - i0)];
+    y[(int64_t)(i0 + r) * ldy + c] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_kernel(T* Y, int64_t ldy, int64_t sY, int nb) {
+  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)blockIdx.x * ldy;
+  for (int c = threadIdx.x; c < nb; c += 256) y[c] = T(0);
+}
+
+// out (full symmetric, row-major nb x nb) = D * sym(lower(in)) * D
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void symmetrize_scale_kernel(const T* in, int64_t ldi, int64_t sI,
+                                                               TO* out, int64_t ldo, int64_t sO,
+                                                               const double* D, int64_t sD, int nb) {
+  const int64_t bz = blockIdx.y;
+  const int r = blockIdx.x;
+  const T* x = in + bz * sI;
+  TO* o = out + bz * sO;
+  const double* d = D + bz * sD;
+  for (int c = threadIdx.x; c < nb; c += 256) {
+    const T v = (c <= r) ? x[(int64_t)r * ldi + c] : x[(int64_t)c * ldi + r];
+    o[(int64_t)r * ldo + c] = (TO)((double)v * d[r] * d[c]);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
+          int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
+          int batch, int mode) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, batch);
+#define GEMM_CASE(a, b)                                                                          \
+  if (TA == a && TB == b) {                                                                      \
+    hipLaunchKernelGGL((gemm_kernel<T, a, b>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda,   \
+                       sA, B, ldb, sB, beta, C, ldc, sC, mode);                                  \
+    return;                                                                                      \
+  }
+  GEMM_CASE(0, 0) GEMM_CASE(0, 1) GEMM_CASE(1, 0) GEMM_CASE(1, 1)
+#undef GEMM_CASE
+}
+
+template <typename T>
+void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv, int64_t sL,
+              int* info) {
+  for (int k0 = 0; k0 < n; k0 += BLK) {
+    hipLaunchKernelGGL(potrf_tile_kernel<T>, dim3(batch), dim3(256), 0, st, A, lda, sA, k0, Linv,
+                       sL, info);
+    const int rest = n - k0 - BLK;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(trsm_panel_kernel<T>, dim3((rest + 63) / 64, batch), dim3(256), 0, st, A,
+                       lda, sA, n, k0, (const T*)Linv, sL);
+    T* panel = A + (int64_t)(k0 + BLK) * lda + k0;
+    T* trail = A + (int64_t)(k0 + BLK) * lda + (k0 + BLK);
+    gemm<T>(st, 0, 1, rest, rest, BLK, T(-1), panel, lda, sA, panel, lda, sA, T(1), trail, lda, sA,
+            batch, GEMM_LOWER);
+  }
+}
+
+template <typename T>
+void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY) {
+  // Y = L_block^{-1} for the diagonal block [off, off+nb) of L (lower).
+  // Y holds the running right-hand side R (block forward substitution on
+  // L Y = I): block row i becomes Linv_ii R_i, then later rows are updated.
+  hipLaunchKernelGGL(zero_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
+  for (int i0 = 0; i0 < nb; i0 += BLK) {
+    if (i0 > 0) {
+      // Y[i-block, 0:i0] = Linv_ii * Y[i-block, 0:i0]  (in place: each output
+      // tile reads only its own columns of the same block row)
+      const T* li = Linv + (int64_t)((off + i0) / BLK) * BLK * BLK;
+      gemm<T>(st, 0, 0, BLK, i0, BLK, T(1), li, BLK, sLi, Y + (int64_t)i0 * ldy, ldy, sY, T(0),
+              Y + (int64_t)i0 * ldy, ldy, sY, batch, 0);
+    }
+    hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(batch), dim3(256), 0, st, Y, ldy, sY, nb, i0,
+                       Linv, sLi, (off + i0) / BLK);
+    const int rest = nb - i0 - BLK;
+    if (rest <= 0) break;
+    // Y[l, 0:i0+BLK] -= L[l, i-block] * Y[i-block, 0:i0+BLK] for rows l below
+    const T* Lli = L + (int64_t)(off + i0 + BLK) * ldl + (off + i0);
+    gemm<T>(st, 0, 0, rest, i0 + BLK, BLK, T(-1), Lli, ldl, sL, Y + (int64_t)i0 * ldy, ldy, sY,
+            T(1), Y + (int64_t)(i0 + BLK) * ldy, ldy, sY, batch, 0);
+  }
+}
+
+template <typename T, typename TO>
+void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* out, int64_t ldo,
+                      int64_t sO, const double* D, int64_t sD, int nb, int batch) {
+  hipLaunchKernelGGL((symmetrize_scale_kernel<T, TO>), dim3(nb, batch), dim3(256), 0, st, in, ldi,
+                     sI, out, ldo, sO, D, sD, nb);
+}
+
+#define INST(T)                                                                                 \
+  template void gemm<T>(hipStream_t, int, int, int, int, int, T, const T*, int64_t, int64_t,    \
+                        const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int);         \
+  template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, T*, int64_t, int*);    \
+  template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, const T*, \
+                               int64_t, T*, int64_t, int64_t);
+INST(double)
+INST(float)
+#undef INST
+template void symmetrize_scale<double, double>(hipStream_t, const double*, int64_t, int64_t,
+                                               double*, int64_t, int64_t, const double*, int64_t,
+                                               int, int);
+template void symmetrize_scale<float, float>(hipStream_t, const float*, int64_t, int64_t, float*,
+                                             int64_t, int64_t, const double*, int64_t, int, int);
+template void symmetrize_scale<float, double>(hipStream_t, const float*, int64_t, int64_t, double*,
+                                              int64_t, int64_t, const double*, int64_t, int, int);
+
+}  // namespace cutbddc

@@ -1,0 +1,251 @@
+"""ctypes binding of libcutbddc.so (include/cutbddc.h).
+
+Argument marshalling only: every step of setup, factorisation and solve runs
+in the library's HIP kernels.  Device buffers are torch tensors on the GPU;
+the library reads and writes them through their data pointers on the
+current torch stream.  There is no CPU fallback: without the built library
+or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcutbddc.so")
+
+CB_OK = 0
+CB_ERR_ARG = -1
+CB_ERR_SINGULAR = -2
+CB_ERR_NOT_SPD = -3
+CB_ERR_NO_CONVERGENCE = -4
+CB_ERR_DEVICE = -5
+CB_ERR_STATE = -6
+CB_ERR_OOM = -7
+_NAMES = {0: "CB_OK", -1: "CB_ERR_ARG", -2: "CB_ERR_SINGULAR", -3: "CB_ERR_NOT_SPD",
+          -4: "CB_ERR_NO_CONVERGENCE", -5: "CB_ERR_DEVICE", -6: "CB_ERR_STATE", -7: "CB_ERR_OOM"}
+
+
+class CBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class cb_problem(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("sub_cells", C.c_int32), ("n_balls", C.c_int32),
+                ("ball_centres", C.POINTER(C.c_double)), ("ball_radii", C.POINTER(C.c_double)),
+                ("kappa", C.POINTER(C.c_double)), ("weighting", C.c_int32), ("objects", C.c_int32),
+                ("coarse_variant", C.c_int32), ("local_precision", C.c_int32),
+                ("full_elements", C.c_int32)]
+
+
+class cb_info(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_active", C.c_int64), ("n_cut", C.c_int64),
+                ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("n_objects", C.c_int32),
+                ("n_iface", C.c_int32), ("max_local_dofs", C.c_int32),
+                ("max_coarse_per_sub", C.c_int32), ("n_fp64_fallbacks", C.c_int32),
+                ("factored", C.c_int32), ("t_integrate_ms", C.c_double),
+                ("t_topology_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_1703_06323_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    lib.cb_setup.argtypes = [C.POINTER(cb_problem), vp, C.POINTER(vp)]
+    lib.cb_factor.argtypes = [vp]
+    lib.cb_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int32, ip, dp]
+    lib.cb_solve_rhs.argtypes = [vp, vp, vp, C.c_double, C.c_int32, ip, dp]
+    lib.cb_grad.argtypes = [vp, vp, vp, vp, vp]
+    lib.cb_apply_operator.argtypes = [vp, vp, vp]
+    lib.cb_apply_preconditioner.argtypes = [vp, vp, vp]
+    lib.cb_load.argtypes = [vp, vp, vp]
+    lib.cb_query.argtypes = [vp, C.POINTER(cb_info)]
+    lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
+    lib.cb_export_cut_matrices.argtypes = [vp, vp, vp, vp]
+    lib.cb_export_coarse.argtypes = [vp, vp]
+    lib.cb_last_error.restype = C.c_char_p
+    lib.cb_destroy.argtypes = [vp]
+    lib.cb_destroy.restype = None
+    for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
+                 "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
+                 "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow=()):
+    if rc != CB_OK and rc not in allow:
+        raise CBError(rc, _lib.cb_last_error().decode())
+    return rc
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """One cut-cube problem resident on the GPU.
+
+    `problem` needs the attributes n, s, centres (n_b x 3), radii (n_b),
+    kappa (n^3 or None), weighting, objects, coarse_variant,
+    local_precision and full_elements."""
+
+    def __init__(self, problem, stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("cutbddc needs a GPU")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        centres = np.ascontiguousarray(problem.centres, dtype=np.float64).reshape(-1)
+        radii = np.ascontiguousarray(problem.radii, dtype=np.float64)
+        kappa = None if problem.kappa is None else np.ascontiguousarray(problem.kappa, dtype=np.float64)
+        self._keep = (centres, radii, kappa)
+        P = C.POINTER(C.c_double)
+        p = cb_problem(int(problem.n), int(problem.s), int(radii.size),
+                       centres.ctypes.data_as(P), radii.ctypes.data_as(P),
+                       kappa.ctypes.data_as(P) if kappa is not None else None,
+                       int(problem.weighting), int(problem.objects), int(problem.coarse_variant),
+                       int(problem.local_precision), int(problem.full_elements))
+        st = torch.cuda.current_stream() if stream is None else stream
+        self.stream = st
+        ctx = C.c_void_p()
+        _check(lib.cb_setup(C.byref(p), C.c_void_p(st.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        self.n = int(problem.n)
+
+    def __del__(self):
+        if getattr(self, "ctx", None) and _lib is not None:
+            _lib.cb_destroy(self.ctx)
+            self.ctx = None
+
+    def close(self):
+        self.__del__()
+
+    # -- phases ------------------------------------------------------------
+    def factor(self):
+        _check(_lib.cb_factor(self.ctx))
+
+    def info(self) -> dict:
+        inf = cb_info()
+        _check(_lib.cb_query(self.ctx, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in cb_info._fields_}
+
+    @property
+    def n_dof(self) -> int:
+        return int(self.info()["n_dof"])
+
+    def _vec(self, n):
+        return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+
+    def _f64(self, t):
+        t = self.torch.as_tensor(t, dtype=self.torch.float64, device=self.device)
+        return t.contiguous()
+
+    def solve(self, f=None, rtol=1e-8, max_iter=1000, allow_no_convergence=False):
+        """Returns (u [n_dof] cuda tensor, iterations, relative residual)."""
+        u = self._vec(self.n_dof)
+        it = C.c_int32(0)
+        rel = C.c_double(0.0)
+        fv = None if f is None else self._f64(f)
+        rc = _lib.cb_solve(self.ctx, _dptr(fv), u.data_ptr(), float(rtol), int(max_iter),
+                           C.byref(it), C.byref(rel))
+        _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
+        return u, int(it.value), float(rel.value)
+
+    def solve_rhs(self, b, rtol=1e-8, max_iter=1000, allow_no_convergence=False):
+        bv = self._f64(b)
+        u = self._vec(self.n_dof)
+        it = C.c_int32(0)
+        rel = C.c_double(0.0)
+        rc = _lib.cb_solve_rhs(self.ctx, bv.data_ptr(), u.data_ptr(), float(rtol), int(max_iter),
+                               C.byref(it), C.byref(rel))
+        _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
+        return u, int(it.value), float(rel.value)
+
+    def grad(self, u, lam):
+        """(dJ/dtheta [n^3], dJ/df [(n+1)^3]) for the adjoint lam."""
+        dth = self._vec(self.n ** 3)
+        df = self._vec((self.n + 1) ** 3)
+        _check(_lib.cb_grad(self.ctx, self._f64(u).data_ptr(), self._f64(lam).data_ptr(),
+                            dth.data_ptr(), df.data_ptr()))
+        return dth, df
+
+    def apply_operator(self, x):
+        y = self._vec(self.n_dof)
+        _check(_lib.cb_apply_operator(self.ctx, self._f64(x).data_ptr(), y.data_ptr()))
+        return y
+
+    def apply_preconditioner(self, r):
+        z = self._vec(self.n_dof)
+        _check(_lib.cb_apply_preconditioner(self.ctx, self._f64(r).data_ptr(), z.data_ptr()))
+        return z
+
+    def load(self, f=None):
+        b = self._vec(self.n_dof)
+        fv = None if f is None else self._f64(f)
+        _check(_lib.cb_load(self.ctx, _dptr(fv), b.data_ptr()))
+        return b
+
+    # -- host exports --------------------------------------------------------
+    def export_indexing(self) -> dict:
+        inf = self.info()
+        n3 = self.n ** 3
+        out = {
+            "cell_status": np.zeros(n3, np.uint8),
+            "cell_count": np.zeros(n3, np.int32),
+            "dof_node": np.zeros(inf["n_dof"], np.int64),
+            "card": np.zeros(inf["n_dof"], np.int32),
+            "obj_ptr": np.zeros(inf["n_objects"] + 1, np.int64),
+            "obj_dofs": np.zeros(inf["n_iface"], np.int64),
+            "obj_type": np.zeros(inf["n_objects"], np.int8),
+            "coarse_of_obj": np.zeros(inf["n_objects"], np.int32),
+        }
+        args = [out[k].ctypes.data_as(C.c_void_p) for k in
+                ("cell_status", "cell_count", "dof_node", "card", "obj_ptr", "obj_dofs",
+                 "obj_type", "coarse_of_obj")]
+        _check(_lib.cb_export_indexing(self.ctx, *args))
+        return out
+
+    def export_cut_matrices(self):
+        n = int(self.info()["n_cut"])
+        K = np.zeros((max(n, 1), 36))
+        M = np.zeros((max(n, 1), 36))
+        cells = np.zeros(max(n, 1), np.int64)
+        _check(_lib.cb_export_cut_matrices(self.ctx, K.ctypes.data_as(C.c_void_p),
+                                           M.ctypes.data_as(C.c_void_p),
+                                           cells.ctypes.data_as(C.c_void_p)))
+        return K[:n], M[:n], cells[:n]
+
+    def export_coarse(self) -> np.ndarray:
+        nc = int(self.info()["n_coarse"])
+        A = np.zeros((nc, nc))
+        _check(_lib.cb_export_coarse(self.ctx, A.ctypes.data_as(C.c_void_p)))
+        return A
+
+
+def unpack36(P: np.ndarray) -> np.ndarray:
+    """(n, 36) packed upper triangles -> (n, 8, 8) symmetric matrices."""
+    out = np.zeros(P.shape[:-1] + (8, 8))
+    k = 0
+    for a in range(8):
+        for b in range(a, 8):
+            out[..., a, b] = P[..., k]
+            out[..., b, a] = P[..., k]
+            k += 1
+    return out

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars: bit-exact for the integer data (cell classification, DOF numbering,
+subdomain sets, objects, coarse numbering); relative 1e-13 for cut-cell
+matrices, operator and load (same arithmetic up to summation order); 1e-10
+for the FP64 preconditioner, coarse matrix and PCG solution at rtol 1e-8
+(both sides run the same PCG from x0 = 0 with the same stopping rule, so the
+iterates differ only by rounding; iteration counts may differ by one when the
+residual lands at the threshold); 1e-6 for the FP32-local path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+try:  # first import of torch on a fresh box is slow: do it at collection time
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+import workloads as W
+from oracle import OracleSolver, topology
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "single_ball_standard_cardinality": lambda: W.single_ball().with_options(weighting=0, coarse_variant=0),
+    "single_ball_standard_stiffness": lambda: W.single_ball().with_options(coarse_variant=0),
+    "single_ball_v1_stiffness": lambda: W.single_ball(),
+    "balls16_s4": lambda: W.random_balls(16, 4, 6, 3),
+    "balls24_s8_lognormal": lambda: W.random_balls(24, 8, 8, 4, lognormal_kappa=True),
+    "balls32_s8_ce": lambda: W.random_balls(32, 8, 12, 9).with_options(objects=1),
+    "uncut16_s4": lambda: W.uncut(16, 4),
+    "one_subdomain": lambda: W.random_balls(8, 8, 3, 5),
+    "full_elements": lambda: W.random_balls(16, 8, 5, 6).with_options(full_elements=1),
+}
+
+_oracles = {}
+_gpus = {}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle(name):
+    if name not in _oracles:
+        _oracles[name] = OracleSolver(CASES[name]())
+    return _oracles[name]
+
+
+def gpu(name):
+    from paper_1703_06323_amd import Solver
+    if name not in _gpus:
+        say(f"[gpu] setup+factor {name}")
+        s = Solver(CASES[name]())
+        s.factor()
+        _gpus[name] = s
+    return _gpus[name]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_indexing_bit_exact(name):
+    o = oracle(name)
+    g = gpu(name).export_indexing()
+    assert np.array_equal(g["cell_count"], o.d.count)
+    assert np.array_equal(g["cell_status"], o.d.status)
+    assert np.array_equal(g["dof_node"], o.d.dof_node)
+    assert np.array_equal(g["card"], o.topo.card())
+    assert np.array_equal(g["obj_ptr"], o.topo.obj_ptr)
+    assert np.array_equal(g["obj_dofs"], o.topo.obj_dofs)
+    assert np.array_equal(g["obj_type"], o.topo.obj_type)
+    assert np.array_equal(g["coarse_of_obj"], o.topo.coarse_of_obj)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cut_cell_matrices(name):
+    from paper_1703_06323_amd.cutbddc import unpack36
+    o = oracle(name)
+    K, M, cells = gpu(name).export_cut_matrices()
+    if CASES[name]().full_elements:
+        assert cells.size == 0
+        return
+    assert np.array_equal(cells, o.d.cut)
+    pos = np.searchsorted(o.d.active, cells)
+    Ko = o.d.Kunit[pos]
+    Mo = o.d.Munit[pos]
+    np.testing.assert_allclose(unpack36(K), Ko, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(unpack36(M), Mo, rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_and_load(name):
+    o = oracle(name)
+    s = gpu(name)
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal(o.n_dof)
+    say(f"[gpu] apply_operator {name}")
+    y = s.apply_operator(x).cpu().numpy()
+    assert rel(y, o.d.A @ x) < 1e-13
+    p = CASES[name]()
+    say(f"[gpu] load {name}")
+    b = s.load(p.f).cpu().numpy()
+    assert rel(b, o.rhs()) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_matrix(name):
+    o = oracle(name)
+    if o.topo.n_coarse == 0:
+        return
+    Ac = gpu(name).export_coarse()
+    assert rel(Ac, o.M.Ac) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_apply(name):
+    o = oracle(name)
+    s = gpu(name)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(o.n_dof)
+    say(f"[gpu] apply_preconditioner {name}")
+    z = s.apply_preconditioner(r).cpu().numpy()
+    assert rel(z, o.M.apply(r)) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64(name):
+    o = oracle(name)
+    s = gpu(name)
+    p = CASES[name]()
+    say(f"[gpu] solve {name}")
+    u, it, relres = s.solve(p.f, rtol=1e-8)
+    x, it_o, rel_o = o.solve(rtol=1e-8)
+    assert relres < 1e-8
+    assert abs(it - it_o) <= 1, (it, it_o)
+    assert rel(u.cpu().numpy(), x) < 1e-10
+
+
+def test_solve_fp32_local():
+    p = W.random_balls(24, 8, 8, 4, lognormal_kappa=True).with_options(local_precision=1)
+    from paper_1703_06323_amd import Solver
+    say("[gpu] fp32-local balls24")
+    s = Solver(p)
+    s.factor()
+    u, it, relres = s.solve(p.f, rtol=1e-8)
+    o = oracle("balls24_s8_lognormal")
+    x, it_o, _ = o.solve(rtol=1e-8)
+    assert relres < 1e-8
+    assert rel(u.cpu().numpy(), x) < 1e-6
+    assert abs(it - it_o) <= 3
+
+
+def test_zero_rhs_and_iteration_cap():
+    import torch
+    s = gpu("single_ball_v1_stiffness")
+    say("[gpu] zero rhs")
+    u, it, relres = s.solve_rhs(torch.zeros(s.n_dof, dtype=torch.float64))
+    assert it == 0 and float(u.abs().max()) == 0.0
+    from paper_1703_06323_amd.cutbddc import CBError, CB_ERR_NO_CONVERGENCE
+    say("[gpu] max_iter=1")
+    with pytest.raises(CBError) as e:
+        s.solve(rtol=1e-14, max_iter=1)
+    assert e.value.code == CB_ERR_NO_CONVERGENCE
+
+
+def test_invalid_arguments_rejected():
+    from paper_1703_06323_amd import Solver
+    from paper_1703_06323_amd.cutbddc import CBError, CB_ERR_ARG, CB_ERR_SINGULAR
+    say("[gpu] invalid arguments")
+    with pytest.raises(CBError) as e:
+        Solver(W.uncut(10, 4))
+    assert e.value.code == CB_ERR_ARG
+    bad = W.uncut(8, 4)
+    bad.kappa = -np.ones(512)
+    with pytest.raises(CBError) as e:
+        Solver(bad)
+    assert e.value.code == CB_ERR_ARG
+    rng = np.random.default_rng(0)
+    dirs = rng.standard_normal((400, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pocket = W.Problem(n=16, s=4, centres=0.5 + 0.3 * dirs, radii=np.full(400, 0.12))
+    with pytest.raises(CBError) as e:
+        Solver(pocket)
+    assert e.value.code == CB_ERR_SINGULAR
