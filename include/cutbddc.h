@@ -73,6 +73,7 @@ typedef struct {
   int64_t n_dof;               /* active interior nodes (unknowns)                        */
   int64_t n_active;            /* active cells                                            */
   int64_t n_cut;               /* cut cells                                               */
+  int64_t n_cut_stored;        /* cut cells with stored matrices (0 with full_elements)   */
   int32_t n_sub;               /* subdomains (m^3, empty blocks included)                 */
   int32_t n_coarse;            /* coarse DOFs                                             */
   int32_t n_objects;           /* interface objects (selected or not)                     */
@@ -144,11 +145,18 @@ int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_coun
 
 /* Cut-cell reference matrices (kappa = 1, h = 1), host copies, packed upper
  * triangles row by row (36 values each), cut cells in ascending cell order:
- * K [n_cut*36], M [n_cut*36], cut_cells [n_cut]. */
+ * K [n_cut_stored*36], M [n_cut_stored*36], cut_cells [n_cut_stored]. */
 int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_cells);
 
 /* Dense coarse matrix A_c [n_coarse^2] (row-major, host) after cb_factor. */
 int cb_export_coarse(const cb_ctx* c, double* Ac);
+
+/* Batched SPD inverse building block used by the local and coarse
+ * factorisations (blocked Cholesky, triangular inverse, Y^T Y on MFMA):
+ * Ainv[b] = A[b]^{-1} for `batch` row-major n x n host matrices, computed on
+ * the device in FP64 (precision 0) or FP32 (precision 1).  Synchronous; the
+ * default stream.  CB_ERR_NOT_SPD if a pivot is not positive. */
+int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv);
 
 const char* cb_last_error(void);
 void cb_destroy(cb_ctx* c);

@@ -301,6 +301,50 @@ extern "C" {
 
 const char* cb_last_error(void) { return g_err.c_str(); }
 
+int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv) {
+  if (n < 1 || batch < 1 || !A || !Ainv || precision < 0 || precision > 1)
+    return fail(CB_ERR_ARG, "invalid argument");
+  const int np = round_up(n, CHOL_BLOCK);
+  const size_t nn = (size_t)np * np;
+  std::vector<double> h((size_t)batch * nn, 0.0);
+  for (int b = 0; b < batch; ++b)
+    for (int i = 0; i < np; ++i)
+      for (int j = 0; j < np; ++j)
+        h[b * nn + (size_t)i * np + j] = (i < n && j < n) ? A[(size_t)b * n * n + (size_t)i * n + j] : (i == j ? 1.0 : 0.0);
+  auto run = [&](auto tag) -> int {
+    using T = decltype(tag);
+    std::vector<T> ht(h.begin(), h.end());
+    DevBuf dA, dL, dY, dP, dOut, dOnes, dInfo;
+    CHK(upload(dA, ht, nullptr));
+    const int nt = np / CHOL_BLOCK;
+    CHK(dalloc(dL, (size_t)batch * nt * CHOL_BLOCK * CHOL_BLOCK * sizeof(T)));
+    CHK(dalloc(dY, (size_t)batch * nn * sizeof(T)));
+    CHK(dalloc(dP, (size_t)batch * nn * sizeof(T)));
+    CHK(dalloc(dOut, (size_t)batch * nn * sizeof(double)));
+    CHK(upload(dOnes, std::vector<double>((size_t)batch * np, 1.0), nullptr));
+    CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
+    const int64_t sL = (int64_t)nt * CHOL_BLOCK * CHOL_BLOCK;
+    cholesky<T>(nullptr, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>());
+    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, batch, dL.as<T>(), sL, dY.as<T>(), np, nn);
+    gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
+            GEMM_LOWER | GEMM_KFROM_DIAG);
+    symmetrize_scale<T, double>(nullptr, dP.as<T>(), np, nn, dOut.as<double>(), np, nn, dOnes.as<double>(), np, np,
+                                batch);
+    HIPCHK(hipGetLastError());
+    std::vector<double> out((size_t)batch * nn);
+    HIPCHK(hipMemcpy(out.data(), dOut.p, out.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int> info(batch);
+    HIPCHK(hipMemcpy(info.data(), dInfo.p, batch * sizeof(int), hipMemcpyDeviceToHost));
+    for (int b = 0; b < batch; ++b)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ainv[(size_t)b * n * n + (size_t)i * n + j] = out[b * nn + (size_t)i * np + j];
+    for (int b = 0; b < batch; ++b)
+      if (info[b]) return fail(CB_ERR_NOT_SPD, "Cholesky breakdown in matrix " + std::to_string(b));
+    return CB_OK;
+  };
+  return precision == CB_FP32_LOCAL ? run(float(0)) : run(double(0));
+}
+
 int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) {
   if (!p || !out) return fail(CB_ERR_ARG, "null argument");
   *out = nullptr;
@@ -478,6 +522,7 @@ int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) {
   c->info.n_dof = t.n_dof;
   c->info.n_active = c->n_active;
   c->info.n_cut = c->n_cut;
+  c->info.n_cut_stored = (int64_t)c->cut_cells.size();
   c->info.n_sub = ns;
   c->info.n_coarse = t.n_coarse;
   c->info.n_objects = (int32_t)t.obj_type.size();

@@ -24,17 +24,23 @@ constexpr int KT = 16;    // K per LDS stage
 constexpr int BLK = 32;   // Cholesky panel width
 
 template <typename T> struct Acc;
+// Operand layouts of the 16x16x4 MFMAs (both types): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Output element v of lane l is
+// D[row(l, v)][l % 16], where the row mapping differs between the FP64 and
+// FP32 instructions (measured on gfx950).
 template <> struct Acc<double> {
   typedef double __attribute__((ext_vector_type(4))) type;
   __device__ static type mfma(double a, double b, type c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 template <> struct Acc<float> {
   typedef float __attribute__((ext_vector_type(4))) type;
   __device__ static type mfma(float a, float b, type c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 // C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = row0 + wr * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int gi = row0 + wr * 32 + mi * 16 + Acc<T>::row(lane, v);
         const int gj = col0 + wc * 32 + ni * 16 + (lane & 15);
         if (gi >= M || gj >= N) continue;
         if ((mode & GEMM_LOWER) && gj > gi) continue;

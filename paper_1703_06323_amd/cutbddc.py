@@ -45,6 +45,7 @@ class cb_problem(C.Structure):
 
 class cb_info(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_active", C.c_int64), ("n_cut", C.c_int64),
+                ("n_cut_stored", C.c_int64),
                 ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("n_objects", C.c_int32),
                 ("n_iface", C.c_int32), ("max_local_dofs", C.c_int32),
                 ("max_coarse_per_sub", C.c_int32), ("n_fp64_fallbacks", C.c_int32),
@@ -77,12 +78,14 @@ def load_library(path: str = LIB_PATH):
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
     lib.cb_export_cut_matrices.argtypes = [vp, vp, vp, vp]
     lib.cb_export_coarse.argtypes = [vp, vp]
+    lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
     lib.cb_last_error.restype = C.c_char_p
     lib.cb_destroy.argtypes = [vp]
     lib.cb_destroy.restype = None
     for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
-                 "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse"):
+                 "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
+                 "cb_dense_spd_inverse"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -223,7 +226,7 @@ class Solver:
         return out
 
     def export_cut_matrices(self):
-        n = int(self.info()["n_cut"])
+        n = int(self.info()["n_cut_stored"])
         K = np.zeros((max(n, 1), 36))
         M = np.zeros((max(n, 1), 36))
         cells = np.zeros(max(n, 1), np.int64)
@@ -237,6 +240,18 @@ class Solver:
         A = np.zeros((nc, nc))
         _check(_lib.cb_export_coarse(self.ctx, A.ctypes.data_as(C.c_void_p)))
         return A
+
+
+def dense_spd_inverse(A: np.ndarray, precision: int = 0) -> np.ndarray:
+    """Batched SPD inverse on the GPU (the factorisation building block)."""
+    lib = load_library()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if A.ndim == 2:
+        A = A[None]
+    out = np.zeros_like(A)
+    _check(lib.cb_dense_spd_inverse(A.shape[1], A.shape[0], precision,
+                                    A.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def unpack36(P: np.ndarray) -> np.ndarray:

@@ -1,0 +1,66 @@
+"""Writes the stored expected values for the full-size parity tests.
+
+Calls only the oracle (and the seeded input generators).  Run from the repo
+root:  python tests/golden/make_golden.py
+Outputs (next to this script):
+  cut_cube_64.json        sizes, iteration count, SHA-256 of the integer
+                          indexing arrays (cell counts, DOF nodes, |S|,
+                          objects, object types, coarse ids)
+  cut_cube_64_sample.npz  seeded sample (16384 DOFs) of the FP64 PCG solution
+                          at rtol 1e-8, plus its full 2-norm
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+from oracle import OracleSolver  # noqa: E402
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def main():
+    p = W.cut_cube_64()
+    t0 = time.time()
+    s = OracleSolver(p)
+    x, it, rel = s.solve(rtol=1e-8)
+    t = s.topo
+    meta = {
+        "workload": p.name, "n": p.n, "s": p.s, "n_balls": int(p.n_balls),
+        "n_dof": int(s.n_dof), "n_active": int(s.d.active.size), "n_cut": int(s.d.cut.size),
+        "n_coarse": int(t.n_coarse), "n_objects": int(t.obj_type.size),
+        "object_types": np.bincount(t.obj_type, minlength=3).tolist(),
+        "iterations_rtol_1e-8": int(it), "relres": float(rel),
+        "sha256": {
+            "cell_count": sha(s.d.count.astype(np.int32)),
+            "dof_node": sha(s.d.dof_node.astype(np.int64)),
+            "card": sha(t.card().astype(np.int32)),
+            "obj_ptr": sha(t.obj_ptr.astype(np.int64)),
+            "obj_dofs": sha(t.obj_dofs.astype(np.int64)),
+            "obj_type": sha(t.obj_type.astype(np.int8)),
+            "coarse_of_obj": sha(t.coarse_of_obj.astype(np.int32)),
+        },
+        "oracle_seconds": time.time() - t0,
+        "oracle_phase_seconds": s.times,
+    }
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(s.n_dof, size=16384, replace=False))
+    np.savez_compressed(os.path.join(HERE, "cut_cube_64_sample.npz"), idx=idx, u=x[idx],
+                        norm=np.array([np.linalg.norm(x)]))
+    with open(os.path.join(HERE, "cut_cube_64.json"), "w") as fh:
+        json.dump(meta, fh, indent=1)
+    print(json.dumps(meta, indent=1))
+
+
+if __name__ == "__main__":
+    main()
