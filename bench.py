@@ -1,0 +1,184 @@
+"""Benchmark: DOFs solved per second to rtol 1e-8 on one MI355X.
+
+Workload (one "step" = the whole hot path on one synthetic problem): the
+unit cube minus 20 seeded balls, 64^3 background cells, 8^3 subdomains of
+8^3 cells, f ~ U(0,1) per node, kappa = 1.  A step runs cell classification
+and cut-cell integration, host indexing, sub-assembly, the local and coarse
+factorisations and the BDDC-preconditioned CG solve to |r| < 1e-8 |b|, and
+releases the problem.  The source vector is resident in HBM before the
+timed region; ball data are passed from the host (80 doubles).
+
+Prints one JSON line.  `value` is the FP64 path; the FP32-local path (local
+factorisations and solves in FP32, outer PCG and coarse solve in FP64) is
+reported alongside with its speedup.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    return ap.parse_args()
+
+
+def run_steps(problem, f_dev, steps, warmup, rtol, profile):
+    import torch
+    from paper_1703_06323_amd import Solver
+
+    def one(prof):
+        s = Solver(problem)
+        if prof:
+            s.profile(True)
+        s.factor()
+        u, it, rel = s.solve(f_dev, rtol=rtol)
+        info = s.info()
+        kt = s.profile_times() if prof else {}
+        s.close()
+        return it, rel, info, kt
+
+    for _ in range(warmup):
+        one(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [one(profile) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, res
+
+
+def cpu_baseline():
+    """The oracle, as it stands, on a bounded sample of the workload: the
+    octant [0, 0.5]^3 of the same 20-ball geometry at the same cell size
+    (32^3 cells, 4^3 subdomains of 8^3 cells, mapped onto the unit cube),
+    full path (integrate, indexing, factor, PCG to rtol 1e-8)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import OracleSolver
+
+    base = W.cut_cube_64()
+    n = 32
+    keep = np.ones(base.radii.size, dtype=bool)
+    p = W.Problem(n=n, s=8, centres=base.centres[keep] * 2.0, radii=base.radii[keep] * 2.0,
+                  name="octant_of_cut_cube_64")
+    n1 = n + 1
+    g = np.arange(n1 ** 3)
+    I, J, K = g % n1, (g // n1) % n1, g // (n1 * n1)
+    # the workload's nodal source restricted to the octant (same h)
+    N1 = 65
+    p.f = base.f[I + N1 * (J + N1 * K)]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s = OracleSolver(p)
+        x, it, rel = s.solve(rtol=1e-8)
+        dt = time.perf_counter() - t0
+    return {"value": s.n_dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"octant [0,0.5]^3 of the workload at the same h: {n}^3 cells, "
+                       f"{(n // 8) ** 3} subdomains of 8^3, {s.n_dof} DOFs, {it} PCG iterations, "
+                       f"full oracle path in {dt:.1f} s on 1 BLAS thread")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1703_06323_amd import Solver  # noqa: F401  (fails loudly without the library)
+
+    torch.cuda.set_device(0)
+    p64 = W.cut_cube_64()
+    f_dev = torch.tensor(p64.f, dtype=torch.float64, device="cuda")
+
+    dt64, res64 = run_steps(p64, f_dev, args.steps, args.warmup, args.rtol, profile=True)
+    it64, rel64, info64, kt64 = res64[-1]
+    n_dof = int(info64["n_dof"])
+    out = {
+        "metric": "DOFs solved/s to rtol 1e-8 (FP32-precond vs FP64) + MFMA util / HBM GB/s",
+        "value": n_dof / dt64,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cut_cube_64_balls20: unit cube minus 20 seeded balls, 64^3 Q1 cells, "
+                        "8^3 subdomains of 8^3 cells, BDDC(cef) variant 1, stiffness weighting, "
+                        "PCG rtol 1e-8, FP64",
+            "n_dof": n_dof, "n_cut": int(info64["n_cut"]), "n_coarse": int(info64["n_coarse"]),
+            "iterations": it64, "relres": rel64,
+            "phase_ms": {k: round(float(info64[k]), 3) for k in
+                         ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},
+        },
+    }
+    if not args.no_fp32:
+        from paper_1703_06323_amd import CBError
+        p32 = p64.with_options(local_precision=1)
+        try:
+            dt32, res32 = run_steps(p32, f_dev, args.steps, args.warmup, args.rtol, profile=False)
+        except CBError as e:
+            res32 = None
+            out["fp32_local"] = {"error": str(e)}
+    if not args.no_fp32 and res32 is not None:
+        it32, rel32, info32, _ = res32[-1]
+        out["fp32_local"] = {
+            "value": n_dof / dt32, "unit": "DOF/s", "ms_per_step": dt32 * 1e3,
+            "iterations": it32, "relres": rel32, "speedup_vs_fp64": dt64 / dt32,
+            "phase_ms": {k: round(float(info32[k]), 3) for k in
+                         ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},
+        }
+    out["roofline"] = roofline(kt64, info64)
+    out["kernel_ms"] = {k: {"total_ms": round(v[0], 4), "launches": v[1]} for k, v in kt64.items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def roofline(kt, info):
+    """Dominant kernel's achieved rate from the library's live HIP-event
+    timing of its launches during the last timed step (see the design doc for
+    the algorithmic byte count)."""
+    name = "apply_interior"
+    if name not in kt or kt[name][1] == 0:
+        return None
+    total_ms, launches = kt[name]
+    # per launch: the active part of every subdomain's Dirichlet inverse
+    # (8 B per entry) plus the gathered input(s) and the scattered output
+    # (2 vectors on the first launch of an apply, 3 on the second: 2.5 avg)
+    alg_bytes = 8.0 * info["sum_nI2"] + 8.0 * 2.5 * info["sum_nI"]
+    avg_s = total_ms / launches * 1e-3
+    achieved = alg_bytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": "apply_interior_kernel<double>", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg_bytes}
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,11 @@ typedef struct {
   int32_t max_coarse_per_sub;  /* largest number of coarse DOFs touching one subdomain    */
   int32_t n_fp64_fallbacks;    /* FP32-local subdomains refactored in FP64                */
   int32_t factored;            /* 1 once cb_factor succeeded                              */
+  int64_t sum_nI2;             /* sum over subdomains of n_I^2 (Dirichlet inverse size)   */
+  int64_t sum_nG2;             /* sum over subdomains of n_G^2 (interface operator size)  */
+  int64_t sum_nI;              /* sum of interior DOF counts                              */
+  int64_t sum_nG;              /* sum of interface DOF counts (with multiplicity)         */
+  double flops_local_chol;     /* sum over subdomains of (n_I+n_G)^3/3 + n_I^3/3           */
   double t_integrate_ms;       /* last phase times (HIP events + host clock)              */
   double t_topology_ms;
   double t_factor_ms;
@@ -129,6 +134,17 @@ int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev); /* z
 int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev);           /* b = M_cut f  */
 
 int cb_query(const cb_ctx* c, cb_info* out);
+
+/* Measurement hooks.  With profiling enabled the library brackets every
+ * launch of the named kernel groups with HIP events on the context stream:
+ * "apply_interior" (Dirichlet inverse products), "apply_neumann" (interface
+ * operator products), "apply_A" (matrix-free operator), "coarse_gemv",
+ * "local_cholesky" (the whole blocked Cholesky of the local matrices),
+ * "local_inverse" (triangular inverses and products), "coarse_factor".
+ * cb_profile_time synchronises the stream and returns the summed elapsed
+ * time and the number of bracketed launches since profiling was enabled. */
+int cb_profile(cb_ctx* c, int32_t enable);
+int cb_profile_time(cb_ctx* c, const char* name, double* total_ms, int64_t* launches);
 
 /* Host copies of the integer data of the discretisation (bit-exact parity).
  * Each output pointer may be NULL; sizes come from cb_query / cb_export_sizes.

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <type_traits>
 #include <string>
@@ -115,8 +116,21 @@ double now_ms() {
 
 }  // namespace
 
+struct ProfEntry {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+
 struct cb_ctx {
   hipStream_t st = nullptr;
+  bool prof = false;
+  std::map<std::string, ProfEntry> prof_ev;
+  ~cb_ctx() {
+    for (auto& kv : prof_ev)
+      for (auto& e : kv.second.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
   Geometry geo;
   Topology topo;
   int N = 0, s = 0, m = 0, ns = 0;
@@ -172,12 +186,37 @@ struct cb_ctx {
 
 namespace {
 
+// Brackets the launches issued during its lifetime with HIP events when
+// profiling is enabled.
+struct ProfScope {
+  cb_ctx* c;
+  hipEvent_t b = nullptr, e = nullptr;
+  const char* name;
+  ProfScope(cb_ctx* ctx, const char* n) : c(ctx), name(n) {
+    if (!c->prof) return;
+    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(b, c->st);
+  }
+  ~ProfScope() {
+    if (!c->prof || !b || !e) return;
+    (void)hipEventRecord(e, c->st);
+    c->prof_ev[name].ev.emplace_back(b, e);
+  }
+};
+
 int apply_A_grid(cb_ctx* c, const double* x, double* y) {
+  ProfScope ps(c, "apply_A");
   GridDesc g{c->N, c->h};
   launch_apply_A(c->st, g, c->cellinfo.as<int32_t>(), c->kappa.as<double>(), c->Kc.as<double>(),
                  c->dofmask.as<uint8_t>(), x, y);
   HIPCHK(hipGetLastError());
   return CB_OK;
+}
+
+template <typename F>
+void timed(cb_ctx* c, const char* name, F&& f) {
+  ProfScope ps(c, name);
+  f();
 }
 
 // z = M r on grid vectors (eq. bddc), steps (1)-(7).
@@ -190,25 +229,30 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z) {
   double* t3 = c->t3.as<double>();
   // (1) delta_I = A_II^{-1} r_I
   launch_fill(st, nn, 0.0, t1);
-  if (c->precision == CB_FP32_LOCAL)
-    launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, nullptr, t1);
-  else
-    launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, nullptr, t1);
+  timed(c, "apply_interior", [&] {
+    if (c->precision == CB_FP32_LOCAL)
+      launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, nullptr, t1);
+    else
+      launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, nullptr, t1);
+  });
   // (2) rhat_G = r_G - (A delta)_G
   CHK(apply_A_grid(c, t1, t2));
   // (3)-(4) weighted restriction, constrained Neumann solves, coarse rhs
-  if (c->precision == CB_FP32_LOCAL)
-    launch_apply_neumann<float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi.as<double>(), c->Dw.as<double>(),
-                                r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
-  else
-    launch_apply_neumann<double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
-                                 c->Dw.as<double>(), r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
+  timed(c, "apply_neumann", [&] {
+    if (c->precision == CB_FP32_LOCAL)
+      launch_apply_neumann<float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi.as<double>(), c->Dw.as<double>(),
+                                  r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
+    else
+      launch_apply_neumann<double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
+                                   c->Dw.as<double>(), r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
+  });
   // (5) coarse correction
   const int nc = c->topo.n_coarse;
   if (nc > 0) {
     launch_coarse_rhs(st, nc, c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(),
                       c->NCp, c->cloc.as<double>(), c->cvec.as<double>());
-    launch_gemv(st, nc, c->ldc, c->Acinv.as<double>(), c->cvec.as<double>(), c->ucvec.as<double>());
+    timed(c, "coarse_gemv",
+          [&] { launch_gemv(st, nc, c->ldc, c->Acinv.as<double>(), c->cvec.as<double>(), c->ucvec.as<double>()); });
     launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
   // (6) weighted average on the interface
@@ -218,10 +262,12 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z) {
                        c->zbuf.as<double>(), z);
   // (7) harmonic extension: z_I = A_II^{-1} (r - A [0; u_G])_I
   CHK(apply_A_grid(c, z, t3));
-  if (c->precision == CB_FP32_LOCAL)
-    launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, t3, z);
-  else
-    launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, t3, z);
+  timed(c, "apply_interior", [&] {
+    if (c->precision == CB_FP32_LOCAL)
+      launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, t3, z);
+    else
+      launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, t3, z);
+  });
   HIPCHK(hipGetLastError());
   return CB_OK;
 }
@@ -528,7 +574,15 @@ int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) {
   c->info.n_objects = (int32_t)t.obj_type.size();
   c->info.n_iface = t.n_iface;
   int maxl = 0;
-  for (int w = 0; w < ns; ++w) maxl = std::max(maxl, t.nI[w] + t.nG[w]);
+  for (int w = 0; w < ns; ++w) {
+    maxl = std::max(maxl, t.nI[w] + t.nG[w]);
+    const double nI = t.nI[w], nG = t.nG[w];
+    c->info.sum_nI2 += (int64_t)t.nI[w] * t.nI[w];
+    c->info.sum_nG2 += (int64_t)t.nG[w] * t.nG[w];
+    c->info.sum_nI += t.nI[w];
+    c->info.sum_nG += t.nG[w];
+    c->info.flops_local_chol += (nI + nG) * (nI + nG) * (nI + nG) / 3.0 + nI * nI * nI / 3.0;
+  }
   c->info.max_local_dofs = maxl;
   c->info.max_coarse_per_sub = t.maxC;
   *out = c.release();
@@ -564,21 +618,25 @@ int factor_impl(cb_ctx* c) {
                  NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
   const int64_t sK = (int64_t)nt * nt;
   const int64_t sL = (int64_t)ntiles * CHOL_BLOCK * CHOL_BLOCK;
-  cholesky<T>(st, K.as<T>(), nt, sK, nt, ns, Linv.as<T>(), sL, c->info_d.as<int>());
+  timed(c, "local_cholesky", [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, ns, Linv.as<T>(), sL, c->info_d.as<int>()); });
   HIPCHK(hipGetLastError());
   // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
   const int64_t sY = (int64_t)nbig * nbig;
-  tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, ns, Linv.as<T>(), sL, Y.as<T>(), NIp, sY);
-  gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, ns,
-          GEMM_LOWER | GEMM_KFROM_DIAG);
+  timed(c, "local_inverse", [&] {
+    tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, ns, Linv.as<T>(), sL, Y.as<T>(), NIp, sY);
+    gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, ns,
+            GEMM_LOWER | GEMM_KFROM_DIAG);
+  });
   CHK(dalloc(c->P, (size_t)ns * NIp * NIp * sizeof(T)));
   symmetrize_scale<T, T>(st, PS.as<T>(), NIp, sY, c->P.as<T>(), NIp, (int64_t)NIp * NIp, c->Ds.as<double>(), nt,
                          NIp, ns);
   HIPCHK(hipGetLastError());
   // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
-  tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, ns, Linv.as<T>(), sL, Y.as<T>(), NGp, sY);
-  gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, ns,
-          GEMM_LOWER | GEMM_KFROM_DIAG);
+  timed(c, "local_inverse", [&] {
+    tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, ns, Linv.as<T>(), sL, Y.as<T>(), NGp, sY);
+    gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, ns,
+            GEMM_LOWER | GEMM_KFROM_DIAG);
+  });
   CHK(dalloc(KS, (size_t)ns * NGp * NGp * sizeof(double)));
   symmetrize_scale<T, double>(st, PS.as<T>(), NGp, sY, KS.as<double>(), NGp, (int64_t)NGp * NGp,
                               c->Ds.as<double>() + NIp, nt, NGp, ns);
@@ -623,6 +681,7 @@ int factor_impl(cb_ctx* c) {
     DevBuf Lc, Yc, PSc, ones;
     const int nct = ldc / CHOL_BLOCK;
     CHK(dalloc(Lc, (size_t)nct * CHOL_BLOCK * CHOL_BLOCK * sizeof(double)));
+    ProfScope cps(c, "coarse_factor");
     cholesky<double>(st, Ac.as<double>(), ldc, 0, ldc, 1, Lc.as<double>(), 0, c->info_d.as<int>() + ns + 1);
     CHK(dalloc(Yc, (size_t)ldc * ldc * sizeof(double)));
     tri_inverse<double>(st, Ac.as<double>(), ldc, 0, 0, ldc, 1, Lc.as<double>(), 0, Yc.as<double>(), ldc, 0);
@@ -830,6 +889,30 @@ int cb_export_coarse(const cb_ctx* c, double* Ac) {
   if (nc == 0) return CB_OK;
   HIPCHK(hipMemcpy2D(Ac, nc * sizeof(double), c->AcKeep.p, ldc * sizeof(double), nc * sizeof(double), nc,
                      hipMemcpyDeviceToHost));
+  return CB_OK;
+}
+
+int cb_profile(cb_ctx* c, int32_t enable) {
+  if (!c) return fail(CB_ERR_ARG, "null context");
+  c->prof = enable != 0;
+  return CB_OK;
+}
+
+int cb_profile_time(cb_ctx* c, const char* name, double* total_ms, int64_t* launches) {
+  if (!c || !name) return fail(CB_ERR_ARG, "null argument");
+  HIPCHK(hipStreamSynchronize(c->st));
+  double tot = 0.0;
+  int64_t n = 0;
+  auto it = c->prof_ev.find(name);
+  if (it != c->prof_ev.end())
+    for (auto& e : it->second.ev) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+      tot += ms;
+      ++n;
+    }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
   return CB_OK;
 }
 

@@ -49,7 +49,9 @@ class cb_info(C.Structure):
                 ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("n_objects", C.c_int32),
                 ("n_iface", C.c_int32), ("max_local_dofs", C.c_int32),
                 ("max_coarse_per_sub", C.c_int32), ("n_fp64_fallbacks", C.c_int32),
-                ("factored", C.c_int32), ("t_integrate_ms", C.c_double),
+                ("factored", C.c_int32), ("sum_nI2", C.c_int64), ("sum_nG2", C.c_int64),
+                ("sum_nI", C.c_int64), ("sum_nG", C.c_int64), ("flops_local_chol", C.c_double),
+                ("t_integrate_ms", C.c_double),
                 ("t_topology_ms", C.c_double), ("t_factor_ms", C.c_double),
                 ("t_solve_ms", C.c_double)]
 
@@ -78,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
     lib.cb_export_cut_matrices.argtypes = [vp, vp, vp, vp]
     lib.cb_export_coarse.argtypes = [vp, vp]
+    lib.cb_profile.argtypes = [vp, C.c_int32]
+    lib.cb_profile_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
     lib.cb_last_error.restype = C.c_char_p
     lib.cb_destroy.argtypes = [vp]
@@ -85,7 +89,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
                  "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
-                 "cb_dense_spd_inverse"):
+                 "cb_dense_spd_inverse", "cb_profile", "cb_profile_time"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -204,6 +208,23 @@ class Solver:
         fv = None if f is None else self._f64(f)
         _check(_lib.cb_load(self.ctx, _dptr(fv), b.data_ptr()))
         return b
+
+    PROFILE_GROUPS = ("apply_interior", "apply_neumann", "apply_A", "coarse_gemv",
+                      "local_cholesky", "local_inverse", "coarse_factor")
+
+    def profile(self, enable=True):
+        _check(_lib.cb_profile(self.ctx, 1 if enable else 0))
+
+    def profile_times(self) -> dict:
+        """{group: (total_ms, launches)} of the bracketed kernel groups."""
+        out = {}
+        for name in self.PROFILE_GROUPS:
+            t = C.c_double(0.0)
+            n = C.c_int64(0)
+            _check(_lib.cb_profile_time(self.ctx, name.encode(), C.byref(t), C.byref(n)))
+            if n.value:
+                out[name] = (float(t.value), int(n.value))
+        return out
 
     # -- host exports --------------------------------------------------------
     def export_indexing(self) -> dict:
