@@ -156,11 +156,12 @@ __global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_p
 }
 
 // Kernel 3: per subdomain, from KS = K_S^{-1} (full, unscaled, FP64):
-// G = KS C^T, S_c = C G, S_c^{-1}, Phi = G S_c^{-1}, A_c^w = S_c^{-1} - R.
+// G = KS C^T, S_c = C G, S_c^{-1}, Phi = G S_c^{-1} (interface part of the
+// coarse basis: C Phi = I and energy-minimising for S_A).
 __global__ __launch_bounds__(256) void coarse_local_kernel(SubDev sd, const double* __restrict__ KS,
                                                            const double* __restrict__ diagA_G,
                                                            double* __restrict__ Gm, double* __restrict__ Phi,
-                                                           double* __restrict__ AcLoc, int* info) {
+                                                           int* info) {
   extern __shared__ double smem[];
   const int w = blockIdx.x;
   const int NGp = sd.NGp, NCp = sd.NCp;
@@ -246,12 +247,68 @@ __global__ __launch_bounds__(256) void coarse_local_kernel(SubDev sd, const doub
         for (int t = 0; t < nC; ++t) acc += g[(int64_t)i * NCp + t] * Sc[t * NCp + u];
       phi[(int64_t)i * NCp + u] = acc;
     }
-  // A_c^w = S_c^{-1} - R (restricted to the nC x nC block)
-  for (int e = tid; e < NCp * NCp; e += 256) {
+}
+
+// Kernel 3b: Y = A_omega X for nt x NCp blocks X, Y (unscaled FP64 local
+// Neumann matrix applied cell by cell; row r owned by one thread).
+__global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, const double* __restrict__ X,
+                                                          double* __restrict__ Y) {
+  const int w = blockIdx.x;
+  const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
+  const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
+  const int s = g.s, m = g.N / g.s, N = g.N;
+  const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
+  const int64_t N1 = N + 1;
+  const int s1 = s + 1;
+  const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
+  const double* x = X + (int64_t)w * nt * NCp;
+  double* y = Y + (int64_t)w * nt * NCp;
+  for (int r = threadIdx.x; r < nt; r += blockDim.x) {
+    double* yr = y + (int64_t)r * NCp;
+    for (int t = 0; t < NCp; ++t) yr[t] = 0.0;
+    int64_t n = -1;
+    if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+    else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
+    if (n < 0) continue;
+    const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
+    const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
+    for (int u = 0; u < 8; ++u) {
+      const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+      if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+      const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
+      const int32_t info = g.cellinfo[c];
+      if (info == CELL_INACTIVE) continue;
+      const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+      const double sc = g.kappa[c] * g.h;
+      for (int b = 0; b < 8; ++b) {
+        const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
+        const int col = loc[bx + s1 * (by + s1 * bz)];
+        if (col < 0) continue;
+        const double kab = sc * (info == CELL_UNCUT ? c_Kref_b[a * 8 + b]
+                                                    : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)]);
+        const double* xc = x + (int64_t)col * NCp;
+        for (int t = 0; t < nC; ++t) yr[t] += kab * xc[t];
+      }
+    }
+  }
+}
+
+// Kernel 3c: local coarse matrix A_c^w = Phi^T (A_omega Phi) as a Gram
+// matrix of the coarse basis (symmetric positive semi-definite by
+// construction), Phi and V = A_omega Phi given as nt x NCp blocks.
+__global__ __launch_bounds__(256) void coarse_gram_kernel(SubDev sd, const double* __restrict__ Phi,
+                                                          const double* __restrict__ V, double* __restrict__ AcLoc) {
+  const int w = blockIdx.x;
+  const int NCp = sd.NCp, nt = sd.NIp + sd.NGp;
+  const int nC = sd.nC[w];
+  const double* ph = Phi + (int64_t)w * nt * NCp;
+  const double* v = V + (int64_t)w * nt * NCp;
+  for (int e = threadIdx.x; e < NCp * NCp; e += blockDim.x) {
     const int t = e / NCp, u = e % NCp;
-    double v = 0.0;
-    if (t < nC && u < nC) v = Sc[e] - (t == u ? rho[t] : 0.0);
-    AcLoc[(int64_t)w * NCp * NCp + e] = v;
+    double acc = 0.0;
+    if (t < nC && u < nC)
+      for (int r = 0; r < nt; ++r) acc += ph[(int64_t)r * NCp + t] * v[(int64_t)r * NCp + u];
+    AcLoc[(int64_t)w * NCp * NCp + e] = acc;
   }
 }
 
@@ -440,10 +497,18 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
 }
 
 void launch_coarse_local(hipStream_t st, const SubDev& sd, int ns, const double* KS,
-                         const double* diagA_G, double* G, double* Phi, double* AcLoc, int* info) {
+                         const double* diagA_G, double* G, double* Phi, int* info) {
   const size_t sh = (size_t)(sd.NCp * sd.NCp + 2 * sd.NCp) * sizeof(double);
-  hipLaunchKernelGGL(coarse_local_kernel, dim3(ns), dim3(256), sh, st, sd, KS, diagA_G, G, Phi, AcLoc,
-                     info);
+  hipLaunchKernelGGL(coarse_local_kernel, dim3(ns), dim3(256), sh, st, sd, KS, diagA_G, G, Phi, info);
+}
+
+void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y) {
+  hipLaunchKernelGGL(local_apply_kernel, dim3(ns), dim3(256), 0, st, sd, g, X, Y);
+}
+
+void launch_coarse_gram(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* V,
+                        double* AcLoc) {
+  hipLaunchKernelGGL(coarse_gram_kernel, dim3(ns), dim3(256), 0, st, sd, Phi, V, AcLoc);
 }
 
 void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,

@@ -630,6 +630,17 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(c->P, (size_t)ns * NIp * NIp * sizeof(T)));
   symmetrize_scale<T, T>(st, PS.as<T>(), NIp, sY, c->P.as<T>(), NIp, (int64_t)NIp * NIp, c->Ds.as<double>(), nt,
                          NIp, ns);
+  // FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
+  DevBuf Pd64;
+  const double* Pd = nullptr;
+  if (std::is_same<T, double>::value) {
+    Pd = reinterpret_cast<const double*>(c->P.p);
+  } else {
+    CHK(dalloc(Pd64, (size_t)ns * NIp * NIp * sizeof(double)));
+    symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, (int64_t)NIp * NIp,
+                                c->Ds.as<double>(), nt, NIp, ns);
+    Pd = Pd64.as<double>();
+  }
   HIPCHK(hipGetLastError());
   // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
   timed(c, "local_inverse", [&] {
@@ -650,8 +661,28 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(c->Phi, (size_t)ns * NGp * NCp * sizeof(double)));
   CHK(dalloc(AcLoc, (size_t)ns * NCp * NCp * sizeof(double)));
   launch_coarse_local(st, sd, ns, KS.as<double>(), c->diagAG.as<double>(), G.as<double>(), c->Phi.as<double>(),
-                      AcLoc.as<double>(), c->info_d.as<int>() + ns);
+                      c->info_d.as<int>() + ns);
   HIPCHK(hipGetLastError());
+  {
+    // full coarse basis Phi = [-A_II^{-1} A_IG Phi_G; Phi_G] and the local
+    // coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi
+    DevBuf PhiF, V;
+    const int64_t sF = (int64_t)nt * NCp;
+    CHK(dalloc(PhiF, (size_t)ns * sF * sizeof(double)));
+    CHK(dalloc(V, (size_t)ns * sF * sizeof(double)));
+    launch_fill(st, (int64_t)ns * sF, 0.0, PhiF.as<double>());
+    HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), c->Phi.p,
+                            (size_t)NGp * NCp * sizeof(double), (size_t)NGp * NCp * sizeof(double), ns,
+                            hipMemcpyDeviceToDevice, st));
+    launch_local_apply(st, sd, g, ns, PhiF.as<double>(), V.as<double>());
+    gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, (int64_t)NIp * NIp, V.as<double>(), NCp, sF, 0.0,
+                 PhiF.as<double>(), NCp, sF, ns, 0);
+    launch_local_apply(st, sd, g, ns, PhiF.as<double>(), V.as<double>());
+    launch_coarse_gram(st, sd, ns, PhiF.as<double>(), V.as<double>(), AcLoc.as<double>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  Pd64.release();
   // Kt = K_S^{-1} - Phi G^T
   gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, c->Phi.as<double>(), NCp, (int64_t)NGp * NCp, G.as<double>(), NCp,
                (int64_t)NGp * NCp, 1.0, KS.as<double>(), NGp, (int64_t)NGp * NGp, ns, 0);

@@ -8,6 +8,8 @@ Outputs (next to this script):
                           objects, object types, coarse ids)
   cut_cube_64_sample.npz  seeded sample (16384 DOFs) of the FP64 PCG solution
                           at rtol 1e-8, plus its full 2-norm
+With the argument `96`, the same files for the 96^3 forty-ball workload with
+log-normal conductivity (cut_cube_96.json, cut_cube_96_sample.npz).
 """
 import hashlib
 import json
@@ -29,8 +31,9 @@ def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def main():
-    p = W.cut_cube_64()
+def main(which="64"):
+    p = W.cut_cube_64() if which == "64" else W.cut_cube_96_lognormal().with_options(local_precision=0)
+    tag = "cut_cube_" + which
     t0 = time.time()
     s = OracleSolver(p)
     x, it, rel = s.solve(rtol=1e-8)
@@ -55,12 +58,12 @@ def main():
     }
     rng = np.random.default_rng(12345)
     idx = np.sort(rng.choice(s.n_dof, size=16384, replace=False))
-    np.savez_compressed(os.path.join(HERE, "cut_cube_64_sample.npz"), idx=idx, u=x[idx],
+    np.savez_compressed(os.path.join(HERE, tag + "_sample.npz"), idx=idx, u=x[idx],
                         norm=np.array([np.linalg.norm(x)]))
-    with open(os.path.join(HERE, "cut_cube_64.json"), "w") as fh:
+    with open(os.path.join(HERE, tag + ".json"), "w") as fh:
         json.dump(meta, fh, indent=1)
     print(json.dumps(meta, indent=1))
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "64")
