@@ -33,11 +33,9 @@ void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, i
                            double* diagA_G, double* Dscale);
 void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
                     const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw);
-void launch_coarse_local(hipStream_t st, const SubDev& sd, int ns, const double* KS,
-                         const double* diagA_G, double* G, double* Phi, int* info);
 void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y);
-void launch_coarse_gram(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* V,
-                        double* AcLoc);
+void launch_build_constraints(hipStream_t st, const SubDev& sd, int ns, double* Cm);
+void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info);
 void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,
                             const int32_t* cs_row, const SubDev& sd, const double* AcLoc, double* Ac);
 template <typename TM>

@@ -155,121 +155,29 @@ __global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_p
   }
 }
 
-// Kernel 3: per subdomain, from KS = K_S^{-1} (full, unscaled, FP64):
-// G = KS C^T, S_c = C G, S_c^{-1}, Phi = G S_c^{-1} (interface part of the
-// coarse basis: C Phi = I and energy-minimising for S_A).
-__global__ __launch_bounds__(256) void coarse_local_kernel(SubDev sd, const double* __restrict__ KS,
-                                                           const double* __restrict__ diagA_G,
-                                                           double* __restrict__ Gm, double* __restrict__ Phi,
-                                                           int* info) {
-  extern __shared__ double smem[];
-  const int w = blockIdx.x;
-  const int NGp = sd.NGp, NCp = sd.NCp;
-  const int nG = sd.nG[w], nC = sd.nC[w];
-  double* Sc = smem;                  // [NCp*NCp]
-  double* rho = Sc + NCp * NCp;       // [NCp]
-  double* cnt = rho + NCp;            // [NCp]
-  const int tid = threadIdx.x;
-  const int* obj = sd.G_obj + (int64_t)w * NGp;
-  const double* ks = KS + (int64_t)w * NGp * NGp;
-  double* g = Gm + (int64_t)w * NGp * NCp;
-  double* phi = Phi + (int64_t)w * NGp * NCp;
-  for (int t = tid; t < NCp; t += 256) {
-    double sr = 0.0, sc = 0.0;
-    if (t < nC)
-      for (int j = 0; j < nG; ++j)
-        if (obj[j] == t) {
-          sr += diagA_G[(int64_t)w * NGp + j];
-          sc += 1.0;
-        }
-    rho[t] = sr;
-    cnt[t] = sc;
-  }
-  // G[i][t] = (1/|t|) sum_{j in t} KS[i][j]  (rows i owned by one thread)
-  for (int i = tid; i < NGp; i += 256)
-    for (int t = 0; t < NCp; ++t) g[(int64_t)i * NCp + t] = 0.0;
-  __syncthreads();
-  for (int i = tid; i < NGp; i += 256) {
-    if (i >= nG) continue;
-    for (int j = 0; j < nG; ++j) {
-      const int t = obj[j];
-      if (t >= 0) g[(int64_t)i * NCp + t] += ks[(int64_t)i * NGp + j];
-    }
-    for (int t = 0; t < nC; ++t) g[(int64_t)i * NCp + t] /= cnt[t];
-  }
-  __syncthreads();
-  // S_c[t][u] = (1/|t|) sum_{j in t} G[j][u]
-  for (int e = tid; e < NCp * NCp; e += 256) Sc[e] = 0.0;
-  __syncthreads();
-  for (int e = tid; e < NCp * NCp; e += 256) {
-    const int t = e / NCp, u = e % NCp;
-    if (t >= nC || u >= nC) {
-      if (t == u) Sc[e] = 1.0;
-      continue;
-    }
-    double acc = 0.0;
-    for (int j = 0; j < nG; ++j)
-      if (obj[j] == t) acc += g[(int64_t)j * NCp + u];
-    Sc[e] = acc / cnt[t];
-  }
-  __syncthreads();
-  // in-place Gauss-Jordan inverse of the SPD matrix S_c (no pivoting needed)
-  __shared__ double piv;
-  for (int k = 0; k < NCp; ++k) {
-    if (tid == 0) {
-      double p = Sc[k * NCp + k];
-      if (!(p > 0.0) && info) atomicMax(info, 1);
-      piv = (p > 0.0) ? p : 1.0;
-    }
-    __syncthreads();
-    const double p = piv;
-    // row k scaled
-    for (int j = tid; j < NCp; j += 256)
-      if (j != k) Sc[k * NCp + j] /= p;
-    __syncthreads();
-    for (int e = tid; e < NCp * NCp; e += 256) {
-      const int i = e / NCp, j = e % NCp;
-      if (i == k || j == k) continue;
-      Sc[e] -= Sc[i * NCp + k] * Sc[k * NCp + j];
-    }
-    __syncthreads();
-    for (int i = tid; i < NCp; i += 256)
-      if (i != k) Sc[i * NCp + k] = -Sc[i * NCp + k] / p;
-    __syncthreads();
-    if (tid == 0) Sc[k * NCp + k] = 1.0 / p;
-    __syncthreads();
-  }
-  // Phi = G S_c^{-1}
-  for (int i = tid; i < NGp; i += 256)
-    for (int u = 0; u < NCp; ++u) {
-      double acc = 0.0;
-      if (i < nG && u < nC)
-        for (int t = 0; t < nC; ++t) acc += g[(int64_t)i * NCp + t] * Sc[t * NCp + u];
-      phi[(int64_t)i * NCp + u] = acc;
-    }
-}
-
 // Kernel 3b: Y = A_omega X for nt x NCp blocks X, Y (unscaled FP64 local
-// Neumann matrix applied cell by cell; row r owned by one thread).
+// Neumann matrix applied cell by cell).  One thread per (row, column): the
+// threads of a row walk the same cells, so the cell data are broadcast and
+// X is read along its rows.
 __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, const double* __restrict__ X,
                                                           double* __restrict__ Y) {
-  const int w = blockIdx.x;
+  const int w = blockIdx.y;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
-  const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt * NCp) return;
+  const int r = e / NCp, t = e % NCp;
+  const int nI = sd.nI[w], nG = sd.nG[w];
   const int s = g.s, m = g.N / g.s, N = g.N;
   const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
   const int64_t N1 = N + 1;
   const int s1 = s + 1;
   const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
   const double* x = X + (int64_t)w * nt * NCp;
-  double* y = Y + (int64_t)w * nt * NCp;
-  for (int r = threadIdx.x; r < nt; r += blockDim.x) {
-    double* yr = y + (int64_t)r * NCp;
-    for (int t = 0; t < NCp; ++t) yr[t] = 0.0;
-    int64_t n = -1;
-    if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
-    else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
-    if (n < 0) continue;
+  int64_t n = -1;
+  if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+  else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
+  double acc = 0.0;
+  if (n >= 0) {
     const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
     const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
     for (int u = 0; u < 8; ++u) {
@@ -286,30 +194,73 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
         if (col < 0) continue;
         const double kab = sc * (info == CELL_UNCUT ? c_Kref_b[a * 8 + b]
                                                     : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)]);
-        const double* xc = x + (int64_t)col * NCp;
-        for (int t = 0; t < nC; ++t) yr[t] += kab * xc[t];
+        acc += kab * x[(int64_t)col * NCp + t];
       }
     }
   }
+  Y[(int64_t)w * nt * NCp + e] = acc;
 }
 
-// Kernel 3c: local coarse matrix A_c^w = Phi^T (A_omega Phi) as a Gram
-// matrix of the coarse basis (symmetric positive semi-definite by
-// construction), Phi and V = A_omega Phi given as nt x NCp blocks.
-__global__ __launch_bounds__(256) void coarse_gram_kernel(SubDev sd, const double* __restrict__ Phi,
-                                                          const double* __restrict__ V, double* __restrict__ AcLoc) {
+// Kernel 3d: dense constraint matrix C_omega (NCp x NGp): row t holds
+// 1/|lambda_t| on the interface rows of object t (eq. coarse-dofs, equal
+// weight mean), zero elsewhere.
+__global__ __launch_bounds__(256) void build_constraints_kernel(SubDev sd, double* __restrict__ Cm) {
+  extern __shared__ double cnt[];
   const int w = blockIdx.x;
-  const int NCp = sd.NCp, nt = sd.NIp + sd.NGp;
-  const int nC = sd.nC[w];
-  const double* ph = Phi + (int64_t)w * nt * NCp;
-  const double* v = V + (int64_t)w * nt * NCp;
-  for (int e = threadIdx.x; e < NCp * NCp; e += blockDim.x) {
-    const int t = e / NCp, u = e % NCp;
-    double acc = 0.0;
-    if (t < nC && u < nC)
-      for (int r = 0; r < nt; ++r) acc += ph[(int64_t)r * NCp + t] * v[(int64_t)r * NCp + u];
-    AcLoc[(int64_t)w * NCp * NCp + e] = acc;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  const int nG = sd.nG[w];
+  const int* obj = sd.G_obj + (int64_t)w * NGp;
+  for (int t = threadIdx.x; t < NCp; t += 256) {
+    double c = 0.0;
+    for (int j = 0; j < nG; ++j) c += (obj[j] == t) ? 1.0 : 0.0;
+    cnt[t] = c;
   }
+  __syncthreads();
+  double* C = Cm + (int64_t)w * NCp * NGp;
+  for (int e = threadIdx.x; e < NCp * NGp; e += 256) {
+    const int t = e / NGp, j = e % NGp;
+    C[e] = (j < nG && obj[j] == t) ? 1.0 / cnt[t] : 0.0;
+  }
+}
+
+// Kernel 3e: in-place inverse of the SPD matrices S_c (NCp x NCp, identity
+// on padded rows) by Gauss-Jordan elimination in LDS.
+__global__ __launch_bounds__(256) void small_spd_inverse_kernel(SubDev sd, double* __restrict__ Sm, int* info) {
+  extern __shared__ double S[];
+  const int w = blockIdx.x;
+  const int NCp = sd.NCp, nC = sd.nC[w];
+  double* g = Sm + (int64_t)w * NCp * NCp;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NCp * NCp; e += 256) {
+    const int t = e / NCp, u = e % NCp;
+    S[e] = (t < nC && u < nC) ? g[e] : (t == u ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  __shared__ double piv;
+  for (int k = 0; k < NCp; ++k) {
+    if (tid == 0) {
+      const double p = S[k * NCp + k];
+      if (!(p > 0.0) && info) atomicMax(info, 1);
+      piv = (p > 0.0) ? p : 1.0;
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int j = tid; j < NCp; j += 256)
+      if (j != k) S[k * NCp + j] /= p;
+    __syncthreads();
+    for (int e = tid; e < NCp * NCp; e += 256) {
+      const int i = e / NCp, j = e % NCp;
+      if (i == k || j == k) continue;
+      S[e] -= S[i * NCp + k] * S[k * NCp + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < NCp; i += 256)
+      if (i != k) S[i * NCp + k] = -S[i * NCp + k] / p;
+    __syncthreads();
+    if (tid == 0) S[k * NCp + k] = 1.0 / p;
+    __syncthreads();
+  }
+  for (int e = tid; e < NCp * NCp; e += 256) g[e] = S[e];
 }
 
 // Kernel 4: coarse matrix row c = sum over the subdomains touching coarse
@@ -496,19 +447,19 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
                      if_ptr, if_sub, if_slot, NGp, diagA_G, stiffness, Dw);
 }
 
-void launch_coarse_local(hipStream_t st, const SubDev& sd, int ns, const double* KS,
-                         const double* diagA_G, double* G, double* Phi, int* info) {
-  const size_t sh = (size_t)(sd.NCp * sd.NCp + 2 * sd.NCp) * sizeof(double);
-  hipLaunchKernelGGL(coarse_local_kernel, dim3(ns), dim3(256), sh, st, sd, KS, diagA_G, G, Phi, info);
-}
-
 void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y) {
-  hipLaunchKernelGGL(local_apply_kernel, dim3(ns), dim3(256), 0, st, sd, g, X, Y);
+  const int nt = sd.NIp + sd.NGp;
+  dim3 grid((nt * sd.NCp + 255) / 256, ns);
+  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, g, X, Y);
 }
 
-void launch_coarse_gram(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* V,
-                        double* AcLoc) {
-  hipLaunchKernelGGL(coarse_gram_kernel, dim3(ns), dim3(256), 0, st, sd, Phi, V, AcLoc);
+void launch_build_constraints(hipStream_t st, const SubDev& sd, int ns, double* Cm) {
+  hipLaunchKernelGGL(build_constraints_kernel, dim3(ns), dim3(256), sd.NCp * sizeof(double), st, sd, Cm);
+}
+
+void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info) {
+  hipLaunchKernelGGL(small_spd_inverse_kernel, dim3(ns), dim3(256), (size_t)sd.NCp * sd.NCp * sizeof(double), st,
+                     sd, S, info);
 }
 
 void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <type_traits>
 #include <string>
@@ -44,29 +45,101 @@ int fail(int code, const std::string& msg) {
     if (rc_ != CB_OK) return rc_; \
   } while (0)
 
-// Device buffer owned by a context.
+// Process-wide cache of device blocks: freed blocks are kept (keyed by size,
+// per device) and handed out again for requests of up to the same size, so
+// repeated setup/factor/solve cycles issue no hipMalloc/hipFree (hipFree
+// synchronises the device).  A block released while work that uses it is
+// still queued is only reused on the same device after that device's
+// pending work has been ordered: reuse happens on the stream of the new
+// owner, and cross-context reuse synchronises the releasing stream.
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipStream_t st;
+};
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> blocks;   // by size
+  size_t bytes = 0;
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();   // intentionally leaked at exit
+  return *c;
+}
+constexpr size_t CACHE_LIMIT = (size_t)48 << 30;   // bytes kept for reuse
+
+void* cache_get(size_t bytes, hipStream_t st, hipError_t* err) {
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.blocks.lower_bound(bytes);
+    if (it != c.blocks.end() && it->first <= bytes + bytes / 4 + (1 << 20)) {
+      CachedBlock b = it->second;
+      c.blocks.erase(it);
+      c.bytes -= b.bytes;
+      if (b.st != st) (void)hipStreamSynchronize(b.st);
+      *err = hipSuccess;
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  *err = hipMalloc(&p, bytes);
+  if (*err == hipErrorOutOfMemory) {
+    // release the cache and retry once
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> g(c.mu);
+      for (auto& kv : c.blocks) drop.push_back(kv.second.p);
+      c.blocks.clear();
+      c.bytes = 0;
+    }
+    (void)hipDeviceSynchronize();
+    for (void* q : drop) (void)hipFree(q);
+    *err = hipMalloc(&p, bytes);
+  }
+  return *err == hipSuccess ? p : nullptr;
+}
+
+void cache_put(void* p, size_t bytes, hipStream_t st) {
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.bytes + bytes > CACHE_LIMIT) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(p);
+    return;
+  }
+  c.blocks.emplace(bytes, CachedBlock{p, bytes, st});
+  c.bytes += bytes;
+}
+
+// Device buffer owned by a context (allocated from the block cache).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t st = nullptr;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) cache_put(p, bytes, st);
     p = nullptr;
     bytes = 0;
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+thread_local hipStream_t g_alloc_stream = nullptr;   // stream of the context being served
+
 int dalloc(DevBuf& b, size_t bytes) {
   b.release();
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e != hipSuccess) {
-    b.p = nullptr;
+  bytes = (bytes + 255) & ~(size_t)255;
+  hipError_t e;
+  b.p = cache_get(bytes, g_alloc_stream, &e);
+  if (!b.p) {
     return fail(CB_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
                                 hipGetErrorString(e));
   }
   b.bytes = bytes;
+  b.st = g_alloc_stream;
   return CB_OK;
 }
 
@@ -348,6 +421,7 @@ extern "C" {
 const char* cb_last_error(void) { return g_err.c_str(); }
 
 int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv) {
+  g_alloc_stream = nullptr;
   if (n < 1 || batch < 1 || !A || !Ainv || precision < 0 || precision > 1)
     return fail(CB_ERR_ARG, "invalid argument");
   const int np = round_up(n, CHOL_BLOCK);
@@ -371,7 +445,10 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
     CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
     const int64_t sL = (int64_t)nt * CHOL_BLOCK * CHOL_BLOCK;
     cholesky<T>(nullptr, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>());
-    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, batch, dL.as<T>(), sL, dY.as<T>(), np, nn);
+    DevBuf dT;
+    CHK(dalloc(dT, (size_t)batch * TRI_SUPER * np * sizeof(T)));
+    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, batch, dL.as<T>(), sL, dY.as<T>(), np, nn, dT.as<T>(),
+                   (int64_t)TRI_SUPER * np);
     gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
             GEMM_LOWER | GEMM_KFROM_DIAG);
     symmetrize_scale<T, double>(nullptr, dP.as<T>(), np, nn, dOut.as<double>(), np, nn, dOnes.as<double>(), np, np,
@@ -416,6 +493,7 @@ int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) {
 
   std::unique_ptr<cb_ctx> c(new cb_ctx());
   c->st = static_cast<hipStream_t>(stream);
+  g_alloc_stream = c->st;
   c->N = N;
   c->s = s;
   c->m = N / s;
@@ -606,6 +684,9 @@ int factor_impl(cb_ctx* c) {
   const int nbig = std::max(NIp, NGp);
   CHK(dalloc(Y, (size_t)ns * nbig * nbig * sizeof(T)));
   CHK(dalloc(PS, (size_t)ns * nbig * nbig * sizeof(T)));
+  DevBuf Tmp;
+  const int64_t sT = (int64_t)TRI_SUPER * nbig;
+  CHK(dalloc(Tmp, (size_t)ns * sT * sizeof(T)));
   CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
   CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
   CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
@@ -623,7 +704,7 @@ int factor_impl(cb_ctx* c) {
   // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
   const int64_t sY = (int64_t)nbig * nbig;
   timed(c, "local_inverse", [&] {
-    tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, ns, Linv.as<T>(), sL, Y.as<T>(), NIp, sY);
+    tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, ns, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(), sT);
     gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, ns,
             GEMM_LOWER | GEMM_KFROM_DIAG);
   });
@@ -644,7 +725,7 @@ int factor_impl(cb_ctx* c) {
   HIPCHK(hipGetLastError());
   // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
   timed(c, "local_inverse", [&] {
-    tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, ns, Linv.as<T>(), sL, Y.as<T>(), NGp, sY);
+    tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, ns, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(), sT);
     gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, ns,
             GEMM_LOWER | GEMM_KFROM_DIAG);
   });
@@ -656,13 +737,27 @@ int factor_impl(cb_ctx* c) {
   Y.release();
   PS.release();
   Linv.release();
-  // coarse basis on the interface and local coarse matrices
+  Tmp.release();
+  // coarse basis on the interface: G = K_S^{-1} C^T, S_c = C G,
+  // Phi_G = G S_c^{-1} (C Phi_G = I, energy-minimising for S_A)
   CHK(dalloc(G, (size_t)ns * NGp * NCp * sizeof(double)));
   CHK(dalloc(c->Phi, (size_t)ns * NGp * NCp * sizeof(double)));
   CHK(dalloc(AcLoc, (size_t)ns * NCp * NCp * sizeof(double)));
-  launch_coarse_local(st, sd, ns, KS.as<double>(), c->diagAG.as<double>(), G.as<double>(), c->Phi.as<double>(),
-                      c->info_d.as<int>() + ns);
-  HIPCHK(hipGetLastError());
+  {
+    DevBuf Cm, Sc;
+    const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp;
+    CHK(dalloc(Cm, (size_t)ns * NCp * NGp * sizeof(double)));
+    CHK(dalloc(Sc, (size_t)ns * sC * sizeof(double)));
+    launch_build_constraints(st, sd, ns, Cm.as<double>());
+    gemm<double>(st, 0, 1, NGp, NCp, NGp, 1.0, KS.as<double>(), NGp, (int64_t)NGp * NGp, Cm.as<double>(), NGp,
+                 (int64_t)NCp * NGp, 0.0, G.as<double>(), NCp, sG, ns, 0);
+    gemm<double>(st, 0, 0, NCp, NCp, NGp, 1.0, Cm.as<double>(), NGp, (int64_t)NCp * NGp, G.as<double>(), NCp, sG,
+                 0.0, Sc.as<double>(), NCp, sC, ns, 0);
+    launch_small_spd_inverse(st, sd, ns, Sc.as<double>(), c->info_d.as<int>() + ns);
+    gemm<double>(st, 0, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NCp, sG, Sc.as<double>(), NCp, sC, 0.0,
+                 c->Phi.as<double>(), NCp, sG, ns, 0);
+    HIPCHK(hipGetLastError());
+  }
   {
     // full coarse basis Phi = [-A_II^{-1} A_IG Phi_G; Phi_G] and the local
     // coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi
@@ -678,7 +773,8 @@ int factor_impl(cb_ctx* c) {
     gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, (int64_t)NIp * NIp, V.as<double>(), NCp, sF, 0.0,
                  PhiF.as<double>(), NCp, sF, ns, 0);
     launch_local_apply(st, sd, g, ns, PhiF.as<double>(), V.as<double>());
-    launch_coarse_gram(st, sd, ns, PhiF.as<double>(), V.as<double>(), AcLoc.as<double>());
+    gemm<double>(st, 1, 0, NCp, NCp, nt, 1.0, PhiF.as<double>(), NCp, sF, V.as<double>(), NCp, sF, 0.0,
+                 AcLoc.as<double>(), NCp, (int64_t)NCp * NCp, ns, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
   }
@@ -715,7 +811,10 @@ int factor_impl(cb_ctx* c) {
     ProfScope cps(c, "coarse_factor");
     cholesky<double>(st, Ac.as<double>(), ldc, 0, ldc, 1, Lc.as<double>(), 0, c->info_d.as<int>() + ns + 1);
     CHK(dalloc(Yc, (size_t)ldc * ldc * sizeof(double)));
-    tri_inverse<double>(st, Ac.as<double>(), ldc, 0, 0, ldc, 1, Lc.as<double>(), 0, Yc.as<double>(), ldc, 0);
+    DevBuf Tc;
+    CHK(dalloc(Tc, (size_t)TRI_SUPER * ldc * sizeof(double)));
+    tri_inverse<double>(st, Ac.as<double>(), ldc, 0, 0, ldc, 1, Lc.as<double>(), 0, Yc.as<double>(), ldc, 0,
+                        Tc.as<double>(), 0);
     CHK(dalloc(PSc, (size_t)ldc * ldc * sizeof(double)));
     gemm<double>(st, 1, 0, ldc, ldc, ldc, 1.0, Yc.as<double>(), ldc, 0, Yc.as<double>(), ldc, 0, 0.0,
                  PSc.as<double>(), ldc, 0, 1, GEMM_LOWER | GEMM_KFROM_DIAG);
@@ -750,6 +849,7 @@ int cb_factor(cb_ctx* c) {
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
   c->factored = false;
+  g_alloc_stream = c->st;
   int rc = c->precision == CB_FP32_LOCAL ? factor_impl<float>(c) : factor_impl<double>(c);
   if (rc != CB_OK) return rc;
   HIPCHK(hipEventRecord(e1, c->st));

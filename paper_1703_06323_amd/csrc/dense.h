@@ -30,10 +30,12 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T
               int* info);
 
 // Y = inverse of the lower-triangular diagonal block [off, off+nb) of L,
-// using the diagonal-tile inverses written by cholesky().
+// using the diagonal-tile inverses written by cholesky().  tmp: workspace of
+// TRI_SUPER * nb elements per matrix (stride sT).
+constexpr int TRI_SUPER = 128;
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY);
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT);
 
 // out = D sym(lower(in)) D, full storage.
 template <typename T, typename TO>

@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace cutbddc {
 namespace {
 
@@ -22,6 +24,7 @@ constexpr int TM = 64;    // output tile rows
 constexpr int TN = 64;    // output tile cols
 constexpr int KT = 16;    // K per LDS stage
 constexpr int BLK = 32;   // Cholesky panel width
+constexpr int SUPER = 128; // super-panel width (K of the trailing updates)
 
 template <typename T> struct Acc;
 // Operand layouts of the 16x16x4 MFMAs (both types): lane l supplies
@@ -118,101 +121,98 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
       }
 }
 
-// Cholesky of the BLK x BLK diagonal tile at (k0, k0) of each matrix, in LDS.
+// Broadcast of lane `l`'s value (l uniform, a compile-time constant after
+// unrolling) to the whole wave.
+__device__ inline double bcast(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float bcast(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Cholesky of the BLK x BLK diagonal tile at (k0, k0) of each matrix, held
+// in registers of one wave (lane i < BLK owns row i; lanes >= BLK idle).
 // Writes L (lower, upper part of the tile zeroed) and L^{-1} into
 // Linv[bz][tile][BLK*BLK].  A non-positive or non-finite pivot sets
 // info[bz] (first failing global row + 1) and is replaced by 1 so that the
 // factorisation continues without NaNs.
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_tile_kernel(T* A, int64_t lda, int64_t sA, int k0,
-                                                         T* Linv, int64_t sL, int* info) {
-  __shared__ T L[BLK][BLK + 1];
-  __shared__ T X[BLK][BLK + 1];
+__global__ __launch_bounds__(64) void potrf_tile_kernel(T* A, int64_t lda, int64_t sA, int k0,
+                                                        T* Linv, int64_t sL, int* info) {
   const int64_t bz = blockIdx.x;
   T* a = A + bz * sA + (int64_t)k0 * lda + k0;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < BLK * BLK; e += 256) L[e / BLK][e % BLK] = a[(int64_t)(e / BLK) * lda + e % BLK];
-  __syncthreads();
+  const int lane = threadIdx.x;
+  const bool own = lane < BLK;
+  T row[BLK];
+#pragma unroll
+  for (int c = 0; c < BLK; ++c) row[c] = own ? a[(int64_t)lane * lda + c] : T(0);
+  int bad = 0;
+#pragma unroll
   for (int j = 0; j < BLK; ++j) {
-    if (tid == 0) {
-      T d = L[j][j];
-      if (!(d > T(0)) || !(d < T(3.0e38))) {
-        if (info && info[bz] == 0) info[bz] = k0 + j + 1;
-        d = T(1);
-      }
-      L[j][j] = sqrt(d);
+    T d = bcast(row[j], j);
+    if (!(d > T(0)) || !(d < T(3.0e38))) {
+      if (!bad) bad = k0 + j + 1;
+      d = T(1);
     }
-    __syncthreads();
-    const T piv = L[j][j];
-    for (int i = j + 1 + tid; i < BLK; i += 256) L[i][j] /= piv;
-    __syncthreads();
-    for (int e = tid; e < BLK * BLK; e += 256) {
-      const int i = e / BLK, l = e % BLK;
-      if (i > j && l > j && l <= i) L[i][l] -= L[i][j] * L[l][j];
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular tile: one column per thread
-  if (tid < BLK) {
-    const int c = tid;
-    for (int i = 0; i < BLK; ++i) {
-      T s = (i == c) ? T(1) : T(0);
-      for (int k = c; k < i; ++k) s -= L[i][k] * X[k][c];
-      X[i][c] = (i < c) ? T(0) : s / L[i][i];
+    const T piv = sqrt(d);
+    const T lij = (lane == j) ? piv : row[j] / piv;
+    if (lane >= j) row[j] = lij;
+#pragma unroll
+    for (int l = j + 1; l < BLK; ++l) {
+      const T llj = bcast(row[j], l);
+      if (lane >= l) row[l] -= lij * llj;
     }
   }
-  __syncthreads();
+  // X = L^{-1} by forward elimination; lane i owns row i of X
+  T x[BLK];
+#pragma unroll
+  for (int c = 0; c < BLK; ++c) x[c] = (c == lane) ? T(1) : T(0);
+#pragma unroll
+  for (int j = 0; j < BLK; ++j) {
+    const T ljj = bcast(row[j], j);
+    if (lane == j) {
+#pragma unroll
+      for (int c = 0; c <= j; ++c) x[c] = x[c] / ljj;
+    }
+#pragma unroll
+    for (int c = 0; c <= j; ++c) {
+      const T xjc = bcast(x[c], j);
+      if (lane > j) x[c] -= row[j] * xjc;
+    }
+  }
+  if (bad && lane == 0 && info && info[bz] == 0) info[bz] = bad;
+  if (!own) return;
   T* li = Linv + bz * sL + (int64_t)(k0 / BLK) * BLK * BLK;
-  for (int e = tid; e < BLK * BLK; e += 256) {
-    const int i = e / BLK, l = e % BLK;
-    a[(int64_t)i * lda + l] = (l <= i) ? L[i][l] : T(0);
-    li[e] = X[i][l];
+#pragma unroll
+  for (int c = 0; c < BLK; ++c) {
+    a[(int64_t)lane * lda + c] = (c <= lane) ? row[c] : T(0);
+    li[lane * BLK + c] = x[c];
   }
 }
 
-// Panel solve: rows r in [k0+BLK, n) of columns [k0, k0+BLK):
-// X = A_panel * L_kk^{-T}.  One workgroup per 64 rows.
+// Copies the diagonal Linv tile into Y's diagonal block (rows/cols i0..i0+BLK).
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_panel_kernel(T* A, int64_t lda, int64_t sA, int n, int k0,
-                                                         const T* Linv, int64_t sL) {
-  __shared__ T P[64][BLK + 1];
-  __shared__ T Li[BLK][BLK + 1];
-  const int64_t bz = blockIdx.y;
-  const int r0 = k0 + BLK + blockIdx.x * 64;
-  T* a = A + bz * sA;
-  const T* li = Linv + bz * sL + (int64_t)(k0 / BLK) * BLK * BLK;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * BLK; e += 256) {
-    const int r = e / BLK, c = e % BLK;
-    P[r][c] = (r0 + r < n) ? a[(int64_t)(r0 + r) * lda + k0 + c] : T(0);
-  }
-  for (int e = tid; e < BLK * BLK; e += 256) Li[e / BLK][e % BLK] = li[e];
-  __syncthreads();
-  for (int e = tid; e < 64 * BLK; e += 256) {
-    const int r = e / BLK, j = e % BLK;
-    if (r0 + r >= n) continue;
-    T s = 0;
-    for (int c = 0; c <= j; ++c) s += P[r][c] * Li[j][c];
-    a[(int64_t)(r0 + r) * lda + k0 + j] = s;
-  }
-}
-
-// Copies the diagonal Linv tile into Y's diagonal block and zeroes the rest
-// of Y's block row to the right of it (Y is built in place block by block).
-template <typename T>
-__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int nb,
-                                                             int i0, const T* Linv, int64_t sL,
-                                                             int tile) {
+__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int i0,
+                                                             const T* Linv, int64_t sL, int tile) {
   const int64_t bz = blockIdx.x;
   T* y = Y + bz * sY;
   const T* li = Linv + bz * sL + (int64_t)tile * BLK * BLK;
-  for (int e = threadIdx.x; e < BLK * nb; e += 256) {
-    const int r = e / nb, c = e % nb;
-    if (c < i0) continue;
-    T v = 0;
-    if (c < i0 + BLK) v = li[r * BLK + (c - i0)];
-    y[(int64_t)(i0 + r) * ldy + c] = v;
-  }
+  for (int e = threadIdx.x; e < BLK * BLK; e += 256)
+    y[(int64_t)(i0 + e / BLK) * ldy + i0 + e % BLK] = li[e];
+}
+
+// Copies an m x n block (row-major, ld) between buffers of a batch.
+template <typename T>
+__global__ __launch_bounds__(256) void copy_block_kernel(const T* src, int64_t lds, int64_t sS, T* dst,
+                                                         int64_t ldd, int64_t sD, int n) {
+  const int64_t bz = blockIdx.y;
+  const int r = blockIdx.x;
+  const T* a = src + bz * sS + (int64_t)r * lds;
+  T* b = dst + bz * sD + (int64_t)r * ldd;
+  for (int c = threadIdx.x; c < n; c += 256) b[c] = a[c];
 }
 
 template <typename T>
@@ -258,43 +258,74 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
 template <typename T>
 void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv, int64_t sL,
               int* info) {
-  for (int k0 = 0; k0 < n; k0 += BLK) {
-    hipLaunchKernelGGL(potrf_tile_kernel<T>, dim3(batch), dim3(256), 0, st, A, lda, sA, k0, Linv,
-                       sL, info);
-    const int rest = n - k0 - BLK;
-    if (rest <= 0) break;
-    hipLaunchKernelGGL(trsm_panel_kernel<T>, dim3((rest + 63) / 64, batch), dim3(256), 0, st, A,
-                       lda, sA, n, k0, (const T*)Linv, sL);
-    T* panel = A + (int64_t)(k0 + BLK) * lda + k0;
-    T* trail = A + (int64_t)(k0 + BLK) * lda + (k0 + BLK);
-    gemm<T>(st, 0, 1, rest, rest, BLK, T(-1), panel, lda, sA, panel, lda, sA, T(1), trail, lda, sA,
-            batch, GEMM_LOWER);
+  // Two-level right-looking blocking: 32-wide panels are factored inside a
+  // SB-wide super-panel (narrow updates), then the trailing matrix gets one
+  // rank-SB update (K = SB) per super-panel.
+  for (int K0 = 0; K0 < n; K0 += SUPER) {
+    const int kend = std::min(K0 + SUPER, n);
+    for (int k0 = K0; k0 < kend; k0 += BLK) {
+      hipLaunchKernelGGL(potrf_tile_kernel<T>, dim3(batch), dim3(64), 0, st, A, lda, sA, k0, Linv,
+                         sL, info);
+      const int rest = n - k0 - BLK;
+      if (rest <= 0) break;
+      T* panel = A + (int64_t)(k0 + BLK) * lda + k0;
+      const T* li = Linv + (int64_t)(k0 / BLK) * BLK * BLK;
+      // panel solve in place: X = A_panel L_kk^{-T} (each output tile reads
+      // only its own rows of the panel)
+      gemm<T>(st, 0, 1, rest, BLK, BLK, T(1), panel, lda, sA, li, BLK, sL, T(0), panel, lda, sA, batch, 0);
+      const int ncols = kend - (k0 + BLK);
+      if (ncols > 0)
+        gemm<T>(st, 0, 1, rest, ncols, BLK, T(-1), panel, lda, sA, panel, lda, sA, T(1),
+                A + (int64_t)(k0 + BLK) * lda + (k0 + BLK), lda, sA, batch, GEMM_LOWER);
+    }
+    const int rest = n - kend;
+    if (rest > 0) {
+      T* P = A + (int64_t)kend * lda + K0;
+      gemm<T>(st, 0, 1, rest, rest, kend - K0, T(-1), P, lda, sA, P, lda, sA, T(1),
+              A + (int64_t)kend * lda + kend, lda, sA, batch, GEMM_LOWER);
+    }
   }
 }
 
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY) {
-  // Y = L_block^{-1} for the diagonal block [off, off+nb) of L (lower).
-  // Y holds the running right-hand side R (block forward substitution on
-  // L Y = I): block row i becomes Linv_ii R_i, then later rows are updated.
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT) {
+  // Y = L_block^{-1} for the diagonal block [off, off+nb) of L (lower) by
+  // block forward substitution on L Y = I.  Y holds the running right-hand
+  // side R; within a SUPER-wide block row the 32-wide steps form
+  // inv(L_SS); the block row's left part becomes inv(L_SS) R_S (through
+  // tmp, SUPER x nb per matrix); rows below get one rank-SUPER update.
   hipLaunchKernelGGL(zero_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
-  for (int i0 = 0; i0 < nb; i0 += BLK) {
-    if (i0 > 0) {
-      // Y[i-block, 0:i0] = Linv_ii * Y[i-block, 0:i0]  (in place: each output
-      // tile reads only its own columns of the same block row)
+  for (int S0 = 0; S0 < nb; S0 += SUPER) {
+    const int send = std::min(S0 + SUPER, nb);
+    for (int i0 = S0; i0 < send; i0 += BLK) {
       const T* li = Linv + (int64_t)((off + i0) / BLK) * BLK * BLK;
-      gemm<T>(st, 0, 0, BLK, i0, BLK, T(1), li, BLK, sLi, Y + (int64_t)i0 * ldy, ldy, sY, T(0),
-              Y + (int64_t)i0 * ldy, ldy, sY, batch, 0);
+      if (i0 > S0)
+        gemm<T>(st, 0, 0, BLK, i0 - S0, BLK, T(1), li, BLK, sLi, Y + (int64_t)i0 * ldy + S0, ldy, sY, T(0),
+                Y + (int64_t)i0 * ldy + S0, ldy, sY, batch, 0);
+      hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(batch), dim3(256), 0, st, Y, ldy, sY, i0, Linv, sLi,
+                         (off + i0) / BLK);
+      const int rin = send - i0 - BLK;
+      if (rin > 0) {
+        const T* Lli = L + (int64_t)(off + i0 + BLK) * ldl + (off + i0);
+        gemm<T>(st, 0, 0, rin, i0 + BLK - S0, BLK, T(-1), Lli, ldl, sL, Y + (int64_t)i0 * ldy + S0, ldy, sY, T(1),
+                Y + (int64_t)(i0 + BLK) * ldy + S0, ldy, sY, batch, 0);
+      }
     }
-    hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(batch), dim3(256), 0, st, Y, ldy, sY, nb, i0,
-                       Linv, sLi, (off + i0) / BLK);
-    const int rest = nb - i0 - BLK;
-    if (rest <= 0) break;
-    // Y[l, 0:i0+BLK] -= L[l, i-block] * Y[i-block, 0:i0+BLK] for rows l below
-    const T* Lli = L + (int64_t)(off + i0 + BLK) * ldl + (off + i0);
-    gemm<T>(st, 0, 0, rest, i0 + BLK, BLK, T(-1), Lli, ldl, sL, Y + (int64_t)i0 * ldy, ldy, sY,
-            T(1), Y + (int64_t)(i0 + BLK) * ldy, ldy, sY, batch, 0);
+    const int h = send - S0;
+    if (S0 > 0) {
+      // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0]
+      gemm<T>(st, 0, 0, h, S0, h, T(1), Y + (int64_t)S0 * ldy + S0, ldy, sY, Y + (int64_t)S0 * ldy, ldy, sY, T(0),
+              tmp, S0, sT, batch, GEMM_KTO_DIAG);
+      hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, (const T*)tmp, (int64_t)S0, sT,
+                         Y + (int64_t)S0 * ldy, ldy, sY, S0);
+    }
+    const int rest = nb - send;
+    if (rest > 0) {
+      const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
+      gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
+              Y + (int64_t)send * ldy, ldy, sY, batch, 0);
+    }
   }
 }
 
@@ -310,7 +341,7 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
                         const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int);         \
   template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, T*, int64_t, int*);    \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, const T*, \
-                               int64_t, T*, int64_t, int64_t);
+                               int64_t, T*, int64_t, int64_t, T*, int64_t);
 INST(double)
 INST(float)
 #undef INST

@@ -31,23 +31,31 @@
 namespace cutbddc {
 namespace {
 
+// Disjoint sets over [0, n): union by size with path halving; every root
+// also records the smallest member of its set.
 struct UnionFind {
-  std::vector<int64_t> p;
-  explicit UnionFind(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
-  int64_t find(int64_t x) {
+  std::vector<int32_t> p, sz, mn;
+  explicit UnionFind(int64_t n) : p(n), sz(n, 1), mn(n) {
+    std::iota(p.begin(), p.end(), 0);
+    std::iota(mn.begin(), mn.end(), 0);
+  }
+  int32_t find(int32_t x) {
     while (p[x] != x) {
       p[x] = p[p[x]];
       x = p[x];
     }
     return x;
   }
-  void unite(int64_t a, int64_t b) {
+  void unite(int32_t a, int32_t b) {
     a = find(a);
     b = find(b);
     if (a == b) return;
-    if (a < b) std::swap(a, b);
-    p[a] = b;  // root = smaller id
+    if (sz[a] < sz[b]) std::swap(a, b);
+    p[b] = a;
+    sz[a] += sz[b];
+    mn[a] = std::min(mn[a], mn[b]);
   }
+  int32_t smallest(int32_t x) { return mn[find(x)]; }
 };
 
 inline bool same_set(const int32_t* a, const int32_t* b) {
@@ -111,8 +119,10 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
   t.n_sub = m * m * m;
   auto cell_id = [&](int64_t i, int64_t j, int64_t k) { return i + N * (j + N * k); };
   auto node_id = [&](int64_t I, int64_t J, int64_t K) { return I + N1 * (J + N1 * K); };
+  std::vector<int32_t> blk(N);   // block index of each cell layer (avoids divisions)
+  for (int i = 0; i < N; ++i) blk[i] = i / s;
   auto sub_of = [&](int64_t i, int64_t j, int64_t k) {
-    return (int32_t)((i / s) + m * ((j / s) + m * (k / s)));
+    return (int32_t)(blk[i] + m * (blk[j] + m * blk[k]));
   };
   auto active = [&](int64_t c) { return cell_count[c] > 0; };
 
@@ -160,39 +170,44 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
         }
     std::vector<uint8_t> rg(nd, 0);
     for (int64_t d = 0; d < nd; ++d)
-      if (grounded[d]) rg[uf.find(d)] = 1;
+      if (grounded[d]) rg[uf.find((int32_t)d)] = 1;
     for (int64_t d = 0; d < nd; ++d)
-      if (!rg[uf.find(d)]) {
+      if (!rg[uf.find((int32_t)d)]) {
         err = "an active component touches no Dirichlet node (singular operator)";
         return -2;
       }
   }
 
   // ---- subdomain sets S(xi) ----------------------------------------------
+  // per DOF node: subdomains of the active cells among its 8 neighbours,
+  // ascending (the cells are visited in ascending subdomain order up to
+  // duplicates, which are merged by insertion)
   t.S.assign(nd * 8, -1);
   t.card.assign(nd, 0);
-  for (int64_t k = 0; k < N; ++k)
-    for (int64_t j = 0; j < N; ++j)
-      for (int64_t i = 0; i < N; ++i) {
-        if (!active(cell_id(i, j, k))) continue;
-        int32_t w = sub_of(i, j, k);
-        for (int a = 0; a < 8; ++a) {
-          int32_t d = t.dof_of_node[node_id(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1))];
-          if (d < 0) continue;
-          int32_t* Sd = &t.S[d * 8];
-          int c = t.card[d];
-          bool found = false;
-          for (int q = 0; q < c; ++q)
-            if (Sd[q] == w) found = true;
-          if (found) continue;
-          int q = c;
-          while (q > 0 && Sd[q - 1] > w) {
-            Sd[q] = Sd[q - 1];
-            --q;
-          }
-          Sd[q] = w;
-          t.card[d] = (uint8_t)(c + 1);
-        }
+  for (int64_t K = 1; K < N; ++K)
+    for (int64_t J = 1; J < N; ++J)
+      for (int64_t I = 1; I < N; ++I) {
+    const int32_t d = t.dof_of_node[node_id(I, J, K)];
+    if (d < 0) continue;
+    int32_t* Sd = &t.S[(int64_t)d * 8];
+    int c = 0;
+    for (int u = 0; u < 8; ++u) {
+      const int64_t ci = I - 1 + (u & 1), cj = J - 1 + ((u >> 1) & 1), ck = K - 1 + ((u >> 2) & 1);
+      if (!active(cell_id(ci, cj, ck))) continue;
+      const int32_t w = sub_of(ci, cj, ck);
+      bool found = false;
+      for (int q = 0; q < c; ++q)
+        if (Sd[q] == w) found = true;
+      if (found) continue;
+      int q = c;
+      while (q > 0 && Sd[q - 1] > w) {
+        Sd[q] = Sd[q - 1];
+        --q;
+      }
+      Sd[q] = w;
+      ++c;
+    }
+    t.card[d] = (uint8_t)c;
       }
 
   // ---- links and objects -------------------------------------------------
@@ -202,17 +217,19 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
     int8_t axis;
   };
   std::vector<Link> links;
-  for (int64_t a = 0; a < nd; ++a) {
-    if (t.card[a] < 2) continue;
-    int64_t node = t.dof_node[a];
-    int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
+  for (int64_t K = 1; K < N; ++K)
+    for (int64_t J = 1; J < N; ++J)
+      for (int64_t I = 1; I < N; ++I) {
+    const int64_t node = node_id(I, J, K);
+    const int32_t a = t.dof_of_node[node];
+    if (a < 0 || t.card[a] < 2) continue;
     int64_t ijk[3] = {I, J, K};
     for (int axis = 0; axis < 3; ++axis) {
       int64_t step = axis == 0 ? 1 : (axis == 1 ? N1 : N1 * N1);
       if (ijk[axis] + 1 > N) continue;
       int32_t b = t.dof_of_node[node + step];
       if (b < 0 || t.card[b] < 2) continue;
-      if (!same_set(&t.S[a * 8], &t.S[(int64_t)b * 8])) continue;
+      if (!same_set(&t.S[(int64_t)a * 8], &t.S[(int64_t)b * 8])) continue;
       int o1 = axis == 0 ? 1 : 0;
       int o2 = axis == 2 ? 1 : 2;
       int32_t St[4];
@@ -229,7 +246,7 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
         }
       bool full = true;
       for (int q = 0; q < t.card[a]; ++q) {
-        int32_t w = t.S[a * 8 + q];
+        int32_t w = t.S[(int64_t)a * 8 + q];
         bool present = false;
         for (int z = 0; z < nst; ++z)
           if (St[z] == w) present = true;
@@ -237,32 +254,35 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
       }
       if (!full) continue;
       links.push_back({(int32_t)a, b, (int8_t)axis});
-      uf.unite(a, b);
+      uf.unite((int32_t)a, b);
     }
-  }
+      }
   // component root = smallest DOF id of the component
   std::vector<int32_t> comp_of(nd, -1);
   std::vector<int64_t> roots;
   for (int64_t a = 0; a < nd; ++a) {
     if (t.card[a] < 2) continue;
-    int64_t r = uf.find(a);
-    if (r == a) {
+    if (uf.smallest((int32_t)a) == a) {
       comp_of[a] = (int32_t)roots.size();
       roots.push_back(a);
     }
   }
   for (int64_t a = 0; a < nd; ++a)
-    if (t.card[a] >= 2) comp_of[a] = comp_of[uf.find(a)];
+    if (t.card[a] >= 2) comp_of[a] = comp_of[uf.smallest((int32_t)a)];
   const int64_t ncomp = (int64_t)roots.size();
   std::vector<uint8_t> is_face(ncomp, 0);
   for (int axis = 0; axis < 3; ++axis) {
     int o1 = axis == 0 ? 1 : 0;
     int o2 = axis == 2 ? 1 : 2;
-    for (int64_t k = 0; k < N; ++k)
-      for (int64_t j = 0; j < N; ++j)
-        for (int64_t i = 0; i < N; ++i) {
-          int64_t c3[3] = {i, j, k};
-          if (c3[axis] + 1 >= N || ((c3[axis] + 1) % s) != 0) continue;
+    // cells lo on the last layer of a block, hi across the block boundary
+    for (int64_t plane = s - 1; plane + 1 < N; plane += s)
+      for (int64_t v = 0; v < N; ++v)
+        for (int64_t u = 0; u < N; ++u) {
+          int64_t c3[3];
+          c3[axis] = plane;
+          c3[o1] = u;
+          c3[o2] = v;
+          const int64_t i = c3[0], j = c3[1], k = c3[2];
           int64_t lo = cell_id(i, j, k);
           int64_t h3[3] = {i, j, k};
           h3[axis] += 1;
@@ -361,12 +381,12 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
     for (int64_t q = lptr[c]; q < lptr[c + 1]; ++q) {
       if (cls[q - lptr[c]] == 2) continue;
       int64_t pa = pos(links[lidx[q]].a), pb = pos(links[lidx[q]].b);
-      if (pa >= 0 && pb >= 0) lu.unite(pa, pb);
+      if (pa >= 0 && pb >= 0) lu.unite((int32_t)pa, (int32_t)pb);
     }
     std::vector<std::vector<int64_t>> parts;
     std::vector<int64_t> part_of(rest.size(), -1);
     for (int64_t r = 0; r < (int64_t)rest.size(); ++r) {
-      int64_t root = lu.find(r);
+      int64_t root = lu.find((int32_t)r);
       if (part_of[root] < 0) {
         part_of[root] = (int64_t)parts.size();
         parts.emplace_back();

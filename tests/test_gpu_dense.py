@@ -9,7 +9,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,batch", [(1, 1), (31, 2), (32, 1), (33, 3), (100, 2), (257, 2)])
+@pytest.mark.parametrize("n,batch", [(1, 1), (31, 2), (32, 1), (33, 3), (100, 2), (257, 2), (300, 3), (700, 1)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_spd_inverse(n, batch, precision):
     from paper_1703_06323_amd.cutbddc import dense_spd_inverse
