@@ -167,6 +167,17 @@ int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_c
 /* Dense coarse matrix A_c [n_coarse^2] (row-major, host) after cb_factor. */
 int cb_export_coarse(const cb_ctx* c, double* Ac);
 
+/* Host-only indexing (no device work): DOF numbering, subdomain sets,
+ * objects (Sect. 3.2), variant-1 splitting (Sect. 4.4) and coarse numbering
+ * built from given per-cell kept-point counts cell_count [N^3] (> 0 means
+ * active), exactly as cb_setup does after its classification kernel.
+ * info receives n_dof, n_sub, n_coarse, n_objects, n_iface; call once with
+ * NULL arrays to size them, then again to fill (layouts as in
+ * cb_export_indexing).  Errors: CB_ERR_ARG, CB_ERR_SINGULAR. */
+int cb_host_indexing(const cb_problem* p, const int32_t* cell_count, cb_info* info, int64_t* dof_node,
+                     int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type,
+                     int32_t* coarse_of_obj);
+
 /* Batched SPD inverse building block used by the local and coarse
  * factorisations (blocked Cholesky, triangular inverse, Y^T Y on MFMA):
  * Ainv[b] = A[b]^{-1} for `batch` row-major n x n host matrices, computed on

@@ -182,6 +182,23 @@ void reference_matrices(const double xi[8], double K[64], double M[64]) {
   }
 }
 
+// Reuse of host indexing storage across contexts (avoids re-faulting the
+// pages of large fresh allocations on every setup).
+std::mutex g_topo_mu;
+std::vector<Topology*> g_topo_pool;
+Topology* take_topology() {
+  std::lock_guard<std::mutex> g(g_topo_mu);
+  if (g_topo_pool.empty()) return new Topology();
+  Topology* t = g_topo_pool.back();
+  g_topo_pool.pop_back();
+  return t;
+}
+void give_topology(Topology* t) {
+  std::lock_guard<std::mutex> g(g_topo_mu);
+  if (g_topo_pool.size() < 4) g_topo_pool.push_back(t);
+  else delete t;
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
@@ -198,6 +215,7 @@ struct cb_ctx {
   bool prof = false;
   std::map<std::string, ProfEntry> prof_ev;
   ~cb_ctx() {
+    give_topology(topo_p);
     for (auto& kv : prof_ev)
       for (auto& e : kv.second.ev) {
         (void)hipEventDestroy(e.first);
@@ -205,7 +223,8 @@ struct cb_ctx {
       }
   }
   Geometry geo;
-  Topology topo;
+  Topology* topo_p = take_topology();
+  Topology& topo = *topo_p;
   int N = 0, s = 0, m = 0, ns = 0;
   double h = 0;
   int weighting = 1, objects = 0, variant = 1, precision = 0, full_elements = 0;
@@ -419,6 +438,44 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int32_t* iters, double* relres
 extern "C" {
 
 const char* cb_last_error(void) { return g_err.c_str(); }
+
+int cb_host_indexing(const cb_problem* p, const int32_t* cell_count, cb_info* info, int64_t* dof_node,
+                     int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type, int32_t* coarse_of_obj) {
+  if (!p || !cell_count || !info) return fail(CB_ERR_ARG, "null argument");
+  const int N = p->n_cells, s = p->sub_cells;
+  if (N < 1 || s < 1 || N % s != 0) return fail(CB_ERR_ARG, "n_cells must be >= 1 and divisible by sub_cells");
+  if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
+    return fail(CB_ERR_ARG, "invalid ball arrays");
+  Geometry geo;
+  geo.N = N;
+  geo.s = s;
+  geo.objects = p->objects;
+  geo.variant = p->coarse_variant;
+  geo.centres.assign(p->ball_centres, p->ball_centres + 3 * p->n_balls);
+  geo.radii.assign(p->ball_radii, p->ball_radii + p->n_balls);
+  std::unique_ptr<Topology> t(new Topology());
+  std::string err;
+  const double t0 = now_ms();
+  const int rc = build_topology(geo, cell_count, *t, err);
+  if (rc == -2) return fail(CB_ERR_SINGULAR, err);
+  if (rc != 0) return fail(CB_ERR_ARG, err);
+  *info = cb_info{};
+  info->n_dof = t->n_dof;
+  info->n_sub = t->n_sub;
+  info->n_coarse = t->n_coarse;
+  info->n_objects = (int32_t)t->obj_type.size();
+  info->n_iface = t->n_iface;
+  info->max_coarse_per_sub = t->maxC;
+  info->t_topology_ms = now_ms() - t0;
+  if (dof_node) std::memcpy(dof_node, t->dof_node.data(), t->n_dof * sizeof(int64_t));
+  if (card)
+    for (int64_t d = 0; d < t->n_dof; ++d) card[d] = t->card[d];
+  if (obj_ptr) std::memcpy(obj_ptr, t->obj_ptr.data(), t->obj_ptr.size() * sizeof(int64_t));
+  if (obj_dofs) std::memcpy(obj_dofs, t->obj_dofs.data(), t->obj_dofs.size() * sizeof(int64_t));
+  if (obj_type) std::memcpy(obj_type, t->obj_type.data(), t->obj_type.size());
+  if (coarse_of_obj) std::memcpy(coarse_of_obj, t->coarse_of_obj.data(), t->coarse_of_obj.size() * sizeof(int32_t));
+  return CB_OK;
+}
 
 int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv) {
   g_alloc_stream = nullptr;

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -64,6 +65,12 @@ struct Topology {
 //   -2: an active component without Dirichlet node (singular operator)
 int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t,
                    std::string& err);
+
+// Empties every array of t but keeps their capacity for the next build.
+void reset_topology(Topology& t);
+
+// Runs f(begin, end) over chunks of [0, n) on the indexing thread pool.
+void parallel_rows(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 
 // Exact class of the FE edge from grid node (I,J,K) to (I,J,K)+e_axis:
 // 0 interior (edge inside Omega), 1 exterior (edge misses Omega), 2 cut.

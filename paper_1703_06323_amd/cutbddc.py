@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
     lib.cb_export_cut_matrices.argtypes = [vp, vp, vp, vp]
     lib.cb_export_coarse.argtypes = [vp, vp]
+    lib.cb_host_indexing.argtypes = [C.POINTER(cb_problem), vp, C.POINTER(cb_info)] + [vp] * 6
     lib.cb_profile.argtypes = [vp, C.c_int32]
     lib.cb_profile_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
@@ -89,7 +90,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
                  "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
-                 "cb_dense_spd_inverse", "cb_profile", "cb_profile_time"):
+                 "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -261,6 +262,39 @@ class Solver:
         A = np.zeros((nc, nc))
         _check(_lib.cb_export_coarse(self.ctx, A.ctypes.data_as(C.c_void_p)))
         return A
+
+
+def _problem_struct(problem):
+    centres = np.ascontiguousarray(problem.centres, dtype=np.float64).reshape(-1)
+    radii = np.ascontiguousarray(problem.radii, dtype=np.float64)
+    P = C.POINTER(C.c_double)
+    p = cb_problem(int(problem.n), int(problem.s), int(radii.size), centres.ctypes.data_as(P),
+                   radii.ctypes.data_as(P), None, int(problem.weighting), int(problem.objects),
+                   int(problem.coarse_variant), int(problem.local_precision),
+                   int(problem.full_elements))
+    return p, (centres, radii)
+
+
+def host_indexing(problem, cell_count) -> dict:
+    """Host-only indexing from given per-cell kept-point counts (no GPU)."""
+    lib = load_library()
+    p, keep = _problem_struct(problem)
+    cnt = np.ascontiguousarray(cell_count, dtype=np.int32)
+    inf = cb_info()
+    _check(lib.cb_host_indexing(C.byref(p), cnt.ctypes.data_as(C.c_void_p), C.byref(inf),
+                                None, None, None, None, None, None))
+    out = {
+        "dof_node": np.zeros(inf.n_dof, np.int64), "card": np.zeros(inf.n_dof, np.int32),
+        "obj_ptr": np.zeros(inf.n_objects + 1, np.int64), "obj_dofs": np.zeros(inf.n_iface, np.int64),
+        "obj_type": np.zeros(inf.n_objects, np.int8), "coarse_of_obj": np.zeros(inf.n_objects, np.int32),
+    }
+    _check(lib.cb_host_indexing(C.byref(p), cnt.ctypes.data_as(C.c_void_p), C.byref(inf),
+                                *[out[k].ctypes.data_as(C.c_void_p) for k in
+                                  ("dof_node", "card", "obj_ptr", "obj_dofs", "obj_type",
+                                   "coarse_of_obj")]))
+    out["n_coarse"] = int(inf.n_coarse)
+    out["t_ms"] = float(inf.t_topology_ms)
+    return out
 
 
 def dense_spd_inverse(A: np.ndarray, precision: int = 0) -> np.ndarray:

@@ -1,0 +1,54 @@
+"""The library's host C++ indexing (DOFs, subdomain sets, objects, variant-1
+splitting, coarse numbering) against the oracle, bit-exact, on the CPU: the
+cell classification is taken from the oracle and fed to the library."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assemble, topology
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_1703_06323_amd", "libcutbddc.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+CASES = {
+    "single_ball_standard": lambda: W.single_ball().with_options(coarse_variant=0),
+    "single_ball_v1": lambda: W.single_ball(),
+    "balls16_s4_v1": lambda: W.random_balls(16, 4, 6, 3),
+    "balls24_s8_ce": lambda: W.random_balls(24, 8, 10, 4).with_options(objects=1),
+    "balls32_s8_v1": lambda: W.random_balls(32, 8, 14, 5),
+    "balls20_s4_dense": lambda: W.random_balls(20, 4, 30, 8),
+    "uncut12_s4": lambda: W.uncut(12, 4),
+    "uncut6_s2": lambda: W.uncut(6, 2),
+    "one_subdomain": lambda: W.random_balls(8, 8, 3, 5),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_host_indexing_matches_oracle(name):
+    from paper_1703_06323_amd.cutbddc import host_indexing
+    p = CASES[name]()
+    d = assemble.discretise(p)
+    t = topology.build(p, d)
+    g = host_indexing(p, d.count)
+    assert np.array_equal(g["dof_node"], d.dof_node)
+    assert np.array_equal(g["card"], t.card())
+    assert np.array_equal(g["obj_ptr"], t.obj_ptr)
+    assert np.array_equal(g["obj_dofs"], t.obj_dofs)
+    assert np.array_equal(g["obj_type"], t.obj_type)
+    assert np.array_equal(g["coarse_of_obj"], t.coarse_of_obj)
+    assert g["n_coarse"] == t.n_coarse
+
+
+def test_host_indexing_rejects_floating_pocket():
+    from paper_1703_06323_amd.cutbddc import host_indexing, CBError, CB_ERR_SINGULAR
+    rng = np.random.default_rng(0)
+    dirs = rng.standard_normal((400, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    p = W.Problem(n=16, s=4, centres=0.5 + 0.3 * dirs, radii=np.full(400, 0.12))
+    d = assemble.discretise(p, check_floating=False)
+    with pytest.raises(CBError) as e:
+        host_indexing(p, d.count)
+    assert e.value.code == CB_ERR_SINGULAR
