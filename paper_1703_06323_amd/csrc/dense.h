@@ -23,6 +23,12 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
           int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
           int batch, int mode);
 
+// Times every GEMM tile shape on scratch matrices of the bucket of
+// (TA, TB, M, N, K, batch, mode) and records the fastest for later calls of
+// that bucket (synchronous, default stream).  Returns the chosen shape.
+template <typename T>
+int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode);
+
 // In-place lower Cholesky of n x n matrices (n a multiple of CHOL_BLOCK).
 // Linv receives the inverses of the diagonal tiles: sL >= (n/32)*32*32.
 template <typename T>

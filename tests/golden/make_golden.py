@@ -9,7 +9,8 @@ Outputs (next to this script):
   cut_cube_64_sample.npz  seeded sample (16384 DOFs) of the FP64 PCG solution
                           at rtol 1e-8, plus its full 2-norm
 With the argument `96`, the same files for the 96^3 forty-ball workload with
-log-normal conductivity (cut_cube_96.json, cut_cube_96_sample.npz).
+log-normal conductivity (cut_cube_96.json, cut_cube_96_sample.npz); with
+`grad`, gradient_64.npz (adjoint gradient of the differentiation workload).
 """
 import hashlib
 import json
@@ -65,5 +66,34 @@ def main(which="64"):
     print(json.dumps(meta, indent=1))
 
 
+def gradient():
+    """Adjoint gradient of J = 0.5 |u - u_t|^2 on the 64^3 twenty-ball
+    workload with kappa = exp(theta): u_t = solution at theta = 0 plus the
+    seeded noise; 32 cells drawn from the active cells (generator stream
+    continued).  Solves at rtol 1e-12."""
+    from oracle import adjoint
+    gc = W.gradient_case()
+    p = gc.problem
+    t0 = time.time()
+    s0 = OracleSolver(p.with_options(kappa=None))
+    u0, it0, _ = s0.solve(rtol=1e-12)
+    ut = u0 + gc.target_noise[s0.d.dof_node]
+    s = OracleSolver(p)
+    u, it, _ = s.solve(rtol=1e-12)
+    lam, itl, _ = s.solve_rhs(u - ut, rtol=1e-12)
+    dth, df = adjoint.gradients(s.d, u, lam)
+    cells = np.sort(gc.rng.choice(s.d.active, size=32, replace=False))
+    rng = np.random.default_rng(777)
+    nodes = np.sort(rng.choice((p.n + 1) ** 3, size=4096, replace=False))
+    np.savez_compressed(os.path.join(HERE, "gradient_64.npz"), ut=ut, cells=cells, dtheta_cells=dth[cells],
+                        nodes=nodes, df_nodes=df[nodes], dtheta_norm=np.array([np.linalg.norm(dth)]),
+                        df_norm=np.array([np.linalg.norm(df)]), J=np.array([0.5 * np.sum((u - ut) ** 2)]))
+    print("gradient golden written", time.time() - t0, "s; iterations", it0, it, itl)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "64")
+    arg = sys.argv[1] if len(sys.argv) > 1 else "64"
+    if arg == "grad":
+        gradient()
+    else:
+        main(arg)
