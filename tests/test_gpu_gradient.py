@@ -1,7 +1,8 @@
 """Adjoint gradient through torch.autograd on the GPU, against the oracle's
 adjoint gradient and central finite differences of the GPU forward solve
-(h = 1e-6, solves at rtol 1e-12 so that the difference quotient is not
-dominated by solver error)."""
+(solves at rtol 1e-13; h = 1e-6 on the small case, h = 1e-3 at 64^3 where the
+per-cell sensitivity is small enough that solver error would dominate the
+difference quotient at h = 1e-6)."""
 import os
 
 import numpy as np
@@ -31,12 +32,24 @@ def loss_and_grads(problem, theta, f, ut, rtol=1e-12):
     return float(J), th.grad.cpu().numpy(), fv.grad.cpu().numpy()
 
 
-def forward_J(problem, theta, f, ut, rtol=1e-13):
+def forward_u(problem, theta, f, rtol=1e-13):
     from paper_1703_06323_amd import Solver
     s = Solver(problem.with_options(kappa=np.exp(theta)))
     s.factor()
     u, it, rel = s.solve(torch.tensor(f, device="cuda"), rtol=rtol)
+    return u
+
+
+def forward_J(problem, theta, f, ut, rtol=1e-13):
+    u = forward_u(problem, theta, f, rtol)
     return 0.5 * float(torch.sum((u - torch.tensor(ut, device="cuda")) ** 2))
+
+
+def fd_quotient(up, um, ut, eps):
+    """(J(+) - J(-)) / (2 eps) without cancellation in J:
+    J(+) - J(-) = 0.5 sum (u+ - u-) (u+ + u- - 2 u_t)."""
+    utt = torch.tensor(ut, device="cuda")
+    return 0.5 * float(torch.sum((up - um) * (up + um - 2 * utt))) / (2 * eps)
 
 
 def test_gradient_matches_oracle_small():
@@ -95,15 +108,18 @@ def test_gradient_full_size_against_oracle_and_fd():
     np.testing.assert_allclose(dth[cells], g["dtheta_cells"], rtol=1e-7, atol=1e-7 * np.abs(g["dtheta_cells"]).max())
     assert abs(np.linalg.norm(dth) - g["dtheta_norm"][0]) <= 1e-7 * g["dtheta_norm"][0]
     np.testing.assert_allclose(df[g["nodes"]], g["df_nodes"], rtol=1e-7, atol=1e-7 * np.abs(g["df_nodes"]).max())
-    eps = 1e-6
-    worst = 0.0
-    floor = 1e-6 * np.abs(dth[cells]).max()
+    # A single cell moves u by ~1e-7 ||u|| per unit theta, so at h = 1e-6 the
+    # 1e-13 solve residual is ~1e-3 of (u+ - u-); h = 1e-3 keeps that noise
+    # near 1e-6 while the central-difference truncation is O(h^2) ~ 1e-6.
+    eps = 1e-3
+    errs = []
     for cell in cells:
         tp, tm = gc.theta.copy(), gc.theta.copy()
         tp[cell] += eps
         tm[cell] -= eps
-        fd = (forward_J(p, tp, p.f, g["ut"]) - forward_J(p, tm, p.f, g["ut"])) / (2 * eps)
-        err = abs(fd - dth[cell]) / max(abs(fd), floor)
-        worst = max(worst, err)
-    print(f"worst relative FD error over 32 cells: {worst:.2e}")
-    assert worst <= 1e-4
+        fd = fd_quotient(forward_u(p, tp, p.f), forward_u(p, tm, p.f), g["ut"], eps)
+        errs.append(abs(fd - dth[cell]) / max(abs(fd), 1e-300))
+        print(f"cell {cell}: adjoint {dth[cell]: .6e} fd {fd: .6e} rel {errs[-1]:.2e}")
+    errs = np.array(errs)
+    print(f"FD relative error over 32 cells: median {np.median(errs):.2e} max {errs.max():.2e}")
+    assert np.median(errs) <= 1e-5 and errs.max() <= 1e-4
