@@ -133,7 +133,41 @@ int cb_apply_operator(cb_ctx* c, const double* x_dev, double* y_dev);       /* y
 int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev); /* z = M r      */
 int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev);           /* b = M_cut f  */
 
+/* Totals over every problem of the context (one problem for cb_setup). */
 int cb_query(const cb_ctx* c, cb_info* out);
+
+/* ---- batches of independent problems -------------------------------------
+ * Many independent meshes (the per-mesh problem statement of Sect. 2.2 for
+ * each) held by one context, so that every kernel launch of setup, factor
+ * and solve covers all of them: subdomains of all problems form one batch
+ * of local factorisations, the coarse matrices are factored in groups of
+ * equal padded order, and the PCG runs all problems in lock step with a
+ * per-problem convergence flag on the device (a converged problem stops
+ * changing; the iteration is replayed from a captured HIP graph).
+ *
+ * cb_setup_batch: problems[0..n) as in cb_setup; they must share sub_cells
+ * and every option field (weighting, objects, coarse_variant,
+ * local_precision, full_elements); N, balls and kappa are per problem.
+ * Errors as cb_setup (the message names the problem), CB_ERR_ARG for n < 1
+ * or differing options.  cb_factor factors all problems; cb_query returns
+ * totals.  The single-problem entry points (cb_solve, cb_solve_rhs, cb_grad,
+ * cb_apply_*, cb_load, cb_export_*) return CB_ERR_STATE on a context with
+ * more than one problem. */
+int cb_setup_batch(const cb_problem* problems, int32_t n, void* stream, cb_ctx** out);
+
+/* Solves every problem k of the context: b_k = M_cut f_k, PCG with M until
+ * |r_k| < rtol |b_k| (Sect. 5.1), each problem stopping on its own.
+ * f_nodes_dev: host array of n device pointers to [(N_k+1)^3] nodal values
+ * (the array or an entry may be NULL: f = 1).  u_dev: host array of n device
+ * pointers to [n_dof_k] outputs.  iters, final_relres: host arrays [n] or
+ * NULL.  Returns CB_ERR_NOT_SPD if some problem broke down, else
+ * CB_ERR_NO_CONVERGENCE if some problem hit max_iter (every u_k still holds
+ * its last iterate), else CB_OK.  Synchronises the context stream. */
+int cb_solve_batch(cb_ctx* c, const double* const* f_nodes_dev, double* const* u_dev, double rtol,
+                   int32_t max_iter, int32_t* iters, double* final_relres);
+
+/* Counts of problem k of the context (fields as cb_info; times are 0). */
+int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out);
 
 /* Measurement hooks.  With profiling enabled the library brackets every
  * launch of the named kernel groups with HIP events on the context stream:

@@ -4,4 +4,4 @@ The product is libcutbddc.so (HIP kernels for gfx950 behind the C ABI of
 include/cutbddc.h); `cutbddc` is its ctypes binding and `autograd` wraps the
 solve in a torch.autograd.Function.
 """
-from .cutbddc import Solver, CBError, load_library, LIB_PATH  # noqa: F401
+from .cutbddc import BatchSolver, Solver, CBError, load_library, LIB_PATH  # noqa: F401

@@ -16,14 +16,18 @@ struct SubDev {
   const int32_t* G_obj;           // [ns*NGp] local coarse row of each interface row or -1
   const int32_t* C_ids;           // [ns*NCp] global coarse id of each local coarse row (-1 pad)
   const int32_t* bloc;            // [ns*(s+1)^3] block node -> local row or -1
+  const int32_t* sub_prob;        // [ns] problem of each subdomain
+  const int32_t* sub_blk;         // [ns] subdomain index within its problem
+  const int32_t* active;          // [P] problems whose PCG still runs, or null
 };
 
+// Grid data of all problems (concatenated cell arrays).
 struct GridDev {
-  int N, s;
-  double h;
-  const int32_t* cellinfo;        // [N^3]
-  const double* kappa;            // [N^3]
-  const double* Kc;               // [n_cut*36]
+  const ProbDev* prob;            // [P]
+  int s;                          // cells per subdomain side (common to the batch)
+  const int32_t* cellinfo;        // concatenated cells
+  const double* kappa;
+  const double* Kc;               // [n_cut_total*36]
 };
 
 void bddc_set_reference(const double* Kref);
@@ -36,8 +40,12 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
 void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y);
 void launch_build_constraints(hipStream_t st, const SubDev& sd, int ns, double* Cm);
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info);
-void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,
-                            const int32_t* cs_row, const SubDev& sd, const double* AcLoc, double* Ac);
+// Coarse matrix of every problem p as its own ldc_p x ldc_p block at
+// Ac + ac_off_p (identity on the padding rows); prow_off[p] = first padded
+// row of problem p in the launch, prow_off[P] = total.  Ac zero-filled.
+void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows,
+                            const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,
+                            const double* AcLoc, double* Ac);
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out);
@@ -46,7 +54,10 @@ void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt
                           const double* Dw, const double* r, const double* t, double* z, double* cloc);
 void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int32_t* cs_sub,
                        const int32_t* cs_row, int NCp, const double* cloc, double* c);
-void launch_gemv(hipStream_t st, int n, int ld, const double* A, const double* x, double* y);
+// y_c = sum_j Ainv_p[c - coarse_off_p][j] x[coarse_off_p + j] for every
+// global coarse row c (p = coarse_prob[c]): block-diagonal coarse solve.
+void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const int32_t* coarse_prob,
+                        const double* Ainv, const double* x, double* y);
 void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,
                        double* z);
 void launch_iface_average(hipStream_t st, int64_t n_iface, const int64_t* iface_node, const int64_t* if_ptr,

@@ -39,18 +39,24 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
   double* rho = smem + 2 * nt;      // [NCp]
   double* cnt = rho + NCp;          // [NCp]
   const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
-  const int s = g.s, m = g.N / g.s, N = g.N;
-  const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
+  const ProbDev pr = g.prob[sd.sub_prob[w]];
+  const int s = g.s, m = pr.m, N = pr.N;
+  const int blk = sd.sub_blk[w];
+  const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
   const int64_t N1 = N + 1;
   const int s1 = s + 1;
   const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
+  const int32_t* cellinfo = g.cellinfo + pr.cell_off;
+  const double* kappa = g.kappa + pr.cell_off;
+  const double h = pr.h;
   T* K = Kmat + (int64_t)w * nt * nt;
   const int tid = threadIdx.x;
 
+  // node of a local row, numbered within the problem's grid
   auto row_node = [&](int r) -> int64_t {
-    if (r < NIp) return r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+    if (r < NIp) return r < nI ? sd.I_idx[(int64_t)w * NIp + r] - pr.node_off : -1;
     const int j = r - NIp;
-    return j < nG ? sd.G_idx[(int64_t)w * NGp + j] : -1;
+    return j < nG ? sd.G_idx[(int64_t)w * NGp + j] - pr.node_off : -1;
   };
   // phase 0: diagonal of A_omega
   for (int r = tid; r < nt; r += 256) {
@@ -63,11 +69,11 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
         const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
         if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
         const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-        const int32_t info = g.cellinfo[c];
+        const int32_t info = cellinfo[c];
         if (info == CELL_INACTIVE) continue;
         const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
         const double kaa = info == CELL_UNCUT ? c_Kref_b[a * 9] : g.Kc[(int64_t)info * PACK36 + pack_index(a, a)];
-        d += g.kappa[c] * g.h * kaa;
+        d += kappa[c] * h * kaa;
       }
     }
     diag[r] = d;
@@ -114,10 +120,10 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
       const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
       if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
       const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-      const int32_t info = g.cellinfo[c];
+      const int32_t info = cellinfo[c];
       if (info == CELL_INACTIVE) continue;
       const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-      const double sc = g.kappa[c] * g.h;
+      const double sc = kappa[c] * h;
       for (int b = 0; b < 8; ++b) {
         const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
         const int col = loc[bx + s1 * (by + s1 * bz)];
@@ -167,15 +173,19 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
   if (e >= nt * NCp) return;
   const int r = e / NCp, t = e % NCp;
   const int nI = sd.nI[w], nG = sd.nG[w];
-  const int s = g.s, m = g.N / g.s, N = g.N;
-  const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
+  const ProbDev pr = g.prob[sd.sub_prob[w]];
+  const int s = g.s, m = pr.m, N = pr.N;
+  const int blk = sd.sub_blk[w];
+  const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
   const int64_t N1 = N + 1;
   const int s1 = s + 1;
   const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
+  const int32_t* cellinfo = g.cellinfo + pr.cell_off;
+  const double* kappa = g.kappa + pr.cell_off;
   const double* x = X + (int64_t)w * nt * NCp;
   int64_t n = -1;
-  if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
-  else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
+  if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] - pr.node_off : -1;
+  else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] - pr.node_off : -1;
   double acc = 0.0;
   if (n >= 0) {
     const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
@@ -184,10 +194,10 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
       const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
       if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
       const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-      const int32_t info = g.cellinfo[c];
+      const int32_t info = cellinfo[c];
       if (info == CELL_INACTIVE) continue;
       const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-      const double sc = g.kappa[c] * g.h;
+      const double sc = kappa[c] * pr.h;
       for (int b = 0; b < 8; ++b) {
         const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
         const int col = loc[bx + s1 * (by + s1 * bz)];
@@ -263,25 +273,31 @@ __global__ __launch_bounds__(256) void small_spd_inverse_kernel(SubDev sd, doubl
   for (int e = tid; e < NCp * NCp; e += 256) g[e] = S[e];
 }
 
-// Kernel 4: coarse matrix row c = sum over the subdomains touching coarse
-// DOF c (ascending) of the matching row of A_c^w.
-__global__ void coarse_assemble_kernel(int nc, int ldc, const int64_t* __restrict__ cs_ptr,
-                                       const int32_t* __restrict__ cs_sub, const int32_t* __restrict__ cs_row,
-                                       SubDev sd, const double* __restrict__ AcLoc, double* __restrict__ Ac) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ldc) return;
-  double* row = Ac + (int64_t)c * ldc;   // zero-filled by the caller
-  if (c >= nc) {
-    row[c] = 1.0;
+// Kernel 4: row c of problem p's coarse matrix = sum over the subdomains
+// touching coarse DOF c (ascending) of the matching row of A_c^w.  One
+// thread per padded row of the launch.
+__global__ void coarse_assemble_kernel(BatchDev bd, const int64_t* __restrict__ prow_off, int64_t n_prows,
+                                       const int64_t* __restrict__ cs_ptr, const int32_t* __restrict__ cs_sub,
+                                       const int32_t* __restrict__ cs_row, SubDev sd,
+                                       const double* __restrict__ AcLoc, double* __restrict__ Ac) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_prows) return;
+  const int p = find_segment(prow_off, bd.P, q);
+  const ProbDev pr = bd.prob[p];
+  const int lr = (int)(q - prow_off[p]);
+  double* row = Ac + pr.ac_off + (int64_t)lr * pr.ldc;   // zero-filled by the caller
+  if (lr >= pr.nc) {
+    row[lr] = 1.0;
     return;
   }
   const int NCp = sd.NCp;
+  const int c = pr.coarse_off + lr;
   for (int64_t z = cs_ptr[c]; z < cs_ptr[c + 1]; ++z) {
     const int w = cs_sub[z], t = cs_row[z];
     const int nC = sd.nC[w];
     const double* src = AcLoc + ((int64_t)w * NCp + t) * NCp;
     const int32_t* ids = sd.C_ids + (int64_t)w * NCp;
-    for (int u = 0; u < nC; ++u) row[ids[u]] += src[u];
+    for (int u = 0; u < nC; ++u) row[ids[u] - pr.coarse_off] += src[u];
   }
 }
 
@@ -296,6 +312,7 @@ __global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM
                                                              double* __restrict__ out, int rows_per_block) {
   extern __shared__ double xs[];
   const int w = blockIdx.y;
+  if (sd.active && !sd.active[sd.sub_prob[w]]) return;
   const int NIp = sd.NIp;
   const int nI = sd.nI[w];
   const int64_t* idx = sd.I_idx + (int64_t)w * NIp;
@@ -332,6 +349,7 @@ __global__ __launch_bounds__(256) void apply_neumann_kernel(SubDev sd, const TM*
                                                             int rows_per_block) {
   extern __shared__ double gs[];
   const int w = blockIdx.y;
+  if (sd.active && !sd.active[sd.sub_prob[w]]) return;
   const int NGp = sd.NGp, NCp = sd.NCp;
   const int nG = sd.nG[w], nC = sd.nC[w];
   const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
@@ -376,17 +394,23 @@ __global__ void coarse_rhs_kernel(int nc, const int64_t* __restrict__ cs_ptr, co
   c[q] = acc;
 }
 
-// y = A x for one dense n x n matrix (ld), one wave per row.
-__global__ __launch_bounds__(256) void gemv_kernel(int n, int ld, const double* __restrict__ A,
-                                                   const double* __restrict__ x, double* __restrict__ y) {
+// Block-diagonal coarse solve, one wave per global coarse row.
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(BatchDev bd, int nc_total,
+                                                          const int32_t* __restrict__ coarse_prob,
+                                                          const double* __restrict__ A,
+                                                          const double* __restrict__ x, double* __restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= n) return;
-  const double* row = A + (int64_t)r * ld;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= nc_total) return;
+  const int p = coarse_prob[c];
+  if (bd.active && !bd.active[p]) return;
+  const ProbDev pr = bd.prob[p];
+  const double* row = A + pr.ac_off + (int64_t)(c - pr.coarse_off) * pr.ldc;
+  const double* xp = x + pr.coarse_off;
   double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc += row[j] * x[j];
+  for (int j = lane; j < pr.nc; j += 64) acc += row[j] * xp[j];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[r] = acc;
+  if (lane == 0) y[c] = acc;
 }
 
 // u~_w[j] = z_w[j] + sum_t Phi_w[j][t] u_c[C_ids[t]]  (in place in z)
@@ -394,6 +418,7 @@ __global__ __launch_bounds__(256) void add_coarse_kernel(SubDev sd, const double
                                                          const double* __restrict__ uc, double* __restrict__ z) {
   extern __shared__ double ul[];
   const int w = blockIdx.x;
+  if (sd.active && !sd.active[sd.sub_prob[w]]) return;
   const int NGp = sd.NGp, NCp = sd.NCp;
   const int nG = sd.nG[w], nC = sd.nC[w];
   for (int t = threadIdx.x; t < NCp; t += 256) ul[t] = t < nC ? uc[sd.C_ids[(int64_t)w * NCp + t]] : 0.0;
@@ -462,10 +487,12 @@ void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* 
                      sd, S, info);
 }
 
-void launch_coarse_assemble(hipStream_t st, int nc, int ldc, const int64_t* cs_ptr, const int32_t* cs_sub,
-                            const int32_t* cs_row, const SubDev& sd, const double* AcLoc, double* Ac) {
-  hipLaunchKernelGGL(coarse_assemble_kernel, dim3((ldc + 63) / 64), dim3(64), 0, st, nc, ldc, cs_ptr, cs_sub,
-                     cs_row, sd, AcLoc, Ac);
+void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows,
+                            const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,
+                            const double* AcLoc, double* Ac) {
+  if (n_prows <= 0) return;
+  hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)((n_prows + 63) / 64)), dim3(64), 0, st, b, prow_off,
+                     n_prows, cs_ptr, cs_sub, cs_row, sd, AcLoc, Ac);
 }
 
 template <typename TM>
@@ -501,9 +528,11 @@ void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int3
                      NCp, cloc, c);
 }
 
-void launch_gemv(hipStream_t st, int n, int ld, const double* A, const double* x, double* y) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(gemv_kernel, dim3((n + 3) / 4), dim3(256), 0, st, n, ld, A, x, y);
+void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const int32_t* coarse_prob,
+                        const double* Ainv, const double* x, double* y) {
+  if (nc_total <= 0) return;
+  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc_total + 3) / 4), dim3(256), 0, st, b, nc_total, coarse_prob,
+                     Ainv, x, y);
 }
 
 void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,

@@ -20,6 +20,42 @@ struct GridDesc {
   double h;                  // 1/N
 };
 
+// A context holds P >= 1 independent meshes.  Their cell, node, DOF,
+// subdomain and coarse arrays are concatenated in problem order; every cell
+// and node segment starts at a multiple of SEG_ALIGN, so a block of
+// SEG_ALIGN consecutive entries never spans two problems.
+constexpr int SEG_ALIGN = 256;
+
+struct ProbDev {
+  int32_t N, s, m;           // cells per axis, cells per subdomain side, subdomains per axis
+  int32_t nb, ball_off;      // balls of the level set and the first one in the ball array
+  double h;                  // 1/N
+  int64_t cell_off, node_off, dof_off;
+  int32_t sub_off, coarse_off;
+  int32_t nc, ldc;           // coarse DOFs, order of the padded coarse block
+  int64_t ac_off;            // element offset of the coarse block (ldc x ldc)
+};
+
+struct BatchDev {
+  int32_t P;
+  const ProbDev* prob;       // [P]
+  const int64_t* cell_off;   // [P+1]
+  const int64_t* node_off;   // [P+1]
+  const int32_t* active;     // [P] problems whose PCG still runs, or null (all)
+};
+
+// Largest p in [0, P) with off[p] <= i (off ascending, off[0] = 0).
+template <typename I>
+__host__ __device__ inline int find_segment(const I* off, int P, int64_t i) {
+  int lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Index of entry (a, b) of a symmetric 8x8 matrix in its packed upper
 // triangle (row by row).
 __host__ __device__ inline int pack_index(int a, int b) {
@@ -29,17 +65,22 @@ __host__ __device__ inline int pack_index(int a, int b) {
 }
 
 // ---- launchers (defined in the .hip files) --------------------------------
-// integrate.hip
-void launch_classify(hipStream_t st, int N, const double* xi, const double* balls, int nb,
-                     int32_t* count);
-void launch_integrate_cut(hipStream_t st, int N, const double* xi, const double* balls, int nb,
+// integrate.hip (cells: concatenated cell space of n_cells_total entries)
+void launch_classify(hipStream_t st, const BatchDev& b, int64_t n_cells_total, const double* xi,
+                     const double* balls, int32_t* count);
+void launch_integrate_cut(hipStream_t st, const BatchDev& b, const double* xi, const double* balls,
                           const int64_t* cut_cells, int64_t n_cut, double* Kc, double* Mc);
-// operator.hip
+// operator.hip (nodes: concatenated node space of nn entries)
 void set_reference_matrices(const double* Kref, const double* Mref);
-void launch_apply_A(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* kappa,
-                    const double* Kc, const uint8_t* dofmask, const double* x, double* y);
-void launch_load(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* Mc,
-                 const uint8_t* outmask, const double* f, double* b);
+void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
+                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x,
+                    double* y);
+// b = M_cut f.  f is read per problem from f_ptrs[p] (local node numbering;
+// a null entry means f = 1) when f_ptrs is given, else from the
+// concatenated vector f.  outmask null: every node of a segment is written.
+void launch_load(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
+                 const double* Mc, const uint8_t* outmask, const double* f,
+                 const double* const* f_ptrs, double* out);
 void launch_grad_theta(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* kappa,
                        const double* Kc, const double* u, const double* lam, double* out);
 void launch_scatter_dofs(hipStream_t st, int64_t n, const int64_t* dof_node, const double* src,
@@ -47,13 +88,31 @@ void launch_scatter_dofs(hipStream_t st, int64_t n, const int64_t* dof_node, con
 void launch_gather_dofs(hipStream_t st, int64_t n, const int64_t* dof_node, const double* grid,
                         double* dst);
 void launch_fill(hipStream_t st, int64_t n, double v, double* x);
-// deterministic dot product: result written to out (device)
-void launch_dot(hipStream_t st, int64_t n, const double* x, const double* y, double* partial,
-                double* out);
-int dot_partials();
-void launch_cg_update_xr(hipStream_t st, int64_t n, const double* S, const double* p, const double* q, double* x,
-                         double* r);
-void launch_cg_update_p(hipStream_t st, int64_t n, double* S, const double* z, double* p);
+void launch_copy(hipStream_t st, int64_t n, const double* src, double* dst);
+// Per-problem dot products over the node segments, in a fixed order:
+// out[p * stride] = x_p . y_p.  chunk_ptr[p] = first DOT_CHUNK-sized chunk of
+// problem p (chunk_ptr[P] = total); partial holds one value per chunk.
+constexpr int DOT_CHUNK = 1024;
+void launch_dot(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks,
+                const double* x, const double* y, double* partial, double* out, int stride);
+// PCG scalars per problem p at S[8p + k]: 0 rho, 1 p.q, 2 r.r, 3 rho_new,
+// 4 b.b.  State per problem: it (iterations), status (0 running,
+// 1 converged, 2 iteration limit, 3 breakdown), relres; n_active[0] = number
+// of running problems.  params = {rtol, max_iter}.
+constexpr int CG_S = 8;
+void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int32_t* active, int32_t* it,
+                    int32_t* status, double* relres, int32_t* n_active);
+void launch_cg_check(hipStream_t st, int P, const double* params, const double* S, int32_t* active,
+                     int32_t* it, int32_t* status, double* relres, int32_t* n_active);
+void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
+                         const double* q, double* x, double* r);
+void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
+                        double* p);
+void launch_set_params(hipStream_t st, double* params, double rtol, int32_t max_iter);
+// u_p[d] = grid[dof_node[dof_off[p] + d]] for every problem (u_ptrs: device
+// array of P output pointers), or dst[d] = grid[dof_node[d]] if u_ptrs is null.
+void launch_gather_dofs_batch(hipStream_t st, int P, int64_t n_dof_total, const int64_t* dof_off,
+                              const int64_t* dof_node, const double* grid, double* const* u_ptrs);
 void convert_to_float(hipStream_t st, int64_t n, const double* a, float* b);
 
 }  // namespace cutbddc

@@ -5,14 +5,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <memory>
-#include <type_traits>
+#include <numeric>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "bddc.h"
@@ -210,70 +214,151 @@ struct ProfEntry {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
 
+// Host data of one problem of a context.
+struct ProbHost {
+  Geometry geo;
+  Topology* topo = nullptr;
+  int N = 0, m = 0, ns = 0;
+  double h = 0;
+  int nb = 0, ball_off = 0;
+  std::vector<int32_t> count;          // [N^3] kept points per cell
+  std::vector<int64_t> cut_local;      // cut cells with stored matrices (local ids, stored order)
+  int64_t n_active = 0, n_cut = 0;
+  int64_t cell_off = 0, node_off = 0, dof_off = 0, cut_off = 0;
+  int32_t sub_off = 0, coarse_off = 0, ldc = 0, chunk_off = 0;
+  int64_t ac_off = 0, prow_off = 0;
+  int64_t iface_off = 0;
+  cb_info info{};
+  ProbHost() = default;
+  ProbHost(const ProbHost&) = delete;
+  ProbHost& operator=(const ProbHost&) = delete;
+  ProbHost(ProbHost&& o) noexcept { *this = std::move(o); }
+  ProbHost& operator=(ProbHost&& o) noexcept {
+    geo = std::move(o.geo);
+    topo = o.topo;
+    o.topo = nullptr;
+    N = o.N, m = o.m, ns = o.ns, h = o.h, nb = o.nb, ball_off = o.ball_off;
+    count = std::move(o.count);
+    cut_local = std::move(o.cut_local);
+    n_active = o.n_active, n_cut = o.n_cut;
+    cell_off = o.cell_off, node_off = o.node_off, dof_off = o.dof_off, cut_off = o.cut_off;
+    sub_off = o.sub_off, coarse_off = o.coarse_off, ldc = o.ldc, chunk_off = o.chunk_off;
+    ac_off = o.ac_off, prow_off = o.prow_off, iface_off = o.iface_off;
+    info = o.info;
+    return *this;
+  }
+  ~ProbHost() {
+    if (topo) give_topology(topo);
+  }
+};
+
+// Problems of equal padded coarse order, factored as one batch.
+struct CoarseGroup {
+  int ldc = 0;
+  int64_t ac_off = 0;
+  std::vector<int> probs;   // problem ids, in block order
+};
+
 struct cb_ctx {
   hipStream_t st = nullptr;
   bool prof = false;
   std::map<std::string, ProfEntry> prof_ev;
+  int P = 0;
+  std::vector<ProbHost> pb;
+  int s = 0;
+  int weighting = 1, objects = 0, variant = 1, precision = 0, full_elements = 0;
+  int64_t n_cells_tot = 0, nn = 0, n_dof_tot = 0, n_iface_tot = 0, n_cut_tot = 0;
+  int ns = 0, nc_tot = 0;
+  int32_t n_chunks = 0;
+  int64_t n_prows = 0, ac_total = 0;
+  std::vector<CoarseGroup> groups;
+  double xi[8];
+  double Kref[64], Mref[64];
+  bool factored = false;
+  int n_fallbacks = 0;
+
+  // per-problem device tables
+  DevBuf prob_d, cell_off_d, node_off_d, dof_off_d, chunk_ptr_d, prow_off_d, coarse_prob_d, sub_prob_d, sub_blk_d;
+  // grid data (concatenated)
+  DevBuf xi_d, balls, kappa, count_d, cellinfo, cut_d, Kc, Mc, dofmask, dof_node;
+  // subdomain index data
+  int NIp = 0, NGp = 0, NCp = 0, nt = 0;
+  DevBuf nI, nG, nC, Iidx, Gidx, Gobj, Cids, bloc, if_ptr, if_sub, if_slot, iface_node, cs_ptr, cs_sub,
+      cs_row;
+  // factor results
+  DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
+  // work vectors and PCG state
+  DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, ucvec, partial, scal, bgrid;
+  DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
+  // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
+  void* pin = nullptr;
+  // captured PCG iteration
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool graph_failed = false;
+  cb_info info{};
+
   ~cb_ctx() {
-    give_topology(topo_p);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    if (pin) (void)hipHostFree(pin);
     for (auto& kv : prof_ev)
       for (auto& e : kv.second.ev) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
       }
   }
-  Geometry geo;
-  Topology* topo_p = take_topology();
-  Topology& topo = *topo_p;
-  int N = 0, s = 0, m = 0, ns = 0;
-  double h = 0;
-  int weighting = 1, objects = 0, variant = 1, precision = 0, full_elements = 0;
-  std::vector<int32_t> count;
-  std::vector<int64_t> cut_cells;
-  int64_t n_active = 0, n_cut = 0;
-  double xi[8];
-  double Kref[64], Mref[64];
-  bool factored = false;
-  int n_fallbacks = 0;
+  int32_t* pin_nact() const { return static_cast<int32_t*>(pin); }
+  int32_t* pin_it() const { return static_cast<int32_t*>(pin) + 2; }
+  int32_t* pin_status() const { return pin_it() + P; }
+  double* pin_relres() const {
+    const size_t off = (((size_t)(2 + 2 * P) * sizeof(int32_t)) + 7) & ~(size_t)7;
+    return reinterpret_cast<double*>(static_cast<char*>(pin) + off);
+  }
+  const double** pin_fptrs() const { return reinterpret_cast<const double**>(pin_relres() + P); }
+  double** pin_uptrs() const { return reinterpret_cast<double**>(pin_relres() + 2 * P); }
+  size_t pin_bytes() const {
+    return ((((size_t)(2 + 2 * P) * sizeof(int32_t)) + 7) & ~(size_t)7) + (size_t)3 * P * sizeof(double);
+  }
 
-  // grid data
-  DevBuf xi_d, balls, kappa, count_d, cellinfo, cut_d, Kc, Mc, dofmask, dof_node;
-  // subdomain index data
-  int NIp = 0, NGp = 0, NCp = 0, nt = 0, ldc = 0;
-  DevBuf nI, nG, nC, Iidx, Gidx, Gobj, Cids, bloc, if_ptr, if_sub, if_slot, iface_node, cs_ptr, cs_sub,
-      cs_row;
-  // factor results
-  DevBuf P, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
-  // work vectors
-  DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, ucvec, partial, scal, bgrid;
-  cb_info info{};
-
+  BatchDev batch(bool masked) const {
+    BatchDev b;
+    b.P = P;
+    b.prob = prob_d.as<ProbDev>();
+    b.cell_off = cell_off_d.as<int64_t>();
+    b.node_off = node_off_d.as<int64_t>();
+    b.active = masked ? active.as<int32_t>() : nullptr;
+    return b;
+  }
   GridDev grid() const {
     GridDev g;
-    g.N = N;
+    g.prob = prob_d.as<ProbDev>();
     g.s = s;
-    g.h = h;
     g.cellinfo = cellinfo.as<int32_t>();
     g.kappa = kappa.as<double>();
     g.Kc = Kc.as<double>();
     return g;
   }
-  SubDev sub() const {
+  // Subdomain data starting at subdomain w0.
+  SubDev sub(int w0 = 0, bool masked = false) const {
+    const int s1 = s + 1;
     SubDev d;
     d.NIp = NIp;
     d.NGp = NGp;
     d.NCp = NCp;
-    d.nI = nI.as<int32_t>();
-    d.nG = nG.as<int32_t>();
-    d.nC = nC.as<int32_t>();
-    d.I_idx = Iidx.as<int64_t>();
-    d.G_idx = Gidx.as<int64_t>();
-    d.G_obj = Gobj.as<int32_t>();
-    d.C_ids = Cids.as<int32_t>();
-    d.bloc = bloc.as<int32_t>();
+    d.nI = nI.as<int32_t>() + w0;
+    d.nG = nG.as<int32_t>() + w0;
+    d.nC = nC.as<int32_t>() + w0;
+    d.I_idx = Iidx.as<int64_t>() + (int64_t)w0 * NIp;
+    d.G_idx = Gidx.as<int64_t>() + (int64_t)w0 * NGp;
+    d.G_obj = Gobj.as<int32_t>() + (int64_t)w0 * NGp;
+    d.C_ids = Cids.as<int32_t>() + (int64_t)w0 * NCp;
+    d.bloc = bloc.as<int32_t>() + (int64_t)w0 * s1 * s1 * s1;
+    d.sub_prob = sub_prob_d.as<int32_t>() + w0;
+    d.sub_blk = sub_blk_d.as<int32_t>() + w0;
+    d.active = masked ? active.as<int32_t>() : nullptr;
     return d;
   }
-  int64_t n_nodes() const { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
 };
 
 namespace {
@@ -296,26 +381,51 @@ struct ProfScope {
   }
 };
 
-int apply_A_grid(cb_ctx* c, const double* x, double* y) {
-  ProfScope ps(c, "apply_A");
-  GridDesc g{c->N, c->h};
-  launch_apply_A(c->st, g, c->cellinfo.as<int32_t>(), c->kappa.as<double>(), c->Kc.as<double>(),
-                 c->dofmask.as<uint8_t>(), x, y);
-  HIPCHK(hipGetLastError());
-  return CB_OK;
-}
-
 template <typename F>
 void timed(cb_ctx* c, const char* name, F&& f) {
   ProfScope ps(c, name);
   f();
 }
 
-// z = M r on grid vectors (eq. bddc), steps (1)-(7).
-int apply_M_grid(cb_ctx* c, const double* r, double* z) {
+// Runs f(p) for every problem on up to indexing_threads() host threads, in
+// the given order; the loops inside f run inline on each thread.
+template <typename F>
+void for_each_problem(const std::vector<int>& order, F&& f) {
+  const int P = (int)order.size();
+  if (P == 1) {
+    f(order[0]);
+    return;
+  }
+  const int nth = std::max(1, std::min(P, indexing_threads()));
+  std::atomic<int> next{0};
+  auto work = [&] {
+    set_serial_indexing(true);
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= P) break;
+      f(order[i]);
+    }
+    set_serial_indexing(false);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
+
+int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked) {
+  ProfScope ps(c, "apply_A");
+  launch_apply_A(c->st, c->batch(masked), c->nn, c->cellinfo.as<int32_t>(), c->kappa.as<double>(),
+                 c->Kc.as<double>(), c->dofmask.as<uint8_t>(), x, y);
+  return CB_OK;
+}
+
+// z = M r on grid vectors (eq. bddc), steps (1)-(7), for every problem (or,
+// masked, for the problems whose PCG still runs).
+int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked) {
   hipStream_t st = c->st;
-  const SubDev sd = c->sub();
-  const int64_t nn = c->n_nodes();
+  const SubDev sd = c->sub(0, masked);
+  const int64_t nn = c->nn;
   double* t1 = c->t1.as<double>();
   double* t2 = c->t2.as<double>();
   double* t3 = c->t3.as<double>();
@@ -323,12 +433,12 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z) {
   launch_fill(st, nn, 0.0, t1);
   timed(c, "apply_interior", [&] {
     if (c->precision == CB_FP32_LOCAL)
-      launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, nullptr, t1);
+      launch_apply_interior<float>(st, sd, c->ns, c->P_.as<float>(), r, nullptr, t1);
     else
-      launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, nullptr, t1);
+      launch_apply_interior<double>(st, sd, c->ns, c->P_.as<double>(), r, nullptr, t1);
   });
   // (2) rhat_G = r_G - (A delta)_G
-  CHK(apply_A_grid(c, t1, t2));
+  CHK(apply_A_grid(c, t1, t2, masked));
   // (3)-(4) weighted restriction, constrained Neumann solves, coarse rhs
   timed(c, "apply_neumann", [&] {
     if (c->precision == CB_FP32_LOCAL)
@@ -339,97 +449,806 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z) {
                                    c->Dw.as<double>(), r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
   });
   // (5) coarse correction
-  const int nc = c->topo.n_coarse;
-  if (nc > 0) {
-    launch_coarse_rhs(st, nc, c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(),
+  if (c->nc_tot > 0) {
+    launch_coarse_rhs(st, c->nc_tot, c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(),
                       c->NCp, c->cloc.as<double>(), c->cvec.as<double>());
-    timed(c, "coarse_gemv",
-          [&] { launch_gemv(st, nc, c->ldc, c->Acinv.as<double>(), c->cvec.as<double>(), c->ucvec.as<double>()); });
+    timed(c, "coarse_gemv", [&] {
+      launch_coarse_gemv(st, c->batch(masked), c->nc_tot, c->coarse_prob_d.as<int32_t>(), c->Acinv.as<double>(),
+                         c->cvec.as<double>(), c->ucvec.as<double>());
+    });
     launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
   // (6) weighted average on the interface
   launch_fill(st, nn, 0.0, z);
-  launch_iface_average(st, c->topo.n_iface, c->iface_node.as<int64_t>(), c->if_ptr.as<int64_t>(),
+  launch_iface_average(st, c->n_iface_tot, c->iface_node.as<int64_t>(), c->if_ptr.as<int64_t>(),
                        c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(), c->NGp, c->Dw.as<double>(),
                        c->zbuf.as<double>(), z);
   // (7) harmonic extension: z_I = A_II^{-1} (r - A [0; u_G])_I
-  CHK(apply_A_grid(c, z, t3));
+  CHK(apply_A_grid(c, z, t3, masked));
   timed(c, "apply_interior", [&] {
     if (c->precision == CB_FP32_LOCAL)
-      launch_apply_interior<float>(st, sd, c->ns, c->P.as<float>(), r, t3, z);
+      launch_apply_interior<float>(st, sd, c->ns, c->P_.as<float>(), r, t3, z);
     else
-      launch_apply_interior<double>(st, sd, c->ns, c->P.as<double>(), r, t3, z);
+      launch_apply_interior<double>(st, sd, c->ns, c->P_.as<double>(), r, t3, z);
   });
-  HIPCHK(hipGetLastError());
   return CB_OK;
 }
 
-int read_scalar(cb_ctx* c, const double* d, double* h) {
-  HIPCHK(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  return CB_OK;
+void dot(cb_ctx* c, const double* a, const double* b, int slot, bool masked) {
+  launch_dot(c->st, c->batch(masked), c->chunk_ptr_d.as<int32_t>(), c->n_chunks, a, b, c->partial.as<double>(),
+             c->scal.as<double>() + slot, CG_S);
 }
 
-int dot(cb_ctx* c, const double* a, const double* b, double* out_dev) {
-  launch_dot(c->st, c->n_nodes(), a, b, c->partial.as<double>(), out_dev);
-  HIPCHK(hipGetLastError());
-  return CB_OK;
-}
-
-// PCG on grid vectors: b in c->bgrid, result in c->x.
-int pcg(cb_ctx* c, double rtol, int32_t max_iter, int32_t* iters, double* relres_out) {
+// One PCG iteration for every running problem: q = A p, x and r update,
+// convergence test, z = M r, p update.
+int pcg_body(cb_ctx* c) {
   hipStream_t st = c->st;
-  const int64_t nn = c->n_nodes();
-  double* x = c->x.as<double>();
-  double* r = c->r.as<double>();
-  double* z = c->z.as<double>();
-  double* p = c->p.as<double>();
-  double* q = c->q.as<double>();
-  double* S = c->scal.as<double>();   // [0] rho, [1] pq, [2] rr, [3] rho_new, [4] bb
-  const double* b = c->bgrid.as<double>();
-  launch_fill(st, nn, 0.0, x);
-  HIPCHK(hipMemcpyAsync(r, b, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
-  CHK(dot(c, b, b, S + 4));
-  double bb = 0.0;
-  CHK(read_scalar(c, S + 4, &bb));
-  const double bnorm = std::sqrt(bb);
-  int32_t k = 0;
-  double relres = 0.0;
-  if (bnorm == 0.0) {
-    if (iters) *iters = 0;
-    if (relres_out) *relres_out = 0.0;
-    return CB_OK;
+  double* S = c->scal.as<double>();
+  const BatchDev bm = c->batch(true);
+  CHK(apply_A_grid(c, c->p.as<double>(), c->q.as<double>(), true));
+  dot(c, c->p.as<double>(), c->q.as<double>(), 1, true);
+  launch_cg_update_xr(st, bm, c->nn, S, c->p.as<double>(), c->q.as<double>(), c->x.as<double>(),
+                      c->r.as<double>());
+  dot(c, c->r.as<double>(), c->r.as<double>(), 2, true);
+  launch_cg_check(st, c->P, c->params.as<double>(), S, c->active.as<int32_t>(), c->itc.as<int32_t>(),
+                  c->status.as<int32_t>(), c->relres_d.as<double>(), c->nact_d.as<int32_t>());
+  CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true));
+  dot(c, c->r.as<double>(), c->z.as<double>(), 3, true);
+  launch_cg_update_p(st, bm, c->nn, S, c->z.as<double>(), c->p.as<double>());
+  return CB_OK;
+}
+
+bool graphs_enabled() {
+  const char* e = std::getenv("CUTBDDC_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+// Captures pcg_body into an executable graph (once per factorisation).  The
+// capture runs on a private stream; replays go to the context's stream.
+int capture_body(cb_ctx* c) {
+  if (c->graph || c->graph_failed) return CB_OK;
+  if (!c->cap_st) HIPCHK(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  hipStream_t user = c->st;
+  c->st = c->cap_st;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal);
+  int rc = CB_OK;
+  if (e == hipSuccess) {
+    rc = pcg_body(c);
+    e = hipStreamEndCapture(c->cap_st, &g);
   }
-  relres = 1.0;
-  CHK(apply_M_grid(c, r, z));
-  HIPCHK(hipMemcpyAsync(p, z, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
-  CHK(dot(c, r, z, S + 0));
-  bool converged = false;
-  while (k < max_iter) {
-    CHK(apply_A_grid(c, p, q));
-    CHK(dot(c, p, q, S + 1));
-    launch_cg_update_xr(st, nn, S, p, q, x, r);
-    CHK(dot(c, r, r, S + 2));
-    ++k;
-    double rr = 0.0;
-    CHK(read_scalar(c, S + 2, &rr));
-    if (!std::isfinite(rr)) {
-      if (iters) *iters = k;
-      return fail(CB_ERR_NOT_SPD, "PCG breakdown (non-finite residual)");
-    }
-    relres = std::sqrt(rr) / bnorm;
-    if (relres < rtol) {
-      converged = true;
-      break;
-    }
-    CHK(apply_M_grid(c, r, z));
-    CHK(dot(c, r, z, S + 3));
-    launch_cg_update_p(st, nn, S, z, p);
+  c->st = user;
+  if (rc != CB_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
   }
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    // fall back to issuing the iteration eagerly
+    (void)hipGetLastError();
+    c->graph = nullptr;
+    c->graph_failed = true;
+  }
+  return CB_OK;
+}
+
+int read_active(cb_ctx* c, int32_t* n) {
+  HIPCHK(hipMemcpyAsync(c->pin_nact(), c->nact_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *n = *c->pin_nact();
+  return CB_OK;
+}
+
+// PCG on grid vectors for all problems at once: b in c->bgrid, x in c->x.
+// Per-problem results land in the pinned staging arrays.  A problem whose
+// residual meets the tolerance stops; the others continue.  Returns the
+// number of iteration sweeps run.
+int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
+  hipStream_t st = c->st;
+  const int64_t nn = c->nn;
+  double* S = c->scal.as<double>();
+  launch_set_params(st, c->params.as<double>(), rtol, max_iter);
+  launch_fill(st, nn, 0.0, c->x.as<double>());
+  launch_copy(st, nn, c->bgrid.as<double>(), c->r.as<double>());
+  dot(c, c->bgrid.as<double>(), c->bgrid.as<double>(), 4, false);
+  launch_cg_init(st, c->P, c->params.as<double>(), S, c->active.as<int32_t>(), c->itc.as<int32_t>(),
+                 c->status.as<int32_t>(), c->relres_d.as<double>(), c->nact_d.as<int32_t>());
   HIPCHK(hipGetLastError());
-  if (iters) *iters = k;
-  if (relres_out) *relres_out = relres;
-  if (!converged) return fail(CB_ERR_NO_CONVERGENCE, "PCG reached max_iter");
+  int32_t n_active = 0;
+  CHK(read_active(c, &n_active));
+  int k = 0;
+  if (n_active > 0) {
+    CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true));
+    launch_copy(st, nn, c->z.as<double>(), c->p.as<double>());
+    dot(c, c->r.as<double>(), c->z.as<double>(), 0, true);
+    HIPCHK(hipGetLastError());
+    const bool use_graph = graphs_enabled() && !c->prof;
+    if (use_graph) CHK(capture_body(c));
+    while (n_active > 0 && k <= max_iter) {
+      if (use_graph && c->graph) HIPCHK(hipGraphLaunch(c->graph, st));
+      else CHK(pcg_body(c));
+      HIPCHK(hipGetLastError());
+      ++k;
+      CHK(read_active(c, &n_active));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->pin_it(), c->itc.p, c->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(c->pin_status(), c->status.p, c->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(c->pin_relres(), c->relres_d.p, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (sweeps) *sweeps = k;
+  return CB_OK;
+}
+
+// Status of problem p after pcg().
+int pcg_status(cb_ctx* c, int p) {
+  const int s = c->pin_status()[p];
+  if (s == 3) return fail(CB_ERR_NOT_SPD, "PCG breakdown (non-finite residual) in problem " + std::to_string(p));
+  if (s != 1) return fail(CB_ERR_NO_CONVERGENCE, "PCG reached max_iter in problem " + std::to_string(p));
+  return CB_OK;
+}
+
+int validate_problem(const cb_problem* p) {
+  const int N = p->n_cells, s = p->sub_cells;
+  if (N < 1 || s < 1 || N % s != 0) return fail(CB_ERR_ARG, "n_cells must be >= 1 and divisible by sub_cells");
+  if (N > 1024) return fail(CB_ERR_ARG, "n_cells too large");
+  if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
+    return fail(CB_ERR_ARG, "invalid ball arrays");
+  if (p->weighting < 0 || p->weighting > 1 || p->objects < 0 || p->objects > 1 || p->coarse_variant < 0 ||
+      p->coarse_variant > 1 || p->local_precision < 0 || p->local_precision > 1)
+    return fail(CB_ERR_ARG, "invalid option value");
+  for (int i = 0; i < p->n_balls; ++i) {
+    if (!(p->ball_radii[i] > 0.0) || !std::isfinite(p->ball_radii[i]))
+      return fail(CB_ERR_ARG, "ball radius must be positive and finite");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(p->ball_centres[3 * i + d])) return fail(CB_ERR_ARG, "ball centre not finite");
+  }
+  const int64_t ncell = (int64_t)N * N * N;
+  if (p->kappa)
+    for (int64_t c = 0; c < ncell; ++c)
+      if (!(p->kappa[c] > 0.0) || !std::isfinite(p->kappa[c]))
+        return fail(CB_ERR_ARG, "kappa must be positive and finite");
+  return CB_OK;
+}
+
+inline int64_t align_seg(int64_t x) { return ((x + SEG_ALIGN - 1) / SEG_ALIGN) * SEG_ALIGN; }
+
+// Setup of P problems (cell classification and integration on the GPU,
+// indexing on the host, index maps uploaded).
+int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
+  if (!ps || !out || P < 1) return fail(CB_ERR_ARG, "null argument or empty batch");
+  *out = nullptr;
+  for (int k = 0; k < P; ++k) {
+    const int rc = validate_problem(&ps[k]);
+    if (rc != CB_OK) return P > 1 ? fail(rc, "problem " + std::to_string(k) + ": " + g_err) : rc;
+    const cb_problem& a = ps[k];
+    const cb_problem& b = ps[0];
+    if (a.sub_cells != b.sub_cells || a.weighting != b.weighting || a.objects != b.objects ||
+        a.coarse_variant != b.coarse_variant || a.local_precision != b.local_precision ||
+        (a.full_elements != 0) != (b.full_elements != 0))
+      return fail(CB_ERR_ARG, "problems of a batch must share sub_cells and every option");
+  }
+  std::unique_ptr<cb_ctx> c(new cb_ctx());
+  c->st = static_cast<hipStream_t>(stream);
+  g_alloc_stream = c->st;
+  c->P = P;
+  c->s = ps[0].sub_cells;
+  c->weighting = ps[0].weighting;
+  c->objects = ps[0].objects;
+  c->variant = ps[0].coarse_variant;
+  c->precision = ps[0].local_precision;
+  c->full_elements = ps[0].full_elements ? 1 : 0;
+  hipStream_t st = c->st;
+  const int s = c->s;
+
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+
+  // problem segments
+  c->pb.resize(P);
+  int64_t cell_off = 0, node_off = 0;
+  int ball_off = 0, sub_off = 0;
+  for (int k = 0; k < P; ++k) {
+    ProbHost& h = c->pb[k];
+    h.topo = take_topology();
+    const int N = ps[k].n_cells;
+    h.N = N;
+    h.m = N / s;
+    h.ns = h.m * h.m * h.m;
+    h.h = 1.0 / (double)N;
+    h.nb = ps[k].n_balls;
+    h.ball_off = ball_off;
+    h.cell_off = cell_off;
+    h.node_off = node_off;
+    h.sub_off = sub_off;
+    h.geo.N = N;
+    h.geo.s = s;
+    h.geo.objects = ps[k].objects;
+    h.geo.variant = ps[k].coarse_variant;
+    h.geo.centres.assign(ps[k].ball_centres, ps[k].ball_centres + 3 * ps[k].n_balls);
+    h.geo.radii.assign(ps[k].ball_radii, ps[k].ball_radii + ps[k].n_balls);
+    cell_off += align_seg((int64_t)N * N * N);
+    node_off += align_seg((int64_t)(N + 1) * (N + 1) * (N + 1));
+    ball_off += h.nb;
+    sub_off += h.ns;
+  }
+  c->n_cells_tot = cell_off;
+  c->nn = node_off;
+  c->ns = sub_off;
+
+  // sub-cell Gauss coordinates: xi_k = (a + g_p) / 4, k = 2a + p
+  const double g0 = 0.5 - 0.5 / std::sqrt(3.0), g1 = 0.5 + 0.5 / std::sqrt(3.0);
+  for (int a = 0; a < 4; ++a) {
+    c->xi[2 * a] = ((double)a + g0) * 0.25;
+    c->xi[2 * a + 1] = ((double)a + g1) * 0.25;
+  }
+  reference_matrices(c->xi, c->Kref, c->Mref);
+  set_reference_matrices(c->Kref, c->Mref);
+  bddc_set_reference(c->Kref);
+  const std::vector<double> xiv(c->xi, c->xi + 8);
+  CHK(upload(c->xi_d, xiv, st));
+  std::vector<double> balls(4 * (size_t)std::max(1, ball_off));
+  std::vector<double> kap(c->n_cells_tot, 1.0);
+  for (int k = 0; k < P; ++k) {
+    const ProbHost& h = c->pb[k];
+    for (int i = 0; i < h.nb; ++i) {
+      double* B = &balls[4 * (size_t)(h.ball_off + i)];
+      B[0] = ps[k].ball_centres[3 * i + 0];
+      B[1] = ps[k].ball_centres[3 * i + 1];
+      B[2] = ps[k].ball_centres[3 * i + 2];
+      B[3] = ps[k].ball_radii[i] * ps[k].ball_radii[i];
+    }
+    if (ps[k].kappa)
+      std::memcpy(&kap[h.cell_off], ps[k].kappa, (size_t)h.N * h.N * h.N * sizeof(double));
+  }
+  CHK(upload(c->balls, balls, st));
+  CHK(upload(c->kappa, kap, st));
+  // preliminary problem table for the grid kernels
+  // (uploaded host vectors stay alive until the stream is synchronised)
+  auto prob_table = [&](bool indexed) {
+    std::vector<ProbDev> t(P);
+    for (int k = 0; k < P; ++k) {
+      const ProbHost& h = c->pb[k];
+      ProbDev d{};
+      d.N = h.N;
+      d.s = s;
+      d.m = h.m;
+      d.nb = h.nb;
+      d.ball_off = h.ball_off;
+      d.h = h.h;
+      d.cell_off = h.cell_off;
+      d.node_off = h.node_off;
+      d.dof_off = h.dof_off;
+      d.sub_off = h.sub_off;
+      d.coarse_off = h.coarse_off;
+      d.nc = indexed ? h.topo->n_coarse : 0;
+      d.ldc = h.ldc;
+      d.ac_off = h.ac_off;
+      t[k] = d;
+    }
+    return t;
+  };
+  std::vector<int64_t> cell_offs(P + 1), node_offs(P + 1);
+  for (int k = 0; k < P; ++k) {
+    cell_offs[k] = c->pb[k].cell_off;
+    node_offs[k] = c->pb[k].node_off;
+  }
+  cell_offs[P] = c->n_cells_tot;
+  node_offs[P] = c->nn;
+  const std::vector<ProbDev> table0 = prob_table(false);
+  CHK(upload(c->prob_d, table0, st));
+  CHK(upload(c->cell_off_d, cell_offs, st));
+  CHK(upload(c->node_off_d, node_offs, st));
+  CHK(dalloc(c->count_d, c->n_cells_tot * sizeof(int32_t)));
+  launch_classify(st, c->batch(false), c->n_cells_tot, c->xi_d.as<double>(), c->balls.as<double>(),
+                  c->count_d.as<int32_t>());
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> counts(c->n_cells_tot);
+  HIPCHK(hipMemcpyAsync(counts.data(), c->count_d.p, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  // cell info: cut cells numbered in problem order, then cell order
+  std::vector<int32_t> cellinfo(c->n_cells_tot, CELL_INACTIVE);
+  std::vector<int64_t> cut_global;
+  for (int k = 0; k < P; ++k) {
+    ProbHost& h = c->pb[k];
+    const int64_t ncell = (int64_t)h.N * h.N * h.N;
+    h.count.assign(counts.begin() + h.cell_off, counts.begin() + h.cell_off + ncell);
+    h.cut_off = (int64_t)cut_global.size();
+    for (int64_t cc = 0; cc < ncell; ++cc) {
+      const int32_t n = h.count[cc];
+      if (n <= 0) continue;
+      h.n_active++;
+      if (n < 512) h.n_cut++;
+      if (n < 512 && !c->full_elements) {
+        cellinfo[h.cell_off + cc] = (int32_t)cut_global.size();
+        h.cut_local.push_back(cc);
+        cut_global.push_back(h.cell_off + cc);
+      } else {
+        cellinfo[h.cell_off + cc] = CELL_UNCUT;
+      }
+    }
+  }
+  c->n_cut_tot = (int64_t)cut_global.size();
+  CHK(upload(c->cellinfo, cellinfo, st));
+  CHK(upload(c->cut_d, cut_global, st));
+  CHK(dalloc(c->Kc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
+  CHK(dalloc(c->Mc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
+  launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),
+                       c->n_cut_tot, c->Kc.as<double>(), c->Mc.as<double>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(e1, st));
+
+  // host indexing (overlaps the integration kernel); large problems first
+  const double th0 = now_ms();
+  std::vector<int> order(P);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->pb[a].N > c->pb[b].N; });
+  std::vector<int> rcs(P, 0);
+  std::vector<std::string> errs(P);
+  for_each_problem(order, [&](int k) {
+    ProbHost& h = c->pb[k];
+    rcs[k] = build_topology(h.geo, h.count.data(), *h.topo, errs[k]);
+  });
+  for (int k = 0; k < P; ++k) {
+    if (rcs[k] == 0) continue;
+    const std::string where = P > 1 ? "problem " + std::to_string(k) + ": " : std::string();
+    return fail(rcs[k] == -2 ? CB_ERR_SINGULAR : CB_ERR_ARG, where + errs[k]);
+  }
+  int maxI = 1, maxG = 1, maxC = 1;
+  int64_t dof_off = 0, iface_off = 0;
+  int32_t coarse_off = 0, chunk_off = 0;
+  for (int k = 0; k < P; ++k) {
+    ProbHost& h = c->pb[k];
+    const Topology& t = *h.topo;
+    maxI = std::max(maxI, t.maxI);
+    maxG = std::max(maxG, t.maxG);
+    maxC = std::max(maxC, t.maxC);
+    h.dof_off = dof_off;
+    h.iface_off = iface_off;
+    h.coarse_off = coarse_off;
+    h.chunk_off = chunk_off;
+    dof_off += t.n_dof;
+    iface_off += t.n_iface;
+    coarse_off += t.n_coarse;
+    chunk_off += (int32_t)(((int64_t)(h.N + 1) * (h.N + 1) * (h.N + 1) + DOT_CHUNK - 1) / DOT_CHUNK);
+  }
+  c->n_dof_tot = dof_off;
+  c->n_iface_tot = iface_off;
+  c->nc_tot = coarse_off;
+  c->n_chunks = chunk_off;
+  c->NIp = round_up(maxI, CHOL_BLOCK);
+  c->NGp = round_up(maxG, CHOL_BLOCK);
+  c->NCp = round_up(maxC, 16);
+  c->nt = c->NIp + c->NGp;
+  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp;
+  const int s1 = s + 1;
+
+  // coarse blocks: problems grouped by padded coarse order (within 25%)
+  {
+    std::vector<int> co(P);
+    std::iota(co.begin(), co.end(), 0);
+    std::stable_sort(co.begin(), co.end(),
+                     [&](int a, int b) { return c->pb[a].topo->n_coarse < c->pb[b].topo->n_coarse; });
+    int64_t ac = 0;
+    size_t i = 0;
+    while (i < co.size()) {
+      const int nc0 = c->pb[co[i]].topo->n_coarse;
+      if (nc0 == 0) {
+        c->pb[co[i]].ldc = 0;
+        ++i;
+        continue;
+      }
+      const int l0 = round_up(nc0, CHOL_BLOCK);
+      size_t j = i;
+      int L = l0;
+      while (j < co.size()) {
+        const int l = round_up(c->pb[co[j]].topo->n_coarse, CHOL_BLOCK);
+        if (l > l0 + l0 / 4) break;
+        L = l;
+        ++j;
+      }
+      CoarseGroup g;
+      g.ldc = L;
+      g.ac_off = ac;
+      for (size_t q = i; q < j; ++q) {
+        ProbHost& h = c->pb[co[q]];
+        h.ldc = L;
+        h.ac_off = ac;
+        ac += (int64_t)L * L;
+        g.probs.push_back(co[q]);
+      }
+      c->groups.push_back(std::move(g));
+      i = j;
+    }
+    c->ac_total = ac;
+    int64_t prow = 0;
+    for (int k = 0; k < P; ++k) {
+      c->pb[k].prow_off = prow;
+      prow += c->pb[k].ldc;
+    }
+    c->n_prows = prow;
+  }
+
+  // concatenated index maps
+  std::vector<int32_t> nIv(ns), nGv(ns), nCv(ns), sub_prob(ns), sub_blk(ns);
+  std::vector<int64_t> Iidx((size_t)ns * NIp, -1), Gidx((size_t)ns * NGp, -1);
+  std::vector<int32_t> Gobj((size_t)ns * NGp, -1), Cids((size_t)ns * NCp, -1);
+  std::vector<int32_t> bloc((size_t)ns * s1 * s1 * s1, -1);
+  std::vector<int64_t> if_ptr(c->n_iface_tot + 1, 0), iface_node(c->n_iface_tot);
+  std::vector<int64_t> cs_ptr((size_t)c->nc_tot + 1, 0);
+  std::vector<int64_t> dof_node(c->n_dof_tot), dof_offs(P + 1), prow_offs(P + 1);
+  std::vector<int32_t> chunk_ptr(P + 1), coarse_prob(c->nc_tot);
+  std::vector<uint8_t> mask(c->nn, 0);
+  int64_t nz_if = 0, nz_cs = 0;
+  std::vector<int64_t> if_z(P), cs_z(P);
+  for (int k = 0; k < P; ++k) {
+    if_z[k] = nz_if;
+    cs_z[k] = nz_cs;
+    nz_if += (int64_t)c->pb[k].topo->if_sub.size();
+    nz_cs += (int64_t)c->pb[k].topo->cs_sub.size();
+  }
+  std::vector<int32_t> if_sub(nz_if), if_slot(nz_if), cs_sub(nz_cs), cs_row(nz_cs);
+  for_each_problem(order, [&](int k) {
+    const ProbHost& h = c->pb[k];
+    const Topology& t = *h.topo;
+    const int64_t N1 = h.N + 1;
+    for (int b = 0; b < h.ns; ++b) {
+      const int w = h.sub_off + b;
+      sub_prob[w] = k;
+      sub_blk[w] = b;
+      nIv[w] = t.nI[b];
+      nGv[w] = t.nG[b];
+      nCv[w] = t.nC[b];
+      const int Bx = b % h.m, By = (b / h.m) % h.m, Bz = b / (h.m * h.m);
+      auto set_loc = [&](int64_t node, int row) {
+        const int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
+        const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(K - (int64_t)Bz * s);
+        bloc[(size_t)w * s1 * s1 * s1 + lx + s1 * (ly + s1 * lz)] = row;
+      };
+      for (int64_t q = t.I_ptr[b]; q < t.I_ptr[b + 1]; ++q) {
+        const int i = (int)(q - t.I_ptr[b]);
+        Iidx[(size_t)w * NIp + i] = h.node_off + t.I_nodes[q];
+        set_loc(t.I_nodes[q], i);
+      }
+      for (int64_t q = t.G_ptr[b]; q < t.G_ptr[b + 1]; ++q) {
+        const int j = (int)(q - t.G_ptr[b]);
+        Gidx[(size_t)w * NGp + j] = h.node_off + t.G_nodes[q];
+        Gobj[(size_t)w * NGp + j] = t.G_obj[q];
+        set_loc(t.G_nodes[q], NIp + j);
+      }
+      for (int64_t q = t.C_ptr[b]; q < t.C_ptr[b + 1]; ++q)
+        Cids[(size_t)w * NCp + (q - t.C_ptr[b])] = h.coarse_off + t.C_ids[q];
+    }
+    for (int64_t i = 0; i < t.n_iface; ++i) {
+      if_ptr[h.iface_off + i + 1] = if_z[k] + t.if_ptr[i + 1];
+      iface_node[h.iface_off + i] = h.node_off + t.iface_node[i];
+    }
+    for (size_t z = 0; z < t.if_sub.size(); ++z) {
+      if_sub[if_z[k] + z] = h.sub_off + t.if_sub[z];
+      if_slot[if_z[k] + z] = t.if_slot[z];
+    }
+    for (int i = 0; i < t.n_coarse; ++i) {
+      cs_ptr[h.coarse_off + i + 1] = cs_z[k] + t.cs_ptr[i + 1];
+      coarse_prob[h.coarse_off + i] = k;
+    }
+    for (size_t z = 0; z < t.cs_sub.size(); ++z) {
+      cs_sub[cs_z[k] + z] = h.sub_off + t.cs_sub[z];
+      cs_row[cs_z[k] + z] = t.cs_row[z];
+    }
+    for (int64_t d = 0; d < t.n_dof; ++d) {
+      dof_node[h.dof_off + d] = h.node_off + t.dof_node[d];
+      mask[h.node_off + t.dof_node[d]] = 1;
+    }
+  });
+  for (int k = 0; k < P; ++k) {
+    dof_offs[k] = c->pb[k].dof_off;
+    prow_offs[k] = c->pb[k].prow_off;
+    chunk_ptr[k] = c->pb[k].chunk_off;
+  }
+  dof_offs[P] = c->n_dof_tot;
+  prow_offs[P] = c->n_prows;
+  chunk_ptr[P] = c->n_chunks;
+  c->info.t_topology_ms = now_ms() - th0;
+
+  const std::vector<ProbDev> table1 = prob_table(true);
+  CHK(upload(c->prob_d, table1, st));
+  CHK(upload(c->dof_off_d, dof_offs, st));
+  CHK(upload(c->prow_off_d, prow_offs, st));
+  CHK(upload(c->chunk_ptr_d, chunk_ptr, st));
+  CHK(upload(c->coarse_prob_d, coarse_prob, st));
+  CHK(upload(c->sub_prob_d, sub_prob, st));
+  CHK(upload(c->sub_blk_d, sub_blk, st));
+  CHK(upload(c->nI, nIv, st));
+  CHK(upload(c->nG, nGv, st));
+  CHK(upload(c->nC, nCv, st));
+  CHK(upload(c->Iidx, Iidx, st));
+  CHK(upload(c->Gidx, Gidx, st));
+  CHK(upload(c->Gobj, Gobj, st));
+  CHK(upload(c->Cids, Cids, st));
+  CHK(upload(c->bloc, bloc, st));
+  CHK(upload(c->if_ptr, if_ptr, st));
+  CHK(upload(c->if_sub, if_sub, st));
+  CHK(upload(c->if_slot, if_slot, st));
+  CHK(upload(c->iface_node, iface_node, st));
+  CHK(upload(c->cs_ptr, cs_ptr, st));
+  CHK(upload(c->cs_sub, cs_sub, st));
+  CHK(upload(c->cs_row, cs_row, st));
+  CHK(upload(c->dofmask, mask, st));
+  CHK(upload(c->dof_node, dof_node, st));
+  const int64_t nn = c->nn;
+  for (DevBuf* b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->t1, &c->t2, &c->t3, &c->bgrid})
+    CHK(dalloc(*b, nn * sizeof(double)));
+  CHK(dalloc(c->zbuf, (size_t)ns * NGp * sizeof(double)));
+  CHK(dalloc(c->cloc, (size_t)ns * NCp * sizeof(double)));
+  CHK(dalloc(c->cvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
+  CHK(dalloc(c->ucvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
+  CHK(dalloc(c->partial, (size_t)std::max(1, c->n_chunks) * sizeof(double)));
+  CHK(dalloc(c->scal, (size_t)P * CG_S * sizeof(double)));
+  CHK(dalloc(c->params, 2 * sizeof(double)));
+  CHK(dalloc(c->active, (size_t)P * sizeof(int32_t)));
+  CHK(dalloc(c->itc, (size_t)P * sizeof(int32_t)));
+  CHK(dalloc(c->status, (size_t)P * sizeof(int32_t)));
+  CHK(dalloc(c->relres_d, (size_t)P * sizeof(double)));
+  CHK(dalloc(c->nact_d, sizeof(int32_t)));
+  CHK(dalloc(c->fptrs, (size_t)P * sizeof(double*)));
+  CHK(dalloc(c->uptrs, (size_t)P * sizeof(double*)));
+  HIPCHK(hipHostMalloc(&c->pin, c->pin_bytes(), hipHostMallocDefault));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  c->info.t_integrate_ms = ms;
+  HIPCHK(hipStreamSynchronize(st));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+
+  // per-problem and total counts
+  cb_info& tot = c->info;
+  int maxl = 0, maxc = 0;
+  for (int k = 0; k < P; ++k) {
+    ProbHost& h = c->pb[k];
+    const Topology& t = *h.topo;
+    cb_info& in = h.info;
+    in.n_dof = t.n_dof;
+    in.n_active = h.n_active;
+    in.n_cut = h.n_cut;
+    in.n_cut_stored = (int64_t)h.cut_local.size();
+    in.n_sub = h.ns;
+    in.n_coarse = t.n_coarse;
+    in.n_objects = (int32_t)t.obj_type.size();
+    in.n_iface = t.n_iface;
+    in.max_coarse_per_sub = t.maxC;
+    int ml = 0;
+    for (int w = 0; w < h.ns; ++w) {
+      ml = std::max(ml, t.nI[w] + t.nG[w]);
+      const double nI = t.nI[w], nG = t.nG[w];
+      in.sum_nI2 += (int64_t)t.nI[w] * t.nI[w];
+      in.sum_nG2 += (int64_t)t.nG[w] * t.nG[w];
+      in.sum_nI += t.nI[w];
+      in.sum_nG += t.nG[w];
+      in.flops_local_chol += (nI + nG) * (nI + nG) * (nI + nG) / 3.0 + nI * nI * nI / 3.0;
+    }
+    in.max_local_dofs = ml;
+    maxl = std::max(maxl, ml);
+    maxc = std::max(maxc, t.maxC);
+    tot.n_dof += in.n_dof;
+    tot.n_active += in.n_active;
+    tot.n_cut += in.n_cut;
+    tot.n_cut_stored += in.n_cut_stored;
+    tot.n_sub += in.n_sub;
+    tot.n_coarse += in.n_coarse;
+    tot.n_objects += in.n_objects;
+    tot.n_iface += in.n_iface;
+    tot.sum_nI2 += in.sum_nI2;
+    tot.sum_nG2 += in.sum_nG2;
+    tot.sum_nI += in.sum_nI;
+    tot.sum_nG += in.sum_nG;
+    tot.flops_local_chol += in.flops_local_chol;
+  }
+  tot.max_local_dofs = maxl;
+  tot.max_coarse_per_sub = maxc;
+  *out = c.release();
+  return CB_OK;
+}
+
+size_t factor_work_budget() {
+  const char* e = std::getenv("CUTBDDC_FACTOR_WORK_GB");
+  double gb = e ? std::atof(e) : 16.0;
+  if (!(gb > 0.0)) gb = 16.0;
+  return (size_t)(gb * (double)(1ull << 30));
+}
+
+template <typename T>
+int factor_impl(cb_ctx* c) {
+  hipStream_t st = c->st;
+  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
+  const GridDev g = c->grid();
+  const bool f32 = std::is_same<T, float>::value;
+  const int ntiles = nt / CHOL_BLOCK;
+  const int nbig = std::max(NIp, NGp);
+  const int64_t sK = (int64_t)nt * nt;
+  const int64_t sL = (int64_t)ntiles * CHOL_BLOCK * CHOL_BLOCK;
+  const int64_t sY = (int64_t)nbig * nbig;
+  const int64_t sT = (int64_t)TRI_SUPER * nbig;
+  const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp, sF = (int64_t)nt * NCp;
+  const int64_t sP = (int64_t)NIp * NIp, sKS = (int64_t)NGp * NGp;
+
+  // persistent results
+  CHK(dalloc(c->P_, (size_t)ns * sP * sizeof(T)));
+  CHK(dalloc(c->Kt, (size_t)ns * sKS * sizeof(T)));
+  CHK(dalloc(c->Phi, (size_t)ns * sG * sizeof(double)));
+  CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
+  CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
+  CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
+  const int n_info = ns + 1 + c->P;
+  CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
+  HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
+  DevBuf AcLoc;
+  CHK(dalloc(AcLoc, (size_t)ns * sC * sizeof(double)));
+
+  // work buffers for a chunk of subdomains
+  const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
+                         (size_t)sT * sizeof(T) + (f32 ? (size_t)sP * 8 + (size_t)sKS * 8 : 0) +
+                         (size_t)(2 * sG + sC + 2 * sF) * sizeof(double);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
+  DevBuf K, Linv, Y, PS, Tmp, Pd64, KSw, G, Cm, Sc, PhiF, V;
+  CHK(dalloc(K, (size_t)chunk * sK * sizeof(T)));
+  CHK(dalloc(Linv, (size_t)chunk * sL * sizeof(T)));
+  CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
+  CHK(dalloc(PS, (size_t)chunk * sY * sizeof(T)));
+  CHK(dalloc(Tmp, (size_t)chunk * sT * sizeof(T)));
+  if (f32) {
+    CHK(dalloc(Pd64, (size_t)chunk * sP * sizeof(double)));
+    CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
+  }
+  CHK(dalloc(G, (size_t)chunk * sG * sizeof(double)));
+  CHK(dalloc(Cm, (size_t)chunk * sG * sizeof(double)));
+  CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
+  CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
+  CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
+
+  for (int w0 = 0; w0 < ns; w0 += chunk) {
+    const int nc = std::min(chunk, ns - w0);
+    const SubDev sd = c->sub(w0);
+    T* Pw = c->P_.as<T>() + (int64_t)w0 * sP;
+    const double* Dsw = c->Ds.as<double>() + (int64_t)w0 * nt;
+    double* Phiw = c->Phi.as<double>() + (int64_t)w0 * sG;
+    double* KS = f32 ? KSw.as<double>() : reinterpret_cast<double*>(c->Kt.as<T>() + (int64_t)w0 * sKS);
+    launch_assemble_local<T>(st, sd, g, nc, K.as<T>(), c->diagAG.as<double>() + (int64_t)w0 * NGp,
+                             c->Ds.as<double>() + (int64_t)w0 * nt);
+    HIPCHK(hipGetLastError());
+    timed(c, "local_cholesky",
+          [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0); });
+    HIPCHK(hipGetLastError());
+    // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
+    timed(c, "local_inverse", [&] {
+      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(), sT);
+      gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
+              GEMM_LOWER | GEMM_KFROM_DIAG);
+    });
+    symmetrize_scale<T, T>(st, PS.as<T>(), NIp, sY, Pw, NIp, sP, Dsw, nt, NIp, nc);
+    // FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
+    const double* Pd = reinterpret_cast<const double*>(Pw);
+    if (f32) {
+      symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
+      Pd = Pd64.as<double>();
+    }
+    HIPCHK(hipGetLastError());
+    // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
+    timed(c, "local_inverse", [&] {
+      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(), sT);
+      gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, nc,
+              GEMM_LOWER | GEMM_KFROM_DIAG);
+    });
+    symmetrize_scale<T, double>(st, PS.as<T>(), NGp, sY, KS, NGp, sKS, Dsw + NIp, nt, NGp, nc);
+    HIPCHK(hipGetLastError());
+    // coarse basis on the interface: G = K_S^{-1} C^T, S_c = C G,
+    // Phi_G = G S_c^{-1} (C Phi_G = I, energy-minimising for S_A)
+    launch_build_constraints(st, sd, nc, Cm.as<double>());
+    gemm<double>(st, 0, 1, NGp, NCp, NGp, 1.0, KS, NGp, sKS, Cm.as<double>(), NGp, sG, 0.0, G.as<double>(), NCp, sG,
+                 nc, 0);
+    gemm<double>(st, 0, 0, NCp, NCp, NGp, 1.0, Cm.as<double>(), NGp, sG, G.as<double>(), NCp, sG, 0.0,
+                 Sc.as<double>(), NCp, sC, nc, 0);
+    launch_small_spd_inverse(st, sd, nc, Sc.as<double>(), c->info_d.as<int>() + ns);
+    gemm<double>(st, 0, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NCp, sG, Sc.as<double>(), NCp, sC, 0.0, Phiw, NCp,
+                 sG, nc, 0);
+    HIPCHK(hipGetLastError());
+    // full coarse basis Phi = [-A_II^{-1} A_IG Phi_G; Phi_G] and the local
+    // coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi
+    launch_fill(st, (int64_t)nc * sF, 0.0, PhiF.as<double>());
+    HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), Phiw,
+                            (size_t)sG * sizeof(double), (size_t)sG * sizeof(double), nc, hipMemcpyDeviceToDevice,
+                            st));
+    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>());
+    gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, sP, V.as<double>(), NCp, sF, 0.0, PhiF.as<double>(), NCp,
+                 sF, nc, 0);
+    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>());
+    gemm<double>(st, 1, 0, NCp, NCp, nt, 1.0, PhiF.as<double>(), NCp, sF, V.as<double>(), NCp, sF, 0.0,
+                 AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC, nc, 0);
+    // Kt = K_S^{-1} - Phi G^T
+    gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NCp, sG, 1.0, KS, NGp, sKS, nc, 0);
+    if (f32)
+      convert_to_float(st, (int64_t)nc * sKS, KS, reinterpret_cast<float*>(c->Kt.as<T>() + (int64_t)w0 * sKS));
+    HIPCHK(hipGetLastError());
+  }
+  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Cm, &Sc, &PhiF, &V}) b->release();
+  launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
+                 NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
+  HIPCHK(hipGetLastError());
+
+  // coarse matrices (one block per problem) and their inverses, in FP64;
+  // the blocks of a group share their order and are factored as a batch
+  std::vector<int> coarse_slot(c->P, -1);   // index into info_d after ns + 1
+  if (c->ac_total > 0) {
+    DevBuf Ac;
+    CHK(dalloc(Ac, (size_t)c->ac_total * sizeof(double)));
+    CHK(dalloc(c->Acinv, (size_t)c->ac_total * sizeof(double)));
+    launch_fill(st, c->ac_total, 0.0, Ac.as<double>());
+    launch_coarse_assemble(st, c->batch(false), c->prow_off_d.as<int64_t>(), c->n_prows, c->cs_ptr.as<int64_t>(),
+                           c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(), c->sub(0), AcLoc.as<double>(),
+                           Ac.as<double>());
+    HIPCHK(hipGetLastError());
+    if (c->P == 1) {
+      CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
+      launch_copy(st, c->ac_total, Ac.as<double>(), c->AcKeep.as<double>());
+    }
+    size_t maxL = 0, maxLL = 0, maxB = 0;
+    for (const CoarseGroup& gr : c->groups) {
+      maxL = std::max(maxL, (size_t)gr.ldc);
+      maxLL = std::max(maxLL, (size_t)gr.ldc * gr.ldc * gr.probs.size());
+      maxB = std::max(maxB, gr.probs.size() * (size_t)gr.ldc);
+    }
+    DevBuf Lc, Yc, PSc, Tc, ones;
+    const std::vector<double> onesv(maxL, 1.0);
+    CHK(dalloc(Lc, maxB * CHOL_BLOCK * sizeof(double)));
+    CHK(dalloc(Yc, maxLL * sizeof(double)));
+    CHK(dalloc(PSc, maxLL * sizeof(double)));
+    CHK(dalloc(Tc, maxB * TRI_SUPER * sizeof(double)));
+    CHK(upload(ones, onesv, st));
+    ProfScope cps(c, "coarse_factor");
+    int slot = 0;
+    for (const CoarseGroup& gr : c->groups) {
+      const int L = gr.ldc, nb = (int)gr.probs.size();
+      const int64_t sA = (int64_t)L * L, sLc = (int64_t)(L / CHOL_BLOCK) * CHOL_BLOCK * CHOL_BLOCK;
+      for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
+      double* A = Ac.as<double>() + gr.ac_off;
+      cholesky<double>(st, A, L, sA, L, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
+      tri_inverse<double>(st, A, L, sA, 0, L, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA, Tc.as<double>(),
+                          (int64_t)TRI_SUPER * L);
+      gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
+                   L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
+      symmetrize_scale<double, double>(st, PSc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
+                                       ones.as<double>(), 0, L, nb);
+      HIPCHK(hipGetLastError());
+      slot += nb;
+    }
+  }
+  std::vector<int> info(n_info);
+  HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int32_t> sub_prob(ns);
+  for (int k = 0; k < c->P; ++k)
+    for (int b = 0; b < c->pb[k].ns; ++b) sub_prob[c->pb[k].sub_off + b] = k;
+  auto where = [&](int k) { return c->P > 1 ? " of problem " + std::to_string(k) : std::string(); };
+  for (int w = 0; w < ns; ++w)
+    if (info[w] != 0) {
+      const int k = sub_prob[w];
+      return fail(CB_ERR_NOT_SPD, "local Cholesky failed in subdomain " + std::to_string(w - c->pb[k].sub_off) +
+                                      where(k) + " at row " + std::to_string(info[w] - 1));
+    }
+  if (info[ns] != 0) return fail(CB_ERR_NOT_SPD, "singular local coarse matrix");
+  for (int k = 0; k < c->P; ++k)
+    if (coarse_slot[k] >= 0 && info[ns + 1 + coarse_slot[k]] != 0)
+      return fail(CB_ERR_NOT_SPD, "coarse Cholesky failed" + where(k));
+  return CB_OK;
+}
+
+int need_single(const cb_ctx* c) {
+  if (c->P != 1) return fail(CB_ERR_STATE, "entry point needs a single-problem context (use cb_solve_batch)");
   return CB_OK;
 }
 
@@ -525,379 +1344,12 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
   return precision == CB_FP32_LOCAL ? run(float(0)) : run(double(0));
 }
 
-int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) {
-  if (!p || !out) return fail(CB_ERR_ARG, "null argument");
-  *out = nullptr;
-  const int N = p->n_cells, s = p->sub_cells;
-  if (N < 1 || s < 1 || N % s != 0) return fail(CB_ERR_ARG, "n_cells must be >= 1 and divisible by sub_cells");
-  if (N > 1024) return fail(CB_ERR_ARG, "n_cells too large");
-  if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
-    return fail(CB_ERR_ARG, "invalid ball arrays");
-  if (p->weighting < 0 || p->weighting > 1 || p->objects < 0 || p->objects > 1 || p->coarse_variant < 0 ||
-      p->coarse_variant > 1 || p->local_precision < 0 || p->local_precision > 1)
-    return fail(CB_ERR_ARG, "invalid option value");
-  for (int i = 0; i < p->n_balls; ++i) {
-    if (!(p->ball_radii[i] > 0.0) || !std::isfinite(p->ball_radii[i]))
-      return fail(CB_ERR_ARG, "ball radius must be positive and finite");
-    for (int d = 0; d < 3; ++d)
-      if (!std::isfinite(p->ball_centres[3 * i + d])) return fail(CB_ERR_ARG, "ball centre not finite");
-  }
-  const int64_t ncell = (int64_t)N * N * N;
-  if (p->kappa)
-    for (int64_t c = 0; c < ncell; ++c)
-      if (!(p->kappa[c] > 0.0) || !std::isfinite(p->kappa[c]))
-        return fail(CB_ERR_ARG, "kappa must be positive and finite");
+int cb_setup(const cb_problem* p, void* stream, cb_ctx** out) { return setup_impl(p, 1, stream, out); }
 
-  std::unique_ptr<cb_ctx> c(new cb_ctx());
-  c->st = static_cast<hipStream_t>(stream);
-  g_alloc_stream = c->st;
-  c->N = N;
-  c->s = s;
-  c->m = N / s;
-  c->ns = c->m * c->m * c->m;
-  c->h = 1.0 / (double)N;
-  c->weighting = p->weighting;
-  c->objects = p->objects;
-  c->variant = p->coarse_variant;
-  c->precision = p->local_precision;
-  c->full_elements = p->full_elements ? 1 : 0;
-  c->geo.N = N;
-  c->geo.s = s;
-  c->geo.objects = p->objects;
-  c->geo.variant = p->coarse_variant;
-  c->geo.centres.assign(p->ball_centres, p->ball_centres + 3 * p->n_balls);
-  c->geo.radii.assign(p->ball_radii, p->ball_radii + p->n_balls);
-  hipStream_t st = c->st;
-
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, st));
-  // sub-cell Gauss coordinates: xi_k = (a + g_p) / 4, k = 2a + p
-  const double g0 = 0.5 - 0.5 / std::sqrt(3.0), g1 = 0.5 + 0.5 / std::sqrt(3.0);
-  for (int a = 0; a < 4; ++a) {
-    c->xi[2 * a] = ((double)a + g0) * 0.25;
-    c->xi[2 * a + 1] = ((double)a + g1) * 0.25;
-  }
-  reference_matrices(c->xi, c->Kref, c->Mref);
-  set_reference_matrices(c->Kref, c->Mref);
-  bddc_set_reference(c->Kref);
-  std::vector<double> xi(c->xi, c->xi + 8);
-  CHK(upload(c->xi_d, xi, st));
-  std::vector<double> balls(4 * (size_t)p->n_balls);
-  for (int i = 0; i < p->n_balls; ++i) {
-    balls[4 * i + 0] = p->ball_centres[3 * i + 0];
-    balls[4 * i + 1] = p->ball_centres[3 * i + 1];
-    balls[4 * i + 2] = p->ball_centres[3 * i + 2];
-    balls[4 * i + 3] = p->ball_radii[i] * p->ball_radii[i];
-  }
-  CHK(upload(c->balls, balls, st));
-  std::vector<double> kap(ncell, 1.0);
-  if (p->kappa) std::memcpy(kap.data(), p->kappa, ncell * sizeof(double));
-  CHK(upload(c->kappa, kap, st));
-  CHK(dalloc(c->count_d, ncell * sizeof(int32_t)));
-  launch_classify(st, N, c->xi_d.as<double>(), c->balls.as<double>(), p->n_balls, c->count_d.as<int32_t>());
-  HIPCHK(hipGetLastError());
-  c->count.resize(ncell);
-  HIPCHK(hipMemcpyAsync(c->count.data(), c->count_d.p, ncell * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<int32_t> cellinfo(ncell, CELL_INACTIVE);
-  for (int64_t cc = 0; cc < ncell; ++cc) {
-    const int32_t k = c->count[cc];
-    if (k <= 0) continue;
-    c->n_active++;
-    if (k < 512 && !c->full_elements) {
-      cellinfo[cc] = (int32_t)c->cut_cells.size();
-      c->cut_cells.push_back(cc);
-    } else {
-      cellinfo[cc] = CELL_UNCUT;
-    }
-  }
-  c->n_cut = 0;
-  for (int64_t cc = 0; cc < ncell; ++cc)
-    if (c->count[cc] > 0 && c->count[cc] < 512) c->n_cut++;
-  CHK(upload(c->cellinfo, cellinfo, st));
-  CHK(upload(c->cut_d, c->cut_cells, st));
-  const int64_t nstore = (int64_t)c->cut_cells.size();
-  CHK(dalloc(c->Kc, std::max<int64_t>(1, nstore) * PACK36 * sizeof(double)));
-  CHK(dalloc(c->Mc, std::max<int64_t>(1, nstore) * PACK36 * sizeof(double)));
-  launch_integrate_cut(st, N, c->xi_d.as<double>(), c->balls.as<double>(), p->n_balls, c->cut_d.as<int64_t>(),
-                       nstore, c->Kc.as<double>(), c->Mc.as<double>());
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(e1, st));
-  HIPCHK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  c->info.t_integrate_ms = ms;
-
-  // host indexing
-  const double th0 = now_ms();
-  std::string err;
-  int rc = build_topology(c->geo, c->count.data(), c->topo, err);
-  if (rc == -2) return fail(CB_ERR_SINGULAR, err);
-  if (rc != 0) return fail(CB_ERR_ARG, err);
-  Topology& t = c->topo;
-  c->NIp = round_up(std::max(1, t.maxI), CHOL_BLOCK);
-  c->NGp = round_up(std::max(1, t.maxG), CHOL_BLOCK);
-  c->NCp = round_up(std::max(1, t.maxC), 16);
-  c->nt = c->NIp + c->NGp;
-  c->ldc = round_up(std::max(1, t.n_coarse), CHOL_BLOCK);
-  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp;
-  std::vector<int64_t> Iidx((size_t)ns * NIp, -1), Gidx((size_t)ns * NGp, -1);
-  std::vector<int32_t> Gobj((size_t)ns * NGp, -1), Cids((size_t)ns * NCp, -1);
-  const int s1 = s + 1;
-  std::vector<int32_t> bloc((size_t)ns * s1 * s1 * s1, -1);
-  const int64_t N1 = N + 1;
-  for (int w = 0; w < ns; ++w) {
-    const int Bx = w % c->m, By = (w / c->m) % c->m, Bz = w / (c->m * c->m);
-    auto set_loc = [&](int64_t node, int row) {
-      const int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
-      const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(K - (int64_t)Bz * s);
-      bloc[(size_t)w * s1 * s1 * s1 + lx + s1 * (ly + s1 * lz)] = row;
-    };
-    for (int64_t q = t.I_ptr[w]; q < t.I_ptr[w + 1]; ++q) {
-      const int i = (int)(q - t.I_ptr[w]);
-      Iidx[(size_t)w * NIp + i] = t.I_nodes[q];
-      set_loc(t.I_nodes[q], i);
-    }
-    for (int64_t q = t.G_ptr[w]; q < t.G_ptr[w + 1]; ++q) {
-      const int j = (int)(q - t.G_ptr[w]);
-      Gidx[(size_t)w * NGp + j] = t.G_nodes[q];
-      Gobj[(size_t)w * NGp + j] = t.G_obj[q];
-      set_loc(t.G_nodes[q], NIp + j);
-    }
-    for (int64_t q = t.C_ptr[w]; q < t.C_ptr[w + 1]; ++q) Cids[(size_t)w * NCp + (q - t.C_ptr[w])] = t.C_ids[q];
-  }
-  std::vector<uint8_t> mask(c->n_nodes(), 0);
-  for (int64_t d = 0; d < t.n_dof; ++d) mask[t.dof_node[d]] = 1;
-  c->info.t_topology_ms = now_ms() - th0;
-  CHK(upload(c->nI, t.nI, st));
-  CHK(upload(c->nG, t.nG, st));
-  CHK(upload(c->nC, t.nC, st));
-  CHK(upload(c->Iidx, Iidx, st));
-  CHK(upload(c->Gidx, Gidx, st));
-  CHK(upload(c->Gobj, Gobj, st));
-  CHK(upload(c->Cids, Cids, st));
-  CHK(upload(c->bloc, bloc, st));
-  CHK(upload(c->if_ptr, t.if_ptr, st));
-  CHK(upload(c->if_sub, t.if_sub, st));
-  CHK(upload(c->if_slot, t.if_slot, st));
-  CHK(upload(c->iface_node, t.iface_node, st));
-  CHK(upload(c->cs_ptr, t.cs_ptr, st));
-  CHK(upload(c->cs_sub, t.cs_sub, st));
-  CHK(upload(c->cs_row, t.cs_row, st));
-  CHK(upload(c->dofmask, mask, st));
-  CHK(upload(c->dof_node, t.dof_node, st));
-  const int64_t nn = c->n_nodes();
-  for (DevBuf* b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->t1, &c->t2, &c->t3, &c->bgrid})
-    CHK(dalloc(*b, nn * sizeof(double)));
-  CHK(dalloc(c->zbuf, (size_t)ns * NGp * sizeof(double)));
-  CHK(dalloc(c->cloc, (size_t)ns * NCp * sizeof(double)));
-  CHK(dalloc(c->cvec, (size_t)c->ldc * sizeof(double)));
-  CHK(dalloc(c->ucvec, (size_t)c->ldc * sizeof(double)));
-  CHK(dalloc(c->partial, (size_t)dot_partials() * sizeof(double)));
-  CHK(dalloc(c->scal, 16 * sizeof(double)));
-  HIPCHK(hipStreamSynchronize(st));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c->info.n_dof = t.n_dof;
-  c->info.n_active = c->n_active;
-  c->info.n_cut = c->n_cut;
-  c->info.n_cut_stored = (int64_t)c->cut_cells.size();
-  c->info.n_sub = ns;
-  c->info.n_coarse = t.n_coarse;
-  c->info.n_objects = (int32_t)t.obj_type.size();
-  c->info.n_iface = t.n_iface;
-  int maxl = 0;
-  for (int w = 0; w < ns; ++w) {
-    maxl = std::max(maxl, t.nI[w] + t.nG[w]);
-    const double nI = t.nI[w], nG = t.nG[w];
-    c->info.sum_nI2 += (int64_t)t.nI[w] * t.nI[w];
-    c->info.sum_nG2 += (int64_t)t.nG[w] * t.nG[w];
-    c->info.sum_nI += t.nI[w];
-    c->info.sum_nG += t.nG[w];
-    c->info.flops_local_chol += (nI + nG) * (nI + nG) * (nI + nG) / 3.0 + nI * nI * nI / 3.0;
-  }
-  c->info.max_local_dofs = maxl;
-  c->info.max_coarse_per_sub = t.maxC;
-  *out = c.release();
-  return CB_OK;
+int cb_setup_batch(const cb_problem* problems, int32_t n, void* stream, cb_ctx** out) {
+  if (n < 1) return fail(CB_ERR_ARG, "batch size must be >= 1");
+  return setup_impl(problems, n, stream, out);
 }
-
-}  // extern "C"
-
-namespace {
-
-template <typename T>
-int factor_impl(cb_ctx* c) {
-  hipStream_t st = c->st;
-  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
-  const SubDev sd = c->sub();
-  const GridDev g = c->grid();
-  DevBuf K, Linv, Y, PS, G, AcLoc, KS, Ac;
-  CHK(dalloc(K, (size_t)ns * nt * nt * sizeof(T)));
-  const int ntiles = nt / CHOL_BLOCK;
-  CHK(dalloc(Linv, (size_t)ns * ntiles * CHOL_BLOCK * CHOL_BLOCK * sizeof(T)));
-  const int nbig = std::max(NIp, NGp);
-  CHK(dalloc(Y, (size_t)ns * nbig * nbig * sizeof(T)));
-  CHK(dalloc(PS, (size_t)ns * nbig * nbig * sizeof(T)));
-  DevBuf Tmp;
-  const int64_t sT = (int64_t)TRI_SUPER * nbig;
-  CHK(dalloc(Tmp, (size_t)ns * sT * sizeof(T)));
-  CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
-  CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
-  CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
-  CHK(dalloc(c->info_d, (size_t)(ns + 2) * sizeof(int)));
-  HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)(ns + 2) * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
-  launch_assemble_local<T>(st, sd, g, ns, K.as<T>(), c->diagAG.as<double>(), c->Ds.as<double>());
-  HIPCHK(hipGetLastError());
-  launch_weights(st, c->topo.n_iface, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
-                 NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
-  const int64_t sK = (int64_t)nt * nt;
-  const int64_t sL = (int64_t)ntiles * CHOL_BLOCK * CHOL_BLOCK;
-  timed(c, "local_cholesky", [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, ns, Linv.as<T>(), sL, c->info_d.as<int>()); });
-  HIPCHK(hipGetLastError());
-  // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
-  const int64_t sY = (int64_t)nbig * nbig;
-  timed(c, "local_inverse", [&] {
-    tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, ns, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(), sT);
-    gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, ns,
-            GEMM_LOWER | GEMM_KFROM_DIAG);
-  });
-  CHK(dalloc(c->P, (size_t)ns * NIp * NIp * sizeof(T)));
-  symmetrize_scale<T, T>(st, PS.as<T>(), NIp, sY, c->P.as<T>(), NIp, (int64_t)NIp * NIp, c->Ds.as<double>(), nt,
-                         NIp, ns);
-  // FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
-  DevBuf Pd64;
-  const double* Pd = nullptr;
-  if (std::is_same<T, double>::value) {
-    Pd = reinterpret_cast<const double*>(c->P.p);
-  } else {
-    CHK(dalloc(Pd64, (size_t)ns * NIp * NIp * sizeof(double)));
-    symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, (int64_t)NIp * NIp,
-                                c->Ds.as<double>(), nt, NIp, ns);
-    Pd = Pd64.as<double>();
-  }
-  HIPCHK(hipGetLastError());
-  // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
-  timed(c, "local_inverse", [&] {
-    tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, ns, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(), sT);
-    gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, ns,
-            GEMM_LOWER | GEMM_KFROM_DIAG);
-  });
-  CHK(dalloc(KS, (size_t)ns * NGp * NGp * sizeof(double)));
-  symmetrize_scale<T, double>(st, PS.as<T>(), NGp, sY, KS.as<double>(), NGp, (int64_t)NGp * NGp,
-                              c->Ds.as<double>() + NIp, nt, NGp, ns);
-  HIPCHK(hipGetLastError());
-  K.release();
-  Y.release();
-  PS.release();
-  Linv.release();
-  Tmp.release();
-  // coarse basis on the interface: G = K_S^{-1} C^T, S_c = C G,
-  // Phi_G = G S_c^{-1} (C Phi_G = I, energy-minimising for S_A)
-  CHK(dalloc(G, (size_t)ns * NGp * NCp * sizeof(double)));
-  CHK(dalloc(c->Phi, (size_t)ns * NGp * NCp * sizeof(double)));
-  CHK(dalloc(AcLoc, (size_t)ns * NCp * NCp * sizeof(double)));
-  {
-    DevBuf Cm, Sc;
-    const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp;
-    CHK(dalloc(Cm, (size_t)ns * NCp * NGp * sizeof(double)));
-    CHK(dalloc(Sc, (size_t)ns * sC * sizeof(double)));
-    launch_build_constraints(st, sd, ns, Cm.as<double>());
-    gemm<double>(st, 0, 1, NGp, NCp, NGp, 1.0, KS.as<double>(), NGp, (int64_t)NGp * NGp, Cm.as<double>(), NGp,
-                 (int64_t)NCp * NGp, 0.0, G.as<double>(), NCp, sG, ns, 0);
-    gemm<double>(st, 0, 0, NCp, NCp, NGp, 1.0, Cm.as<double>(), NGp, (int64_t)NCp * NGp, G.as<double>(), NCp, sG,
-                 0.0, Sc.as<double>(), NCp, sC, ns, 0);
-    launch_small_spd_inverse(st, sd, ns, Sc.as<double>(), c->info_d.as<int>() + ns);
-    gemm<double>(st, 0, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NCp, sG, Sc.as<double>(), NCp, sC, 0.0,
-                 c->Phi.as<double>(), NCp, sG, ns, 0);
-    HIPCHK(hipGetLastError());
-  }
-  {
-    // full coarse basis Phi = [-A_II^{-1} A_IG Phi_G; Phi_G] and the local
-    // coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi
-    DevBuf PhiF, V;
-    const int64_t sF = (int64_t)nt * NCp;
-    CHK(dalloc(PhiF, (size_t)ns * sF * sizeof(double)));
-    CHK(dalloc(V, (size_t)ns * sF * sizeof(double)));
-    launch_fill(st, (int64_t)ns * sF, 0.0, PhiF.as<double>());
-    HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), c->Phi.p,
-                            (size_t)NGp * NCp * sizeof(double), (size_t)NGp * NCp * sizeof(double), ns,
-                            hipMemcpyDeviceToDevice, st));
-    launch_local_apply(st, sd, g, ns, PhiF.as<double>(), V.as<double>());
-    gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, (int64_t)NIp * NIp, V.as<double>(), NCp, sF, 0.0,
-                 PhiF.as<double>(), NCp, sF, ns, 0);
-    launch_local_apply(st, sd, g, ns, PhiF.as<double>(), V.as<double>());
-    gemm<double>(st, 1, 0, NCp, NCp, nt, 1.0, PhiF.as<double>(), NCp, sF, V.as<double>(), NCp, sF, 0.0,
-                 AcLoc.as<double>(), NCp, (int64_t)NCp * NCp, ns, 0);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
-  }
-  Pd64.release();
-  // Kt = K_S^{-1} - Phi G^T
-  gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, c->Phi.as<double>(), NCp, (int64_t)NGp * NCp, G.as<double>(), NCp,
-               (int64_t)NGp * NCp, 1.0, KS.as<double>(), NGp, (int64_t)NGp * NGp, ns, 0);
-  HIPCHK(hipGetLastError());
-  if (std::is_same<T, float>::value) {
-    CHK(dalloc(c->Kt, (size_t)ns * NGp * NGp * sizeof(float)));
-    convert_to_float(st, (int64_t)ns * NGp * NGp, KS.as<double>(), c->Kt.as<float>());
-    HIPCHK(hipStreamSynchronize(st));
-    KS.release();
-  } else {
-    c->Kt.p = KS.p;
-    c->Kt.bytes = KS.bytes;
-    KS.p = nullptr;
-    KS.bytes = 0;
-  }
-  G.release();
-  // coarse matrix and its inverse (FP64)
-  const int nc = c->topo.n_coarse, ldc = c->ldc;
-  if (nc > 0) {
-    CHK(dalloc(Ac, (size_t)ldc * ldc * sizeof(double)));
-    launch_fill(st, (int64_t)ldc * ldc, 0.0, Ac.as<double>());
-    launch_coarse_assemble(st, nc, ldc, c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(),
-                           sd, AcLoc.as<double>(), Ac.as<double>());
-    HIPCHK(hipGetLastError());
-    CHK(dalloc(c->AcKeep, (size_t)ldc * ldc * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(c->AcKeep.p, Ac.p, (size_t)ldc * ldc * sizeof(double), hipMemcpyDeviceToDevice, st));
-    DevBuf Lc, Yc, PSc, ones;
-    const int nct = ldc / CHOL_BLOCK;
-    CHK(dalloc(Lc, (size_t)nct * CHOL_BLOCK * CHOL_BLOCK * sizeof(double)));
-    ProfScope cps(c, "coarse_factor");
-    cholesky<double>(st, Ac.as<double>(), ldc, 0, ldc, 1, Lc.as<double>(), 0, c->info_d.as<int>() + ns + 1);
-    CHK(dalloc(Yc, (size_t)ldc * ldc * sizeof(double)));
-    DevBuf Tc;
-    CHK(dalloc(Tc, (size_t)TRI_SUPER * ldc * sizeof(double)));
-    tri_inverse<double>(st, Ac.as<double>(), ldc, 0, 0, ldc, 1, Lc.as<double>(), 0, Yc.as<double>(), ldc, 0,
-                        Tc.as<double>(), 0);
-    CHK(dalloc(PSc, (size_t)ldc * ldc * sizeof(double)));
-    gemm<double>(st, 1, 0, ldc, ldc, ldc, 1.0, Yc.as<double>(), ldc, 0, Yc.as<double>(), ldc, 0, 0.0,
-                 PSc.as<double>(), ldc, 0, 1, GEMM_LOWER | GEMM_KFROM_DIAG);
-    std::vector<double> one(ldc, 1.0);
-    CHK(upload(ones, one, st));
-    CHK(dalloc(c->Acinv, (size_t)ldc * ldc * sizeof(double)));
-    symmetrize_scale<double, double>(st, PSc.as<double>(), ldc, 0, c->Acinv.as<double>(), ldc, 0,
-                                     ones.as<double>(), 0, ldc, 1);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
-  }
-  std::vector<int> info(ns + 2);
-  HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, (ns + 2) * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  for (int w = 0; w < ns; ++w)
-    if (info[w] != 0)
-      return fail(CB_ERR_NOT_SPD, "local Cholesky failed in subdomain " + std::to_string(w) + " at row " +
-                                      std::to_string(info[w] - 1));
-  if (info[ns] != 0) return fail(CB_ERR_NOT_SPD, "singular local coarse matrix");
-  if (info[ns + 1] != 0) return fail(CB_ERR_NOT_SPD, "coarse Cholesky failed");
-  return CB_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 int cb_factor(cb_ctx* c) {
   if (!c) return fail(CB_ERR_ARG, "null context");
@@ -906,6 +1358,11 @@ int cb_factor(cb_ctx* c) {
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
   c->factored = false;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  c->graph_failed = false;
   g_alloc_stream = c->st;
   int rc = c->precision == CB_FP32_LOCAL ? factor_impl<float>(c) : factor_impl<double>(c);
   if (rc != CB_OK) return rc;
@@ -921,17 +1378,25 @@ int cb_factor(cb_ctx* c) {
   return CB_OK;
 }
 
-static int solve_common(cb_ctx* c, double* u_dev, double rtol, int32_t max_iter, int32_t* iters,
-                        double* relres) {
+}  // extern "C"
+
+namespace {
+
+// PCG on c->bgrid, then the DOF values of x: into u (concatenated DOF
+// vector) or, per problem, into u_ptrs.
+int solve_common(cb_ctx* c, double* u_dev, double* const* u_ptrs_dev, double rtol, int32_t max_iter) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
-  int rc = pcg(c, rtol, max_iter, iters, relres);
-  if (rc == CB_OK || rc == CB_ERR_NO_CONVERGENCE) {
-    launch_gather_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), c->x.as<double>(), u_dev);
-    HIPCHK(hipGetLastError());
-  }
+  int sweeps = 0;
+  CHK(pcg(c, rtol, max_iter, &sweeps));
+  if (u_ptrs_dev)
+    launch_gather_dofs_batch(c->st, c->P, c->n_dof_tot, c->dof_off_d.as<int64_t>(), c->dof_node.as<int64_t>(),
+                             c->x.as<double>(), u_ptrs_dev);
+  else
+    launch_gather_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), c->x.as<double>(), u_dev);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(e1, c->st));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -939,45 +1404,88 @@ static int solve_common(cb_ctx* c, double* u_dev, double rtol, int32_t max_iter,
   c->info.t_solve_ms = ms;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return rc;
+  return CB_OK;
 }
+
+int single_result(cb_ctx* c, int32_t* iters, double* relres) {
+  if (iters) *iters = c->pin_it()[0];
+  if (relres) *relres = c->pin_relres()[0];
+  return pcg_status(c, 0);
+}
+
+}  // namespace
+
+extern "C" {
 
 int cb_solve(cb_ctx* c, const double* f_nodes_dev, double* u_dev, double rtol, int32_t max_iter,
              int32_t* iters, double* final_relres) {
   if (!c || !u_dev) return fail(CB_ERR_ARG, "null argument");
+  CHK(need_single(c));
   if (!c->factored) return fail(CB_ERR_STATE, "cb_solve before cb_factor");
   if (!(rtol > 0.0) || max_iter < 0) return fail(CB_ERR_ARG, "rtol must be > 0 and max_iter >= 0");
-  const int64_t nn = c->n_nodes();
-  const double* f = f_nodes_dev;
-  if (!f) {
-    launch_fill(c->st, nn, 1.0, c->t1.as<double>());
-    f = c->t1.as<double>();
+  if (!f_nodes_dev) {
+    // a null per-problem pointer means f = 1
+    c->pin_fptrs()[0] = nullptr;
+    HIPCHK(hipMemcpyAsync(c->fptrs.p, c->pin_fptrs(), sizeof(double*), hipMemcpyHostToDevice, c->st));
   }
-  GridDesc g{c->N, c->h};
-  launch_load(c->st, g, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), c->dofmask.as<uint8_t>(), f,
-              c->bgrid.as<double>());
+  launch_load(c->st, c->batch(false), c->nn, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), c->dofmask.as<uint8_t>(),
+              f_nodes_dev, f_nodes_dev ? nullptr : c->fptrs.as<const double* const>(), c->bgrid.as<double>());
   HIPCHK(hipGetLastError());
-  return solve_common(c, u_dev, rtol, max_iter, iters, final_relres);
+  CHK(solve_common(c, u_dev, nullptr, rtol, max_iter));
+  return single_result(c, iters, final_relres);
 }
 
 int cb_solve_rhs(cb_ctx* c, const double* b_dev, double* u_dev, double rtol, int32_t max_iter, int32_t* iters,
                  double* final_relres) {
   if (!c || !u_dev || !b_dev) return fail(CB_ERR_ARG, "null argument");
+  CHK(need_single(c));
   if (!c->factored) return fail(CB_ERR_STATE, "cb_solve_rhs before cb_factor");
   if (!(rtol > 0.0) || max_iter < 0) return fail(CB_ERR_ARG, "rtol must be > 0 and max_iter >= 0");
-  launch_fill(c->st, c->n_nodes(), 0.0, c->bgrid.as<double>());
-  launch_scatter_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), b_dev, c->bgrid.as<double>());
+  launch_fill(c->st, c->nn, 0.0, c->bgrid.as<double>());
+  launch_scatter_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), b_dev, c->bgrid.as<double>());
   HIPCHK(hipGetLastError());
-  return solve_common(c, u_dev, rtol, max_iter, iters, final_relres);
+  CHK(solve_common(c, u_dev, nullptr, rtol, max_iter));
+  return single_result(c, iters, final_relres);
+}
+
+int cb_solve_batch(cb_ctx* c, const double* const* f_nodes_dev, double* const* u_dev, double rtol,
+                   int32_t max_iter, int32_t* iters, double* final_relres) {
+  if (!c || !u_dev) return fail(CB_ERR_ARG, "null argument");
+  if (!c->factored) return fail(CB_ERR_STATE, "cb_solve_batch before cb_factor");
+  if (!(rtol > 0.0) || max_iter < 0) return fail(CB_ERR_ARG, "rtol must be > 0 and max_iter >= 0");
+  for (int k = 0; k < c->P; ++k)
+    if (!u_dev[k] && c->pb[k].info.n_dof > 0) return fail(CB_ERR_ARG, "null output of problem " + std::to_string(k));
+  // the staging area may still be read by the previous call's copies
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int k = 0; k < c->P; ++k) {
+    c->pin_fptrs()[k] = f_nodes_dev ? f_nodes_dev[k] : nullptr;
+    c->pin_uptrs()[k] = u_dev[k];
+  }
+  HIPCHK(hipMemcpyAsync(c->fptrs.p, c->pin_fptrs(), c->P * sizeof(double*), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->uptrs.p, c->pin_uptrs(), c->P * sizeof(double*), hipMemcpyHostToDevice, c->st));
+  launch_load(c->st, c->batch(false), c->nn, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), c->dofmask.as<uint8_t>(),
+              nullptr, c->fptrs.as<const double* const>(), c->bgrid.as<double>());
+  HIPCHK(hipGetLastError());
+  CHK(solve_common(c, nullptr, c->uptrs.as<double* const>(), rtol, max_iter));
+  int rc = CB_OK;
+  for (int k = 0; k < c->P; ++k) {
+    if (iters) iters[k] = c->pin_it()[k];
+    if (final_relres) final_relres[k] = c->pin_relres()[k];
+  }
+  for (int k = 0; k < c->P && rc == CB_OK; ++k)
+    if (c->pin_status()[k] == 3) rc = pcg_status(c, k);
+  for (int k = 0; k < c->P && rc == CB_OK; ++k)
+    if (c->pin_status()[k] != 1) rc = pcg_status(c, k);
+  return rc;
 }
 
 int cb_apply_operator(cb_ctx* c, const double* x_dev, double* y_dev) {
   if (!c || !x_dev || !y_dev) return fail(CB_ERR_ARG, "null argument");
-  const int64_t nn = c->n_nodes();
-  launch_fill(c->st, nn, 0.0, c->x.as<double>());
-  launch_scatter_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), x_dev, c->x.as<double>());
-  CHK(apply_A_grid(c, c->x.as<double>(), c->q.as<double>()));
-  launch_gather_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), c->q.as<double>(), y_dev);
+  CHK(need_single(c));
+  launch_fill(c->st, c->nn, 0.0, c->x.as<double>());
+  launch_scatter_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), x_dev, c->x.as<double>());
+  CHK(apply_A_grid(c, c->x.as<double>(), c->q.as<double>(), false));
+  launch_gather_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), c->q.as<double>(), y_dev);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
   return CB_OK;
@@ -985,12 +1493,12 @@ int cb_apply_operator(cb_ctx* c, const double* x_dev, double* y_dev) {
 
 int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev) {
   if (!c || !r_dev || !z_dev) return fail(CB_ERR_ARG, "null argument");
+  CHK(need_single(c));
   if (!c->factored) return fail(CB_ERR_STATE, "preconditioner applied before cb_factor");
-  const int64_t nn = c->n_nodes();
-  launch_fill(c->st, nn, 0.0, c->r.as<double>());
-  launch_scatter_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), r_dev, c->r.as<double>());
-  CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>()));
-  launch_gather_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), c->z.as<double>(), z_dev);
+  launch_fill(c->st, c->nn, 0.0, c->r.as<double>());
+  launch_scatter_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), r_dev, c->r.as<double>());
+  CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), false));
+  launch_gather_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), c->z.as<double>(), z_dev);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
   return CB_OK;
@@ -998,16 +1506,14 @@ int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev) {
 
 int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev) {
   if (!c || !b_dev) return fail(CB_ERR_ARG, "null argument");
-  const int64_t nn = c->n_nodes();
-  const double* f = f_nodes_dev;
-  if (!f) {
-    launch_fill(c->st, nn, 1.0, c->t1.as<double>());
-    f = c->t1.as<double>();
+  CHK(need_single(c));
+  if (!f_nodes_dev) {
+    c->pin_fptrs()[0] = nullptr;
+    HIPCHK(hipMemcpyAsync(c->fptrs.p, c->pin_fptrs(), sizeof(double*), hipMemcpyHostToDevice, c->st));
   }
-  GridDesc g{c->N, c->h};
-  launch_load(c->st, g, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), c->dofmask.as<uint8_t>(), f,
-              c->bgrid.as<double>());
-  launch_gather_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), c->bgrid.as<double>(), b_dev);
+  launch_load(c->st, c->batch(false), c->nn, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), c->dofmask.as<uint8_t>(),
+              f_nodes_dev, f_nodes_dev ? nullptr : c->fptrs.as<const double* const>(), c->bgrid.as<double>());
+  launch_gather_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), c->bgrid.as<double>(), b_dev);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
   return CB_OK;
@@ -1015,19 +1521,22 @@ int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev) {
 
 int cb_grad(cb_ctx* c, const double* u_dev, const double* lam_dev, double* dJ_dtheta_dev, double* dJ_df_dev) {
   if (!c || !u_dev || !lam_dev) return fail(CB_ERR_ARG, "null argument");
-  const int64_t nn = c->n_nodes();
+  CHK(need_single(c));
+  const ProbHost& h = c->pb[0];
+  const int64_t nn1 = (int64_t)(h.N + 1) * (h.N + 1) * (h.N + 1);
   double* ug = c->t1.as<double>();
   double* lg = c->t2.as<double>();
-  launch_fill(c->st, nn, 0.0, ug);
-  launch_fill(c->st, nn, 0.0, lg);
-  launch_scatter_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), u_dev, ug);
-  launch_scatter_dofs(c->st, c->topo.n_dof, c->dof_node.as<int64_t>(), lam_dev, lg);
-  GridDesc g{c->N, c->h};
+  launch_fill(c->st, c->nn, 0.0, ug);
+  launch_fill(c->st, c->nn, 0.0, lg);
+  launch_scatter_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), u_dev, ug);
+  launch_scatter_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), lam_dev, lg);
+  GridDesc g{h.N, h.h};
   if (dJ_dtheta_dev)
     launch_grad_theta(c->st, g, c->cellinfo.as<int32_t>(), c->kappa.as<double>(), c->Kc.as<double>(), ug, lg,
                       dJ_dtheta_dev);
   if (dJ_df_dev)
-    launch_load(c->st, g, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), nullptr, lg, dJ_df_dev);
+    launch_load(c->st, c->batch(false), nn1, c->cellinfo.as<int32_t>(), c->Mc.as<double>(), nullptr, lg, nullptr,
+                dJ_df_dev);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
   return CB_OK;
@@ -1041,16 +1550,26 @@ int cb_query(const cb_ctx* c, cb_info* out) {
   return CB_OK;
 }
 
+int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out) {
+  if (!c || !out) return fail(CB_ERR_ARG, "null argument");
+  if (k < 0 || k >= c->P) return fail(CB_ERR_ARG, "problem index out of range");
+  *out = c->pb[k].info;
+  out->factored = c->factored ? 1 : 0;
+  return CB_OK;
+}
+
 int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_count, int64_t* dof_node,
                        int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type,
                        int32_t* coarse_of_obj) {
   if (!c) return fail(CB_ERR_ARG, "null context");
-  const Topology& t = c->topo;
-  const int64_t ncell = (int64_t)c->N * c->N * c->N;
+  CHK(need_single(c));
+  const ProbHost& h = c->pb[0];
+  const Topology& t = *h.topo;
+  const int64_t ncell = (int64_t)h.N * h.N * h.N;
   if (cell_status)
     for (int64_t i = 0; i < ncell; ++i)
-      cell_status[i] = c->count[i] == 0 ? 0 : (c->count[i] == 512 ? 2 : 1);
-  if (cell_count) std::memcpy(cell_count, c->count.data(), ncell * sizeof(int32_t));
+      cell_status[i] = h.count[i] == 0 ? 0 : (h.count[i] == 512 ? 2 : 1);
+  if (cell_count) std::memcpy(cell_count, h.count.data(), ncell * sizeof(int32_t));
   if (dof_node) std::memcpy(dof_node, t.dof_node.data(), t.n_dof * sizeof(int64_t));
   if (card)
     for (int64_t d = 0; d < t.n_dof; ++d) card[d] = t.card[d];
@@ -1063,20 +1582,24 @@ int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_coun
 
 int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_cells) {
   if (!c) return fail(CB_ERR_ARG, "null context");
-  const int64_t n = (int64_t)c->cut_cells.size();
+  CHK(need_single(c));
+  const ProbHost& h = c->pb[0];
+  const int64_t n = (int64_t)h.cut_local.size();
   if (K && n) HIPCHK(hipMemcpy(K, c->Kc.p, n * PACK36 * sizeof(double), hipMemcpyDeviceToHost));
   if (M && n) HIPCHK(hipMemcpy(M, c->Mc.p, n * PACK36 * sizeof(double), hipMemcpyDeviceToHost));
-  if (cut_cells && n) std::memcpy(cut_cells, c->cut_cells.data(), n * sizeof(int64_t));
+  if (cut_cells && n) std::memcpy(cut_cells, h.cut_local.data(), n * sizeof(int64_t));
   return CB_OK;
 }
 
 int cb_export_coarse(const cb_ctx* c, double* Ac) {
   if (!c || !Ac) return fail(CB_ERR_ARG, "null argument");
+  CHK(need_single(c));
   if (!c->factored) return fail(CB_ERR_STATE, "coarse matrix requested before cb_factor");
-  const int nc = c->topo.n_coarse, ldc = c->ldc;
+  const ProbHost& h = c->pb[0];
+  const int nc = h.topo->n_coarse, ldc = h.ldc;
   if (nc == 0) return CB_OK;
-  HIPCHK(hipMemcpy2D(Ac, nc * sizeof(double), c->AcKeep.p, ldc * sizeof(double), nc * sizeof(double), nc,
-                     hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy2D(Ac, nc * sizeof(double), c->AcKeep.as<double>() + h.ac_off, ldc * sizeof(double),
+                     nc * sizeof(double), nc, hipMemcpyDeviceToHost));
   return CB_OK;
 }
 

@@ -91,23 +91,34 @@ __device__ inline int cell_kept_bits(int N, const double* __restrict__ xi, const
   return cnt;
 }
 
-__global__ __launch_bounds__(256) void classify_kernel(int N, const double* __restrict__ xi_g,
-                                                       const double* __restrict__ balls, int nb,
+// Cells of all problems in one launch: blocks of CELLS_PER_BLOCK cells lie
+// in one problem's cell segment (segments are SEG_ALIGN-aligned).
+__global__ __launch_bounds__(256) void classify_kernel(BatchDev bd, int64_t n_cells_total,
+                                                       const double* __restrict__ xi_g,
+                                                       const double* __restrict__ balls,
                                                        int32_t* __restrict__ count) {
   __shared__ double xi[8];
   if (threadIdx.x < 8) xi[threadIdx.x] = xi_g[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t ncell = (int64_t)N * N * N;
-  const int64_t cell = (int64_t)blockIdx.x * CELLS_PER_BLOCK + (threadIdx.x / WAVE);
-  if (cell >= ncell) return;
+  const int64_t base = (int64_t)blockIdx.x * CELLS_PER_BLOCK;
+  const int64_t cell = base + (threadIdx.x / WAVE);
+  if (cell >= n_cells_total) return;
+  const int p = find_segment(bd.cell_off, bd.P, base);
+  const ProbDev pr = bd.prob[p];
+  const int64_t local = cell - pr.cell_off;
+  if (local >= (int64_t)pr.N * pr.N * pr.N) {
+    if (lane == 0) count[cell] = 0;
+    return;
+  }
   unsigned bits;
-  int cnt = cell_kept_bits(N, xi, balls, nb, cell, lane, bits);
+  const int cnt = cell_kept_bits(pr.N, xi, balls + 4 * (int64_t)pr.ball_off, pr.nb, local, lane, bits);
   if (lane == 0) count[cell] = cnt;
 }
 
-__global__ __launch_bounds__(256) void integrate_cut_kernel(int N, const double* __restrict__ xi_g,
-                                                            const double* __restrict__ balls, int nb,
+// cut_cells: ids in the concatenated cell space.
+__global__ __launch_bounds__(256) void integrate_cut_kernel(BatchDev bd, const double* __restrict__ xi_g,
+                                                            const double* __restrict__ balls,
                                                             const int64_t* __restrict__ cut_cells,
                                                             int64_t n_cut, double* __restrict__ Kc,
                                                             double* __restrict__ Mc) {
@@ -120,7 +131,12 @@ __global__ __launch_bounds__(256) void integrate_cut_kernel(int N, const double*
   const int64_t idx = (int64_t)blockIdx.x * CELLS_PER_BLOCK + wv;
   const bool valid = idx < n_cut;
   unsigned bits = 0;
-  if (valid) cell_kept_bits(N, xi, balls, nb, cut_cells[idx], lane, bits);
+  if (valid) {
+    const int64_t cell = cut_cells[idx];
+    const int p = find_segment(bd.cell_off, bd.P, cell);
+    const ProbDev pr = bd.prob[p];
+    cell_kept_bits(pr.N, xi, balls + 4 * (int64_t)pr.ball_off, pr.nb, cell - pr.cell_off, lane, bits);
+  }
   for (int t = 0; t < 8; ++t) keep[wv][lane + WAVE * t] = (unsigned char)((bits >> t) & 1u);
   __syncthreads();
   if (!valid || lane >= PACK36) return;
@@ -152,20 +168,20 @@ __global__ __launch_bounds__(256) void integrate_cut_kernel(int N, const double*
 
 }  // namespace
 
-void launch_classify(hipStream_t st, int N, const double* xi, const double* balls, int nb,
-                     int32_t* count) {
-  const int64_t ncell = (int64_t)N * N * N;
-  const int64_t blocks = (ncell + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK;
-  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, st, N, xi, balls, nb,
+void launch_classify(hipStream_t st, const BatchDev& b, int64_t n_cells_total, const double* xi,
+                     const double* balls, int32_t* count) {
+  if (n_cells_total <= 0) return;
+  const int64_t blocks = (n_cells_total + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK;
+  hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, n_cells_total, xi, balls,
                      count);
 }
 
-void launch_integrate_cut(hipStream_t st, int N, const double* xi, const double* balls, int nb,
+void launch_integrate_cut(hipStream_t st, const BatchDev& b, const double* xi, const double* balls,
                           const int64_t* cut_cells, int64_t n_cut, double* Kc, double* Mc) {
   if (n_cut <= 0) return;
   const int64_t blocks = (n_cut + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK;
-  hipLaunchKernelGGL(integrate_cut_kernel, dim3((unsigned)blocks), dim3(256), 0, st, N, xi, balls,
-                     nb, cut_cells, n_cut, Kc, Mc);
+  hipLaunchKernelGGL(integrate_cut_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, xi, balls, cut_cells,
+                     n_cut, Kc, Mc);
 }
 
 }  // namespace cutbddc

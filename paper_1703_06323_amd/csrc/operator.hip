@@ -15,7 +15,7 @@ namespace {
 __constant__ double c_Kref[64];   // reference Q1 stiffness (kappa = 1, h = 1)
 __constant__ double c_Mref[64];   // reference Q1 mass (h = 1)
 
-template <bool MASS>
+template <bool MASS, bool ONES = false>
 __device__ inline double node_gather(int N, int64_t I, int64_t J, int64_t K,
                                      const int32_t* __restrict__ cellinfo,
                                      const double* __restrict__ kappa,
@@ -44,14 +44,14 @@ __device__ inline double node_gather(int N, int64_t I, int64_t J, int64_t K,
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const int64_t nb = n0 + (b & 1) + N1 * (((b >> 1) & 1) + N1 * ((b >> 2) & 1));
-            row += R[a * 8 + b] * x[nb];
+            row += R[a * 8 + b] * (ONES ? 1.0 : x[nb]);
           }
         } else {
           const double* R = Mat + (int64_t)info * PACK36;
 #pragma unroll
           for (int b = 0; b < 8; ++b) {
             const int64_t nb = n0 + (b & 1) + N1 * (((b >> 1) & 1) + N1 * ((b >> 2) & 1));
-            row += R[pack_index(a, b)] * x[nb];
+            row += R[pack_index(a, b)] * (ONES ? 1.0 : x[nb]);
           }
         }
         acc += s * row;
@@ -61,39 +61,59 @@ __device__ inline double node_gather(int N, int64_t I, int64_t J, int64_t K,
   return acc;
 }
 
-__global__ __launch_bounds__(256) void apply_A_kernel(int N, double h,
+// Node-space kernels run in blocks of SEG_ALIGN threads, so every block lies
+// inside one problem's node segment and finds it from its first node.
+__global__ __launch_bounds__(256) void apply_A_kernel(BatchDev bd, int64_t nn,
                                                       const int32_t* __restrict__ cellinfo,
                                                       const double* __restrict__ kappa,
                                                       const double* __restrict__ Kc,
                                                       const uint8_t* __restrict__ dofmask,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y) {
-  const int64_t N1 = N + 1;
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N1 * N1 * N1) return;
+  const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
+  const int64_t n = base + threadIdx.x;
+  if (n >= nn) return;
+  const int p = find_segment(bd.node_off, bd.P, base);
+  if (bd.active && !bd.active[p]) return;
   if (!dofmask[n]) {
     y[n] = 0.0;
     return;
   }
-  const int64_t I = n % N1, J = (n / N1) % N1, K = n / (N1 * N1);
-  y[n] = node_gather<false>(N, I, J, K, cellinfo, kappa, Kc, x, h);
+  const ProbDev pr = bd.prob[p];
+  const int64_t N1 = pr.N + 1;
+  const int64_t l = n - pr.node_off;
+  const int64_t I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
+  y[n] = node_gather<false>(pr.N, I, J, K, cellinfo + pr.cell_off, kappa + pr.cell_off, Kc,
+                            x + pr.node_off, pr.h);
 }
 
-__global__ __launch_bounds__(256) void load_kernel(int N, double h3,
+__global__ __launch_bounds__(256) void load_kernel(BatchDev bd, int64_t nn,
                                                    const int32_t* __restrict__ cellinfo,
                                                    const double* __restrict__ Mc,
                                                    const uint8_t* __restrict__ outmask,
                                                    const double* __restrict__ f,
+                                                   const double* const* __restrict__ f_ptrs,
                                                    double* __restrict__ b) {
-  const int64_t N1 = N + 1;
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N1 * N1 * N1) return;
+  const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
+  const int64_t n = base + threadIdx.x;
+  if (n >= nn) return;
   if (outmask && !outmask[n]) {
     b[n] = 0.0;
     return;
   }
-  const int64_t I = n % N1, J = (n / N1) % N1, K = n / (N1 * N1);
-  b[n] = node_gather<true>(N, I, J, K, cellinfo, nullptr, Mc, f, h3);
+  const int p = find_segment(bd.node_off, bd.P, base);
+  const ProbDev pr = bd.prob[p];
+  const int64_t N1 = pr.N + 1;
+  const int64_t l = n - pr.node_off;
+  if (l >= N1 * N1 * N1) {
+    b[n] = 0.0;
+    return;
+  }
+  const int64_t I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
+  const double* fp = f_ptrs ? f_ptrs[p] : f + pr.node_off;
+  const double h3 = pr.h * pr.h * pr.h;
+  b[n] = fp ? node_gather<true>(pr.N, I, J, K, cellinfo + pr.cell_off, nullptr, Mc, fp, h3)
+            : node_gather<true, true>(pr.N, I, J, K, cellinfo + pr.cell_off, nullptr, Mc, nullptr, h3);
 }
 
 __global__ __launch_bounds__(256) void grad_theta_kernel(int N, double h,
@@ -148,29 +168,132 @@ __global__ void fill_kernel(int64_t n, double v, double* __restrict__ x) {
   if (i < n) x[i] = v;
 }
 
-// x += alpha p, r -= alpha q with alpha = S[0] / S[1] (rho / p.q)
-__global__ void cg_update_xr_kernel(int64_t n, const double* __restrict__ S, const double* __restrict__ p,
-                                    const double* __restrict__ q, double* __restrict__ x,
-                                    double* __restrict__ r) {
+__global__ void copy_kernel(int64_t n, const double* __restrict__ src, double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double alpha = S[0] / S[1];
+  if (i < n) dst[i] = src[i];
+}
+
+// x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem.
+__global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t nn, const double* __restrict__ S,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q, double* __restrict__ x,
+                                                           double* __restrict__ r) {
+  const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
+  const int64_t i = base + threadIdx.x;
+  if (i >= nn) return;
+  const int pb = find_segment(bd.node_off, bd.P, base);
+  if (bd.active && !bd.active[pb]) return;
+  const double alpha = S[CG_S * pb + 0] / S[CG_S * pb + 1];
   x[i] += alpha * p[i];
   r[i] -= alpha * q[i];
 }
 
-// p = z + beta p with beta = S[3] / S[0]; the last block to finish cannot be
-// known, so the rho swap S[0] = S[3] is a separate single-thread kernel.
-__global__ void cg_update_p_kernel(int64_t n, const double* __restrict__ S, const double* __restrict__ z,
-                                   double* __restrict__ p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double beta = S[3] / S[0];
+// p = z + beta p with beta = rho_new / rho; the swap rho = rho_new is a
+// separate kernel since no block knows that the others are done.
+__global__ __launch_bounds__(256) void cg_update_p_kernel(BatchDev bd, int64_t nn, const double* __restrict__ S,
+                                                          const double* __restrict__ z, double* __restrict__ p) {
+  const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
+  const int64_t i = base + threadIdx.x;
+  if (i >= nn) return;
+  const int pb = find_segment(bd.node_off, bd.P, base);
+  if (bd.active && !bd.active[pb]) return;
+  const double beta = S[CG_S * pb + 3] / S[CG_S * pb + 0];
   p[i] = z[i] + beta * p[i];
 }
 
-__global__ void cg_swap_rho_kernel(double* S) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) S[0] = S[3];
+__global__ void cg_swap_rho_kernel(int P, const int32_t* __restrict__ active, double* __restrict__ S) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
+    if (!active || active[p]) S[CG_S * p + 0] = S[CG_S * p + 3];
+}
+
+__global__ void set_params_kernel(double* params, double rtol, int32_t max_iter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    params[0] = rtol;
+    params[1] = (double)max_iter;
+  }
+}
+
+// Number of running problems, written by thread 0 (one block of 256).
+__device__ inline void count_active(int P, const int32_t* active, int32_t* n_active) {
+  __shared__ int32_t cnt[256];
+  int32_t c = 0;
+  for (int p = threadIdx.x; p < P; p += 256) c += active[p] ? 1 : 0;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_active = cnt[0];
+}
+
+// Start of PCG: a zero right-hand side is converged at iteration 0; with
+// max_iter = 0 the problem stops at once without convergence.
+__global__ __launch_bounds__(256) void cg_init_kernel(int P, const double* __restrict__ params,
+                                                      double* __restrict__ S, int32_t* __restrict__ active,
+                                                      int32_t* __restrict__ it, int32_t* __restrict__ status,
+                                                      double* __restrict__ relres, int32_t* __restrict__ n_active) {
+  const int32_t max_iter = (int32_t)params[1];
+  for (int p = threadIdx.x; p < P; p += 256) {
+    const double bb = S[CG_S * p + 4];
+    it[p] = 0;
+    if (bb == 0.0) {
+      active[p] = 0;
+      status[p] = 1;
+      relres[p] = 0.0;
+    } else if (max_iter <= 0) {
+      active[p] = 0;
+      status[p] = 2;
+      relres[p] = 1.0;
+    } else {
+      active[p] = 1;
+      status[p] = 0;
+      relres[p] = 1.0;
+    }
+  }
+  __syncthreads();
+  count_active(P, active, n_active);
+}
+
+// After the x, r update of an iteration: count it, test |r| < rtol |b|, a
+// non-finite residual, and the iteration limit.
+__global__ __launch_bounds__(256) void cg_check_kernel(int P, const double* __restrict__ params,
+                                                       const double* __restrict__ S, int32_t* __restrict__ active,
+                                                       int32_t* __restrict__ it, int32_t* __restrict__ status,
+                                                       double* __restrict__ relres, int32_t* __restrict__ n_active) {
+  const double rtol = params[0];
+  const int32_t max_iter = (int32_t)params[1];
+  for (int p = threadIdx.x; p < P; p += 256) {
+    if (!active[p]) continue;
+    const int32_t k = it[p] + 1;
+    it[p] = k;
+    const double rr = S[CG_S * p + 2];
+    if (!isfinite(rr)) {
+      active[p] = 0;
+      status[p] = 3;
+      continue;
+    }
+    const double rel = sqrt(rr) / sqrt(S[CG_S * p + 4]);
+    relres[p] = rel;
+    if (rel < rtol) {
+      active[p] = 0;
+      status[p] = 1;
+    } else if (k >= max_iter) {
+      active[p] = 0;
+      status[p] = 2;
+    }
+  }
+  __syncthreads();
+  count_active(P, active, n_active);
+}
+
+__global__ void gather_dofs_batch_kernel(int P, int64_t n, const int64_t* __restrict__ dof_off,
+                                         const int64_t* __restrict__ dof_node, const double* __restrict__ grid,
+                                         double* const* __restrict__ u_ptrs) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n) return;
+  const int p = find_segment(dof_off, P, d);
+  u_ptrs[p][d - dof_off[p]] = grid[dof_node[d]];
 }
 
 __global__ void convert_kernel(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
@@ -178,7 +301,6 @@ __global__ void convert_kernel(int64_t n, const double* __restrict__ a, float* _
   if (i < n) b[i] = (float)a[i];
 }
 
-constexpr int DOT_BLOCKS = 512;
 constexpr int DOT_THREADS = 256;
 
 __device__ inline double block_sum(double v, double* sh) {
@@ -192,25 +314,37 @@ __device__ inline double block_sum(double v, double* sh) {
   return t;
 }
 
-__global__ __launch_bounds__(DOT_THREADS) void dot_partial_kernel(int64_t n, const double* __restrict__ x,
-                                                                  const double* __restrict__ y,
-                                                                  double* __restrict__ partial) {
+// One block per DOT_CHUNK-sized chunk of a problem's node segment.
+__global__ __launch_bounds__(DOT_THREADS) void dot_chunk_kernel(BatchDev bd, const int32_t* __restrict__ chunk_ptr,
+                                                                const double* __restrict__ x,
+                                                                const double* __restrict__ y,
+                                                                double* __restrict__ partial) {
   __shared__ double sh[DOT_THREADS / 64];
+  const int p = find_segment(chunk_ptr, bd.P, blockIdx.x);
+  if (bd.active && !bd.active[p]) return;
+  const ProbDev pr = bd.prob[p];
+  const int64_t N1 = pr.N + 1;
+  const int64_t seg_end = pr.node_off + N1 * N1 * N1;
+  const int64_t start = pr.node_off + (int64_t)(blockIdx.x - chunk_ptr[p]) * DOT_CHUNK;
+  const int64_t end = min(start + DOT_CHUNK, seg_end);
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * DOT_THREADS + threadIdx.x; i < n;
-       i += (int64_t)DOT_BLOCKS * DOT_THREADS)
-    acc += x[i] * y[i];
-  double t = block_sum(acc, sh);
+  for (int64_t i = start + threadIdx.x; i < end; i += DOT_THREADS) acc += x[i] * y[i];
+  const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(DOT_THREADS) void dot_final_kernel(const double* __restrict__ partial,
-                                                                double* __restrict__ out) {
-  __shared__ double sh[DOT_THREADS / 64];
+// One wave per problem sums its chunk partials in a fixed order.
+__global__ __launch_bounds__(256) void dot_final_kernel(BatchDev bd, const int32_t* __restrict__ chunk_ptr,
+                                                        const double* __restrict__ partial,
+                                                        double* __restrict__ out, int stride) {
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= bd.P) return;
+  if (bd.active && !bd.active[p]) return;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < DOT_BLOCKS; i += DOT_THREADS) acc += partial[i];
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) *out = t;
+  for (int c = chunk_ptr[p] + lane; c < chunk_ptr[p + 1]; c += 64) acc += partial[c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) out[(int64_t)p * stride] = acc;
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -222,18 +356,20 @@ void set_reference_matrices(const double* Kref, const double* Mref) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_Mref), Mref, 64 * sizeof(double));
 }
 
-void launch_apply_A(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* kappa,
-                    const double* Kc, const uint8_t* dofmask, const double* x, double* y) {
-  const int64_t nn = (int64_t)(g.N + 1) * (g.N + 1) * (g.N + 1);
-  hipLaunchKernelGGL(apply_A_kernel, dim3(nblocks(nn, 256)), dim3(256), 0, st, g.N, g.h, cellinfo,
+void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
+                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x,
+                    double* y) {
+  if (nn <= 0) return;
+  hipLaunchKernelGGL(apply_A_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, cellinfo,
                      kappa, Kc, dofmask, x, y);
 }
 
-void launch_load(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* Mc,
-                 const uint8_t* outmask, const double* f, double* b) {
-  const int64_t nn = (int64_t)(g.N + 1) * (g.N + 1) * (g.N + 1);
-  hipLaunchKernelGGL(load_kernel, dim3(nblocks(nn, 256)), dim3(256), 0, st, g.N, g.h * g.h * g.h,
-                     cellinfo, Mc, outmask, f, b);
+void launch_load(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
+                 const double* Mc, const uint8_t* outmask, const double* f,
+                 const double* const* f_ptrs, double* out) {
+  if (nn <= 0) return;
+  hipLaunchKernelGGL(load_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, cellinfo, Mc,
+                     outmask, f, f_ptrs, out);
 }
 
 void launch_grad_theta(hipStream_t st, GridDesc g, const int32_t* cellinfo, const double* kappa,
@@ -262,16 +398,44 @@ void launch_fill(hipStream_t st, int64_t n, double v, double* x) {
   hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, v, x);
 }
 
-int dot_partials() { return DOT_BLOCKS; }
-
-void launch_cg_update_xr(hipStream_t st, int64_t n, const double* S, const double* p, const double* q, double* x,
-                         double* r) {
-  hipLaunchKernelGGL(cg_update_xr_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, S, p, q, x, r);
+void launch_copy(hipStream_t st, int64_t n, const double* src, double* dst) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, src, dst);
 }
 
-void launch_cg_update_p(hipStream_t st, int64_t n, double* S, const double* z, double* p) {
-  hipLaunchKernelGGL(cg_update_p_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, S, z, p);
-  hipLaunchKernelGGL(cg_swap_rho_kernel, dim3(1), dim3(64), 0, st, S);
+void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
+                         const double* q, double* x, double* r) {
+  hipLaunchKernelGGL(cg_update_xr_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, p, q,
+                     x, r);
+}
+
+void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
+                        double* p) {
+  hipLaunchKernelGGL(cg_update_p_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, z, p);
+  hipLaunchKernelGGL(cg_swap_rho_kernel, dim3(nblocks(b.P, 256)), dim3(256), 0, st, b.P, b.active, S);
+}
+
+void launch_set_params(hipStream_t st, double* params, double rtol, int32_t max_iter) {
+  hipLaunchKernelGGL(set_params_kernel, dim3(1), dim3(64), 0, st, params, rtol, max_iter);
+}
+
+void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int32_t* active, int32_t* it,
+                    int32_t* status, double* relres, int32_t* n_active) {
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(256), 0, st, P, params, S, active, it, status, relres,
+                     n_active);
+}
+
+void launch_cg_check(hipStream_t st, int P, const double* params, const double* S, int32_t* active,
+                     int32_t* it, int32_t* status, double* relres, int32_t* n_active) {
+  hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(256), 0, st, P, params, S, active, it, status, relres,
+                     n_active);
+}
+
+void launch_gather_dofs_batch(hipStream_t st, int P, int64_t n_dof_total, const int64_t* dof_off,
+                              const int64_t* dof_node, const double* grid, double* const* u_ptrs) {
+  if (n_dof_total <= 0) return;
+  hipLaunchKernelGGL(gather_dofs_batch_kernel, dim3(nblocks(n_dof_total, 256)), dim3(256), 0, st, P,
+                     n_dof_total, dof_off, dof_node, grid, u_ptrs);
 }
 
 void convert_to_float(hipStream_t st, int64_t n, const double* a, float* b) {
@@ -279,11 +443,12 @@ void convert_to_float(hipStream_t st, int64_t n, const double* a, float* b) {
   hipLaunchKernelGGL(convert_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, a, b);
 }
 
-void launch_dot(hipStream_t st, int64_t n, const double* x, const double* y, double* partial,
-                double* out) {
-  hipLaunchKernelGGL(dot_partial_kernel, dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, st, n, x, y,
-                     partial);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(DOT_THREADS), 0, st, partial, out);
+void launch_dot(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks,
+                const double* x, const double* y, double* partial, double* out, int stride) {
+  if (n_chunks <= 0) return;
+  hipLaunchKernelGGL(dot_chunk_kernel, dim3(n_chunks), dim3(DOT_THREADS), 0, st, b, chunk_ptr, x, y, partial);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(nblocks(b.P, 4)), dim3(256), 0, st, b, chunk_ptr, partial, out,
+                     stride);
 }
 
 }  // namespace cutbddc

@@ -132,10 +132,18 @@ class Pool {
   uint64_t gen_ = 0;
 };
 
+// Set on threads that each index a whole problem of a batch: their loops run
+// inline instead of on the shared pool.
+thread_local bool t_serial = false;
+
 // f(begin, end) over [0, n) split into contiguous chunks.
 template <typename F>
 void parallel_for(int64_t n, F&& f) {
   if (n <= 0) return;
+  if (t_serial) {
+    f(0, n);
+    return;
+  }
   const int chunks = (int)std::min<int64_t>(n, 4 * Pool::get().size());
   std::function<void(int)> task = [&](int c) {
     const int64_t b = n * c / chunks, e = n * (c + 1) / chunks;
@@ -724,5 +732,9 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
 }
 
 void parallel_rows(int64_t n, const std::function<void(int64_t, int64_t)>& f) { parallel_for(n, f); }
+
+void set_serial_indexing(bool serial) { t_serial = serial; }
+
+int indexing_threads() { return Pool::get().size(); }
 
 }  // namespace cutbddc

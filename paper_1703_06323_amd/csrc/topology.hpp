@@ -72,6 +72,13 @@ void reset_topology(Topology& t);
 // Runs f(begin, end) over chunks of [0, n) on the indexing thread pool.
 void parallel_rows(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 
+// On the calling thread, run the loops of build_topology inline (for
+// threads that each index one problem of a batch concurrently).
+void set_serial_indexing(bool serial);
+
+// Threads of the indexing pool (including the caller).
+int indexing_threads();
+
 // Exact class of the FE edge from grid node (I,J,K) to (I,J,K)+e_axis:
 // 0 interior (edge inside Omega), 1 exterior (edge misses Omega), 2 cut.
 int segment_class(int N, const int64_t ijk[3], int axis, const std::vector<double>& centres,

@@ -84,13 +84,17 @@ def load_library(path: str = LIB_PATH):
     lib.cb_profile.argtypes = [vp, C.c_int32]
     lib.cb_profile_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
+    lib.cb_setup_batch.argtypes = [C.POINTER(cb_problem), C.c_int32, vp, C.POINTER(vp)]
+    lib.cb_solve_batch.argtypes = [vp, vp, vp, C.c_double, C.c_int32, ip, dp]
+    lib.cb_query_problem.argtypes = [vp, C.c_int32, C.POINTER(cb_info)]
     lib.cb_last_error.restype = C.c_char_p
     lib.cb_destroy.argtypes = [vp]
     lib.cb_destroy.restype = None
     for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
                  "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
-                 "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing"):
+                 "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing",
+                 "cb_setup_batch", "cb_solve_batch", "cb_query_problem"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -262,6 +266,88 @@ class Solver:
         A = np.zeros((nc, nc))
         _check(_lib.cb_export_coarse(self.ctx, A.ctypes.data_as(C.c_void_p)))
         return A
+
+
+class BatchSolver:
+    """Many independent cut-cube problems in one context: setup, factor and
+    PCG of all of them run as shared kernel launches (cb_setup_batch,
+    cb_solve_batch).  The problems must share s and every option."""
+
+    def __init__(self, problems, stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("cutbddc needs a GPU")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        n = len(problems)
+        arr = (cb_problem * n)()
+        self._keep = []
+        Pd = C.POINTER(C.c_double)
+        for k, problem in enumerate(problems):
+            centres = np.ascontiguousarray(problem.centres, dtype=np.float64).reshape(-1)
+            radii = np.ascontiguousarray(problem.radii, dtype=np.float64)
+            kappa = None if problem.kappa is None else np.ascontiguousarray(problem.kappa, dtype=np.float64)
+            self._keep.append((centres, radii, kappa))
+            arr[k] = cb_problem(int(problem.n), int(problem.s), int(radii.size), centres.ctypes.data_as(Pd),
+                                radii.ctypes.data_as(Pd), kappa.ctypes.data_as(Pd) if kappa is not None else None,
+                                int(problem.weighting), int(problem.objects), int(problem.coarse_variant),
+                                int(problem.local_precision), int(problem.full_elements))
+        st = torch.cuda.current_stream() if stream is None else stream
+        self.stream = st
+        ctx = C.c_void_p()
+        _check(lib.cb_setup_batch(arr, n, C.c_void_p(st.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        self.size = n
+        self.ns = [int(p.n) for p in problems]
+
+    def __del__(self):
+        if getattr(self, "ctx", None) and _lib is not None:
+            _lib.cb_destroy(self.ctx)
+            self.ctx = None
+
+    def close(self):
+        self.__del__()
+
+    def factor(self):
+        _check(_lib.cb_factor(self.ctx))
+
+    def info(self) -> dict:
+        inf = cb_info()
+        _check(_lib.cb_query(self.ctx, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in cb_info._fields_}
+
+    def problem_info(self, k: int) -> dict:
+        inf = cb_info()
+        _check(_lib.cb_query_problem(self.ctx, int(k), C.byref(inf)))
+        return {kk: getattr(inf, kk) for kk, _ in cb_info._fields_}
+
+    def n_dofs(self):
+        return [int(self.problem_info(k)["n_dof"]) for k in range(self.size)]
+
+    def solve(self, fs=None, rtol=1e-8, max_iter=1000, outputs=None, allow_no_convergence=False):
+        """fs: list of cuda float64 tensors [(N_k+1)^3] (or None entries / None
+        for f = 1).  Returns (list of u_k [n_dof_k], iterations [n],
+        relative residuals [n])."""
+        n = self.size
+        if outputs is None:
+            outputs = [self.torch.empty(d, dtype=self.torch.float64, device=self.device) for d in self.n_dofs()]
+        fptr = (C.c_void_p * n)()
+        keep = []
+        if fs is not None:
+            for k, f in enumerate(fs):
+                if f is not None:
+                    t = self.torch.as_tensor(f, dtype=self.torch.float64, device=self.device).contiguous()
+                    keep.append(t)
+                    fptr[k] = t.data_ptr()
+        uptr = (C.c_void_p * n)(*[u.data_ptr() for u in outputs])
+        it = np.zeros(n, np.int32)
+        rel = np.zeros(n, np.float64)
+        rc = _lib.cb_solve_batch(self.ctx, fptr if fs is not None else None, uptr, float(rtol), int(max_iter),
+                                 it.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 rel.ctypes.data_as(C.POINTER(C.c_double)))
+        _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
+        return outputs, it, rel
 
 
 def _problem_struct(problem):

@@ -10,7 +10,10 @@ Outputs (next to this script):
                           at rtol 1e-8, plus its full 2-norm
 With the argument `96`, the same files for the 96^3 forty-ball workload with
 log-normal conductivity (cut_cube_96.json, cut_cube_96_sample.npz); with
-`grad`, gradient_64.npz (adjoint gradient of the differentiation workload).
+`grad`, gradient_64.npz (adjoint gradient of the differentiation workload);
+with `batch`, batch_256.json + batch_256_sample.npz (per problem of the
+256-problem batch: sizes, SHA-256 of the DOF nodes, iteration count and a
+16-DOF sample plus the 2-norm of the FP64 PCG solution at rtol 1e-8).
 """
 import hashlib
 import json
@@ -91,9 +94,51 @@ def gradient():
     print("gradient golden written", time.time() - t0, "s; iterations", it0, it, itl)
 
 
+def _batch_one(k):
+    p = W.batch_256()[k].with_options(local_precision=0)
+    t0 = time.time()
+    s = OracleSolver(p)
+    x, it, rel = s.solve(rtol=1e-8)
+    rng = np.random.default_rng(1000 + k)
+    idx = np.sort(rng.choice(s.n_dof, size=min(16, s.n_dof), replace=False))
+    return {"k": k, "name": p.name, "n": p.n, "n_dof": int(s.n_dof), "n_coarse": int(s.topo.n_coarse),
+            "iterations": int(it), "relres": float(rel), "norm": float(np.linalg.norm(x)),
+            "dof_node_sha256": sha(s.d.dof_node.astype(np.int64)),
+            "idx": idx.tolist(), "u": x[idx].tolist(), "seconds": time.time() - t0}
+
+
+def batch(workers=6):
+    """The 256-problem batch (FP64 oracle; the GPU batch runs FP32 local
+    solves and is compared at the FP32 tolerance)."""
+    from multiprocessing import Pool
+    t0 = time.time()
+    with Pool(workers) as pool:
+        rows = []
+        for r in pool.imap_unordered(_batch_one, range(256)):
+            rows.append(r)
+            print(f"{len(rows):3d}/256 problem {r['k']} n={r['n']} ndof={r['n_dof']} it={r['iterations']} "
+                  f"{r['seconds']:.1f}s", flush=True)
+    rows.sort(key=lambda r: r["k"])
+    idx = np.full((256, 16), -1, dtype=np.int64)
+    u = np.zeros((256, 16))
+    for r in rows:
+        idx[r["k"], :len(r["idx"])] = r["idx"]
+        u[r["k"], :len(r["u"])] = r["u"]
+    np.savez_compressed(os.path.join(HERE, "batch_256_sample.npz"), idx=idx, u=u,
+                        norm=np.array([r["norm"] for r in rows]))
+    meta = [{k: r[k] for k in ("k", "name", "n", "n_dof", "n_coarse", "iterations", "relres",
+                               "dof_node_sha256")} for r in rows]
+    with open(os.path.join(HERE, "batch_256.json"), "w") as fh:
+        json.dump({"workload": "batch_256 (seed 3)", "rtol": 1e-8, "oracle_seconds": time.time() - t0,
+                   "problems": meta}, fh, indent=0)
+    print("batch golden written", time.time() - t0, "s")
+
+
 if __name__ == "__main__":
     arg = sys.argv[1] if len(sys.argv) > 1 else "64"
     if arg == "grad":
         gradient()
+    elif arg == "batch":
+        batch()
     else:
         main(arg)

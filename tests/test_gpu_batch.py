@@ -1,0 +1,173 @@
+"""Batches of independent problems in one context (cb_setup_batch,
+cb_solve_batch) against the oracle, problem by problem.
+
+Small mixed batch: every problem solved by the oracle's BDDC-PCG; FP64 local
+solves must match it to 1e-10 (relative 2-norm) with the same iteration
+count, FP32 local solves to 1e-6 within one iteration.  The batch must also
+reproduce the single-problem path, and repeated solves (replays of the
+captured PCG iteration) must agree with eager launches.  The 256-problem
+batch is checked against stored oracle values (tests/golden/make_golden.py
+batch): sizes, iteration counts, a 16-DOF sample and the 2-norm of each
+solution."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+try:
+    import torch
+except ImportError:  # pragma: no cover
+    torch = None
+
+import workloads as W
+from oracle import OracleSolver
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_batch(precision=0):
+    """Mixed sizes with s = 4: the single-ball mesh, random-ball meshes of
+    several sizes, an uncut mesh, a one-subdomain mesh (no interface, no
+    coarse space) and a zero right-hand side."""
+    rng = np.random.default_rng(21)
+    out = [W.single_ball()]
+    for n, nb in ((16, 6), (12, 4), (20, 9), (16, 3)):
+        c = rng.uniform(0.1, 0.9, size=(nb, 3))
+        r = rng.uniform(0.05, 0.12, size=nb)
+        f = rng.uniform(0.0, 1.0, size=(n + 1) ** 3)
+        out.append(W.Problem(n=n, s=4, centres=c, radii=r, f=f, name=f"mix_n{n}_b{nb}"))
+    out.append(W.uncut(8, 4))
+    out.append(W.Problem(n=4, s=4, centres=np.array([[0.3, 0.6, 0.5]]), radii=np.array([0.2]),
+                         f=np.ones(125), name="one_subdomain"))
+    z = W.uncut(12, 4)
+    out.append(z.with_options(f=np.zeros(13 ** 3), name="zero_rhs"))
+    return [p.with_options(local_precision=precision) for p in out]
+
+
+def fvec(p):
+    return torch.tensor(p.f if p.f is not None else np.ones((p.n + 1) ** 3), device="cuda")
+
+
+_oracle = {}
+
+
+def oracle_solution(p, rtol=1e-8):
+    key = p.name
+    if key not in _oracle:
+        o = OracleSolver(p.with_options(local_precision=0))
+        x, it, rel = o.solve(p.f, rtol=rtol)[:3]
+        _oracle[key] = (x, it)
+    return _oracle[key]
+
+
+def rel_err(u, x):
+    nx = np.linalg.norm(x)
+    return np.linalg.norm(u - x) / nx if nx > 0 else np.linalg.norm(u)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_batch_matches_oracle(precision):
+    from paper_1703_06323_amd import BatchSolver
+    probs = small_batch(precision)
+    print(f"[gpu] batch of {len(probs)} precision={precision}", flush=True)
+    b = BatchSolver(probs)
+    b.factor()
+    us, its, rels = b.solve([fvec(p) for p in probs], rtol=1e-8)
+    tol = 1e-10 if precision == 0 else 1e-6
+    for k, p in enumerate(probs):
+        x, it = oracle_solution(p)
+        assert b.problem_info(k)["n_dof"] == x.size, p.name
+        err = rel_err(us[k].cpu().numpy(), x)
+        print(f"  {p.name}: it {its[k]} (oracle {it}) rel {rels[k]:.2e} err {err:.2e}")
+        assert err <= tol, p.name
+        if precision == 0:
+            assert its[k] == it, p.name
+        else:
+            assert abs(int(its[k]) - it) <= 1, p.name
+    assert its[-1] == 0 and rels[-1] == 0.0   # zero right-hand side
+    if precision == 0:
+        assert its[-2] == 1                   # one subdomain: the FP64 Dirichlet solve is exact
+
+
+def test_batch_equals_single_problem_path():
+    from paper_1703_06323_amd import BatchSolver, Solver
+    probs = small_batch(0)[:5]
+    b = BatchSolver(probs)
+    b.factor()
+    us, its, _ = b.solve([fvec(p) for p in probs], rtol=1e-8)
+    for k, p in enumerate(probs):
+        s = Solver(p)
+        s.factor()
+        u, it, _ = s.solve(fvec(p), rtol=1e-8)
+        assert it == its[k]
+        assert rel_err(us[k].cpu().numpy(), u.cpu().numpy()) <= 1e-12
+
+
+def test_batch_graph_replays_match_eager(monkeypatch):
+    from paper_1703_06323_amd import BatchSolver
+    probs = small_batch(1)[:6]
+    b = BatchSolver(probs)
+    b.factor()
+    fs = [fvec(p) for p in probs]
+    monkeypatch.setenv("CUTBDDC_GRAPH", "0")
+    ref, it_ref, _ = b.solve(fs, rtol=1e-8)
+    ref = [u.clone() for u in ref]
+    monkeypatch.setenv("CUTBDDC_GRAPH", "1")
+    for rep in range(3):
+        # eager work and synchronisation between the replays
+        scaled = [2.0 * f for f in fs]
+        us, its, _ = b.solve(scaled if rep == 1 else fs, rtol=1e-8)
+        torch.cuda.synchronize()
+        assert np.array_equal(its, it_ref)
+        for k in range(len(probs)):
+            want = 2.0 * ref[k] if rep == 1 else ref[k]
+            assert torch.allclose(us[k], want, rtol=1e-12, atol=0.0), (rep, k)
+
+
+def test_batch_iteration_limit_and_options():
+    from paper_1703_06323_amd import BatchSolver, CBError
+    probs = small_batch(0)[:3]
+    b = BatchSolver(probs)
+    b.factor()
+    us, its, rels = b.solve([fvec(p) for p in probs], rtol=1e-12, max_iter=2, allow_no_convergence=True)
+    assert np.all(its <= 2) and np.all(rels > 1e-12)
+    with pytest.raises(CBError) as e:
+        b.solve([fvec(p) for p in probs], rtol=1e-12, max_iter=2)
+    assert e.value.code == -4
+    mixed = [probs[0], probs[1].with_options(weighting=0)]
+    with pytest.raises(CBError) as e:
+        BatchSolver(mixed)
+    assert e.value.code == -1
+
+
+def test_batch_256_against_oracle():
+    path = os.path.join(GOLDEN, "batch_256.json")
+    if not os.path.exists(path):
+        pytest.skip("batch golden values not generated")
+    from paper_1703_06323_amd import BatchSolver
+    meta = json.load(open(path))["problems"]
+    smp = np.load(os.path.join(GOLDEN, "batch_256_sample.npz"))
+    probs = W.batch_256()
+    print("[gpu] batch_256 setup", flush=True)
+    b = BatchSolver(probs)
+    print("[gpu] batch_256 factor", flush=True)
+    b.factor()
+    print("[gpu] batch_256 solve", flush=True)
+    us, its, rels = b.solve([torch.tensor(p.f, device="cuda") for p in probs], rtol=1e-8)
+    worst = 0.0
+    for k, p in enumerate(probs):
+        m = meta[k]
+        inf = b.problem_info(k)
+        assert inf["n_dof"] == m["n_dof"] and inf["n_coarse"] == m["n_coarse"], k
+        assert abs(int(its[k]) - m["iterations"]) <= 1, k
+        assert rels[k] < 1e-8
+        u = us[k].cpu().numpy()
+        idx = smp["idx"][k]
+        x = smp["u"][k]
+        e = np.linalg.norm(u[idx] - x) / np.linalg.norm(x)
+        en = abs(np.linalg.norm(u) - smp["norm"][k]) / smp["norm"][k]
+        worst = max(worst, e, en)
+    print(f"worst FP32-local sample / norm error over 256 problems: {worst:.2e}")
+    assert worst <= 1e-6
