@@ -37,8 +37,12 @@ void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, i
                            double* diagA_G, double* Dscale);
 void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
                     const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw);
-void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y);
-void launch_build_constraints(hipStream_t st, const SubDev& sd, int ns, double* Cm);
+// Rows [r0, r0 + nrows) of Y = A_omega X (FP64, nt x NCp blocks).
+void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y,
+                        int r0, int nrows);
+// G = K_S^{-1} C^T and S_c = C G with C the object-mean constraints.
+void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* G);
+void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* G, double* Sc);
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info);
 // Coarse matrix of every problem p as its own ldc_p x ldc_p block at
 // Ac + ac_off_p (identity on the padding rows); prow_off[p] = first padded

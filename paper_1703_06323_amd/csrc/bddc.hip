@@ -161,75 +161,150 @@ __global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_p
   }
 }
 
-// Kernel 3b: Y = A_omega X for nt x NCp blocks X, Y (unscaled FP64 local
-// Neumann matrix applied cell by cell).  One thread per (row, column): the
-// threads of a row walk the same cells, so the cell data are broadcast and
-// X is read along its rows.
+// Kernel 3b: Y[r][t] = sum_c A_omega[r][c] X[c][t] for the local rows r in
+// [r0, r0 + nrows) (unscaled FP64 local Neumann matrix; X, Y are nt x NCp
+// per subdomain).  One block per (LA_ROWS-row chunk, subdomain): one thread
+// per row first sums the row's stencil (at most 27 neighbours, over the
+// active cells of the subdomain around the row's node) into LDS; then all
+// threads stream X along its rows.
+constexpr int LA_ROWS = 64;
 __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, const double* __restrict__ X,
-                                                          double* __restrict__ Y) {
+                                                          double* __restrict__ Y, int r0, int nrows) {
+  __shared__ double sval[LA_ROWS][27];
+  __shared__ int scol[LA_ROWS][27];
   const int w = blockIdx.y;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nt * NCp) return;
-  const int r = e / NCp, t = e % NCp;
-  const int nI = sd.nI[w], nG = sd.nG[w];
-  const ProbDev pr = g.prob[sd.sub_prob[w]];
-  const int s = g.s, m = pr.m, N = pr.N;
-  const int blk = sd.sub_blk[w];
-  const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
-  const int64_t N1 = N + 1;
-  const int s1 = s + 1;
-  const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
-  const int32_t* cellinfo = g.cellinfo + pr.cell_off;
-  const double* kappa = g.kappa + pr.cell_off;
-  const double* x = X + (int64_t)w * nt * NCp;
-  int64_t n = -1;
-  if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] - pr.node_off : -1;
-  else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] - pr.node_off : -1;
-  double acc = 0.0;
-  if (n >= 0) {
-    const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
-    const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
-    for (int u = 0; u < 8; ++u) {
-      const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
-      if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-      const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-      const int32_t info = cellinfo[c];
-      if (info == CELL_INACTIVE) continue;
-      const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-      const double sc = kappa[c] * pr.h;
-      for (int b = 0; b < 8; ++b) {
-        const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
-        const int col = loc[bx + s1 * (by + s1 * bz)];
-        if (col < 0) continue;
-        const double kab = sc * (info == CELL_UNCUT ? c_Kref_b[a * 8 + b]
-                                                    : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)]);
-        acc += kab * x[(int64_t)col * NCp + t];
+  const int rb = r0 + blockIdx.x * LA_ROWS;
+  const int tid = threadIdx.x;
+  if (tid < LA_ROWS) {
+    for (int k = 0; k < 27; ++k) {
+      sval[tid][k] = 0.0;
+      scol[tid][k] = -1;
+    }
+    const int r = rb + tid;
+    const int nI = sd.nI[w], nG = sd.nG[w];
+    int64_t n = -1;
+    if (r < r0 + nrows) {
+      if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+      else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
+    }
+    if (n >= 0) {
+      const ProbDev pr = g.prob[sd.sub_prob[w]];
+      const int s = g.s, m = pr.m, N = pr.N, s1 = s + 1, N1 = pr.N + 1;
+      const int blk = sd.sub_blk[w];
+      const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
+      const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
+      const int32_t* cellinfo = g.cellinfo + pr.cell_off;
+      const double* kappa = g.kappa + pr.cell_off;
+      const int l = (int)(n - pr.node_off);
+      const int I = l % N1, J = (l / N1) % N1, Kk = l / (N1 * N1);
+      const int lx = I - Bx * s, ly = J - By * s, lz = Kk - Bz * s;
+      for (int u = 0; u < 8; ++u) {
+        const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+        if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+        const int64_t c = (int64_t)(Bx * s + cx) + (int64_t)N * ((By * s + cy) + (int64_t)N * (Bz * s + cz));
+        const int32_t info = cellinfo[c];
+        if (info == CELL_INACTIVE) continue;
+        const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+        const double sc = kappa[c] * pr.h;
+        for (int b = 0; b < 8; ++b) {
+          const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
+          const int col = loc[bx + s1 * (by + s1 * bz)];
+          if (col < 0) continue;
+          const int slot = (bx - lx + 1) + 3 * (by - ly + 1) + 9 * (bz - lz + 1);
+          const double kab = info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
+          sval[tid][slot] += sc * kab;
+          scol[tid][slot] = col;
+        }
       }
     }
   }
-  Y[(int64_t)w * nt * NCp + e] = acc;
+  __syncthreads();
+  const int R = min(LA_ROWS, r0 + nrows - rb);
+  const double* x = X + (int64_t)w * nt * NCp;
+  double* y = Y + (int64_t)w * nt * NCp;
+  for (int e = tid; e < R * NCp; e += 256) {
+    const int rr = e / NCp, t = e - rr * NCp;
+    double acc = 0.0;
+    for (int k = 0; k < 27; ++k) {
+      const int col = scol[rr][k];
+      if (col >= 0) acc += sval[rr][k] * x[(int64_t)col * NCp + t];
+    }
+    y[(int64_t)(rb + rr) * NCp + t] = acc;
+  }
 }
 
-// Kernel 3d: dense constraint matrix C_omega (NCp x NGp): row t holds
-// 1/|lambda_t| on the interface rows of object t (eq. coarse-dofs, equal
-// weight mean), zero elsewhere.
-__global__ __launch_bounds__(256) void build_constraints_kernel(SubDev sd, double* __restrict__ Cm) {
-  extern __shared__ double cnt[];
-  const int w = blockIdx.x;
+// Interface slots of each local object of subdomain w, grouped by object:
+// members of object t at mem[ptr[t] .. ptr[t+1]), ascending (eq.
+// coarse-dofs: the coarse DOF of object t is the mean over these slots).
+__device__ inline void object_members(const SubDev& sd, int w, int* ptr, int* mem) {
   const int NGp = sd.NGp, NCp = sd.NCp;
-  const int nG = sd.nG[w];
+  const int nG = sd.nG[w], nC = sd.nC[w];
   const int* obj = sd.G_obj + (int64_t)w * NGp;
-  for (int t = threadIdx.x; t < NCp; t += 256) {
-    double c = 0.0;
-    for (int j = 0; j < nG; ++j) c += (obj[j] == t) ? 1.0 : 0.0;
-    cnt[t] = c;
+  for (int t = threadIdx.x; t < NCp; t += blockDim.x) {
+    int c = 0;
+    if (t < nC)
+      for (int j = 0; j < nG; ++j) c += obj[j] == t ? 1 : 0;
+    ptr[t + 1] = c;
   }
   __syncthreads();
-  double* C = Cm + (int64_t)w * NCp * NGp;
-  for (int e = threadIdx.x; e < NCp * NGp; e += 256) {
-    const int t = e / NGp, j = e % NGp;
-    C[e] = (j < nG && obj[j] == t) ? 1.0 / cnt[t] : 0.0;
+  if (threadIdx.x == 0) {
+    ptr[0] = 0;
+    for (int t = 0; t < NCp; ++t) ptr[t + 1] += ptr[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nC; t += blockDim.x) {
+    int q = ptr[t];
+    for (int j = 0; j < nG; ++j)
+      if (obj[j] == t) mem[q++] = j;
+  }
+  __syncthreads();
+}
+
+// Kernel 3c: G = K_S^{-1} C^T without forming C: column t of G is the mean
+// of the columns of K_S^{-1} over the slots of object t.  One block per
+// (CC_ROWS-row chunk, subdomain); G is NGp x NCp, K_S^{-1} NGp x NGp.
+constexpr int CC_ROWS = 64;
+__global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const double* __restrict__ KS,
+                                                              double* __restrict__ G) {
+  extern __shared__ int smem_i[];
+  const int w = blockIdx.y;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  int* ptr = smem_i;
+  int* mem = smem_i + NCp + 1;
+  object_members(sd, w, ptr, mem);
+  const double* ks = KS + (int64_t)w * NGp * NGp;
+  double* gw = G + (int64_t)w * NGp * NCp;
+  const int rb = blockIdx.x * CC_ROWS;
+  const int R = min(CC_ROWS, NGp - rb);
+  for (int e = threadIdx.x; e < R * NCp; e += 256) {
+    const int rr = e / NCp, t = e - rr * NCp;
+    const double* row = ks + (int64_t)(rb + rr) * NGp;
+    const int b = ptr[t], en = ptr[t + 1];
+    double acc = 0.0;
+    for (int q = b; q < en; ++q) acc += row[mem[q]];
+    gw[(int64_t)(rb + rr) * NCp + t] = en > b ? acc / (double)(en - b) : 0.0;
+  }
+}
+
+// Kernel 3d: S_c = C G: row t of S_c is the mean of the rows of G over the
+// slots of object t (NCp x NCp per subdomain).
+__global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const double* __restrict__ G,
+                                                              double* __restrict__ Sc) {
+  extern __shared__ int smem_i[];
+  const int w = blockIdx.x;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  int* ptr = smem_i;
+  int* mem = smem_i + NCp + 1;
+  object_members(sd, w, ptr, mem);
+  const double* gw = G + (int64_t)w * NGp * NCp;
+  double* sc = Sc + (int64_t)w * NCp * NCp;
+  for (int e = threadIdx.x; e < NCp * NCp; e += 256) {
+    const int t = e / NCp, u = e - t * NCp;
+    const int b = ptr[t], en = ptr[t + 1];
+    double acc = 0.0;
+    for (int q = b; q < en; ++q) acc += gw[(int64_t)mem[q] * NCp + u];
+    sc[e] = en > b ? acc / (double)(en - b) : 0.0;
   }
 }
 
@@ -472,14 +547,24 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
                      if_ptr, if_sub, if_slot, NGp, diagA_G, stiffness, Dw);
 }
 
-void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y) {
-  const int nt = sd.NIp + sd.NGp;
-  dim3 grid((nt * sd.NCp + 255) / 256, ns);
-  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, g, X, Y);
+void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y,
+                        int r0, int nrows) {
+  if (nrows <= 0 || ns <= 0) return;
+  dim3 grid((nrows + LA_ROWS - 1) / LA_ROWS, ns);
+  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, g, X, Y, r0, nrows);
 }
 
-void launch_build_constraints(hipStream_t st, const SubDev& sd, int ns, double* Cm) {
-  hipLaunchKernelGGL(build_constraints_kernel, dim3(ns), dim3(256), sd.NCp * sizeof(double), st, sd, Cm);
+void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* G) {
+  if (ns <= 0) return;
+  dim3 grid((sd.NGp + CC_ROWS - 1) / CC_ROWS, ns);
+  hipLaunchKernelGGL(constraint_cols_kernel, grid, dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st, sd,
+                     KS, G);
+}
+
+void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* G, double* Sc) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL(constraint_rows_kernel, dim3(ns), dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st,
+                     sd, G, Sc);
 }
 
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info) {

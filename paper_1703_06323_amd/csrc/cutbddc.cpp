@@ -1067,10 +1067,9 @@ int factor_impl(cb_ctx* c) {
   const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
   const GridDev g = c->grid();
   const bool f32 = std::is_same<T, float>::value;
-  const int ntiles = nt / CHOL_BLOCK;
   const int nbig = std::max(NIp, NGp);
   const int64_t sK = (int64_t)nt * nt;
-  const int64_t sL = (int64_t)ntiles * CHOL_BLOCK * CHOL_BLOCK;
+  const int64_t sL = (int64_t)diag_blocks(nt, NIp) * DB * DB;
   const int64_t sY = (int64_t)nbig * nbig;
   const int64_t sT = (int64_t)TRI_SUPER * nbig;
   const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp, sF = (int64_t)nt * NCp;
@@ -1093,9 +1092,9 @@ int factor_impl(cb_ctx* c) {
   // work buffers for a chunk of subdomains
   const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
                          (size_t)sT * sizeof(T) + (f32 ? (size_t)sP * 8 + (size_t)sKS * 8 : 0) +
-                         (size_t)(2 * sG + sC + 2 * sF) * sizeof(double);
+                         (size_t)(sG + sC + 2 * sF) * sizeof(double);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
-  DevBuf K, Linv, Y, PS, Tmp, Pd64, KSw, G, Cm, Sc, PhiF, V;
+  DevBuf K, Linv, Y, PS, Tmp, Pd64, KSw, G, Sc, PhiF, V;
   CHK(dalloc(K, (size_t)chunk * sK * sizeof(T)));
   CHK(dalloc(Linv, (size_t)chunk * sL * sizeof(T)));
   CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
@@ -1106,7 +1105,6 @@ int factor_impl(cb_ctx* c) {
     CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
   }
   CHK(dalloc(G, (size_t)chunk * sG * sizeof(double)));
-  CHK(dalloc(Cm, (size_t)chunk * sG * sizeof(double)));
   CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
   CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
   CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
@@ -1122,11 +1120,12 @@ int factor_impl(cb_ctx* c) {
                              c->Ds.as<double>() + (int64_t)w0 * nt);
     HIPCHK(hipGetLastError());
     timed(c, "local_cholesky",
-          [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0); });
+          [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0); });
     HIPCHK(hipGetLastError());
     // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(), sT);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(),
+                     sT);
       gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
@@ -1140,7 +1139,8 @@ int factor_impl(cb_ctx* c) {
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(), sT);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(),
+                     sT);
       gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
@@ -1148,34 +1148,34 @@ int factor_impl(cb_ctx* c) {
     HIPCHK(hipGetLastError());
     // coarse basis on the interface: G = K_S^{-1} C^T, S_c = C G,
     // Phi_G = G S_c^{-1} (C Phi_G = I, energy-minimising for S_A)
-    launch_build_constraints(st, sd, nc, Cm.as<double>());
-    gemm<double>(st, 0, 1, NGp, NCp, NGp, 1.0, KS, NGp, sKS, Cm.as<double>(), NGp, sG, 0.0, G.as<double>(), NCp, sG,
-                 nc, 0);
-    gemm<double>(st, 0, 0, NCp, NCp, NGp, 1.0, Cm.as<double>(), NGp, sG, G.as<double>(), NCp, sG, 0.0,
-                 Sc.as<double>(), NCp, sC, nc, 0);
+    launch_constraint_cols(st, sd, nc, KS, G.as<double>());
+    launch_constraint_rows(st, sd, nc, G.as<double>(), Sc.as<double>());
     launch_small_spd_inverse(st, sd, nc, Sc.as<double>(), c->info_d.as<int>() + ns);
     gemm<double>(st, 0, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NCp, sG, Sc.as<double>(), NCp, sC, 0.0, Phiw, NCp,
                  sG, nc, 0);
     HIPCHK(hipGetLastError());
-    // full coarse basis Phi = [-A_II^{-1} A_IG Phi_G; Phi_G] and the local
-    // coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi
+    // full coarse basis Phi = [Phi_I; Phi_G] with Phi_I = -A_II^{-1} A_IG Phi_G,
+    // and the local coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi.
+    // A_omega Phi vanishes on the interior rows, so the Gram matrix is
+    // Phi_G^T (A_omega Phi)_G; only the needed rows of A_omega X are formed.
     launch_fill(st, (int64_t)nc * sF, 0.0, PhiF.as<double>());
     HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), Phiw,
                             (size_t)sG * sizeof(double), (size_t)sG * sizeof(double), nc, hipMemcpyDeviceToDevice,
                             st));
-    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>());
+    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>(), 0, NIp);
     gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, sP, V.as<double>(), NCp, sF, 0.0, PhiF.as<double>(), NCp,
                  sF, nc, 0);
-    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>());
-    gemm<double>(st, 1, 0, NCp, NCp, nt, 1.0, PhiF.as<double>(), NCp, sF, V.as<double>(), NCp, sF, 0.0,
-                 AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC, nc, 0);
+    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>(), NIp, NGp);
+    gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
+                 V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
+                 nc, 0);
     // Kt = K_S^{-1} - Phi G^T
     gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NCp, sG, 1.0, KS, NGp, sKS, nc, 0);
     if (f32)
       convert_to_float(st, (int64_t)nc * sKS, KS, reinterpret_cast<float*>(c->Kt.as<T>() + (int64_t)w0 * sKS));
     HIPCHK(hipGetLastError());
   }
-  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Cm, &Sc, &PhiF, &V}) b->release();
+  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
   launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
                  NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
   HIPCHK(hipGetLastError());
@@ -1196,15 +1196,16 @@ int factor_impl(cb_ctx* c) {
       CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
       launch_copy(st, c->ac_total, Ac.as<double>(), c->AcKeep.as<double>());
     }
-    size_t maxL = 0, maxLL = 0, maxB = 0;
+    size_t maxL = 0, maxLL = 0, maxB = 0, maxD = 0;
     for (const CoarseGroup& gr : c->groups) {
       maxL = std::max(maxL, (size_t)gr.ldc);
       maxLL = std::max(maxLL, (size_t)gr.ldc * gr.ldc * gr.probs.size());
       maxB = std::max(maxB, gr.probs.size() * (size_t)gr.ldc);
+      maxD = std::max(maxD, gr.probs.size() * (size_t)diag_blocks(gr.ldc, 0) * DB * DB);
     }
     DevBuf Lc, Yc, PSc, Tc, ones;
     const std::vector<double> onesv(maxL, 1.0);
-    CHK(dalloc(Lc, maxB * CHOL_BLOCK * sizeof(double)));
+    CHK(dalloc(Lc, maxD * sizeof(double)));
     CHK(dalloc(Yc, maxLL * sizeof(double)));
     CHK(dalloc(PSc, maxLL * sizeof(double)));
     CHK(dalloc(Tc, maxB * TRI_SUPER * sizeof(double)));
@@ -1213,11 +1214,11 @@ int factor_impl(cb_ctx* c) {
     int slot = 0;
     for (const CoarseGroup& gr : c->groups) {
       const int L = gr.ldc, nb = (int)gr.probs.size();
-      const int64_t sA = (int64_t)L * L, sLc = (int64_t)(L / CHOL_BLOCK) * CHOL_BLOCK * CHOL_BLOCK;
+      const int64_t sA = (int64_t)L * L, sLc = (int64_t)diag_blocks(L, 0) * DB * DB;
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
       double* A = Ac.as<double>() + gr.ac_off;
-      cholesky<double>(st, A, L, sA, L, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
-      tri_inverse<double>(st, A, L, sA, 0, L, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA, Tc.as<double>(),
+      cholesky<double>(st, A, L, sA, L, 0, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
+      tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA, Tc.as<double>(),
                           (int64_t)TRI_SUPER * L);
       gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
                    L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
@@ -1312,18 +1313,17 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
     std::vector<T> ht(h.begin(), h.end());
     DevBuf dA, dL, dY, dP, dOut, dOnes, dInfo;
     CHK(upload(dA, ht, nullptr));
-    const int nt = np / CHOL_BLOCK;
-    CHK(dalloc(dL, (size_t)batch * nt * CHOL_BLOCK * CHOL_BLOCK * sizeof(T)));
+    const int64_t sL = (int64_t)diag_blocks(np, 0) * DB * DB;
+    CHK(dalloc(dL, (size_t)batch * sL * sizeof(T)));
     CHK(dalloc(dY, (size_t)batch * nn * sizeof(T)));
     CHK(dalloc(dP, (size_t)batch * nn * sizeof(T)));
     CHK(dalloc(dOut, (size_t)batch * nn * sizeof(double)));
     CHK(upload(dOnes, std::vector<double>((size_t)batch * np, 1.0), nullptr));
     CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
-    const int64_t sL = (int64_t)nt * CHOL_BLOCK * CHOL_BLOCK;
-    cholesky<T>(nullptr, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>());
+    cholesky<T>(nullptr, dA.as<T>(), np, nn, np, 0, batch, dL.as<T>(), sL, dInfo.as<int>());
     DevBuf dT;
     CHK(dalloc(dT, (size_t)batch * TRI_SUPER * np * sizeof(T)));
-    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, batch, dL.as<T>(), sL, dY.as<T>(), np, nn, dT.as<T>(),
+    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, 0, batch, dL.as<T>(), sL, dY.as<T>(), np, nn, dT.as<T>(),
                    (int64_t)TRI_SUPER * np);
     gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
             GEMM_LOWER | GEMM_KFROM_DIAG);

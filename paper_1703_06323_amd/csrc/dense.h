@@ -29,18 +29,38 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
 template <typename T>
 int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode);
 
-// In-place lower Cholesky of n x n matrices (n a multiple of CHOL_BLOCK).
-// Linv receives the inverses of the diagonal tiles: sL >= (n/32)*32*32.
+// Diagonal blocks of the factorisations have order DB (the last block of a
+// range may be smaller).  Blocks start at 0 and, when a split point is
+// given, again at the split (so that the two diagonal ranges [0, split) and
+// [split, n) are unions of whole blocks).
+constexpr int DB = 128;
+inline int diag_blocks(int n, int split) {
+  if (split <= 0 || split >= n) return (n + DB - 1) / DB;
+  return (split + DB - 1) / DB + (n - split + DB - 1) / DB;
+}
+// Index of the diagonal block that starts at position p.
+inline int diag_block_index(int p, int split) {
+  if (split <= 0 || p < split) return p / DB;
+  return (split + DB - 1) / DB + (p - split) / DB;
+}
+
+// In-place lower Cholesky of n x n matrices (n a multiple of CHOL_BLOCK;
+// split 0 or a multiple of CHOL_BLOCK).  Linv receives, per matrix, the
+// inverse of every diagonal block as a DB x DB row-major block (zero above
+// the diagonal): sL >= diag_blocks(n, split) * DB * DB.  info[b] is set to
+// (first row with a non-positive pivot) + 1 for matrix b; the pivot is then
+// replaced by 1 so that the factorisation finishes without NaNs.
 template <typename T>
-void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv, int64_t sL,
+void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
               int* info);
 
-// Y = inverse of the lower-triangular diagonal block [off, off+nb) of L,
-// using the diagonal-tile inverses written by cholesky().  tmp: workspace of
-// TRI_SUPER * nb elements per matrix (stride sT).
-constexpr int TRI_SUPER = 128;
+// Y = inverse of the lower-triangular diagonal range [off, off+nb) of L
+// (off and off+nb block starts of the same split), from the diagonal-block
+// inverses written by cholesky().  tmp: workspace of TRI_SUPER * nb elements
+// per matrix (stride sT).
+constexpr int TRI_SUPER = DB;
 template <typename T>
-void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
+void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
                  const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT);
 
 // out = D sym(lower(in)) D, full storage.

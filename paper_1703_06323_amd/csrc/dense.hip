@@ -1,9 +1,10 @@
 // Batched dense linear algebra on CDNA4 matrix cores (MFMA), FP64 and FP32.
 //
 // Used for the subdomain Dirichlet and constrained-Neumann factorisations and
-// the coarse matrix: blocked right-looking Cholesky with 32-wide panels, a
-// triangular inverse by block forward substitution, and the product
-// Y^T Y that turns the inverse factor into the inverse.  Every kernel takes a
+// the coarse matrix: blocked right-looking Cholesky over 128-wide diagonal
+// blocks (each factored and inverted in LDS), a triangular inverse by block
+// forward substitution, and the product Y^T Y that turns the inverse factor
+// into the inverse.  Every kernel takes a
 // batch of equally sized, row-major matrices (stride between matrices) and
 // runs one workgroup per (tile, matrix), so the same code factors one large
 // coarse matrix or thousands of subdomain matrices.
@@ -24,11 +25,6 @@
 namespace cutbddc {
 namespace {
 
-constexpr int TM = 64;    // output tile rows
-constexpr int TN = 64;    // output tile cols
-constexpr int KT = 16;    // K per LDS stage
-constexpr int BLK = 32;   // Cholesky panel width
-constexpr int SUPER = 128; // super-panel width (K of the trailing updates)
 
 template <typename T> struct Acc;
 // Operand layouts of the 16x16x4 MFMAs (both types): lane l supplies
@@ -50,12 +46,28 @@ template <> struct Acc<float> {
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+template <typename T> struct Vec16;   // 16-byte vector of T
+template <> struct Vec16<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
+};
+template <> struct Vec16<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+
 // C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, BM x BN output
 // tile per 256-thread workgroup: four waves in a 2 x 2 arrangement, each
-// owning (BM/32) x (BN/32) MFMA 16x16 blocks; the K loop stages BM x 16 and
-// 16 x BN operand tiles in LDS.
+// owning (BM/32) x (BN/32) MFMA 16x16 blocks.
 //   TA = 0: A(i,k) = A[i*lda + k];  TA = 1: A(i,k) = A[k*lda + i]
 //   TB = 0: B(k,j) = B[k*ldb + j];  TB = 1: B(k,j) = B[j*ldb + k]
+// The K loop runs in stages of KT (128 bytes of k per row); both operand
+// tiles sit in LDS with k contiguous (As[i][k], Bs[j][k]), double buffered:
+// the global loads of stage s+1 are in flight while stage s is multiplied,
+// and one barrier separates the stages.  Within a 16-wide k block the four
+// MFMAs take k = 4*(lane/16) + q (q = 0..3) instead of consecutive k, so a
+// lane fetches its 4 values of A and of B with one 16-byte LDS read each.
+// vec: the operands allow 16-byte global loads (leading dimensions, batch
+// strides and base addresses are multiples of 16 bytes); edge vectors fall
+// back to element loads either way.
 // C is written only after the whole K loop, so a call may overwrite its own
 // B operand when each output tile reads only its own columns of B (and the
 // same for A and rows); the dispatcher keeps such calls on 64-wide tiles.
@@ -63,11 +75,18 @@ template <typename T, int TA, int TB, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
-                                                   int64_t sC, int mode) {
+                                                   int64_t sC, int mode, int vec) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
+  constexpr int KT = 128 / sizeof(T);           // k per stage
+  constexpr int LDK = KT + VW;                  // LDS row length (padded)
   constexpr int WM = BM / 2, WN = BN / 2;       // per-wave outputs
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
-  __shared__ T As[BM][KT + 1];
-  __shared__ T Bs[KT][BN + 1];
+  constexpr int AV = BM * KT / VW / 256;        // vectors per thread per stage
+  constexpr int BV = BN * KT / VW / 256;
+  static_assert(AV >= 1 && BV >= 1, "tile too small");
+  __shared__ __align__(16) T As[2][BM][LDK];
+  __shared__ __align__(16) T Bs[2][BN][LDK];
   const int row0 = blockIdx.y * BM;
   const int col0 = blockIdx.x * BN;
   const int64_t bz = blockIdx.z;
@@ -81,42 +100,152 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int wr = wv >> 1, wc = wv & 1;
+
+  V ra[AV], rb[BV];
+  // tile coordinates (row or column index, k) of the first element of
+  // vector q of this thread
+  auto a_coord = [&](int q, int& i, int& k) {
+    const int v = tid + 256 * q;
+    if (TA == 0) {
+      i = v / (KT / VW);
+      k = (v % (KT / VW)) * VW;
+    } else {
+      k = v / (BM / VW);
+      i = (v % (BM / VW)) * VW;
+    }
+  };
+  auto b_coord = [&](int q, int& j, int& k) {
+    const int v = tid + 256 * q;
+    if (TB == 1) {
+      j = v / (KT / VW);
+      k = (v % (KT / VW)) * VW;
+    } else {
+      k = v / (BN / VW);
+      j = (v % (BN / VW)) * VW;
+    }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < AV; ++q) {
+      int i, k;
+      a_coord(q, i, k);
+      const int gi = row0 + i, gk = k0 + k;
+      V x;
+      if (TA == 0) {
+        if (vec && gi < M && gk + VW <= kend) {
+          x = *reinterpret_cast<const V*>(A + (int64_t)gi * lda + gk);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VW; ++c) x[c] = (gi < M && gk + c < kend) ? A[(int64_t)gi * lda + gk + c] : T(0);
+        }
+      } else {
+        if (vec && gk < kend && gi + VW <= M) {
+          x = *reinterpret_cast<const V*>(A + (int64_t)gk * lda + gi);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VW; ++c) x[c] = (gi + c < M && gk < kend) ? A[(int64_t)gk * lda + gi + c] : T(0);
+        }
+      }
+      ra[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < BV; ++q) {
+      int j, k;
+      b_coord(q, j, k);
+      const int gj = col0 + j, gk = k0 + k;
+      V x;
+      if (TB == 1) {
+        if (vec && gj < N && gk + VW <= kend) {
+          x = *reinterpret_cast<const V*>(B + (int64_t)gj * ldb + gk);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VW; ++c) x[c] = (gj < N && gk + c < kend) ? B[(int64_t)gj * ldb + gk + c] : T(0);
+        }
+      } else {
+        if (vec && gk < kend && gj + VW <= N) {
+          x = *reinterpret_cast<const V*>(B + (int64_t)gk * ldb + gj);
+        } else {
+#pragma unroll
+          for (int c = 0; c < VW; ++c) x[c] = (gj + c < N && gk < kend) ? B[(int64_t)gk * ldb + gj + c] : T(0);
+        }
+      }
+      rb[q] = x;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < AV; ++q) {
+      int i, k;
+      a_coord(q, i, k);
+      if (TA == 0) {
+        *reinterpret_cast<V*>(&As[buf][i][k]) = ra[q];
+      } else {
+#pragma unroll
+        for (int c = 0; c < VW; ++c) As[buf][i + c][k] = ra[q][c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BV; ++q) {
+      int j, k;
+      b_coord(q, j, k);
+      if (TB == 1) {
+        *reinterpret_cast<V*>(&Bs[buf][j][k]) = rb[q];
+      } else {
+#pragma unroll
+        for (int c = 0; c < VW; ++c) Bs[buf][j + c][k] = rb[q][c];
+      }
+    }
+  };
+
   typename Acc<T>::type acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+
+  const int ks = 4 * (lane >> 4);
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
-    for (int e = tid; e < BM * KT; e += 256) {
-      int i, k;
-      if (TA == 0) { i = e / KT; k = e % KT; } else { k = e / BM; i = e % BM; }
-      const int gi = row0 + i, gk = k0 + k;
-      T v = 0;
-      if (gi < M && gk < kend) v = TA == 0 ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi];
-      As[i][k] = v;
-    }
-    for (int e = tid; e < KT * BN; e += 256) {
-      int k, j;
-      if (TB == 0) { k = e / BN; j = e % BN; } else { j = e / KT; k = e % KT; }
-      const int gj = col0 + j, gk = k0 + k;
-      T v = 0;
-      if (gj < N && gk < kend) v = TB == 0 ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk];
-      Bs[k][j] = v;
-    }
-    __syncthreads();
+    const bool more = k0 + KT < kend;
+    if (more) load(k0 + KT);
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 4) {
-      T bv[FN];
-#pragma unroll
-      for (int ni = 0; ni < FN; ++ni) bv[ni] = Bs[kk + (lane >> 4)][wc * WN + ni * 16 + (lane & 15)];
+    for (int kb = 0; kb < KT; kb += 16) {
+      T av[FM][4], bv[FN][4];
 #pragma unroll
       for (int mi = 0; mi < FM; ++mi) {
-        const T av = As[wr * WM + mi * 16 + (lane & 15)][kk + (lane >> 4)];
+        const T* src = &As[buf][wr * WM + mi * 16 + (lane & 15)][kb + ks];
 #pragma unroll
-        for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = Acc<T>::mfma(av, bv[ni], acc[mi][ni]);
+        for (int h = 0; h < 4; h += VW) {
+          const V x = *reinterpret_cast<const V*>(src + h);
+#pragma unroll
+          for (int c = 0; c < VW; ++c) av[mi][h + c] = x[c];
+        }
       }
+#pragma unroll
+      for (int ni = 0; ni < FN; ++ni) {
+        const T* src = &Bs[buf][wc * WN + ni * 16 + (lane & 15)][kb + ks];
+#pragma unroll
+        for (int h = 0; h < 4; h += VW) {
+          const V x = *reinterpret_cast<const V*>(src + h);
+#pragma unroll
+          for (int c = 0; c < VW; ++c) bv[ni][h + c] = x[c];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = Acc<T>::mfma(av[mi][q], bv[ni][q], acc[mi][ni]);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int mi = 0; mi < FM; ++mi)
@@ -134,105 +263,182 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
       }
 }
 
-// Cholesky of the BLK x BLK diagonal tile at (k0, k0) of each matrix by one
-// wave.  Thread t owns half (t & 1) of row (t >> 1) in registers (16
-// values; the step loop is unrolled so every register index is static).  At
-// step j the pivot and then the new column j go through small LDS vectors,
-// so each step costs two barriers and a burst of independent LDS reads.
-// L^{-1} follows by forward elimination on [L | I] with the same layout.
-// Writes L (lower, upper part of the tile zeroed) and L^{-1} into
-// Linv[bz][tile][BLK*BLK].  A non-positive or non-finite pivot sets
-// info[bz] (first failing global row + 1) and is replaced by 1 so that the
-// factorisation continues without NaNs.
+// Factors the b x b diagonal block (b <= DB) at (k0, k0) of every matrix and
+// inverts the factor, with 256 threads.  The block is split into 8 x 8
+// tiles; each of the 136 lower tiles lives in the registers of one thread.
+// Right-looking Cholesky, one column j per step: the owner of the diagonal
+// tile takes the pivot, the owners of tile column j/8 scale column j and
+// publish it in LDS, and every thread updates its tile (64 independent
+// FMAs).  The step loop is unrolled by 8 so that every register index is
+// static.  Rows and columns beyond b are identity.  L is then kept in LDS and
+// L^{-1} is formed in the same registers by forward elimination on
+// L X = I (row j of X scaled and published, rows below updated).  Writes L
+// back (upper part of the block zeroed) and L^{-1} (zero above the
+// diagonal) to the DB x DB block `blk` of Linv[bz].  A non-positive or
+// non-finite pivot sets info[bz] (first failing global row + 1) and is
+// replaced by 1.
 template <typename T>
-__global__ __launch_bounds__(64) void potrf_tile_kernel(T* A, int64_t lda, int64_t sA, int k0,
-                                                        T* Linv, int64_t sL, int* info) {
-  constexpr int H = BLK / 2;
-  __shared__ T pv[BLK];
-  __shared__ T colj[BLK];
-  __shared__ T Lt[BLK][BLK + 1];
+__global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int64_t sA, int k0, int b, T* Linv,
+                                                          int64_t sL, int blk, int* info) {
+  constexpr int TS = 8, NT = DB / TS, NLT = NT * (NT + 1) / 2;
+  __shared__ T S[DB][DB + 1];
+  __shared__ T vec[DB];
+  __shared__ T pinv;
+  __shared__ int bad;
   const int64_t bz = blockIdx.x;
   T* a = A + bz * sA + (int64_t)k0 * lda + k0;
   const int t = threadIdx.x;
-  const int i = t >> 1, c0 = (t & 1) * H;
-  T r[H];
-#pragma unroll
-  for (int q = 0; q < H; ++q) r[q] = a[(int64_t)i * lda + c0 + q];
-  int bad = 0;
-#pragma unroll
-  for (int j = 0; j < BLK; ++j) {
-    const bool mine = (j >= c0 && j < c0 + H);   // this thread's half holds column j
-    if (i == j && mine) {
-      T d = r[j - c0];
-      if (!(d > T(0)) || !(d < T(3.0e38))) d = T(-1);
-      pv[j] = d;
+  // lower tile (I, C), I >= C, of this thread: t = I (I + 1) / 2 + C
+  int I = -1, C = -1;
+  if (t < NLT) {
+    int q = t, r = 0;
+    while (q > r) {
+      q -= r + 1;
+      ++r;
     }
-    __syncthreads();
-    T d = pv[j];
-    if (d < T(0)) {
-      if (!bad) bad = k0 + j + 1;
-      d = T(1);
-    }
-    const T piv = sqrt(d);
-    if (mine) {
-      if (i == j) r[j - c0] = piv;
-      if (i > j) r[j - c0] = r[j - c0] / piv;
-      if (i >= j) colj[i] = r[j - c0];
-    }
-    __syncthreads();
-    if (i > j) {
-      const T lij = colj[i];
-#pragma unroll
-      for (int q = 0; q < H; ++q) {
-        const int l = c0 + q;
-        if (l > j && l <= i) r[q] -= lij * colj[l];
-      }
-    }
+    I = r;
+    C = q;
   }
-  // L to LDS, then X = L^{-1} row segments in registers
+  if (t == 0) bad = 0;
+  T r[TS][TS];
+  if (I >= 0) {
 #pragma unroll
-  for (int q = 0; q < H; ++q) Lt[i][c0 + q] = r[q];
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) {
+        const int row = TS * I + rr, col = TS * C + cc;
+        r[rr][cc] = (row < b && col < b) ? a[(int64_t)row * lda + col] : (row == col ? T(1) : T(0));
+      }
+  }
   __syncthreads();
-  T x[H];
+  const int nJ = (b + TS - 1) / TS;
+  for (int J = 0; J < nJ; ++J) {
 #pragma unroll
-  for (int q = 0; q < H; ++q) x[q] = (c0 + q == i) ? T(1) : T(0);
+    for (int jj = 0; jj < TS; ++jj) {
+      const int j = TS * J + jj;
+      if (j >= b) break;
+      if (I == J && C == J) {
+        T d = r[jj][jj];
+        if (!(d > T(0)) || !(d < T(3.0e38))) {
+          if (bad == 0) bad = k0 + j + 1;
+          d = T(1);
+        }
+        d = sqrt(d);
+        r[jj][jj] = d;
+        pinv = T(1) / d;
+      }
+      __syncthreads();
+      if (C == J && I >= J) {
+        const T inv = pinv;
 #pragma unroll
-  for (int j = 0; j < BLK; ++j) {
-    if (i == j) {
-      const T inv = T(1) / Lt[j][j];
+        for (int rr = 0; rr < TS; ++rr) {
+          const int row = TS * I + rr;
+          if (row > j) r[rr][jj] *= inv;
+          vec[row] = row > j ? r[rr][jj] : T(0);
+        }
+      }
+      __syncthreads();
+      // rank-1 update; vec is zero on rows <= j, so no element needs a test
+      // (entries above the diagonal of diagonal tiles are discarded later)
+      if (I >= J && C >= J) {
+        T li[TS], lc[TS];
 #pragma unroll
-      for (int q = 0; q < H; ++q) {
-        x[q] = x[q] * inv;
-        colj[c0 + q] = x[q];
+        for (int q = 0; q < TS; ++q) {
+          li[q] = vec[TS * I + q];
+          lc[q] = vec[TS * C + q];
+        }
+#pragma unroll
+        for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < TS; ++cc) r[rr][cc] = fma(-li[rr], lc[cc], r[rr][cc]);
       }
     }
-    __syncthreads();
-    if (i > j) {
-      const T lij = Lt[i][j];
+  }
+  // L back to memory and into LDS; upper part of the block zeroed
+  if (I >= 0) {
 #pragma unroll
-      for (int q = 0; q < H; ++q)
-        if (c0 + q <= j) x[q] -= lij * colj[c0 + q];
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) {
+        const int row = TS * I + rr, col = TS * C + cc;
+        const T v = col <= row ? r[rr][cc] : T(0);
+        S[row][col] = v;
+        if (row < b && col < b) a[(int64_t)row * lda + col] = v;
+      }
+  }
+  for (int e = t; e < b * b; e += 256) {
+    const int row = e / b, col = e - row * b;
+    if (col / TS > row / TS) a[(int64_t)row * lda + col] = T(0);
+  }
+  __syncthreads();
+  // X = L^{-1}: X = I, then for each j: X[j, :] /= L[j][j]; rows below
+  // X[i, :] -= L[i][j] X[j, :]
+  if (I >= 0) {
+#pragma unroll
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) r[rr][cc] = (TS * I + rr == TS * C + cc) ? T(1) : T(0);
+  }
+  for (int J = 0; J < nJ; ++J) {
+#pragma unroll
+    for (int jj = 0; jj < TS; ++jj) {
+      const int j = TS * J + jj;
+      if (j >= b) break;
+      if (I == J) {
+        const T inv = T(1) / S[j][j];
+#pragma unroll
+        for (int cc = 0; cc < TS; ++cc) {
+          const int col = TS * C + cc;
+          if (col <= j) r[jj][cc] *= inv;
+          vec[col] = col <= j ? r[jj][cc] : T(0);
+        }
+      }
+      __syncthreads();
+      // rows below j: L (in S) is zero above the diagonal and vec is zero on
+      // columns > j, so only row j itself must be excluded
+      if (I >= J && C <= J && I >= 0) {
+        T lr[TS], xc[TS];
+#pragma unroll
+        for (int q = 0; q < TS; ++q) {
+          lr[q] = S[TS * I + q][j];
+          xc[q] = vec[TS * C + q];
+        }
+        if (I == J) lr[jj] = T(0);
+#pragma unroll
+        for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < TS; ++cc) r[rr][cc] = fma(-lr[rr], xc[cc], r[rr][cc]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (bad && t == 0 && info && info[bz] == 0) info[bz] = bad;
-  T* li = Linv + bz * sL + (int64_t)(k0 / BLK) * BLK * BLK;
+  T* li = Linv + bz * sL + (int64_t)blk * DB * DB;
+  if (I >= 0) {
 #pragma unroll
-  for (int q = 0; q < H; ++q) {
-    a[(int64_t)i * lda + c0 + q] = (c0 + q <= i) ? r[q] : T(0);
-    li[i * BLK + c0 + q] = x[q];
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) {
+        const int row = TS * I + rr, col = TS * C + cc;
+        li[row * DB + col] = (row < b && col < b && col <= row) ? r[rr][cc] : T(0);
+      }
   }
+  for (int e = t; e < DB * DB; e += 256) {
+    const int row = e / DB, col = e - row * DB;
+    if (col / TS > row / TS) li[e] = T(0);
+  }
+  if (t == 0 && bad && info && info[bz] == 0) info[bz] = bad;
 }
 
-// Copies the diagonal Linv tile into Y's diagonal block (rows/cols i0..i0+BLK).
+// Copies the h x h inverse block `blk` of Linv into Y's diagonal block at
+// (i0, i0).
 template <typename T>
-__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int i0,
-                                                             const T* Linv, int64_t sL, int tile) {
-  const int64_t bz = blockIdx.x;
-  T* y = Y + bz * sY;
-  const T* li = Linv + bz * sL + (int64_t)tile * BLK * BLK;
-  for (int e = threadIdx.x; e < BLK * BLK; e += 256)
-    y[(int64_t)(i0 + e / BLK) * ldy + i0 + e % BLK] = li[e];
+__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int i0, int h,
+                                                             const T* Linv, int64_t sL, int blk) {
+  const int64_t bz = blockIdx.y;
+  const int r = blockIdx.x;
+  T* y = Y + bz * sY + (int64_t)(i0 + r) * ldy + i0;
+  const T* li = Linv + bz * sL + (int64_t)blk * DB * DB + (int64_t)r * DB;
+  for (int c = threadIdx.x; c < h; c += 256) y[c] = li[c];
 }
 
 // Copies an m x n block (row-major, ld) between buffers of a batch.
@@ -274,7 +480,7 @@ __global__ __launch_bounds__(256) void symmetrize_scale_kernel(const T* in, int6
 // Tile shapes: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128.  The choice
 // for a call is looked up by (type, TA, TB, mode bits, shape bucket); buckets
 // are powers of two of M, N, K and of the batch size.  Calls that overwrite
-// their own operand (in place) always use 64x64 tiles.  The table is filled
+// their own operand (in place) use a single tile column (or row).  The table is filled
 // by gemm_autotune(), which times every shape on scratch matrices of the
 // bucket's size and keeps the fastest; untuned buckets use 64x64.
 namespace {
@@ -310,10 +516,14 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
   const int BM = (shape == 1 || shape == 3) ? 128 : 64;
   const int BN = (shape == 2 || shape == 3) ? 128 : 64;
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+  constexpr int VW = 16 / sizeof(T);
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const int vec = (lda % VW == 0 && ldb % VW == 0 && (batch == 1 || (sA % VW == 0 && sB % VW == 0)) && al(A) &&
+                   al(B)) ? 1 : 0;
 #define GEMM_CASE(a, b, bm, bn)                                                                        \
   if (TA == a && TB == b && BM == bm && BN == bn) {                                                    \
     hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
-                       sA, B, ldb, sB, beta, C, ldc, sC, mode);                                        \
+                       sA, B, ldb, sB, beta, C, ldc, sC, mode, vec);                                   \
     return;                                                                                            \
   }
 #define GEMM_SHAPES(a, b) \
@@ -331,7 +541,12 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
   if (M <= 0 || N <= 0 || batch <= 0) return;
   int shape = 0;
   const bool in_place = ((const T*)C == A) || ((const T*)C == B);
-  if (!in_place) {
+  if (in_place) {
+    // one tile column (C == A: tiles read only their own rows) or one tile
+    // row (C == B: tiles read only their own columns)
+    if ((const T*)C == A) shape = N > 64 ? 2 : 0;
+    else shape = M > 64 ? 1 : 0;
+  } else {
     bool known = false;
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
@@ -403,67 +618,53 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
 }
 
 template <typename T>
-void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv, int64_t sL,
+void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
               int* info) {
-  // Two-level right-looking blocking: 32-wide panels are factored inside a
-  // SB-wide super-panel (narrow updates), then the trailing matrix gets one
-  // rank-SB update (K = SB) per super-panel.
-  for (int K0 = 0; K0 < n; K0 += SUPER) {
-    const int kend = std::min(K0 + SUPER, n);
-    for (int k0 = K0; k0 < kend; k0 += BLK) {
-      hipLaunchKernelGGL(potrf_tile_kernel<T>, dim3(batch), dim3(64), 0, st, A, lda, sA, k0, Linv,
-                         sL, info);
-      const int rest = n - k0 - BLK;
-      if (rest <= 0) break;
-      T* panel = A + (int64_t)(k0 + BLK) * lda + k0;
-      const T* li = Linv + (int64_t)(k0 / BLK) * BLK * BLK;
-      // panel solve in place: X = A_panel L_kk^{-T} (each output tile reads
-      // only its own rows of the panel)
-      gemm<T>(st, 0, 1, rest, BLK, BLK, T(1), panel, lda, sA, li, BLK, sL, T(0), panel, lda, sA, batch, 0);
-      const int ncols = kend - (k0 + BLK);
-      if (ncols > 0)
-        gemm<T>(st, 0, 1, rest, ncols, BLK, T(-1), panel, lda, sA, panel, lda, sA, T(1),
-                A + (int64_t)(k0 + BLK) * lda + (k0 + BLK), lda, sA, batch, GEMM_LOWER);
-    }
-    const int rest = n - kend;
+  // Right-looking blocked Cholesky over DB-wide diagonal blocks: the block
+  // is factored and inverted in LDS, the panel below becomes
+  // A_panel L_kk^{-T} (one GEMM, in place: a single 128-wide column tile
+  // reads only its own rows), and the trailing matrix gets one rank-b update.
+  if (split <= 0 || split >= n) split = 0;
+  int K0 = 0;
+  while (K0 < n) {
+    const int lim = (split > 0 && K0 < split) ? split : n;
+    const int b = std::min(DB, lim - K0);
+    const int K1 = K0 + b;
+    hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(256), 0, st, A, lda, sA, K0, b, Linv, sL,
+                       diag_block_index(K0, split), info);
+    const int rest = n - K1;
     if (rest > 0) {
-      T* P = A + (int64_t)kend * lda + K0;
-      gemm<T>(st, 0, 1, rest, rest, kend - K0, T(-1), P, lda, sA, P, lda, sA, T(1),
-              A + (int64_t)kend * lda + kend, lda, sA, batch, GEMM_LOWER);
+      T* panel = A + (int64_t)K1 * lda + K0;
+      const T* li = Linv + (int64_t)diag_block_index(K0, split) * DB * DB;
+      gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
+      gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
+              lda, sA, batch, GEMM_LOWER);
     }
+    K0 = K1;
   }
 }
 
 template <typename T>
-void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int batch,
+void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
                  const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT) {
-  // Y = L_block^{-1} for the diagonal block [off, off+nb) of L (lower) by
-  // block forward substitution on L Y = I.  Y holds the running right-hand
-  // side R; within a SUPER-wide block row the 32-wide steps form
-  // inv(L_SS); the block row's left part becomes inv(L_SS) R_S (through
-  // tmp, SUPER x nb per matrix); rows below get one rank-SUPER update.
+  // Y = L_block^{-1} for the diagonal range [off, off+nb) of L (lower) by
+  // block forward substitution on L Y = I over the factor's diagonal blocks
+  // S: Y holds the running right-hand side R; Y[S, S] = inv(L_SS),
+  // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0] (through tmp), and the rows below
+  // get one rank-|S| update.
   hipLaunchKernelGGL(zero_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
-  for (int S0 = 0; S0 < nb; S0 += SUPER) {
-    const int send = std::min(S0 + SUPER, nb);
-    for (int i0 = S0; i0 < send; i0 += BLK) {
-      const T* li = Linv + (int64_t)((off + i0) / BLK) * BLK * BLK;
-      if (i0 > S0)
-        gemm<T>(st, 0, 0, BLK, i0 - S0, BLK, T(1), li, BLK, sLi, Y + (int64_t)i0 * ldy + S0, ldy, sY, T(0),
-                Y + (int64_t)i0 * ldy + S0, ldy, sY, batch, 0);
-      hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(batch), dim3(256), 0, st, Y, ldy, sY, i0, Linv, sLi,
-                         (off + i0) / BLK);
-      const int rin = send - i0 - BLK;
-      if (rin > 0) {
-        const T* Lli = L + (int64_t)(off + i0 + BLK) * ldl + (off + i0);
-        gemm<T>(st, 0, 0, rin, i0 + BLK - S0, BLK, T(-1), Lli, ldl, sL, Y + (int64_t)i0 * ldy + S0, ldy, sY, T(1),
-                Y + (int64_t)(i0 + BLK) * ldy + S0, ldy, sY, batch, 0);
-      }
-    }
-    const int h = send - S0;
+  int S0 = 0;
+  while (S0 < nb) {
+    const int p = off + S0;
+    const int lim = (split > 0 && p < split) ? std::min(split - off, nb) : nb;
+    const int h = std::min(DB, lim - S0);
+    const int send = S0 + h;
+    const int blk = diag_block_index(p, split);
+    const T* li = Linv + (int64_t)blk * DB * DB;
+    hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, Y, ldy, sY, S0, h, Linv, sLi,
+                       blk);
     if (S0 > 0) {
-      // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0]
-      gemm<T>(st, 0, 0, h, S0, h, T(1), Y + (int64_t)S0 * ldy + S0, ldy, sY, Y + (int64_t)S0 * ldy, ldy, sY, T(0),
-              tmp, S0, sT, batch, GEMM_KTO_DIAG);
+      gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), tmp, S0, sT, batch, 0);
       hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, (const T*)tmp, (int64_t)S0, sT,
                          Y + (int64_t)S0 * ldy, ldy, sY, S0);
     }
@@ -473,6 +674,7 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
       gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
               Y + (int64_t)send * ldy, ldy, sY, batch, 0);
     }
+    S0 = send;
   }
 }
 
@@ -487,8 +689,8 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template void gemm<T>(hipStream_t, int, int, int, int, int, T, const T*, int64_t, int64_t,    \
                         const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int);         \
   template int gemm_autotune<T>(int, int, int, int, int, int, int);                              \
-  template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, T*, int64_t, int*);    \
-  template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, const T*, \
+  template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*); \
+  template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
                                int64_t, T*, int64_t, int64_t, T*, int64_t);
 INST(double)
 INST(float)
