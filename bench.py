@@ -233,10 +233,11 @@ def roofline(kt, info):
     if name not in kt or kt[name][1] == 0:
         return None
     total_ms, launches = kt[name]
-    # per launch: the active part of every subdomain's Dirichlet inverse
-    # (8 B per entry) plus the gathered input(s) and the scattered output
-    # (2 vectors on the first launch of an apply, 3 on the second: 2.5 avg)
-    alg_bytes = 8.0 * info["sum_nI2"] + 8.0 * 2.5 * info["sum_nI"]
+    # per launch: the unique entries of every subdomain's symmetric
+    # Dirichlet inverse (lower triangle with diagonal, 8 B each) plus the
+    # gathered input(s) and the scattered output (2 vectors on the first
+    # launch of an apply, 3 on the second: 2.5 on average)
+    alg_bytes = 8.0 * (info["sum_nI2"] + info["sum_nI"]) / 2.0 + 8.0 * 2.5 * info["sum_nI"]
     avg_s = total_ms / launches * 1e-3
     achieved = alg_bytes / avg_s / 1e9
     return {"bound": "hbm", "kernel": "apply_interior_kernel<double>", "achieved": achieved,

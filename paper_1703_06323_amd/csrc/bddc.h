@@ -50,6 +50,16 @@ void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* 
 void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows,
                             const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,
                             const double* AcLoc, double* Ac);
+// Symmetric operators in packed lower-block storage: SB x SB blocks (I, J),
+// J <= I, packed_blocks(n) blocks of SB*SB values per subdomain.
+constexpr int SB = 32;
+inline int packed_elems(int n) { return (n / SB) * (n / SB + 1) / 2 * SB * SB; }
+// out[w] = D_w sym(in_w) D_w in packed storage (only the lower triangle of
+// in_w is read; D may be null).  n a multiple of SB.
+template <typename TI, typename TO>
+void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,
+                       int64_t sD, TO* out);
+// P, Kt: packed storage.
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out);

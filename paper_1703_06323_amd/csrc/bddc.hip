@@ -19,6 +19,8 @@
 //   A_c^omega = Phi^T S_A Phi = S_c^{-1} - R  (local coarse matrix)
 #include "bddc.h"
 
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace cutbddc {
@@ -378,20 +380,143 @@ __global__ void coarse_assemble_kernel(BatchDev bd, const int64_t* __restrict__ 
 
 // ---- apply ----------------------------------------------------------------
 
-// out[node(I_idx)] = P_w * (a - b)[I_idx]  (b may be null), per subdomain.
-// One workgroup per (subdomain, row chunk); each wave reduces one row at a time.
+// ---- symmetric operators in packed lower-block storage --------------------
+// A symmetric n x n operator (n a multiple of SB) is kept as its lower SB x SB
+// blocks (I, J), J <= I, in row-major block order; block q = I (I + 1) / 2 + J
+// holds SB*SB values in the order in which the apply kernel's lanes read
+// them: lane l = r + 32 h (row r, column half h) reads its 16 values of row
+// r, columns 16 h + [0, 16), as 16-byte vectors k; vector (k, l) sits at
+// (k * 64 + l) * 16 bytes, so each wave-wide load reads 1 KB contiguously.
+__device__ inline int packed_offset(int r, int c, int vw) {
+  const int h = c >> 4, cc = c & 15;
+  return ((cc / vw) * 64 + r + 32 * h) * vw + (cc % vw);
+}
+
+// out (packed) = D sym(in) D where sym(in)[i][j] = in[max(i,j)][min(i,j)]
+// (only the lower triangle of in is read); D may be null (identity).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void pack_lower_kernel(const TI* __restrict__ in, int64_t ldi, int64_t sI,
+                                                         const double* __restrict__ D, int64_t sD,
+                                                         TO* __restrict__ out, int nbk) {
+  constexpr int VW = 16 / sizeof(TO);
+  const int64_t w = blockIdx.y;
+  const int q = blockIdx.x;
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= q) ++I;
+  const int J = q - I * (I + 1) / 2;
+  const TI* x = in + w * sI;
+  const double* d = D ? D + w * sD : nullptr;
+  TO* o = out + (w * nbk + q) * (int64_t)(SB * SB);
+  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+    const int r = e / SB, c = e % SB;
+    const int i = SB * I + r, j = SB * J + c;
+    const TI v = i >= j ? x[(int64_t)i * ldi + j] : x[(int64_t)j * ldi + i];
+    const double sc = d ? d[i] * d[j] : 1.0;
+    o[packed_offset(r, c, VW)] = (TO)((double)v * sc);
+  }
+}
+
+// ys[0, nbu*SB) = P xs for one packed symmetric operator P with nb block rows,
+// of which the first nbu hold active rows (blocks beyond are skipped: xs is
+// zero there).  Run by the whole workgroup; each wave takes whole blocks:
+// the row part of block (I, J) goes to rowp, for I != J the transposed part
+// (P_IJ^T x_I) to colp, through a butterfly transpose-reduce within each
+// 32-lane half.  The partials are summed per row in a fixed order, so the
+// result does not depend on the wave schedule.
+template <typename TM>
+__device__ inline void symv_packed(const TM* __restrict__ Pk, int nbu, const double* xs, double* rowp, double* colp,
+                                   double* ys) {
+  typedef typename std::conditional<sizeof(TM) == 4, float __attribute__((ext_vector_type(4))),
+                                    double __attribute__((ext_vector_type(2)))>::type V;
+  constexpr int VW = 16 / sizeof(TM), NV = 16 / VW;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int nq = nbu * (nbu + 1) / 2;
+  int I = 0;
+  for (int q = wv; q < nq; q += nw) {
+    while ((I + 1) * (I + 2) / 2 <= q) ++I;
+    const int J = q - I * (I + 1) / 2;
+    const V* src = reinterpret_cast<const V*>(Pk + (int64_t)q * SB * SB) + lane;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const V x = src[k * 64];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[k * VW + e] = (double)x[e];
+    }
+    const double* xj = xs + SB * J + 16 * h;
+    double rs = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) rs += v[c] * xj[c];
+    rs += __shfl_xor(rs, 32, 64);
+    if (h == 0) rowp[q * SB + r] = rs;
+    if (I != J) {
+      const double xi = xs[SB * I + r];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] *= xi;
+      // sum over the 32 rows of each of the 16 columns: after the halving
+      // steps lane r holds column (r >> 1) of its half
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool up = (r & 16) != 0;
+        const double send = up ? v[k] : v[k + 8];
+        const double keep = up ? v[k + 8] : v[k];
+        v[k] = keep + __shfl_xor(send, 16, 64);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool up = (r & 8) != 0;
+        const double send = up ? v[k] : v[k + 4];
+        const double keep = up ? v[k + 4] : v[k];
+        v[k] = keep + __shfl_xor(send, 8, 64);
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const bool up = (r & 4) != 0;
+        const double send = up ? v[k] : v[k + 2];
+        const double keep = up ? v[k + 2] : v[k];
+        v[k] = keep + __shfl_xor(send, 4, 64);
+      }
+      {
+        const bool up = (r & 2) != 0;
+        const double send = up ? v[0] : v[1];
+        const double keep = up ? v[1] : v[0];
+        v[0] = keep + __shfl_xor(send, 2, 64);
+      }
+      v[0] += __shfl_xor(v[0], 1, 64);
+      if ((r & 1) == 0) colp[q * SB + 16 * h + (r >> 1)] = v[0];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbu * SB; i += blockDim.x) {
+    const int Ib = i / SB, ri = i % SB;
+    double acc = 0.0;
+    for (int Jb = 0; Jb <= Ib; ++Jb) acc += rowp[(Ib * (Ib + 1) / 2 + Jb) * SB + ri];
+    for (int Kb = Ib + 1; Kb < nbu; ++Kb) acc += colp[(Kb * (Kb + 1) / 2 + Ib) * SB + ri];
+    ys[i] = acc;
+  }
+  __syncthreads();
+}
+
+// out[node(I_idx)] = P_w (a - b)[I_idx] (b may be null), one workgroup per
+// subdomain, P_w = A_II^{-1} in packed storage.
 template <typename TM>
 __global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM* __restrict__ P,
                                                              const double* __restrict__ a,
                                                              const double* __restrict__ b,
-                                                             double* __restrict__ out, int rows_per_block) {
-  extern __shared__ double xs[];
-  const int w = blockIdx.y;
+                                                             double* __restrict__ out) {
+  extern __shared__ double lds[];
+  const int w = blockIdx.x;
   if (sd.active && !sd.active[sd.sub_prob[w]]) return;
-  const int NIp = sd.NIp;
+  const int NIp = sd.NIp, nbk = (NIp / SB) * (NIp / SB + 1) / 2;
   const int nI = sd.nI[w];
+  const int nbu = (nI + SB - 1) / SB;
+  double* xs = lds;                 // [NIp]
+  double* ys = xs + NIp;            // [NIp]
+  double* rowp = ys + NIp;          // [nbk * SB]
+  double* colp = rowp + nbk * SB;   // [nbk * SB]
   const int64_t* idx = sd.I_idx + (int64_t)w * NIp;
-  for (int j = threadIdx.x; j < NIp; j += 256) {
+  for (int j = threadIdx.x; j < NIp; j += blockDim.x) {
     double v = 0.0;
     if (j < nI) {
       const int64_t n = idx[j];
@@ -400,35 +525,31 @@ __global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM
     xs[j] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(nI, r0 + rows_per_block);
-  const TM* Pw = P + (int64_t)w * NIp * NIp;
-  for (int r = r0 + wv; r < r1; r += 4) {
-    const TM* row = Pw + (int64_t)r * NIp;
-    double acc = 0.0;
-    for (int j = lane; j < nI; j += 64) acc += (double)row[j] * xs[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) out[idx[r]] = acc;
-  }
+  symv_packed<TM>(P + (int64_t)w * nbk * SB * SB, nbu, xs, rowp, colp, ys);
+  for (int j = threadIdx.x; j < nI; j += blockDim.x) out[idx[j]] = ys[j];
 }
 
-// z_w = Kt_w g_w with g_w[j] = Dw[j] (r - t)[G_idx[j]]; cloc_w = Phi_w^T g_w.
+// z_w = Kt_w g_w with g_w[j] = Dw[j] (r - t)[G_idx[j]] (Kt_w packed);
+// cloc_w = Phi_w^T g_w.
 template <typename TM>
 __global__ __launch_bounds__(256) void apply_neumann_kernel(SubDev sd, const TM* __restrict__ Kt,
                                                             const double* __restrict__ Phi,
                                                             const double* __restrict__ Dw,
                                                             const double* __restrict__ r,
                                                             const double* __restrict__ t,
-                                                            double* __restrict__ z, double* __restrict__ cloc,
-                                                            int rows_per_block) {
-  extern __shared__ double gs[];
-  const int w = blockIdx.y;
+                                                            double* __restrict__ z, double* __restrict__ cloc) {
+  extern __shared__ double lds[];
+  const int w = blockIdx.x;
   if (sd.active && !sd.active[sd.sub_prob[w]]) return;
-  const int NGp = sd.NGp, NCp = sd.NCp;
+  const int NGp = sd.NGp, NCp = sd.NCp, nbk = (NGp / SB) * (NGp / SB + 1) / 2;
   const int nG = sd.nG[w], nC = sd.nC[w];
+  const int nbu = (nG + SB - 1) / SB;
+  double* gs = lds;                 // [NGp]
+  double* ys = gs + NGp;            // [NGp]
+  double* rowp = ys + NGp;          // [nbk * SB]
+  double* colp = rowp + nbk * SB;   // [nbk * SB]
   const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
-  for (int j = threadIdx.x; j < NGp; j += 256) {
+  for (int j = threadIdx.x; j < NGp; j += blockDim.x) {
     double v = 0.0;
     if (j < nG) {
       const int64_t n = idx[j];
@@ -437,25 +558,17 @@ __global__ __launch_bounds__(256) void apply_neumann_kernel(SubDev sd, const TM*
     gs[j] = v;
   }
   __syncthreads();
+  symv_packed<TM>(Kt + (int64_t)w * nbk * SB * SB, nbu, gs, rowp, colp, ys);
+  for (int j = threadIdx.x; j < NGp; j += blockDim.x) z[(int64_t)w * NGp + j] = j < nG ? ys[j] : 0.0;
+  // coarse right-hand side: one wave per coarse row
+  const double* ph = Phi + (int64_t)w * NGp * NCp;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(nG, r0 + rows_per_block);
-  const TM* Kw = Kt + (int64_t)w * NGp * NGp;
-  for (int i = r0 + wv; i < r1; i += 4) {
-    const TM* row = Kw + (int64_t)i * NGp;
+  for (int u = wv; u < NCp; u += blockDim.x >> 6) {
     double acc = 0.0;
-    for (int j = lane; j < nG; j += 64) acc += (double)row[j] * gs[j];
+    if (u < nC)
+      for (int j = lane; j < nG; j += 64) acc += ph[(int64_t)j * NCp + u] * gs[j];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) z[(int64_t)w * NGp + i] = acc;
-  }
-  if (blockIdx.x == 0) {
-    const double* ph = Phi + (int64_t)w * NGp * NCp;
-    for (int u = threadIdx.x; u < NCp; u += 256) {
-      double acc = 0.0;
-      if (u < nC)
-        for (int j = 0; j < nG; ++j) acc += ph[(int64_t)j * NCp + u] * gs[j];
-      cloc[(int64_t)w * NCp + u] = acc;
-    }
+    if (lane == 0) cloc[(int64_t)w * NCp + u] = acc;
   }
 }
 
@@ -580,13 +693,30 @@ void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* pr
                      n_prows, cs_ptr, cs_sub, cs_row, sd, AcLoc, Ac);
 }
 
+inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
+
+template <typename TI, typename TO>
+void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,
+                       int64_t sD, TO* out) {
+  if (ns <= 0 || n <= 0) return;
+  hipLaunchKernelGGL((pack_lower_kernel<TI, TO>), dim3(packed_blocks(n), ns), dim3(256), 0, st, in, ldi, sI, D, sD,
+                     out, packed_blocks(n));
+}
+template void launch_pack_lower<float, float>(hipStream_t, int, int, const float*, int64_t, int64_t, const double*,
+                                              int64_t, float*);
+template void launch_pack_lower<double, double>(hipStream_t, int, int, const double*, int64_t, int64_t,
+                                                const double*, int64_t, double*);
+template void launch_pack_lower<double, float>(hipStream_t, int, int, const double*, int64_t, int64_t,
+                                               const double*, int64_t, float*);
+
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out) {
-  const int rpb = 64;
-  dim3 grid((sd.NIp + rpb - 1) / rpb, ns);
-  hipLaunchKernelGGL(apply_interior_kernel<TM>, grid, dim3(256), sd.NIp * sizeof(double), st, sd, P, a, b,
-                     out, rpb);
+  const size_t sh = (size_t)(2 * sd.NIp + 2 * packed_blocks(sd.NIp) * SB) * sizeof(double);
+  static bool attr = (hipFuncSetAttribute((const void*)apply_interior_kernel<TM>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
+  (void)attr;
+  hipLaunchKernelGGL(apply_interior_kernel<TM>, dim3(ns), dim3(256), sh, st, sd, P, a, b, out);
 }
 template void launch_apply_interior<double>(hipStream_t, const SubDev&, int, const double*, const double*,
                                             const double*, double*);
@@ -596,10 +726,11 @@ template void launch_apply_interior<float>(hipStream_t, const SubDev&, int, cons
 template <typename TM>
 void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc) {
-  const int rpb = 64;
-  dim3 grid((sd.NGp + rpb - 1) / rpb, ns);
-  hipLaunchKernelGGL(apply_neumann_kernel<TM>, grid, dim3(256), sd.NGp * sizeof(double), st, sd, Kt, Phi,
-                     Dw, r, t, z, cloc, rpb);
+  const size_t sh = (size_t)(2 * sd.NGp + 2 * packed_blocks(sd.NGp) * SB) * sizeof(double);
+  static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
+  (void)attr;
+  hipLaunchKernelGGL(apply_neumann_kernel<TM>, dim3(ns), dim3(256), sh, st, sd, Kt, Phi, Dw, r, t, z, cloc);
 }
 template void launch_apply_neumann<double>(hipStream_t, const SubDev&, int, const double*, const double*,
                                            const double*, const double*, const double*, double*, double*);

@@ -1066,7 +1066,6 @@ int factor_impl(cb_ctx* c) {
   hipStream_t st = c->st;
   const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
   const GridDev g = c->grid();
-  const bool f32 = std::is_same<T, float>::value;
   const int nbig = std::max(NIp, NGp);
   const int64_t sK = (int64_t)nt * nt;
   const int64_t sL = (int64_t)diag_blocks(nt, NIp) * DB * DB;
@@ -1075,9 +1074,11 @@ int factor_impl(cb_ctx* c) {
   const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp, sF = (int64_t)nt * NCp;
   const int64_t sP = (int64_t)NIp * NIp, sKS = (int64_t)NGp * NGp;
 
-  // persistent results
-  CHK(dalloc(c->P_, (size_t)ns * sP * sizeof(T)));
-  CHK(dalloc(c->Kt, (size_t)ns * sKS * sizeof(T)));
+  // persistent results (A_II^{-1} and the interface operator in packed
+  // symmetric storage)
+  const int64_t pkI = packed_elems(NIp), pkG = packed_elems(NGp);
+  CHK(dalloc(c->P_, (size_t)ns * pkI * sizeof(T)));
+  CHK(dalloc(c->Kt, (size_t)ns * pkG * sizeof(T)));
   CHK(dalloc(c->Phi, (size_t)ns * sG * sizeof(double)));
   CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
   CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
@@ -1091,7 +1092,7 @@ int factor_impl(cb_ctx* c) {
 
   // work buffers for a chunk of subdomains
   const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
-                         (size_t)sT * sizeof(T) + (f32 ? (size_t)sP * 8 + (size_t)sKS * 8 : 0) +
+                         (size_t)sT * sizeof(T) + (size_t)sP * 8 + (size_t)sKS * 8 +
                          (size_t)(sG + sC + 2 * sF) * sizeof(double);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
   DevBuf K, Linv, Y, PS, Tmp, Pd64, KSw, G, Sc, PhiF, V;
@@ -1100,10 +1101,8 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
   CHK(dalloc(PS, (size_t)chunk * sY * sizeof(T)));
   CHK(dalloc(Tmp, (size_t)chunk * sT * sizeof(T)));
-  if (f32) {
-    CHK(dalloc(Pd64, (size_t)chunk * sP * sizeof(double)));
-    CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
-  }
+  CHK(dalloc(Pd64, (size_t)chunk * sP * sizeof(double)));
+  CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
   CHK(dalloc(G, (size_t)chunk * sG * sizeof(double)));
   CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
   CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
@@ -1112,10 +1111,9 @@ int factor_impl(cb_ctx* c) {
   for (int w0 = 0; w0 < ns; w0 += chunk) {
     const int nc = std::min(chunk, ns - w0);
     const SubDev sd = c->sub(w0);
-    T* Pw = c->P_.as<T>() + (int64_t)w0 * sP;
     const double* Dsw = c->Ds.as<double>() + (int64_t)w0 * nt;
     double* Phiw = c->Phi.as<double>() + (int64_t)w0 * sG;
-    double* KS = f32 ? KSw.as<double>() : reinterpret_cast<double*>(c->Kt.as<T>() + (int64_t)w0 * sKS);
+    double* KS = KSw.as<double>();
     launch_assemble_local<T>(st, sd, g, nc, K.as<T>(), c->diagAG.as<double>() + (int64_t)w0 * NGp,
                              c->Ds.as<double>() + (int64_t)w0 * nt);
     HIPCHK(hipGetLastError());
@@ -1129,13 +1127,10 @@ int factor_impl(cb_ctx* c) {
       gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
-    symmetrize_scale<T, T>(st, PS.as<T>(), NIp, sY, Pw, NIp, sP, Dsw, nt, NIp, nc);
-    // FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
-    const double* Pd = reinterpret_cast<const double*>(Pw);
-    if (f32) {
-      symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
-      Pd = Pd64.as<double>();
-    }
+    launch_pack_lower<T, T>(st, NIp, nc, PS.as<T>(), NIp, sY, Dsw, nt, c->P_.as<T>() + (int64_t)w0 * pkI);
+    // full FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
+    symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
+    const double* Pd = Pd64.as<double>();
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
     timed(c, "local_inverse", [&] {
@@ -1171,8 +1166,7 @@ int factor_impl(cb_ctx* c) {
                  nc, 0);
     // Kt = K_S^{-1} - Phi G^T
     gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NCp, sG, 1.0, KS, NGp, sKS, nc, 0);
-    if (f32)
-      convert_to_float(st, (int64_t)nc * sKS, KS, reinterpret_cast<float*>(c->Kt.as<T>() + (int64_t)w0 * sKS));
+    launch_pack_lower<double, T>(st, NGp, nc, KS, NGp, sKS, nullptr, 0, c->Kt.as<T>() + (int64_t)w0 * pkG);
     HIPCHK(hipGetLastError());
   }
   for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
