@@ -208,6 +208,30 @@ double now_ms() {
       .count();
 }
 
+// Pinned host staging for the large setup copies (cell counts down, cell
+// info and cut-cell lists up), kept per host thread and grown on demand.
+// A setup call synchronises its stream before it returns, so the next call
+// on the same thread may reuse the buffer.
+struct PinnedStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+  void* get(size_t need) {
+    if (need > bytes) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      bytes = 0;
+      const size_t want = std::max<size_t>(need, (size_t)1 << 20);
+      if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+      bytes = want;
+    }
+    return p;
+  }
+};
+thread_local PinnedStage t_stage;
+
 }  // namespace
 
 struct ProfEntry {
@@ -691,7 +715,6 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   const std::vector<double> xiv(c->xi, c->xi + 8);
   CHK(upload(c->xi_d, xiv, st));
   std::vector<double> balls(4 * (size_t)std::max(1, ball_off));
-  std::vector<double> kap(c->n_cells_tot, 1.0);
   for (int k = 0; k < P; ++k) {
     const ProbHost& h = c->pb[k];
     for (int i = 0; i < h.nb; ++i) {
@@ -701,11 +724,16 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
       B[2] = ps[k].ball_centres[3 * i + 2];
       B[3] = ps[k].ball_radii[i] * ps[k].ball_radii[i];
     }
-    if (ps[k].kappa)
-      std::memcpy(&kap[h.cell_off], ps[k].kappa, (size_t)h.N * h.N * h.N * sizeof(double));
   }
   CHK(upload(c->balls, balls, st));
-  CHK(upload(c->kappa, kap, st));
+  // kappa: 1 on the device, then the given per-cell values
+  CHK(dalloc(c->kappa, c->n_cells_tot * sizeof(double)));
+  launch_fill(st, c->n_cells_tot, 1.0, c->kappa.as<double>());
+  for (int k = 0; k < P; ++k)
+    if (ps[k].kappa)
+      HIPCHK(hipMemcpyAsync(c->kappa.as<double>() + c->pb[k].cell_off, ps[k].kappa,
+                            (size_t)c->pb[k].N * c->pb[k].N * c->pb[k].N * sizeof(double), hipMemcpyHostToDevice,
+                            st));
   // preliminary problem table for the grid kernels
   // (uploaded host vectors stay alive until the stream is synchronised)
   auto prob_table = [&](bool indexed) {
@@ -746,35 +774,54 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   launch_classify(st, c->batch(false), c->n_cells_tot, c->xi_d.as<double>(), c->balls.as<double>(),
                   c->count_d.as<int32_t>());
   HIPCHK(hipGetLastError());
-  std::vector<int32_t> counts(c->n_cells_tot);
-  HIPCHK(hipMemcpyAsync(counts.data(), c->count_d.p, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  std::vector<int> porder(P);
+  std::iota(porder.begin(), porder.end(), 0);
+  int32_t* counts = static_cast<int32_t*>(t_stage.get((size_t)c->n_cells_tot * 16));
+  if (!counts) return fail(CB_ERR_OOM, "pinned staging allocation failed");
+  HIPCHK(hipMemcpyAsync(counts, c->count_d.p, c->n_cells_tot * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
 
   // cell info: cut cells numbered in problem order, then cell order
-  std::vector<int32_t> cellinfo(c->n_cells_tot, CELL_INACTIVE);
-  std::vector<int64_t> cut_global;
-  for (int k = 0; k < P; ++k) {
+  for_each_problem(porder, [&](int k) {
     ProbHost& h = c->pb[k];
     const int64_t ncell = (int64_t)h.N * h.N * h.N;
-    h.count.assign(counts.begin() + h.cell_off, counts.begin() + h.cell_off + ncell);
-    h.cut_off = (int64_t)cut_global.size();
+    h.count.assign(counts + h.cell_off, counts + h.cell_off + ncell);
     for (int64_t cc = 0; cc < ncell; ++cc) {
       const int32_t n = h.count[cc];
       if (n <= 0) continue;
       h.n_active++;
-      if (n < 512) h.n_cut++;
-      if (n < 512 && !c->full_elements) {
-        cellinfo[h.cell_off + cc] = (int32_t)cut_global.size();
-        h.cut_local.push_back(cc);
-        cut_global.push_back(h.cell_off + cc);
-      } else {
-        cellinfo[h.cell_off + cc] = CELL_UNCUT;
+      if (n < 512) {
+        h.n_cut++;
+        if (!c->full_elements) h.cut_local.push_back(cc);
       }
     }
+  });
+  int64_t cut_tot = 0;
+  for (int k = 0; k < P; ++k) {
+    c->pb[k].cut_off = cut_tot;
+    cut_tot += (int64_t)c->pb[k].cut_local.size();
   }
-  c->n_cut_tot = (int64_t)cut_global.size();
-  CHK(upload(c->cellinfo, cellinfo, st));
-  CHK(upload(c->cut_d, cut_global, st));
+  c->n_cut_tot = cut_tot;
+  // same staging area after the counts: cell info (4 B per cell), then the
+  // cut-cell list (8 B per cut cell, at most one per cell)
+  int32_t* cellinfo = counts + c->n_cells_tot;
+  int64_t* cut_global = reinterpret_cast<int64_t*>(counts + 2 * c->n_cells_tot);
+  for_each_problem(porder, [&](int k) {
+    const ProbHost& h = c->pb[k];
+    const int64_t ncell = (int64_t)h.N * h.N * h.N;
+    int32_t* ci = cellinfo + h.cell_off;
+    for (int64_t cc = 0; cc < ncell; ++cc) ci[cc] = h.count[cc] > 0 ? CELL_UNCUT : CELL_INACTIVE;
+    for (int64_t cc = ncell; cc < align_seg(ncell); ++cc) ci[cc] = CELL_INACTIVE;
+    for (size_t q = 0; q < h.cut_local.size(); ++q) {
+      ci[h.cut_local[q]] = (int32_t)(h.cut_off + (int64_t)q);
+      cut_global[h.cut_off + (int64_t)q] = h.cell_off + h.cut_local[q];
+    }
+  });
+  CHK(dalloc(c->cellinfo, c->n_cells_tot * sizeof(int32_t)));
+  CHK(dalloc(c->cut_d, std::max<int64_t>(1, cut_tot) * sizeof(int64_t)));
+  HIPCHK(hipMemcpyAsync(c->cellinfo.p, cellinfo, c->n_cells_tot * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (cut_tot > 0)
+    HIPCHK(hipMemcpyAsync(c->cut_d.p, cut_global, cut_tot * sizeof(int64_t), hipMemcpyHostToDevice, st));
   CHK(dalloc(c->Kc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
   CHK(dalloc(c->Mc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
   launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),

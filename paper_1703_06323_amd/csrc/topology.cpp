@@ -287,11 +287,20 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
   // ---- subdomain sets S(xi) (node-parallel) -------------------------------
   t.S.assign(nd * 8, -1);
   t.card.assign(nd, 0);
-  parallel_for(nd, [&](int64_t db, int64_t de) {
-    for (int64_t d = db; d < de; ++d) {
-      const int64_t node = t.dof_node[d];
-      const int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
-      int32_t* Sd = &t.S[d * 8];
+  // slab by slab in node order (DOF nodes are interior: their 8 cells exist)
+  parallel_for(N1, [&](int64_t kb, int64_t ke) {
+    for (int64_t K = std::max<int64_t>(kb, 1); K < std::min<int64_t>(ke, N); ++K)
+      for (int64_t J = 1; J < N; ++J)
+        for (int64_t I = 1; I < N; ++I) {
+      const int32_t d = t.dof_of_node[node_id(I, J, K)];
+      if (d < 0) continue;
+      int32_t* Sd = &t.S[(int64_t)d * 8];
+      if (I % s != 0 && J % s != 0 && K % s != 0) {
+        // strictly inside a block: all 8 cells are in it, one of them active
+        Sd[0] = sub_of(I - 1, J - 1, K - 1);
+        t.card[d] = 1;
+        continue;
+      }
       int c = 0;
       for (int u = 0; u < 8; ++u) {
         const int64_t ci = I - 1 + (u & 1), cj = J - 1 + ((u >> 1) & 1), ck = K - 1 + ((u >> 2) & 1);
@@ -310,7 +319,7 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
         ++c;
       }
       t.card[d] = (uint8_t)c;
-    }
+        }
   });
 
   // ---- floating components ---------------------------------------------
@@ -330,6 +339,32 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
       std::vector<uint8_t> used(nbn), gr(nbn);
       for (int64_t w = wb; w < we; ++w) {
         const int Bx = (int)(w % m), By = (int)((w / m) % m), Bz = (int)(w / (m * m));
+        // a block whose cells are all active is one component (neighbouring
+        // cells always share a DOF node when N > 1)
+        bool full = N > 1, face_any = false;
+        for (int cz = 0; cz < s && full; ++cz)
+          for (int cy = 0; cy < s && full; ++cy)
+            for (int cx = 0; cx < s; ++cx) {
+              const int64_t i = (int64_t)Bx * s + cx, j = (int64_t)By * s + cy, k = (int64_t)Bz * s + cz;
+              if (!active(cell_id(i, j, k))) {
+                full = false;
+                break;
+              }
+              if (i == 0 || j == 0 || k == 0 || i == N - 1 || j == N - 1 || k == N - 1) face_any = true;
+            }
+        if (full) {
+          int32_t nc = 0;
+          for (int lz = 0; lz <= s; ++lz)
+            for (int ly = 0; ly <= s; ++ly)
+              for (int lx = 0; lx <= s; ++lx)
+                if (t.dof_of_node[node_id((int64_t)Bx * s + lx, (int64_t)By * s + ly, (int64_t)Bz * s + lz)] >= 0) {
+                  lcomp[w * nbn + lx + s1 * (ly + s1 * lz)] = 0;
+                  nc = 1;
+                }
+          if (nc && face_any) lground[w * nbn] = 1;
+          nlc[w + 1] = nc;
+          continue;
+        }
         std::iota(p.begin(), p.end(), 0);
         std::fill(used.begin(), used.end(), 0);
         std::fill(gr.begin(), gr.end(), 0);
@@ -379,20 +414,26 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
     for (int32_t w = 0; w < ns; ++w) base[w + 1] = base[w] + nlc[w + 1];
     const int32_t ncomp_all = base[ns];
     UnionFind guf(ncomp_all);
-    for (int64_t d = 0; d < nd; ++d) {
-      if (t.card[d] < 2) continue;
-      const int64_t node = t.dof_node[d];
-      const int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
-      int32_t first = -1;
-      for (int q = 0; q < t.card[d]; ++q) {
-        const int32_t w = t.S[d * 8 + q];
-        const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
-        const int ln = (int)(I - (int64_t)Bx * s) + s1 * ((int)(J - (int64_t)By * s) + s1 * (int)(K - (int64_t)Bz * s));
-        const int32_t idg = base[w] + lcomp[w * nbn + ln];
-        if (first < 0) first = idg;
-        else guf.unite(first, idg);
-      }
+    std::vector<int32_t> bx0(ns), by0(ns), bz0(ns);   // block origins (node coordinates)
+    for (int32_t w = 0; w < ns; ++w) {
+      bx0[w] = (w % m) * s;
+      by0[w] = ((w / m) % m) * s;
+      bz0[w] = (w / (m * m)) * s;
     }
+    for (int64_t K = 1; K < N; ++K)
+      for (int64_t J = 1; J < N; ++J)
+        for (int64_t I = 1; I < N; ++I) {
+          const int32_t d = t.dof_of_node[node_id(I, J, K)];
+          if (d < 0 || t.card[d] < 2) continue;
+          int32_t first = -1;
+          for (int q = 0; q < t.card[d]; ++q) {
+            const int32_t w = t.S[(int64_t)d * 8 + q];
+            const int ln = (int)(I - bx0[w]) + s1 * ((int)(J - by0[w]) + s1 * (int)(K - bz0[w]));
+            const int32_t idg = base[w] + lcomp[w * nbn + ln];
+            if (first < 0) first = idg;
+            else guf.unite(first, idg);
+          }
+        }
     std::vector<uint8_t> rg(ncomp_all, 0);
     for (int32_t w = 0; w < ns; ++w)
       for (int32_t c = 0; c < nlc[w + 1]; ++c)
@@ -648,11 +689,16 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
   auto block_nodes = [&](int32_t w, auto&& fn) {
     const int Bx = w % m, By = (w / m) % m, Bz = w / (m * m);
     for (int lz = 0; lz <= s; ++lz)
-      for (int ly = 0; ly <= s; ++ly)
-        for (int lx = 0; lx <= s; ++lx) {
-          const int64_t n = node_id((int64_t)Bx * s + lx, (int64_t)By * s + ly, (int64_t)Bz * s + lz);
+      for (int ly = 0; ly <= s; ++ly) {
+        const bool inner_yz = lz > 0 && lz < s && ly > 0 && ly < s;
+        int64_t n = node_id((int64_t)Bx * s, (int64_t)By * s + ly, (int64_t)Bz * s + lz);
+        for (int lx = 0; lx <= s; ++lx, ++n) {
           const int32_t d = t.dof_of_node[n];
           if (d < 0) continue;
+          if (inner_yz && lx > 0 && lx < s) {   // interior node of this block: S = {w}
+            fn(n, d, 0);
+            continue;
+          }
           const int32_t* Sd = &t.S[(int64_t)d * 8];
           int k = -1;
           for (int q = 0; q < t.card[d]; ++q)
@@ -660,6 +706,7 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
           if (k < 0) continue;
           fn(n, d, k);
         }
+      }
   };
   parallel_for(ns, [&](int64_t wb, int64_t we) {
     for (int64_t w = wb; w < we; ++w) {
