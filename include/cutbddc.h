@@ -179,6 +179,10 @@ int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out);
  * time and the number of bracketed launches since profiling was enabled. */
 int cb_profile(cb_ctx* c, int32_t enable);
 int cb_profile_time(cb_ctx* c, const char* name, double* total_ms, int64_t* launches);
+/* Per-launch durations (ms, in launch order) of the named group: at most
+ * `cap` values are written to ms (host array); *n receives the number of
+ * launches recorded.  Synchronises the stream. */
+int cb_profile_launches(cb_ctx* c, const char* name, double* ms, int64_t cap, int64_t* n);
 
 /* Host copies of the integer data of the discretisation (bit-exact parity).
  * Each output pointer may be NULL; sizes come from cb_query / cb_export_sizes.

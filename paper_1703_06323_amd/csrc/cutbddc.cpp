@@ -1668,6 +1668,24 @@ int cb_profile_time(cb_ctx* c, const char* name, double* total_ms, int64_t* laun
   return CB_OK;
 }
 
+int cb_profile_launches(cb_ctx* c, const char* name, double* ms, int64_t cap, int64_t* n) {
+  if (!c || !name || (cap > 0 && !ms)) return fail(CB_ERR_ARG, "null argument");
+  HIPCHK(hipStreamSynchronize(c->st));
+  int64_t k = 0;
+  auto it = c->prof_ev.find(name);
+  if (it != c->prof_ev.end())
+    for (auto& e : it->second.ev) {
+      if (k < cap) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+        ms[k] = t;
+      }
+      ++k;
+    }
+  if (n) *n = k;
+  return CB_OK;
+}
+
 void cb_destroy(cb_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);

@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.cb_host_indexing.argtypes = [C.POINTER(cb_problem), vp, C.POINTER(cb_info)] + [vp] * 6
     lib.cb_profile.argtypes = [vp, C.c_int32]
     lib.cb_profile_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.cb_profile_launches.argtypes = [vp, C.c_char_p, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
     lib.cb_setup_batch.argtypes = [C.POINTER(cb_problem), C.c_int32, vp, C.POINTER(vp)]
     lib.cb_solve_batch.argtypes = [vp, vp, vp, C.c_double, C.c_int32, ip, dp]
@@ -94,7 +95,7 @@ def load_library(path: str = LIB_PATH):
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
                  "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
                  "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing",
-                 "cb_setup_batch", "cb_solve_batch", "cb_query_problem"):
+                 "cb_setup_batch", "cb_solve_batch", "cb_query_problem", "cb_profile_launches"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -229,6 +230,16 @@ class Solver:
             _check(_lib.cb_profile_time(self.ctx, name.encode(), C.byref(t), C.byref(n)))
             if n.value:
                 out[name] = (float(t.value), int(n.value))
+        return out
+
+    def profile_launches(self, name: str) -> np.ndarray:
+        """Durations (ms) of every bracketed launch of one kernel group."""
+        n = C.c_int64(0)
+        _check(_lib.cb_profile_launches(self.ctx, name.encode(), None, 0, C.byref(n)))
+        out = np.zeros(n.value, np.float64)
+        if n.value:
+            _check(_lib.cb_profile_launches(self.ctx, name.encode(), out.ctypes.data_as(C.c_void_p), n.value,
+                                            C.byref(n)))
         return out
 
     # -- host exports --------------------------------------------------------
