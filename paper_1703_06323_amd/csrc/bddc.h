@@ -40,9 +40,10 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
 // Rows [r0, r0 + nrows) of Y = A_omega X (FP64, nt x NCp blocks).
 void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y,
                         int r0, int nrows);
-// G = K_S^{-1} C^T and S_c = C G with C the object-mean constraints.
-void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* G);
-void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* G, double* Sc);
+// Gt = (K_S^{-1} C^T)^T (NCp x NGp) and S_c = C G with C the object-mean
+// constraints.
+void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt);
+void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* Gt, double* Sc);
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info);
 // Coarse matrix of every problem p as its own ldc_p x ldc_p block at
 // Ac + ac_off_p (identity on the padding rows); prow_off[p] = first padded
@@ -59,6 +60,11 @@ inline int packed_elems(int n) { return (n / SB) * (n / SB + 1) / 2 * SB * SB; }
 template <typename TI, typename TO>
 void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,
                        int64_t sD, TO* out);
+// Packed Kt = K_S^{-1} - Phi G^T from K_S^{-1} (NGp x NGp, lower triangle
+// read), Phi (NGp x NCp) and Gt (NCp x NGp), per subdomain.
+template <typename TO>
+void launch_pack_interface(hipStream_t st, int NGp, int NCp, int ns, const double* KS, const double* Phi,
+                           const double* Gt, TO* out);
 // P, Kt: packed storage.
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,

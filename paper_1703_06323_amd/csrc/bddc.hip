@@ -28,121 +28,168 @@ namespace {
 
 __constant__ double c_Kref_b[64];
 
-// Kernel 1: per subdomain, unscaled diagonal of A_omega, rho per coarse
-// object, Jacobi scaling, and the scaled padded matrix K.
+__device__ inline void object_members(const SubDev& sd, int w, int* ptr, int* mem);
+
+// The s^3 cells of block (Bx, By, Bz) into LDS: cell info and kappa h (0 on
+// inactive cells), indexed cx + s (cy + s cz).  Caller synchronises.
+__device__ inline void load_block_cells(const GridDev& g, const ProbDev& pr, int Bx, int By, int Bz, int* cinfo,
+                                        double* ckh) {
+  const int s = g.s, n = s * s * s;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int cx = e % s, cy = (e / s) % s, cz = e / (s * s);
+    const int64_t c = (int64_t)(Bx * s + cx) + (int64_t)pr.N * ((By * s + cy) + (int64_t)pr.N * (Bz * s + cz));
+    const int32_t info = g.cellinfo[pr.cell_off + c];
+    cinfo[e] = info;
+    ckh[e] = info == CELL_INACTIVE ? 0.0 : g.kappa[pr.cell_off + c] * pr.h;
+  }
+}
+
+// Kernel 1: per subdomain, the unscaled diagonal of A_omega, rho per coarse
+// object, the Jacobi scaling, and the scaled padded matrix
+// K = D (A_omega + C^T R C) D (identity on padding rows).  The diagonal and
+// rho come first (one thread per row / object); then each wave builds whole
+// rows in LDS: 27 lanes each sum one neighbour of the row's node over the
+// cells around it (fixed order), lanes over the object's slots add the
+// C^T R C term, and the row is written out with coalesced stores.
 template <typename T>
-__global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat,
-                                                             double* diagA_G, double* Dscale) {
+__global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat, double* diagA_G,
+                                                             double* Dscale) {
   extern __shared__ double smem[];
   const int w = blockIdx.x;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
+  const int s = g.s, s3 = s * s * s;
   double* diag = smem;              // [nt]
-  double* Ds = smem + nt;           // [nt]
-  double* rho = smem + 2 * nt;      // [NCp]
-  double* cnt = rho + NCp;          // [NCp]
+  double* Ds = diag + nt;           // [nt]
+  double* rho = Ds + nt;            // [NCp]: rho_t / |t|^2
+  double* ckh = rho + NCp;          // [s^3]: kappa h per block cell
+  int* optr = reinterpret_cast<int*>(ckh + s3);    // [NCp + 1]
+  int* omem = optr + NCp + 1;                      // [NGp]
+  int* cinfo = omem + NGp;                         // [s^3]
+  T* rows = reinterpret_cast<T*>(ckh + s3 + (NCp + 1 + NGp + s3 + 1) / 2);   // [4][nt]
   const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
   const ProbDev pr = g.prob[sd.sub_prob[w]];
-  const int s = g.s, m = pr.m, N = pr.N;
+  const int m = pr.m, N1 = pr.N + 1;
   const int blk = sd.sub_blk[w];
   const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
-  const int64_t N1 = N + 1;
   const int s1 = s + 1;
   const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
-  const int32_t* cellinfo = g.cellinfo + pr.cell_off;
-  const double* kappa = g.kappa + pr.cell_off;
-  const double h = pr.h;
+  const int* gobj = sd.G_obj + (int64_t)w * NGp;
   T* K = Kmat + (int64_t)w * nt * nt;
   const int tid = threadIdx.x;
+  load_block_cells(g, pr, Bx, By, Bz, cinfo, ckh);
+  __syncthreads();
 
-  // node of a local row, numbered within the problem's grid
-  auto row_node = [&](int r) -> int64_t {
-    if (r < NIp) return r < nI ? sd.I_idx[(int64_t)w * NIp + r] - pr.node_off : -1;
-    const int j = r - NIp;
-    return j < nG ? sd.G_idx[(int64_t)w * NGp + j] - pr.node_off : -1;
+  // local block coordinates of the node of row r (false for padding rows)
+  auto row_xyz = [&](int r, int& lx, int& ly, int& lz) -> bool {
+    int64_t n;
+    if (r < NIp) {
+      if (r >= nI) return false;
+      n = sd.I_idx[(int64_t)w * NIp + r];
+    } else {
+      if (r - NIp >= nG) return false;
+      n = sd.G_idx[(int64_t)w * NGp + (r - NIp)];
+    }
+    const int l = (int)(n - pr.node_off);
+    lx = l % N1 - Bx * s;
+    ly = (l / N1) % N1 - By * s;
+    lz = l / (N1 * N1) - Bz * s;
+    return true;
   };
   // phase 0: diagonal of A_omega
   for (int r = tid; r < nt; r += 256) {
-    const int64_t n = row_node(r);
+    int lx, ly, lz;
     double d = 0.0;
-    if (n >= 0) {
-      const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
-      const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
+    if (row_xyz(r, lx, ly, lz)) {
       for (int u = 0; u < 8; ++u) {
         const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
         if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-        const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-        const int32_t info = cellinfo[c];
+        const int lc = cx + s * (cy + s * cz);
+        const int32_t info = cinfo[lc];
         if (info == CELL_INACTIVE) continue;
         const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
         const double kaa = info == CELL_UNCUT ? c_Kref_b[a * 9] : g.Kc[(int64_t)info * PACK36 + pack_index(a, a)];
-        d += kappa[c] * h * kaa;
+        d += ckh[lc] * kaa;
       }
     }
     diag[r] = d;
     if (r >= NIp) diagA_G[(int64_t)w * NGp + (r - NIp)] = d;
   }
-  __syncthreads();
-  // phase 1: rho_t = sum of the diagonal over object t, |t|
+  object_members(sd, w, optr, omem);   // ends with a barrier
+  // phase 1: rho_t / |t|^2 with rho_t the sum of the diagonal over object t
   for (int t = tid; t < NCp; t += 256) {
-    double sr = 0.0, sc = 0.0;
-    if (t < nC)
-      for (int j = 0; j < nG; ++j)
-        if (sd.G_obj[(int64_t)w * NGp + j] == t) {
-          sr += diag[NIp + j];
-          sc += 1.0;
-        }
-    rho[t] = sr;
-    cnt[t] = sc;
+    double sr = 0.0;
+    const int b0 = optr[t], b1 = optr[t + 1];
+    for (int q = b0; q < b1; ++q) sr += diag[NIp + omem[q]];
+    rho[t] = (t < nC && b1 > b0) ? sr / ((double)(b1 - b0) * (double)(b1 - b0)) : 0.0;
   }
   __syncthreads();
   for (int r = tid; r < nt; r += 256) {
-    const int64_t n = row_node(r);
+    int lx, ly, lz;
+    const bool real = row_xyz(r, lx, ly, lz);
     double dk = diag[r];
-    if (r >= NIp && n >= 0) {
-      const int t = sd.G_obj[(int64_t)w * NGp + (r - NIp)];
-      if (t >= 0) dk += rho[t] / (cnt[t] * cnt[t]);
+    if (r >= NIp && real) {
+      const int t = gobj[r - NIp];
+      if (t >= 0) dk += rho[t];
     }
-    Ds[r] = n >= 0 ? 1.0 / sqrt(dk) : 1.0;
+    Ds[r] = real ? 1.0 / sqrt(dk) : 1.0;
     Dscale[(int64_t)w * nt + r] = Ds[r];
   }
   __syncthreads();
-  // phase 2: zero, then write scaled entries (row r owned by one thread)
-  for (int64_t e = tid; e < (int64_t)nt * nt; e += 256) K[e] = T(0);
-  __syncthreads();
-  for (int r = tid; r < nt; r += 256) {
-    const int64_t n = row_node(r);
+  // phase 2: rows, one wave per row
+  const int lane = tid & 63, wv = tid >> 6;
+  T* rb = rows + wv * nt;
+  for (int r = wv; r < nt; r += 4) {
+    for (int c = lane; c < nt; c += 64) rb[c] = T(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int lx, ly, lz;
+    if (!row_xyz(r, lx, ly, lz)) {
+      if (lane == 0) rb[r] = T(1);
+    } else {
+      if (lane < 27) {
+        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+        const int bx = lx + dx, by = ly + dy, bz = lz + dz;
+        int col = -1;
+        if (bx >= 0 && by >= 0 && bz >= 0 && bx <= s && by <= s && bz <= s) col = loc[bx + s1 * (by + s1 * bz)];
+        if (col >= 0) {
+          double v = 0.0;
+          for (int u = 0; u < 8; ++u) {
+            const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+            if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+            // the neighbour must be a corner of this cell too
+            const int ox = bx - cx, oy = by - cy, oz = bz - cz;
+            if (ox < 0 || ox > 1 || oy < 0 || oy > 1 || oz < 0 || oz > 1) continue;
+            const int lc = cx + s * (cy + s * cz);
+            const int32_t info = cinfo[lc];
+            if (info == CELL_INACTIVE) continue;
+            const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+            const int bb = ox + 2 * oy + 4 * oz;
+            const double kab = info == CELL_UNCUT ? c_Kref_b[a * 8 + bb]
+                                                  : g.Kc[(int64_t)info * PACK36 + pack_index(a, bb)];
+            v += ckh[lc] * kab;
+          }
+          rb[col] = (T)(v * Ds[r] * Ds[col]);
+        }
+      }
+      if (r >= NIp) {
+        const int t = gobj[r - NIp];
+        if (t >= 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const double add = rho[t] * Ds[r];
+          for (int q = optr[t] + lane; q < optr[t + 1]; q += 64) {
+            const int col = NIp + omem[q];
+            rb[col] = (T)((double)rb[col] + add * Ds[col]);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     T* Kr = K + (int64_t)r * nt;
-    if (n < 0) {
-      Kr[r] = T(1);
-      continue;
-    }
-    const int64_t I = n % N1, J = (n / N1) % N1, Kk = n / (N1 * N1);
-    const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(Kk - (int64_t)Bz * s);
-    for (int u = 0; u < 8; ++u) {
-      const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
-      if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-      const int64_t c = ((int64_t)Bx * s + cx) + N * (((int64_t)By * s + cy) + (int64_t)N * ((int64_t)Bz * s + cz));
-      const int32_t info = cellinfo[c];
-      if (info == CELL_INACTIVE) continue;
-      const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-      const double sc = kappa[c] * h;
-      for (int b = 0; b < 8; ++b) {
-        const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
-        const int col = loc[bx + s1 * (by + s1 * bz)];
-        if (col < 0) continue;
-        const double kab = info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
-        Kr[col] = (T)((double)Kr[col] + sc * kab * Ds[r] * Ds[col]);
-      }
-    }
-    if (r >= NIp) {
-      const int t = sd.G_obj[(int64_t)w * NGp + (r - NIp)];
-      if (t >= 0) {
-        const double add = rho[t] / (cnt[t] * cnt[t]);
-        for (int j = 0; j < nG; ++j)
-          if (sd.G_obj[(int64_t)w * NGp + j] == t)
-            Kr[NIp + j] = (T)((double)Kr[NIp + j] + add * Ds[r] * Ds[NIp + j]);
-      }
-    }
+    for (int c = lane; c < nt; c += 64) Kr[c] = rb[c];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -174,10 +221,20 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
                                                           double* __restrict__ Y, int r0, int nrows) {
   __shared__ double sval[LA_ROWS][27];
   __shared__ int scol[LA_ROWS][27];
+  extern __shared__ double la_cells[];   // [s^3] kappa h, then [s^3] cell info
   const int w = blockIdx.y;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
   const int rb = r0 + blockIdx.x * LA_ROWS;
   const int tid = threadIdx.x;
+  const int s3 = g.s * g.s * g.s;
+  double* ckh = la_cells;
+  int* cinfo = reinterpret_cast<int*>(la_cells + s3);
+  {
+    const ProbDev pr = g.prob[sd.sub_prob[w]];
+    const int blk = sd.sub_blk[w], m = pr.m;
+    load_block_cells(g, pr, blk % m, (blk / m) % m, blk / (m * m), cinfo, ckh);
+  }
+  __syncthreads();
   if (tid < LA_ROWS) {
     for (int k = 0; k < 27; ++k) {
       sval[tid][k] = 0.0;
@@ -196,19 +253,17 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
       const int blk = sd.sub_blk[w];
       const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
       const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
-      const int32_t* cellinfo = g.cellinfo + pr.cell_off;
-      const double* kappa = g.kappa + pr.cell_off;
       const int l = (int)(n - pr.node_off);
       const int I = l % N1, J = (l / N1) % N1, Kk = l / (N1 * N1);
       const int lx = I - Bx * s, ly = J - By * s, lz = Kk - Bz * s;
       for (int u = 0; u < 8; ++u) {
         const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
         if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-        const int64_t c = (int64_t)(Bx * s + cx) + (int64_t)N * ((By * s + cy) + (int64_t)N * (Bz * s + cz));
-        const int32_t info = cellinfo[c];
+        const int lc = cx + s * (cy + s * cz);
+        const int32_t info = cinfo[lc];
         if (info == CELL_INACTIVE) continue;
         const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-        const double sc = kappa[c] * pr.h;
+        const double sc = ckh[lc];
         for (int b = 0; b < 8; ++b) {
           const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
           const int col = loc[bx + s1 * (by + s1 * bz)];
@@ -263,12 +318,14 @@ __device__ inline void object_members(const SubDev& sd, int w, int* ptr, int* me
   __syncthreads();
 }
 
-// Kernel 3c: G = K_S^{-1} C^T without forming C: column t of G is the mean
-// of the columns of K_S^{-1} over the slots of object t.  One block per
-// (CC_ROWS-row chunk, subdomain); G is NGp x NCp, K_S^{-1} NGp x NGp.
-constexpr int CC_ROWS = 64;
+// Kernel 3c: Gt = (K_S^{-1} C^T)^T without forming C: since K_S^{-1} is
+// symmetric, row t of Gt is the mean of the rows of K_S^{-1} over the slots
+// of object t, so every row of K_S^{-1} is read once and coalesced.  One
+// block per (CC_COLS-column chunk, subdomain); Gt is NCp x NGp.
+constexpr int CC_COLS = 256;
+__device__ inline int packed_offset(int r, int c, int vw);
 __global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const double* __restrict__ KS,
-                                                              double* __restrict__ G) {
+                                                              double* __restrict__ Gt) {
   extern __shared__ int smem_i[];
   const int w = blockIdx.y;
   const int NGp = sd.NGp, NCp = sd.NCp;
@@ -276,22 +333,20 @@ __global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const d
   int* mem = smem_i + NCp + 1;
   object_members(sd, w, ptr, mem);
   const double* ks = KS + (int64_t)w * NGp * NGp;
-  double* gw = G + (int64_t)w * NGp * NCp;
-  const int rb = blockIdx.x * CC_ROWS;
-  const int R = min(CC_ROWS, NGp - rb);
-  for (int e = threadIdx.x; e < R * NCp; e += 256) {
-    const int rr = e / NCp, t = e - rr * NCp;
-    const double* row = ks + (int64_t)(rb + rr) * NGp;
+  double* gt = Gt + (int64_t)w * NCp * NGp;
+  const int i = blockIdx.x * CC_COLS + threadIdx.x;
+  if (i >= NGp) return;
+  for (int t = 0; t < NCp; ++t) {
     const int b = ptr[t], en = ptr[t + 1];
     double acc = 0.0;
-    for (int q = b; q < en; ++q) acc += row[mem[q]];
-    gw[(int64_t)(rb + rr) * NCp + t] = en > b ? acc / (double)(en - b) : 0.0;
+    for (int q = b; q < en; ++q) acc += ks[(int64_t)mem[q] * NGp + i];
+    gt[(int64_t)t * NGp + i] = en > b ? acc / (double)(en - b) : 0.0;
   }
 }
 
-// Kernel 3d: S_c = C G: row t of S_c is the mean of the rows of G over the
-// slots of object t (NCp x NCp per subdomain).
-__global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const double* __restrict__ G,
+// Kernel 3d: S_c = C G: S_c[t][u] is the mean of Gt[u][j] over the slots j
+// of object t (NCp x NCp per subdomain).
+__global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const double* __restrict__ Gt,
                                                               double* __restrict__ Sc) {
   extern __shared__ int smem_i[];
   const int w = blockIdx.x;
@@ -299,14 +354,65 @@ __global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const d
   int* ptr = smem_i;
   int* mem = smem_i + NCp + 1;
   object_members(sd, w, ptr, mem);
-  const double* gw = G + (int64_t)w * NGp * NCp;
+  const double* gt = Gt + (int64_t)w * NCp * NGp;
   double* sc = Sc + (int64_t)w * NCp * NCp;
   for (int e = threadIdx.x; e < NCp * NCp; e += 256) {
     const int t = e / NCp, u = e - t * NCp;
     const int b = ptr[t], en = ptr[t + 1];
     double acc = 0.0;
-    for (int q = b; q < en; ++q) acc += gw[(int64_t)mem[q] * NCp + u];
+    for (int q = b; q < en; ++q) acc += gt[(int64_t)u * NGp + mem[q]];
     sc[e] = en > b ? acc / (double)(en - b) : 0.0;
+  }
+}
+
+// Kernel 3f: the constrained-Neumann interface operator
+// Kt = K_S^{-1} - Phi G^T written straight into packed symmetric storage
+// (type TO).  One block per (packed block, subdomain): the 32 rows of Phi
+// and the 32 columns of G^T of the block are staged in LDS; thread t forms
+// column t % 32 of rows t / 32 + 8k (k < 4), sharing each G value over four
+// rows.  The block goes through an LDS tile so that the upper part of a
+// diagonal block is the mirror of its lower part (exact symmetry).
+template <typename TO>
+__global__ __launch_bounds__(256) void pack_interface_kernel(const double* __restrict__ KS, const double* __restrict__ Phi,
+                                                             const double* __restrict__ Gt, int NGp, int NCp,
+                                                             TO* __restrict__ out, int nbk) {
+  constexpr int VW = 16 / sizeof(TO);
+  extern __shared__ double lds_pk[];
+  const int64_t w = blockIdx.y;
+  const int q = blockIdx.x;
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= q) ++I;
+  const int J = q - I * (I + 1) / 2;
+  double* phiI = lds_pk;             // [SB][NCp] rows 32I.. of Phi
+  double* gJ = phiI + SB * NCp;      // [NCp][SB] columns 32J.. of Gt
+  double* tile = gJ + NCp * SB;      // [SB][SB + 1]
+  const double* ph = Phi + w * NGp * NCp;
+  const double* gt = Gt + w * NCp * NGp;
+  for (int e = threadIdx.x; e < SB * NCp; e += 256) {
+    phiI[e] = ph[(int64_t)SB * I * NCp + e];
+    const int tt = e / SB, c = e - tt * SB;
+    gJ[e] = gt[(int64_t)tt * NGp + SB * J + c];
+  }
+  __syncthreads();
+  const double* ks = KS + w * NGp * NGp;
+  const int c = threadIdx.x & (SB - 1), r0 = threadIdx.x >> 5;
+  double acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = ks[(int64_t)(SB * I + r0 + 8 * k) * NGp + SB * J + c];
+#pragma unroll 4
+  for (int t = 0; t < NCp; ++t) {
+    const double gv = gJ[t * SB + c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] -= phiI[(r0 + 8 * k) * NCp + t] * gv;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tile[(r0 + 8 * k) * (SB + 1) + c] = acc[k];
+  __syncthreads();
+  TO* o = out + (w * nbk + q) * (int64_t)(SB * SB);
+  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+    const int r = e / SB, cc = e - r * SB;
+    const double v = (I != J || cc <= r) ? tile[r * (SB + 1) + cc] : tile[cc * (SB + 1) + r];
+    o[packed_offset(r, cc, VW)] = (TO)v;
   }
 }
 
@@ -645,7 +751,9 @@ template <typename T>
 void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
                            double* diagA_G, double* Dscale) {
   const int nt = sd.NIp + sd.NGp;
-  const size_t sh = (size_t)(2 * nt + 2 * sd.NCp) * sizeof(double);
+  const int s3 = g.s * g.s * g.s;
+  const size_t sh = (size_t)(2 * nt + sd.NCp + s3 + (sd.NCp + 1 + sd.NGp + s3 + 1) / 2) * sizeof(double) +
+                    (size_t)4 * nt * sizeof(T);
   hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(256), sh, st, sd, g, K, diagA_G, Dscale);
 }
 template void launch_assemble_local<double>(hipStream_t, const SubDev&, const GridDev&, int, double*,
@@ -664,21 +772,37 @@ void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int 
                         int r0, int nrows) {
   if (nrows <= 0 || ns <= 0) return;
   dim3 grid((nrows + LA_ROWS - 1) / LA_ROWS, ns);
-  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, g, X, Y, r0, nrows);
+  const size_t sh = (size_t)g.s * g.s * g.s * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), sh, st, sd, g, X, Y, r0, nrows);
 }
 
-void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* G) {
+inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
+
+void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt) {
   if (ns <= 0) return;
-  dim3 grid((sd.NGp + CC_ROWS - 1) / CC_ROWS, ns);
+  dim3 grid((sd.NGp + CC_COLS - 1) / CC_COLS, ns);
   hipLaunchKernelGGL(constraint_cols_kernel, grid, dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st, sd,
-                     KS, G);
+                     KS, Gt);
 }
 
-void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* G, double* Sc) {
+void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* Gt, double* Sc) {
   if (ns <= 0) return;
   hipLaunchKernelGGL(constraint_rows_kernel, dim3(ns), dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st,
-                     sd, G, Sc);
+                     sd, Gt, Sc);
 }
+
+template <typename TO>
+void launch_pack_interface(hipStream_t st, int NGp, int NCp, int ns, const double* KS, const double* Phi,
+                           const double* Gt, TO* out) {
+  if (ns <= 0) return;
+  const size_t sh = (size_t)(2 * SB * NCp + SB * (SB + 1)) * sizeof(double);
+  hipLaunchKernelGGL(pack_interface_kernel<TO>, dim3(packed_blocks(NGp), ns), dim3(256), sh, st, KS, Phi, Gt, NGp,
+                     NCp, out, packed_blocks(NGp));
+}
+template void launch_pack_interface<float>(hipStream_t, int, int, int, const double*, const double*, const double*,
+                                           float*);
+template void launch_pack_interface<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
+                                            double*);
 
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info) {
   hipLaunchKernelGGL(small_spd_inverse_kernel, dim3(ns), dim3(256), (size_t)sd.NCp * sd.NCp * sizeof(double), st,
@@ -692,8 +816,6 @@ void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* pr
   hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)((n_prows + 63) / 64)), dim3(64), 0, st, b, prow_off,
                      n_prows, cs_ptr, cs_sub, cs_row, sd, AcLoc, Ac);
 }
-
-inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
 
 template <typename TI, typename TO>
 void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,

@@ -1193,7 +1193,7 @@ int factor_impl(cb_ctx* c) {
     launch_constraint_cols(st, sd, nc, KS, G.as<double>());
     launch_constraint_rows(st, sd, nc, G.as<double>(), Sc.as<double>());
     launch_small_spd_inverse(st, sd, nc, Sc.as<double>(), c->info_d.as<int>() + ns);
-    gemm<double>(st, 0, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NCp, sG, Sc.as<double>(), NCp, sC, 0.0, Phiw, NCp,
+    gemm<double>(st, 1, 0, NGp, NCp, NCp, 1.0, G.as<double>(), NGp, sG, Sc.as<double>(), NCp, sC, 0.0, Phiw, NCp,
                  sG, nc, 0);
     HIPCHK(hipGetLastError());
     // full coarse basis Phi = [Phi_I; Phi_G] with Phi_I = -A_II^{-1} A_IG Phi_G,
@@ -1211,9 +1211,8 @@ int factor_impl(cb_ctx* c) {
     gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
                  V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
                  nc, 0);
-    // Kt = K_S^{-1} - Phi G^T
-    gemm<double>(st, 0, 1, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NCp, sG, 1.0, KS, NGp, sKS, nc, 0);
-    launch_pack_lower<double, T>(st, NGp, nc, KS, NGp, sKS, nullptr, 0, c->Kt.as<T>() + (int64_t)w0 * pkG);
+    // Kt = K_S^{-1} - Phi G^T, packed
+    launch_pack_interface<T>(st, NGp, NCp, nc, KS, Phiw, G.as<double>(), c->Kt.as<T>() + (int64_t)w0 * pkG);
     HIPCHK(hipGetLastError());
   }
   for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();

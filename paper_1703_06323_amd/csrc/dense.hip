@@ -264,34 +264,42 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
 }
 
 // Factors the b x b diagonal block (b <= DB) at (k0, k0) of every matrix and
-// inverts the factor, with 256 threads.  The block is split into 8 x 8
-// tiles; each of the 136 lower tiles lives in the registers of one thread.
-// Right-looking Cholesky, one column j per step: the owner of the diagonal
-// tile takes the pivot, the owners of tile column j/8 scale column j and
-// publish it in LDS, and every thread updates its tile (64 independent
-// FMAs).  The step loop is unrolled by 8 so that every register index is
-// static.  Rows and columns beyond b are identity.  L is then kept in LDS and
-// L^{-1} is formed in the same registers by forward elimination on
-// L X = I (row j of X scaled and published, rows below updated).  Writes L
-// back (upper part of the block zeroed) and L^{-1} (zero above the
+// inverts the factor, in one pass.  The block is split into 8 x 8 tiles; the
+// 136 lower tiles of L live in the registers of waves 0-2 (one tile per
+// thread) and the 136 lower tiles of X = L^{-1} in waves 3-5, so no wave
+// holds both kinds.  Step j (right-looking Cholesky and forward elimination
+// on L X = I, both driven by column j of L):
+//   1. the owner of the diagonal tile takes the pivot L_jj;
+//   2. the owners of tile column j/8 of L scale column j and publish it in
+//      LDS; the owners of tile row j/8 of X scale row j of X by 1 / L_jj and
+//      publish it;
+//   3. every L tile gets the rank-1 update with column j, and every X tile
+//      below row j subtracts L_ij X_j.
+// The published vectors are zero outside the rows (columns) they cover, so
+// the updates need no element tests.  The step loop is unrolled by 8 so that
+// every register index is static.  Rows and columns beyond b are identity.
+// Writes L back (upper part of the block zeroed) and L^{-1} (zero above the
 // diagonal) to the DB x DB block `blk` of Linv[bz].  A non-positive or
 // non-finite pivot sets info[bz] (first failing global row + 1) and is
 // replaced by 1.
+constexpr int DF_THREADS = 384;
 template <typename T>
-__global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int64_t sA, int k0, int b, T* Linv,
-                                                          int64_t sL, int blk, int* info) {
-  constexpr int TS = 8, NT = DB / TS, NLT = NT * (NT + 1) / 2;
-  __shared__ T S[DB][DB + 1];
-  __shared__ T vec[DB];
+__global__ __launch_bounds__(DF_THREADS) void diag_factor_kernel(T* A, int64_t lda, int64_t sA, int k0, int b,
+                                                                 T* Linv, int64_t sL, int blk, int* info) {
+  constexpr int TS = 8, NT = DB / TS, NLT = NT * (NT + 1) / 2, XOFF = 192;
+  __shared__ T vec[DB];    // column j of L below the diagonal, zero elsewhere
+  __shared__ T vecx[DB];   // row j of X up to the diagonal, zero elsewhere
   __shared__ T pinv;
   __shared__ int bad;
   const int64_t bz = blockIdx.x;
   T* a = A + bz * sA + (int64_t)k0 * lda + k0;
   const int t = threadIdx.x;
-  // lower tile (I, C), I >= C, of this thread: t = I (I + 1) / 2 + C
+  const bool isL = t < NLT;
+  const bool isX = t >= XOFF && t < XOFF + NLT;
+  // lower tile (I, C), I >= C, of this thread: index = I (I + 1) / 2 + C
   int I = -1, C = -1;
-  if (t < NLT) {
-    int q = t, r = 0;
+  if (isL || isX) {
+    int q = isL ? t : t - XOFF, r = 0;
     while (q > r) {
       q -= r + 1;
       ++r;
@@ -301,7 +309,7 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
   }
   if (t == 0) bad = 0;
   T r[TS][TS];
-  if (I >= 0) {
+  if (isL) {
 #pragma unroll
     for (int rr = 0; rr < TS; ++rr)
 #pragma unroll
@@ -309,6 +317,11 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
         const int row = TS * I + rr, col = TS * C + cc;
         r[rr][cc] = (row < b && col < b) ? a[(int64_t)row * lda + col] : (row == col ? T(1) : T(0));
       }
+  } else if (isX) {
+#pragma unroll
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) r[rr][cc] = (TS * I + rr == TS * C + cc) ? T(1) : T(0);
   }
   __syncthreads();
   const int nJ = (b + TS - 1) / TS;
@@ -317,7 +330,7 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
     for (int jj = 0; jj < TS; ++jj) {
       const int j = TS * J + jj;
       if (j >= b) break;
-      if (I == J && C == J) {
+      if (isL && I == J && C == J) {
         T d = r[jj][jj];
         if (!(d > T(0)) || !(d < T(3.0e38))) {
           if (bad == 0) bad = k0 + j + 1;
@@ -328,19 +341,24 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
         pinv = T(1) / d;
       }
       __syncthreads();
-      if (C == J && I >= J) {
-        const T inv = pinv;
+      const T inv = pinv;
+      if (isL && C == J) {
 #pragma unroll
         for (int rr = 0; rr < TS; ++rr) {
           const int row = TS * I + rr;
           if (row > j) r[rr][jj] *= inv;
           vec[row] = row > j ? r[rr][jj] : T(0);
         }
+      } else if (isX && I == J) {
+#pragma unroll
+        for (int cc = 0; cc < TS; ++cc) {
+          const int col = TS * C + cc;
+          if (col <= j) r[jj][cc] *= inv;
+          vecx[col] = col <= j ? r[jj][cc] : T(0);
+        }
       }
       __syncthreads();
-      // rank-1 update; vec is zero on rows <= j, so no element needs a test
-      // (entries above the diagonal of diagonal tiles are discarded later)
-      if (I >= J && C >= J) {
+      if (isL && C >= J) {
         T li[TS], lc[TS];
 #pragma unroll
         for (int q = 0; q < TS; ++q) {
@@ -351,69 +369,31 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
         for (int rr = 0; rr < TS; ++rr)
 #pragma unroll
           for (int cc = 0; cc < TS; ++cc) r[rr][cc] = fma(-li[rr], lc[cc], r[rr][cc]);
-      }
-    }
-  }
-  // L back to memory and into LDS; upper part of the block zeroed
-  if (I >= 0) {
-#pragma unroll
-    for (int rr = 0; rr < TS; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < TS; ++cc) {
-        const int row = TS * I + rr, col = TS * C + cc;
-        const T v = col <= row ? r[rr][cc] : T(0);
-        S[row][col] = v;
-        if (row < b && col < b) a[(int64_t)row * lda + col] = v;
-      }
-  }
-  for (int e = t; e < b * b; e += 256) {
-    const int row = e / b, col = e - row * b;
-    if (col / TS > row / TS) a[(int64_t)row * lda + col] = T(0);
-  }
-  __syncthreads();
-  // X = L^{-1}: X = I, then for each j: X[j, :] /= L[j][j]; rows below
-  // X[i, :] -= L[i][j] X[j, :]
-  if (I >= 0) {
-#pragma unroll
-    for (int rr = 0; rr < TS; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < TS; ++cc) r[rr][cc] = (TS * I + rr == TS * C + cc) ? T(1) : T(0);
-  }
-  for (int J = 0; J < nJ; ++J) {
-#pragma unroll
-    for (int jj = 0; jj < TS; ++jj) {
-      const int j = TS * J + jj;
-      if (j >= b) break;
-      if (I == J) {
-        const T inv = T(1) / S[j][j];
-#pragma unroll
-        for (int cc = 0; cc < TS; ++cc) {
-          const int col = TS * C + cc;
-          if (col <= j) r[jj][cc] *= inv;
-          vec[col] = col <= j ? r[jj][cc] : T(0);
-        }
-      }
-      __syncthreads();
-      // rows below j: L (in S) is zero above the diagonal and vec is zero on
-      // columns > j, so only row j itself must be excluded
-      if (I >= J && C <= J && I >= 0) {
+      } else if (isX && I >= J && C <= J) {
         T lr[TS], xc[TS];
 #pragma unroll
         for (int q = 0; q < TS; ++q) {
-          lr[q] = S[TS * I + q][j];
-          xc[q] = vec[TS * C + q];
+          lr[q] = vec[TS * I + q];
+          xc[q] = vecx[TS * C + q];
         }
-        if (I == J) lr[jj] = T(0);
 #pragma unroll
         for (int rr = 0; rr < TS; ++rr)
 #pragma unroll
           for (int cc = 0; cc < TS; ++cc) r[rr][cc] = fma(-lr[rr], xc[cc], r[rr][cc]);
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
   T* li = Linv + bz * sL + (int64_t)blk * DB * DB;
-  if (I >= 0) {
+  if (isL) {
+#pragma unroll
+    for (int rr = 0; rr < TS; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < TS; ++cc) {
+        const int row = TS * I + rr, col = TS * C + cc;
+        if (row < b && col < b) a[(int64_t)row * lda + col] = col <= row ? r[rr][cc] : T(0);
+      }
+  } else if (isX) {
 #pragma unroll
     for (int rr = 0; rr < TS; ++rr)
 #pragma unroll
@@ -422,9 +402,13 @@ __global__ __launch_bounds__(256) void diag_factor_kernel(T* A, int64_t lda, int
         li[row * DB + col] = (row < b && col < b && col <= row) ? r[rr][cc] : T(0);
       }
   }
-  for (int e = t; e < DB * DB; e += 256) {
+  // upper tiles: zero in the block of A and in the inverse
+  for (int e = t; e < DB * DB; e += DF_THREADS) {
     const int row = e / DB, col = e - row * DB;
-    if (col / TS > row / TS) li[e] = T(0);
+    if (col / TS > row / TS) {
+      li[e] = T(0);
+      if (row < b && col < b) a[(int64_t)row * lda + col] = T(0);
+    }
   }
   if (t == 0 && bad && info && info[bz] == 0) info[bz] = bad;
 }
@@ -471,6 +455,40 @@ __global__ __launch_bounds__(256) void symmetrize_scale_kernel(const T* in, int6
   for (int c = threadIdx.x; c < nb; c += 256) {
     const T v = (c <= r) ? x[(int64_t)r * ldi + c] : x[(int64_t)c * ldi + r];
     o[(int64_t)r * ldo + c] = (TO)((double)v * d[r] * d[c]);
+  }
+}
+
+// The same for nb a multiple of 32, by 32 x 32 tiles: the lower tile (I, J)
+// is read once (coalesced) into LDS and written to (I, J) and, transposed,
+// to (J, I), both coalesced.  One block per lower tile.
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void symmetrize_scale_tiled_kernel(const T* in, int64_t ldi, int64_t sI,
+                                                                     TO* out, int64_t ldo, int64_t sO,
+                                                                     const double* D, int64_t sD) {
+  __shared__ double tile[32][33];
+  const int64_t bz = blockIdx.y;
+  const int q = blockIdx.x;
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= q) ++I;
+  const int J = q - I * (I + 1) / 2;
+  const T* x = in + bz * sI;
+  TO* o = out + bz * sO;
+  const double* d = D + bz * sD;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    tile[r][c] = (double)x[(int64_t)(32 * I + r) * ldi + 32 * J + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    const int i = 32 * I + r, j = 32 * J + c;
+    const double v = (I != J || c <= r) ? tile[r][c] : tile[c][r];
+    o[(int64_t)i * ldo + j] = (TO)(v * d[i] * d[j]);
+    if (I != J) {
+      // element (32 J + r, 32 I + c) of the upper tile = tile[c][r]
+      const int i2 = 32 * J + r, j2 = 32 * I + c;
+      o[(int64_t)i2 * ldo + j2] = (TO)(tile[c][r] * d[i2] * d[j2]);
+    }
   }
 }
 
@@ -630,7 +648,7 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
     const int lim = (split > 0 && K0 < split) ? split : n;
     const int b = std::min(DB, lim - K0);
     const int K1 = K0 + b;
-    hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(256), 0, st, A, lda, sA, K0, b, Linv, sL,
+    hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(DF_THREADS), 0, st, A, lda, sA, K0, b, Linv, sL,
                        diag_block_index(K0, split), info);
     const int rest = n - K1;
     if (rest > 0) {
@@ -681,6 +699,12 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
 template <typename T, typename TO>
 void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* out, int64_t ldo,
                       int64_t sO, const double* D, int64_t sD, int nb, int batch) {
+  if (nb % 32 == 0) {
+    const int nt = nb / 32;
+    hipLaunchKernelGGL((symmetrize_scale_tiled_kernel<T, TO>), dim3(nt * (nt + 1) / 2, batch), dim3(256), 0, st, in,
+                       ldi, sI, out, ldo, sO, D, sD);
+    return;
+  }
   hipLaunchKernelGGL((symmetrize_scale_kernel<T, TO>), dim3(nb, batch), dim3(256), 0, st, in, ldi,
                      sI, out, ldo, sO, D, sD, nb);
 }
