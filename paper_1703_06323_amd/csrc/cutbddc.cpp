@@ -22,6 +22,7 @@
 #include "bddc.h"
 #include "common.h"
 #include "dense.h"
+#include "indexing.h"
 #include "topology.hpp"
 
 using namespace cutbddc;
@@ -188,21 +189,6 @@ void reference_matrices(const double xi[8], double K[64], double M[64]) {
 
 // Reuse of host indexing storage across contexts (avoids re-faulting the
 // pages of large fresh allocations on every setup).
-std::mutex g_topo_mu;
-std::vector<Topology*> g_topo_pool;
-Topology* take_topology() {
-  std::lock_guard<std::mutex> g(g_topo_mu);
-  if (g_topo_pool.empty()) return new Topology();
-  Topology* t = g_topo_pool.back();
-  g_topo_pool.pop_back();
-  return t;
-}
-void give_topology(Topology* t) {
-  std::lock_guard<std::mutex> g(g_topo_mu);
-  if (g_topo_pool.size() < 4) g_topo_pool.push_back(t);
-  else delete t;
-}
-
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
@@ -240,40 +226,17 @@ struct ProfEntry {
 
 // Host data of one problem of a context.
 struct ProbHost {
-  Geometry geo;
-  Topology* topo = nullptr;
   int N = 0, m = 0, ns = 0;
   double h = 0;
   int nb = 0, ball_off = 0;
-  std::vector<int32_t> count;          // [N^3] kept points per cell
-  std::vector<int64_t> cut_local;      // cut cells with stored matrices (local ids, stored order)
-  int64_t n_active = 0, n_cut = 0;
-  int64_t cell_off = 0, node_off = 0, dof_off = 0, cut_off = 0;
+  int64_t n_active = 0, n_cut = 0, n_cut_stored = 0;
+  int64_t n_dof = 0, n_iface = 0;
+  int32_t n_obj = 0, n_coarse = 0, maxC = 0;
+  int64_t cell_off = 0, node_off = 0, dof_off = 0, cut_off = 0, obj_off = 0;
   int32_t sub_off = 0, coarse_off = 0, ldc = 0, chunk_off = 0;
   int64_t ac_off = 0, prow_off = 0;
   int64_t iface_off = 0;
   cb_info info{};
-  ProbHost() = default;
-  ProbHost(const ProbHost&) = delete;
-  ProbHost& operator=(const ProbHost&) = delete;
-  ProbHost(ProbHost&& o) noexcept { *this = std::move(o); }
-  ProbHost& operator=(ProbHost&& o) noexcept {
-    geo = std::move(o.geo);
-    topo = o.topo;
-    o.topo = nullptr;
-    N = o.N, m = o.m, ns = o.ns, h = o.h, nb = o.nb, ball_off = o.ball_off;
-    count = std::move(o.count);
-    cut_local = std::move(o.cut_local);
-    n_active = o.n_active, n_cut = o.n_cut;
-    cell_off = o.cell_off, node_off = o.node_off, dof_off = o.dof_off, cut_off = o.cut_off;
-    sub_off = o.sub_off, coarse_off = o.coarse_off, ldc = o.ldc, chunk_off = o.chunk_off;
-    ac_off = o.ac_off, prow_off = o.prow_off, iface_off = o.iface_off;
-    info = o.info;
-    return *this;
-  }
-  ~ProbHost() {
-    if (topo) give_topology(topo);
-  }
 };
 
 // Problems of equal padded coarse order, factored as one batch.
@@ -302,7 +265,11 @@ struct cb_ctx {
   int n_fallbacks = 0;
 
   // per-problem device tables
-  DevBuf prob_d, cell_off_d, node_off_d, dof_off_d, chunk_ptr_d, prow_off_d, coarse_prob_d, sub_prob_d, sub_blk_d;
+  DevBuf prob_d, cell_off_d, node_off_d, sub_off_d, dof_off_d, chunk_ptr_d, prow_off_d, coarse_prob_d, sub_prob_d,
+      sub_blk_d;
+  // device indexing work arrays (kept for the index export)
+  DevBuf iwork;
+  IndexWork iw{};
   // grid data (concatenated)
   DevBuf xi_d, balls, kappa, count_d, cellinfo, cut_d, Kc, Mc, dofmask, dof_node;
   // subdomain index data
@@ -409,32 +376,6 @@ template <typename F>
 void timed(cb_ctx* c, const char* name, F&& f) {
   ProfScope ps(c, name);
   f();
-}
-
-// Runs f(p) for every problem on up to indexing_threads() host threads, in
-// the given order; the loops inside f run inline on each thread.
-template <typename F>
-void for_each_problem(const std::vector<int>& order, F&& f) {
-  const int P = (int)order.size();
-  if (P == 1) {
-    f(order[0]);
-    return;
-  }
-  const int nth = std::max(1, std::min(P, indexing_threads()));
-  std::atomic<int> next{0};
-  auto work = [&] {
-    set_serial_indexing(true);
-    for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= P) break;
-      f(order[i]);
-    }
-    set_serial_indexing(false);
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nth; ++t) th.emplace_back(work);
-  work();
-  for (auto& t : th) t.join();
 }
 
 int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked) {
@@ -638,8 +579,9 @@ int validate_problem(const cb_problem* p) {
 
 inline int64_t align_seg(int64_t x) { return ((x + SEG_ALIGN - 1) / SEG_ALIGN) * SEG_ALIGN; }
 
-// Setup of P problems (cell classification and integration on the GPU,
-// indexing on the host, index maps uploaded).
+// Setup of P problems: cell classification, indexing and cut-cell
+// integration on the GPU, with one readback of the per-problem counts (the
+// host sizes the index maps and groups the coarse problems).
 int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   if (!ps || !out || P < 1) return fail(CB_ERR_ARG, "null argument or empty batch");
   *out = nullptr;
@@ -677,7 +619,6 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   int ball_off = 0, sub_off = 0;
   for (int k = 0; k < P; ++k) {
     ProbHost& h = c->pb[k];
-    h.topo = take_topology();
     const int N = ps[k].n_cells;
     h.N = N;
     h.m = N / s;
@@ -688,12 +629,6 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     h.cell_off = cell_off;
     h.node_off = node_off;
     h.sub_off = sub_off;
-    h.geo.N = N;
-    h.geo.s = s;
-    h.geo.objects = ps[k].objects;
-    h.geo.variant = ps[k].coarse_variant;
-    h.geo.centres.assign(ps[k].ball_centres, ps[k].ball_centres + 3 * ps[k].n_balls);
-    h.geo.radii.assign(ps[k].ball_radii, ps[k].ball_radii + ps[k].n_balls);
     cell_off += align_seg((int64_t)N * N * N);
     node_off += align_seg((int64_t)(N + 1) * (N + 1) * (N + 1));
     ball_off += h.nb;
@@ -752,7 +687,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
       d.dof_off = h.dof_off;
       d.sub_off = h.sub_off;
       d.coarse_off = h.coarse_off;
-      d.nc = indexed ? h.topo->n_coarse : 0;
+      d.nc = indexed ? h.n_coarse : 0;
       d.ldc = h.ldc;
       d.ac_off = h.ac_off;
       t[k] = d;
@@ -770,120 +705,123 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(upload(c->prob_d, table0, st));
   CHK(upload(c->cell_off_d, cell_offs, st));
   CHK(upload(c->node_off_d, node_offs, st));
-  CHK(dalloc(c->count_d, c->n_cells_tot * sizeof(int32_t)));
-  launch_classify(st, c->batch(false), c->n_cells_tot, c->xi_d.as<double>(), c->balls.as<double>(),
+  std::vector<int32_t> sub_offs(P + 1);
+  for (int k = 0; k < P; ++k) sub_offs[k] = c->pb[k].sub_off;
+  sub_offs[P] = c->ns;
+  CHK(upload(c->sub_off_d, sub_offs, st));
+  const int64_t nn = c->nn, ncell = c->n_cells_tot;
+  const int ns = c->ns;
+  CHK(dalloc(c->count_d, ncell * sizeof(int32_t)));
+  launch_classify(st, c->batch(false), ncell, c->xi_d.as<double>(), c->balls.as<double>(),
                   c->count_d.as<int32_t>());
   HIPCHK(hipGetLastError());
-  std::vector<int> porder(P);
-  std::iota(porder.begin(), porder.end(), 0);
-  int32_t* counts = static_cast<int32_t*>(t_stage.get((size_t)c->n_cells_tot * 16));
-  if (!counts) return fail(CB_ERR_OOM, "pinned staging allocation failed");
-  HIPCHK(hipMemcpyAsync(counts, c->count_d.p, c->n_cells_tot * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  hipEvent_t ea, eb;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  HIPCHK(hipEventRecord(ea, st));
 
-  // cell info: cut cells numbered in problem order, then cell order
-  for_each_problem(porder, [&](int k) {
-    ProbHost& h = c->pb[k];
-    const int64_t ncell = (int64_t)h.N * h.N * h.N;
-    h.count.assign(counts + h.cell_off, counts + h.cell_off + ncell);
-    for (int64_t cc = 0; cc < ncell; ++cc) {
-      const int32_t n = h.count[cc];
-      if (n <= 0) continue;
-      h.n_active++;
-      if (n < 512) {
-        h.n_cut++;
-        if (!c->full_elements) h.cut_local.push_back(cc);
-      }
-    }
-  });
-  int64_t cut_tot = 0;
-  for (int k = 0; k < P; ++k) {
-    c->pb[k].cut_off = cut_tot;
-    cut_tot += (int64_t)c->pb[k].cut_local.size();
+  // ---- device indexing (one readback of the counts) ----------------------
+  {
+    const size_t nbs = (size_t)index_scan_blocks(std::max(ncell, nn));
+    const size_t al = 256;
+    auto up = [&](size_t x) { return (x + al - 1) / al * al; };
+    const size_t u8 = up((size_t)nn), i32 = up((size_t)nn * 4), sg = up((size_t)(P + 1) * sizeof(Count4));
+    const size_t total = 5 * u8 + 10 * i32 + up(nbs * sizeof(Count4)) + 3 * sg + up((size_t)P * 4);
+    CHK(dalloc(c->iwork, total));
+    char* q = static_cast<char*>(c->iwork.p);
+    IndexWork& w = c->iw;
+    // the per-problem results first: one contiguous readback
+    w.seg_cells = reinterpret_cast<Count4*>(q), q += sg;
+    w.seg_nodes = reinterpret_cast<Count4*>(q), q += sg;
+    w.seg_obj = reinterpret_cast<Count4*>(q), q += sg;
+    w.floating = reinterpret_cast<int32_t*>(q), q += up((size_t)P * 4);
+    for (uint8_t** u : {&w.smask, &w.link, &w.face, &w.cutdof, &w.ground}) *u = reinterpret_cast<uint8_t*>(q), q += u8;
+    for (int32_t** v : {&w.par0, &w.par1, &w.par2, &w.size1, &w.size2, &w.gif, &w.gifp, &w.oidx, &w.ocid, &w.ocsp})
+      *v = reinterpret_cast<int32_t*>(q), q += i32;
+    w.bsum = reinterpret_cast<Count4*>(q);
   }
-  c->n_cut_tot = cut_tot;
-  // same staging area after the counts: cell info (4 B per cell), then the
-  // cut-cell list (8 B per cut cell, at most one per cell)
-  int32_t* cellinfo = counts + c->n_cells_tot;
-  int64_t* cut_global = reinterpret_cast<int64_t*>(counts + 2 * c->n_cells_tot);
-  for_each_problem(porder, [&](int k) {
-    const ProbHost& h = c->pb[k];
-    const int64_t ncell = (int64_t)h.N * h.N * h.N;
-    int32_t* ci = cellinfo + h.cell_off;
-    for (int64_t cc = 0; cc < ncell; ++cc) ci[cc] = h.count[cc] > 0 ? CELL_UNCUT : CELL_INACTIVE;
-    for (int64_t cc = ncell; cc < align_seg(ncell); ++cc) ci[cc] = CELL_INACTIVE;
-    for (size_t q = 0; q < h.cut_local.size(); ++q) {
-      ci[h.cut_local[q]] = (int32_t)(h.cut_off + (int64_t)q);
-      cut_global[h.cut_off + (int64_t)q] = h.cell_off + h.cut_local[q];
-    }
-  });
-  CHK(dalloc(c->cellinfo, c->n_cells_tot * sizeof(int32_t)));
-  CHK(dalloc(c->cut_d, std::max<int64_t>(1, cut_tot) * sizeof(int64_t)));
-  HIPCHK(hipMemcpyAsync(c->cellinfo.p, cellinfo, c->n_cells_tot * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  if (cut_tot > 0)
-    HIPCHK(hipMemcpyAsync(c->cut_d.p, cut_global, cut_tot * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  CHK(dalloc(c->Kc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
-  CHK(dalloc(c->Mc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
-  launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),
-                       c->n_cut_tot, c->Kc.as<double>(), c->Mc.as<double>());
+  const size_t sgb = ((size_t)(P + 1) * sizeof(Count4) + 255) / 256 * 256;
+  const size_t small_bytes = 3 * sgb + (size_t)P * 4;
+  CHK(dalloc(c->cellinfo, ncell * sizeof(int32_t)));
+  CHK(dalloc(c->cut_d, ncell * sizeof(int64_t)));
+  launch_index_cells(st, c->batch(false), ncell, c->count_d.as<int32_t>(), c->full_elements ? 0 : 1, c->iw,
+                     c->cellinfo.as<int32_t>(), c->cut_d.as<int64_t>());
+  CHK(dalloc(c->dofmask, nn));
+  CHK(dalloc(c->dof_node, nn * sizeof(int64_t)));
+  CHK(dalloc(c->nI, (size_t)ns * sizeof(int32_t)));
+  CHK(dalloc(c->nG, (size_t)ns * sizeof(int32_t)));
+  CHK(dalloc(c->nC, (size_t)ns * sizeof(int32_t)));
+  launch_index_nodes(st, c->batch(false), ncell, nn, ns, c->sub_off_d.as<int32_t>(), c->count_d.as<int32_t>(),
+                     c->balls.as<double>(), c->variant, c->objects, c->iw, c->dofmask.as<uint8_t>(),
+                     c->dof_node.as<int64_t>(), c->nI.as<int32_t>(), c->nG.as<int32_t>(), c->nC.as<int32_t>());
   HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(e1, st));
-
-  // host indexing (overlaps the integration kernel); large problems first
-  const double th0 = now_ms();
-  std::vector<int> order(P);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->pb[a].N > c->pb[b].N; });
-  std::vector<int> rcs(P, 0);
-  std::vector<std::string> errs(P);
-  for_each_problem(order, [&](int k) {
-    ProbHost& h = c->pb[k];
-    rcs[k] = build_topology(h.geo, h.count.data(), *h.topo, errs[k]);
-  });
-  for (int k = 0; k < P; ++k) {
-    if (rcs[k] == 0) continue;
-    const std::string where = P > 1 ? "problem " + std::to_string(k) + ": " : std::string();
-    return fail(rcs[k] == -2 ? CB_ERR_SINGULAR : CB_ERR_ARG, where + errs[k]);
-  }
+  char* stage = static_cast<char*>(t_stage.get(small_bytes + 3 * (size_t)ns * sizeof(int32_t) + 256));
+  if (!stage) return fail(CB_ERR_OOM, "pinned staging allocation failed");
+  int32_t* nIh = reinterpret_cast<int32_t*>(stage + ((small_bytes + 255) / 256) * 256);
+  int32_t* nGh = nIh + ns;
+  int32_t* nCh = nGh + ns;
+  HIPCHK(hipMemcpyAsync(stage, c->iw.seg_cells, small_bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nIh, c->nI.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nGh, c->nG.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nCh, c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const Count4* segc = reinterpret_cast<const Count4*>(stage);
+  const Count4* segn = reinterpret_cast<const Count4*>(stage + sgb);
+  const Count4* sego = reinterpret_cast<const Count4*>(stage + 2 * sgb);
+  const int32_t* floating = reinterpret_cast<const int32_t*>(stage + 3 * sgb);
+  for (int k = 0; k < P; ++k)
+    if (floating[k]) {
+      const std::string where = P > 1 ? "problem " + std::to_string(k) + ": " : std::string();
+      return fail(CB_ERR_SINGULAR, where + "an active component touches no Dirichlet node (singular operator)");
+    }
   int maxI = 1, maxG = 1, maxC = 1;
-  int64_t dof_off = 0, iface_off = 0;
-  int32_t coarse_off = 0, chunk_off = 0;
+  int32_t chunk_off = 0;
   for (int k = 0; k < P; ++k) {
     ProbHost& h = c->pb[k];
-    const Topology& t = *h.topo;
-    maxI = std::max(maxI, t.maxI);
-    maxG = std::max(maxG, t.maxG);
-    maxC = std::max(maxC, t.maxC);
-    h.dof_off = dof_off;
-    h.iface_off = iface_off;
-    h.coarse_off = coarse_off;
+    h.n_active = segc[k + 1].x - segc[k].x;
+    h.n_cut = segc[k + 1].y - segc[k].y;
+    h.n_cut_stored = segc[k + 1].z - segc[k].z;
+    h.cut_off = segc[k].z;
+    h.dof_off = segn[k].x;
+    h.n_dof = segn[k + 1].x - segn[k].x;
+    h.iface_off = segn[k].y;
+    h.n_iface = segn[k + 1].y - segn[k].y;
+    h.obj_off = sego[k].x;
+    h.n_obj = sego[k + 1].x - sego[k].x;
+    h.coarse_off = sego[k].y;
+    h.n_coarse = sego[k + 1].y - sego[k].y;
+    h.maxC = 0;
+    for (int b = h.sub_off; b < h.sub_off + h.ns; ++b) {
+      maxI = std::max(maxI, nIh[b]);
+      maxG = std::max(maxG, nGh[b]);
+      h.maxC = std::max(h.maxC, nCh[b]);
+    }
+    maxC = std::max(maxC, h.maxC);
     h.chunk_off = chunk_off;
-    dof_off += t.n_dof;
-    iface_off += t.n_iface;
-    coarse_off += t.n_coarse;
     chunk_off += (int32_t)(((int64_t)(h.N + 1) * (h.N + 1) * (h.N + 1) + DOT_CHUNK - 1) / DOT_CHUNK);
   }
-  c->n_dof_tot = dof_off;
-  c->n_iface_tot = iface_off;
-  c->nc_tot = coarse_off;
+  c->n_cut_tot = segc[P].z;
+  c->n_dof_tot = segn[P].x;
+  c->n_iface_tot = segn[P].y;
+  c->nc_tot = sego[P].y;
+  const int64_t if_len = segn[P].z, cs_len = sego[P].z;
   c->n_chunks = chunk_off;
   c->NIp = round_up(maxI, CHOL_BLOCK);
   c->NGp = round_up(maxG, CHOL_BLOCK);
   c->NCp = round_up(maxC, 16);
   c->nt = c->NIp + c->NGp;
-  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp;
+  const int NIp = c->NIp, NGp = c->NGp, NCp = c->NCp;
   const int s1 = s + 1;
 
   // coarse blocks: problems grouped by padded coarse order (within 25%)
   {
     std::vector<int> co(P);
     std::iota(co.begin(), co.end(), 0);
-    std::stable_sort(co.begin(), co.end(),
-                     [&](int a, int b) { return c->pb[a].topo->n_coarse < c->pb[b].topo->n_coarse; });
+    std::stable_sort(co.begin(), co.end(), [&](int a, int b) { return c->pb[a].n_coarse < c->pb[b].n_coarse; });
     int64_t ac = 0;
     size_t i = 0;
     while (i < co.size()) {
-      const int nc0 = c->pb[co[i]].topo->n_coarse;
+      const int nc0 = c->pb[co[i]].n_coarse;
       if (nc0 == 0) {
         c->pb[co[i]].ldc = 0;
         ++i;
@@ -893,7 +831,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
       size_t j = i;
       int L = l0;
       while (j < co.size()) {
-        const int l = round_up(c->pb[co[j]].topo->n_coarse, CHOL_BLOCK);
+        const int l = round_up(c->pb[co[j]].n_coarse, CHOL_BLOCK);
         if (l > l0 + l0 / 4) break;
         L = l;
         ++j;
@@ -920,77 +858,55 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     c->n_prows = prow;
   }
 
-  // concatenated index maps
-  std::vector<int32_t> nIv(ns), nGv(ns), nCv(ns), sub_prob(ns), sub_blk(ns);
-  std::vector<int64_t> Iidx((size_t)ns * NIp, -1), Gidx((size_t)ns * NGp, -1);
-  std::vector<int32_t> Gobj((size_t)ns * NGp, -1), Cids((size_t)ns * NCp, -1);
-  std::vector<int32_t> bloc((size_t)ns * s1 * s1 * s1, -1);
-  std::vector<int64_t> if_ptr(c->n_iface_tot + 1, 0), iface_node(c->n_iface_tot);
-  std::vector<int64_t> cs_ptr((size_t)c->nc_tot + 1, 0);
-  std::vector<int64_t> dof_node(c->n_dof_tot), dof_offs(P + 1), prow_offs(P + 1);
-  std::vector<int32_t> chunk_ptr(P + 1), coarse_prob(c->nc_tot);
-  std::vector<uint8_t> mask(c->nn, 0);
-  int64_t nz_if = 0, nz_cs = 0;
-  std::vector<int64_t> if_z(P), cs_z(P);
-  for (int k = 0; k < P; ++k) {
-    if_z[k] = nz_if;
-    cs_z[k] = nz_cs;
-    nz_if += (int64_t)c->pb[k].topo->if_sub.size();
-    nz_cs += (int64_t)c->pb[k].topo->cs_sub.size();
-  }
-  std::vector<int32_t> if_sub(nz_if), if_slot(nz_if), cs_sub(nz_cs), cs_row(nz_cs);
-  for_each_problem(order, [&](int k) {
-    const ProbHost& h = c->pb[k];
-    const Topology& t = *h.topo;
-    const int64_t N1 = h.N + 1;
-    for (int b = 0; b < h.ns; ++b) {
-      const int w = h.sub_off + b;
-      sub_prob[w] = k;
-      sub_blk[w] = b;
-      nIv[w] = t.nI[b];
-      nGv[w] = t.nG[b];
-      nCv[w] = t.nC[b];
-      const int Bx = b % h.m, By = (b / h.m) % h.m, Bz = b / (h.m * h.m);
-      auto set_loc = [&](int64_t node, int row) {
-        const int64_t I = node % N1, J = (node / N1) % N1, K = node / (N1 * N1);
-        const int lx = (int)(I - (int64_t)Bx * s), ly = (int)(J - (int64_t)By * s), lz = (int)(K - (int64_t)Bz * s);
-        bloc[(size_t)w * s1 * s1 * s1 + lx + s1 * (ly + s1 * lz)] = row;
-      };
-      for (int64_t q = t.I_ptr[b]; q < t.I_ptr[b + 1]; ++q) {
-        const int i = (int)(q - t.I_ptr[b]);
-        Iidx[(size_t)w * NIp + i] = h.node_off + t.I_nodes[q];
-        set_loc(t.I_nodes[q], i);
-      }
-      for (int64_t q = t.G_ptr[b]; q < t.G_ptr[b + 1]; ++q) {
-        const int j = (int)(q - t.G_ptr[b]);
-        Gidx[(size_t)w * NGp + j] = h.node_off + t.G_nodes[q];
-        Gobj[(size_t)w * NGp + j] = t.G_obj[q];
-        set_loc(t.G_nodes[q], NIp + j);
-      }
-      for (int64_t q = t.C_ptr[b]; q < t.C_ptr[b + 1]; ++q)
-        Cids[(size_t)w * NCp + (q - t.C_ptr[b])] = h.coarse_off + t.C_ids[q];
-    }
-    for (int64_t i = 0; i < t.n_iface; ++i) {
-      if_ptr[h.iface_off + i + 1] = if_z[k] + t.if_ptr[i + 1];
-      iface_node[h.iface_off + i] = h.node_off + t.iface_node[i];
-    }
-    for (size_t z = 0; z < t.if_sub.size(); ++z) {
-      if_sub[if_z[k] + z] = h.sub_off + t.if_sub[z];
-      if_slot[if_z[k] + z] = t.if_slot[z];
-    }
-    for (int i = 0; i < t.n_coarse; ++i) {
-      cs_ptr[h.coarse_off + i + 1] = cs_z[k] + t.cs_ptr[i + 1];
-      coarse_prob[h.coarse_off + i] = k;
-    }
-    for (size_t z = 0; z < t.cs_sub.size(); ++z) {
-      cs_sub[cs_z[k] + z] = h.sub_off + t.cs_sub[z];
-      cs_row[cs_z[k] + z] = t.cs_row[z];
-    }
-    for (int64_t d = 0; d < t.n_dof; ++d) {
-      dof_node[h.dof_off + d] = h.node_off + t.dof_node[d];
-      mask[h.node_off + t.dof_node[d]] = 1;
-    }
-  });
+  // per-subdomain index maps and interface / coarse lists
+  CHK(dalloc(c->Iidx, (size_t)ns * NIp * sizeof(int64_t)));
+  CHK(dalloc(c->Gidx, (size_t)ns * NGp * sizeof(int64_t)));
+  CHK(dalloc(c->Gobj, (size_t)ns * NGp * sizeof(int32_t)));
+  CHK(dalloc(c->Cids, (size_t)ns * NCp * sizeof(int32_t)));
+  CHK(dalloc(c->bloc, (size_t)ns * s1 * s1 * s1 * sizeof(int32_t)));
+  CHK(dalloc(c->if_ptr, (size_t)(c->n_iface_tot + 1) * sizeof(int64_t)));
+  CHK(dalloc(c->if_sub, (size_t)std::max<int64_t>(1, if_len) * sizeof(int32_t)));
+  CHK(dalloc(c->if_slot, (size_t)std::max<int64_t>(1, if_len) * sizeof(int32_t)));
+  CHK(dalloc(c->iface_node, (size_t)std::max<int64_t>(1, c->n_iface_tot) * sizeof(int64_t)));
+  CHK(dalloc(c->cs_ptr, (size_t)(c->nc_tot + 1) * sizeof(int64_t)));
+  CHK(dalloc(c->cs_sub, (size_t)std::max<int64_t>(1, cs_len) * sizeof(int32_t)));
+  CHK(dalloc(c->cs_row, (size_t)std::max<int64_t>(1, cs_len) * sizeof(int32_t)));
+  CHK(dalloc(c->coarse_prob_d, (size_t)std::max(1, c->nc_tot) * sizeof(int32_t)));
+  CHK(dalloc(c->sub_prob_d, (size_t)ns * sizeof(int32_t)));
+  CHK(dalloc(c->sub_blk_d, (size_t)ns * sizeof(int32_t)));
+  IndexMaps mp;
+  mp.NIp = NIp;
+  mp.NGp = NGp;
+  mp.NCp = NCp;
+  mp.I_idx = c->Iidx.as<int64_t>();
+  mp.G_idx = c->Gidx.as<int64_t>();
+  mp.G_obj = c->Gobj.as<int32_t>();
+  mp.C_ids = c->Cids.as<int32_t>();
+  mp.bloc = c->bloc.as<int32_t>();
+  mp.if_ptr = c->if_ptr.as<int64_t>();
+  mp.if_sub = c->if_sub.as<int32_t>();
+  mp.if_slot = c->if_slot.as<int32_t>();
+  mp.iface_node = c->iface_node.as<int64_t>();
+  mp.cs_ptr = c->cs_ptr.as<int64_t>();
+  mp.cs_sub = c->cs_sub.as<int32_t>();
+  mp.cs_row = c->cs_row.as<int32_t>();
+  mp.coarse_prob = c->coarse_prob_d.as<int32_t>();
+  mp.sub_prob = c->sub_prob_d.as<int32_t>();
+  mp.sub_blk = c->sub_blk_d.as<int32_t>();
+  launch_index_fill(st, c->batch(false), ns, s, c->sub_off_d.as<int32_t>(), c->iw, mp);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(eb, st));
+
+  // cut-cell integration
+  CHK(dalloc(c->Kc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
+  CHK(dalloc(c->Mc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
+  launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),
+                       c->n_cut_tot, c->Kc.as<double>(), c->Mc.as<double>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(e1, st));
+
+  std::vector<int64_t> dof_offs(P + 1), prow_offs(P + 1);
+  std::vector<int32_t> chunk_ptr(P + 1);
   for (int k = 0; k < P; ++k) {
     dof_offs[k] = c->pb[k].dof_off;
     prow_offs[k] = c->pb[k].prow_off;
@@ -999,34 +915,11 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   dof_offs[P] = c->n_dof_tot;
   prow_offs[P] = c->n_prows;
   chunk_ptr[P] = c->n_chunks;
-  c->info.t_topology_ms = now_ms() - th0;
-
   const std::vector<ProbDev> table1 = prob_table(true);
   CHK(upload(c->prob_d, table1, st));
   CHK(upload(c->dof_off_d, dof_offs, st));
   CHK(upload(c->prow_off_d, prow_offs, st));
   CHK(upload(c->chunk_ptr_d, chunk_ptr, st));
-  CHK(upload(c->coarse_prob_d, coarse_prob, st));
-  CHK(upload(c->sub_prob_d, sub_prob, st));
-  CHK(upload(c->sub_blk_d, sub_blk, st));
-  CHK(upload(c->nI, nIv, st));
-  CHK(upload(c->nG, nGv, st));
-  CHK(upload(c->nC, nCv, st));
-  CHK(upload(c->Iidx, Iidx, st));
-  CHK(upload(c->Gidx, Gidx, st));
-  CHK(upload(c->Gobj, Gobj, st));
-  CHK(upload(c->Cids, Cids, st));
-  CHK(upload(c->bloc, bloc, st));
-  CHK(upload(c->if_ptr, if_ptr, st));
-  CHK(upload(c->if_sub, if_sub, st));
-  CHK(upload(c->if_slot, if_slot, st));
-  CHK(upload(c->iface_node, iface_node, st));
-  CHK(upload(c->cs_ptr, cs_ptr, st));
-  CHK(upload(c->cs_sub, cs_sub, st));
-  CHK(upload(c->cs_row, cs_row, st));
-  CHK(upload(c->dofmask, mask, st));
-  CHK(upload(c->dof_node, dof_node, st));
-  const int64_t nn = c->nn;
   for (DevBuf* b : {&c->x, &c->r, &c->z, &c->p, &c->q, &c->t1, &c->t2, &c->t3, &c->bgrid})
     CHK(dalloc(*b, nn * sizeof(double)));
   CHK(dalloc(c->zbuf, (size_t)ns * NGp * sizeof(double)));
@@ -1044,43 +937,48 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->fptrs, (size_t)P * sizeof(double*)));
   CHK(dalloc(c->uptrs, (size_t)P * sizeof(double*)));
   HIPCHK(hipHostMalloc(&c->pin, c->pin_bytes(), hipHostMallocDefault));
-  HIPCHK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  c->info.t_integrate_ms = ms;
   HIPCHK(hipStreamSynchronize(st));
+  {
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&m0, e0, ea));
+    HIPCHK(hipEventElapsedTime(&m1, ea, eb));
+    HIPCHK(hipEventElapsedTime(&m2, eb, e1));
+    c->info.t_integrate_ms = m0 + m2;
+    c->info.t_topology_ms = m1;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
 
   // per-problem and total counts
   cb_info& tot = c->info;
   int maxl = 0, maxc = 0;
   for (int k = 0; k < P; ++k) {
     ProbHost& h = c->pb[k];
-    const Topology& t = *h.topo;
     cb_info& in = h.info;
-    in.n_dof = t.n_dof;
+    in.n_dof = h.n_dof;
     in.n_active = h.n_active;
     in.n_cut = h.n_cut;
-    in.n_cut_stored = (int64_t)h.cut_local.size();
+    in.n_cut_stored = h.n_cut_stored;
     in.n_sub = h.ns;
-    in.n_coarse = t.n_coarse;
-    in.n_objects = (int32_t)t.obj_type.size();
-    in.n_iface = t.n_iface;
-    in.max_coarse_per_sub = t.maxC;
+    in.n_coarse = h.n_coarse;
+    in.n_objects = h.n_obj;
+    in.n_iface = h.n_iface;
+    in.max_coarse_per_sub = h.maxC;
     int ml = 0;
-    for (int w = 0; w < h.ns; ++w) {
-      ml = std::max(ml, t.nI[w] + t.nG[w]);
-      const double nI = t.nI[w], nG = t.nG[w];
-      in.sum_nI2 += (int64_t)t.nI[w] * t.nI[w];
-      in.sum_nG2 += (int64_t)t.nG[w] * t.nG[w];
-      in.sum_nI += t.nI[w];
-      in.sum_nG += t.nG[w];
+    for (int b = h.sub_off; b < h.sub_off + h.ns; ++b) {
+      ml = std::max(ml, nIh[b] + nGh[b]);
+      const double nI = nIh[b], nG = nGh[b];
+      in.sum_nI2 += (int64_t)nIh[b] * nIh[b];
+      in.sum_nG2 += (int64_t)nGh[b] * nGh[b];
+      in.sum_nI += nIh[b];
+      in.sum_nG += nGh[b];
       in.flops_local_chol += (nI + nG) * (nI + nG) * (nI + nG) / 3.0 + nI * nI * nI / 3.0;
     }
     in.max_local_dofs = ml;
     maxl = std::max(maxl, ml);
-    maxc = std::max(maxc, t.maxC);
+    maxc = std::max(maxc, h.maxC);
     tot.n_dof += in.n_dof;
     tot.n_active += in.n_active;
     tot.n_cut += in.n_cut;
@@ -1604,19 +1502,76 @@ int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_coun
   if (!c) return fail(CB_ERR_ARG, "null context");
   CHK(need_single(c));
   const ProbHost& h = c->pb[0];
-  const Topology& t = *h.topo;
   const int64_t ncell = (int64_t)h.N * h.N * h.N;
-  if (cell_status)
-    for (int64_t i = 0; i < ncell; ++i)
-      cell_status[i] = h.count[i] == 0 ? 0 : (h.count[i] == 512 ? 2 : 1);
-  if (cell_count) std::memcpy(cell_count, h.count.data(), ncell * sizeof(int32_t));
-  if (dof_node) std::memcpy(dof_node, t.dof_node.data(), t.n_dof * sizeof(int64_t));
+  const int64_t N1 = h.N + 1, nnode = N1 * N1 * N1;
+  HIPCHK(hipStreamSynchronize(c->st));
+  auto down = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+  };
+  if (cell_status || cell_count) {
+    std::vector<int32_t> cnt(ncell);
+    HIPCHK(down(cnt.data(), c->count_d.as<int32_t>() + h.cell_off, ncell * sizeof(int32_t)));
+    if (cell_status)
+      for (int64_t i = 0; i < ncell; ++i) cell_status[i] = cnt[i] == 0 ? 0 : (cnt[i] == 512 ? 2 : 1);
+    if (cell_count) std::memcpy(cell_count, cnt.data(), ncell * sizeof(int32_t));
+  }
+  // node data of the problem
+  const IndexWork& w = c->iw;
+  std::vector<uint8_t> smask(nnode), face(nnode);
+  std::vector<int32_t> par1(nnode), par2(nnode), size2(nnode), oidx(nnode), ocid(nnode);
+  std::vector<int64_t> dn(std::max<int64_t>(1, h.n_dof));
+  HIPCHK(down(smask.data(), w.smask + h.node_off, nnode));
+  HIPCHK(down(face.data(), w.face + h.node_off, nnode));
+  HIPCHK(down(par1.data(), w.par1 + h.node_off, nnode * sizeof(int32_t)));
+  HIPCHK(down(par2.data(), w.par2 + h.node_off, nnode * sizeof(int32_t)));
+  HIPCHK(down(size2.data(), w.size2 + h.node_off, nnode * sizeof(int32_t)));
+  HIPCHK(down(oidx.data(), w.oidx + h.node_off, nnode * sizeof(int32_t)));
+  HIPCHK(down(ocid.data(), w.ocid + h.node_off, nnode * sizeof(int32_t)));
+  if (h.n_dof) HIPCHK(down(dn.data(), c->dof_node.as<int64_t>() + h.dof_off, h.n_dof * sizeof(int64_t)));
+  for (int64_t d = 0; d < h.n_dof; ++d) dn[d] -= h.node_off;
+  if (dof_node) std::memcpy(dof_node, dn.data(), h.n_dof * sizeof(int64_t));
   if (card)
-    for (int64_t d = 0; d < t.n_dof; ++d) card[d] = t.card[d];
-  if (obj_ptr) std::memcpy(obj_ptr, t.obj_ptr.data(), t.obj_ptr.size() * sizeof(int64_t));
-  if (obj_dofs) std::memcpy(obj_dofs, t.obj_dofs.data(), t.obj_dofs.size() * sizeof(int64_t));
-  if (obj_type) std::memcpy(obj_type, t.obj_type.data(), t.obj_type.size());
-  if (coarse_of_obj) std::memcpy(coarse_of_obj, t.coarse_of_obj.data(), t.coarse_of_obj.size() * sizeof(int32_t));
+    for (int64_t d = 0; d < h.n_dof; ++d) card[d] = __builtin_popcount(smask[dn[d]]);
+  // objects: interface DOFs grouped by their root, ascending within each
+  const int64_t nobj = h.n_obj;
+  std::vector<int64_t> ptr(nobj + 1, 0);
+  auto obj_of = [&](int64_t ln) -> int64_t {
+    const int64_t r = (int64_t)par2[ln] - h.node_off;
+    if (r < 0 || r >= nnode) return -1;
+    const int64_t o = (int64_t)oidx[r] - h.obj_off;
+    return (o >= 0 && o < nobj) ? o : -1;
+  };
+  int64_t n_if = 0;
+  for (int64_t d = 0; d < h.n_dof; ++d) {
+    if (dn[d] < 0 || dn[d] >= nnode) return fail(CB_ERR_STATE, "index export: DOF node out of range");
+    if (__builtin_popcount(smask[dn[d]]) < 2) continue;
+    const int64_t o = obj_of(dn[d]);
+    if (o < 0)
+      return fail(CB_ERR_STATE, "index export: DOF " + std::to_string(d) + " (node " + std::to_string(dn[d]) +
+                                    ") has root " + std::to_string(par2[dn[d]]) + " without an object index (" +
+                                    std::to_string(oidx[std::min<int64_t>(std::max<int64_t>(0, par2[dn[d]] - h.node_off), nnode - 1)]) +
+                                    ", objects " + std::to_string(nobj) + ")");
+    ptr[o + 1]++;
+    ++n_if;
+  }
+  if (n_if != h.n_iface) return fail(CB_ERR_STATE, "index export: interface count mismatch");
+  for (int64_t o = 0; o < nobj; ++o) ptr[o + 1] += ptr[o];
+  if (obj_ptr) std::memcpy(obj_ptr, ptr.data(), (nobj + 1) * sizeof(int64_t));
+  if (obj_dofs) {
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t d = 0; d < h.n_dof; ++d)
+      if (__builtin_popcount(smask[dn[d]]) >= 2) obj_dofs[fill[obj_of(dn[d])]++] = d;
+  }
+  for (int64_t ln = 0; ln < nnode; ++ln) {
+    if (__builtin_popcount(smask[ln]) < 2 || par2[ln] != ln + h.node_off) continue;
+    const int64_t o = oidx[ln] - h.obj_off;
+    if (o < 0 || o >= nobj) return fail(CB_ERR_STATE, "index export: object index out of range");
+    if (par1[ln] - h.node_off < 0 || par1[ln] - h.node_off >= nnode)
+      return fail(CB_ERR_STATE, "index export: pass-1 root out of range");
+    if (obj_type)
+      obj_type[o] = size2[ln] == 1 ? OBJ_CORNER : (face[par1[ln] - h.node_off] ? OBJ_FACE : OBJ_EDGE);
+    if (coarse_of_obj) coarse_of_obj[o] = ocid[ln] >= 0 ? ocid[ln] - h.coarse_off : -1;
+  }
   return CB_OK;
 }
 
@@ -1624,10 +1579,14 @@ int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_c
   if (!c) return fail(CB_ERR_ARG, "null context");
   CHK(need_single(c));
   const ProbHost& h = c->pb[0];
-  const int64_t n = (int64_t)h.cut_local.size();
+  const int64_t n = h.n_cut_stored;
+  HIPCHK(hipStreamSynchronize(c->st));
   if (K && n) HIPCHK(hipMemcpy(K, c->Kc.p, n * PACK36 * sizeof(double), hipMemcpyDeviceToHost));
   if (M && n) HIPCHK(hipMemcpy(M, c->Mc.p, n * PACK36 * sizeof(double), hipMemcpyDeviceToHost));
-  if (cut_cells && n) std::memcpy(cut_cells, h.cut_local.data(), n * sizeof(int64_t));
+  if (cut_cells && n) {
+    HIPCHK(hipMemcpy(cut_cells, c->cut_d.as<int64_t>() + h.cut_off, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) cut_cells[i] -= h.cell_off;
+  }
   return CB_OK;
 }
 
@@ -1636,7 +1595,7 @@ int cb_export_coarse(const cb_ctx* c, double* Ac) {
   CHK(need_single(c));
   if (!c->factored) return fail(CB_ERR_STATE, "coarse matrix requested before cb_factor");
   const ProbHost& h = c->pb[0];
-  const int nc = h.topo->n_coarse, ldc = h.ldc;
+  const int nc = h.n_coarse, ldc = h.ldc;
   if (nc == 0) return CB_OK;
   HIPCHK(hipMemcpy2D(Ac, nc * sizeof(double), c->AcKeep.as<double>() + h.ac_off, ldc * sizeof(double),
                      nc * sizeof(double), nc, hipMemcpyDeviceToHost));

@@ -75,7 +75,7 @@ template <typename T, int TA, int TB, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
-                                                   int64_t sC, int mode, int vec) {
+                                                   int64_t sC, int mode, int vec, int swz) {
   typedef typename Vec16<T>::type V;
   constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int KT = 128 / sizeof(T);           // k per stage
@@ -87,9 +87,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
   static_assert(AV >= 1 && BV >= 1, "tile too small");
   __shared__ __align__(16) T As[2][BM][LDK];
   __shared__ __align__(16) T Bs[2][BN][LDK];
-  const int row0 = blockIdx.y * BM;
-  const int col0 = blockIdx.x * BN;
-  const int64_t bz = blockIdx.z;
+  // Workgroups are handed to the 8 XCDs round-robin by linear id; with swz
+  // the tiles are renumbered so that each XCD runs a contiguous range of
+  // (tile, matrix) pairs, i.e. whole matrices, whose operand panels then
+  // stay in that XCD's L2.  The map is a bijection for any grid size.
+  int64_t tx = blockIdx.x, ty = blockIdx.y, tz = blockIdx.z;
+  if (swz) {
+    const int64_t gx = gridDim.x, gxy = gx * gridDim.y;
+    const int64_t tot = gxy * gridDim.z, L = tx + gx * ty + gxy * tz;
+    const int64_t q = tot / 8, r = tot % 8, x = L % 8, s = L / 8;
+    const int64_t Lp = x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+    tz = Lp / gxy;
+    ty = (Lp - tz * gxy) / gx;
+    tx = Lp - tz * gxy - ty * gx;
+  }
+  const int row0 = (int)ty * BM;
+  const int col0 = (int)tx * BN;
+  const int64_t bz = tz;
   if ((mode & GEMM_LOWER) && col0 > row0 + BM - 1) return;
   A += bz * sA;
   B += bz * sB;
@@ -527,6 +541,15 @@ TuneKey tune_key(int TA, int TB, int M, int N, int K, int batch, int mode) {
   return TuneKey{(int)sizeof(T), TA, TB, mode & 7, log2b(M), log2b(N), log2b(std::max(K, 1)), log2b(batch)};
 }
 
+// CUTBDDC_XCD=0 turns the XCD-contiguous tile order off (for comparison).
+bool gemm_xcd_swizzle() {
+  static const bool on = [] {
+    const char* e = std::getenv("CUTBDDC_XCD");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 template <typename T>
 void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A,
                  int64_t lda, int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
@@ -538,10 +561,11 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   const int vec = (lda % VW == 0 && ldb % VW == 0 && (batch == 1 || (sA % VW == 0 && sB % VW == 0)) && al(A) &&
                    al(B)) ? 1 : 0;
+  const int swz = gemm_xcd_swizzle() ? 1 : 0;
 #define GEMM_CASE(a, b, bm, bn)                                                                        \
   if (TA == a && TB == b && BM == bm && BN == bn) {                                                    \
     hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
-                       sA, B, ldb, sB, beta, C, ldc, sC, mode, vec);                                   \
+                       sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz);                              \
     return;                                                                                            \
   }
 #define GEMM_SHAPES(a, b) \
