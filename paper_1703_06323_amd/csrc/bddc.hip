@@ -604,10 +604,14 @@ __device__ inline void symv_packed(const TM* __restrict__ Pk, int nbu, const dou
   __syncthreads();
 }
 
+// Threads per workgroup of the packed apply kernels: with two subdomains
+// per CU, 512 threads keep 4 waves per SIMD streaming operator blocks.
+constexpr int APPLY_T = 512;
+
 // out[node(I_idx)] = P_w (a - b)[I_idx] (b may be null), one workgroup per
 // subdomain, P_w = A_II^{-1} in packed storage.
 template <typename TM>
-__global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM* __restrict__ P,
+__global__ __launch_bounds__(APPLY_T) void apply_interior_kernel(SubDev sd, const TM* __restrict__ P,
                                                              const double* __restrict__ a,
                                                              const double* __restrict__ b,
                                                              double* __restrict__ out) {
@@ -638,7 +642,7 @@ __global__ __launch_bounds__(256) void apply_interior_kernel(SubDev sd, const TM
 // z_w = Kt_w g_w with g_w[j] = Dw[j] (r - t)[G_idx[j]] (Kt_w packed);
 // cloc_w = Phi_w^T g_w.
 template <typename TM>
-__global__ __launch_bounds__(256) void apply_neumann_kernel(SubDev sd, const TM* __restrict__ Kt,
+__global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const TM* __restrict__ Kt,
                                                             const double* __restrict__ Phi,
                                                             const double* __restrict__ Dw,
                                                             const double* __restrict__ r,
@@ -838,7 +842,7 @@ void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P
   static bool attr = (hipFuncSetAttribute((const void*)apply_interior_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
-  hipLaunchKernelGGL(apply_interior_kernel<TM>, dim3(ns), dim3(256), sh, st, sd, P, a, b, out);
+  hipLaunchKernelGGL(apply_interior_kernel<TM>, dim3(ns), dim3(APPLY_T), sh, st, sd, P, a, b, out);
 }
 template void launch_apply_interior<double>(hipStream_t, const SubDev&, int, const double*, const double*,
                                             const double*, double*);
@@ -852,7 +856,7 @@ void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt
   static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
-  hipLaunchKernelGGL(apply_neumann_kernel<TM>, dim3(ns), dim3(256), sh, st, sd, Kt, Phi, Dw, r, t, z, cloc);
+  hipLaunchKernelGGL(apply_neumann_kernel<TM>, dim3(ns), dim3(APPLY_T), sh, st, sd, Kt, Phi, Dw, r, t, z, cloc);
 }
 template void launch_apply_neumann<double>(hipStream_t, const SubDev&, int, const double*, const double*,
                                            const double*, const double*, const double*, double*, double*);

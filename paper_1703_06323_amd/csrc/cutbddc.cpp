@@ -283,6 +283,8 @@ struct cb_ctx {
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
   void* pin = nullptr;
+  // second stream for work that overlaps the coarse factorisation
+  hipStream_t aux_st = nullptr;
   // captured PCG iteration
   hipStream_t cap_st = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -292,6 +294,7 @@ struct cb_ctx {
   ~cb_ctx() {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (cap_st) (void)hipStreamDestroy(cap_st);
+    if (aux_st) (void)hipStreamDestroy(aux_st);
     if (pin) (void)hipHostFree(pin);
     for (auto& kv : prof_ev)
       for (auto& e : kv.second.ev) {
@@ -1155,9 +1158,15 @@ int factor_impl(cb_ctx* c) {
       const int64_t sA = (int64_t)L * L, sLc = (int64_t)diag_blocks(L, 0) * DB * DB;
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
       double* A = Ac.as<double>() + gr.ac_off;
-      cholesky<double>(st, A, L, sA, L, 0, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
-      tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA, Tc.as<double>(),
-                          (int64_t)TRI_SUPER * L);
+      // the triangular inverse trails the factorisation on a second stream
+      if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
+      if (cholesky_inverse<double>(st, c->aux_st, A, L, sA, L, nb, Lc.as<double>(), sLc,
+                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA, Tc.as<double>(),
+                                   (int64_t)TRI_SUPER * L) != 0) {
+        cholesky<double>(st, A, L, sA, L, 0, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
+        tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA,
+                            Tc.as<double>(), (int64_t)TRI_SUPER * L);
+      }
       gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
                    L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
       symmetrize_scale<double, double>(st, PSc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
@@ -1258,11 +1267,17 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
     CHK(dalloc(dOut, (size_t)batch * nn * sizeof(double)));
     CHK(upload(dOnes, std::vector<double>((size_t)batch * np, 1.0), nullptr));
     CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
-    cholesky<T>(nullptr, dA.as<T>(), np, nn, np, 0, batch, dL.as<T>(), sL, dInfo.as<int>());
     DevBuf dT;
     CHK(dalloc(dT, (size_t)batch * TRI_SUPER * np * sizeof(T)));
-    tri_inverse<T>(nullptr, dA.as<T>(), np, nn, 0, np, 0, batch, dL.as<T>(), sL, dY.as<T>(), np, nn, dT.as<T>(),
-                   (int64_t)TRI_SUPER * np);
+    // the factorisation with the overlapped triangular inverse, as for the
+    // coarse matrices
+    hipStream_t st2 = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+    const int rc = cholesky_inverse<T>(nullptr, st2, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>(),
+                                       dY.as<T>(), nn, dT.as<T>(), (int64_t)TRI_SUPER * np);
+    (void)hipStreamSynchronize(st2);
+    (void)hipStreamDestroy(st2);
+    if (rc != 0) return fail(CB_ERR_DEVICE, "event creation failed");
     gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
             GEMM_LOWER | GEMM_KFROM_DIAG);
     symmetrize_scale<T, double>(nullptr, dP.as<T>(), np, nn, dOut.as<double>(), np, nn, dOnes.as<double>(), np, np,

@@ -63,6 +63,15 @@ template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
                  const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT);
 
+// Cholesky of n x n matrices (no split) and Y = L^{-1} (as tri_inverse over
+// the whole range, Y with leading dimension lda and stride sY), the inverse
+// steps issued on st2 one block behind the factorisation so that they overlap
+// with it; st waits for st2 before returning.  Returns -1 if no event could
+// be created (nothing is issued then).
+template <typename T>
+int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
+                     int64_t sL, int* info, T* Y, int64_t sY, T* tmp, int64_t sT);
+
 // out = D sym(lower(in)) D, full storage.
 template <typename T, typename TO>
 void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* out, int64_t ldo,

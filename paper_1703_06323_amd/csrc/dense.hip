@@ -71,7 +71,7 @@ template <> struct Vec16<double> {
 // C is written only after the whole K loop, so a call may overwrite its own
 // B operand when each output tile reads only its own columns of B (and the
 // same for A and rows); the dispatcher keeps such calls on 64-wide tiles.
-template <typename T, int TA, int TB, int BM, int BN>
+template <typename T, int TA, int TB, int BM, int BN, int DEPTH = 1>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
   const int lane = tid & 63, wv = tid >> 6;
   const int wr = wv >> 1, wc = wv & 1;
 
-  V ra[AV], rb[BV];
+  V ra[AV], rb[BV], ra2[AV], rb2[BV];
   // tile coordinates (row or column index, k) of the first element of
   // vector q of this thread
   auto a_coord = [&](int q, int& i, int& k) {
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
       j = (v % (BN / VW)) * VW;
     }
   };
-  auto load = [&](int k0) {
+  auto load = [&](int k0, V (&ra)[AV], V (&rb)[BV]) {
 #pragma unroll
     for (int q = 0; q < AV; ++q) {
       int i, k;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
       rb[q] = x;
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const V (&ra)[AV], const V (&rb)[BV]) {
 #pragma unroll
     for (int q = 0; q < AV; ++q) {
       int i, k;
@@ -218,15 +218,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
     for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
 
   const int ks = 4 * (lane >> 4);
-  int buf = 0;
-  if (kbeg < kend) {
-    load(kbeg);
-    store(0);
-  }
-  __syncthreads();
-  for (int k0 = kbeg; k0 < kend; k0 += KT) {
-    const bool more = k0 + KT < kend;
-    if (more) load(k0 + KT);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kb = 0; kb < KT; kb += 16) {
       T av[FM][4], bv[FN][4];
@@ -257,10 +249,58 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
 #pragma unroll
           for (int ni = 0; ni < FN; ++ni) acc[mi][ni] = Acc<T>::mfma(av[mi][q], bv[ni][q], acc[mi][ni]);
     }
-    if (more) store(buf ^ 1);
+  };
+  if (DEPTH == 1) {
+    int buf = 0;
+    if (kbeg < kend) {
+      load(kbeg, ra, rb);
+      store(0, ra, rb);
+    }
     __syncthreads();
-    buf ^= 1;
+    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+      const bool more = k0 + KT < kend;
+      if (more) load(k0 + KT, ra, rb);
+      compute(buf);
+      if (more) store(buf ^ 1, ra, rb);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    // two stages in flight: the registers of stage s+2 are loaded while
+    // stage s is multiplied and stage s+1 waits in the other register set
+    if (kbeg < kend) {
+      load(kbeg, ra, rb);
+      store(0, ra, rb);
+    }
+    if (kbeg + KT < kend) load(kbeg + KT, ra2, rb2);
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += 2 * KT) {
+      if (k0 + 2 * KT < kend) load(k0 + 2 * KT, ra, rb);
+      compute(0);
+      if (k0 + KT < kend) store(1, ra2, rb2);
+      __syncthreads();
+      if (k0 + KT >= kend) break;
+      if (k0 + 3 * KT < kend) load(k0 + 3 * KT, ra2, rb2);
+      compute(1);
+      if (k0 + 2 * KT < kend) store(0, ra, rb);
+      __syncthreads();
+    }
   }
+  // Epilogue: every C value is loaded before the first store (C may alias
+  // A or B, so loads interleaved with stores would each wait for the one
+  // before); the arithmetic per element is unchanged.
+  T cold[FM][FN][4];
+#pragma unroll
+  for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wr * WM + mi * 16 + Acc<T>::row(lane, v);
+        const int gj = col0 + wc * WN + ni * 16 + (lane & 15);
+        const bool ok = gi < M && gj < N && !((mode & GEMM_LOWER) && gj > gi);
+        cold[mi][ni][v] = (ok && beta != T(0)) ? C[(int64_t)gi * ldc + gj] : T(0);
+      }
 #pragma unroll
   for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
@@ -271,9 +311,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
         const int gj = col0 + wc * WN + ni * 16 + (lane & 15);
         if (gi >= M || gj >= N) continue;
         if ((mode & GEMM_LOWER) && gj > gi) continue;
-        T* c = C + (int64_t)gi * ldc + gj;
         const T r = alpha * acc[mi][ni][v];
-        *c = (beta == T(0)) ? r : r + beta * (*c);
+        C[(int64_t)gi * ldc + gj] = (beta == T(0)) ? r : r + beta * cold[mi][ni][v];
       }
 }
 
@@ -427,6 +466,201 @@ __global__ __launch_bounds__(DF_THREADS) void diag_factor_kernel(T* A, int64_t l
   if (t == 0 && bad && info && info[bz] == 0) info[bz] = bad;
 }
 
+// Blocked variant of the diagonal step for blocks of order b, b a multiple
+// of 16 (b <= DB): the same outputs as diag_factor_kernel (L in place with
+// the upper part of the block zeroed, X = L^{-1} into block `blk` of Linv,
+// info for a bad pivot), with far fewer workgroup barriers.  The block lives
+// in LDS as 16 x 16 tiles (lower tiles of L and of X, element (r, c) of a
+// tile at r * 16 + (c ^ r) so that reading a tile column is free of bank
+// conflicts).  For each tile column p:
+//   1. wave 0 factors the diagonal tile and inverts it in registers,
+//      column by column, exchanging values with lane shuffles (no
+//      barriers);
+//   2. every wave takes one tile: a panel tile L_ip = A_ip X_pp^T (i > p) or
+//      a tile of row p of X, X_pj = -X_pp (sum_{j<=k<p} L_pk X_kj);
+//   3. the trailing tiles A_ij -= L_ip L_jp^T (p < j <= i) are shared out.
+// Tile products run on the 16x16x4 MFMAs.
+constexpr int DK_THREADS = 512;
+constexpr int DK_TILES = (DB / 16) * (DB / 16 + 1) / 2;
+__device__ inline int dk_tile(int I, int J) { return I * (I + 1) / 2 + J; }
+__device__ inline int dk_at(int r, int c) { return r * 16 + (c ^ r); }
+__device__ inline double dk_bcast(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)(u & 0xffffffffull), lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float dk_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// 1/sqrt(d) for the pivots of the wave-level factorisation: the hardware
+// estimate refined by Newton steps y <- y (3/2 - d y^2 / 2) (two for FP64,
+// one for FP32), a few ulp from the rounded value.
+__device__ inline double dk_rsqrt(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+__device__ inline float dk_rsqrt(float d) {
+  float y = __builtin_amdgcn_rsqf(d);
+  const float h = 0.5f * d;
+  return fmaf(y, fmaf(-h * y, y, 0.5f), y);
+}
+
+// acc += op(P) op(Q) over one 16-wide k range for the calling wave:
+// P[r][k] (tile p, rows r) times Q^T (qt = 1: Q[c][k]) or Q (qt = 0: Q[k][c]).
+template <typename T>
+__device__ inline void dk_mma(typename Acc<T>::type& acc, const T* P, const T* Q, int qt, int lane) {
+  const int r = lane & 15, kk = lane >> 4;
+  T a[4], b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + kk;
+    a[s] = P[dk_at(r, k)];
+    b[s] = qt ? Q[dk_at(r, k)] : Q[dk_at(k, r)];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = Acc<T>::mfma(a[s], b[s], acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t lda, int64_t sA, int k0, int b,
+                                                                T* Linv, int64_t sL, int blk, int* info) {
+  extern __shared__ __align__(16) unsigned char dk_lds[];
+  T* Ls = reinterpret_cast<T*>(dk_lds);
+  T* Xs = Ls + DK_TILES * 256;
+  const int64_t bz = blockIdx.x;
+  T* a = A + bz * sA + (int64_t)k0 * lda + k0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = b >> 4;
+  typedef typename Acc<T>::type AccT;
+  // load the lower tiles (upper part of diagonal tiles as zero); X = 0
+  for (int e = tid; e < DK_TILES * 256; e += DK_THREADS) {
+    const int q = e >> 8, rc = e & 255, r = rc >> 4, c = rc & 15;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= q) ++I;
+    const int J = q - I * (I + 1) / 2;
+    T v = T(0);
+    if (I < nt && (I != J || c <= r)) v = a[(int64_t)(16 * I + r) * lda + 16 * J + c];
+    Ls[q * 256 + dk_at(r, c)] = v;
+    Xs[q * 256 + dk_at(r, c)] = T(0);
+  }
+  __syncthreads();
+  int bad = 0;   // wave 0: first failing row + 1
+  // wave 0: factor and invert diagonal tile p in registers; lane (r, g)
+  // holds columns g + 4t of row r
+  auto factor_diag = [&](int p) {
+    T* Lp = Ls + dk_tile(p, p) * 256;
+    T* Xp = Xs + dk_tile(p, p) * 256;
+    const int r = lane & 15, g = lane >> 4;
+    T av[4], xv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = g + 4 * t;
+      av[t] = c <= r ? Lp[dk_at(r, c)] : T(0);
+      xv[t] = c == r ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int tj = j >> 2, gj = j & 3;
+      const T colj = av[tj];   // column j before this step changes it
+      T d = dk_bcast(colj, j + 16 * gj);
+      if (!(d > T(0)) || !(d < T(3.0e38))) {
+        if (bad == 0) bad = k0 + 16 * p + j + 1;
+        d = T(1);
+      }
+      const T inv = dk_rsqrt(d);
+      const T ljj = d * inv;
+      const T lrj = __shfl(colj, r + 16 * gj, 64) * inv;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = g + 4 * t;
+        const T lcj = __shfl(colj, c + 16 * gj, 64) * inv;
+        const T xjc = __shfl(xv[t], j + 16 * g, 64) * inv;
+        if (c == j) av[t] = r > j ? lrj : (r == j ? ljj : T(0));
+        else if (c > j && r >= c) av[t] = fma(-lrj, lcj, av[t]);
+        if (r == j) xv[t] = xjc;
+        else if (r > j) xv[t] = fma(-lrj, xjc, xv[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = g + 4 * t;
+      Lp[dk_at(r, c)] = av[t];
+      Xp[dk_at(r, c)] = xv[t];
+    }
+  };
+  // A_ij -= L_ip L_jp^T by the calling wave
+  auto trail = [&](int p, int i, int j) {
+    AccT acc = {0, 0, 0, 0};
+    dk_mma<T>(acc, Ls + dk_tile(i, p) * 256, Ls + dk_tile(j, p) * 256, 1, lane);
+    T* Aij = Ls + dk_tile(i, j) * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Aij[dk_at(Acc<T>::row(lane, v), lane & 15)] -= acc[v];
+  };
+  if (wv == 0) factor_diag(0);
+  __syncthreads();
+  for (int p = 0; p < nt; ++p) {
+    // 2. panel tiles and row p of X, one tile per wave
+    for (int item = wv; item < nt - 1; item += DK_THREADS / 64) {
+      AccT acc = {0, 0, 0, 0};
+      if (item < nt - 1 - p) {
+        const int i = p + 1 + item;
+        T* Lip = Ls + dk_tile(i, p) * 256;
+        dk_mma<T>(acc, Lip, Xs + dk_tile(p, p) * 256, 1, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Lip[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
+      } else {
+        const int j = item - (nt - 1 - p);
+        T* Xpj = Xs + dk_tile(p, j) * 256;
+        for (int k = j; k < p; ++k)
+          dk_mma<T>(acc, Ls + dk_tile(p, k) * 256, Xs + dk_tile(k, j) * 256, 0, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
+        __builtin_amdgcn_wave_barrier();
+        AccT acc2 = {0, 0, 0, 0};
+        dk_mma<T>(acc2, Xs + dk_tile(p, p) * 256, Xpj, 0, lane);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = -acc2[v];
+      }
+    }
+    __syncthreads();
+    if (p + 1 == nt) break;
+    // 3. trailing update; wave 0 takes the next diagonal tile and factors
+    // it at once (lookahead), the other waves share the remaining tiles
+    const int m = nt - 1 - p, ntr = m * (m + 1) / 2;
+    if (wv == 0) {
+      trail(p, p + 1, p + 1);
+      __builtin_amdgcn_wave_barrier();
+      factor_diag(p + 1);
+    } else {
+      for (int item = 1 + (wv - 1); item < ntr; item += DK_THREADS / 64 - 1) {
+        int ii = 0;
+        while ((ii + 1) * (ii + 2) / 2 <= item) ++ii;
+        const int jj = item - ii * (ii + 1) / 2;
+        trail(p, p + 1 + ii, p + 1 + jj);
+      }
+    }
+    __syncthreads();
+  }
+  // write L (upper part of the block zero) and X (zero above the diagonal
+  // and outside the b x b block)
+  T* li = Linv + bz * sL + (int64_t)blk * DB * DB;
+  for (int e = tid; e < DB * DB; e += DK_THREADS) {
+    const int row = e / DB, col = e - row * DB;
+    const int I = row >> 4, J = col >> 4, r = row & 15, c = col & 15;
+    const bool in = row < b && col < b && col <= row;
+    const int at = (I >= J && I < 8) ? dk_tile(I, J) * 256 + dk_at(r, c) : 0;
+    li[e] = in ? Xs[at] : T(0);
+    if (row < b && col < b) a[(int64_t)row * lda + col] = in ? Ls[at] : T(0);
+  }
+  if (tid == 0 && bad && info && info[bz] == 0) info[bz] = bad;
+}
+
 // Copies the h x h inverse block `blk` of Linv into Y's diagonal block at
 // (i0, i0).
 template <typename T>
@@ -539,6 +773,15 @@ bool autotune_enabled() {
 template <typename T>
 TuneKey tune_key(int TA, int TB, int M, int N, int K, int batch, int mode) {
   return TuneKey{(int)sizeof(T), TA, TB, mode & 7, log2b(M), log2b(N), log2b(std::max(K, 1)), log2b(batch)};
+}
+
+// CUTBDDC_DIAG_BLOCKED=0 selects the register-tile diagonal kernel.
+bool diag_blocked_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("CUTBDDC_DIAG_BLOCKED");
+    return !(e && e[0] == '0');
+  }();
+  return on;
 }
 
 // CUTBDDC_XCD=0 turns the XCD-contiguous tile order off (for comparison).
@@ -659,6 +902,23 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
   return best;
 }
 
+// Factors and inverts the diagonal block of order b at (K0, K0).
+template <typename T>
+void diag_step(hipStream_t st, T* A, int64_t lda, int64_t sA, int K0, int b, T* Linv, int64_t sL, int blk, int batch,
+               int* info) {
+  if (b % 16 == 0 && diag_blocked_enabled()) {
+    static const bool attr =
+        hipFuncSetAttribute((const void*)diag_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(2 * DK_TILES * 256 * sizeof(T))) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(diag_block_kernel<T>, dim3(batch), dim3(DK_THREADS), 2 * DK_TILES * 256 * sizeof(T), st, A,
+                       lda, sA, K0, b, Linv, sL, blk, info);
+  } else {
+    hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(DF_THREADS), 0, st, A, lda, sA, K0, b, Linv, sL, blk,
+                       info);
+  }
+}
+
 template <typename T>
 void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
               int* info) {
@@ -672,8 +932,7 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
     const int lim = (split > 0 && K0 < split) ? split : n;
     const int b = std::min(DB, lim - K0);
     const int K1 = K0 + b;
-    hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(DF_THREADS), 0, st, A, lda, sA, K0, b, Linv, sL,
-                       diag_block_index(K0, split), info);
+    diag_step<T>(st, A, lda, sA, K0, b, Linv, sL, diag_block_index(K0, split), batch, info);
     const int rest = n - K1;
     if (rest > 0) {
       T* panel = A + (int64_t)K1 * lda + K0;
@@ -683,6 +942,31 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
               lda, sA, batch, GEMM_LOWER);
     }
     K0 = K1;
+  }
+}
+
+// One block step of the triangular inverse (see tri_inverse): block row S
+// = [S0, S0 + h) of Y becomes final and the rows below receive its rank-h
+// update.  Reads only the diagonal-block inverse and the column block of L
+// below it, both final once the Cholesky sweep has passed that block.
+template <typename T>
+void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
+                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT, int S0,
+                      int h) {
+  const int send = S0 + h;
+  const int blk = diag_block_index(off + S0, split);
+  const T* li = Linv + (int64_t)blk * DB * DB;
+  hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, Y, ldy, sY, S0, h, Linv, sLi, blk);
+  if (S0 > 0) {
+    gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), tmp, S0, sT, batch, 0);
+    hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, (const T*)tmp, (int64_t)S0, sT,
+                       Y + (int64_t)S0 * ldy, ldy, sY, S0);
+  }
+  const int rest = nb - send;
+  if (rest > 0) {
+    const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
+    gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
+            Y + (int64_t)send * ldy, ldy, sY, batch, 0);
   }
 }
 
@@ -700,24 +984,45 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
     const int p = off + S0;
     const int lim = (split > 0 && p < split) ? std::min(split - off, nb) : nb;
     const int h = std::min(DB, lim - S0);
-    const int send = S0 + h;
-    const int blk = diag_block_index(p, split);
-    const T* li = Linv + (int64_t)blk * DB * DB;
-    hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, Y, ldy, sY, S0, h, Linv, sLi,
-                       blk);
-    if (S0 > 0) {
-      gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), tmp, S0, sT, batch, 0);
-      hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, (const T*)tmp, (int64_t)S0, sT,
-                         Y + (int64_t)S0 * ldy, ldy, sY, S0);
-    }
-    const int rest = nb - send;
-    if (rest > 0) {
-      const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
-      gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
-              Y + (int64_t)send * ldy, ldy, sY, batch, 0);
-    }
-    S0 = send;
+    tri_inverse_step<T>(st, L, ldl, sL, off, nb, split, batch, Linv, sLi, Y, ldy, sY, tmp, sT, S0, h);
+    S0 += h;
   }
+}
+
+template <typename T>
+int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
+                     int64_t sL, int* info, T* Y, int64_t sY, T* tmp, int64_t sT) {
+  // Cholesky sweep on st; block step k of the triangular inverse follows on
+  // st2 as soon as the sweep has produced diagonal block k and the column
+  // block below it.
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return -1;
+  hipLaunchKernelGGL(zero_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
+  int K0 = 0;
+  while (K0 < n) {
+    const int b = std::min(DB, n - K0);
+    const int K1 = K0 + b;
+    diag_step<T>(st, A, lda, sA, K0, b, Linv, sL, diag_block_index(K0, 0), batch, info);
+    const int rest = n - K1;
+    if (rest > 0) {
+      T* panel = A + (int64_t)K1 * lda + K0;
+      const T* li = Linv + (int64_t)diag_block_index(K0, 0) * DB * DB;
+      gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
+    }
+    (void)hipEventRecord(ev, st);
+    (void)hipStreamWaitEvent(st2, ev, 0);
+    tri_inverse_step<T>(st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, tmp, sT, K0, b);
+    if (rest > 0) {
+      T* panel = A + (int64_t)K1 * lda + K0;
+      gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
+              lda, sA, batch, GEMM_LOWER);
+    }
+    K0 = K1;
+  }
+  (void)hipEventRecord(ev, st2);
+  (void)hipStreamWaitEvent(st, ev, 0);
+  (void)hipEventDestroy(ev);
+  return 0;
 }
 
 template <typename T, typename TO>
@@ -739,7 +1044,9 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template int gemm_autotune<T>(int, int, int, int, int, int, int);                              \
   template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*); \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
-                               int64_t, T*, int64_t, int64_t, T*, int64_t);
+                               int64_t, T*, int64_t, int64_t, T*, int64_t);                        \
+  template int cholesky_inverse<T>(hipStream_t, hipStream_t, T*, int64_t, int64_t, int, int, T*, int64_t, int*, \
+                                   T*, int64_t, T*, int64_t);
 INST(double)
 INST(float)
 #undef INST
