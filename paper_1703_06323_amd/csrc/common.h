@@ -104,8 +104,10 @@ void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int3
                     int32_t* status, double* relres, int32_t* n_active);
 void launch_cg_check(hipStream_t st, int P, const double* params, const double* S, int32_t* active,
                      int32_t* it, int32_t* status, double* relres, int32_t* n_active);
+// x, r update; zero1 and zero2 (may be null) are cleared on the same nodes.
 void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
-                         const double* q, double* x, double* r);
+                         const double* q, double* x, double* r, double* zero1, double* zero2);
+// p update, then rho = rho_new.
 void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
                         double* p);
 void launch_set_params(hipStream_t st, double* params, double rtol, int32_t max_iter);

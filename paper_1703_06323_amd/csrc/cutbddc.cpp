@@ -285,6 +285,8 @@ struct cb_ctx {
   void* pin = nullptr;
   // second stream for work that overlaps the coarse factorisation
   hipStream_t aux_st = nullptr;
+  hipEvent_t aux_ev = nullptr;
+  hipEvent_t nact_ev = nullptr;   // readback of the running-problem count
   // captured PCG iteration
   hipStream_t cap_st = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -295,6 +297,8 @@ struct cb_ctx {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (cap_st) (void)hipStreamDestroy(cap_st);
     if (aux_st) (void)hipStreamDestroy(aux_st);
+    if (aux_ev) (void)hipEventDestroy(aux_ev);
+    if (nact_ev) (void)hipEventDestroy(nact_ev);
     if (pin) (void)hipHostFree(pin);
     for (auto& kv : prof_ev)
       for (auto& e : kv.second.ev) {
@@ -390,15 +394,16 @@ int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked) {
 
 // z = M r on grid vectors (eq. bddc), steps (1)-(7), for every problem (or,
 // masked, for the problems whose PCG still runs).
-int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked) {
+int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked, bool cleared = false) {
   hipStream_t st = c->st;
   const SubDev sd = c->sub(0, masked);
   const int64_t nn = c->nn;
   double* t1 = c->t1.as<double>();
   double* t2 = c->t2.as<double>();
   double* t3 = c->t3.as<double>();
-  // (1) delta_I = A_II^{-1} r_I
-  launch_fill(st, nn, 0.0, t1);
+  // (1) delta_I = A_II^{-1} r_I (t1 and z start at zero: cleared here or,
+  // within a PCG iteration, by the x, r update)
+  if (!cleared) launch_fill(st, nn, 0.0, t1);
   timed(c, "apply_interior", [&] {
     if (c->precision == CB_FP32_LOCAL)
       launch_apply_interior<float>(st, sd, c->ns, c->P_.as<float>(), r, nullptr, t1);
@@ -427,7 +432,7 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked) {
     launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
   // (6) weighted average on the interface
-  launch_fill(st, nn, 0.0, z);
+  if (!cleared) launch_fill(st, nn, 0.0, z);
   launch_iface_average(st, c->n_iface_tot, c->iface_node.as<int64_t>(), c->if_ptr.as<int64_t>(),
                        c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(), c->NGp, c->Dw.as<double>(),
                        c->zbuf.as<double>(), z);
@@ -447,8 +452,9 @@ void dot(cb_ctx* c, const double* a, const double* b, int slot, bool masked) {
              c->scal.as<double>() + slot, CG_S);
 }
 
-// One PCG iteration for every running problem: q = A p, x and r update,
-// convergence test, z = M r, p update.
+// One PCG iteration for every running problem: q = A p, x and r update
+// (which also clears the preconditioner's scratch vectors), convergence
+// test, z = M r, p update.
 int pcg_body(cb_ctx* c) {
   hipStream_t st = c->st;
   double* S = c->scal.as<double>();
@@ -456,11 +462,11 @@ int pcg_body(cb_ctx* c) {
   CHK(apply_A_grid(c, c->p.as<double>(), c->q.as<double>(), true));
   dot(c, c->p.as<double>(), c->q.as<double>(), 1, true);
   launch_cg_update_xr(st, bm, c->nn, S, c->p.as<double>(), c->q.as<double>(), c->x.as<double>(),
-                      c->r.as<double>());
+                      c->r.as<double>(), c->t1.as<double>(), c->z.as<double>());
   dot(c, c->r.as<double>(), c->r.as<double>(), 2, true);
   launch_cg_check(st, c->P, c->params.as<double>(), S, c->active.as<int32_t>(), c->itc.as<int32_t>(),
                   c->status.as<int32_t>(), c->relres_d.as<double>(), c->nact_d.as<int32_t>());
-  CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true));
+  CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true, true));
   dot(c, c->r.as<double>(), c->z.as<double>(), 3, true);
   launch_cg_update_p(st, bm, c->nn, S, c->z.as<double>(), c->p.as<double>());
   return CB_OK;
@@ -533,12 +539,32 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
     HIPCHK(hipGetLastError());
     const bool use_graph = graphs_enabled() && !c->prof;
     if (use_graph) CHK(capture_body(c));
-    while (n_active > 0 && k <= max_iter) {
+    if (!c->nact_ev) HIPCHK(hipEventCreateWithFlags(&c->nact_ev, hipEventDisableTiming));
+    auto issue = [&]() -> int {
       if (use_graph && c->graph) HIPCHK(hipGraphLaunch(c->graph, st));
       else CHK(pcg_body(c));
       HIPCHK(hipGetLastError());
       ++k;
-      CHK(read_active(c, &n_active));
+      return CB_OK;
+    };
+    auto queue_read = [&]() -> int {
+      HIPCHK(hipMemcpyAsync(c->pin_nact(), c->nact_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipEventRecord(c->nact_ev, st));
+      return CB_OK;
+    };
+    // One iteration stays queued ahead of the host's convergence readback:
+    // the readback after iteration k overlaps iteration k+1, which is a
+    // masked no-op for every problem that has stopped (the device stops a
+    // problem at its own max_iter, so the loop always ends).
+    CHK(issue());
+    CHK(queue_read());
+    for (;;) {
+      const bool ahead = k <= max_iter;
+      if (ahead) CHK(issue());
+      HIPCHK(hipEventSynchronize(c->nact_ev));
+      n_active = *c->pin_nact();
+      if (n_active == 0 || !ahead) break;
+      CHK(queue_read());
     }
   }
   HIPCHK(hipMemcpyAsync(c->pin_it(), c->itc.p, c->P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1031,6 +1057,8 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
   CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
   CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
+  if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
+  if (!c->aux_ev) HIPCHK(hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
   const int n_info = ns + 1 + c->P;
   CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
   HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
@@ -1055,6 +1083,14 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
   CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
   CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
+  // on every exit, st waits for the second stream before the buffers above
+  // return to the cache (destroyed after this guard)
+  struct AuxJoin {
+    cb_ctx* c;
+    ~AuxJoin() {
+      if (hipEventRecord(c->aux_ev, c->aux_st) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev, 0);
+    }
+  } aux_join{c};
 
   for (int w0 = 0; w0 < ns; w0 += chunk) {
     const int nc = std::min(chunk, ns - w0);
@@ -1112,11 +1148,19 @@ int factor_impl(cb_ctx* c) {
     gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
                  V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
                  nc, 0);
-    // Kt = K_S^{-1} - Phi G^T, packed
-    launch_pack_interface<T>(st, NGp, NCp, nc, KS, Phiw, G.as<double>(), c->Kt.as<T>() + (int64_t)w0 * pkG);
+    // Kt = K_S^{-1} - Phi G^T, packed; for the last chunk on the second
+    // stream, where it overlaps the coarse factorisation (nothing later on
+    // st touches its inputs, which stay allocated until the streams join)
+    if (w0 + nc < ns) {
+      launch_pack_interface<T>(st, NGp, NCp, nc, KS, Phiw, G.as<double>(), c->Kt.as<T>() + (int64_t)w0 * pkG);
+    } else {
+      HIPCHK(hipEventRecord(c->aux_ev, st));
+      HIPCHK(hipStreamWaitEvent(c->aux_st, c->aux_ev, 0));
+      launch_pack_interface<T>(c->aux_st, NGp, NCp, nc, KS, Phiw, G.as<double>(),
+                               c->Kt.as<T>() + (int64_t)w0 * pkG);
+    }
     HIPCHK(hipGetLastError());
   }
-  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
   launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
                  NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
   HIPCHK(hipGetLastError());
@@ -1159,7 +1203,6 @@ int factor_impl(cb_ctx* c) {
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
       double* A = Ac.as<double>() + gr.ac_off;
       // the triangular inverse trails the factorisation on a second stream
-      if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
       if (cholesky_inverse<double>(st, c->aux_st, A, L, sA, L, nb, Lc.as<double>(), sLc,
                                    c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA, Tc.as<double>(),
                                    (int64_t)TRI_SUPER * L) != 0) {
@@ -1175,6 +1218,10 @@ int factor_impl(cb_ctx* c) {
       slot += nb;
     }
   }
+  // join the second stream before the chunk buffers go back to the cache
+  HIPCHK(hipEventRecord(c->aux_ev, c->aux_st));
+  HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
+  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
   std::vector<int> info(n_info);
   HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));

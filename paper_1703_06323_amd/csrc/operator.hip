@@ -173,11 +173,14 @@ __global__ void copy_kernel(int64_t n, const double* __restrict__ src, double* _
   if (i < n) dst[i] = src[i];
 }
 
-// x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem.
+// x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem;
+// zero1 and zero2 (may be null) are cleared on the same nodes (the
+// preconditioner's scratch vectors, so that they need no fill of their own).
 __global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t nn, const double* __restrict__ S,
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q, double* __restrict__ x,
-                                                           double* __restrict__ r) {
+                                                           double* __restrict__ r, double* __restrict__ zero1,
+                                                           double* __restrict__ zero2) {
   const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
   const int64_t i = base + threadIdx.x;
   if (i >= nn) return;
@@ -186,6 +189,8 @@ __global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t 
   const double alpha = S[CG_S * pb + 0] / S[CG_S * pb + 1];
   x[i] += alpha * p[i];
   r[i] -= alpha * q[i];
+  if (zero1) zero1[i] = 0.0;
+  if (zero2) zero2[i] = 0.0;
 }
 
 // p = z + beta p with beta = rho_new / rho; the swap rho = rho_new is a
@@ -256,11 +261,10 @@ __global__ __launch_bounds__(256) void cg_init_kernel(int P, const double* __res
 }
 
 // After the x, r update of an iteration: count it, test |r| < rtol |b|, a
-// non-finite residual, and the iteration limit.
-__global__ __launch_bounds__(256) void cg_check_kernel(int P, const double* __restrict__ params,
-                                                       const double* __restrict__ S, int32_t* __restrict__ active,
-                                                       int32_t* __restrict__ it, int32_t* __restrict__ status,
-                                                       double* __restrict__ relres, int32_t* __restrict__ n_active) {
+// non-finite residual, and the iteration limit (one workgroup of 256).
+__device__ void cg_check_block(int P, const double* __restrict__ params, const double* S,
+                               int32_t* __restrict__ active, int32_t* __restrict__ it, int32_t* __restrict__ status,
+                               double* __restrict__ relres, int32_t* __restrict__ n_active) {
   const double rtol = params[0];
   const int32_t max_iter = (int32_t)params[1];
   for (int p = threadIdx.x; p < P; p += 256) {
@@ -285,6 +289,13 @@ __global__ __launch_bounds__(256) void cg_check_kernel(int P, const double* __re
   }
   __syncthreads();
   count_active(P, active, n_active);
+}
+
+__global__ __launch_bounds__(256) void cg_check_kernel(int P, const double* __restrict__ params,
+                                                       const double* __restrict__ S, int32_t* __restrict__ active,
+                                                       int32_t* __restrict__ it, int32_t* __restrict__ status,
+                                                       double* __restrict__ relres, int32_t* __restrict__ n_active) {
+  cg_check_block(P, params, S, active, it, status, relres, n_active);
 }
 
 __global__ void gather_dofs_batch_kernel(int P, int64_t n, const int64_t* __restrict__ dof_off,
@@ -404,9 +415,9 @@ void launch_copy(hipStream_t st, int64_t n, const double* src, double* dst) {
 }
 
 void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
-                         const double* q, double* x, double* r) {
+                         const double* q, double* x, double* r, double* zero1, double* zero2) {
   hipLaunchKernelGGL(cg_update_xr_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, p, q,
-                     x, r);
+                     x, r, zero1, zero2);
 }
 
 void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
