@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (profiles/
 # apply_interior_cut_cube_64_traffic.md), each scaled by the same counter on
 # a copy of known size (FETCH x 2.0, WRITE x 1.0).  Valid for the packed
-# symmetric apply kernel; set to None when that kernel changes.
-APPLY_INTERIOR_TRAFFIC_BYTES = 258.0e6
+# symmetric apply kernel as it stands; set to None when that kernel changes.
+APPLY_INTERIOR_TRAFFIC_BYTES = 277.9e6
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix
 
@@ -52,6 +52,10 @@ def parse():
 
 
 def run_steps(problem, f_dev, steps, warmup, rtol, profile):
+    """Times `steps` setup + factor + solve cycles on the production path.
+    With profile, one more (untimed) cycle follows with the library's
+    per-group event timing, and the dominant kernel's average launch
+    duration is taken from back-to-back launches on that context."""
     import torch
     from paper_1703_06323_amd import Solver
 
@@ -64,7 +68,7 @@ def run_steps(problem, f_dev, steps, warmup, rtol, profile):
         info = s.info()
         kt = s.profile_times() if prof else {}
         if prof:
-            kt["apply_interior_launch_ms"] = s.profile_launches("apply_interior")
+            kt["apply_interior_avg_ms"] = s.time_kernel("apply_interior", 20)
         s.close()
         return it, rel, info, kt
 
@@ -72,10 +76,11 @@ def run_steps(problem, f_dev, steps, warmup, rtol, profile):
         one(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [one(profile) for _ in range(steps)]
+    res = [one(False) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, res
+    kt = one(True)[3] if profile else {}
+    return dt, res, kt
 
 
 def run_batch(steps, warmup, rtol):
@@ -187,8 +192,8 @@ def main():
     p64 = W.cut_cube_64()
     f_dev = torch.tensor(p64.f, dtype=torch.float64, device="cuda")
 
-    dt64, res64 = run_steps(p64, f_dev, args.steps, args.warmup, args.rtol, profile=True)
-    it64, rel64, info64, kt64 = res64[-1]
+    dt64, res64, kt64 = run_steps(p64, f_dev, args.steps, args.warmup, args.rtol, profile=True)
+    it64, rel64, info64, _ = res64[-1]
     n_dof = int(info64["n_dof"])
     out = {
         "metric": "DOFs solved/s to rtol 1e-8 (FP32-precond vs FP64) + MFMA util / HBM GB/s",
@@ -217,7 +222,7 @@ def main():
         from paper_1703_06323_amd import CBError
         p32 = p64.with_options(local_precision=1)
         try:
-            dt32, res32 = run_steps(p32, f_dev, args.steps, args.warmup, args.rtol, profile=False)
+            dt32, res32, _ = run_steps(p32, f_dev, args.steps, args.warmup, args.rtol, profile=False)
         except CBError as e:
             res32 = None
             out["fp32_local"] = {"error": str(e)}
@@ -232,37 +237,47 @@ def main():
     if not args.no_batch:
         out["batch_256"] = run_batch(args.batch_steps, 1, args.rtol)
     out["roofline"] = roofline(kt64, info64)
+    out["mfma"] = mfma_util(kt64, info64)
     out["kernel_ms"] = {k: {"total_ms": round(v[0], 4), "launches": v[1]} for k, v in kt64.items()
-                        if k != "apply_interior_launch_ms"}
+                        if k != "apply_interior_avg_ms"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 
 def roofline(kt, info):
-    """Dominant kernel's achieved rate from the library's live HIP-event
-    timing of its launches during the last timed step (see the design doc for
-    the algorithmic byte count)."""
-    import numpy as np
-    d = kt.get("apply_interior_launch_ms")
-    if d is None or len(d) == 0:
+    """Dominant kernel's achieved rate: algorithmic bytes per launch over
+    the average launch duration that the library measures with two HIP
+    events around 20 back-to-back launches on the context stream."""
+    avg_ms = kt.get("apply_interior_avg_ms")
+    if not avg_ms:
         return None
-    # the preconditioner issued after the convergence test of the last
-    # iteration runs masked (its launches return at once); average over the
-    # launches that did the work
-    full = d[d >= 0.25 * np.median(d)]
-    total_ms, launches = float(full.sum()), int(full.size)
     # per launch: the unique entries of every subdomain's symmetric
     # Dirichlet inverse (lower triangle with diagonal, 8 B each) plus the
     # gathered input(s) and the scattered output (2 vectors on the first
     # launch of an apply, 3 on the second: 2.5 on average)
     alg_bytes = 8.0 * (info["sum_nI2"] + info["sum_nI"]) / 2.0 + 8.0 * 2.5 * info["sum_nI"]
-    avg_s = total_ms / launches * 1e-3
+    avg_s = avg_ms * 1e-3
     achieved = alg_bytes / avg_s / 1e9
     return {"bound": "hbm", "kernel": "apply_interior_kernel<double>", "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": APPLY_INTERIOR_TRAFFIC_BYTES, "avg_launch_us": avg_s * 1e6,
             "alg_bytes_per_launch": alg_bytes}
+
+
+def mfma_util(kt, info):
+    """MFMA utilisation of the subdomain factorisations (FP64 path): the
+    algorithmic Cholesky flops, sum over subdomains of n_N^3/3 + n_I^3/3 with
+    active DOFs only, over the event-timed blocked Cholesky of all local
+    matrices (diagonal blocks, panels and trailing updates), against the
+    dense FP64 peak."""
+    v = kt.get("local_cholesky")
+    if not v or v[0] <= 0:
+        return None
+    flops = float(info["flops_local_chol"])
+    tf = flops / (v[0] * 1e-3) / 1e12
+    return {"kernel": "local Cholesky (blocked, FP64)", "flops": flops, "ms": v[0], "achieved": tf,
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS}
 
 
 if __name__ == "__main__":

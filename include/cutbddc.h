@@ -183,6 +183,14 @@ int cb_profile_time(cb_ctx* c, const char* name, double* total_ms, int64_t* laun
  * `cap` values are written to ms (host array); *n receives the number of
  * launches recorded.  Synchronises the stream. */
 int cb_profile_launches(cb_ctx* c, const char* name, double* ms, int64_t cap, int64_t* n);
+/* Average duration (ms) of one launch of a preconditioner kernel over `reps`
+ * back-to-back launches on the context stream, bracketed by two HIP events
+ * (so that launch gaps do not count): which = 0 the Dirichlet inverse
+ * product (apply_interior, input r), 1 the interface operator product
+ * (apply_neumann).  The kernels write only the context's scratch vectors.
+ * Needs a factored context; synchronises the stream.  CB_ERR_STATE before
+ * cb_factor, CB_ERR_ARG for reps < 1 or an unknown kernel. */
+int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms);
 
 /* Host copies of the integer data of the discretisation (bit-exact parity).
  * Each output pointer may be NULL; sizes come from cb_query / cb_export_sizes.

@@ -1706,6 +1706,44 @@ int cb_profile_launches(cb_ctx* c, const char* name, double* ms, int64_t cap, in
   return CB_OK;
 }
 
+int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms) {
+  if (!c || !avg_ms || reps < 1 || which < 0 || which > 1) return fail(CB_ERR_ARG, "invalid argument");
+  if (!c->factored) return fail(CB_ERR_STATE, "kernel timing requested before cb_factor");
+  hipStream_t st = c->st;
+  const SubDev sd = c->sub(0, false);
+  const bool f32 = c->precision == CB_FP32_LOCAL;
+  auto launch = [&] {
+    if (which == 0) {
+      if (f32) launch_apply_interior<float>(st, sd, c->ns, c->P_.as<float>(), c->r.as<double>(), nullptr,
+                                            c->t1.as<double>());
+      else launch_apply_interior<double>(st, sd, c->ns, c->P_.as<double>(), c->r.as<double>(), nullptr,
+                                         c->t1.as<double>());
+    } else {
+      if (f32) launch_apply_neumann<float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi.as<double>(),
+                                           c->Dw.as<double>(), c->r.as<double>(), c->t2.as<double>(),
+                                           c->zbuf.as<double>(), c->cloc.as<double>());
+      else launch_apply_neumann<double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
+                                        c->Dw.as<double>(), c->r.as<double>(), c->t2.as<double>(),
+                                        c->zbuf.as<double>(), c->cloc.as<double>());
+    }
+  };
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  launch();   // warm
+  HIPCHK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) launch();
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return CB_OK;
+}
+
 void cb_destroy(cb_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);

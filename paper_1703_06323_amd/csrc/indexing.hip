@@ -172,8 +172,16 @@ __device__ inline int mask_rank(uint32_t mask, int I, int J, int K, int s, int B
 }
 
 // ---- union-find ---------------------------------------------------------
+// Walks read parents with cacheable loads (relaxed atomics of workgroup
+// scope), which may return an out-of-date parent: every value ever stored
+// in par[x] is an ancestor of x (smaller, same set), so a walk still ends at
+// a node that is or was a root, and a hook on a node that is no longer a
+// root fails its compare-and-swap (agent scope) and is retried from the
+// parent the swap returns.  Stores (path halving, only ever on non-roots)
+// are agent-scope, so no cached copy can overwrite a hook.  Agent-coherent
+// loads would be correct too but pay a memory round trip per step.
 __device__ inline int32_t uf_load(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ inline int32_t uf_find(int32_t* par, int32_t x) {
   int32_t cur = uf_load(&par[x]);
@@ -220,13 +228,14 @@ __global__ __launch_bounds__(IT) void zero_i32_kernel(int64_t n, int32_t* a, int
     if (b) b[i] = 0;
   }
 }
-// After all joins: par[i] = root of i.  The walk itself writes nothing, so
-// the only store to par[i] is this thread's (and it stores the root).
+// After all joins: par[i] = root of i.  The walk reads coherent values and
+// writes nothing, so the only store to par[i] is this thread's (and it
+// stores the root).
 __global__ __launch_bounds__(IT) void compress_kernel(int64_t n, int32_t* par) {
   const int64_t i = (int64_t)blockIdx.x * IT + threadIdx.x;
   if (i >= n) return;
   int32_t r = (int32_t)i, q;
-  while ((q = uf_load(&par[r])) != r) r = q;
+  while ((q = __hip_atomic_load(&par[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != r) r = q;
   par[i] = r;
 }
 

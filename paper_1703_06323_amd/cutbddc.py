@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.cb_profile.argtypes = [vp, C.c_int32]
     lib.cb_profile_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.cb_profile_launches.argtypes = [vp, C.c_char_p, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.cb_time_kernel.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     lib.cb_dense_spd_inverse.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp]
     lib.cb_setup_batch.argtypes = [C.POINTER(cb_problem), C.c_int32, vp, C.POINTER(vp)]
     lib.cb_solve_batch.argtypes = [vp, vp, vp, C.c_double, C.c_int32, ip, dp]
@@ -95,7 +96,8 @@ def load_library(path: str = LIB_PATH):
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
                  "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
                  "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing",
-                 "cb_setup_batch", "cb_solve_batch", "cb_query_problem", "cb_profile_launches"):
+                 "cb_setup_batch", "cb_solve_batch", "cb_query_problem", "cb_profile_launches",
+                 "cb_time_kernel"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -231,6 +233,14 @@ class Solver:
             if n.value:
                 out[name] = (float(t.value), int(n.value))
         return out
+
+    def time_kernel(self, which: str, reps: int = 20) -> float:
+        """Average launch duration (ms) of "apply_interior" or "apply_neumann"
+        over `reps` back-to-back launches (cb_time_kernel)."""
+        code = {"apply_interior": 0, "apply_neumann": 1}[which]
+        ms = C.c_double()
+        _check(_lib.cb_time_kernel(self.ctx, code, int(reps), C.byref(ms)))
+        return ms.value
 
     def profile_launches(self, name: str) -> np.ndarray:
         """Durations (ms) of every bracketed launch of one kernel group."""
