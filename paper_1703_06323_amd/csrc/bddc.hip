@@ -235,45 +235,51 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, 
     load_block_cells(g, pr, blk % m, (blk / m) % m, blk / (m * m), cinfo, ckh);
   }
   __syncthreads();
-  if (tid < LA_ROWS) {
-    for (int k = 0; k < 27; ++k) {
-      sval[tid][k] = 0.0;
-      scol[tid][k] = -1;
-    }
-    const int r = rb + tid;
+  // rows of A_omega, one task per (row, neighbour slot): the entry couples
+  // the row's node with neighbour k and sums, in a fixed cell order, over
+  // the active cells of the block that contain both nodes
+  {
+    const ProbDev pr = g.prob[sd.sub_prob[w]];
+    const int s = g.s, m = pr.m, s1 = s + 1, N1 = pr.N + 1;
+    const int blk = sd.sub_blk[w];
+    const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
+    const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
     const int nI = sd.nI[w], nG = sd.nG[w];
-    int64_t n = -1;
-    if (r < r0 + nrows) {
-      if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
-      else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
-    }
-    if (n >= 0) {
-      const ProbDev pr = g.prob[sd.sub_prob[w]];
-      const int s = g.s, m = pr.m, N = pr.N, s1 = s + 1, N1 = pr.N + 1;
-      const int blk = sd.sub_blk[w];
-      const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
-      const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
-      const int l = (int)(n - pr.node_off);
-      const int I = l % N1, J = (l / N1) % N1, Kk = l / (N1 * N1);
-      const int lx = I - Bx * s, ly = J - By * s, lz = Kk - Bz * s;
-      for (int u = 0; u < 8; ++u) {
-        const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
-        if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-        const int lc = cx + s * (cy + s * cz);
-        const int32_t info = cinfo[lc];
-        if (info == CELL_INACTIVE) continue;
-        const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-        const double sc = ckh[lc];
-        for (int b = 0; b < 8; ++b) {
-          const int bx = cx + (b & 1), by = cy + ((b >> 1) & 1), bz = cz + ((b >> 2) & 1);
-          const int col = loc[bx + s1 * (by + s1 * bz)];
-          if (col < 0) continue;
-          const int slot = (bx - lx + 1) + 3 * (by - ly + 1) + 9 * (bz - lz + 1);
-          const double kab = info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
-          sval[tid][slot] += sc * kab;
-          scol[tid][slot] = col;
+    for (int task = tid; task < LA_ROWS * 27; task += blockDim.x) {
+      const int rr = task / 27, k = task - rr * 27;
+      const int r = rb + rr;
+      int64_t n = -1;
+      if (r < r0 + nrows) {
+        if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
+        else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
+      }
+      double v = 0.0;
+      int col = -1;
+      if (n >= 0) {
+        const int l = (int)(n - pr.node_off);
+        const int lx = l % N1 - Bx * s, ly = (l / N1) % N1 - By * s, lz = l / (N1 * N1) - Bz * s;
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        const int bx = lx + dx, by = ly + dy, bz = lz + dz;
+        if (bx >= 0 && by >= 0 && bz >= 0 && bx <= s && by <= s && bz <= s) col = loc[bx + s1 * (by + s1 * bz)];
+        if (col >= 0) {
+          for (int u = 0; u < 8; ++u) {
+            const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
+            if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
+            // the cell must also contain the neighbour
+            if (bx < cx || bx > cx + 1 || by < cy || by > cy + 1 || bz < cz || bz > cz + 1) continue;
+            const int lc = cx + s * (cy + s * cz);
+            const int32_t info = cinfo[lc];
+            if (info == CELL_INACTIVE) continue;
+            const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
+            const int b = (bx - cx) + 2 * (by - cy) + 4 * (bz - cz);
+            const double kab =
+                info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
+            v += ckh[lc] * kab;
+          }
         }
       }
+      sval[rr][k] = v;
+      scol[rr][k] = col;
     }
   }
   __syncthreads();

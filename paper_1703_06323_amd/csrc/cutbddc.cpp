@@ -1044,7 +1044,6 @@ int factor_impl(cb_ctx* c) {
   const int64_t sK = (int64_t)nt * nt;
   const int64_t sL = (int64_t)diag_blocks(nt, NIp) * DB * DB;
   const int64_t sY = (int64_t)nbig * nbig;
-  const int64_t sT = (int64_t)TRI_SUPER * nbig;
   const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp, sF = (int64_t)nt * NCp;
   const int64_t sP = (int64_t)NIp * NIp, sKS = (int64_t)NGp * NGp;
 
@@ -1068,15 +1067,14 @@ int factor_impl(cb_ctx* c) {
 
   // work buffers for a chunk of subdomains
   const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
-                         (size_t)sT * sizeof(T) + (size_t)sP * 8 + (size_t)sKS * 8 +
+                         (size_t)sP * 8 + (size_t)sKS * 8 +
                          (size_t)(sG + sC + 2 * sF) * sizeof(double);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
-  DevBuf K, Linv, Y, PS, Tmp, Pd64, KSw, G, Sc, PhiF, V;
+  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V;
   CHK(dalloc(K, (size_t)chunk * sK * sizeof(T)));
   CHK(dalloc(Linv, (size_t)chunk * sL * sizeof(T)));
   CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
   CHK(dalloc(PS, (size_t)chunk * sY * sizeof(T)));
-  CHK(dalloc(Tmp, (size_t)chunk * sT * sizeof(T)));
   CHK(dalloc(Pd64, (size_t)chunk * sP * sizeof(double)));
   CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
   CHK(dalloc(G, (size_t)chunk * sG * sizeof(double)));
@@ -1106,8 +1104,7 @@ int factor_impl(cb_ctx* c) {
     HIPCHK(hipGetLastError());
     // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY, Tmp.as<T>(),
-                     sT);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY);
       gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
@@ -1118,8 +1115,7 @@ int factor_impl(cb_ctx* c) {
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, Tmp.as<T>(),
-                     sT);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY);
       gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
@@ -1181,19 +1177,17 @@ int factor_impl(cb_ctx* c) {
       CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
       launch_copy(st, c->ac_total, Ac.as<double>(), c->AcKeep.as<double>());
     }
-    size_t maxL = 0, maxLL = 0, maxB = 0, maxD = 0;
+    size_t maxL = 0, maxLL = 0, maxD = 0;
     for (const CoarseGroup& gr : c->groups) {
       maxL = std::max(maxL, (size_t)gr.ldc);
       maxLL = std::max(maxLL, (size_t)gr.ldc * gr.ldc * gr.probs.size());
-      maxB = std::max(maxB, gr.probs.size() * (size_t)gr.ldc);
       maxD = std::max(maxD, gr.probs.size() * (size_t)diag_blocks(gr.ldc, 0) * DB * DB);
     }
-    DevBuf Lc, Yc, PSc, Tc, ones;
+    DevBuf Lc, Yc, PSc, ones;
     const std::vector<double> onesv(maxL, 1.0);
     CHK(dalloc(Lc, maxD * sizeof(double)));
     CHK(dalloc(Yc, maxLL * sizeof(double)));
     CHK(dalloc(PSc, maxLL * sizeof(double)));
-    CHK(dalloc(Tc, maxB * TRI_SUPER * sizeof(double)));
     CHK(upload(ones, onesv, st));
     ProfScope cps(c, "coarse_factor");
     int slot = 0;
@@ -1203,12 +1197,10 @@ int factor_impl(cb_ctx* c) {
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
       double* A = Ac.as<double>() + gr.ac_off;
       // the triangular inverse trails the factorisation on a second stream
-      if (cholesky_inverse<double>(st, c->aux_st, A, L, sA, L, nb, Lc.as<double>(), sLc,
-                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA, Tc.as<double>(),
-                                   (int64_t)TRI_SUPER * L) != 0) {
+      if (cholesky_inverse<double>(st, c->aux_st, c->aux_ev, A, L, sA, L, nb, Lc.as<double>(), sLc,
+                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA) != 0) {
         cholesky<double>(st, A, L, sA, L, 0, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
-        tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA,
-                            Tc.as<double>(), (int64_t)TRI_SUPER * L);
+        tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA);
       }
       gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
                    L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
@@ -1221,7 +1213,7 @@ int factor_impl(cb_ctx* c) {
   // join the second stream before the chunk buffers go back to the cache
   HIPCHK(hipEventRecord(c->aux_ev, c->aux_st));
   HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
-  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Tmp, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
+  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
   std::vector<int> info(n_info);
   HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1314,17 +1306,21 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
     CHK(dalloc(dOut, (size_t)batch * nn * sizeof(double)));
     CHK(upload(dOnes, std::vector<double>((size_t)batch * np, 1.0), nullptr));
     CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
-    DevBuf dT;
-    CHK(dalloc(dT, (size_t)batch * TRI_SUPER * np * sizeof(T)));
     // the factorisation with the overlapped triangular inverse, as for the
     // coarse matrices
     hipStream_t st2 = nullptr;
+    hipEvent_t ev = nullptr;
     HIPCHK(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
-    const int rc = cholesky_inverse<T>(nullptr, st2, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>(),
-                                       dY.as<T>(), nn, dT.as<T>(), (int64_t)TRI_SUPER * np);
-    (void)hipStreamSynchronize(st2);
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(st2);
+      return fail(CB_ERR_DEVICE, "event creation failed");
+    }
+    const int rc = cholesky_inverse<T>(nullptr, st2, ev, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL,
+                                       dInfo.as<int>(), dY.as<T>(), nn);
+    (void)hipDeviceSynchronize();
+    (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(st2);
-    if (rc != 0) return fail(CB_ERR_DEVICE, "event creation failed");
+    if (rc != 0) return fail(CB_ERR_DEVICE, "event record or wait failed");
     gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
             GEMM_LOWER | GEMM_KFROM_DIAG);
     symmetrize_scale<T, double>(nullptr, dP.as<T>(), np, nn, dOut.as<double>(), np, nn, dOnes.as<double>(), np, np,

@@ -56,21 +56,20 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
 
 // Y = inverse of the lower-triangular diagonal range [off, off+nb) of L
 // (off and off+nb block starts of the same split), from the diagonal-block
-// inverses written by cholesky().  tmp: workspace of TRI_SUPER * nb elements
-// per matrix (stride sT).
-constexpr int TRI_SUPER = DB;
+// inverses written by cholesky().
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT);
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY);
 
 // Cholesky of n x n matrices (no split) and Y = L^{-1} (as tri_inverse over
 // the whole range, Y with leading dimension lda and stride sY), the inverse
 // steps issued on st2 one block behind the factorisation so that they overlap
-// with it; st waits for st2 before returning.  Returns -1 if no event could
-// be created (nothing is issued then).
+// with it; st waits for st2 before returning.  ev: an event owned by the
+// caller, recorded and waited on at every step (it must outlive the work).
+// Returns -1 if an event record or wait fails.
 template <typename T>
-int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
-                     int64_t sL, int* info, T* Y, int64_t sY, T* tmp, int64_t sT);
+int cholesky_inverse(hipStream_t st, hipStream_t st2, hipEvent_t ev, T* A, int64_t lda, int64_t sA, int n, int batch,
+                     T* Linv, int64_t sL, int* info, T* Y, int64_t sY);
 
 // out = D sym(lower(in)) D, full storage.
 template <typename T, typename TO>

@@ -661,33 +661,12 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
   if (tid == 0 && bad && info && info[bz] == 0) info[bz] = bad;
 }
 
-// Copies the h x h inverse block `blk` of Linv into Y's diagonal block at
-// (i0, i0).
+// Y (nb x nb per matrix) = identity.
 template <typename T>
-__global__ __launch_bounds__(256) void set_diag_block_kernel(T* Y, int64_t ldy, int64_t sY, int i0, int h,
-                                                             const T* Linv, int64_t sL, int blk) {
-  const int64_t bz = blockIdx.y;
+__global__ __launch_bounds__(256) void eye_kernel(T* Y, int64_t ldy, int64_t sY, int nb) {
   const int r = blockIdx.x;
-  T* y = Y + bz * sY + (int64_t)(i0 + r) * ldy + i0;
-  const T* li = Linv + bz * sL + (int64_t)blk * DB * DB + (int64_t)r * DB;
-  for (int c = threadIdx.x; c < h; c += 256) y[c] = li[c];
-}
-
-// Copies an m x n block (row-major, ld) between buffers of a batch.
-template <typename T>
-__global__ __launch_bounds__(256) void copy_block_kernel(const T* src, int64_t lds, int64_t sS, T* dst,
-                                                         int64_t ldd, int64_t sD, int n) {
-  const int64_t bz = blockIdx.y;
-  const int r = blockIdx.x;
-  const T* a = src + bz * sS + (int64_t)r * lds;
-  T* b = dst + bz * sD + (int64_t)r * ldd;
-  for (int c = threadIdx.x; c < n; c += 256) b[c] = a[c];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void zero_kernel(T* Y, int64_t ldy, int64_t sY, int nb) {
-  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)blockIdx.x * ldy;
-  for (int c = threadIdx.x; c < nb; c += 256) y[c] = T(0);
+  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)r * ldy;
+  for (int c = threadIdx.x; c < nb; c += 256) y[c] = c == r ? T(1) : T(0);
 }
 
 // out (full symmetric, row-major nb x nb) = D * sym(lower(in)) * D
@@ -951,17 +930,15 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
 // below it, both final once the Cholesky sweep has passed that block.
 template <typename T>
 void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT, int S0,
-                      int h) {
+                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, int S0, int h) {
   const int send = S0 + h;
   const int blk = diag_block_index(off + S0, split);
   const T* li = Linv + (int64_t)blk * DB * DB;
-  hipLaunchKernelGGL(set_diag_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, Y, ldy, sY, S0, h, Linv, sLi, blk);
-  if (S0 > 0) {
-    gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), tmp, S0, sT, batch, 0);
-    hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, (const T*)tmp, (int64_t)S0, sT,
-                       Y + (int64_t)S0 * ldy, ldy, sY, S0);
-  }
+  // Y[S, 0:send] = inv(L_SS) R_S[:, 0:send]; R_S[:, S] is still the identity,
+  // so this also sets Y[S, S] = inv(L_SS).  In place: a single tile row
+  // reads only its own columns of R_S before writing them.
+  gemm<T>(st, 0, 0, h, send, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
+          sY, batch, 0);
   const int rest = nb - send;
   if (rest > 0) {
     const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
@@ -972,32 +949,29 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
 
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, T* tmp, int64_t sT) {
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY) {
   // Y = L_block^{-1} for the diagonal range [off, off+nb) of L (lower) by
   // block forward substitution on L Y = I over the factor's diagonal blocks
-  // S: Y holds the running right-hand side R; Y[S, S] = inv(L_SS),
-  // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0] (through tmp), and the rows below
-  // get one rank-|S| update.
-  hipLaunchKernelGGL(zero_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
+  // S: Y holds the running right-hand side R (initially I); Y[S, 0:send] =
+  // inv(L_SS) R_S[:, 0:send], and the rows below get one rank-|S| update.
+  hipLaunchKernelGGL(eye_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
   int S0 = 0;
   while (S0 < nb) {
     const int p = off + S0;
     const int lim = (split > 0 && p < split) ? std::min(split - off, nb) : nb;
     const int h = std::min(DB, lim - S0);
-    tri_inverse_step<T>(st, L, ldl, sL, off, nb, split, batch, Linv, sLi, Y, ldy, sY, tmp, sT, S0, h);
+    tri_inverse_step<T>(st, L, ldl, sL, off, nb, split, batch, Linv, sLi, Y, ldy, sY, S0, h);
     S0 += h;
   }
 }
 
 template <typename T>
-int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
-                     int64_t sL, int* info, T* Y, int64_t sY, T* tmp, int64_t sT) {
+int cholesky_inverse(hipStream_t st, hipStream_t st2, hipEvent_t ev, T* A, int64_t lda, int64_t sA, int n, int batch,
+                     T* Linv, int64_t sL, int* info, T* Y, int64_t sY) {
   // Cholesky sweep on st; block step k of the triangular inverse follows on
   // st2 as soon as the sweep has produced diagonal block k and the column
-  // block below it.
-  hipEvent_t ev;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return -1;
-  hipLaunchKernelGGL(zero_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
+  // block below it.  ev belongs to the caller (re-recorded for every step).
+  hipLaunchKernelGGL(eye_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
   int K0 = 0;
   while (K0 < n) {
     const int b = std::min(DB, n - K0);
@@ -1009,9 +983,8 @@ int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t
       const T* li = Linv + (int64_t)diag_block_index(K0, 0) * DB * DB;
       gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
     }
-    (void)hipEventRecord(ev, st);
-    (void)hipStreamWaitEvent(st2, ev, 0);
-    tri_inverse_step<T>(st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, tmp, sT, K0, b);
+    if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(st2, ev, 0) != hipSuccess) return -1;
+    tri_inverse_step<T>(st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, K0, b);
     if (rest > 0) {
       T* panel = A + (int64_t)K1 * lda + K0;
       gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
@@ -1019,9 +992,7 @@ int cholesky_inverse(hipStream_t st, hipStream_t st2, T* A, int64_t lda, int64_t
     }
     K0 = K1;
   }
-  (void)hipEventRecord(ev, st2);
-  (void)hipStreamWaitEvent(st, ev, 0);
-  (void)hipEventDestroy(ev);
+  if (hipEventRecord(ev, st2) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess) return -1;
   return 0;
 }
 
@@ -1044,9 +1015,9 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template int gemm_autotune<T>(int, int, int, int, int, int, int);                              \
   template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*); \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
-                               int64_t, T*, int64_t, int64_t, T*, int64_t);                        \
-  template int cholesky_inverse<T>(hipStream_t, hipStream_t, T*, int64_t, int64_t, int, int, T*, int64_t, int*, \
-                                   T*, int64_t, T*, int64_t);
+                               int64_t, T*, int64_t, int64_t);                                      \
+  template int cholesky_inverse<T>(hipStream_t, hipStream_t, hipEvent_t, T*, int64_t, int64_t, int, int, T*,  \
+                                   int64_t, int*, T*, int64_t);
 INST(double)
 INST(float)
 #undef INST
