@@ -55,8 +55,10 @@ template <> struct Vec16<double> {
 };
 
 // C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, BM x BN output
-// tile per 256-thread workgroup: four waves in a 2 x 2 arrangement, each
-// owning (BM/32) x (BN/32) MFMA 16x16 blocks.
+// tile per workgroup of (BM/32) x (BN/32) waves, each owning a 32 x 32
+// sub-tile (2 x 2 MFMA 16x16 blocks): larger tiles keep the per-wave
+// registers (and so the waves per SIMD) of the smallest one while sharing
+// the LDS operand tiles among more waves.
 //   TA = 0: A(i,k) = A[i*lda + k];  TA = 1: A(i,k) = A[k*lda + i]
 //   TB = 0: B(k,j) = B[k*ldb + j];  TB = 1: B(k,j) = B[j*ldb + k]
 // The K loop runs in stages of KT (128 bytes of k per row); both operand
@@ -72,7 +74,7 @@ template <> struct Vec16<double> {
 // B operand when each output tile reads only its own columns of B (and the
 // same for A and rows); the dispatcher keeps such calls on 64-wide tiles.
 template <typename T, int TA, int TB, int BM, int BN, int DEPTH = 1>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
+__global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
                                                    int64_t sC, int mode, int vec, int swz) {
@@ -80,10 +82,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
   constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int KT = 128 / sizeof(T);           // k per stage
   constexpr int LDK = KT + VW;                  // LDS row length (padded)
-  constexpr int WM = BM / 2, WN = BN / 2;       // per-wave outputs
+  constexpr int WGN = BN / 32;                  // waves along N
+  constexpr int NT = 64 * (BM / 32) * WGN;      // threads
+  constexpr int WM = 32, WN = 32;               // per-wave outputs
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
-  constexpr int AV = BM * KT / VW / 256;        // vectors per thread per stage
-  constexpr int BV = BN * KT / VW / 256;
+  constexpr int AV = BM * KT / VW / NT;         // vectors per thread per stage
+  constexpr int BV = BN * KT / VW / NT;
   static_assert(AV >= 1 && BV >= 1, "tile too small");
   __shared__ __align__(16) T As[2][BM][LDK];
   __shared__ __align__(16) T Bs[2][BN][LDK];
@@ -113,13 +117,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
   if (mode & GEMM_KTO_DIAG) kend = min(K, row0 + BM);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int wr = wv >> 1, wc = wv & 1;
+  const int wr = wv / WGN, wc = wv % WGN;
 
   V ra[AV], rb[BV], ra2[AV], rb2[BV];
   // tile coordinates (row or column index, k) of the first element of
   // vector q of this thread
   auto a_coord = [&](int q, int& i, int& k) {
-    const int v = tid + 256 * q;
+    const int v = tid + NT * q;
     if (TA == 0) {
       i = v / (KT / VW);
       k = (v % (KT / VW)) * VW;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, T alpha,
     }
   };
   auto b_coord = [&](int q, int& j, int& k) {
-    const int v = tid + 256 * q;
+    const int v = tid + NT * q;
     if (TB == 1) {
       j = v / (KT / VW);
       k = (v % (KT / VW)) * VW;
@@ -786,7 +790,8 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
   const int swz = gemm_xcd_swizzle() ? 1 : 0;
 #define GEMM_CASE(a, b, bm, bn)                                                                        \
   if (TA == a && TB == b && BM == bm && BN == bn) {                                                    \
-    hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
+    hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn>), grid, dim3(64 * (bm / 32) * (bn / 32)), 0, st, M, N, K, \
+                       alpha, A, lda,                                                                  \
                        sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz);                              \
     return;                                                                                            \
   }
