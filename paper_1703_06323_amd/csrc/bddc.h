@@ -46,11 +46,14 @@ void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const doub
 void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* Gt, double* Sc);
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info);
 // Coarse matrix of every problem p as its own ldc_p x ldc_p block at
-// Ac + ac_off_p (identity on the padding rows); prow_off[p] = first padded
-// row of problem p in the launch, prow_off[P] = total.  Ac zero-filled.
-void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows,
+// Ac + ac_off_p (identity on the padding rows; every entry written);
+// prow_off[p] = first padded row of problem p in the launch, prow_off[P] =
+// n_prows.  keep (may be null) receives the same values.  max_ldc = largest
+// ldc_p: rows up to COARSE_ASSEMBLE_LDS_LDC long are built in LDS.
+constexpr int COARSE_ASSEMBLE_LDS_LDC = 16384;
+void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows, int max_ldc,
                             const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,
-                            const double* AcLoc, double* Ac);
+                            const double* AcLoc, double* Ac, double* keep);
 // Symmetric operators in packed lower-block storage: SB x SB blocks (I, J),
 // J <= I, packed_blocks(n) blocks of SB*SB values per subdomain.
 constexpr int SB = 32;
@@ -60,11 +63,6 @@ inline int packed_elems(int n) { return (n / SB) * (n / SB + 1) / 2 * SB * SB; }
 template <typename TI, typename TO>
 void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,
                        int64_t sD, TO* out);
-// Packed Kt = K_S^{-1} - Phi G^T from K_S^{-1} (NGp x NGp, lower triangle
-// read), Phi (NGp x NCp) and Gt (NCp x NGp), per subdomain.
-template <typename TO>
-void launch_pack_interface(hipStream_t st, int NGp, int NCp, int ns, const double* KS, const double* Phi,
-                           const double* Gt, TO* out);
 // P, Kt: packed storage.
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,

@@ -371,57 +371,6 @@ __global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const d
   }
 }
 
-// Kernel 3f: the constrained-Neumann interface operator
-// Kt = K_S^{-1} - Phi G^T written straight into packed symmetric storage
-// (type TO).  One block per (packed block, subdomain): the 32 rows of Phi
-// and the 32 columns of G^T of the block are staged in LDS; thread t forms
-// column t % 32 of rows t / 32 + 8k (k < 4), sharing each G value over four
-// rows.  The block goes through an LDS tile so that the upper part of a
-// diagonal block is the mirror of its lower part (exact symmetry).
-template <typename TO>
-__global__ __launch_bounds__(256) void pack_interface_kernel(const double* __restrict__ KS, const double* __restrict__ Phi,
-                                                             const double* __restrict__ Gt, int NGp, int NCp,
-                                                             TO* __restrict__ out, int nbk) {
-  constexpr int VW = 16 / sizeof(TO);
-  extern __shared__ double lds_pk[];
-  const int64_t w = blockIdx.y;
-  const int q = blockIdx.x;
-  int I = 0;
-  while ((I + 1) * (I + 2) / 2 <= q) ++I;
-  const int J = q - I * (I + 1) / 2;
-  double* phiI = lds_pk;             // [SB][NCp] rows 32I.. of Phi
-  double* gJ = phiI + SB * NCp;      // [NCp][SB] columns 32J.. of Gt
-  double* tile = gJ + NCp * SB;      // [SB][SB + 1]
-  const double* ph = Phi + w * NGp * NCp;
-  const double* gt = Gt + w * NCp * NGp;
-  for (int e = threadIdx.x; e < SB * NCp; e += 256) {
-    phiI[e] = ph[(int64_t)SB * I * NCp + e];
-    const int tt = e / SB, c = e - tt * SB;
-    gJ[e] = gt[(int64_t)tt * NGp + SB * J + c];
-  }
-  __syncthreads();
-  const double* ks = KS + w * NGp * NGp;
-  const int c = threadIdx.x & (SB - 1), r0 = threadIdx.x >> 5;
-  double acc[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) acc[k] = ks[(int64_t)(SB * I + r0 + 8 * k) * NGp + SB * J + c];
-#pragma unroll 4
-  for (int t = 0; t < NCp; ++t) {
-    const double gv = gJ[t * SB + c];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] -= phiI[(r0 + 8 * k) * NCp + t] * gv;
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) tile[(r0 + 8 * k) * (SB + 1) + c] = acc[k];
-  __syncthreads();
-  TO* o = out + (w * nbk + q) * (int64_t)(SB * SB);
-  for (int e = threadIdx.x; e < SB * SB; e += 256) {
-    const int r = e / SB, cc = e - r * SB;
-    const double v = (I != J || cc <= r) ? tile[r * (SB + 1) + cc] : tile[cc * (SB + 1) + r];
-    o[packed_offset(r, cc, VW)] = (TO)v;
-  }
-}
-
 // Kernel 3e: in-place inverse of the SPD matrices S_c (NCp x NCp, identity
 // on padded rows) by Gauss-Jordan elimination in LDS.
 __global__ __launch_bounds__(256) void small_spd_inverse_kernel(SubDev sd, double* __restrict__ Sm, int* info) {
@@ -463,30 +412,46 @@ __global__ __launch_bounds__(256) void small_spd_inverse_kernel(SubDev sd, doubl
 }
 
 // Kernel 4: row c of problem p's coarse matrix = sum over the subdomains
-// touching coarse DOF c (ascending) of the matching row of A_c^w.  One
-// thread per padded row of the launch.
-__global__ void coarse_assemble_kernel(BatchDev bd, const int64_t* __restrict__ prow_off, int64_t n_prows,
-                                       const int64_t* __restrict__ cs_ptr, const int32_t* __restrict__ cs_sub,
-                                       const int32_t* __restrict__ cs_row, SubDev sd,
-                                       const double* __restrict__ AcLoc, double* __restrict__ Ac) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_prows) return;
+// touching coarse DOF c (ascending) of the matching row of A_c^w.
+// One workgroup per padded row: the row is accumulated in LDS by one wave
+// (the entries of one subdomain go to distinct columns; the subdomains
+// follow one another in program order, so every entry is summed in
+// ascending subdomain order) and then written whole, zeros included, to Ac
+// and, if given, to keep.  Padding rows are identity rows.
+template <bool IN_LDS>
+__global__ __launch_bounds__(256) void coarse_assemble_kernel(BatchDev bd, const int64_t* __restrict__ prow_off,
+                                                              const int64_t* __restrict__ cs_ptr,
+                                                              const int32_t* __restrict__ cs_sub,
+                                                              const int32_t* __restrict__ cs_row, SubDev sd,
+                                                              const double* __restrict__ AcLoc, double* Ac,
+                                                              double* __restrict__ keep) {
+  extern __shared__ double crow_lds[];
+  const int64_t q = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  if (q >= prow_off[bd.P]) return;
   const int p = find_segment(prow_off, bd.P, q);
   const ProbDev pr = bd.prob[p];
   const int lr = (int)(q - prow_off[p]);
-  double* row = Ac + pr.ac_off + (int64_t)lr * pr.ldc;   // zero-filled by the caller
-  if (lr >= pr.nc) {
-    row[lr] = 1.0;
-    return;
+  const int ldc = pr.ldc, tid = threadIdx.x;
+  const int64_t off = pr.ac_off + (int64_t)lr * ldc;
+  double* crow = IN_LDS ? crow_lds : Ac + off;   // rows too long for LDS are built in place
+  for (int i = tid; i < ldc; i += 256) crow[i] = i == lr && lr >= pr.nc ? 1.0 : 0.0;
+  __syncthreads();
+  if (lr < pr.nc && tid < 64) {
+    const int NCp = sd.NCp;
+    const int c = pr.coarse_off + lr;
+    for (int64_t z = cs_ptr[c]; z < cs_ptr[c + 1]; ++z) {
+      const int w = cs_sub[z], t = cs_row[z];
+      const int nC = sd.nC[w];
+      const double* src = AcLoc + ((int64_t)w * NCp + t) * NCp;
+      const int32_t* ids = sd.C_ids + (int64_t)w * NCp;
+      for (int u = tid; u < nC; u += 64) crow[ids[u] - pr.coarse_off] += src[u];
+    }
   }
-  const int NCp = sd.NCp;
-  const int c = pr.coarse_off + lr;
-  for (int64_t z = cs_ptr[c]; z < cs_ptr[c + 1]; ++z) {
-    const int w = cs_sub[z], t = cs_row[z];
-    const int nC = sd.nC[w];
-    const double* src = AcLoc + ((int64_t)w * NCp + t) * NCp;
-    const int32_t* ids = sd.C_ids + (int64_t)w * NCp;
-    for (int u = 0; u < nC; ++u) row[ids[u] - pr.coarse_off] += src[u];
+  __syncthreads();
+  for (int i = tid; i < ldc; i += 256) {
+    const double v = crow[i];
+    if (IN_LDS) Ac[off + i] = v;
+    if (keep) keep[off + i] = v;
   }
 }
 
@@ -801,30 +766,29 @@ void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const doub
                      sd, Gt, Sc);
 }
 
-template <typename TO>
-void launch_pack_interface(hipStream_t st, int NGp, int NCp, int ns, const double* KS, const double* Phi,
-                           const double* Gt, TO* out) {
-  if (ns <= 0) return;
-  const size_t sh = (size_t)(2 * SB * NCp + SB * (SB + 1)) * sizeof(double);
-  hipLaunchKernelGGL(pack_interface_kernel<TO>, dim3(packed_blocks(NGp), ns), dim3(256), sh, st, KS, Phi, Gt, NGp,
-                     NCp, out, packed_blocks(NGp));
-}
-template void launch_pack_interface<float>(hipStream_t, int, int, int, const double*, const double*, const double*,
-                                           float*);
-template void launch_pack_interface<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
-                                            double*);
 
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info) {
   hipLaunchKernelGGL(small_spd_inverse_kernel, dim3(ns), dim3(256), (size_t)sd.NCp * sd.NCp * sizeof(double), st,
                      sd, S, info);
 }
 
-void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows,
+void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows, int max_ldc,
                             const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,
-                            const double* AcLoc, double* Ac) {
+                            const double* AcLoc, double* Ac, double* keep) {
   if (n_prows <= 0) return;
-  hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)((n_prows + 63) / 64)), dim3(64), 0, st, b, prow_off,
-                     n_prows, cs_ptr, cs_sub, cs_row, sd, AcLoc, Ac);
+  const int64_t gx = std::min<int64_t>(n_prows, 65535);
+  const dim3 grid((unsigned)gx, (unsigned)((n_prows + gx - 1) / gx));
+  if (max_ldc <= COARSE_ASSEMBLE_LDS_LDC) {
+    static const bool attr = hipFuncSetAttribute((const void*)coarse_assemble_kernel<true>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)(COARSE_ASSEMBLE_LDS_LDC * sizeof(double))) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(coarse_assemble_kernel<true>, grid, dim3(256), (size_t)max_ldc * sizeof(double), st, b,
+                       prow_off, cs_ptr, cs_sub, cs_row, sd, AcLoc, Ac, keep);
+  } else {
+    hipLaunchKernelGGL(coarse_assemble_kernel<false>, grid, dim3(256), 0, st, b, prow_off, cs_ptr, cs_sub, cs_row,
+                       sd, AcLoc, Ac, keep);
+  }
 }
 
 template <typename TI, typename TO>

@@ -283,9 +283,9 @@ struct cb_ctx {
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
   void* pin = nullptr;
-  // second stream for work that overlaps the coarse factorisation
-  hipStream_t aux_st = nullptr;
-  hipEvent_t aux_ev = nullptr;
+  // second and third streams for work that overlaps the coarse factorisation
+  hipStream_t aux_st = nullptr, aux_st3 = nullptr;
+  hipEvent_t aux_ev = nullptr, aux_ev3 = nullptr;
   hipEvent_t nact_ev = nullptr;   // readback of the running-problem count
   // captured PCG iteration
   hipStream_t cap_st = nullptr;
@@ -297,7 +297,9 @@ struct cb_ctx {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (cap_st) (void)hipStreamDestroy(cap_st);
     if (aux_st) (void)hipStreamDestroy(aux_st);
+    if (aux_st3) (void)hipStreamDestroy(aux_st3);
     if (aux_ev) (void)hipEventDestroy(aux_ev);
+    if (aux_ev3) (void)hipEventDestroy(aux_ev3);
     if (nact_ev) (void)hipEventDestroy(nact_ev);
     if (pin) (void)hipHostFree(pin);
     for (auto& kv : prof_ev)
@@ -1057,7 +1059,9 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
   CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
   if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
+  if (!c->aux_st3) HIPCHK(hipStreamCreateWithFlags(&c->aux_st3, hipStreamNonBlocking));
   if (!c->aux_ev) HIPCHK(hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
+  if (!c->aux_ev3) HIPCHK(hipEventCreateWithFlags(&c->aux_ev3, hipEventDisableTiming));
   const int n_info = ns + 1 + c->P;
   CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
   HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
@@ -1081,12 +1085,13 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
   CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
   CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
-  // on every exit, st waits for the second stream before the buffers above
+  // on every exit, st waits for the other streams before the buffers above
   // return to the cache (destroyed after this guard)
   struct AuxJoin {
     cb_ctx* c;
     ~AuxJoin() {
       if (hipEventRecord(c->aux_ev, c->aux_st) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev, 0);
+      if (hipEventRecord(c->aux_ev3, c->aux_st3) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev3, 0);
     }
   } aux_join{c};
 
@@ -1144,17 +1149,11 @@ int factor_impl(cb_ctx* c) {
     gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
                  V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
                  nc, 0);
-    // Kt = K_S^{-1} - Phi G^T, packed; for the last chunk on the second
-    // stream, where it overlaps the coarse factorisation (nothing later on
-    // st touches its inputs, which stay allocated until the streams join)
-    if (w0 + nc < ns) {
-      launch_pack_interface<T>(st, NGp, NCp, nc, KS, Phiw, G.as<double>(), c->Kt.as<T>() + (int64_t)w0 * pkG);
-    } else {
-      HIPCHK(hipEventRecord(c->aux_ev, st));
-      HIPCHK(hipStreamWaitEvent(c->aux_st, c->aux_ev, 0));
-      launch_pack_interface<T>(c->aux_st, NGp, NCp, nc, KS, Phiw, G.as<double>(),
-                               c->Kt.as<T>() + (int64_t)w0 * pkG);
-    }
+    // Kt = K_S^{-1} - Phi G^T: the lower part in place in K_S^{-1} (MFMA),
+    // then packed with its mirror
+    gemm<double>(st, 0, 0, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NGp, sG, 1.0, KS, NGp, sKS, nc,
+                 GEMM_LOWER);
+    launch_pack_lower<double, T>(st, NGp, nc, KS, NGp, sKS, nullptr, 0, c->Kt.as<T>() + (int64_t)w0 * pkG);
     HIPCHK(hipGetLastError());
   }
   launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
@@ -1168,21 +1167,18 @@ int factor_impl(cb_ctx* c) {
     DevBuf Ac;
     CHK(dalloc(Ac, (size_t)c->ac_total * sizeof(double)));
     CHK(dalloc(c->Acinv, (size_t)c->ac_total * sizeof(double)));
-    launch_fill(st, c->ac_total, 0.0, Ac.as<double>());
-    launch_coarse_assemble(st, c->batch(false), c->prow_off_d.as<int64_t>(), c->n_prows, c->cs_ptr.as<int64_t>(),
-                           c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(), c->sub(0), AcLoc.as<double>(),
-                           Ac.as<double>());
-    HIPCHK(hipGetLastError());
-    if (c->P == 1) {
-      CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
-      launch_copy(st, c->ac_total, Ac.as<double>(), c->AcKeep.as<double>());
-    }
     size_t maxL = 0, maxLL = 0, maxD = 0;
     for (const CoarseGroup& gr : c->groups) {
       maxL = std::max(maxL, (size_t)gr.ldc);
       maxLL = std::max(maxLL, (size_t)gr.ldc * gr.ldc * gr.probs.size());
       maxD = std::max(maxD, gr.probs.size() * (size_t)diag_blocks(gr.ldc, 0) * DB * DB);
     }
+    // a single problem keeps its coarse matrix for export
+    if (c->P == 1) CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
+    launch_coarse_assemble(st, c->batch(false), c->prow_off_d.as<int64_t>(), c->n_prows, (int)maxL,
+                           c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(), c->sub(0),
+                           AcLoc.as<double>(), Ac.as<double>(), c->P == 1 ? c->AcKeep.as<double>() : nullptr);
+    HIPCHK(hipGetLastError());
     DevBuf Lc, Yc, PSc, ones;
     const std::vector<double> onesv(maxL, 1.0);
     CHK(dalloc(Lc, maxD * sizeof(double)));
@@ -1196,12 +1192,12 @@ int factor_impl(cb_ctx* c) {
       const int64_t sA = (int64_t)L * L, sLc = (int64_t)diag_blocks(L, 0) * DB * DB;
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
       double* A = Ac.as<double>() + gr.ac_off;
-      // the triangular inverse trails the factorisation on a second stream
-      if (cholesky_inverse<double>(st, c->aux_st, c->aux_ev, A, L, sA, L, nb, Lc.as<double>(), sLc,
-                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA) != 0) {
-        cholesky<double>(st, A, L, sA, L, 0, nb, Lc.as<double>(), sLc, c->info_d.as<int>() + ns + 1 + slot);
-        tri_inverse<double>(st, A, L, sA, 0, L, 0, nb, Lc.as<double>(), sLc, Yc.as<double>(), L, sA);
-      }
+      // the triangular inverse and the far trailing updates run beside the
+      // factorisation on two more streams
+      const AuxStreams ax{c->aux_st, c->aux_st3, c->aux_ev, c->aux_ev3};
+      if (cholesky_inverse<double>(st, ax, A, L, sA, L, nb, Lc.as<double>(), sLc,
+                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA) != 0)
+        return fail(CB_ERR_DEVICE, "event record or wait failed in the coarse factorisation");
       gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
                    L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
       symmetrize_scale<double, double>(st, PSc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
@@ -1308,18 +1304,24 @@ int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const doub
     CHK(upload(dInfo, std::vector<int>(batch, 0), nullptr));
     // the factorisation with the overlapped triangular inverse, as for the
     // coarse matrices
-    hipStream_t st2 = nullptr;
-    hipEvent_t ev = nullptr;
-    HIPCHK(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-      (void)hipStreamDestroy(st2);
-      return fail(CB_ERR_DEVICE, "event creation failed");
+    AuxStreams ax{nullptr, nullptr, nullptr, nullptr};
+    auto release = [&ax] {
+      (void)hipDeviceSynchronize();
+      if (ax.ev2) (void)hipEventDestroy(ax.ev2);
+      if (ax.ev3) (void)hipEventDestroy(ax.ev3);
+      if (ax.st2) (void)hipStreamDestroy(ax.st2);
+      if (ax.st3) (void)hipStreamDestroy(ax.st3);
+    };
+    if (hipStreamCreateWithFlags(&ax.st2, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ax.st3, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ax.ev2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ax.ev3, hipEventDisableTiming) != hipSuccess) {
+      release();
+      return fail(CB_ERR_DEVICE, "stream or event creation failed");
     }
-    const int rc = cholesky_inverse<T>(nullptr, st2, ev, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL,
-                                       dInfo.as<int>(), dY.as<T>(), nn);
-    (void)hipDeviceSynchronize();
-    (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(st2);
+    const int rc = cholesky_inverse<T>(nullptr, ax, dA.as<T>(), np, nn, np, batch, dL.as<T>(), sL, dInfo.as<int>(),
+                                       dY.as<T>(), nn);
+    release();
     if (rc != 0) return fail(CB_ERR_DEVICE, "event record or wait failed");
     gemm<T>(nullptr, 1, 0, np, np, np, T(1), dY.as<T>(), np, nn, dY.as<T>(), np, nn, T(0), dP.as<T>(), np, nn, batch,
             GEMM_LOWER | GEMM_KFROM_DIAG);

@@ -61,15 +61,24 @@ template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
                  const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY);
 
+// Streams and events lent to cholesky_inverse by the caller (default
+// priority, non-blocking).  The events are recorded and waited on at every
+// step, so they must outlive the work.
+struct AuxStreams {
+  hipStream_t st2, st3;
+  hipEvent_t ev2, ev3;
+};
+
 // Cholesky of n x n matrices (no split) and Y = L^{-1} (as tri_inverse over
-// the whole range, Y with leading dimension lda and stride sY), the inverse
-// steps issued on st2 one block behind the factorisation so that they overlap
-// with it; st waits for st2 before returning.  ev: an event owned by the
-// caller, recorded and waited on at every step (it must outlive the work).
-// Returns -1 if an event record or wait fails.
+// the whole range, Y with leading dimension lda and stride sY), with one
+// block of lookahead: after the panel of block k, st updates only column
+// block k+1 and goes on to factor it, while st3 updates the rest of the
+// trailing matrix; the triangular-inverse step of block k runs on st2.  st
+// waits for st2 and st3 before returning.  Returns -1 if an event record or
+// wait fails.
 template <typename T>
-int cholesky_inverse(hipStream_t st, hipStream_t st2, hipEvent_t ev, T* A, int64_t lda, int64_t sA, int n, int batch,
-                     T* Linv, int64_t sL, int* info, T* Y, int64_t sY);
+int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
+                     int64_t sL, int* info, T* Y, int64_t sY);
 
 // out = D sym(lower(in)) D, full storage.
 template <typename T, typename TO>

@@ -9,8 +9,8 @@
 // runs one workgroup per (tile, matrix), so the same code factors one large
 // coarse matrix or thousands of subdomain matrices.
 //
-// GEMM tiles: 64 or 128 rows x 64 or 128 columns per 256-thread workgroup,
-// four 64-wide waves in a 2 x 2 arrangement; the shape per call comes from a
+// GEMM tiles: 64 or 128 rows x 64 or 128 columns per workgroup, one 64-wide
+// wave per 32 x 32 sub-tile (4 to 16 waves); the shape per call comes from a
 // small autotuner table (see gemm_autotune).
 #include "dense.h"
 
@@ -21,6 +21,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace cutbddc {
 namespace {
@@ -61,7 +62,9 @@ template <> struct Vec16<double> {
 // the LDS operand tiles among more waves.
 //   TA = 0: A(i,k) = A[i*lda + k];  TA = 1: A(i,k) = A[k*lda + i]
 //   TB = 0: B(k,j) = B[k*ldb + j];  TB = 1: B(k,j) = B[j*ldb + k]
-// The K loop runs in stages of KT (128 bytes of k per row); both operand
+// The K loop runs in stages of KT (KB bytes of k per row: 128, or 256 / 512
+// for short K loops, which are bound by the load latency of each stage, not
+// by the multiplies); both operand
 // tiles sit in LDS with k contiguous (As[i][k], Bs[j][k]), double buffered:
 // the global loads of stage s+1 are in flight while stage s is multiplied,
 // and one barrier separates the stages.  Within a 16-wide k block the four
@@ -73,14 +76,14 @@ template <> struct Vec16<double> {
 // C is written only after the whole K loop, so a call may overwrite its own
 // B operand when each output tile reads only its own columns of B (and the
 // same for A and rows); the dispatcher keeps such calls on 64-wide tiles.
-template <typename T, int TA, int TB, int BM, int BN, int DEPTH = 1>
+template <typename T, int TA, int TB, int BM, int BN, int DEPTH = 1, int KB = 128>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
                                                    int64_t sC, int mode, int vec, int swz) {
   typedef typename Vec16<T>::type V;
   constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
-  constexpr int KT = 128 / sizeof(T);           // k per stage
+  constexpr int KT = KB / (int)sizeof(T);       // k per stage
   constexpr int LDK = KT + VW;                  // LDS row length (padded)
   constexpr int WGN = BN / 32;                  // waves along N
   constexpr int NT = 64 * (BM / 32) * WGN;      // threads
@@ -486,6 +489,7 @@ __global__ __launch_bounds__(DF_THREADS) void diag_factor_kernel(T* A, int64_t l
 // Tile products run on the 16x16x4 MFMAs.
 constexpr int DK_THREADS = 512;
 constexpr int DK_TILES = (DB / 16) * (DB / 16 + 1) / 2;
+static_assert(DB == 128, "the tile-row lookup of the diagonal kernel assumes 8 x 8 tiles");
 __device__ inline int dk_tile(int I, int J) { return I * (I + 1) / 2 + J; }
 __device__ inline int dk_at(int r, int c) { return r * 16 + (c ^ r); }
 __device__ inline double dk_bcast(double v, int lane) {
@@ -496,6 +500,19 @@ __device__ inline double dk_bcast(double v, int lane) {
 }
 __device__ inline float dk_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+// Value of lane 16 * (lane / 16) + J (row broadcast within each group of 16
+// lanes, DPP row_newbcast): no trip through the LDS unit.
+template <int J>
+__device__ inline float dk_rowbcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, false));
+}
+template <int J>
+__device__ inline double dk_rowbcast(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), 0x150 + J, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x150 + J, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // 1/sqrt(d) for the pivots of the wave-level factorisation: the hardware
@@ -541,21 +558,33 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = b >> 4;
   typedef typename Acc<T>::type AccT;
-  // load the lower tiles (upper part of diagonal tiles as zero); X = 0
-  for (int e = tid; e < DK_TILES * 256; e += DK_THREADS) {
+  // load the lower tiles (upper part of diagonal tiles as zero); X = 0.
+  // Every load is issued before the first LDS write.
+  constexpr int LD_IT = DK_TILES * 256 / DK_THREADS;
+  static_assert(LD_IT * DK_THREADS == DK_TILES * 256, "load split");
+  T ld[LD_IT];
+#pragma unroll
+  for (int it = 0; it < LD_IT; ++it) {
+    const int e = tid + it * DK_THREADS;
     const int q = e >> 8, rc = e & 255, r = rc >> 4, c = rc & 15;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= q) ++I;
+    const int I = (q >= 1) + (q >= 3) + (q >= 6) + (q >= 10) + (q >= 15) + (q >= 21) + (q >= 28);
     const int J = q - I * (I + 1) / 2;
-    T v = T(0);
-    if (I < nt && (I != J || c <= r)) v = a[(int64_t)(16 * I + r) * lda + 16 * J + c];
-    Ls[q * 256 + dk_at(r, c)] = v;
+    ld[it] = (I < nt && (I != J || c <= r)) ? a[(int64_t)(16 * I + r) * lda + 16 * J + c] : T(0);
+  }
+#pragma unroll
+  for (int it = 0; it < LD_IT; ++it) {
+    const int e = tid + it * DK_THREADS;
+    const int q = e >> 8, rc = e & 255, r = rc >> 4, c = rc & 15;
+    Ls[q * 256 + dk_at(r, c)] = ld[it];
     Xs[q * 256 + dk_at(r, c)] = T(0);
   }
   __syncthreads();
   int bad = 0;   // wave 0: first failing row + 1
-  // wave 0: factor and invert diagonal tile p in registers; lane (r, g)
-  // holds columns g + 4t of row r
+  // wave 0: factor and invert diagonal tile p in registers.  Lane (r, g)
+  // holds columns g + 4t of row r of the whole symmetric tile (both
+  // triangles, updated alike, so they stay exactly equal): row j of A and X
+  // reaches every lane by a row broadcast from lane j of its own group, and
+  // only column j of A (one value per lane) needs a lane shuffle.
   auto factor_diag = [&](int p) {
     T* Lp = Ls + dk_tile(p, p) * 256;
     T* Xp = Xs + dk_tile(p, p) * 256;
@@ -564,36 +593,63 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = g + 4 * t;
-      av[t] = c <= r ? Lp[dk_at(r, c)] : T(0);
+      av[t] = c <= r ? Lp[dk_at(r, c)] : Lp[dk_at(c, r)];
       xv[t] = c == r ? T(1) : T(0);
     }
+    auto step = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int tj = j >> 2, gj = j & 3;
+      // Row j of A is needed in columns c > j (registers t >= tj), row j of
+      // X in columns c <= j (t <= tj; it is zero to the right of j, so the
+      // columns of X right of j are left as they are).
+      T arow[4], xrow[4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int tj = j >> 2, gj = j & 3;
-      const T colj = av[tj];   // column j before this step changes it
-      T d = dk_bcast(colj, j + 16 * gj);
+      for (int t = tj; t < 4; ++t) arow[t] = dk_rowbcast<j>(av[t]);   // A[j][g + 4t]
+#pragma unroll
+      for (int t = 0; t <= tj; ++t) xrow[t] = dk_rowbcast<j>(xv[t]);  // X[j][g + 4t]
+      const T acol = __shfl(av[tj], r + 16 * gj, 64);   // A[r][j]
+      T d = dk_bcast(av[tj], j + 16 * gj);
       if (!(d > T(0)) || !(d < T(3.0e38))) {
         if (bad == 0) bad = k0 + 16 * p + j + 1;
         d = T(1);
       }
       const T inv = dk_rsqrt(d);
       const T ljj = d * inv;
-      const T lrj = __shfl(colj, r + 16 * gj, 64) * inv;
+      const T lrj = acol * inv;
+      const T lrm = r > j ? lrj : T(0);   // rows above the pivot keep their values
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int c = g + 4 * t;
-        const T lcj = __shfl(colj, c + 16 * gj, 64) * inv;
-        const T xjc = __shfl(xv[t], j + 16 * g, 64) * inv;
-        if (c == j) av[t] = r > j ? lrj : (r == j ? ljj : T(0));
-        else if (c > j && r >= c) av[t] = fma(-lrj, lcj, av[t]);
-        if (r == j) xv[t] = xjc;
-        else if (r > j) xv[t] = fma(-lrj, xjc, xv[t]);
+      for (int t = tj + 1; t < 4; ++t) av[t] = fma(-lrm, arow[t] * inv, av[t]);
+      {
+        const T lcm = g > gj ? arow[tj] * inv : T(0);
+        const T an = fma(-lrm, lcm, av[tj]);
+        av[tj] = (g == gj && r >= j) ? (r == j ? ljj : lrj) : an;
       }
-    }
+#pragma unroll
+      for (int t = 0; t <= tj; ++t) {
+        const T xjc = xrow[t] * inv;
+        xv[t] = r == j ? xjc : fma(-lrm, xjc, xv[t]);
+      }
+    };
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 1>{});
+    step(std::integral_constant<int, 2>{});
+    step(std::integral_constant<int, 3>{});
+    step(std::integral_constant<int, 4>{});
+    step(std::integral_constant<int, 5>{});
+    step(std::integral_constant<int, 6>{});
+    step(std::integral_constant<int, 7>{});
+    step(std::integral_constant<int, 8>{});
+    step(std::integral_constant<int, 9>{});
+    step(std::integral_constant<int, 10>{});
+    step(std::integral_constant<int, 11>{});
+    step(std::integral_constant<int, 12>{});
+    step(std::integral_constant<int, 13>{});
+    step(std::integral_constant<int, 14>{});
+    step(std::integral_constant<int, 15>{});
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = g + 4 * t;
-      Lp[dk_at(r, c)] = av[t];
+      Lp[dk_at(r, c)] = c <= r ? av[t] : T(0);
       Xp[dk_at(r, c)] = xv[t];
     }
   };
@@ -605,62 +661,98 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
 #pragma unroll
     for (int v = 0; v < 4; ++v) Aij[dk_at(Acc<T>::row(lane, v), lane & 15)] -= acc[v];
   };
+  // tile X_pj (j < p) of row p of X = L^{-1}: -X_pp sum_{j<=k<p} L_pk X_kj,
+  // by the calling wave
+  auto xrow_tile = [&](int p, int j) {
+    AccT acc = {0, 0, 0, 0};
+    T* Xpj = Xs + dk_tile(p, j) * 256;
+    for (int k = j; k < p; ++k) dk_mma<T>(acc, Ls + dk_tile(p, k) * 256, Xs + dk_tile(k, j) * 256, 0, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
+    __builtin_amdgcn_wave_barrier();
+    AccT acc2 = {0, 0, 0, 0};
+    dk_mma<T>(acc2, Xs + dk_tile(p, p) * 256, Xpj, 0, lane);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = -acc2[v];
+  };
+  constexpr int NW = DK_THREADS / 64;
   if (wv == 0) factor_diag(0);
   __syncthreads();
   for (int p = 0; p < nt; ++p) {
-    // 2. panel tiles and row p of X, one tile per wave
-    for (int item = wv; item < nt - 1; item += DK_THREADS / 64) {
+    // 2. panel tiles L_ip = A_ip X_pp^T (i > p), one per wave
+    for (int i = p + 1 + wv; i < nt; i += NW) {
       AccT acc = {0, 0, 0, 0};
-      if (item < nt - 1 - p) {
-        const int i = p + 1 + item;
-        T* Lip = Ls + dk_tile(i, p) * 256;
-        dk_mma<T>(acc, Lip, Xs + dk_tile(p, p) * 256, 1, lane);
+      T* Lip = Ls + dk_tile(i, p) * 256;
+      dk_mma<T>(acc, Lip, Xs + dk_tile(p, p) * 256, 1, lane);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Lip[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
-      } else {
-        const int j = item - (nt - 1 - p);
-        T* Xpj = Xs + dk_tile(p, j) * 256;
-        for (int k = j; k < p; ++k)
-          dk_mma<T>(acc, Ls + dk_tile(p, k) * 256, Xs + dk_tile(k, j) * 256, 0, lane);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
-        __builtin_amdgcn_wave_barrier();
-        AccT acc2 = {0, 0, 0, 0};
-        dk_mma<T>(acc2, Xs + dk_tile(p, p) * 256, Xpj, 0, lane);
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = -acc2[v];
-      }
+      for (int v = 0; v < 4; ++v) Lip[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
     }
     __syncthreads();
     if (p + 1 == nt) break;
-    // 3. trailing update; wave 0 takes the next diagonal tile and factors
-    // it at once (lookahead), the other waves share the remaining tiles
+    // 3. wave 0: the next diagonal tile's update and factorisation
+    // (lookahead); the other waves: row p of X (its inputs are final: L row
+    // p, X rows above, X_pp), heaviest tile first, then the remaining
+    // trailing tiles
     const int m = nt - 1 - p, ntr = m * (m + 1) / 2;
     if (wv == 0) {
       trail(p, p + 1, p + 1);
       __builtin_amdgcn_wave_barrier();
       factor_diag(p + 1);
     } else {
-      for (int item = 1 + (wv - 1); item < ntr; item += DK_THREADS / 64 - 1) {
-        int ii = 0;
-        while ((ii + 1) * (ii + 2) / 2 <= item) ++ii;
-        const int jj = item - ii * (ii + 1) / 2;
-        trail(p, p + 1 + ii, p + 1 + jj);
+      for (int item = wv - 1; item < p + ntr - 1; item += NW - 1) {
+        if (item < p) {
+          xrow_tile(p, item);
+        } else {
+          const int q = item - p + 1;
+          int ii = 0;
+          while ((ii + 1) * (ii + 2) / 2 <= q) ++ii;
+          const int jj = q - ii * (ii + 1) / 2;
+          trail(p, p + 1 + ii, p + 1 + jj);
+        }
       }
     }
     __syncthreads();
   }
+  // row nt - 1 of X
+  for (int j = wv; j < nt - 1; j += NW) xrow_tile(nt - 1, j);
+  __syncthreads();
   // write L (upper part of the block zero) and X (zero above the diagonal
-  // and outside the b x b block)
+  // and outside the b x b block), VW consecutive columns per thread (b and
+  // the tile edges are multiples of 16, so a group never straddles them)
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = 16 / sizeof(T);
   T* li = Linv + bz * sL + (int64_t)blk * DB * DB;
-  for (int e = tid; e < DB * DB; e += DK_THREADS) {
-    const int row = e / DB, col = e - row * DB;
-    const int I = row >> 4, J = col >> 4, r = row & 15, c = col & 15;
-    const bool in = row < b && col < b && col <= row;
-    const int at = (I >= J && I < 8) ? dk_tile(I, J) * 256 + dk_at(r, c) : 0;
-    li[e] = in ? Xs[at] : T(0);
-    if (row < b && col < b) a[(int64_t)row * lda + col] = in ? Ls[at] : T(0);
+  const bool vec = ((lda | sA | k0) % VW) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool vecl = (sL % VW) == 0 && (reinterpret_cast<uintptr_t>(Linv) & 15) == 0;
+  for (int e = tid; e < DB * DB / VW; e += DK_THREADS) {
+    const int row = e / (DB / VW), col = (e - row * (DB / VW)) * VW;
+    const int I = row >> 4, J = col >> 4, r = row & 15;
+    const bool tile = row < b && col < b && J <= I;
+    V xo, lo;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      const int c = (col + k) & 15;
+      const bool in = tile && col + k <= row;
+      const int at = tile ? dk_tile(I, J) * 256 + dk_at(r, c) : 0;
+      xo[k] = in ? Xs[at] : T(0);
+      lo[k] = in ? Ls[at] : T(0);
+    }
+    if (vecl) {
+      *reinterpret_cast<V*>(li + e * VW) = xo;
+    } else {
+#pragma unroll
+      for (int k = 0; k < VW; ++k) li[e * VW + k] = xo[k];
+    }
+    if (row < b && col < b) {
+      T* dst = a + (int64_t)row * lda + col;
+      if (vec) {
+        *reinterpret_cast<V*>(dst) = lo;
+      } else {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) dst[k] = lo[k];
+      }
+    }
   }
   if (tid == 0 && bad && info && info[bz] == 0) info[bz] = bad;
 }
@@ -726,12 +818,15 @@ __global__ __launch_bounds__(256) void symmetrize_scale_tiled_kernel(const T* in
 }  // namespace
 
 // ---- GEMM dispatch and tile-shape autotuner -----------------------------
-// Tile shapes: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128.  The choice
-// for a call is looked up by (type, TA, TB, mode bits, shape bucket); buckets
-// are powers of two of M, N, K and of the batch size.  Calls that overwrite
-// their own operand (in place) use a single tile column (or row).  The table is filled
-// by gemm_autotune(), which times every shape on scratch matrices of the
-// bucket's size and keeps the fastest; untuned buckets use 64x64.
+// Tile shapes (rows x columns, bytes of k per stage): 0 = 64x64, 1 = 128x64,
+// 2 = 64x128, 3 = 128x128 (128 B); 4 = 64x64, 5 = 32x64 (512 B); 6 = 64x128,
+// 7 = 128x64 (256 B).  The choice for a call is looked up by (type, TA, TB,
+// mode bits, in-place kind, shape bucket); buckets are powers of two of M,
+// N, K and of the batch size.  Calls that overwrite their own operand (in
+// place) are limited to shapes with a single tile column (or row).  The
+// table is filled by gemm_autotune(), which times every allowed shape on
+// scratch matrices of the bucket's size and keeps the fastest; with the
+// autotuner off, calls use 64x64 (64x128 / 128x64 in place).
 namespace {
 struct TuneKey {
   int dt, ta, tb, mode, bm, bn, bk, bb;
@@ -753,9 +848,21 @@ bool autotune_enabled() {
   }();
   return on;
 }
+// inplace: 0, or IN_PLACE_A (C == A: the call needs a single tile column)
+// or IN_PLACE_B (C == B: a single tile row)
+constexpr int IN_PLACE_A = 8, IN_PLACE_B = 16;
 template <typename T>
-TuneKey tune_key(int TA, int TB, int M, int N, int K, int batch, int mode) {
-  return TuneKey{(int)sizeof(T), TA, TB, mode & 7, log2b(M), log2b(N), log2b(std::max(K, 1)), log2b(batch)};
+TuneKey tune_key(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace) {
+  return TuneKey{(int)sizeof(T), TA, TB, (mode & 7) | inplace, log2b(M), log2b(N), log2b(std::max(K, 1)),
+                 log2b(batch)};
+}
+constexpr int GEMM_NSHAPES = 8;
+const int SBM[GEMM_NSHAPES] = {64, 128, 64, 128, 64, 32, 64, 128};
+const int SBN[GEMM_NSHAPES] = {64, 64, 128, 128, 64, 64, 128, 64};
+bool shape_allowed(int shape, int M, int N, int inplace) {
+  if (inplace == IN_PLACE_A) return SBN[shape] >= N;
+  if (inplace == IN_PLACE_B) return SBM[shape] >= M;
+  return true;
 }
 
 // CUTBDDC_DIAG_BLOCKED=0 selects the register-tile diagonal kernel.
@@ -780,23 +887,26 @@ template <typename T>
 void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A,
                  int64_t lda, int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
                  int64_t sC, int batch, int mode) {
-  const int BM = (shape == 1 || shape == 3) ? 128 : 64;
-  const int BN = (shape == 2 || shape == 3) ? 128 : 64;
+  // shapes: 0-3 = 64x64, 128x64, 64x128, 128x128 (128-byte k stages);
+  // 4 = 64x64 and 5 = 32x64 with 512-byte stages; 6 = 64x128 and 7 = 128x64
+  // with 256-byte stages
+  const int BM = SBM[shape], BN = SBN[shape];
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
   constexpr int VW = 16 / sizeof(T);
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   const int vec = (lda % VW == 0 && ldb % VW == 0 && (batch == 1 || (sA % VW == 0 && sB % VW == 0)) && al(A) &&
                    al(B)) ? 1 : 0;
   const int swz = gemm_xcd_swizzle() ? 1 : 0;
-#define GEMM_CASE(a, b, bm, bn)                                                                        \
-  if (TA == a && TB == b && BM == bm && BN == bn) {                                                    \
-    hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn>), grid, dim3(64 * (bm / 32) * (bn / 32)), 0, st, M, N, K, \
-                       alpha, A, lda,                                                                  \
-                       sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz);                              \
-    return;                                                                                            \
+#define GEMM_CASE(a, b, sh, bm, bn, kb)                                                                   \
+  if (TA == a && TB == b && shape == sh) {                                                                 \
+    hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn, 1, kb>), grid, dim3(64 * (bm / 32) * (bn / 32)), 0, st, M, \
+                       N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz);             \
+    return;                                                                                                \
   }
-#define GEMM_SHAPES(a, b) \
-  GEMM_CASE(a, b, 64, 64) GEMM_CASE(a, b, 128, 64) GEMM_CASE(a, b, 64, 128) GEMM_CASE(a, b, 128, 128)
+#define GEMM_SHAPES(a, b)                                                                              \
+  GEMM_CASE(a, b, 0, 64, 64, 128) GEMM_CASE(a, b, 1, 128, 64, 128) GEMM_CASE(a, b, 2, 64, 128, 128)    \
+  GEMM_CASE(a, b, 3, 128, 128, 128) GEMM_CASE(a, b, 4, 64, 64, 512) GEMM_CASE(a, b, 5, 32, 64, 512)    \
+  GEMM_CASE(a, b, 6, 64, 128, 256) GEMM_CASE(a, b, 7, 128, 64, 256)
   GEMM_SHAPES(0, 0) GEMM_SHAPES(0, 1) GEMM_SHAPES(1, 0) GEMM_SHAPES(1, 1)
 #undef GEMM_SHAPES
 #undef GEMM_CASE
@@ -804,36 +914,40 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
 }  // namespace
 
 template <typename T>
+int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace);
+
+template <typename T>
 void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
           int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
           int batch, int mode) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  int shape = 0;
-  const bool in_place = ((const T*)C == A) || ((const T*)C == B);
-  if (in_place) {
-    // one tile column (C == A: tiles read only their own rows) or one tile
-    // row (C == B: tiles read only their own columns)
-    if ((const T*)C == A) shape = N > 64 ? 2 : 0;
-    else shape = M > 64 ? 1 : 0;
-  } else {
-    bool known = false;
-    {
-      std::lock_guard<std::mutex> g(g_tune_mu);
-      auto it = g_tune.find(tune_key<T>(TA, TB, M, N, K, batch, mode));
-      if (it != g_tune.end()) {
-        shape = it->second;
-        known = true;
-      }
-    }
-    if (!known && autotune_enabled()) shape = gemm_autotune<T>(TA, TB, M, N, K, batch, mode);
+  // C == A: one tile column, whose tiles read only their own rows of A;
+  // C == B: one tile row, whose tiles read only their own columns of B
+  const int inplace = ((const T*)C == A) ? IN_PLACE_A : ((const T*)C == B) ? IN_PLACE_B : 0;
+  int shape = -1;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key<T>(TA, TB, M, N, K, batch, mode, inplace));
+    if (it != g_tune.end()) shape = it->second;
+  }
+  if (shape < 0 && autotune_enabled()) shape = gemm_autotune_impl<T>(TA, TB, M, N, K, batch, mode, inplace);
+  if (shape < 0) {
+    shape = 0;
+    if (inplace == IN_PLACE_A) shape = N > 64 ? 2 : 0;
+    if (inplace == IN_PLACE_B) shape = M > 64 ? 1 : 0;
   }
   gemm_launch<T>(shape, st, TA, TB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, mode);
 }
 
 template <typename T>
 int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
+  return gemm_autotune_impl<T>(TA, TB, M, N, K, batch, mode, 0);
+}
+
+template <typename T>
+int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
-  const TuneKey key = tune_key<T>(TA, TB, M, N, K, batch, mode);
+  const TuneKey key = tune_key<T>(TA, TB, M, N, K, batch, mode, inplace);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
@@ -844,13 +958,17 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
   // scratch capped at ~2 GB: time a smaller batch for very large calls
   const int64_t per = (sA + sB + sC) * (int64_t)sizeof(T);
   batch = (int)std::max<int64_t>(1, std::min<int64_t>(batch, ((int64_t)2 << 30) / std::max<int64_t>(per, 1)));
+  int best = -1;
+  for (int shape = 0; shape < GEMM_NSHAPES && best < 0; ++shape)
+    if (shape_allowed(shape, M, N, inplace)) best = shape;
+  if (best < 0) return 0;
   T *A = nullptr, *B = nullptr, *C = nullptr;
   if (hipMalloc(&A, sA * batch * sizeof(T)) != hipSuccess || hipMalloc(&B, sB * batch * sizeof(T)) != hipSuccess ||
       hipMalloc(&C, sC * batch * sizeof(T)) != hipSuccess) {
     (void)hipFree(A);
     (void)hipFree(B);
     (void)hipFree(C);
-    return 0;
+    return best;
   }
   (void)hipMemset(A, 0, sA * batch * sizeof(T));
   (void)hipMemset(B, 0, sB * batch * sizeof(T));
@@ -858,9 +976,11 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  int best = 0;
   float best_ms = 1e30f;
-  for (int shape = 0; shape < 4; ++shape) {
+  // the candidates run on separate C, with the in-place call's tile
+  // constraint: the same kernels, timed without the aliasing
+  for (int shape = 0; shape < GEMM_NSHAPES; ++shape) {
+    if (!shape_allowed(shape, M, N, inplace)) continue;
     float tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       (void)hipEventRecord(e0, nullptr);
@@ -971,33 +1091,48 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
 }
 
 template <typename T>
-int cholesky_inverse(hipStream_t st, hipStream_t st2, hipEvent_t ev, T* A, int64_t lda, int64_t sA, int n, int batch,
-                     T* Linv, int64_t sL, int* info, T* Y, int64_t sY) {
-  // Cholesky sweep on st; block step k of the triangular inverse follows on
-  // st2 as soon as the sweep has produced diagonal block k and the column
-  // block below it.  ev belongs to the caller (re-recorded for every step).
+int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
+                     int64_t sL, int* info, T* Y, int64_t sY) {
+  // Block step k on st: diagonal block, panel, then the update of column
+  // block k+1 only (after the far update of step k-1, which also covered
+  // it).  The far update of step k (rows and columns right of block k+1)
+  // runs on st3 beside the factorisation of block k+1: the two touch
+  // disjoint parts of A and read only the panel of block k.  Step k of the
+  // triangular inverse reads the final column block k and runs on st2.
   hipLaunchKernelGGL(eye_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
+  bool far_pending = false;
   int K0 = 0;
   while (K0 < n) {
     const int b = std::min(DB, n - K0);
     const int K1 = K0 + b;
     diag_step<T>(st, A, lda, sA, K0, b, Linv, sL, diag_block_index(K0, 0), batch, info);
     const int rest = n - K1;
+    T* panel = A + (int64_t)K1 * lda + K0;
     if (rest > 0) {
-      T* panel = A + (int64_t)K1 * lda + K0;
       const T* li = Linv + (int64_t)diag_block_index(K0, 0) * DB * DB;
       gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
     }
-    if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(st2, ev, 0) != hipSuccess) return -1;
-    tri_inverse_step<T>(st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, K0, b);
+    if (hipEventRecord(ax.ev2, st) != hipSuccess || hipStreamWaitEvent(ax.st2, ax.ev2, 0) != hipSuccess) return -1;
+    tri_inverse_step<T>(ax.st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, K0, b);
     if (rest > 0) {
-      T* panel = A + (int64_t)K1 * lda + K0;
-      gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
-              lda, sA, batch, GEMM_LOWER);
+      const int b2 = std::min(DB, rest);
+      if (far_pending && hipStreamWaitEvent(st, ax.ev3, 0) != hipSuccess) return -1;
+      gemm<T>(st, 0, 1, rest, b2, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1, lda,
+              sA, batch, GEMM_LOWER);
+      far_pending = rest > b2;
+      if (far_pending) {
+        const int K2 = K1 + b2;
+        T* pf = panel + (int64_t)b2 * lda;
+        if (hipStreamWaitEvent(ax.st3, ax.ev2, 0) != hipSuccess) return -1;
+        gemm<T>(ax.st3, 0, 1, rest - b2, rest - b2, b, T(-1), pf, lda, sA, pf, lda, sA, T(1),
+                A + (int64_t)K2 * lda + K2, lda, sA, batch, GEMM_LOWER);
+        if (hipEventRecord(ax.ev3, ax.st3) != hipSuccess) return -1;
+      }
     }
     K0 = K1;
   }
-  if (hipEventRecord(ev, st2) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess) return -1;
+  if (hipEventRecord(ax.ev2, ax.st2) != hipSuccess || hipStreamWaitEvent(st, ax.ev2, 0) != hipSuccess) return -1;
+  if (hipEventRecord(ax.ev3, ax.st3) != hipSuccess || hipStreamWaitEvent(st, ax.ev3, 0) != hipSuccess) return -1;
   return 0;
 }
 
@@ -1021,7 +1156,7 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*); \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
                                int64_t, T*, int64_t, int64_t);                                      \
-  template int cholesky_inverse<T>(hipStream_t, hipStream_t, hipEvent_t, T*, int64_t, int64_t, int, int, T*,  \
+  template int cholesky_inverse<T>(hipStream_t, const AuxStreams&, T*, int64_t, int64_t, int, int, T*,  \
                                    int64_t, int*, T*, int64_t);
 INST(double)
 INST(float)
