@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -92,8 +93,18 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   constexpr int AV = BM * KT / VW / NT;         // vectors per thread per stage
   constexpr int BV = BN * KT / VW / NT;
   static_assert(AV >= 1 && BV >= 1, "tile too small");
-  __shared__ __align__(16) T As[2][BM][LDK];
-  __shared__ __align__(16) T Bs[2][BN][LDK];
+  // An operand whose global rows run along k (TA = 0, TB = 1) sits in LDS
+  // as [row][k] and is read 16 bytes at a time; the other kind (TA = 1,
+  // TB = 0) sits as [k][row], so that its 16-byte global vectors go to LDS
+  // unchanged (a [row][k] store would scatter them over rows and collide
+  // in the banks), and is read one element per MFMA operand.  FP32 [k][row]
+  // rows are padded by 4 so that the k rows 4 apart read by lane groups in
+  // one LDS cycle fall in different banks.
+  constexpr int PK = sizeof(T) == 4 ? 4 : 0;
+  constexpr int AR = TA == 0 ? BM : KT, AC = TA == 0 ? LDK : BM + PK;
+  constexpr int BR = TB == 1 ? BN : KT, BC = TB == 1 ? LDK : BN + PK;
+  __shared__ __align__(16) T As[2][AR][AC];
+  __shared__ __align__(16) T Bs[2][BR][BC];
   // Workgroups are handed to the 8 XCDs round-robin by linear id; with swz
   // the tiles are renumbered so that each XCD runs a contiguous range of
   // (tile, matrix) pairs, i.e. whole matrices, whose operand panels then
@@ -198,23 +209,15 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
     for (int q = 0; q < AV; ++q) {
       int i, k;
       a_coord(q, i, k);
-      if (TA == 0) {
-        *reinterpret_cast<V*>(&As[buf][i][k]) = ra[q];
-      } else {
-#pragma unroll
-        for (int c = 0; c < VW; ++c) As[buf][i + c][k] = ra[q][c];
-      }
+      if constexpr (TA == 0) *reinterpret_cast<V*>(&As[buf][i][k]) = ra[q];
+      else *reinterpret_cast<V*>(&As[buf][k][i]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < BV; ++q) {
       int j, k;
       b_coord(q, j, k);
-      if (TB == 1) {
-        *reinterpret_cast<V*>(&Bs[buf][j][k]) = rb[q];
-      } else {
-#pragma unroll
-        for (int c = 0; c < VW; ++c) Bs[buf][j + c][k] = rb[q][c];
-      }
+      if constexpr (TB == 1) *reinterpret_cast<V*>(&Bs[buf][j][k]) = rb[q];
+      else *reinterpret_cast<V*>(&Bs[buf][k][j]) = rb[q];
     }
   };
 
@@ -231,22 +234,34 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
       T av[FM][4], bv[FN][4];
 #pragma unroll
       for (int mi = 0; mi < FM; ++mi) {
-        const T* src = &As[buf][wr * WM + mi * 16 + (lane & 15)][kb + ks];
+        const int i = wr * WM + mi * 16 + (lane & 15);
+        if constexpr (TA == 0) {
+          const T* src = &As[buf][i][kb + ks];
 #pragma unroll
-        for (int h = 0; h < 4; h += VW) {
-          const V x = *reinterpret_cast<const V*>(src + h);
+          for (int h = 0; h < 4; h += VW) {
+            const V x = *reinterpret_cast<const V*>(src + h);
 #pragma unroll
-          for (int c = 0; c < VW; ++c) av[mi][h + c] = x[c];
+            for (int c = 0; c < VW; ++c) av[mi][h + c] = x[c];
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) av[mi][h] = As[buf][kb + ks + h][i];
         }
       }
 #pragma unroll
       for (int ni = 0; ni < FN; ++ni) {
-        const T* src = &Bs[buf][wc * WN + ni * 16 + (lane & 15)][kb + ks];
+        const int j = wc * WN + ni * 16 + (lane & 15);
+        if constexpr (TB == 1) {
+          const T* src = &Bs[buf][j][kb + ks];
 #pragma unroll
-        for (int h = 0; h < 4; h += VW) {
-          const V x = *reinterpret_cast<const V*>(src + h);
+          for (int h = 0; h < 4; h += VW) {
+            const V x = *reinterpret_cast<const V*>(src + h);
 #pragma unroll
-          for (int c = 0; c < VW; ++c) bv[ni][h + c] = x[c];
+            for (int c = 0; c < VW; ++c) bv[ni][h + c] = x[c];
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) bv[ni][h] = Bs[buf][kb + ks + h][j];
         }
       }
 #pragma unroll
@@ -821,11 +836,11 @@ __global__ __launch_bounds__(256) void symmetrize_scale_tiled_kernel(const T* in
 // Tile shapes (rows x columns, bytes of k per stage): 0 = 64x64, 1 = 128x64,
 // 2 = 64x128, 3 = 128x128 (128 B); 4 = 64x64, 5 = 32x64 (512 B); 6 = 64x128,
 // 7 = 128x64 (256 B).  The choice for a call is looked up by (type, TA, TB,
-// mode bits, in-place kind, shape bucket); buckets are powers of two of M,
-// N, K and of the batch size.  Calls that overwrite their own operand (in
+// mode bits, in-place kind, size classes of M, N and K, power of two of
+// the batch size).  Calls that overwrite their own operand (in
 // place) are limited to shapes with a single tile column (or row).  The
 // table is filled by gemm_autotune(), which times every allowed shape on
-// scratch matrices of the bucket's size and keeps the fastest; with the
+// scratch matrices of the first call's size and keeps the fastest; with the
 // autotuner off, calls use 64x64 (64x128 / 128x64 in place).
 namespace {
 struct TuneKey {
@@ -841,6 +856,15 @@ inline int log2b(int x) {
   while ((1 << (b + 1)) <= x) ++b;
   return b;
 }
+// CUTBDDC_AUTOTUNE_LOG=1 prints every tuning decision (with the time of
+// each candidate) to stderr.
+bool autotune_log() {
+  static const bool on = [] {
+    const char* e = std::getenv("CUTBDDC_AUTOTUNE_LOG");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
 bool autotune_enabled() {
   static const bool on = [] {
     const char* e = std::getenv("CUTBDDC_AUTOTUNE");
@@ -851,10 +875,18 @@ bool autotune_enabled() {
 // inplace: 0, or IN_PLACE_A (C == A: the call needs a single tile column)
 // or IN_PLACE_B (C == B: a single tile row)
 constexpr int IN_PLACE_A = 8, IN_PLACE_B = 16;
+// Size classes of the tuning table: tile waste depends on the remainders
+// of M and N modulo the tile sizes, so sizes up to 1024 are told apart in
+// steps of 32 and up to 8192 in steps of 128; larger ones by powers of two.
+inline int size_class(int x) {
+  if (x <= 1024) return (x + 31) / 32;
+  if (x <= 8192) return 32 + (x + 127) / 128;
+  return 1000 + log2b(x);
+}
 template <typename T>
 TuneKey tune_key(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace) {
-  return TuneKey{(int)sizeof(T), TA, TB, (mode & 7) | inplace, log2b(M), log2b(N), log2b(std::max(K, 1)),
-                 log2b(batch)};
+  return TuneKey{(int)sizeof(T), TA, TB, (mode & 7) | inplace, size_class(M), size_class(N),
+                 size_class(std::max(K, 1)), log2b(batch)};
 }
 constexpr int GEMM_NSHAPES = 8;
 const int SBM[GEMM_NSHAPES] = {64, 128, 64, 128, 64, 32, 64, 128};
@@ -976,23 +1008,30 @@ int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode,
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
+  // work queued by the caller on other streams would run beside the
+  // candidates and distort their times
+  (void)hipDeviceSynchronize();
   float best_ms = 1e30f;
   // the candidates run on separate C, with the in-place call's tile
-  // constraint: the same kernels, timed without the aliasing
+  // constraint: the same kernels, timed without the aliasing; the fastest
+  // of three timed runs (after one untimed) counts
   for (int shape = 0; shape < GEMM_NSHAPES; ++shape) {
     if (!shape_allowed(shape, M, N, inplace)) continue;
-    float tot = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
+    float t = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
       (void)hipEventRecord(e0, nullptr);
       gemm_launch<T>(shape, nullptr, TA, TB, M, N, K, T(1), A, la, sA, B, lb, sB, T(1), C, N, sC, batch, mode);
       (void)hipEventRecord(e1, nullptr);
       (void)hipEventSynchronize(e1);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0) tot += ms;
+      if (rep > 0) t = std::min(t, ms);
     }
-    if (tot < best_ms) {
-      best_ms = tot;
+    if (autotune_log())
+      std::fprintf(stderr, "[gemm tune] T%zu TA%d TB%d M%d N%d K%d batch%d mode%d inplace%d shape%d %.1f us\n",
+                   sizeof(T), TA, TB, M, N, K, batch, mode, inplace, shape, t * 1e3f);
+    if (t < best_ms) {
+      best_ms = t;
       best = shape;
     }
   }
