@@ -676,8 +676,22 @@ __global__ __launch_bounds__(256) void coarse_gemv_kernel(BatchDev bd, int nc_to
   const ProbDev pr = bd.prob[p];
   const double* row = A + pr.ac_off + (int64_t)(c - pr.coarse_off) * pr.ldc;
   const double* xp = x + pr.coarse_off;
+  const int nc = pr.nc;
   double acc = 0.0;
-  for (int j = lane; j < pr.nc; j += 64) acc += row[j] * xp[j];
+  if (((reinterpret_cast<uintptr_t>(row) | reinterpret_cast<uintptr_t>(xp)) & 15) == 0) {
+    // 16-byte loads: lane takes the pairs (j, j + 1), j = 2 lane + 128 m
+    int j = 2 * lane;
+#pragma unroll 4
+    for (; j + 1 < nc; j += 128) {
+      const double2 a = *reinterpret_cast<const double2*>(row + j);
+      const double2 b = *reinterpret_cast<const double2*>(xp + j);
+      acc += a.x * b.x;
+      acc += a.y * b.y;
+    }
+    if (j < nc) acc += row[j] * xp[j];
+  } else {
+    for (int j = lane; j < nc; j += 64) acc += row[j] * xp[j];
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[c] = acc;
 }

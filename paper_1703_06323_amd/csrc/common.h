@@ -72,9 +72,11 @@ void launch_integrate_cut(hipStream_t st, const BatchDev& b, const double* xi, c
                           const int64_t* cut_cells, int64_t n_cut, double* Kc, double* Mc);
 // operator.hip (nodes: concatenated node space of nn entries)
 void set_reference_matrices(const double* Kref, const double* Mref);
+// y = A x on the node space; with dpart, dpart[block] = the block's part of
+// x.y (blocks of SEG_ALIGN nodes, numbered over the whole node space).
 void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
                     const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x,
-                    double* y);
+                    double* y, double* dpart = nullptr);
 // b = M_cut f.  f is read per problem from f_ptrs[p] (local node numbering;
 // a null entry means f = 1) when f_ptrs is given, else from the
 // concatenated vector f.  outmask null: every node of a segment is written.
@@ -95,21 +97,34 @@ void launch_copy(hipStream_t st, int64_t n, const double* src, double* dst);
 constexpr int DOT_CHUNK = 1024;
 void launch_dot(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks,
                 const double* x, const double* y, double* partial, double* out, int stride);
-// PCG scalars per problem p at S[8p + k]: 0 rho, 1 p.q, 2 r.r, 3 rho_new,
-// 4 b.b.  State per problem: it (iterations), status (0 running,
-// 1 converged, 2 iteration limit, 3 breakdown), relres; n_active[0] = number
-// of running problems.  params = {rtol, max_iter}.
+// only the chunk parts of launch_dot (partial[chunk])
+void launch_dot_chunks(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks, const double* x,
+                       const double* y, double* partial);
+// PCG scalars per problem p at S[8p + k]: 0 rho of the previous iteration,
+// 1 p.q, 2 r.r, 3 rho = r.z of the latest preconditioned residual, 4 b.b.
+// State per problem: it (iterations), status (0 running, 1 converged,
+// 2 iteration limit, 3 breakdown), relres; n_active[0] = number of running
+// problems.  params = {rtol, max_iter}.
 constexpr int CG_S = 8;
 void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int32_t* active, int32_t* it,
                     int32_t* status, double* relres, int32_t* n_active);
-void launch_cg_check(hipStream_t st, int P, const double* params, const double* S, int32_t* active,
-                     int32_t* it, int32_t* status, double* relres, int32_t* n_active);
-// x, r update; zero1 and zero2 (may be null) are cleared on the same nodes.
-void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
-                         const double* q, double* x, double* r, double* zero1, double* zero2);
-// p update, then rho = rho_new.
-void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
-                        double* p);
+// Convergence test after the x, r update: r.r of each running problem from
+// the block parts rr_part (blocks of SEG_ALIGN nodes; node_off [P+1]) into
+// slot 2; moves slot 3 to slot 0; writes the count of running problems to
+// n_active and to host memory nact_host (may be null).
+void launch_cg_check(hipStream_t st, int P, const int64_t* node_off, const double* rr_part, const double* params,
+                     double* S, int32_t* active, int32_t* it, int32_t* status, double* relres, int32_t* n_active,
+                     int32_t* nact_host);
+// x, r update (alpha = S[3] / p.q, p.q = sum of the problem's block parts
+// pq_part, stored in slot 1); the block parts of the new r.r go to rr_part;
+// zero1 and zero2 (may be null) are cleared on the same nodes.
+void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* pq_part,
+                         const double* p, const double* q, double* x, double* r, double* zero1, double* zero2,
+                         double* rr_part);
+// p update (beta = r.z / S[0], r.z = sum of the problem's chunk parts
+// rz_part from launch_dot_chunks, stored in slot 3).
+void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const int32_t* chunk_ptr,
+                        const double* rz_part, const double* z, double* p);
 void launch_set_params(hipStream_t st, double* params, double rtol, int32_t max_iter);
 // u_p[d] = grid[dof_node[dof_off[p] + d]] for every problem (u_ptrs: device
 // array of P output pointers), or dst[d] = grid[dof_node[d]] if u_ptrs is null.

@@ -280,9 +280,11 @@ struct cb_ctx {
   DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
   // work vectors and PCG state
   DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, ucvec, partial, scal, bgrid;
+  DevBuf pq_part, rr_part;   // per node block (SEG_ALIGN nodes): parts of p.q and r.r
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
   void* pin = nullptr;
+  int32_t* pin_nact_dev = nullptr;   // device address of pin_nact()
   // second and third streams for work that overlaps the coarse factorisation
   hipStream_t aux_st = nullptr, aux_st3 = nullptr;
   hipEvent_t aux_ev = nullptr, aux_ev3 = nullptr;
@@ -387,10 +389,10 @@ void timed(cb_ctx* c, const char* name, F&& f) {
   f();
 }
 
-int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked) {
+int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked, double* dpart = nullptr) {
   ProfScope ps(c, "apply_A");
   launch_apply_A(c->st, c->batch(masked), c->nn, c->cellinfo.as<int32_t>(), c->kappa.as<double>(),
-                 c->Kc.as<double>(), c->dofmask.as<uint8_t>(), x, y);
+                 c->Kc.as<double>(), c->dofmask.as<uint8_t>(), x, y, dpart);
   return CB_OK;
 }
 
@@ -454,23 +456,26 @@ void dot(cb_ctx* c, const double* a, const double* b, int slot, bool masked) {
              c->scal.as<double>() + slot, CG_S);
 }
 
-// One PCG iteration for every running problem: q = A p, x and r update
-// (which also clears the preconditioner's scratch vectors), convergence
-// test, z = M r, p update.
+// One PCG iteration for every running problem: q = A p (with the block
+// parts of p.q), x and r update (which also clears the preconditioner's
+// scratch vectors and forms the block parts of r.r), convergence test,
+// z = M r, chunk parts of r.z, p update (which sums them).
 int pcg_body(cb_ctx* c) {
   hipStream_t st = c->st;
   double* S = c->scal.as<double>();
   const BatchDev bm = c->batch(true);
-  CHK(apply_A_grid(c, c->p.as<double>(), c->q.as<double>(), true));
-  dot(c, c->p.as<double>(), c->q.as<double>(), 1, true);
-  launch_cg_update_xr(st, bm, c->nn, S, c->p.as<double>(), c->q.as<double>(), c->x.as<double>(),
-                      c->r.as<double>(), c->t1.as<double>(), c->z.as<double>());
-  dot(c, c->r.as<double>(), c->r.as<double>(), 2, true);
-  launch_cg_check(st, c->P, c->params.as<double>(), S, c->active.as<int32_t>(), c->itc.as<int32_t>(),
-                  c->status.as<int32_t>(), c->relres_d.as<double>(), c->nact_d.as<int32_t>());
+  CHK(apply_A_grid(c, c->p.as<double>(), c->q.as<double>(), true, c->pq_part.as<double>()));
+  launch_cg_update_xr(st, bm, c->nn, S, c->pq_part.as<double>(), c->p.as<double>(), c->q.as<double>(),
+                      c->x.as<double>(), c->r.as<double>(), c->t1.as<double>(), c->z.as<double>(),
+                      c->rr_part.as<double>());
+  launch_cg_check(st, c->P, c->node_off_d.as<int64_t>(), c->rr_part.as<double>(), c->params.as<double>(), S,
+                  c->active.as<int32_t>(), c->itc.as<int32_t>(), c->status.as<int32_t>(), c->relres_d.as<double>(),
+                  c->nact_d.as<int32_t>(), c->pin_nact_dev);
   CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true, true));
-  dot(c, c->r.as<double>(), c->z.as<double>(), 3, true);
-  launch_cg_update_p(st, bm, c->nn, S, c->z.as<double>(), c->p.as<double>());
+  launch_dot_chunks(st, bm, c->chunk_ptr_d.as<int32_t>(), c->n_chunks, c->r.as<double>(), c->z.as<double>(),
+                    c->partial.as<double>());
+  launch_cg_update_p(st, bm, c->nn, S, c->chunk_ptr_d.as<int32_t>(), c->partial.as<double>(), c->z.as<double>(),
+                     c->p.as<double>());
   return CB_OK;
 }
 
@@ -537,7 +542,7 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
   if (n_active > 0) {
     CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true));
     launch_copy(st, nn, c->z.as<double>(), c->p.as<double>());
-    dot(c, c->r.as<double>(), c->z.as<double>(), 0, true);
+    dot(c, c->r.as<double>(), c->z.as<double>(), 3, true);
     HIPCHK(hipGetLastError());
     const bool use_graph = graphs_enabled() && !c->prof;
     if (use_graph) CHK(capture_body(c));
@@ -549,8 +554,11 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
       ++k;
       return CB_OK;
     };
+    // the check kernel of every iteration writes the count of running
+    // problems straight to pinned host memory; the event marks the end of
+    // an iteration (a later iteration may already have lowered the count,
+    // which only ends the loop with work that is queued anyway)
     auto queue_read = [&]() -> int {
-      HIPCHK(hipMemcpyAsync(c->pin_nact(), c->nact_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipEventRecord(c->nact_ev, st));
       return CB_OK;
     };
@@ -564,7 +572,7 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
       const bool ahead = k <= max_iter;
       if (ahead) CHK(issue());
       HIPCHK(hipEventSynchronize(c->nact_ev));
-      n_active = *c->pin_nact();
+      n_active = *static_cast<volatile int32_t*>(c->pin_nact());
       if (n_active == 0 || !ahead) break;
       CHK(queue_read());
     }
@@ -958,6 +966,9 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->cvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
   CHK(dalloc(c->ucvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
   CHK(dalloc(c->partial, (size_t)std::max(1, c->n_chunks) * sizeof(double)));
+  const size_t n_blk = std::max<size_t>(1, (size_t)((c->nn + SEG_ALIGN - 1) / SEG_ALIGN));
+  CHK(dalloc(c->pq_part, n_blk * sizeof(double)));
+  CHK(dalloc(c->rr_part, n_blk * sizeof(double)));
   CHK(dalloc(c->scal, (size_t)P * CG_S * sizeof(double)));
   CHK(dalloc(c->params, 2 * sizeof(double)));
   CHK(dalloc(c->active, (size_t)P * sizeof(int32_t)));
@@ -968,6 +979,11 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->fptrs, (size_t)P * sizeof(double*)));
   CHK(dalloc(c->uptrs, (size_t)P * sizeof(double*)));
   HIPCHK(hipHostMalloc(&c->pin, c->pin_bytes(), hipHostMallocDefault));
+  {
+    void* dp = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&dp, c->pin, 0));
+    c->pin_nact_dev = static_cast<int32_t*>(dp);
+  }
   HIPCHK(hipStreamSynchronize(st));
   {
     float m0 = 0.f, m1 = 0.f, m2 = 0.f;

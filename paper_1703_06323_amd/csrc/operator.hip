@@ -16,49 +16,80 @@ __constant__ double c_Kref[64];   // reference Q1 stiffness (kappa = 1, h = 1)
 __constant__ double c_Mref[64];   // reference Q1 mass (h = 1)
 
 template <bool MASS, bool ONES = false>
-__device__ inline double node_gather(int N, int64_t I, int64_t J, int64_t K,
-                                     const int32_t* __restrict__ cellinfo,
-                                     const double* __restrict__ kappa,
-                                     const double* __restrict__ Mat, const double* __restrict__ x,
-                                     double scale) {
-  const int64_t N1 = N + 1;
+__device__ inline double node_gather(int N, int I, int J, int K, const int32_t* __restrict__ cellinfo,
+                                     const double* __restrict__ kappa, const double* __restrict__ Mat,
+                                     const double* __restrict__ x, double scale) {
+  const int N1 = N + 1;
+  // x at the 27 nodes (I + dx - 1, J + dy - 1, K + dz - 1) around the node,
+  // each loaded once (zero off the grid, where no active cell reads it)
+  double xn[3][3][3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int i = I + dx - 1, j = J + dy - 1, k = K + dz - 1;
+        const bool in = !ONES && i >= 0 && i < N1 && j >= 0 && j < N1 && k >= 0 && k < N1;
+        xn[dz][dy][dx] = in ? x[i + N1 * (j + N1 * k)] : 0.0;
+      }
   double acc = 0.0;
+#pragma unroll
   for (int w = 0; w < 2; ++w) {
-    const int64_t ck = K - 1 + w;
+    const int ck = K - 1 + w;
     if (ck < 0 || ck >= N) continue;
+#pragma unroll
     for (int v = 0; v < 2; ++v) {
-      const int64_t cj = J - 1 + v;
+      const int cj = J - 1 + v;
       if (cj < 0 || cj >= N) continue;
+#pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int64_t ci = I - 1 + u;
+        const int ci = I - 1 + u;
         if (ci < 0 || ci >= N) continue;
-        const int64_t c = ci + N * (cj + N * ck);
+        const int64_t c = ci + (int64_t)N * (cj + (int64_t)N * ck);
         const int32_t info = cellinfo[c];
         if (info == CELL_INACTIVE) continue;
-        const int a = (1 - u) + 2 * (1 - v) + 4 * (1 - w);
-        const int64_t n0 = ci + N1 * (cj + N1 * ck);
+        const int a = (1 - u) + 2 * (1 - v) + 4 * (1 - w);   // the node's corner in the cell
         const double s = MASS ? scale : kappa[c] * scale;
         double row = 0.0;
         if (info == CELL_UNCUT) {
           const double* R = MASS ? c_Mref : c_Kref;
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const int64_t nb = n0 + (b & 1) + N1 * (((b >> 1) & 1) + N1 * ((b >> 2) & 1));
-            row += R[a * 8 + b] * (ONES ? 1.0 : x[nb]);
-          }
+          for (int b = 0; b < 8; ++b)
+            row += R[a * 8 + b] * (ONES ? 1.0 : xn[w + ((b >> 2) & 1)][v + ((b >> 1) & 1)][u + (b & 1)]);
         } else {
           const double* R = Mat + (int64_t)info * PACK36;
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const int64_t nb = n0 + (b & 1) + N1 * (((b >> 1) & 1) + N1 * ((b >> 2) & 1));
-            row += R[pack_index(a, b)] * (ONES ? 1.0 : x[nb]);
-          }
+          for (int b = 0; b < 8; ++b)
+            row += R[pack_index(a, b)] * (ONES ? 1.0 : xn[w + ((b >> 2) & 1)][v + ((b >> 1) & 1)][u + (b & 1)]);
         }
         acc += s * row;
       }
     }
   }
   return acc;
+}
+
+// Sum of v over the workgroup, returned to every thread (the same order in
+// every workgroup: lanes by shuffles, then the waves in order).  sh holds
+// one double per wave.
+__device__ inline double wg_sum_all(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// Sum of part[b0, b1) by the whole workgroup, returned to every thread; all
+// workgroups that call it with the same range get the same value.
+__device__ inline double wg_sum_range(const double* __restrict__ part, int64_t b0, int64_t b1, double* sh) {
+  double acc = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) acc += part[i];
+  return wg_sum_all(acc, sh);
 }
 
 // Node-space kernels run in blocks of SEG_ALIGN threads, so every block lies
@@ -69,22 +100,28 @@ __global__ __launch_bounds__(256) void apply_A_kernel(BatchDev bd, int64_t nn,
                                                       const double* __restrict__ Kc,
                                                       const uint8_t* __restrict__ dofmask,
                                                       const double* __restrict__ x,
-                                                      double* __restrict__ y) {
+                                                      double* __restrict__ y, double* __restrict__ dpart) {
+  __shared__ double sh[SEG_ALIGN / 64];
   const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
   const int64_t n = base + threadIdx.x;
-  if (n >= nn) return;
+  if (base >= nn) return;
   const int p = find_segment(bd.node_off, bd.P, base);
   if (bd.active && !bd.active[p]) return;
-  if (!dofmask[n]) {
-    y[n] = 0.0;
-    return;
+  double v = 0.0;
+  if (n < nn && dofmask[n]) {
+    const ProbDev pr = bd.prob[p];
+    const int N1 = pr.N + 1;
+    const int l = (int)(n - pr.node_off);
+    const int I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
+    v = node_gather<false>(pr.N, I, J, K, cellinfo + pr.cell_off, kappa + pr.cell_off, Kc, x + pr.node_off,
+                           pr.h);
   }
-  const ProbDev pr = bd.prob[p];
-  const int64_t N1 = pr.N + 1;
-  const int64_t l = n - pr.node_off;
-  const int64_t I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
-  y[n] = node_gather<false>(pr.N, I, J, K, cellinfo + pr.cell_off, kappa + pr.cell_off, Kc,
-                            x + pr.node_off, pr.h);
+  if (n < nn) y[n] = v;
+  if (dpart) {
+    // this block's part of x.y
+    const double t = wg_sum_all(n < nn ? x[n] * v : 0.0, sh);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+  }
 }
 
 __global__ __launch_bounds__(256) void load_kernel(BatchDev bd, int64_t nn,
@@ -103,13 +140,14 @@ __global__ __launch_bounds__(256) void load_kernel(BatchDev bd, int64_t nn,
   }
   const int p = find_segment(bd.node_off, bd.P, base);
   const ProbDev pr = bd.prob[p];
-  const int64_t N1 = pr.N + 1;
+  const int N1 = pr.N + 1;
   const int64_t l = n - pr.node_off;
-  if (l >= N1 * N1 * N1) {
+  if (l >= (int64_t)N1 * N1 * N1) {
     b[n] = 0.0;
     return;
   }
-  const int64_t I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
+  const int li = (int)l;
+  const int I = li % N1, J = (li / N1) % N1, K = li / (N1 * N1);
   const double* fp = f_ptrs ? f_ptrs[p] : f + pr.node_off;
   const double h3 = pr.h * pr.h * pr.h;
   b[n] = fp ? node_gather<true>(pr.N, I, J, K, cellinfo + pr.cell_off, nullptr, Mc, fp, h3)
@@ -173,42 +211,57 @@ __global__ void copy_kernel(int64_t n, const double* __restrict__ src, double* _
   if (i < n) dst[i] = src[i];
 }
 
-// x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem;
-// zero1 and zero2 (may be null) are cleared on the same nodes (the
-// preconditioner's scratch vectors, so that they need no fill of their own).
-__global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t nn, const double* __restrict__ S,
+// x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem
+// (rho = r.z of the latest preconditioned residual, slot 3; p.q from the
+// block parts of the operator kernel, also stored in slot 1); the block
+// parts of the new r.r go to rr_part.  zero1 and zero2 (may be null) are
+// cleared on the same nodes (the preconditioner's scratch vectors, so that
+// they need no fill of their own).
+__global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t nn, double* __restrict__ S,
+                                                           const double* __restrict__ pq_part,
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q, double* __restrict__ x,
                                                            double* __restrict__ r, double* __restrict__ zero1,
-                                                           double* __restrict__ zero2) {
+                                                           double* __restrict__ zero2, double* __restrict__ rr_part) {
+  __shared__ double sh[SEG_ALIGN / 64];
   const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
   const int64_t i = base + threadIdx.x;
-  if (i >= nn) return;
+  if (base >= nn) return;
   const int pb = find_segment(bd.node_off, bd.P, base);
   if (bd.active && !bd.active[pb]) return;
-  const double alpha = S[CG_S * pb + 0] / S[CG_S * pb + 1];
-  x[i] += alpha * p[i];
-  r[i] -= alpha * q[i];
-  if (zero1) zero1[i] = 0.0;
-  if (zero2) zero2[i] = 0.0;
+  const int64_t b0 = bd.node_off[pb] / SEG_ALIGN, b1 = (bd.node_off[pb + 1] + SEG_ALIGN - 1) / SEG_ALIGN;
+  const double pq = wg_sum_range(pq_part, b0, b1, sh);
+  if ((int64_t)blockIdx.x == b0 && threadIdx.x == 0) S[CG_S * pb + 1] = pq;
+  const double alpha = S[CG_S * pb + 3] / pq;
+  double rn = 0.0;
+  if (i < nn) {
+    x[i] += alpha * p[i];
+    rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    if (zero1) zero1[i] = 0.0;
+    if (zero2) zero2[i] = 0.0;
+  }
+  const double t = wg_sum_all(rn * rn, sh);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = t;
 }
 
-// p = z + beta p with beta = rho_new / rho; the swap rho = rho_new is a
-// separate kernel since no block knows that the others are done.
-__global__ __launch_bounds__(256) void cg_update_p_kernel(BatchDev bd, int64_t nn, const double* __restrict__ S,
+// p = z + beta p with beta = rho_new / rho: rho_new = r.z from the chunk
+// parts of the dot kernel (also stored in slot 3), rho in slot 0 (moved
+// there by the check of the iteration).
+__global__ __launch_bounds__(256) void cg_update_p_kernel(BatchDev bd, int64_t nn, double* __restrict__ S,
+                                                          const int32_t* __restrict__ chunk_ptr,
+                                                          const double* __restrict__ rz_part,
                                                           const double* __restrict__ z, double* __restrict__ p) {
+  __shared__ double sh[SEG_ALIGN / 64];
   const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
   const int64_t i = base + threadIdx.x;
-  if (i >= nn) return;
+  if (base >= nn) return;
   const int pb = find_segment(bd.node_off, bd.P, base);
   if (bd.active && !bd.active[pb]) return;
-  const double beta = S[CG_S * pb + 3] / S[CG_S * pb + 0];
-  p[i] = z[i] + beta * p[i];
-}
-
-__global__ void cg_swap_rho_kernel(int P, const int32_t* __restrict__ active, double* __restrict__ S) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
-    if (!active || active[p]) S[CG_S * p + 0] = S[CG_S * p + 3];
+  const double rz = wg_sum_range(rz_part, chunk_ptr[pb], chunk_ptr[pb + 1], sh);
+  if (base == bd.node_off[pb] && threadIdx.x == 0) S[CG_S * pb + 3] = rz;
+  const double beta = rz / S[CG_S * pb + 0];
+  if (i < nn) p[i] = z[i] + beta * p[i];
 }
 
 __global__ void set_params_kernel(double* params, double rtol, int32_t max_iter) {
@@ -218,8 +271,9 @@ __global__ void set_params_kernel(double* params, double rtol, int32_t max_iter)
   }
 }
 
-// Number of running problems, written by thread 0 (one block of 256).
-__device__ inline void count_active(int P, const int32_t* active, int32_t* n_active) {
+// Number of running problems, written by thread 0 (one block of 256) to
+// n_active and, if given, to host memory.
+__device__ inline void count_active(int P, const int32_t* active, int32_t* n_active, int32_t* host = nullptr) {
   __shared__ int32_t cnt[256];
   int32_t c = 0;
   for (int p = threadIdx.x; p < P; p += 256) c += active[p] ? 1 : 0;
@@ -229,7 +283,10 @@ __device__ inline void count_active(int P, const int32_t* active, int32_t* n_act
     if ((int)threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *n_active = cnt[0];
+  if (threadIdx.x == 0) {
+    *n_active = cnt[0];
+    if (host) *host = cnt[0];
+  }
 }
 
 // Start of PCG: a zero right-hand side is converged at iteration 0; with
@@ -262,13 +319,32 @@ __global__ __launch_bounds__(256) void cg_init_kernel(int P, const double* __res
 
 // After the x, r update of an iteration: count it, test |r| < rtol |b|, a
 // non-finite residual, and the iteration limit (one workgroup of 256).
-__device__ void cg_check_block(int P, const double* __restrict__ params, const double* S,
-                               int32_t* __restrict__ active, int32_t* __restrict__ it, int32_t* __restrict__ status,
-                               double* __restrict__ relres, int32_t* __restrict__ n_active) {
+// r.r of a running problem is the sum of its block parts (one wave per
+// problem) and goes to slot 2.  The rho of the iteration (slot 3, read by
+// the x, r update) moves to slot 0, where the p update finds it after slot
+// 3 receives the new r.z.  The count of running problems also goes to
+// host memory (nact_host, may be null).
+__global__ __launch_bounds__(256) void cg_check_kernel(int P, const int64_t* __restrict__ node_off,
+                                                       const double* __restrict__ rr_part,
+                                                       const double* __restrict__ params, double* __restrict__ S,
+                                                       int32_t* __restrict__ active, int32_t* __restrict__ it,
+                                                       int32_t* __restrict__ status, double* __restrict__ relres,
+                                                       int32_t* __restrict__ n_active, int32_t* nact_host) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int p = wv; p < P; p += 4) {
+    if (!active[p]) continue;
+    double acc = 0.0;
+    const int64_t b1 = (node_off[p + 1] + SEG_ALIGN - 1) / SEG_ALIGN;
+    for (int64_t b = node_off[p] / SEG_ALIGN + lane; b < b1; b += 64) acc += rr_part[b];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) S[CG_S * p + 2] = acc;
+  }
+  __syncthreads();
   const double rtol = params[0];
   const int32_t max_iter = (int32_t)params[1];
   for (int p = threadIdx.x; p < P; p += 256) {
     if (!active[p]) continue;
+    S[CG_S * p + 0] = S[CG_S * p + 3];
     const int32_t k = it[p] + 1;
     it[p] = k;
     const double rr = S[CG_S * p + 2];
@@ -288,14 +364,7 @@ __device__ void cg_check_block(int P, const double* __restrict__ params, const d
     }
   }
   __syncthreads();
-  count_active(P, active, n_active);
-}
-
-__global__ __launch_bounds__(256) void cg_check_kernel(int P, const double* __restrict__ params,
-                                                       const double* __restrict__ S, int32_t* __restrict__ active,
-                                                       int32_t* __restrict__ it, int32_t* __restrict__ status,
-                                                       double* __restrict__ relres, int32_t* __restrict__ n_active) {
-  cg_check_block(P, params, S, active, it, status, relres, n_active);
+  count_active(P, active, n_active, nact_host);
 }
 
 __global__ void gather_dofs_batch_kernel(int P, int64_t n, const int64_t* __restrict__ dof_off,
@@ -368,11 +437,11 @@ void set_reference_matrices(const double* Kref, const double* Mref) {
 }
 
 void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
-                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x,
-                    double* y) {
+                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x, double* y,
+                    double* dpart) {
   if (nn <= 0) return;
   hipLaunchKernelGGL(apply_A_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, cellinfo,
-                     kappa, Kc, dofmask, x, y);
+                     kappa, Kc, dofmask, x, y, dpart);
 }
 
 void launch_load(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
@@ -414,16 +483,17 @@ void launch_copy(hipStream_t st, int64_t n, const double* src, double* dst) {
   hipLaunchKernelGGL(copy_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, src, dst);
 }
 
-void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, const double* S, const double* p,
-                         const double* q, double* x, double* r, double* zero1, double* zero2) {
-  hipLaunchKernelGGL(cg_update_xr_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, p, q,
-                     x, r, zero1, zero2);
+void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* pq_part,
+                         const double* p, const double* q, double* x, double* r, double* zero1, double* zero2,
+                         double* rr_part) {
+  hipLaunchKernelGGL(cg_update_xr_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, pq_part,
+                     p, q, x, r, zero1, zero2, rr_part);
 }
 
-void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* z,
-                        double* p) {
-  hipLaunchKernelGGL(cg_update_p_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, z, p);
-  hipLaunchKernelGGL(cg_swap_rho_kernel, dim3(nblocks(b.P, 256)), dim3(256), 0, st, b.P, b.active, S);
+void launch_cg_update_p(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const int32_t* chunk_ptr,
+                        const double* rz_part, const double* z, double* p) {
+  hipLaunchKernelGGL(cg_update_p_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, S, chunk_ptr,
+                     rz_part, z, p);
 }
 
 void launch_set_params(hipStream_t st, double* params, double rtol, int32_t max_iter) {
@@ -436,10 +506,11 @@ void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int3
                      n_active);
 }
 
-void launch_cg_check(hipStream_t st, int P, const double* params, const double* S, int32_t* active,
-                     int32_t* it, int32_t* status, double* relres, int32_t* n_active) {
-  hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(256), 0, st, P, params, S, active, it, status, relres,
-                     n_active);
+void launch_cg_check(hipStream_t st, int P, const int64_t* node_off, const double* rr_part, const double* params,
+                     double* S, int32_t* active, int32_t* it, int32_t* status, double* relres, int32_t* n_active,
+                     int32_t* nact_host) {
+  hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(256), 0, st, P, node_off, rr_part, params, S, active, it,
+                     status, relres, n_active, nact_host);
 }
 
 void launch_gather_dofs_batch(hipStream_t st, int P, int64_t n_dof_total, const int64_t* dof_off,
@@ -452,6 +523,12 @@ void launch_gather_dofs_batch(hipStream_t st, int P, int64_t n_dof_total, const 
 void convert_to_float(hipStream_t st, int64_t n, const double* a, float* b) {
   if (n <= 0) return;
   hipLaunchKernelGGL(convert_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, n, a, b);
+}
+
+void launch_dot_chunks(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks, const double* x,
+                       const double* y, double* partial) {
+  if (n_chunks <= 0) return;
+  hipLaunchKernelGGL(dot_chunk_kernel, dim3(n_chunks), dim3(DOT_THREADS), 0, st, b, chunk_ptr, x, y, partial);
 }
 
 void launch_dot(hipStream_t st, const BatchDev& b, const int32_t* chunk_ptr, int32_t n_chunks,
