@@ -306,12 +306,15 @@ struct NodeScan {
   __device__ void finish(Count4 tot) const { seg[b.P] = tot; }
 };
 
+__device__ inline int64_t axis_step(int axis, int64_t N1) { return axis == 0 ? 1 : (axis == 1 ? N1 : N1 * N1); }
+
 // ---- floating components ---------------------------------------------------
-// Every active cell joins its DOF nodes; a cell on the cube boundary marks
-// its component as grounded (after the joins, in a second launch).
-__global__ __launch_bounds__(IT) void float_join_kernel(BatchDev b, int64_t nc, const int32_t* __restrict__ count,
-                                                        const uint8_t* __restrict__ smask, int32_t* par,
-                                                        uint8_t* ground, int mark) {
+// After the joins (float_local_kernel, float_cross_kernel, compression): an
+// active cell on the cube boundary marks the component of its DOF corners
+// as grounded.
+__global__ __launch_bounds__(IT) void float_ground_kernel(BatchDev b, int64_t nc, const int32_t* __restrict__ count,
+                                                          const uint8_t* __restrict__ smask,
+                                                          const int32_t* __restrict__ par, uint8_t* ground) {
   const int64_t c = (int64_t)blockIdx.x * IT + threadIdx.x;
   if (c >= nc) return;
   const int p = find_segment(b.cell_off, b.P, c);
@@ -319,19 +322,106 @@ __global__ __launch_bounds__(IT) void float_join_kernel(BatchDev b, int64_t nc, 
   const int64_t N = d.N, N1 = N + 1, lc = c - d.cell_off;
   if (lc >= N * N * N || count[c] <= 0) return;
   const int64_t i = lc % N, j = (lc / N) % N, k = lc / (N * N);
-  int32_t first = -1;
+  if (!(i == 0 || j == 0 || k == 0 || i == N - 1 || j == N - 1 || k == N - 1)) return;
   for (int u = 0; u < 8; ++u) {
     const int64_t n = d.node_off + (i + (u & 1)) + N1 * ((j + (u >> 1 & 1)) + N1 * (k + (u >> 2)));
-    if (!smask[n]) continue;
-    if (first < 0) {
-      first = (int32_t)n;
-      if (mark) break;
-    } else {
-      uf_unite(par, first, (int32_t)n);
+    if (smask[n]) {
+      ground[par[n]] = 1;
+      return;
     }
   }
-  if (mark && first >= 0 && (i == 0 || j == 0 || k == 0 || i == N - 1 || j == N - 1 || k == N - 1))
-    ground[par[first]] = 1;
+}
+
+// Edge-based joins for the floating check.  The DOF corners of an active
+// cell are the cell's corners off the cube faces: a sub-box of the cell,
+// connected through its edges, so DOF nodes joined by active cells are the
+// DOF nodes joined by FE edges that belong to an active cell.  Whether the
+// edge from node (I, J, K) along axis a is such an edge:
+__device__ inline bool active_edge(const int32_t* __restrict__ cnt, int N, int I, int J, int K, int axis) {
+  const int o1 = axis == 0 ? 1 : 0, o2 = axis == 2 ? 1 : 2;   // the two other axes
+  const int ijk[3] = {I, J, K};
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      int c3[3] = {ijk[0], ijk[1], ijk[2]};
+      c3[o1] -= u;
+      c3[o2] -= v;
+      if (c3[0] < 0 || c3[1] < 0 || c3[2] < 0 || c3[0] >= N || c3[1] >= N || c3[2] >= N) continue;
+      if (cnt[c3[0] + (int64_t)N * (c3[1] + (int64_t)N * c3[2])] > 0) return true;
+    }
+  return false;
+}
+
+// Pass 1: joins along the active FE edges whose two nodes lie in the same
+// block of IT consecutive nodes, by union-find in LDS (larger root below the
+// smaller node); every node then points to its block-local root.  Pass 2
+// (float_cross_kernel) joins the edges that leave the block, by the global
+// union-find.
+__global__ __launch_bounds__(IT) void float_local_kernel(BatchDev b, int64_t nn, const int32_t* __restrict__ count,
+                                                         const uint8_t* __restrict__ smask, int32_t* __restrict__ par) {
+  __shared__ int32_t lp[IT];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * IT, n = base + tid;
+  lp[tid] = tid;
+  __syncthreads();
+  NodePos q;
+  if (n < nn && smask[n] && node_pos(b, n, q)) {
+    const ProbDev& d = b.prob[q.p];
+    const int64_t N1 = q.N + 1;
+    const int32_t* cnt = count + d.cell_off;
+    const int ijk[3] = {q.I, q.J, q.K};
+    for (int axis = 0; axis < 3; ++axis) {
+      const int64_t m = n + axis_step(axis, N1);
+      if (ijk[axis] + 1 > q.N || m >= base + IT || !smask[m] || !active_edge(cnt, q.N, q.I, q.J, q.K, axis))
+        continue;
+      int ra = tid, rb = (int)(m - base);
+      for (;;) {
+        while (true) {
+          const int t = __hip_atomic_load(&lp[ra], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (t == ra) break;
+          ra = t;
+        }
+        while (true) {
+          const int t = __hip_atomic_load(&lp[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (t == rb) break;
+          rb = t;
+        }
+        if (ra == rb) break;
+        if (ra < rb) {
+          const int t = ra;
+          ra = rb;
+          rb = t;
+        }
+        if (atomicCAS(&lp[ra], ra, rb) == ra) break;
+      }
+    }
+  }
+  __syncthreads();
+  if (n < nn) {
+    int r = tid;
+    while (true) {
+      const int t = lp[r];
+      if (t == r) break;
+      r = t;
+    }
+    par[n] = (int32_t)(base + r);
+  }
+}
+
+__global__ __launch_bounds__(IT) void float_cross_kernel(BatchDev b, int64_t nn, const int32_t* __restrict__ count,
+                                                         const uint8_t* __restrict__ smask, int32_t* par) {
+  const int64_t n = (int64_t)blockIdx.x * IT + threadIdx.x;
+  const int64_t end = ((int64_t)blockIdx.x + 1) * IT;
+  NodePos q;
+  if (n >= nn || !smask[n] || !node_pos(b, n, q)) return;
+  const ProbDev& d = b.prob[q.p];
+  const int64_t N1 = q.N + 1;
+  const int32_t* cnt = count + d.cell_off;
+  const int ijk[3] = {q.I, q.J, q.K};
+  for (int axis = 0; axis < 3; ++axis) {
+    const int64_t m = n + axis_step(axis, N1);
+    if (ijk[axis] + 1 > q.N || m < end || !smask[m] || !active_edge(cnt, q.N, q.I, q.J, q.K, axis)) continue;
+    uf_unite(par, (int32_t)n, (int32_t)m);
+  }
 }
 
 __global__ __launch_bounds__(IT) void float_check_kernel(BatchDev b, int64_t nn, const uint8_t* __restrict__ smask,
@@ -343,7 +433,6 @@ __global__ __launch_bounds__(IT) void float_check_kernel(BatchDev b, int64_t nn,
 }
 
 // ---- links and objects -----------------------------------------------------
-__device__ inline int64_t axis_step(int axis, int64_t N1) { return axis == 0 ? 1 : (axis == 1 ? N1 : N1 * N1); }
 
 __global__ __launch_bounds__(IT) void link_kernel(BatchDev b, int64_t nn, const int32_t* __restrict__ count,
                                                   const uint8_t* __restrict__ smask, uint8_t* __restrict__ link) {
@@ -775,10 +864,10 @@ void launch_index_nodes(hipStream_t st, const BatchDev& b, int64_t n_cells_total
   hipLaunchKernelGGL(zero_i32_kernel, gn, blk, 0, st, nn, w.size1, w.size2);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(b.P)), blk, 0, st, (int64_t)b.P, w.floating, (int32_t*)nullptr);
   // floating components: join, compress, mark grounded roots, check
-  hipLaunchKernelGGL(iota_kernel, gn, blk, 0, st, nn, w.par0);
-  hipLaunchKernelGGL(float_join_kernel, gc, blk, 0, st, b, n_cells_total, count, w.smask, w.par0, w.ground, 0);
+  hipLaunchKernelGGL(float_local_kernel, gn, blk, 0, st, b, nn, count, w.smask, w.par0);
+  hipLaunchKernelGGL(float_cross_kernel, gn, blk, 0, st, b, nn, count, w.smask, w.par0);
   hipLaunchKernelGGL(compress_kernel, gn, blk, 0, st, nn, w.par0);
-  hipLaunchKernelGGL(float_join_kernel, gc, blk, 0, st, b, n_cells_total, count, w.smask, w.par0, w.ground, 1);
+  hipLaunchKernelGGL(float_ground_kernel, gc, blk, 0, st, b, n_cells_total, count, w.smask, w.par0, w.ground);
   hipLaunchKernelGGL(float_check_kernel, gn, blk, 0, st, b, nn, w.smask, w.par0, w.ground, w.floating);
   // objects before the variant-1 split
   hipLaunchKernelGGL(link_kernel, gn, blk, 0, st, b, nn, count, w.smask, w.link);
