@@ -44,6 +44,14 @@ __device__ inline void load_block_cells(const GridDev& g, const ProbDev& pr, int
   }
 }
 
+template <typename T> struct RowVec;   // 16 bytes of T
+template <> struct RowVec<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
+};
+template <> struct RowVec<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+
 // Kernel 1: per subdomain, the unscaled diagonal of A_omega, rho per coarse
 // object, the Jacobi scaling, and the scaled padded matrix
 // K = D (A_omega + C^T R C) D (identity on padding rows).  The diagonal and
@@ -51,9 +59,10 @@ __device__ inline void load_block_cells(const GridDev& g, const ProbDev& pr, int
 // rows in LDS: 27 lanes each sum one neighbour of the row's node over the
 // cells around it (fixed order), lanes over the object's slots add the
 // C^T R C term, and the row is written out with coalesced stores.
+constexpr int ASM_WAVES = 8;   // rows in flight per subdomain (one per wave)
 template <typename T>
-__global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat, double* diagA_G,
-                                                             double* Dscale) {
+__global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat,
+                                                                       double* diagA_G, double* Dscale) {
   extern __shared__ double smem[];
   const int w = blockIdx.x;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
@@ -65,7 +74,7 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
   int* optr = reinterpret_cast<int*>(ckh + s3);    // [NCp + 1]
   int* omem = optr + NCp + 1;                      // [NGp]
   int* cinfo = omem + NGp;                         // [s^3]
-  T* rows = reinterpret_cast<T*>(ckh + s3 + (NCp + 1 + NGp + s3 + 1) / 2);   // [4][nt]
+  T* rows = reinterpret_cast<T*>(ckh + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4));   // [ASM_WAVES][nt]
   const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
   const ProbDev pr = g.prob[sd.sub_prob[w]];
   const int m = pr.m, N1 = pr.N + 1;
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
     return true;
   };
   // phase 0: diagonal of A_omega
-  for (int r = tid; r < nt; r += 256) {
+  for (int r = tid; r < nt; r += 64 * ASM_WAVES) {
     int lx, ly, lz;
     double d = 0.0;
     if (row_xyz(r, lx, ly, lz)) {
@@ -116,14 +125,14 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
   }
   object_members(sd, w, optr, omem);   // ends with a barrier
   // phase 1: rho_t / |t|^2 with rho_t the sum of the diagonal over object t
-  for (int t = tid; t < NCp; t += 256) {
+  for (int t = tid; t < NCp; t += 64 * ASM_WAVES) {
     double sr = 0.0;
     const int b0 = optr[t], b1 = optr[t + 1];
     for (int q = b0; q < b1; ++q) sr += diag[NIp + omem[q]];
     rho[t] = (t < nC && b1 > b0) ? sr / ((double)(b1 - b0) * (double)(b1 - b0)) : 0.0;
   }
   __syncthreads();
-  for (int r = tid; r < nt; r += 256) {
+  for (int r = tid; r < nt; r += 64 * ASM_WAVES) {
     int lx, ly, lz;
     const bool real = row_xyz(r, lx, ly, lz);
     double dk = diag[r];
@@ -138,8 +147,10 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
   // phase 2: rows, one wave per row
   const int lane = tid & 63, wv = tid >> 6;
   T* rb = rows + wv * nt;
-  for (int r = wv; r < nt; r += 4) {
-    for (int c = lane; c < nt; c += 64) rb[c] = T(0);
+  typedef typename RowVec<T>::type V;
+  constexpr int VW = 16 / sizeof(T);
+  for (int r = wv; r < nt; r += ASM_WAVES) {
+    for (int c = lane * VW; c < nt; c += 64 * VW) *reinterpret_cast<V*>(rb + c) = V{};
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     int lx, ly, lz;
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(256) void assemble_local_kernel(SubDev sd, GridDev 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     T* Kr = K + (int64_t)r * nt;
-    for (int c = lane; c < nt; c += 64) Kr[c] = rb[c];
+    for (int c = lane * VW; c < nt; c += 64 * VW) *reinterpret_cast<V*>(Kr + c) = *reinterpret_cast<const V*>(rb + c);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -741,9 +752,12 @@ void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, i
                            double* diagA_G, double* Dscale) {
   const int nt = sd.NIp + sd.NGp;
   const int s3 = g.s * g.s * g.s;
-  const size_t sh = (size_t)(2 * nt + sd.NCp + s3 + (sd.NCp + 1 + sd.NGp + s3 + 1) / 2) * sizeof(double) +
-                    (size_t)4 * nt * sizeof(T);
-  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(256), sh, st, sd, g, K, diagA_G, Dscale);
+  const size_t sh = (size_t)(2 * nt + sd.NCp + s3 + 2 * ((sd.NCp + 1 + sd.NGp + s3 + 3) / 4)) * sizeof(double) +
+                    (size_t)ASM_WAVES * nt * sizeof(T);
+  static const bool attr = hipFuncSetAttribute((const void*)assemble_local_kernel<T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+  (void)attr;
+  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G, Dscale);
 }
 template void launch_assemble_local<double>(hipStream_t, const SubDev&, const GridDev&, int, double*,
                                             double*, double*);
