@@ -32,14 +32,20 @@ struct GridDev {
 
 void bddc_set_reference(const double* Kref);
 
+// Stencil rows of A_omega kept for the Gram-matrix products: for row r of
+// subdomain w, slot k (neighbour offset (k%3-1, k/3%3-1, k/9-1)) holds the
+// unscaled entry and its column (-1: none), at [(w nt + r) 27 + k].
+constexpr int STENCIL = 27;
+// Also writes the stencil rows (st_val, st_col) when they are non-null.
 template <typename T>
 void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
-                           double* diagA_G, double* Dscale);
+                           double* diagA_G, double* Dscale, double* st_val, int32_t* st_col);
 void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
                     const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw);
-// Rows [r0, r0 + nrows) of Y = A_omega X (FP64, nt x NCp blocks).
-void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y,
-                        int r0, int nrows);
+// Rows [r0, r0 + nrows) of Y = A_omega X (FP64, nt x NCp blocks), from the
+// stencil rows written by launch_assemble_local.
+void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* st_val, const int32_t* st_col,
+                        const double* X, double* Y, int r0, int nrows);
 // Gt = (K_S^{-1} C^T)^T (NCp x NGp) and S_c = C G with C the object-mean
 // constraints.
 void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt);

@@ -62,7 +62,9 @@ template <> struct RowVec<double> {
 constexpr int ASM_WAVES = 8;   // rows in flight per subdomain (one per wave)
 template <typename T>
 __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat,
-                                                                       double* diagA_G, double* Dscale) {
+                                                                       double* diagA_G, double* Dscale,
+                                                                       double* __restrict__ st_val,
+                                                                       int32_t* __restrict__ st_col) {
   extern __shared__ double smem[];
   const int w = blockIdx.x;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
@@ -154,8 +156,13 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev s
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     int lx, ly, lz;
+    const int64_t so = ((int64_t)w * nt + r) * STENCIL;
     if (!row_xyz(r, lx, ly, lz)) {
       if (lane == 0) rb[r] = T(1);
+      if (st_val && lane < STENCIL) {
+        st_val[so + lane] = 0.0;
+        st_col[so + lane] = -1;
+      }
     } else {
       if (lane < 27) {
         const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
@@ -180,7 +187,11 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev s
             v += ckh[lc] * kab;
           }
           rb[col] = (T)(v * Ds[r] * Ds[col]);
+          if (st_val) st_val[so + lane] = v;
+        } else if (st_val) {
+          st_val[so + lane] = 0.0;
         }
+        if (st_col) st_col[so + lane] = col;
       }
       if (r >= NIp) {
         const int t = gobj[r - NIp];
@@ -223,86 +234,35 @@ __global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_p
 
 // Kernel 3b: Y[r][t] = sum_c A_omega[r][c] X[c][t] for the local rows r in
 // [r0, r0 + nrows) (unscaled FP64 local Neumann matrix; X, Y are nt x NCp
-// per subdomain).  One block per (LA_ROWS-row chunk, subdomain): one thread
-// per row first sums the row's stencil (at most 27 neighbours, over the
-// active cells of the subdomain around the row's node) into LDS; then all
-// threads stream X along its rows.
+// per subdomain), from the stencil rows stored by the assembly.  One block
+// per (LA_ROWS-row chunk, subdomain): the chunk's stencil rows go to LDS,
+// then all threads stream X along its rows (entries summed in slot order).
 constexpr int LA_ROWS = 64;
-__global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, GridDev g, const double* __restrict__ X,
-                                                          double* __restrict__ Y, int r0, int nrows) {
-  __shared__ double sval[LA_ROWS][27];
-  __shared__ int scol[LA_ROWS][27];
-  extern __shared__ double la_cells[];   // [s^3] kappa h, then [s^3] cell info
+__global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, const double* __restrict__ st_val,
+                                                          const int32_t* __restrict__ st_col,
+                                                          const double* __restrict__ X, double* __restrict__ Y,
+                                                          int r0, int nrows) {
+  __shared__ double sval[LA_ROWS * STENCIL];
+  __shared__ int scol[LA_ROWS * STENCIL];
   const int w = blockIdx.y;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
   const int rb = r0 + blockIdx.x * LA_ROWS;
   const int tid = threadIdx.x;
-  const int s3 = g.s * g.s * g.s;
-  double* ckh = la_cells;
-  int* cinfo = reinterpret_cast<int*>(la_cells + s3);
-  {
-    const ProbDev pr = g.prob[sd.sub_prob[w]];
-    const int blk = sd.sub_blk[w], m = pr.m;
-    load_block_cells(g, pr, blk % m, (blk / m) % m, blk / (m * m), cinfo, ckh);
-  }
-  __syncthreads();
-  // rows of A_omega, one task per (row, neighbour slot): the entry couples
-  // the row's node with neighbour k and sums, in a fixed cell order, over
-  // the active cells of the block that contain both nodes
-  {
-    const ProbDev pr = g.prob[sd.sub_prob[w]];
-    const int s = g.s, m = pr.m, s1 = s + 1, N1 = pr.N + 1;
-    const int blk = sd.sub_blk[w];
-    const int Bx = blk % m, By = (blk / m) % m, Bz = blk / (m * m);
-    const int* loc = sd.bloc + (int64_t)w * s1 * s1 * s1;
-    const int nI = sd.nI[w], nG = sd.nG[w];
-    for (int task = tid; task < LA_ROWS * 27; task += blockDim.x) {
-      const int rr = task / 27, k = task - rr * 27;
-      const int r = rb + rr;
-      int64_t n = -1;
-      if (r < r0 + nrows) {
-        if (r < NIp) n = r < nI ? sd.I_idx[(int64_t)w * NIp + r] : -1;
-        else n = (r - NIp) < nG ? sd.G_idx[(int64_t)w * NGp + (r - NIp)] : -1;
-      }
-      double v = 0.0;
-      int col = -1;
-      if (n >= 0) {
-        const int l = (int)(n - pr.node_off);
-        const int lx = l % N1 - Bx * s, ly = (l / N1) % N1 - By * s, lz = l / (N1 * N1) - Bz * s;
-        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-        const int bx = lx + dx, by = ly + dy, bz = lz + dz;
-        if (bx >= 0 && by >= 0 && bz >= 0 && bx <= s && by <= s && bz <= s) col = loc[bx + s1 * (by + s1 * bz)];
-        if (col >= 0) {
-          for (int u = 0; u < 8; ++u) {
-            const int cx = lx - 1 + (u & 1), cy = ly - 1 + ((u >> 1) & 1), cz = lz - 1 + ((u >> 2) & 1);
-            if (cx < 0 || cy < 0 || cz < 0 || cx >= s || cy >= s || cz >= s) continue;
-            // the cell must also contain the neighbour
-            if (bx < cx || bx > cx + 1 || by < cy || by > cy + 1 || bz < cz || bz > cz + 1) continue;
-            const int lc = cx + s * (cy + s * cz);
-            const int32_t info = cinfo[lc];
-            if (info == CELL_INACTIVE) continue;
-            const int a = (lx - cx) + 2 * (ly - cy) + 4 * (lz - cz);
-            const int b = (bx - cx) + 2 * (by - cy) + 4 * (bz - cz);
-            const double kab =
-                info == CELL_UNCUT ? c_Kref_b[a * 8 + b] : g.Kc[(int64_t)info * PACK36 + pack_index(a, b)];
-            v += ckh[lc] * kab;
-          }
-        }
-      }
-      sval[rr][k] = v;
-      scol[rr][k] = col;
-    }
-  }
-  __syncthreads();
   const int R = min(LA_ROWS, r0 + nrows - rb);
+  const int64_t so = ((int64_t)w * nt + rb) * STENCIL;
+  for (int e = tid; e < R * STENCIL; e += 256) {
+    sval[e] = st_val[so + e];
+    scol[e] = st_col[so + e];
+  }
+  __syncthreads();
   const double* x = X + (int64_t)w * nt * NCp;
   double* y = Y + (int64_t)w * nt * NCp;
   for (int e = tid; e < R * NCp; e += 256) {
     const int rr = e / NCp, t = e - rr * NCp;
     double acc = 0.0;
-    for (int k = 0; k < 27; ++k) {
-      const int col = scol[rr][k];
-      if (col >= 0) acc += sval[rr][k] * x[(int64_t)col * NCp + t];
+    for (int k = 0; k < STENCIL; ++k) {
+      const int col = scol[rr * STENCIL + k];
+      if (col >= 0) acc += sval[rr * STENCIL + k] * x[(int64_t)col * NCp + t];
     }
     y[(int64_t)(rb + rr) * NCp + t] = acc;
   }
@@ -749,7 +709,7 @@ void bddc_set_reference(const double* Kref) {
 
 template <typename T>
 void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
-                           double* diagA_G, double* Dscale) {
+                           double* diagA_G, double* Dscale, double* st_val, int32_t* st_col) {
   const int nt = sd.NIp + sd.NGp;
   const int s3 = g.s * g.s * g.s;
   const size_t sh = (size_t)(2 * nt + sd.NCp + s3 + 2 * ((sd.NCp + 1 + sd.NGp + s3 + 3) / 4)) * sizeof(double) +
@@ -757,12 +717,13 @@ void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, i
   static const bool attr = hipFuncSetAttribute((const void*)assemble_local_kernel<T>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
   (void)attr;
-  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G, Dscale);
+  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G, Dscale,
+                     st_val, st_col);
 }
 template void launch_assemble_local<double>(hipStream_t, const SubDev&, const GridDev&, int, double*,
-                                            double*, double*);
+                                            double*, double*, double*, int32_t*);
 template void launch_assemble_local<float>(hipStream_t, const SubDev&, const GridDev&, int, float*,
-                                           double*, double*);
+                                           double*, double*, double*, int32_t*);
 
 void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
                     const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw) {
@@ -771,12 +732,11 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
                      if_ptr, if_sub, if_slot, NGp, diagA_G, stiffness, Dw);
 }
 
-void launch_local_apply(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, const double* X, double* Y,
-                        int r0, int nrows) {
+void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* st_val, const int32_t* st_col,
+                        const double* X, double* Y, int r0, int nrows) {
   if (nrows <= 0 || ns <= 0) return;
   dim3 grid((nrows + LA_ROWS - 1) / LA_ROWS, ns);
-  const size_t sh = (size_t)g.s * g.s * g.s * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), sh, st, sd, g, X, Y, r0, nrows);
+  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, st_val, st_col, X, Y, r0, nrows);
 }
 
 inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }

@@ -1088,9 +1088,10 @@ int factor_impl(cb_ctx* c) {
   // work buffers for a chunk of subdomains
   const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
                          (size_t)sP * 8 + (size_t)sKS * 8 +
-                         (size_t)(sG + sC + 2 * sF) * sizeof(double);
+                         (size_t)(sG + sC + 2 * sF) * sizeof(double) +
+                         (size_t)nt * STENCIL * (sizeof(double) + sizeof(int32_t));
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
-  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V;
+  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V, StV, StC;
   CHK(dalloc(K, (size_t)chunk * sK * sizeof(T)));
   CHK(dalloc(Linv, (size_t)chunk * sL * sizeof(T)));
   CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
@@ -1101,6 +1102,8 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
   CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
   CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
+  CHK(dalloc(StV, (size_t)chunk * nt * STENCIL * sizeof(double)));
+  CHK(dalloc(StC, (size_t)chunk * nt * STENCIL * sizeof(int32_t)));
   // on every exit, st waits for the other streams before the buffers above
   // return to the cache (destroyed after this guard)
   struct AuxJoin {
@@ -1118,7 +1121,7 @@ int factor_impl(cb_ctx* c) {
     double* Phiw = c->Phi.as<double>() + (int64_t)w0 * sG;
     double* KS = KSw.as<double>();
     launch_assemble_local<T>(st, sd, g, nc, K.as<T>(), c->diagAG.as<double>() + (int64_t)w0 * NGp,
-                             c->Ds.as<double>() + (int64_t)w0 * nt);
+                             c->Ds.as<double>() + (int64_t)w0 * nt, StV.as<double>(), StC.as<int32_t>());
     HIPCHK(hipGetLastError());
     timed(c, "local_cholesky",
           [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0); });
@@ -1158,10 +1161,11 @@ int factor_impl(cb_ctx* c) {
     HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), Phiw,
                             (size_t)sG * sizeof(double), (size_t)sG * sizeof(double), nc, hipMemcpyDeviceToDevice,
                             st));
-    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>(), 0, NIp);
+    launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), 0, NIp);
     gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, sP, V.as<double>(), NCp, sF, 0.0, PhiF.as<double>(), NCp,
                  sF, nc, 0);
-    launch_local_apply(st, sd, g, nc, PhiF.as<double>(), V.as<double>(), NIp, NGp);
+    launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), NIp,
+                       NGp);
     gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
                  V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
                  nc, 0);
@@ -1225,7 +1229,7 @@ int factor_impl(cb_ctx* c) {
   // join the second stream before the chunk buffers go back to the cache
   HIPCHK(hipEventRecord(c->aux_ev, c->aux_st));
   HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
-  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V}) b->release();
+  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V, &StV, &StC}) b->release();
   std::vector<int> info(n_info);
   HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
