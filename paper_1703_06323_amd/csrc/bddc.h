@@ -78,10 +78,13 @@ void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt
                           const double* Dw, const double* r, const double* t, double* z, double* cloc);
 void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int32_t* cs_sub,
                        const int32_t* cs_row, int NCp, const double* cloc, double* c);
-// y_c = sum_j Ainv_p[c - coarse_off_p][j] x[coarse_off_p + j] for every
-// global coarse row c (p = coarse_prob[c]): block-diagonal coarse solve.
+// Coarse solve y = A_c^{-1} x = Y^T (Y x) per problem, Y = L^{-1} of the
+// coarse Cholesky factor, from M_p (ldc_p x ldc_p at ac_off_p) holding Y in
+// its lower triangle and Y^T in its upper one (the diagonal is shared):
+// t = tril(M) x, then y = triu(M) t, one workgroup per global coarse row c
+// (p = coarse_prob[c]).  t has nc_total entries.
 void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const int32_t* coarse_prob,
-                        const double* Ainv, const double* x, double* y);
+                        const double* M, const double* x, double* t, double* y);
 void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,
                        double* z);
 void launch_iface_average(hipStream_t st, int64_t n_iface, const int64_t* iface_node, const int64_t* if_ptr,

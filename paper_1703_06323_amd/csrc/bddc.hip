@@ -634,37 +634,50 @@ __global__ void coarse_rhs_kernel(int nc, const int64_t* __restrict__ cs_ptr, co
   c[q] = acc;
 }
 
-// Block-diagonal coarse solve, one wave per global coarse row.
-__global__ __launch_bounds__(256) void coarse_gemv_kernel(BatchDev bd, int nc_total,
-                                                          const int32_t* __restrict__ coarse_prob,
+// One triangular half of the coarse solve, one workgroup per global coarse
+// row (rows differ in length, and workgroups balance them): y[c] = sum over
+// j in [lo, hi] of M_p[r][j] x[j], r the problem-local row, [lo, hi] =
+// [0, r] (lower) or [r, nc_p - 1] (upper).
+constexpr int CT_T = 256;
+__global__ __launch_bounds__(CT_T) void coarse_tri_kernel(BatchDev bd, const int32_t* __restrict__ coarse_prob,
                                                           const double* __restrict__ A,
-                                                          const double* __restrict__ x, double* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= nc_total) return;
+                                                          const double* __restrict__ x, double* __restrict__ y,
+                                                          int upper) {
+  __shared__ double sh[CT_T / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = blockIdx.x;
   const int p = coarse_prob[c];
   if (bd.active && !bd.active[p]) return;
   const ProbDev pr = bd.prob[p];
-  const double* row = A + pr.ac_off + (int64_t)(c - pr.coarse_off) * pr.ldc;
+  const int r = c - pr.coarse_off;
+  const double* row = A + pr.ac_off + (int64_t)r * pr.ldc;
   const double* xp = x + pr.coarse_off;
-  const int nc = pr.nc;
+  const int lo = upper ? r : 0, hi = upper ? pr.nc - 1 : r;
   double acc = 0.0;
   if (((reinterpret_cast<uintptr_t>(row) | reinterpret_cast<uintptr_t>(xp)) & 15) == 0) {
-    // 16-byte loads: lane takes the pairs (j, j + 1), j = 2 lane + 128 m
-    int j = 2 * lane;
-#pragma unroll 4
-    for (; j + 1 < nc; j += 128) {
-      const double2 a = *reinterpret_cast<const double2*>(row + j);
-      const double2 b = *reinterpret_cast<const double2*>(xp + j);
-      acc += a.x * b.x;
-      acc += a.y * b.y;
+    // 16-byte loads of the pairs (j, j + 1), j even; a pair's element below
+    // lo is dropped, and a pair reaching past hi loads only j
+    for (int j = (lo & ~1) + 2 * tid; j <= hi; j += 2 * CT_T) {
+      if (j + 1 <= hi) {
+        const double2 a = *reinterpret_cast<const double2*>(row + j);
+        const double2 b = *reinterpret_cast<const double2*>(xp + j);
+        if (j >= lo) acc += a.x * b.x;
+        acc += a.y * b.y;
+      } else {
+        acc += row[j] * xp[j];   // j = hi >= lo here
+      }
     }
-    if (j < nc) acc += row[j] * xp[j];
   } else {
-    for (int j = lane; j < nc; j += 64) acc += row[j] * xp[j];
+    for (int j = lo + tid; j <= hi; j += CT_T) acc += row[j] * xp[j];
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[c] = acc;
+  if (lane == 0) sh[wv] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < CT_T / 64; ++i) t += sh[i];
+    y[c] = t;
+  }
 }
 
 // u~_w[j] = z_w[j] + sum_t Phi_w[j][t] u_c[C_ids[t]]  (in place in z)
@@ -829,10 +842,10 @@ void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int3
 }
 
 void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const int32_t* coarse_prob,
-                        const double* Ainv, const double* x, double* y) {
+                        const double* M, const double* x, double* t, double* y) {
   if (nc_total <= 0) return;
-  hipLaunchKernelGGL(coarse_gemv_kernel, dim3((nc_total + 3) / 4), dim3(256), 0, st, b, nc_total, coarse_prob,
-                     Ainv, x, y);
+  hipLaunchKernelGGL(coarse_tri_kernel, dim3(nc_total), dim3(CT_T), 0, st, b, coarse_prob, M, x, t, 0);
+  hipLaunchKernelGGL(coarse_tri_kernel, dim3(nc_total), dim3(CT_T), 0, st, b, coarse_prob, M, t, y, 1);
 }
 
 void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,

@@ -279,7 +279,7 @@ struct cb_ctx {
   // factor results
   DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
   // work vectors and PCG state
-  DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, ucvec, partial, scal, bgrid;
+  DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, tcvec, ucvec, partial, scal, bgrid;
   DevBuf pq_part, rr_part;   // per node block (SEG_ALIGN nodes): parts of p.q and r.r
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
@@ -431,7 +431,7 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked, bool cleare
                       c->NCp, c->cloc.as<double>(), c->cvec.as<double>());
     timed(c, "coarse_gemv", [&] {
       launch_coarse_gemv(st, c->batch(masked), c->nc_tot, c->coarse_prob_d.as<int32_t>(), c->Acinv.as<double>(),
-                         c->cvec.as<double>(), c->ucvec.as<double>());
+                         c->cvec.as<double>(), c->tcvec.as<double>(), c->ucvec.as<double>());
     });
     launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
@@ -965,6 +965,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->cloc, (size_t)ns * NCp * sizeof(double)));
   CHK(dalloc(c->cvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
   CHK(dalloc(c->ucvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
+  CHK(dalloc(c->tcvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
   CHK(dalloc(c->partial, (size_t)std::max(1, c->n_chunks) * sizeof(double)));
   const size_t n_blk = std::max<size_t>(1, (size_t)((c->nn + SEG_ALIGN - 1) / SEG_ALIGN));
   CHK(dalloc(c->pq_part, n_blk * sizeof(double)));
@@ -1199,11 +1200,10 @@ int factor_impl(cb_ctx* c) {
                            c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(), c->sub(0),
                            AcLoc.as<double>(), Ac.as<double>(), c->P == 1 ? c->AcKeep.as<double>() : nullptr);
     HIPCHK(hipGetLastError());
-    DevBuf Lc, Yc, PSc, ones;
+    DevBuf Lc, Yc, ones;
     const std::vector<double> onesv(maxL, 1.0);
     CHK(dalloc(Lc, maxD * sizeof(double)));
     CHK(dalloc(Yc, maxLL * sizeof(double)));
-    CHK(dalloc(PSc, maxLL * sizeof(double)));
     CHK(upload(ones, onesv, st));
     ProfScope cps(c, "coarse_factor");
     int slot = 0;
@@ -1218,9 +1218,9 @@ int factor_impl(cb_ctx* c) {
       if (cholesky_inverse<double>(st, ax, A, L, sA, L, nb, Lc.as<double>(), sLc,
                                    c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA) != 0)
         return fail(CB_ERR_DEVICE, "event record or wait failed in the coarse factorisation");
-      gemm<double>(st, 1, 0, L, L, L, 1.0, Yc.as<double>(), L, sA, Yc.as<double>(), L, sA, 0.0, PSc.as<double>(),
-                   L, sA, nb, GEMM_LOWER | GEMM_KFROM_DIAG);
-      symmetrize_scale<double, double>(st, PSc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
+      // the solve applies Y^T (Y x): keep Y in the lower triangle and its
+      // transpose in the upper one
+      symmetrize_scale<double, double>(st, Yc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
                                        ones.as<double>(), 0, L, nb);
       HIPCHK(hipGetLastError());
       slot += nb;
