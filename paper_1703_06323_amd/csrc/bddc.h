@@ -55,7 +55,9 @@ void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* 
 // Ac + ac_off_p (identity on the padding rows; every entry written);
 // prow_off[p] = first padded row of problem p in the launch, prow_off[P] =
 // n_prows.  keep (may be null) receives the same values.  max_ldc = largest
-// ldc_p: rows up to COARSE_ASSEMBLE_LDS_LDC long are built in LDS.
+// ldc_p: rows up to COARSE_ASSEMBLE_LDS_LDC long (or the smaller limit in
+// the environment variable CUTBDDC_COARSE_ROW_LDS) are built in LDS, longer
+// ones in place in Ac (the same sums in the same order).
 constexpr int COARSE_ASSEMBLE_LDS_LDC = 16384;
 void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows, int max_ldc,
                             const int64_t* cs_ptr, const int32_t* cs_sub, const int32_t* cs_row, const SubDev& sd,

@@ -19,6 +19,8 @@
 //   A_c^omega = Phi^T S_A Phi = S_c^{-1} - R  (local coarse matrix)
 #include "bddc.h"
 
+#include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -779,7 +781,12 @@ void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* pr
   if (n_prows <= 0) return;
   const int64_t gx = std::min<int64_t>(n_prows, 65535);
   const dim3 grid((unsigned)gx, (unsigned)((n_prows + gx - 1) / gx));
-  if (max_ldc <= COARSE_ASSEMBLE_LDS_LDC) {
+  // CUTBDDC_COARSE_ROW_LDS lowers the longest row built in LDS (read at
+  // every call, so that the global-memory path can be tested on small
+  // problems)
+  int lim = COARSE_ASSEMBLE_LDS_LDC;
+  if (const char* e = std::getenv("CUTBDDC_COARSE_ROW_LDS")) lim = std::max(0, std::min(lim, std::atoi(e)));
+  if (max_ldc <= lim) {
     static const bool attr = hipFuncSetAttribute((const void*)coarse_assemble_kernel<true>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)(COARSE_ASSEMBLE_LDS_LDC * sizeof(double))) == hipSuccess;

@@ -50,6 +50,17 @@ int fail(int code, const std::string& msg) {
     if (rc_ != CB_OK) return rc_; \
   } while (0)
 
+// Two timing events owned by one call, destroyed on every exit (error
+// returns included).
+struct EventPair {
+  hipEvent_t* a;
+  hipEvent_t* b;
+  ~EventPair() {
+    if (*a) (void)hipEventDestroy(*a);
+    if (*b) (void)hipEventDestroy(*b);
+  }
+};
+
 // Process-wide cache of device blocks: freed blocks are kept (keyed by size,
 // per device) and handed out again for requests of up to the same size, so
 // repeated setup/factor/solve cycles issue no hipMalloc/hipFree (hipFree
@@ -377,7 +388,11 @@ struct ProfScope {
     (void)hipEventRecord(b, c->st);
   }
   ~ProfScope() {
-    if (!c->prof || !b || !e) return;
+    if (!c->prof) return;
+    if (!b || !e) {
+      if (b) (void)hipEventDestroy(b);
+      return;
+    }
     (void)hipEventRecord(e, c->st);
     c->prof_ev[name].ev.emplace_back(b, e);
   }
@@ -647,7 +662,8 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   hipStream_t st = c->st;
   const int s = c->s;
 
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair ev01{&e0, &e1};
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, st));
@@ -754,7 +770,8 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   launch_classify(st, c->batch(false), ncell, c->xi_d.as<double>(), c->balls.as<double>(),
                   c->count_d.as<int32_t>());
   HIPCHK(hipGetLastError());
-  hipEvent_t ea, eb;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  EventPair ev_ab{&ea, &eb};
   HIPCHK(hipEventCreate(&ea));
   HIPCHK(hipEventCreate(&eb));
   HIPCHK(hipEventRecord(ea, st));
@@ -994,10 +1011,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     c->info.t_integrate_ms = m0 + m2;
     c->info.t_topology_ms = m1;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(ea);
-  (void)hipEventDestroy(eb);
+
 
   // per-problem and total counts
   cb_info& tot = c->info;
@@ -1371,7 +1385,8 @@ int cb_setup_batch(const cb_problem* problems, int32_t n, void* stream, cb_ctx**
 
 int cb_factor(cb_ctx* c) {
   if (!c) return fail(CB_ERR_ARG, "null context");
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair ev01{&e0, &e1};
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
@@ -1389,8 +1404,6 @@ int cb_factor(cb_ctx* c) {
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   c->info.t_factor_ms = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->factored = true;
   c->info.factored = 1;
   return CB_OK;
@@ -1403,7 +1416,8 @@ namespace {
 // PCG on c->bgrid, then the DOF values of x: into u (concatenated DOF
 // vector) or, per problem, into u_ptrs.
 int solve_common(cb_ctx* c, double* u_dev, double* const* u_ptrs_dev, double rtol, int32_t max_iter) {
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair ev01{&e0, &e1};
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
@@ -1420,8 +1434,6 @@ int solve_common(cb_ctx* c, double* u_dev, double* const* u_ptrs_dev, double rto
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   c->info.t_solve_ms = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return CB_OK;
 }
 
@@ -1745,7 +1757,8 @@ int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms) {
                                         c->zbuf.as<double>(), c->cloc.as<double>());
     }
   };
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair ev01{&e0, &e1};
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   launch();   // warm
@@ -1756,8 +1769,6 @@ int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms) {
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   *avg_ms = (double)ms / reps;
   return CB_OK;
 }

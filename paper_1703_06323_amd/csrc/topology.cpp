@@ -69,7 +69,11 @@ struct UnionFind {
 };
 
 // Fixed pool of worker threads for the data-parallel loops of the indexing
-// (created once per process; at most 16 workers).
+// (created once per process; at most 16 workers).  Each run has a
+// generation number; tasks are claimed and counted under the mutex, and only
+// while the claimer's generation is the current one, so every task of a run
+// is executed exactly once and the completion count of a run ends at its
+// task count.
 class Pool {
  public:
   static Pool& get() {
@@ -83,16 +87,19 @@ class Pool {
       for (int t = 0; t < ntasks; ++t) f(t);
       return;
     }
-    std::unique_lock<std::mutex> lk(mu_);
-    job_ = &f;
-    ntasks_ = ntasks;
-    next_.store(0);
-    done_ = 0;
-    ++gen_;
-    lk.unlock();
+    std::lock_guard<std::mutex> one_run(run_mu_);
+    uint64_t g;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &f;
+      ntasks_ = ntasks;
+      next_ = 0;
+      done_ = 0;
+      g = ++gen_;
+    }
     cv_.notify_all();
-    work();
-    lk.lock();
+    work(g);
+    std::unique_lock<std::mutex> lk(mu_);
     done_cv_.wait(lk, [&] { return done_ == ntasks_; });
     job_ = nullptr;
   }
@@ -104,31 +111,34 @@ class Pool {
     for (int i = 0; i < n; ++i) workers_.emplace_back([this] { loop(); });
     for (auto& w : workers_) w.detach();
   }
-  void work() {
-    for (;;) {
-      int t = next_.fetch_add(1);
-      if (t >= ntasks_) break;
-      (*job_)(t);
-      std::lock_guard<std::mutex> g(mu_);
+  void work(uint64_t g) {
+    std::unique_lock<std::mutex> lk(mu_);
+    while (gen_ == g && next_ < ntasks_) {
+      const int t = next_++;
+      const std::function<void(int)>* job = job_;
+      lk.unlock();
+      (*job)(t);
+      lk.lock();
       if (++done_ == ntasks_) done_cv_.notify_all();
     }
   }
   void loop() {
     uint64_t seen = 0;
     for (;;) {
-      std::unique_lock<std::mutex> lk(mu_);
-      cv_.wait(lk, [&] { return gen_ != seen && job_ != nullptr; });
-      seen = gen_;
-      lk.unlock();
-      work();
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+      }
+      work(seen);
     }
   }
   std::vector<std::thread> workers_;
-  std::mutex mu_;
+  std::mutex run_mu_;   // one run at a time
+  std::mutex mu_;       // guards everything below
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)>* job_ = nullptr;
-  int ntasks_ = 0, done_ = 0;
-  std::atomic<int> next_{0};
+  int ntasks_ = 0, next_ = 0, done_ = 0;
   uint64_t gen_ = 0;
 };
 

@@ -36,14 +36,7 @@ def _cases():
 
 CASES = _cases()
 
-# One GPU run stopped inside this case (no output for 180 s, killed; the GPU
-# kept answering).  Reading the setup, export and host-indexing code showed
-# no cause, so the case stays off the GPU.
-_OFF_GPU = {"r3_n16_s4_b36_v0_o1": "hung once on the GPU with no cause found in the code; kept off the GPU"}
-
-
-@pytest.mark.parametrize("name", [pytest.param(n, marks=pytest.mark.skip(reason=_OFF_GPU[n])) if n in _OFF_GPU
-                                  else n for n in CASES])
+@pytest.mark.parametrize("name", list(CASES))
 def test_device_indexing_matches_host(name):
     from paper_1703_06323_amd import Solver
     from paper_1703_06323_amd.cutbddc import CBError, CB_ERR_SINGULAR, host_indexing

@@ -119,6 +119,25 @@ def test_coarse_matrix(name):
     assert rel(Ac, o.M.Ac) < 1e-10
 
 
+def test_coarse_matrix_global_rows(monkeypatch):
+    """The coarse assembly builds rows longer than its LDS limit in place in
+    global memory: forcing that path must give the same matrix bit for bit
+    (same sums in the same order) and the same solve."""
+    from paper_1703_06323_amd import Solver
+    name = "balls32_s8_ce"
+    ref = gpu(name).export_coarse()
+    monkeypatch.setenv("CUTBDDC_COARSE_ROW_LDS", "1")
+    say(f"[gpu] setup+factor {name} with global coarse rows")
+    s = Solver(CASES[name]())
+    s.factor()
+    assert np.array_equal(s.export_coarse(), ref)
+    p = CASES[name]()
+    u, it, relres = s.solve(p.f, rtol=1e-8)
+    u0, it0, _ = gpu(name).solve(p.f, rtol=1e-8)
+    assert it == it0 and np.array_equal(u.cpu().numpy(), u0.cpu().numpy())
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_preconditioner_apply(name):
     o = oracle(name)

@@ -52,3 +52,34 @@ def test_host_indexing_rejects_floating_pocket():
     with pytest.raises(CBError) as e:
         host_indexing(p, d.count)
     assert e.value.code == CB_ERR_SINGULAR
+
+
+_REPEAT = r"""
+import sys
+sys.path[:0] = [{root!r}, {tests!r}]
+import numpy as np
+import workloads as W
+from oracle import assemble
+from paper_1703_06323_amd.cutbddc import host_indexing
+cases = []
+for k, (n, s, nb) in enumerate([(12, 4, 28), (8, 4, 25), (8, 2, 38)]):
+    p = W.random_balls(n, s, nb, 102 + k)
+    cases.append((p, assemble.discretise(p, check_floating=False).count, None))
+cases = [(p, c, host_indexing(p, c)["dof_node"]) for p, c, _ in cases]
+for it in range({reps}):
+    for p, c, ref in cases:
+        assert np.array_equal(host_indexing(p, c)["dof_node"], ref)
+print("ok", flush=True)
+"""
+
+
+def test_host_indexing_many_calls_finish():
+    """Back-to-back calls reuse the indexing's worker pool thousands of times;
+    a task claimed twice around the start of a run used to leave the caller
+    waiting for ever.  Run in a child process under a time limit."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = _REPEAT.format(root=root, tests=os.path.join(root, "tests"), reps=2500)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
