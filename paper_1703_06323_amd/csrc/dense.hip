@@ -85,7 +85,10 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   typedef typename Vec16<T>::type V;
   constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int KT = KB / (int)sizeof(T);       // k per stage
-  constexpr int LDK = KT + VW;                  // LDS row length (padded)
+  constexpr int LDK = KT;                       // LDS row length
+  constexpr int CPR = KT / VW;                  // 16-byte chunks per [row][k] row
+  constexpr int SWM = CPR >= 16 ? 15 : 7;       // swizzle mask
+  static_assert(CPR >= 8 && (CPR & (CPR - 1)) == 0, "stage width");
   constexpr int WGN = BN / 32;                  // waves along N
   constexpr int NT = 64 * (BM / 32) * WGN;      // threads
   constexpr int WM = 32, WN = 32;               // per-wave outputs
@@ -97,10 +100,15 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   // as [row][k] and is read 16 bytes at a time; the other kind (TA = 1,
   // TB = 0) sits as [k][row], so that its 16-byte global vectors go to LDS
   // unchanged (a [row][k] store would scatter them over rows and collide
-  // in the banks), and is read one element per MFMA operand.  FP32 [k][row]
-  // rows are padded by 4 so that the k rows 4 apart read by lane groups in
-  // one LDS cycle fall in different banks.
-  constexpr int PK = sizeof(T) == 4 ? 4 : 0;
+  // in the banks), and is read one element per MFMA operand.
+  // [row][k] rows are unpadded and the 16-byte chunk c of row r is kept at
+  // chunk c ^ g(r), g(r) = (r ^ (r >> 1)) & SWM (a Gray code): the 16 rows
+  // read by a wave at one k, and the rows stored by consecutive lanes, then
+  // spread over distinct bank groups both for 8 lanes per LDS cycle over 32
+  // banks and for 16 lanes over 64 banks.  [k][row] rows are padded by 4
+  // elements so that the k rows 4 apart read by lane groups in one LDS
+  // cycle fall in different banks.
+  constexpr int PK = 4;
   constexpr int AR = TA == 0 ? BM : KT, AC = TA == 0 ? LDK : BM + PK;
   constexpr int BR = TB == 1 ? BN : KT, BC = TB == 1 ? LDK : BN + PK;
   __shared__ __align__(16) T As[2][AR][AC];
@@ -134,6 +142,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   const int wr = wv / WGN, wc = wv % WGN;
 
   V ra[AV], rb[BV], ra2[AV], rb2[BV];
+  // element offset within a [row][k] LDS row of the chunk holding k (k a
+  // multiple of VW)
+  auto sw = [](int r, int k) { return ((k / VW) ^ ((r ^ (r >> 1)) & SWM)) * VW; };
   // tile coordinates (row or column index, k) of the first element of
   // vector q of this thread
   auto a_coord = [&](int q, int& i, int& k) {
@@ -209,14 +220,14 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
     for (int q = 0; q < AV; ++q) {
       int i, k;
       a_coord(q, i, k);
-      if constexpr (TA == 0) *reinterpret_cast<V*>(&As[buf][i][k]) = ra[q];
+      if constexpr (TA == 0) *reinterpret_cast<V*>(&As[buf][i][sw(i, k)]) = ra[q];
       else *reinterpret_cast<V*>(&As[buf][k][i]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < BV; ++q) {
       int j, k;
       b_coord(q, j, k);
-      if constexpr (TB == 1) *reinterpret_cast<V*>(&Bs[buf][j][k]) = rb[q];
+      if constexpr (TB == 1) *reinterpret_cast<V*>(&Bs[buf][j][sw(j, k)]) = rb[q];
       else *reinterpret_cast<V*>(&Bs[buf][k][j]) = rb[q];
     }
   };
@@ -227,6 +238,26 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
 
+  // Old C values: loaded just before the last K stage is multiplied (the
+  // stage-staging registers are free by then), so that their latency hides
+  // behind that stage.  Only this workgroup writes its C tile, and only
+  // after the loop, so the values are those of the call's start even when C
+  // aliases A or B.
+  T cold[FM][FN][4];
+  auto load_c = [&]() {
+#pragma unroll
+    for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = row0 + wr * WM + mi * 16 + Acc<T>::row(lane, v);
+          const int gj = col0 + wc * WN + ni * 16 + (lane & 15);
+          const bool ok = gi < M && gj < N && !((mode & GEMM_LOWER) && gj > gi);
+          cold[mi][ni][v] = (ok && beta != T(0)) ? C[(int64_t)gi * ldc + gj] : T(0);
+        }
+  };
+
   const int ks = 4 * (lane >> 4);
   auto compute = [&](int buf) {
 #pragma unroll
@@ -236,10 +267,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
       for (int mi = 0; mi < FM; ++mi) {
         const int i = wr * WM + mi * 16 + (lane & 15);
         if constexpr (TA == 0) {
-          const T* src = &As[buf][i][kb + ks];
 #pragma unroll
           for (int h = 0; h < 4; h += VW) {
-            const V x = *reinterpret_cast<const V*>(src + h);
+            const V x = *reinterpret_cast<const V*>(&As[buf][i][sw(i, kb + ks + h)]);
 #pragma unroll
             for (int c = 0; c < VW; ++c) av[mi][h + c] = x[c];
           }
@@ -252,10 +282,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
       for (int ni = 0; ni < FN; ++ni) {
         const int j = wc * WN + ni * 16 + (lane & 15);
         if constexpr (TB == 1) {
-          const T* src = &Bs[buf][j][kb + ks];
 #pragma unroll
           for (int h = 0; h < 4; h += VW) {
-            const V x = *reinterpret_cast<const V*>(src + h);
+            const V x = *reinterpret_cast<const V*>(&Bs[buf][j][sw(j, kb + ks + h)]);
 #pragma unroll
             for (int c = 0; c < VW; ++c) bv[ni][h + c] = x[c];
           }
@@ -279,14 +308,16 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
       store(0, ra, rb);
     }
     __syncthreads();
-    for (int k0 = kbeg; k0 < kend; k0 += KT) {
-      const bool more = k0 + KT < kend;
-      if (more) load(k0 + KT, ra, rb);
+    int k0 = kbeg;
+    for (; k0 + KT < kend; k0 += KT) {
+      load(k0 + KT, ra, rb);
       compute(buf);
-      if (more) store(buf ^ 1, ra, rb);
+      store(buf ^ 1, ra, rb);
       __syncthreads();
       buf ^= 1;
     }
+    load_c();
+    if (k0 < kend) compute(buf);   // last stage (no LDS writes follow)
   } else {
     // two stages in flight: the registers of stage s+2 are loaded while
     // stage s is multiplied and stage s+1 waits in the other register set
@@ -307,22 +338,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
       if (k0 + 2 * KT < kend) store(0, ra, rb);
       __syncthreads();
     }
+    load_c();
   }
-  // Epilogue: every C value is loaded before the first store (C may alias
-  // A or B, so loads interleaved with stores would each wait for the one
-  // before); the arithmetic per element is unchanged.
-  T cold[FM][FN][4];
-#pragma unroll
-  for (int mi = 0; mi < FM; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < FN; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = row0 + wr * WM + mi * 16 + Acc<T>::row(lane, v);
-        const int gj = col0 + wc * WN + ni * 16 + (lane & 15);
-        const bool ok = gi < M && gj < N && !((mode & GEMM_LOWER) && gj > gi);
-        cold[mi][ni][v] = (ok && beta != T(0)) ? C[(int64_t)gi * ldc + gj] : T(0);
-      }
+  // Epilogue
 #pragma unroll
   for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
