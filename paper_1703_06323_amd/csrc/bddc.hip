@@ -473,27 +473,40 @@ __global__ __launch_bounds__(256) void pack_lower_kernel(const TI* __restrict__ 
 // (P_IJ^T x_I) to colp, through a butterfly transpose-reduce within each
 // 32-lane half.  The partials are summed per row in a fixed order, so the
 // result does not depend on the wave schedule.
-template <typename TM>
-__device__ inline void symv_packed(const TM* __restrict__ Pk, int nbu, const double* xs, double* rowp, double* colp,
-                                   double* ys) {
+// gather() fills xs (with a barrier after it); it runs after the first
+// operator block of every wave has been requested, so that the two overlap.
+template <typename TM, typename Gather>
+__device__ inline void symv_packed(const TM* __restrict__ Pk, int nbu, Gather&& gather, const double* xs,
+                                   double* rowp, double* colp, double* ys) {
   typedef typename std::conditional<sizeof(TM) == 4, float __attribute__((ext_vector_type(4))),
                                     double __attribute__((ext_vector_type(2)))>::type V;
   constexpr int VW = 16 / sizeof(TM), NV = 16 / VW;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int nq = nbu * (nbu + 1) / 2;
+  // the next block of this wave is loaded before the current one is
+  // reduced, so that the wave keeps a block's loads in flight throughout
+  V nxt[NV];
+  auto fetch = [&](int q) {
+    const V* src = reinterpret_cast<const V*>(Pk + (int64_t)q * SB * SB) + lane;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) nxt[k] = src[k * 64];
+  };
+  if (wv < nq) fetch(wv);
+  gather();
+  __syncthreads();
   int I = 0;
   for (int q = wv; q < nq; q += nw) {
     while ((I + 1) * (I + 2) / 2 <= q) ++I;
     const int J = q - I * (I + 1) / 2;
-    const V* src = reinterpret_cast<const V*>(Pk + (int64_t)q * SB * SB) + lane;
     double v[16];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const V x = src[k * 64];
+      const V x = nxt[k];
 #pragma unroll
       for (int e = 0; e < VW; ++e) v[k * VW + e] = (double)x[e];
     }
+    if (q + nw < nq) fetch(q + nw);
     const double* xj = xs + SB * J + 16 * h;
     double rs = 0.0;
 #pragma unroll
@@ -570,16 +583,17 @@ __global__ __launch_bounds__(APPLY_T) void apply_interior_kernel(SubDev sd, cons
   double* rowp = ys + NIp;          // [nbk * SB]
   double* colp = rowp + nbk * SB;   // [nbk * SB]
   const int64_t* idx = sd.I_idx + (int64_t)w * NIp;
-  for (int j = threadIdx.x; j < NIp; j += blockDim.x) {
-    double v = 0.0;
-    if (j < nI) {
-      const int64_t n = idx[j];
-      v = a[n] - (b ? b[n] : 0.0);
+  auto gather = [&]() {
+    for (int j = threadIdx.x; j < NIp; j += blockDim.x) {
+      double v = 0.0;
+      if (j < nI) {
+        const int64_t n = idx[j];
+        v = a[n] - (b ? b[n] : 0.0);
+      }
+      xs[j] = v;
     }
-    xs[j] = v;
-  }
-  __syncthreads();
-  symv_packed<TM>(P + (int64_t)w * nbk * SB * SB, nbu, xs, rowp, colp, ys);
+  };
+  symv_packed<TM>(P + (int64_t)w * nbk * SB * SB, nbu, gather, xs, rowp, colp, ys);
   for (int j = threadIdx.x; j < nI; j += blockDim.x) out[idx[j]] = ys[j];
 }
 
@@ -603,26 +617,39 @@ __global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const
   double* rowp = ys + NGp;          // [nbk * SB]
   double* colp = rowp + nbk * SB;   // [nbk * SB]
   const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
-  for (int j = threadIdx.x; j < NGp; j += blockDim.x) {
-    double v = 0.0;
-    if (j < nG) {
-      const int64_t n = idx[j];
-      v = Dw[(int64_t)w * NGp + j] * (r[n] - t[n]);
+  auto gather = [&]() {
+    for (int j = threadIdx.x; j < NGp; j += blockDim.x) {
+      double v = 0.0;
+      if (j < nG) {
+        const int64_t n = idx[j];
+        v = Dw[(int64_t)w * NGp + j] * (r[n] - t[n]);
+      }
+      gs[j] = v;
     }
-    gs[j] = v;
-  }
-  __syncthreads();
-  symv_packed<TM>(Kt + (int64_t)w * nbk * SB * SB, nbu, gs, rowp, colp, ys);
+  };
+  symv_packed<TM>(Kt + (int64_t)w * nbk * SB * SB, nbu, gather, gs, rowp, colp, ys);
   for (int j = threadIdx.x; j < NGp; j += blockDim.x) z[(int64_t)w * NGp + j] = j < nG ? ys[j] : 0.0;
-  // coarse right-hand side: one wave per coarse row
+  // coarse right-hand side cloc_w = Phi_w^T g_w: thread t takes column
+  // u = t % nu of the rows j = t / nu + G k (G = blockDim / nu row groups),
+  // so that consecutive threads read consecutive entries of a row; the G
+  // partial sums of a column are added in a fixed order
+  double* part = colp + nbk * SB;   // [blockDim]
   const double* ph = Phi + (int64_t)w * NGp * NCp;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int u = wv; u < NCp; u += blockDim.x >> 6) {
+  const int tid = threadIdx.x;
+  for (int u0 = 0; u0 < NCp; u0 += blockDim.x) {
+    const int nu = min(NCp - u0, (int)blockDim.x), G = blockDim.x / nu;
+    const int u = u0 + tid % nu, gq = tid / nu;
     double acc = 0.0;
-    if (u < nC)
-      for (int j = lane; j < nG; j += 64) acc += ph[(int64_t)j * NCp + u] * gs[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) cloc[(int64_t)w * NCp + u] = acc;
+    if (gq < G && u < nC)
+      for (int j = gq; j < nG; j += G) acc += ph[(int64_t)j * NCp + u] * gs[j];
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < nu) {
+      double sum = 0.0;
+      for (int q = 0; q < G; ++q) sum += part[q * nu + tid];
+      cloc[(int64_t)w * NCp + u0 + tid] = sum;
+    }
+    __syncthreads();
   }
 }
 
@@ -830,7 +857,7 @@ template void launch_apply_interior<float>(hipStream_t, const SubDev&, int, cons
 template <typename TM>
 void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc) {
-  const size_t sh = (size_t)(2 * sd.NGp + 2 * packed_blocks(sd.NGp) * SB) * sizeof(double);
+  const size_t sh = (size_t)(2 * sd.NGp + 2 * packed_blocks(sd.NGp) * SB + APPLY_T) * sizeof(double);
   static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
