@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # apply_interior_cut_cube_64_traffic.md), each scaled by the same counter on
 # a copy of known size (FETCH x 2.0, WRITE x 1.0).  Valid for the packed
 # symmetric apply kernel as it stands; set to None when that kernel changes.
-APPLY_INTERIOR_TRAFFIC_BYTES = 277.9e6
+APPLY_INTERIOR_TRAFFIC_BYTES = 277.4e6
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix
 
