@@ -18,6 +18,7 @@
 //   Kt  = K_S^{-1} - Phi G^T                  (constrained Neumann solve on the interface)
 //   A_c^omega = Phi^T S_A Phi = S_c^{-1} - R  (local coarse matrix)
 #include "bddc.h"
+#include "dense.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -210,8 +211,13 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev s
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // Only the columns up to the end of the row's diagonal block of the
+    // blocked Cholesky (blocks of DB rows from 0 to NIp, then from NIp) are
+    // stored: the factorisation reads the lower triangle and whole diagonal
+    // blocks, never the rest of the upper triangle.
+    const int cend = r < NIp ? min(NIp, (r / DB + 1) * DB) : min(nt, NIp + ((r - NIp) / DB + 1) * DB);
     T* Kr = K + (int64_t)r * nt;
-    for (int c = lane * VW; c < nt; c += 64 * VW) *reinterpret_cast<V*>(Kr + c) = *reinterpret_cast<const V*>(rb + c);
+    for (int c = lane * VW; c < cend; c += 64 * VW) *reinterpret_cast<V*>(Kr + c) = *reinterpret_cast<const V*>(rb + c);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
