@@ -267,11 +267,14 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, const doubl
   double* y = Y + (int64_t)w * nt * NCp;
   for (int e = tid; e < R * NCp; e += 256) {
     const int rr = e / NCp, t = e - rr * NCp;
+    // An empty slot holds the value 0 (and column -1): its load goes to
+    // column 0 and adds 0, so all 27 loads issue together, unconditionally.
+    double xv[STENCIL];
+#pragma unroll
+    for (int k = 0; k < STENCIL; ++k) xv[k] = x[(int64_t)max(scol[rr * STENCIL + k], 0) * NCp + t];
     double acc = 0.0;
-    for (int k = 0; k < STENCIL; ++k) {
-      const int col = scol[rr * STENCIL + k];
-      if (col >= 0) acc += sval[rr * STENCIL + k] * x[(int64_t)col * NCp + t];
-    }
+#pragma unroll
+    for (int k = 0; k < STENCIL; ++k) acc += sval[rr * STENCIL + k] * xv[k];
     y[(int64_t)(rb + rr) * NCp + t] = acc;
   }
 }
