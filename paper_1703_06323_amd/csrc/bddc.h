@@ -19,6 +19,10 @@ struct SubDev {
   const int32_t* sub_prob;        // [ns] problem of each subdomain
   const int32_t* sub_blk;         // [ns] subdomain index within its problem
   const int32_t* active;          // [P] problems whose PCG still runs, or null
+  // Interface slots of each local object, grouped by object (see
+  // launch_object_lists), or null: kernels that need them then build them.
+  const int32_t* optr;            // [ns*(NCp+1)] start of object t's members
+  const int32_t* omem;            // [ns*NGp] member slots, ascending per object
 };
 
 // Grid data of all problems (concatenated cell arrays).
@@ -31,6 +35,10 @@ struct GridDev {
 };
 
 void bddc_set_reference(const double* Kref);
+
+// optr/omem of every subdomain (sizes as in SubDev), built once so that the
+// assembly and the constraint kernels need not scan the interface for them.
+void launch_object_lists(hipStream_t st, const SubDev& sd, int ns, int32_t* optr, int32_t* omem);
 
 // Stencil rows of A_omega kept for the Gram-matrix products: for row r of
 // subdomain w, slot k (neighbour offset (k%3-1, k/3%3-1, k/9-1)) holds the

@@ -32,6 +32,7 @@ namespace {
 __constant__ double c_Kref_b[64];
 
 __device__ inline void object_members(const SubDev& sd, int w, int* ptr, int* mem);
+__device__ inline void object_members_get(const SubDev& sd, int w, int* ptr, int* mem);
 
 // The s^3 cells of block (Bx, By, Bz) into LDS: cell info and kappa h (0 on
 // inactive cells), indexed cx + s (cy + s cz).  Caller synchronises.
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev s
     diag[r] = d;
     if (r >= NIp) diagA_G[(int64_t)w * NGp + (r - NIp)] = d;
   }
-  object_members(sd, w, optr, omem);   // ends with a barrier
+  object_members_get(sd, w, optr, omem);   // ends with a barrier
   // phase 1: rho_t / |t|^2 with rho_t the sum of the diagonal over object t
   for (int t = tid; t < NCp; t += 64 * ASM_WAVES) {
     double sr = 0.0;
@@ -306,6 +307,33 @@ __device__ inline void object_members(const SubDev& sd, int w, int* ptr, int* me
   __syncthreads();
 }
 
+// The same lists from sd.optr / sd.omem when they have been built.
+__device__ inline void object_members_get(const SubDev& sd, int w, int* ptr, int* mem) {
+  if (!sd.optr) {
+    object_members(sd, w, ptr, mem);
+    return;
+  }
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  for (int t = threadIdx.x; t <= NCp; t += blockDim.x) ptr[t] = sd.optr[(int64_t)w * (NCp + 1) + t];
+  for (int j = threadIdx.x; j < NGp; j += blockDim.x) mem[j] = sd.omem[(int64_t)w * NGp + j];
+  __syncthreads();
+}
+
+// One workgroup per subdomain: its object lists to optr / omem (member
+// slots beyond the last object's are -1).
+__global__ __launch_bounds__(256) void object_lists_kernel(SubDev sd, int32_t* __restrict__ optr,
+                                                           int32_t* __restrict__ omem) {
+  extern __shared__ int smem_i[];
+  const int w = blockIdx.x;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  int* ptr = smem_i;
+  int* mem = smem_i + NCp + 1;
+  object_members(sd, w, ptr, mem);
+  const int used = ptr[NCp];
+  for (int t = threadIdx.x; t <= NCp; t += blockDim.x) optr[(int64_t)w * (NCp + 1) + t] = ptr[t];
+  for (int j = threadIdx.x; j < NGp; j += blockDim.x) omem[(int64_t)w * NGp + j] = j < used ? mem[j] : -1;
+}
+
 // Kernel 3c: Gt = (K_S^{-1} C^T)^T without forming C: since K_S^{-1} is
 // symmetric, row t of Gt is the mean of the rows of K_S^{-1} over the slots
 // of object t, so every row of K_S^{-1} is read once and coalesced.  One
@@ -319,7 +347,7 @@ __global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const d
   const int NGp = sd.NGp, NCp = sd.NCp;
   int* ptr = smem_i;
   int* mem = smem_i + NCp + 1;
-  object_members(sd, w, ptr, mem);
+  object_members_get(sd, w, ptr, mem);
   const double* ks = KS + (int64_t)w * NGp * NGp;
   double* gt = Gt + (int64_t)w * NCp * NGp;
   const int i = blockIdx.x * CC_COLS + threadIdx.x;
@@ -341,7 +369,7 @@ __global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const d
   const int NGp = sd.NGp, NCp = sd.NCp;
   int* ptr = smem_i;
   int* mem = smem_i + NCp + 1;
-  object_members(sd, w, ptr, mem);
+  object_members_get(sd, w, ptr, mem);
   const double* gt = Gt + (int64_t)w * NCp * NGp;
   double* sc = Sc + (int64_t)w * NCp * NCp;
   for (int e = threadIdx.x; e < NCp * NCp; e += 256) {
@@ -781,6 +809,12 @@ void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, cons
   if (n_iface <= 0) return;
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)((n_iface + 255) / 256)), dim3(256), 0, st, n_iface,
                      if_ptr, if_sub, if_slot, NGp, diagA_G, stiffness, Dw);
+}
+
+void launch_object_lists(hipStream_t st, const SubDev& sd, int ns, int32_t* optr, int32_t* omem) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL(object_lists_kernel, dim3(ns), dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st, sd,
+                     optr, omem);
 }
 
 void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* st_val, const int32_t* st_col,

@@ -289,6 +289,7 @@ struct cb_ctx {
       cs_row;
   // factor results
   DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
+  DevBuf optr_d, omem_d;   // object member lists per subdomain (built at factorisation)
   // work vectors and PCG state
   DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, tcvec, ucvec, partial, scal, bgrid;
   DevBuf pq_part, rr_part;   // per node block (SEG_ALIGN nodes): parts of p.q and r.r
@@ -370,6 +371,8 @@ struct cb_ctx {
     d.sub_prob = sub_prob_d.as<int32_t>() + w0;
     d.sub_blk = sub_blk_d.as<int32_t>() + w0;
     d.active = masked ? active.as<int32_t>() : nullptr;
+    d.optr = optr_d.p ? optr_d.as<int32_t>() + (int64_t)w0 * (NCp + 1) : nullptr;
+    d.omem = omem_d.p ? omem_d.as<int32_t>() + (int64_t)w0 * NGp : nullptr;
     return d;
   }
 };
@@ -1099,6 +1102,13 @@ int factor_impl(cb_ctx* c) {
   HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
   DevBuf AcLoc;
   CHK(dalloc(AcLoc, (size_t)ns * sC * sizeof(double)));
+  // object member lists, once for all subdomains (sub() hands them out below)
+  c->optr_d.release();
+  c->omem_d.release();
+  CHK(dalloc(c->optr_d, (size_t)ns * (NCp + 1) * sizeof(int32_t)));
+  CHK(dalloc(c->omem_d, (size_t)ns * NGp * sizeof(int32_t)));
+  launch_object_lists(st, c->sub(0), ns, c->optr_d.as<int32_t>(), c->omem_d.as<int32_t>());
+  HIPCHK(hipGetLastError());
 
   // work buffers for a chunk of subdomains
   const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
