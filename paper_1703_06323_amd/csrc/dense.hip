@@ -798,6 +798,16 @@ __global__ __launch_bounds__(256) void eye_kernel(T* Y, int64_t ldy, int64_t sY,
   for (int c = threadIdx.x; c < nb; c += 256) y[c] = c == r ? T(1) : T(0);
 }
 
+// Y[r][c] = L[r][c] for r, c < h (one row per block; batch along y).
+template <typename T>
+__global__ __launch_bounds__(256) void copy_block_kernel(const T* __restrict__ L, int64_t ldl, int64_t sL, T* Y,
+                                                          int64_t ldy, int64_t sY, int h) {
+  const int r = blockIdx.x;
+  const T* l = L + (int64_t)blockIdx.y * sL + (int64_t)r * ldl;
+  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)r * ldy;
+  for (int c = threadIdx.x; c < h; c += 256) y[c] = l[c];
+}
+
 // out (full symmetric, row-major nb x nb) = D * sym(lower(in)) * D
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void symmetrize_scale_kernel(const T* in, int64_t ldi, int64_t sI,
@@ -1116,11 +1126,15 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
   const int send = S0 + h;
   const int blk = diag_block_index(off + S0, split);
   const T* li = Linv + (int64_t)blk * DB * DB;
-  // Y[S, 0:send] = inv(L_SS) R_S[:, 0:send]; R_S[:, S] is still the identity,
-  // so this also sets Y[S, S] = inv(L_SS).  In place: a single tile row
-  // reads only its own columns of R_S before writing them.
-  gemm<T>(st, 0, 0, h, send, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
-          sY, batch, 0);
+  // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0] (in place: a single tile row reads
+  // only its own columns of R_S before writing them).  R_S[:, S] is still the
+  // identity, so Y[S, S] = inv(L_SS) is a copy (the product would give the
+  // same values exactly).
+  if (S0 > 0)
+    gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
+            sY, batch, 0);
+  hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, li, DB, sLi,
+                     Y + (int64_t)S0 * ldy + S0, ldy, sY, h);
   const int rest = nb - send;
   if (rest > 0) {
     const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
