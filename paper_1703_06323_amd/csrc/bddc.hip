@@ -654,6 +654,8 @@ __global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const
   double* rowp = ys + NGp;          // [nbk * SB]
   double* colp = rowp + nbk * SB;   // [nbk * SB]
   const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
+  // the coarse restriction needs only g_w: it is formed right after the
+  // gather, while the first operator blocks are in flight
   auto gather = [&]() {
     for (int j = threadIdx.x; j < NGp; j += blockDim.x) {
       double v = 0.0;
@@ -663,31 +665,32 @@ __global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const
       }
       gs[j] = v;
     }
+    __syncthreads();
+    // coarse right-hand side cloc_w = Phi_w^T g_w: thread t takes column
+    // u = t % nu of the rows j = t / nu + G k (G = blockDim / nu row groups),
+    // so that consecutive threads read consecutive entries of a row; the G
+    // partial sums of a column are added in a fixed order
+    double* part = colp + nbk * SB;   // [blockDim]
+    const double* ph = Phi + (int64_t)w * NGp * NCp;
+    const int tid = threadIdx.x;
+    for (int u0 = 0; u0 < NCp; u0 += blockDim.x) {
+      const int nu = min(NCp - u0, (int)blockDim.x), G = blockDim.x / nu;
+      const int u = u0 + tid % nu, gq = tid / nu;
+      double acc = 0.0;
+      if (gq < G && u < nC)
+        for (int j = gq; j < nG; j += G) acc += ph[(int64_t)j * NCp + u] * gs[j];
+      part[tid] = acc;
+      __syncthreads();
+      if (tid < nu) {
+        double sum = 0.0;
+        for (int q = 0; q < G; ++q) sum += part[q * nu + tid];
+        cloc[(int64_t)w * NCp + u0 + tid] = sum;
+      }
+      __syncthreads();
+    }
   };
   symv_packed<TM>(Kt + (int64_t)w * nbk * SB * SB, nbu, gather, gs, rowp, colp, ys);
   for (int j = threadIdx.x; j < NGp; j += blockDim.x) z[(int64_t)w * NGp + j] = j < nG ? ys[j] : 0.0;
-  // coarse right-hand side cloc_w = Phi_w^T g_w: thread t takes column
-  // u = t % nu of the rows j = t / nu + G k (G = blockDim / nu row groups),
-  // so that consecutive threads read consecutive entries of a row; the G
-  // partial sums of a column are added in a fixed order
-  double* part = colp + nbk * SB;   // [blockDim]
-  const double* ph = Phi + (int64_t)w * NGp * NCp;
-  const int tid = threadIdx.x;
-  for (int u0 = 0; u0 < NCp; u0 += blockDim.x) {
-    const int nu = min(NCp - u0, (int)blockDim.x), G = blockDim.x / nu;
-    const int u = u0 + tid % nu, gq = tid / nu;
-    double acc = 0.0;
-    if (gq < G && u < nC)
-      for (int j = gq; j < nG; j += G) acc += ph[(int64_t)j * NCp + u] * gs[j];
-    part[tid] = acc;
-    __syncthreads();
-    if (tid < nu) {
-      double sum = 0.0;
-      for (int q = 0; q < G; ++q) sum += part[q * nu + tid];
-      cloc[(int64_t)w * NCp + u0 + tid] = sum;
-    }
-    __syncthreads();
-  }
 }
 
 __global__ void coarse_rhs_kernel(int nc, const int64_t* __restrict__ cs_ptr, const int32_t* __restrict__ cs_sub,
