@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void integrate_cut_kernel(BatchDev bd, const d
                                                             int64_t n_cut, double* __restrict__ Kc,
                                                             double* __restrict__ Mc) {
   __shared__ double xi[8];
-  __shared__ unsigned char keep[CELLS_PER_BLOCK][512];
+  __shared__ __align__(8) unsigned char keep[CELLS_PER_BLOCK][512];
   if (threadIdx.x < 8) xi[threadIdx.x] = xi_g[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
@@ -149,18 +149,36 @@ __global__ __launch_bounds__(256) void integrate_cut_kernel(BatchDev bd, const d
   const int b = a + rem;
   const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
   const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+  // Tensor-product form: with X_i = f_a(x_i) f_b(x_i) (f = p or 1 - p by the
+  // corner's bit), Y_j, Z_k alike and g = +-1 the product of the two
+  // derivative signs per axis, the stiffness term at point (i, j, k) is
+  // gx Y_j Z_k + X_i (gy Z_k + gz Y_j) and the mass term X_i Y_j Z_k.
+  double X[8], Y[8], Z[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double p = xi[i], m = 1.0 - p;
+    X[i] = (ax ? p : m) * (bx ? p : m);
+    Y[i] = (ay ? p : m) * (by ? p : m);
+    Z[i] = (az ? p : m) * (bz ? p : m);
+  }
+  const double gx = ax == bx ? 1.0 : -1.0, gy = ay == by ? 1.0 : -1.0, gz = az == bz ? 1.0 : -1.0;
+  const uint64_t* kb = reinterpret_cast<const uint64_t*>(keep[wv]);
   double ks = 0.0, ms = 0.0;
-  for (int q = 0; q < 512; ++q) {
-    if (!keep[wv][q]) continue;
-    const double px = xi[q & 7], py = xi[(q >> 3) & 7], pz = xi[q >> 6];
-    const double fax = ax ? px : 1.0 - px, fay = ay ? py : 1.0 - py, faz = az ? pz : 1.0 - pz;
-    const double fbx = bx ? px : 1.0 - px, fby = by ? py : 1.0 - py, fbz = bz ? pz : 1.0 - pz;
-    const double gax = ax ? 1.0 : -1.0, gay = ay ? 1.0 : -1.0, gaz = az ? 1.0 : -1.0;
-    const double gbx = bx ? 1.0 : -1.0, gby = by ? 1.0 : -1.0, gbz = bz ? 1.0 : -1.0;
-    const double dxa = gax * fay * faz, dya = fax * gay * faz, dza = fax * fay * gaz;
-    const double dxb = gbx * fby * fbz, dyb = fbx * gby * fbz, dzb = fbx * fby * gbz;
-    ks += (dxa * dxb + dya * dyb + dza * dzb);
-    ms += (fax * fay * faz) * (fbx * fby * fbz);
+  // points in ascending q = 64 k + 8 j + i; byte i of kb[8 k + j] is point q
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t mk = kb[8 * k + j];
+      if (!mk) continue;
+      const double yz = Y[j] * Z[k], w = gy * Z[k] + gz * Y[j], gyz = gx * yz;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if ((mk >> (8 * i)) & 0xffu) {
+          ks += gyz + X[i] * w;
+          ms += X[i] * yz;
+        }
+    }
   }
   Kc[idx * PACK36 + lane] = ks * (1.0 / 512.0);
   Mc[idx * PACK36 + lane] = ms * (1.0 / 512.0);
