@@ -91,8 +91,12 @@ __device__ inline int cell_kept_bits(int N, const double* __restrict__ xi, const
   return cnt;
 }
 
-// Cells of all problems in one launch: blocks of CELLS_PER_BLOCK cells lie
-// in one problem's cell segment (segments are SEG_ALIGN-aligned).
+// Cells of all problems in one launch, 64 consecutive cells per wave.
+// Each lane first tests its cell's point box against the problem's balls:
+// a box inside a ball keeps no point and a box clear of every ball keeps
+// all 512 (what cell_kept_bits returns in those cases); the remaining cells
+// get the point-by-point test of cell_kept_bits, one after another with the
+// whole wave.
 __global__ __launch_bounds__(256) void classify_kernel(BatchDev bd, int64_t n_cells_total,
                                                        const double* __restrict__ xi_g,
                                                        const double* __restrict__ balls,
@@ -101,19 +105,42 @@ __global__ __launch_bounds__(256) void classify_kernel(BatchDev bd, int64_t n_ce
   if (threadIdx.x < 8) xi[threadIdx.x] = xi_g[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t base = (int64_t)blockIdx.x * CELLS_PER_BLOCK;
-  const int64_t cell = base + (threadIdx.x / WAVE);
-  if (cell >= n_cells_total) return;
-  const int p = find_segment(bd.cell_off, bd.P, base);
-  const ProbDev pr = bd.prob[p];
-  const int64_t local = cell - pr.cell_off;
-  if (local >= (int64_t)pr.N * pr.N * pr.N) {
-    if (lane == 0) count[cell] = 0;
-    return;
+  const int64_t wbase = ((int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * WAVE;
+  const int64_t cell = wbase + lane;
+  bool detail = false;
+  if (cell < n_cells_total) {
+    const ProbDev pr = bd.prob[find_segment(bd.cell_off, bd.P, cell)];
+    const int64_t local = cell - pr.cell_off;
+    const int N = pr.N;
+    if (local >= (int64_t)N * N * N) {
+      count[cell] = 0;
+    } else {
+      const double h = 1.0 / (double)N;
+      const int64_t i = local % N, j = (local / N) % N, k = local / ((int64_t)N * N);
+      const double lo[3] = {((double)i + xi[0]) * h, ((double)j + xi[0]) * h, ((double)k + xi[0]) * h};
+      const double hi[3] = {((double)i + xi[7]) * h, ((double)j + xi[7]) * h, ((double)k + xi[7]) * h};
+      const double* bl = balls + 4 * (int64_t)pr.ball_off;
+      bool near = false, inside = false;
+      for (int b = 0; b < pr.nb && !inside; ++b) {
+        const int rel = ball_box_relation(lo, hi, bl + 4 * b);
+        inside = rel == 2;
+        near = near || rel == 1;
+      }
+      if (inside) count[cell] = 0;
+      else if (!near) count[cell] = 512;
+      else detail = true;
+    }
   }
-  unsigned bits;
-  const int cnt = cell_kept_bits(pr.N, xi, balls + 4 * (int64_t)pr.ball_off, pr.nb, local, lane, bits);
-  if (lane == 0) count[cell] = cnt;
+  unsigned long long todo = __ballot(detail);
+  while (todo) {
+    const int l = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int64_t c = wbase + l;
+    const ProbDev pr = bd.prob[find_segment(bd.cell_off, bd.P, c)];
+    unsigned bits;
+    const int cnt = cell_kept_bits(pr.N, xi, balls + 4 * (int64_t)pr.ball_off, pr.nb, c - pr.cell_off, lane, bits);
+    if (lane == 0) count[c] = cnt;
+  }
 }
 
 // cut_cells: ids in the concatenated cell space.
@@ -189,7 +216,7 @@ __global__ __launch_bounds__(256) void integrate_cut_kernel(BatchDev bd, const d
 void launch_classify(hipStream_t st, const BatchDev& b, int64_t n_cells_total, const double* xi,
                      const double* balls, int32_t* count) {
   if (n_cells_total <= 0) return;
-  const int64_t blocks = (n_cells_total + CELLS_PER_BLOCK - 1) / CELLS_PER_BLOCK;
+  const int64_t blocks = (n_cells_total + 255) / 256;   // 64 cells per wave
   hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, n_cells_total, xi, balls,
                      count);
 }
