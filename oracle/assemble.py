@@ -54,10 +54,20 @@ def keep_masks(problem, cells):
     return geometry.kept_points(problem.n, problem.centres, problem.radii, cells)
 
 
-def discretise(problem, check_floating: bool = True) -> Discretisation:
+def discretise(problem, check_floating: bool = True, count=None) -> Discretisation:
+    """Discrete problem of `problem`.  `count` (optional, int[n^3]) replaces
+    the classification by hand-made cell data for tests of the indexing
+    rules: every entry must be 0 (inactive) or 512 (whole cell kept), and the
+    problem must have no balls, so active cells integrate as whole cells."""
     n = problem.n
     h = 1.0 / n
-    status, count = geometry.classify(n, problem.centres, problem.radii)
+    if count is None:
+        status, count = geometry.classify(n, problem.centres, problem.radii)
+    else:
+        count = np.asarray(count, dtype=np.int32).reshape(-1)
+        if count.size != n ** 3 or ((count != 0) & (count != 512)).any() or problem.n_balls:
+            raise ValueError("hand-made cell data: n^3 counts of 0 or 512, no balls")
+        status = np.where(count == 512, geometry.INTERIOR, geometry.INACTIVE).astype(np.uint8)
     active = np.flatnonzero(status != geometry.INACTIVE).astype(np.int64)
     cut = np.flatnonzero(status == geometry.CUT).astype(np.int64)
     kappa = (np.ones(n ** 3) if problem.kappa is None

@@ -83,3 +83,32 @@ def test_host_indexing_many_calls_finish():
     code = _REPEAT.format(root=root, tests=os.path.join(root, "tests"), reps=2500)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
+
+
+def _hand_counts(n, inactive):
+    c = np.full(n ** 3, 512, dtype=np.int32)
+    for (i, j, k) in inactive:
+        c[i + n * (j + n * k)] = 0
+    return c
+
+
+@pytest.mark.parametrize("n,s,inactive", [
+    (8, 4, [(3, 1, k) for k in range(4)]),      # links broken on a face and on a coarse edge
+    (6, 3, [(2, 1, 1)]),                        # a face demoted to an edge
+])
+def test_host_indexing_hand_cut_partitions(n, s, inactive):
+    """The hand-made partitions whose objects are written out in
+    test_oracle_assemble_topology: the library's host indexing agrees with
+    the oracle bit for bit."""
+    from paper_1703_06323_amd.cutbddc import host_indexing
+    p = W.uncut(n, s)
+    count = _hand_counts(n, inactive)
+    d = assemble.discretise(p, count=count)
+    t = topology.build(p, d)
+    g = host_indexing(p, count)
+    assert np.array_equal(g["dof_node"], d.dof_node)
+    assert np.array_equal(g["card"], t.card())
+    assert np.array_equal(g["obj_ptr"], t.obj_ptr)
+    assert np.array_equal(g["obj_dofs"], t.obj_dofs)
+    assert np.array_equal(g["obj_type"], t.obj_type)
+    assert np.array_equal(g["coarse_of_obj"], t.coarse_of_obj)

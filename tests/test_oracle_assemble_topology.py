@@ -174,3 +174,163 @@ def test_variant1_splits_cut_edges_into_corners():
     assert found_cut
     # the split objects still partition the interface
     assert np.array_equal(np.sort(t1.obj_dofs), np.flatnonzero(t1.card() >= 2))
+
+
+# ---- hand-made cut partitions: the link and face rules of Sect. 3.2 ----------
+#
+# The objects below are written out by hand, not computed by the oracle.  On an
+# uncut mesh with 2 x 2 x 2 blocks of s^3 cells (block planes at index s), an
+# interface node belongs to the object given by which of its coordinates equal
+# s and, for the others, on which side of s they lie; three coordinates at s
+# make the corner, two an edge, one a face.
+
+def _uncut_two_block_objects(n, s):
+    objs = {}
+    for K in range(1, n):
+        for J in range(1, n):
+            for I in range(1, n):
+                key = tuple("s" if v == s else ("lo" if v < s else "hi") for v in (I, J, K))
+                n_at = key.count("s")
+                if n_at == 0:
+                    continue
+                objs.setdefault(key, set()).add((I, J, K))
+    typ = {3: topology.CORNER, 2: topology.EDGE, 1: topology.FACE}
+    return {frozenset(v): typ[k.count("s")] for k, v in objs.items()}
+
+
+def _oracle_objects(p, count):
+    d = assemble.discretise(p, count=count)
+    t = topology.build(p, d)
+    n1 = p.n + 1
+    got = {}
+    for o, dofs in enumerate(t.objects()):
+        nodes = d.dof_node[dofs]
+        key = frozenset((int(g % n1), int((g // n1) % n1), int(g // (n1 * n1))) for g in nodes)
+        got[key] = int(t.obj_type[o])
+    return d, t, got
+
+
+def _counts(n, inactive):
+    c = np.full(n ** 3, 512, dtype=np.int32)
+    for (i, j, k) in inactive:
+        c[i + n * (j + n * k)] = 0
+    return c
+
+
+def test_hand_cut_partition_breaks_links():
+    """n = 8, s = 4.  The column of cells (3, 1, k), k = 0..3, of subdomain 0
+    is removed.  Every node of the face x = 0.5 (I = 4) between subdomains 0
+    and 1 keeps S = {0, 1} (cells (3, 0, k) and (3, 2, k) stay), but the FE
+    edges from row J = 1 to row J = 2 of that face lie only in removed cells
+    on the subdomain-0 side, so they link nothing: the face splits into the
+    3-node line J = 1 (an edge: it holds no mesh face) and a 6-node face.  The
+    same happens on the coarse edge I = 4, K = 4 (S = {0, 1, 4, 5}): its FE
+    edge from J = 1 to J = 2 lies in cell (3, 1, 3) of subdomain 0 only, so
+    node (4, 1, 4) becomes a corner and (4, 2, 4)-(4, 3, 4) an edge."""
+    n, s = 8, 4
+    p = W.uncut(n, s)
+    count = _counts(n, [(3, 1, k) for k in range(4)])
+    expect = _uncut_two_block_objects(n, s)
+    face = frozenset((4, J, K) for J in (1, 2, 3) for K in (1, 2, 3))
+    edge = frozenset((4, J, 4) for J in (1, 2, 3))
+    assert expect.pop(face) == topology.FACE and expect.pop(edge) == topology.EDGE
+    expect[frozenset((4, 1, K) for K in (1, 2, 3))] = topology.EDGE
+    expect[frozenset((4, J, K) for J in (2, 3) for K in (1, 2, 3))] = topology.FACE
+    expect[frozenset({(4, 1, 4)})] = topology.CORNER
+    expect[frozenset({(4, 2, 4), (4, 3, 4)})] = topology.EDGE
+    d, t, got = _oracle_objects(p, count)
+    assert d.n_dof == (n - 1) ** 3          # every node is still in an active cell
+    assert got == expect
+    assert t.n_coarse == len(expect) == 21
+    # objects ordered by their smallest DOF, coarse ids in that order (cef)
+    firsts = t.obj_dofs[t.obj_ptr[:-1]]
+    assert np.all(np.diff(firsts) > 0)
+    assert np.array_equal(t.coarse_of_obj, np.arange(len(expect)))
+    # S of the split face's nodes is still {0, 1}
+    n1 = n + 1
+    for J in (1, 2, 3):
+        for K in (1, 2, 3):
+            assert t.S(d.dof_of_node[4 + n1 * (J + n1 * K)]) == (0, 1)
+
+
+def test_hand_cut_partition_face_needs_two_active_cells():
+    """n = 6, s = 3.  Cell (2, 1, 1) of subdomain 0 is removed.  The 2 x 2
+    interface nodes (3, J, K), J, K in {1, 2}, stay linked (each of their FE
+    edges also lies in another active cell of subdomain 0), but the only mesh
+    face among them has the removed cell on one side, so the object is an
+    edge, not a face.  All other objects are those of the uncut mesh."""
+    n, s = 6, 3
+    p = W.uncut(n, s)
+    count = _counts(n, [(2, 1, 1)])
+    expect = _uncut_two_block_objects(n, s)
+    key = frozenset((3, J, K) for J in (1, 2) for K in (1, 2))
+    assert expect[key] == topology.FACE
+    expect[key] = topology.EDGE
+    _, t, got = _oracle_objects(p, count)
+    assert got == expect
+    # BDDC(ce) drops faces only: the demoted object keeps its coarse DOF
+    _, t_ce, _ = _oracle_objects(p.with_options(objects=1), count)
+    assert t_ce.n_coarse == sum(1 for v in expect.values() if v != topology.FACE)
+
+
+# ---- the load b = M_cut f for a non-constant source ---------------------------
+
+def test_load_of_tensor_product_source_on_uncut_mesh():
+    """Uncut mesh, nodal source f(I, J, K) = a_I b_J c_K.  Its Q1 interpolant
+    is a product of 1-D piecewise-linear functions, and so is every hat
+    function, so b_i = int f phi_i = h^3 (w * a)_I (w * b)_J (w * c)_K with the
+    1-D mass stencil w = (1, 4, 1) / 6 (per unit length).  Exact in the
+    kept-point rule (degree <= 2 per axis); any exchange of a cell's local
+    nodes between the source and the test function breaks it."""
+    n = 6
+    h = 1.0 / n
+    rng = np.random.default_rng(3)
+    a, bb, c = rng.uniform(0.5, 2.0, (3, n + 1))
+    n1 = n + 1
+    f = (a[None, None, :] * bb[None, :, None] * c[:, None, None]).ravel()
+    p = W.uncut(n, 3)
+    d = assemble.discretise(p)
+    b = assemble.load(d, f)
+
+    def w(v, i):
+        return (v[i - 1] + 4.0 * v[i] + v[i + 1]) / 6.0
+
+    for dof, g in enumerate(d.dof_node):
+        I, J, K = g % n1, (g // n1) % n1, g // (n1 * n1)
+        expect = h ** 3 * w(a, I) * w(bb, J) * w(c, K)
+        assert abs(b[dof] - expect) <= 1e-15 * abs(expect), (I, J, K)
+
+
+def test_load_on_cut_mesh_by_global_hats():
+    """Cut mesh (n = 4, one ball), arbitrary nodal source: b_i equals the sum,
+    over every kept point x_q of every active cell, of (h^3 / 512) phi_i(x_q)
+    f_h(x_q), where phi_i and f_h are evaluated from the global tent functions
+    prod_d max(0, 1 - |x_d - X_d| / h) at the physical point (no element-local
+    node numbering).  Brute force over all nodes."""
+    from oracle import geometry
+    n = 4
+    h = 1.0 / n
+    p = W.Problem(n=n, s=2, centres=np.array([[0.45, 0.6, 0.4]]), radii=np.array([0.33]))
+    d = assemble.discretise(p)
+    assert d.cut.size > 0
+    rng = np.random.default_rng(5)
+    n1 = n + 1
+    f = rng.uniform(-1.0, 1.0, n1 ** 3)
+    b = assemble.load(d, f)
+    X = geometry.axis_coords(n)                     # (n, 8) physical coordinates
+    keep = geometry.kept_points(n, p.centres, p.radii, d.active)
+    grid = np.arange(n1) * h
+    expect = np.zeros(n1 ** 3)
+    for t, cell in enumerate(d.active):
+        i, j, k = cell % n, (cell // n) % n, cell // (n * n)
+        q = np.flatnonzero(keep[t])
+        px = X[i][q % 8]
+        py = X[j][(q // 8) % 8]
+        pz = X[k][q // 64]
+        tx = np.maximum(0.0, 1.0 - np.abs(px[:, None] - grid[None, :]) / h)   # (nq, n1)
+        ty = np.maximum(0.0, 1.0 - np.abs(py[:, None] - grid[None, :]) / h)
+        tz = np.maximum(0.0, 1.0 - np.abs(pz[:, None] - grid[None, :]) / h)
+        phi = (tz[:, :, None, None] * ty[:, None, :, None] * tx[:, None, None, :]).reshape(q.size, -1)
+        fq = phi @ f
+        expect += (h ** 3 / 512.0) * (phi * fq[:, None]).sum(axis=0)
+    np.testing.assert_allclose(b, expect[d.dof_node], rtol=1e-13, atol=1e-16)
