@@ -205,6 +205,21 @@ int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_coun
                        int64_t* dof_node, int32_t* card, int64_t* obj_ptr,
                        int64_t* obj_dofs, int8_t* obj_type, int32_t* coarse_of_obj);
 
+/* The same arrays for problem k of a context (any number of problems; sizes
+ * from cb_query_problem).  Numbering is local to the problem: cells, nodes
+ * and DOFs of problem k start at 0.  CB_ERR_ARG for k out of range. */
+int cb_export_problem_indexing(const cb_ctx* c, int32_t k, uint8_t* cell_status, int32_t* cell_count,
+                               int64_t* dof_node, int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs,
+                               int8_t* obj_type, int32_t* coarse_of_obj);
+
+/* Local DOFs of every subdomain of problem k (Sect. 3.1: the DOFs of the
+ * nodes of the subdomain's active cells), host copies:
+ *  sub_ptr  [n_sub+1]         CSR offsets, subdomains in id order
+ *                             Bx + m (By + m Bz), empty blocks included
+ *  sub_dofs [sub_ptr[n_sub]]  DOF ids, ascending within a subdomain
+ * sub_dofs may be NULL (sizes only).  CB_ERR_ARG for k out of range. */
+int cb_export_subdomains(const cb_ctx* c, int32_t k, int64_t* sub_ptr, int64_t* sub_dofs);
+
 /* Cut-cell reference matrices (kappa = 1, h = 1), host copies, packed upper
  * triangles row by row (36 values each), cut cells in ascending cell order:
  * K [n_cut_stored*36], M [n_cut_stored*36], cut_cells [n_cut_stored]. */

@@ -86,6 +86,11 @@ void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P
 template <typename TM>
 void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc);
+// Largest dynamic LDS request in bytes of the per-subdomain kernels (local
+// assembly, packed applies, coarse-basis Gram inverse) for padded orders
+// NIp, NGp, NCp and subdomain side s; it must not exceed LDS_BYTES.
+constexpr size_t LDS_BYTES = 160 * 1024;
+size_t bddc_lds_need(int NIp, int NGp, int NCp, int s, int fp32_local);
 void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int32_t* cs_sub,
                        const int32_t* cs_row, int NCp, const double* cloc, double* c);
 // Coarse solve y = A_c^{-1} x = Y^T (Y x) per problem, Y = L^{-1} of the

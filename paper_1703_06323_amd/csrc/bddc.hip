@@ -789,13 +789,31 @@ void bddc_set_reference(const double* Kref) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_Kref_b), Kref, 64 * sizeof(double));
 }
 
+inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
+
+// Dynamic LDS bytes of the per-subdomain kernels, from the padded sizes.
+size_t lds_assemble_local(int NIp, int NGp, int NCp, int s, size_t elem) {
+  const int nt = NIp + NGp;
+  const int s3 = s * s * s;
+  return (size_t)(2 * nt + NCp + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4)) * sizeof(double) +
+         (size_t)ASM_WAVES * nt * elem;
+}
+size_t lds_apply_interior(int NIp) { return (size_t)(2 * NIp + 2 * packed_blocks(NIp) * SB) * sizeof(double); }
+size_t lds_apply_neumann(int NGp) {
+  return (size_t)(2 * NGp + 2 * packed_blocks(NGp) * SB + APPLY_T) * sizeof(double);
+}
+size_t lds_small_spd_inverse(int NCp) { return (size_t)NCp * NCp * sizeof(double); }
+
+size_t bddc_lds_need(int NIp, int NGp, int NCp, int s, int fp32_local) {
+  const size_t elem = fp32_local ? sizeof(float) : sizeof(double);
+  return std::max(std::max(lds_assemble_local(NIp, NGp, NCp, s, elem), lds_apply_interior(NIp)),
+                  std::max(lds_apply_neumann(NGp), lds_small_spd_inverse(NCp)));
+}
+
 template <typename T>
 void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
                            double* diagA_G, double* Dscale, double* st_val, int32_t* st_col) {
-  const int nt = sd.NIp + sd.NGp;
-  const int s3 = g.s * g.s * g.s;
-  const size_t sh = (size_t)(2 * nt + sd.NCp + s3 + 2 * ((sd.NCp + 1 + sd.NGp + s3 + 3) / 4)) * sizeof(double) +
-                    (size_t)ASM_WAVES * nt * sizeof(T);
+  const size_t sh = lds_assemble_local(sd.NIp, sd.NGp, sd.NCp, g.s, sizeof(T));
   static const bool attr = hipFuncSetAttribute((const void*)assemble_local_kernel<T>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
   (void)attr;
@@ -827,8 +845,6 @@ void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* 
   hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, st_val, st_col, X, Y, r0, nrows);
 }
 
-inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
-
 void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt) {
   if (ns <= 0) return;
   dim3 grid((sd.NGp + CC_COLS - 1) / CC_COLS, ns);
@@ -844,8 +860,8 @@ void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const doub
 
 
 void launch_small_spd_inverse(hipStream_t st, const SubDev& sd, int ns, double* S, int* info) {
-  hipLaunchKernelGGL(small_spd_inverse_kernel, dim3(ns), dim3(256), (size_t)sd.NCp * sd.NCp * sizeof(double), st,
-                     sd, S, info);
+  hipLaunchKernelGGL(small_spd_inverse_kernel, dim3(ns), dim3(256), lds_small_spd_inverse(sd.NCp), st, sd, S,
+                     info);
 }
 
 void launch_coarse_assemble(hipStream_t st, const BatchDev& b, const int64_t* prow_off, int64_t n_prows, int max_ldc,
@@ -889,7 +905,7 @@ template void launch_pack_lower<double, float>(hipStream_t, int, int, const doub
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out) {
-  const size_t sh = (size_t)(2 * sd.NIp + 2 * packed_blocks(sd.NIp) * SB) * sizeof(double);
+  const size_t sh = lds_apply_interior(sd.NIp);
   static bool attr = (hipFuncSetAttribute((const void*)apply_interior_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
@@ -903,7 +919,7 @@ template void launch_apply_interior<float>(hipStream_t, const SubDev&, int, cons
 template <typename TM>
 void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc) {
-  const size_t sh = (size_t)(2 * sd.NGp + 2 * packed_blocks(sd.NGp) * SB + APPLY_T) * sizeof(double);
+  const size_t sh = lds_apply_neumann(sd.NGp);
   static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;

@@ -626,6 +626,17 @@ int validate_problem(const cb_problem* p) {
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(p->ball_centres[3 * i + d])) return fail(CB_ERR_ARG, "ball centre not finite");
   }
+  {
+    // the per-subdomain kernels hold padded local vectors and partial sums in
+    // LDS: reject block sizes whose uncut subdomain (interior (s-1)^3 nodes,
+    // interface (s+1)^3 - (s-1)^3, 26 coarse DOFs) would not fit
+    const int nI = (s - 1) * (s - 1) * (s - 1), nG = (s + 1) * (s + 1) * (s + 1) - nI;
+    const size_t need = bddc_lds_need(round_up(std::max(1, nI), CHOL_BLOCK), round_up(nG, CHOL_BLOCK), 32, s,
+                                      p->local_precision);
+    if (need > LDS_BYTES)
+      return fail(CB_ERR_ARG, "sub_cells = " + std::to_string(s) + " needs " + std::to_string(need) +
+                                  " bytes of LDS per subdomain workgroup (limit " + std::to_string(LDS_BYTES) + ")");
+  }
   const int64_t ncell = (int64_t)N * N * N;
   if (p->kappa)
     for (int64_t c = 0; c < ncell; ++c)
@@ -868,6 +879,14 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   c->NIp = round_up(maxI, CHOL_BLOCK);
   c->NGp = round_up(maxG, CHOL_BLOCK);
   c->NCp = round_up(maxC, 16);
+  {
+    const size_t need = bddc_lds_need(c->NIp, c->NGp, c->NCp, s, c->precision);
+    if (need > LDS_BYTES)
+      return fail(CB_ERR_ARG, "padded local orders (interior " + std::to_string(c->NIp) + ", interface " +
+                                  std::to_string(c->NGp) + ", coarse " + std::to_string(c->NCp) + ") need " +
+                                  std::to_string(need) + " bytes of LDS per subdomain workgroup (limit " +
+                                  std::to_string(LDS_BYTES) + ")");
+  }
   c->nt = c->NIp + c->NGp;
   const int NIp = c->NIp, NGp = c->NGp, NCp = c->NCp;
   const int s1 = s + 1;
@@ -1071,10 +1090,50 @@ size_t factor_work_budget() {
   return (size_t)(gb * (double)(1ull << 30));
 }
 
+// Work buffers of the local factorisation for a chunk of subdomains, in the
+// compute type T of the local Cholesky and inverses.
 template <typename T>
-int factor_impl(cb_ctx* c) {
+struct FactorWork {
+  int chunk = 0;
+  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V, StV, StC;
+  static size_t per_sub(const cb_ctx* c) {
+    const int nt = c->nt, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nbig = std::max(NIp, NGp);
+    return (size_t)nt * nt * sizeof(T) + (size_t)diag_blocks(nt, NIp) * DB * DB * sizeof(T) +
+           2 * (size_t)nbig * nbig * sizeof(T) + (size_t)NIp * NIp * 8 + (size_t)NGp * NGp * 8 +
+           (size_t)(NGp * NCp + NCp * NCp + 2 * nt * NCp) * sizeof(double) +
+           (size_t)nt * STENCIL * (sizeof(double) + sizeof(int32_t));
+  }
+  int alloc(const cb_ctx* c, int n) {
+    chunk = n;
+    const int nt = c->nt, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nbig = std::max(NIp, NGp);
+    const size_t sF = (size_t)nt * NCp;
+    CHK(dalloc(K, (size_t)n * nt * nt * sizeof(T)));
+    CHK(dalloc(Linv, (size_t)n * diag_blocks(nt, NIp) * DB * DB * sizeof(T)));
+    CHK(dalloc(Y, (size_t)n * nbig * nbig * sizeof(T)));
+    CHK(dalloc(PS, (size_t)n * nbig * nbig * sizeof(T)));
+    CHK(dalloc(Pd64, (size_t)n * NIp * NIp * sizeof(double)));
+    CHK(dalloc(KSw, (size_t)n * NGp * NGp * sizeof(double)));
+    CHK(dalloc(G, (size_t)n * NGp * NCp * sizeof(double)));
+    CHK(dalloc(Sc, (size_t)n * NCp * NCp * sizeof(double)));
+    CHK(dalloc(PhiF, (size_t)n * sF * sizeof(double)));
+    CHK(dalloc(V, (size_t)n * sF * sizeof(double)));
+    CHK(dalloc(StV, (size_t)n * nt * STENCIL * sizeof(double)));
+    CHK(dalloc(StC, (size_t)n * nt * STENCIL * sizeof(int32_t)));
+    return CB_OK;
+  }
+  void release() {
+    for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V, &StV, &StC}) b->release();
+  }
+};
+
+// Local factorisation of subdomains [w0, w0 + nc) (Sect. 3.3-3.4): assembly
+// of the local matrix, Cholesky in type T, the Dirichlet inverse and the
+// constrained interface operator stored in type TS, the FP64 coarse basis
+// and the local coarse matrix.  Pivot failures go to info[w].
+template <typename T, typename TS>
+int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
   hipStream_t st = c->st;
-  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
+  const int NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
   const GridDev g = c->grid();
   const int nbig = std::max(NIp, NGp);
   const int64_t sK = (int64_t)nt * nt;
@@ -1082,65 +1141,11 @@ int factor_impl(cb_ctx* c) {
   const int64_t sY = (int64_t)nbig * nbig;
   const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp, sF = (int64_t)nt * NCp;
   const int64_t sP = (int64_t)NIp * NIp, sKS = (int64_t)NGp * NGp;
-
-  // persistent results (A_II^{-1} and the interface operator in packed
-  // symmetric storage)
   const int64_t pkI = packed_elems(NIp), pkG = packed_elems(NGp);
-  CHK(dalloc(c->P_, (size_t)ns * pkI * sizeof(T)));
-  CHK(dalloc(c->Kt, (size_t)ns * pkG * sizeof(T)));
-  CHK(dalloc(c->Phi, (size_t)ns * sG * sizeof(double)));
-  CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
-  CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
-  CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
-  if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
-  if (!c->aux_st3) HIPCHK(hipStreamCreateWithFlags(&c->aux_st3, hipStreamNonBlocking));
-  if (!c->aux_ev) HIPCHK(hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
-  if (!c->aux_ev3) HIPCHK(hipEventCreateWithFlags(&c->aux_ev3, hipEventDisableTiming));
-  const int n_info = ns + 1 + c->P;
-  CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
-  HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
-  HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
-  DevBuf AcLoc;
-  CHK(dalloc(AcLoc, (size_t)ns * sC * sizeof(double)));
-  // object member lists, once for all subdomains (sub() hands them out below)
-  c->optr_d.release();
-  c->omem_d.release();
-  CHK(dalloc(c->optr_d, (size_t)ns * (NCp + 1) * sizeof(int32_t)));
-  CHK(dalloc(c->omem_d, (size_t)ns * NGp * sizeof(int32_t)));
-  launch_object_lists(st, c->sub(0), ns, c->optr_d.as<int32_t>(), c->omem_d.as<int32_t>());
-  HIPCHK(hipGetLastError());
-
-  // work buffers for a chunk of subdomains
-  const size_t per_sub = (size_t)sK * sizeof(T) + (size_t)sL * sizeof(T) + 2 * (size_t)sY * sizeof(T) +
-                         (size_t)sP * 8 + (size_t)sKS * 8 +
-                         (size_t)(sG + sC + 2 * sF) * sizeof(double) +
-                         (size_t)nt * STENCIL * (sizeof(double) + sizeof(int32_t));
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / per_sub));
-  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V, StV, StC;
-  CHK(dalloc(K, (size_t)chunk * sK * sizeof(T)));
-  CHK(dalloc(Linv, (size_t)chunk * sL * sizeof(T)));
-  CHK(dalloc(Y, (size_t)chunk * sY * sizeof(T)));
-  CHK(dalloc(PS, (size_t)chunk * sY * sizeof(T)));
-  CHK(dalloc(Pd64, (size_t)chunk * sP * sizeof(double)));
-  CHK(dalloc(KSw, (size_t)chunk * sKS * sizeof(double)));
-  CHK(dalloc(G, (size_t)chunk * sG * sizeof(double)));
-  CHK(dalloc(Sc, (size_t)chunk * sC * sizeof(double)));
-  CHK(dalloc(PhiF, (size_t)chunk * sF * sizeof(double)));
-  CHK(dalloc(V, (size_t)chunk * sF * sizeof(double)));
-  CHK(dalloc(StV, (size_t)chunk * nt * STENCIL * sizeof(double)));
-  CHK(dalloc(StC, (size_t)chunk * nt * STENCIL * sizeof(int32_t)));
-  // on every exit, st waits for the other streams before the buffers above
-  // return to the cache (destroyed after this guard)
-  struct AuxJoin {
-    cb_ctx* c;
-    ~AuxJoin() {
-      if (hipEventRecord(c->aux_ev, c->aux_st) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev, 0);
-      if (hipEventRecord(c->aux_ev3, c->aux_st3) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev3, 0);
-    }
-  } aux_join{c};
-
-  for (int w0 = 0; w0 < ns; w0 += chunk) {
-    const int nc = std::min(chunk, ns - w0);
+  const int ns = c->ns;
+  DevBuf &K = fw.K, &Linv = fw.Linv, &Y = fw.Y, &PS = fw.PS, &Pd64 = fw.Pd64, &KSw = fw.KSw, &G = fw.G,
+         &Sc = fw.Sc, &PhiF = fw.PhiF, &V = fw.V, &StV = fw.StV, &StC = fw.StC;
+  {
     const SubDev sd = c->sub(w0);
     const double* Dsw = c->Ds.as<double>() + (int64_t)w0 * nt;
     double* Phiw = c->Phi.as<double>() + (int64_t)w0 * sG;
@@ -1157,7 +1162,7 @@ int factor_impl(cb_ctx* c) {
       gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG);
     });
-    launch_pack_lower<T, T>(st, NIp, nc, PS.as<T>(), NIp, sY, Dsw, nt, c->P_.as<T>() + (int64_t)w0 * pkI);
+    launch_pack_lower<T, TS>(st, NIp, nc, PS.as<T>(), NIp, sY, Dsw, nt, c->P_.as<TS>() + (int64_t)w0 * pkI);
     // full FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
     symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
     const double* Pd = Pd64.as<double>();
@@ -1192,14 +1197,99 @@ int factor_impl(cb_ctx* c) {
     launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), NIp,
                        NGp);
     gemm<double>(st, 1, 0, NCp, NCp, NGp, 1.0, PhiF.as<double>() + (int64_t)NIp * NCp, NCp, sF,
-                 V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc.as<double>() + (int64_t)w0 * sC, NCp, sC,
-                 nc, 0);
+                 V.as<double>() + (int64_t)NIp * NCp, NCp, sF, 0.0, AcLoc + (int64_t)w0 * sC, NCp, sC, nc, 0);
     // Kt = K_S^{-1} - Phi G^T: the lower part in place in K_S^{-1} (MFMA),
     // then packed with its mirror
     gemm<double>(st, 0, 0, NGp, NGp, NCp, -1.0, Phiw, NCp, sG, G.as<double>(), NGp, sG, 1.0, KS, NGp, sKS, nc,
                  GEMM_LOWER);
-    launch_pack_lower<double, T>(st, NGp, nc, KS, NGp, sKS, nullptr, 0, c->Kt.as<T>() + (int64_t)w0 * pkG);
+    launch_pack_lower<double, TS>(st, NGp, nc, KS, NGp, sKS, nullptr, 0, c->Kt.as<TS>() + (int64_t)w0 * pkG);
     HIPCHK(hipGetLastError());
+  }
+  return CB_OK;
+}
+
+// Subdomains whose FP32 local Cholesky met a non-positive pivot are factored
+// again in FP64; their operators are then stored in FP32 like the others.
+// CUTBDDC_FORCE_FP32_BREAKDOWN=w (test hook) treats global subdomain w as
+// such a failure.  Returns the number of refactored subdomains in *n_redo.
+int fp64_refactor(cb_ctx* c, double* AcLoc, int* n_redo) {
+  hipStream_t st = c->st;
+  const int ns = c->ns;
+  std::vector<int> info(ns);
+  HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (const char* e = std::getenv("CUTBDDC_FORCE_FP32_BREAKDOWN")) {
+    const int w = std::atoi(e);
+    if (w >= 0 && w < ns && info[w] == 0) info[w] = 1;
+  }
+  std::vector<int> redo;
+  for (int w = 0; w < ns; ++w)
+    if (info[w] != 0) redo.push_back(w);
+  *n_redo = (int)redo.size();
+  if (redo.empty()) return CB_OK;
+  FactorWork<double> fw;
+  CHK(fw.alloc(c, 1));
+  for (int w : redo) {
+    HIPCHK(hipMemsetAsync(c->info_d.as<int>() + w, 0, sizeof(int), st));
+    CHK((factor_chunk<double, float>(c, fw, w, 1, AcLoc)));
+  }
+  return CB_OK;
+}
+
+template <typename T>
+int factor_impl(cb_ctx* c) {
+  hipStream_t st = c->st;
+  const int ns = c->ns, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nt = c->nt;
+  const int64_t sG = (int64_t)NGp * NCp, sC = (int64_t)NCp * NCp;
+
+  // persistent results (A_II^{-1} and the interface operator in packed
+  // symmetric storage)
+  const int64_t pkI = packed_elems(NIp), pkG = packed_elems(NGp);
+  CHK(dalloc(c->P_, (size_t)ns * pkI * sizeof(T)));
+  CHK(dalloc(c->Kt, (size_t)ns * pkG * sizeof(T)));
+  CHK(dalloc(c->Phi, (size_t)ns * sG * sizeof(double)));
+  CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
+  CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
+  CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
+  if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
+  if (!c->aux_st3) HIPCHK(hipStreamCreateWithFlags(&c->aux_st3, hipStreamNonBlocking));
+  if (!c->aux_ev) HIPCHK(hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
+  if (!c->aux_ev3) HIPCHK(hipEventCreateWithFlags(&c->aux_ev3, hipEventDisableTiming));
+  const int n_info = ns + 1 + c->P;
+  CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
+  HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
+  DevBuf AcLoc;
+  CHK(dalloc(AcLoc, (size_t)ns * sC * sizeof(double)));
+  // object member lists, once for all subdomains (sub() hands them out below)
+  c->optr_d.release();
+  c->omem_d.release();
+  CHK(dalloc(c->optr_d, (size_t)ns * (NCp + 1) * sizeof(int32_t)));
+  CHK(dalloc(c->omem_d, (size_t)ns * NGp * sizeof(int32_t)));
+  launch_object_lists(st, c->sub(0), ns, c->optr_d.as<int32_t>(), c->omem_d.as<int32_t>());
+  HIPCHK(hipGetLastError());
+
+  // work buffers for a chunk of subdomains
+  const int chunk =
+      (int)std::max<size_t>(1, std::min<size_t>((size_t)ns, factor_work_budget() / FactorWork<T>::per_sub(c)));
+  FactorWork<T> fw;
+  CHK(fw.alloc(c, chunk));
+  // on every exit, st waits for the other streams before the buffers above
+  // return to the cache (destroyed after this guard)
+  struct AuxJoin {
+    cb_ctx* c;
+    ~AuxJoin() {
+      if (hipEventRecord(c->aux_ev, c->aux_st) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev, 0);
+      if (hipEventRecord(c->aux_ev3, c->aux_st3) == hipSuccess) (void)hipStreamWaitEvent(c->st, c->aux_ev3, 0);
+    }
+  } aux_join{c};
+
+  for (int w0 = 0; w0 < ns; w0 += chunk) CHK((factor_chunk<T, T>(c, fw, w0, std::min(chunk, ns - w0),
+                                                                    AcLoc.as<double>())));
+  c->n_fallbacks = 0;
+  if (std::is_same<T, float>::value) {
+    fw.release();
+    CHK(fp64_refactor(c, AcLoc.as<double>(), &c->n_fallbacks));
   }
   launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
                  NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
@@ -1253,7 +1343,7 @@ int factor_impl(cb_ctx* c) {
   // join the second stream before the chunk buffers go back to the cache
   HIPCHK(hipEventRecord(c->aux_ev, c->aux_st));
   HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
-  for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V, &StV, &StC}) b->release();
+  fw.release();
   std::vector<int> info(n_info);
   HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1598,12 +1688,15 @@ int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out) {
   return CB_OK;
 }
 
-int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_count, int64_t* dof_node,
-                       int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type,
-                       int32_t* coarse_of_obj) {
-  if (!c) return fail(CB_ERR_ARG, "null context");
-  CHK(need_single(c));
-  const ProbHost& h = c->pb[0];
+}  // extern "C"
+
+namespace {
+
+// Host copies of the integer indexing of problem k (see cb_export_indexing).
+int export_indexing_impl(const cb_ctx* c, int k, uint8_t* cell_status, int32_t* cell_count, int64_t* dof_node,
+                         int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type,
+                         int32_t* coarse_of_obj) {
+  const ProbHost& h = c->pb[k];
   const int64_t ncell = (int64_t)h.N * h.N * h.N;
   const int64_t N1 = h.N + 1, nnode = N1 * N1 * N1;
   HIPCHK(hipStreamSynchronize(c->st));
@@ -1673,6 +1766,66 @@ int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_coun
     if (obj_type)
       obj_type[o] = size2[ln] == 1 ? OBJ_CORNER : (face[par1[ln] - h.node_off] ? OBJ_FACE : OBJ_EDGE);
     if (coarse_of_obj) coarse_of_obj[o] = ocid[ln] >= 0 ? ocid[ln] - h.coarse_off : -1;
+  }
+  return CB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cb_export_indexing(const cb_ctx* c, uint8_t* cell_status, int32_t* cell_count, int64_t* dof_node,
+                       int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs, int8_t* obj_type,
+                       int32_t* coarse_of_obj) {
+  if (!c) return fail(CB_ERR_ARG, "null context");
+  CHK(need_single(c));
+  return export_indexing_impl(c, 0, cell_status, cell_count, dof_node, card, obj_ptr, obj_dofs, obj_type,
+                              coarse_of_obj);
+}
+
+int cb_export_problem_indexing(const cb_ctx* c, int32_t k, uint8_t* cell_status, int32_t* cell_count,
+                               int64_t* dof_node, int32_t* card, int64_t* obj_ptr, int64_t* obj_dofs,
+                               int8_t* obj_type, int32_t* coarse_of_obj) {
+  if (!c) return fail(CB_ERR_ARG, "null context");
+  if (k < 0 || k >= c->P) return fail(CB_ERR_ARG, "problem index out of range");
+  return export_indexing_impl(c, k, cell_status, cell_count, dof_node, card, obj_ptr, obj_dofs, obj_type,
+                              coarse_of_obj);
+}
+
+int cb_export_subdomains(const cb_ctx* c, int32_t k, int64_t* sub_ptr, int64_t* sub_dofs) {
+  if (!c || !sub_ptr) return fail(CB_ERR_ARG, "null argument");
+  if (k < 0 || k >= c->P) return fail(CB_ERR_ARG, "problem index out of range");
+  const ProbHost& h = c->pb[k];
+  HIPCHK(hipStreamSynchronize(c->st));
+  const int NIp = c->NIp, NGp = c->NGp;
+  std::vector<int64_t> I((size_t)h.ns * NIp), G((size_t)h.ns * NGp), dn(std::max<int64_t>(1, h.n_dof));
+  if (h.ns) {
+    HIPCHK(hipMemcpy(I.data(), c->Iidx.as<int64_t>() + (int64_t)h.sub_off * NIp, I.size() * sizeof(int64_t),
+                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(G.data(), c->Gidx.as<int64_t>() + (int64_t)h.sub_off * NGp, G.size() * sizeof(int64_t),
+                     hipMemcpyDeviceToHost));
+  }
+  if (h.n_dof)
+    HIPCHK(hipMemcpy(dn.data(), c->dof_node.as<int64_t>() + h.dof_off, h.n_dof * sizeof(int64_t),
+                     hipMemcpyDeviceToHost));
+  // grid node -> DOF id (DOFs are in ascending node order)
+  auto dof_of = [&](int64_t node) -> int64_t {
+    const auto it = std::lower_bound(dn.begin(), dn.begin() + h.n_dof, node);
+    return (it != dn.begin() + h.n_dof && *it == node) ? (int64_t)(it - dn.begin()) : -1;
+  };
+  sub_ptr[0] = 0;
+  std::vector<int64_t> loc;
+  for (int w = 0; w < h.ns; ++w) {
+    loc.clear();
+    for (int i = 0; i < NIp; ++i)
+      if (I[(size_t)w * NIp + i] >= 0) loc.push_back(dof_of(I[(size_t)w * NIp + i]));
+    for (int j = 0; j < NGp; ++j)
+      if (G[(size_t)w * NGp + j] >= 0) loc.push_back(dof_of(G[(size_t)w * NGp + j]));
+    for (int64_t d : loc)
+      if (d < 0) return fail(CB_ERR_STATE, "subdomain export: a local node is not a DOF");
+    std::sort(loc.begin(), loc.end());
+    if (sub_dofs) std::copy(loc.begin(), loc.end(), sub_dofs + sub_ptr[w]);
+    sub_ptr[w + 1] = sub_ptr[w] + (int64_t)loc.size();
   }
   return CB_OK;
 }

@@ -764,7 +764,7 @@ int build_topology(const Geometry& g, const int32_t* cell_count, Topology& t, st
         const int32_t q = iface_of[d];
         t.if_sub[t.if_ptr[q] + k] = (int32_t)w;
         t.if_slot[t.if_ptr[q] + k] = slot;
-        t.iface_node[q] = n;
+        if (k == 0) t.iface_node[q] = n;   // written once, by the first subdomain of S
       });
     }
   });

@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.cb_load.argtypes = [vp, vp, vp]
     lib.cb_query.argtypes = [vp, C.POINTER(cb_info)]
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
+    lib.cb_export_problem_indexing.argtypes = [vp, C.c_int32] + [vp] * 8
+    lib.cb_export_subdomains.argtypes = [vp, C.c_int32, vp, vp]
     lib.cb_export_cut_matrices.argtypes = [vp, vp, vp, vp]
     lib.cb_export_coarse.argtypes = [vp, vp]
     lib.cb_host_indexing.argtypes = [C.POINTER(cb_problem), vp, C.POINTER(cb_info)] + [vp] * 6
@@ -94,7 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.cb_destroy.restype = None
     for name in ("cb_setup", "cb_factor", "cb_solve", "cb_solve_rhs", "cb_grad",
                  "cb_apply_operator", "cb_apply_preconditioner", "cb_load", "cb_query",
-                 "cb_export_indexing", "cb_export_cut_matrices", "cb_export_coarse",
+                 "cb_export_indexing", "cb_export_problem_indexing", "cb_export_subdomains",
+                 "cb_export_cut_matrices", "cb_export_coarse",
                  "cb_dense_spd_inverse", "cb_profile", "cb_profile_time", "cb_host_indexing",
                  "cb_setup_batch", "cb_solve_batch", "cb_query_problem", "cb_profile_launches",
                  "cb_time_kernel"):
@@ -254,23 +257,11 @@ class Solver:
 
     # -- host exports --------------------------------------------------------
     def export_indexing(self) -> dict:
-        inf = self.info()
-        n3 = self.n ** 3
-        out = {
-            "cell_status": np.zeros(n3, np.uint8),
-            "cell_count": np.zeros(n3, np.int32),
-            "dof_node": np.zeros(inf["n_dof"], np.int64),
-            "card": np.zeros(inf["n_dof"], np.int32),
-            "obj_ptr": np.zeros(inf["n_objects"] + 1, np.int64),
-            "obj_dofs": np.zeros(inf["n_iface"], np.int64),
-            "obj_type": np.zeros(inf["n_objects"], np.int8),
-            "coarse_of_obj": np.zeros(inf["n_objects"], np.int32),
-        }
-        args = [out[k].ctypes.data_as(C.c_void_p) for k in
-                ("cell_status", "cell_count", "dof_node", "card", "obj_ptr", "obj_dofs",
-                 "obj_type", "coarse_of_obj")]
-        _check(_lib.cb_export_indexing(self.ctx, *args))
-        return out
+        return _export_indexing(self.ctx, None, self.n, self.info())
+
+    def export_subdomains(self):
+        """(sub_ptr, sub_dofs): local DOFs of every subdomain, ascending."""
+        return _export_subdomains(self.ctx, 0, int(self.info()["n_sub"]))
 
     def export_cut_matrices(self):
         n = int(self.info()["n_cut_stored"])
@@ -346,6 +337,12 @@ class BatchSolver:
     def n_dofs(self):
         return [int(self.problem_info(k)["n_dof"]) for k in range(self.size)]
 
+    def export_indexing(self, k: int) -> dict:
+        return _export_indexing(self.ctx, int(k), self.ns[k], self.problem_info(k))
+
+    def export_subdomains(self, k: int):
+        return _export_subdomains(self.ctx, int(k), int(self.problem_info(k)["n_sub"]))
+
     def solve(self, fs=None, rtol=1e-8, max_iter=1000, outputs=None, allow_no_convergence=False):
         """fs: list of cuda float64 tensors [(N_k+1)^3] (or None entries / None
         for f = 1).  Returns (list of u_k [n_dof_k], iterations [n],
@@ -369,6 +366,40 @@ class BatchSolver:
                                  rel.ctypes.data_as(C.POINTER(C.c_double)))
         _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
         return outputs, it, rel
+
+
+_INDEX_KEYS = ("cell_status", "cell_count", "dof_node", "card", "obj_ptr", "obj_dofs", "obj_type",
+               "coarse_of_obj")
+
+
+def _export_indexing(ctx, k, n, inf) -> dict:
+    """Integer indexing of problem k of a context (k None: the single-problem
+    entry point)."""
+    n3 = n ** 3
+    out = {
+        "cell_status": np.zeros(n3, np.uint8),
+        "cell_count": np.zeros(n3, np.int32),
+        "dof_node": np.zeros(inf["n_dof"], np.int64),
+        "card": np.zeros(inf["n_dof"], np.int32),
+        "obj_ptr": np.zeros(inf["n_objects"] + 1, np.int64),
+        "obj_dofs": np.zeros(inf["n_iface"], np.int64),
+        "obj_type": np.zeros(inf["n_objects"], np.int8),
+        "coarse_of_obj": np.zeros(inf["n_objects"], np.int32),
+    }
+    args = [out[key].ctypes.data_as(C.c_void_p) for key in _INDEX_KEYS]
+    if k is None:
+        _check(_lib.cb_export_indexing(ctx, *args))
+    else:
+        _check(_lib.cb_export_problem_indexing(ctx, k, *args))
+    return out
+
+
+def _export_subdomains(ctx, k, n_sub):
+    ptr = np.zeros(n_sub + 1, np.int64)
+    _check(_lib.cb_export_subdomains(ctx, k, ptr.ctypes.data_as(C.c_void_p), None))
+    dofs = np.zeros(max(int(ptr[-1]), 1), np.int64)
+    _check(_lib.cb_export_subdomains(ctx, k, ptr.ctypes.data_as(C.c_void_p), dofs.ctypes.data_as(C.c_void_p)))
+    return ptr, dofs[:int(ptr[-1])]
 
 
 def _problem_struct(problem):

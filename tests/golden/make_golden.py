@@ -13,7 +13,9 @@ log-normal conductivity (cut_cube_96.json, cut_cube_96_sample.npz); with
 `grad`, gradient_64.npz (adjoint gradient of the differentiation workload);
 with `batch`, batch_256.json + batch_256_sample.npz (per problem of the
 256-problem batch: sizes, SHA-256 of the DOF nodes, iteration count and a
-16-DOF sample plus the 2-norm of the FP64 PCG solution at rtol 1e-8).
+16-DOF sample plus the 2-norm of the FP64 PCG solution at rtol 1e-8); with
+`batch_full`, batch_256_full.npz (the whole FP64 PCG solution of the first
+problem of each mesh size of that batch).
 """
 import hashlib
 import json
@@ -134,11 +136,30 @@ def batch(workers=6):
     print("batch golden written", time.time() - t0, "s")
 
 
+def batch_full():
+    """Whole solution vectors of one problem per mesh size of the batch (the
+    first of each size), FP64 oracle at rtol 1e-8."""
+    probs = W.batch_256()
+    first = {}
+    for k, p in enumerate(probs):
+        first.setdefault(p.n, k)
+    out = {"k": np.array(sorted(first.values()), dtype=np.int64)}
+    for k in out["k"]:
+        p = probs[k].with_options(local_precision=0)
+        s = OracleSolver(p)
+        x, it, rel = s.solve(rtol=1e-8)
+        out[f"u{k}"] = x
+        print(f"problem {k} n={p.n} n_dof={s.n_dof} iterations {it}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "batch_256_full.npz"), **out)
+
+
 if __name__ == "__main__":
     arg = sys.argv[1] if len(sys.argv) > 1 else "64"
     if arg == "grad":
         gradient()
     elif arg == "batch":
         batch()
+    elif arg == "batch_full":
+        batch_full()
     else:
         main(arg)

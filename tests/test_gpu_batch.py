@@ -7,8 +7,9 @@ count, FP32 local solves to 1e-6 within one iteration.  The batch must also
 reproduce the single-problem path, and repeated solves (replays of the
 captured PCG iteration) must agree with eager launches.  The 256-problem
 batch is checked against stored oracle values (tests/golden/make_golden.py
-batch): sizes, iteration counts, a 16-DOF sample and the 2-norm of each
-solution."""
+batch, batch_full): sizes, the DOF numbering of every problem (SHA-256),
+iteration counts, a 16-DOF sample and the 2-norm of each solution, and the
+whole solution vector of the first problem of each mesh size."""
 import json
 import os
 
@@ -157,10 +158,25 @@ def test_batch_256_against_oracle():
     print("[gpu] batch_256 solve", flush=True)
     us, its, rels = b.solve([torch.tensor(p.f, device="cuda") for p in probs], rtol=1e-8)
     worst = 0.0
+    full_path = os.path.join(GOLDEN, "batch_256_full.npz")
+    full = np.load(full_path) if os.path.exists(full_path) else None
+    full_ks = set(int(k) for k in full["k"]) if full is not None else set()
+    import hashlib
     for k, p in enumerate(probs):
         m = meta[k]
         inf = b.problem_info(k)
         assert inf["n_dof"] == m["n_dof"] and inf["n_coarse"] == m["n_coarse"], k
+        # bit-exact DOF numbering of every problem of the batch
+        dn = b.export_indexing(k)["dof_node"].astype(np.int64)
+        assert hashlib.sha256(np.ascontiguousarray(dn).tobytes()).hexdigest() == m["dof_node_sha256"], k
+        if k in full_ks:
+            x = full[f"u{k}"]
+            u_k = us[k].cpu().numpy()
+            e_full = np.linalg.norm(u_k - x) / np.linalg.norm(x)
+            e_elem = np.max(np.abs(u_k - x)) / np.max(np.abs(x))
+            print(f"  problem {k} (n={p.n}, {x.size} DOFs): whole-vector error {e_full:.2e}, "
+                  f"element-wise {e_elem:.2e}, iterations {its[k]} (oracle {m['iterations']})")
+            assert e_full <= 1e-6 and e_elem <= 1e-6, k
         assert abs(int(its[k]) - m["iterations"]) <= 1, k
         assert rels[k] < 1e-8
         u = us[k].cpu().numpy()

@@ -54,9 +54,7 @@ def solver(tag, precision):
     return _solvers[key]
 
 
-def test_cut_cube_64_indexing_matches_oracle():
-    meta, _ = load("cut_cube_64")
-    s, _ = solver("cut_cube_64", 0)
+def check_hashes(s, meta):
     g = s.export_indexing()
     inf = s.info()
     assert inf["n_dof"] == meta["n_dof"] and inf["n_coarse"] == meta["n_coarse"]
@@ -69,6 +67,18 @@ def test_cut_cube_64_indexing_matches_oracle():
     assert sha(g["obj_dofs"].astype(np.int64)) == h["obj_dofs"]
     assert sha(g["obj_type"].astype(np.int8)) == h["obj_type"]
     assert sha(g["coarse_of_obj"].astype(np.int32)) == h["coarse_of_obj"]
+
+
+def test_cut_cube_64_indexing_matches_oracle():
+    meta, _ = load("cut_cube_64")
+    s, _ = solver("cut_cube_64", 0)
+    check_hashes(s, meta)
+
+
+def test_cut_cube_96_indexing_matches_oracle():
+    meta, _ = load("cut_cube_96")
+    s, _ = solver("cut_cube_96", 1)
+    check_hashes(s, meta)
 
 
 def test_cut_cube_64_fp64_solution():
@@ -88,9 +98,11 @@ def test_cut_cube_64_fp32_local_solution():
     print("[gpu] solve cut_cube_64 fp32-local", flush=True)
     u, it, rel = s.solve(p.f, rtol=1e-8)
     assert rel < 1e-8
-    assert sample_err(u.cpu().numpy(), smp) < 1e-6
-    print(f"fp32-local iterations {it} vs fp64 oracle {meta['iterations_rtol_1e-8']}")
-    assert it <= meta["iterations_rtol_1e-8"] + 5
+    err = sample_err(u.cpu().numpy(), smp)
+    print(f"fp32-local cut_cube_64: iterations {it} vs FP64 oracle {meta['iterations_rtol_1e-8']}, "
+          f"sample error {err:.2e}")
+    assert err < 1e-6
+    assert abs(it - meta["iterations_rtol_1e-8"]) <= 1
 
 
 def test_cut_cube_96_fp32_local_solution():
@@ -99,5 +111,8 @@ def test_cut_cube_96_fp32_local_solution():
     print("[gpu] solve cut_cube_96 fp32-local", flush=True)
     u, it, rel = s.solve(p.f, rtol=1e-8)
     assert rel < 1e-8
-    assert sample_err(u.cpu().numpy(), smp) < 1e-6
-    assert it <= meta["iterations_rtol_1e-8"] + 5
+    err = sample_err(u.cpu().numpy(), smp)
+    print(f"fp32-local cut_cube_96: iterations {it} vs FP64 oracle {meta['iterations_rtol_1e-8']}, "
+          f"sample error {err:.2e}")
+    assert err < 1e-6
+    assert abs(it - meta["iterations_rtol_1e-8"]) <= 1

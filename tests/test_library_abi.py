@@ -36,3 +36,48 @@ def test_binding_signatures_load():
     from paper_1703_06323_amd import cutbddc
     lib = cutbddc.load_library()
     assert lib.cb_last_error() is not None
+
+
+def _setup_status(problem):
+    """cb_setup's status for a problem that argument validation must reject
+    before any device work (so it runs without a GPU)."""
+    from paper_1703_06323_amd import cutbddc
+    lib = cutbddc.load_library()
+    p, keep = cutbddc._problem_struct(problem)
+    ctx = ctypes.c_void_p()
+    rc = lib.cb_setup(ctypes.byref(p), None, ctypes.byref(ctx))
+    return rc, lib.cb_last_error().decode(), ctx
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("s", [12, 16])
+def test_setup_rejects_blocks_too_large_for_lds(s):
+    """Subdomain blocks whose padded local vectors and partial sums exceed
+    the 160 KB of LDS of a workgroup are an argument error at setup, not a
+    launch failure inside factor or solve."""
+    import workloads as W
+    from paper_1703_06323_amd import cutbddc
+    rc, msg, ctx = _setup_status(W.uncut(2 * s, s))
+    assert rc == cutbddc.CB_ERR_ARG and "LDS" in msg, (rc, msg)
+    assert not ctx.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_setup_argument_errors():
+    import numpy as np
+
+    import workloads as W
+    from paper_1703_06323_amd import cutbddc
+    assert _setup_status(W.uncut(10, 4))[0] == cutbddc.CB_ERR_ARG                 # s does not divide N
+    assert _setup_status(W.uncut(8, 4).with_options(weighting=3))[0] == cutbddc.CB_ERR_ARG
+    assert _setup_status(W.uncut(8, 4).with_options(coarse_variant=7))[0] == cutbddc.CB_ERR_ARG
+    bad = W.Problem(n=8, s=4, centres=np.array([[0.5, 0.5, 0.5]]), radii=np.array([-0.1]))
+    assert _setup_status(bad)[0] == cutbddc.CB_ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_null_context_errors():
+    from paper_1703_06323_amd import cutbddc
+    lib = cutbddc.load_library()
+    assert lib.cb_factor(None) == cutbddc.CB_ERR_ARG
+    assert lib.cb_query(None, None) == cutbddc.CB_ERR_ARG
