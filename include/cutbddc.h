@@ -246,6 +246,21 @@ int cb_host_indexing(const cb_problem* p, const int32_t* cell_count, cb_info* in
  * default stream.  CB_ERR_NOT_SPD if a pivot is not positive. */
 int cb_dense_spd_inverse(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv);
 
+/* Allocation-free variant of cb_dense_spd_inverse, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors; the
+ * host arrays A and Ainv are still the caller's.  Every intermediate lives
+ * in a fixed 64 MiB device array that the library holds on each GPU it runs
+ * on until the process ends: the padded matrices need
+ *   batch * (n^2 * 8 + np^2 * (3 s + 8) + ceil(np/128) * 128^2 * s) bytes
+ * plus a few KB, np = n rounded up to 32, s = 8 (precision 0) or 4
+ * (precision 1), each part rounded up to 256 bytes.  Larger requests return
+ * CB_ERR_ARG.  No hipMalloc, hipFree or tuning allocation happens: GEMM tile
+ * shapes not tuned before fall back to the default tile.  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU race and must be
+ * serialised by the caller. */
+int cb_dense_spd_inverse_noalloc(int32_t n, int32_t batch, int32_t precision, const double* A, double* Ainv);
+
 const char* cb_last_error(void);
 void cb_destroy(cb_ctx* c);
 

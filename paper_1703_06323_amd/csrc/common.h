@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace cutbddc {
 
@@ -63,6 +64,9 @@ __host__ __device__ inline int pack_index(int a, int b) {
   int c = a < b ? b : a;
   return r * 8 - (r * (r - 1)) / 2 + (c - r);
 }
+
+// Records msg as the thread's last error (cb_last_error) and returns code.
+int report_error(int code, const std::string& msg);
 
 // ---- launchers (defined in the .hip files) --------------------------------
 // integrate.hip (cells: concatenated cell space of n_cells_total entries)

@@ -1944,3 +1944,7 @@ void cb_destroy(cb_ctx* c) {
 }
 
 }  // extern "C"
+
+namespace cutbddc {
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace cutbddc

@@ -33,6 +33,9 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode);
 // range may be smaller).  Blocks start at 0 and, when a split point is
 // given, again at the split (so that the two diagonal ranges [0, split) and
 // [split, n) are unions of whole blocks).
+// With false, gemm() on the calling thread never runs the autotuner (which
+// allocates its test operands): shapes not tuned yet use the default tile.
+void gemm_set_thread_tuning(bool on);
 constexpr int DB = 128;
 inline int diag_blocks(int n, int split) {
   if (split <= 0 || split >= n) return (n + DB - 1) / DB;

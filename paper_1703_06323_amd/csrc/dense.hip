@@ -976,6 +976,11 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
 template <typename T>
 int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace);
 
+namespace {
+thread_local bool t_tuning = true;   // may gemm() tune an unseen shape on this thread
+}
+void gemm_set_thread_tuning(bool on) { t_tuning = on; }
+
 template <typename T>
 void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
           int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
@@ -990,7 +995,8 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
     auto it = g_tune.find(tune_key<T>(TA, TB, M, N, K, batch, mode, inplace));
     if (it != g_tune.end()) shape = it->second;
   }
-  if (shape < 0 && autotune_enabled()) shape = gemm_autotune_impl<T>(TA, TB, M, N, K, batch, mode, inplace);
+  if (shape < 0 && autotune_enabled() && t_tuning)
+    shape = gemm_autotune_impl<T>(TA, TB, M, N, K, batch, mode, inplace);
   if (shape < 0) {
     shape = 0;
     if (inplace == IN_PLACE_A) shape = N > 64 ? 2 : 0;
