@@ -14,6 +14,7 @@ the reading taken is stated in the function's docstring.
 Modules
   geometry   sub-cell Gauss points, kept-point test, cell classification (Sect. 2.1)
   integrate  cut-cell element stiffness / mass (Sect. 2.2, A_e with Gamma_D = 0)
+  surface    Nitsche terms on the ball surfaces and beta_e (Sect. 2.2, eq. local-eigenvals)
   assemble   DOF numbering, global operator and load (Sect. 2.2)
   topology   subdomains, node subdomain sets, objects, variant-1 splitting,
              coarse numbering (Sects. 3.1, 3.2, 4.4)
@@ -25,5 +26,5 @@ Modules
 
 Parity pins for each function live in tests/test_oracle_*.py.
 """
-from . import geometry, integrate, assemble, topology, bddc, pcg, adjoint  # noqa: F401
+from . import geometry, integrate, surface, assemble, topology, bddc, pcg, adjoint  # noqa: F401
 from .driver import OracleSolver  # noqa: F401

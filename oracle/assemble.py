@@ -8,6 +8,9 @@ Readings taken:
     numbered in ascending order of g = I + (N+1)(J + (N+1) K).
   * b = M_cut f: the source is the Q1 field with the given nodal values on
     all (N+1)^3 grid nodes, integrated with the kept-point rule.
+  * With cut_boundary = 1 the ball surfaces carry homogeneous Dirichlet
+    data imposed by Nitsche's method (module `surface`): the cut cells'
+    unit stiffness gains the surface terms, the load is unchanged.
   * A connected set of active cells (joined through shared DOF nodes) that
     touches no Dirichlet node leaves A-bar singular; such meshes are rejected.
 """
@@ -79,6 +82,11 @@ def discretise(problem, check_floating: bool = True, count=None) -> Discretisati
         keep = keep_masks(problem, active[sl])
         Kunit[sl] = integrate.unit_stiffness(keep)
         Munit[sl] = integrate.unit_mass(keep)
+    if getattr(problem, "cut_boundary", 0) == 1 and not problem.full_elements and cut.size:
+        # weak Dirichlet data on the ball surfaces (Nitsche, Sect. 2.2)
+        from . import surface
+        pos = np.searchsorted(active, cut)
+        Kunit[pos], _ = surface.nitsche_unit_stiffness(problem, Kunit[pos], cut)
     nodes = integrate.cell_nodes(n, active)
 
     # DOFs: interior grid nodes touched by an active cell (Sect. 5.1: strong
