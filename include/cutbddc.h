@@ -12,8 +12,9 @@
  *   - Preconditioner: M = I0 A0^-1 I0^T + Q A~^-1 Q^T, Q = E W (eq. bddc),
  *     coarse DOFs = object means (eq. coarse-dofs), BDDC(cef) or BDDC(ce),
  *     topological (eq. weighting) or stiffness (eq. alge-weighting) weights,
- *     standard objects (Sect. 3.2) or variant 1 (cut coarse edges split,
- *     Sect. 4.4).
+ *     standard objects (Sect. 3.2), variant 1 (cut coarse edges split,
+ *     Sect. 4.4) or variant 2 (coarse edges split where the stiffness
+ *     weighting coefficient changes, Sect. 4.5).
  *   - Solver: PCG with |r|_2 < rtol |b|_2 (Sect. 5.1).
  *
  * Conventions for every entry point:
@@ -52,7 +53,7 @@ enum cb_status {
 
 enum cb_weighting { CB_W_CARDINALITY = 0, CB_W_STIFFNESS = 1 };
 enum cb_objects { CB_OBJ_CEF = 0, CB_OBJ_CE = 1 };
-enum cb_variant { CB_CV_STANDARD = 0, CB_CV_V1 = 1 };
+enum cb_variant { CB_CV_STANDARD = 0, CB_CV_V1 = 1, CB_CV_V2 = 2 };
 enum cb_precision { CB_FP64 = 0, CB_FP32_LOCAL = 1 };
 
 typedef struct {
@@ -91,6 +92,8 @@ typedef struct {
   double t_topology_ms;
   double t_factor_ms;
   double t_solve_ms;
+  int64_t sum_nGnC;            /* sum over subdomains of n_G * (coarse DOFs touching it)  */
+  int64_t n_nodes;             /* grid nodes (N+1)^3, summed over problems                */
 } cb_info;
 
 typedef struct cb_ctx cb_ctx;
@@ -232,6 +235,8 @@ int cb_export_coarse(const cb_ctx* c, double* Ac);
  * objects (Sect. 3.2), variant-1 splitting (Sect. 4.4) and coarse numbering
  * built from given per-cell kept-point counts cell_count [N^3] (> 0 means
  * active), exactly as cb_setup does after its classification kernel.
+ * Variant 2 is not available here (it needs the integrated cut cells):
+ * CB_ERR_ARG.
  * info receives n_dof, n_sub, n_coarse, n_objects, n_iface; call once with
  * NULL arrays to size them, then again to fill (layouts as in
  * cb_export_indexing).  Errors: CB_ERR_ARG, CB_ERR_SINGULAR. */

@@ -26,6 +26,16 @@ Readings taken (the paper gives no algorithm for these steps):
     against the balls: interior (t in Omega) if every ball is at distance
     > r from t, exterior (t misses Omega) if the closed chords of the balls
     cover t, cut otherwise.  Sub-edges of one DOF become corners.
+  * Variant 2 (Sect. 4.5) applies with the stiffness weighting: the
+    weighting coefficient of an interface DOF xi is the vector of its
+    weights A^w_xixi / sum_{w' in S} A^w'_xixi over w in S (eq.
+    alge-weighting), each A^w_xixi summed over the active cells of w that
+    contain xi in ascending cell order.  Two DOFs of an edge object joined by
+    one of its links have the same coefficient when every component differs
+    by at most V2_TOL; edges are re-aggregated through such links only, and
+    a DOF left alone becomes a corner.  Faces and corners are unchanged.  With
+    the topological weighting every coefficient on an object is 1/|S|, so
+    variant 2 leaves the standard objects.
   * The mean value of eq. coarse-dofs is the equal-weight nodal mean
     1/|lambda| sum_{xi in lambda} u(xi) (a row scaling of the constraint,
     which leaves the BDDC space unchanged).
@@ -40,6 +50,9 @@ import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components
 
 CORNER, EDGE, FACE = 0, 1, 2
+# Variant 2: "the same weighting coefficient, up to machine precision"
+# (Sect. 4.5); coefficients lie in [0, 1].
+V2_TOL = 1e-12
 
 
 @dataclass
@@ -140,6 +153,40 @@ def segment_class(n, node_lo, axis, centres, radii):
         if cur >= b:
             return 1
     return 2
+
+
+def stiffness_coefficients(problem, d, S_ptr, S_ids, sub_all):
+    """Weighting coefficients of eq. alge-weighting per interface DOF: a dict
+    DOF -> array over S(xi) (ascending subdomains) of A^w_xixi / sum_{w'}
+    A^w'_xixi, with A^w_xixi = sum of kappa_e h K_e[a, a] over the active
+    cells e of w containing xi, in ascending cell order."""
+    n, h = problem.n, 1.0 / problem.n
+    pos = np.full(n ** 3, -1, dtype=np.int64)
+    pos[d.active] = np.arange(d.active.size)
+    n1 = n + 1
+    out = {}
+    for dof in np.flatnonzero(np.diff(S_ptr) >= 2):
+        node = int(d.dof_node[dof])
+        I, J, K = node % n1, (node // n1) % n1, node // (n1 * n1)
+        S = S_ids[S_ptr[dof]:S_ptr[dof + 1]]
+        diag = np.zeros(S.size)
+        for w in (0, 1):                 # cells in ascending id: k, then j, then i
+            for v in (0, 1):
+                for u in (0, 1):
+                    ci, cj, ck = I - 1 + u, J - 1 + v, K - 1 + w
+                    if min(ci, cj, ck) < 0 or max(ci, cj, ck) >= n:
+                        continue
+                    c = ci + n * (cj + n * ck)
+                    if pos[c] < 0:
+                        continue
+                    a = (1 - u) + 2 * (1 - v) + 4 * (1 - w)     # the node's corner in the cell
+                    t = int(np.flatnonzero(S == sub_all[c])[0])
+                    diag[t] += d.kappa[c] * h * d.Kunit[pos[c], a, a]
+        tot = 0.0
+        for t in range(S.size):
+            tot += diag[t]
+        out[int(dof)] = diag / tot
+    return out
 
 
 def build(problem, d) -> Topology:
@@ -309,6 +356,30 @@ def build(problem, d) -> Topology:
             nc, lab2 = connected_components(Gs, directed=False)
             for c in range(nc):
                 part = np.sort(rest[lab2 == c])
+                new.append((part, CORNER if part.size == 1 else EDGE))
+        objs = new
+
+    # ---- variant 2: split edges with non-constant weighting coefficients ------
+    if problem.coarse_variant == 2 and problem.weighting == 1:
+        coef = stiffness_coefficients(problem, d, S_ptr, S_ids, sub_all)
+        link_obj = obj_of[li]
+        new = []
+        for o, (dofs, typ) in enumerate(objs):
+            if typ != EDGE:
+                new.append((dofs, typ))
+                continue
+            sel = np.flatnonzero(link_obj == o)
+            pos = {x: t for t, x in enumerate(dofs.tolist())}
+            ra, rb = [], []
+            for e in sel:
+                a, b = int(li[e]), int(lj[e])
+                if np.max(np.abs(coef[a] - coef[b])) <= V2_TOL:
+                    ra.append(pos[a])
+                    rb.append(pos[b])
+            Gs = sp.coo_matrix((np.ones(len(ra)), (ra, rb)), shape=(dofs.size, dofs.size))
+            nc, lab2 = connected_components(Gs, directed=False)
+            for c in range(nc):
+                part = np.sort(dofs[lab2 == c])
                 new.append((part, CORNER if part.size == 1 else EDGE))
         objs = new
 

@@ -43,7 +43,16 @@ struct BatchDev {
   const int64_t* cell_off;   // [P+1]
   const int64_t* node_off;   // [P+1]
   const int32_t* active;     // [P] problems whose PCG still runs, or null (all)
+  // Work items of the matrix-free operator: the blocks of SEG_ALIGN nodes;
+  // problem p owns items [op_off[p], op_off[p+1]) = node_off / SEG_ALIGN,
+  // op_prob[item] = p.  op_lx, op_lc: lengths of the LDS ranges of x and of
+  // the cell data per block (SEG_ALIGN + 2 (N+1) + 2 and 2 SEG_ALIGN + 2 N +
+  // 2 for the largest N of the context).
+  const int32_t* op_off;     // [P+1]
+  const int32_t* op_prob;    // [items]
+  int32_t op_lx, op_lc;
 };
+
 
 // Largest p in [0, P) with off[p] <= i (off ascending, off[0] = 0).
 template <typename I>
@@ -76,11 +85,18 @@ void launch_integrate_cut(hipStream_t st, const BatchDev& b, const double* xi, c
                           const int64_t* cut_cells, int64_t n_cut, double* Kc, double* Mc);
 // operator.hip (nodes: concatenated node space of nn entries)
 void set_reference_matrices(const double* Kref, const double* Mref);
-// y = A x on the node space; with dpart, dpart[block] = the block's part of
-// x.y (blocks of SEG_ALIGN nodes, numbered over the whole node space).
-void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
-                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x,
+// Raises the operator kernel's dynamic LDS limit (call outside stream
+// capture, before its first launch); 0 on success.
+int prepare_apply_A();
+// y = A x on the node space (n_items = b.op_off[P] work items); with dpart,
+// dpart[item] = the work item's part of x.y.
+// Kf: the cut cells' unit stiffness as full row-major 8x8 matrices
+// (launch_expand_rows).
+void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, int32_t n_items, const int32_t* cellinfo,
+                    const double* kappa, const double* Kf, const uint8_t* dofmask, const double* x,
                     double* y, double* dpart = nullptr);
+// Kf[e] (64 values, row-major) = the packed matrix Kc[e] (36 values), for n cut cells.
+void launch_expand_rows(hipStream_t st, int64_t n_cut, const double* Kc, double* Kf);
 // b = M_cut f.  f is read per problem from f_ptrs[p] (local node numbering;
 // a null entry means f = 1) when f_ptrs is given, else from the
 // concatenated vector f.  outmask null: every node of a segment is written.
@@ -119,8 +135,8 @@ void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int3
 void launch_cg_check(hipStream_t st, int P, const int64_t* node_off, const double* rr_part, const double* params,
                      double* S, int32_t* active, int32_t* it, int32_t* status, double* relres, int32_t* n_active,
                      int32_t* nact_host);
-// x, r update (alpha = S[3] / p.q, p.q = sum of the problem's block parts
-// pq_part, stored in slot 1); the block parts of the new r.r go to rr_part;
+// x, r update (alpha = S[3] / p.q, p.q = sum of the problem's work-item
+// parts pq_part of the operator, stored in slot 1); the block parts of the new r.r go to rr_part;
 // zero1 and zero2 (may be null) are cleared on the same nodes.
 void launch_cg_update_xr(hipStream_t st, const BatchDev& b, int64_t nn, double* S, const double* pq_part,
                          const double* p, const double* q, double* x, double* r, double* zero1, double* zero2,

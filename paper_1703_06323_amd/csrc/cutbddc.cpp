@@ -276,13 +276,16 @@ struct cb_ctx {
   int n_fallbacks = 0;
 
   // per-problem device tables
+  DevBuf kdiag_d;            // diagonal of the uncut reference stiffness (variant 2)
+  DevBuf op_off_d, op_prob_d;   // operator work items (BatchDev::op_off, op_prob)
+  int32_t op_items = 0, op_lx = 0, op_lc = 0;
   DevBuf prob_d, cell_off_d, node_off_d, sub_off_d, dof_off_d, chunk_ptr_d, prow_off_d, coarse_prob_d, sub_prob_d,
       sub_blk_d;
   // device indexing work arrays (kept for the index export)
   DevBuf iwork;
   IndexWork iw{};
   // grid data (concatenated)
-  DevBuf xi_d, balls, kappa, count_d, cellinfo, cut_d, Kc, Mc, dofmask, dof_node;
+  DevBuf xi_d, balls, kappa, count_d, cellinfo, cut_d, Kc, Mc, Kf, dofmask, dof_node;
   // subdomain index data
   int NIp = 0, NGp = 0, NCp = 0, nt = 0;
   DevBuf nI, nG, nC, Iidx, Gidx, Gobj, Cids, bloc, if_ptr, if_sub, if_slot, iface_node, cs_ptr, cs_sub,
@@ -342,6 +345,10 @@ struct cb_ctx {
     b.cell_off = cell_off_d.as<int64_t>();
     b.node_off = node_off_d.as<int64_t>();
     b.active = masked ? active.as<int32_t>() : nullptr;
+    b.op_off = op_off_d.as<int32_t>();
+    b.op_prob = op_prob_d.as<int32_t>();
+    b.op_lx = op_lx;
+    b.op_lc = op_lc;
     return b;
   }
   GridDev grid() const {
@@ -409,8 +416,8 @@ void timed(cb_ctx* c, const char* name, F&& f) {
 
 int apply_A_grid(cb_ctx* c, const double* x, double* y, bool masked, double* dpart = nullptr) {
   ProfScope ps(c, "apply_A");
-  launch_apply_A(c->st, c->batch(masked), c->nn, c->cellinfo.as<int32_t>(), c->kappa.as<double>(),
-                 c->Kc.as<double>(), c->dofmask.as<uint8_t>(), x, y, dpart);
+  launch_apply_A(c->st, c->batch(masked), c->nn, c->op_items, c->cellinfo.as<int32_t>(), c->kappa.as<double>(),
+                 c->Kf.as<double>(), c->dofmask.as<uint8_t>(), x, y, dpart);
   return CB_OK;
 }
 
@@ -618,7 +625,7 @@ int validate_problem(const cb_problem* p) {
   if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
     return fail(CB_ERR_ARG, "invalid ball arrays");
   if (p->weighting < 0 || p->weighting > 1 || p->objects < 0 || p->objects > 1 || p->coarse_variant < 0 ||
-      p->coarse_variant > 1 || p->local_precision < 0 || p->local_precision > 1)
+      p->coarse_variant > 2 || p->local_precision < 0 || p->local_precision > 1)
     return fail(CB_ERR_ARG, "invalid option value");
   for (int i = 0; i < p->n_balls; ++i) {
     if (!(p->ball_radii[i] > 0.0) || !std::isfinite(p->ball_radii[i]))
@@ -778,6 +785,22 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   for (int k = 0; k < P; ++k) sub_offs[k] = c->pb[k].sub_off;
   sub_offs[P] = c->ns;
   CHK(upload(c->sub_off_d, sub_offs, st));
+  // operator work items: the node blocks of every problem
+  {
+    std::vector<int32_t> op_offs(P + 1, 0), op_prob((size_t)(c->nn / SEG_ALIGN));
+    int maxN = 1;
+    for (int k = 0; k < P; ++k) {
+      op_offs[k + 1] = (int32_t)(node_offs[k + 1] / SEG_ALIGN);
+      for (int32_t it = op_offs[k]; it < op_offs[k + 1]; ++it) op_prob[it] = k;
+      maxN = std::max(maxN, c->pb[k].N);
+    }
+    c->op_items = op_offs[P];
+    c->op_lx = SEG_ALIGN + 2 * (maxN + 1) + 2;
+    c->op_lc = 2 * SEG_ALIGN + 2 * maxN + 2;
+    CHK(upload(c->op_off_d, op_offs, st));
+    CHK(upload(c->op_prob_d, op_prob, st));
+    if (prepare_apply_A() != 0) return fail(CB_ERR_DEVICE, "setting the operator kernel's LDS limit failed");
+  }
   const int64_t nn = c->nn, ncell = c->n_cells_tot;
   const int ns = c->ns;
   CHK(dalloc(c->count_d, ncell * sizeof(int32_t)));
@@ -816,13 +839,36 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->cut_d, ncell * sizeof(int64_t)));
   launch_index_cells(st, c->batch(false), ncell, c->count_d.as<int32_t>(), c->full_elements ? 0 : 1, c->iw,
                      c->cellinfo.as<int32_t>(), c->cut_d.as<int64_t>());
+  // Variant 2 compares weighting coefficients built from the cut-cell
+  // matrices, so those are integrated before the node passes (one extra
+  // readback: the number of stored cut cells); otherwise after them.
+  const bool integrate_first = c->variant == 2;
+  auto integrate = [&](int64_t n_cut) -> int {
+    CHK(dalloc(c->Kc, std::max<int64_t>(1, n_cut) * PACK36 * sizeof(double)));
+    CHK(dalloc(c->Mc, std::max<int64_t>(1, n_cut) * PACK36 * sizeof(double)));
+    launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),
+                         n_cut, c->Kc.as<double>(), c->Mc.as<double>());
+    HIPCHK(hipGetLastError());
+    return CB_OK;
+  };
+  if (integrate_first) {
+    Count4 tot{};
+    HIPCHK(hipMemcpyAsync(&tot, c->iw.seg_cells + P, sizeof(Count4), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    CHK(integrate(tot.z));
+    std::vector<double> kd(8);
+    for (int a = 0; a < 8; ++a) kd[a] = c->Kref[a * 8 + a];
+    CHK(upload(c->kdiag_d, kd, st));
+  }
+  const V2Inputs v2in{c->weighting == CB_W_STIFFNESS ? 1 : 0, c->cellinfo.as<int32_t>(), c->kappa.as<double>(),
+                      c->Kc.as<double>(), c->kdiag_d.as<double>()};
   CHK(dalloc(c->dofmask, nn));
   CHK(dalloc(c->dof_node, nn * sizeof(int64_t)));
   CHK(dalloc(c->nI, (size_t)ns * sizeof(int32_t)));
   CHK(dalloc(c->nG, (size_t)ns * sizeof(int32_t)));
   CHK(dalloc(c->nC, (size_t)ns * sizeof(int32_t)));
   launch_index_nodes(st, c->batch(false), ncell, nn, ns, c->sub_off_d.as<int32_t>(), c->count_d.as<int32_t>(),
-                     c->balls.as<double>(), c->variant, c->objects, c->iw, c->dofmask.as<uint8_t>(),
+                     c->balls.as<double>(), c->variant, c->objects, v2in, c->iw, c->dofmask.as<uint8_t>(),
                      c->dof_node.as<int64_t>(), c->nI.as<int32_t>(), c->nG.as<int32_t>(), c->nC.as<int32_t>());
   HIPCHK(hipGetLastError());
   char* stage = static_cast<char*>(t_stage.get(small_bytes + 3 * (size_t)ns * sizeof(int32_t) + 256));
@@ -976,11 +1022,10 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   HIPCHK(hipEventRecord(eb, st));
 
   // cut-cell integration
-  CHK(dalloc(c->Kc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
-  CHK(dalloc(c->Mc, std::max<int64_t>(1, c->n_cut_tot) * PACK36 * sizeof(double)));
-  launch_integrate_cut(st, c->batch(false), c->xi_d.as<double>(), c->balls.as<double>(), c->cut_d.as<int64_t>(),
-                       c->n_cut_tot, c->Kc.as<double>(), c->Mc.as<double>());
-  HIPCHK(hipGetLastError());
+  if (!integrate_first) CHK(integrate(c->n_cut_tot));
+  // full row-major copies of the cut cells' stiffness for the operator
+  CHK(dalloc(c->Kf, std::max<int64_t>(1, c->n_cut_tot) * 64 * sizeof(double)));
+  launch_expand_rows(st, c->n_cut_tot, c->Kc.as<double>(), c->Kf.as<double>());
   HIPCHK(hipEventRecord(e1, st));
 
   std::vector<int64_t> dof_offs(P + 1), prow_offs(P + 1);
@@ -1007,7 +1052,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->tcvec, (size_t)std::max(1, c->nc_tot) * sizeof(double)));
   CHK(dalloc(c->partial, (size_t)std::max(1, c->n_chunks) * sizeof(double)));
   const size_t n_blk = std::max<size_t>(1, (size_t)((c->nn + SEG_ALIGN - 1) / SEG_ALIGN));
-  CHK(dalloc(c->pq_part, n_blk * sizeof(double)));
+  CHK(dalloc(c->pq_part, (size_t)std::max(1, c->op_items) * sizeof(double)));
   CHK(dalloc(c->rr_part, n_blk * sizeof(double)));
   CHK(dalloc(c->scal, (size_t)P * CG_S * sizeof(double)));
   CHK(dalloc(c->params, 2 * sizeof(double)));
@@ -1058,6 +1103,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
       in.sum_nG2 += (int64_t)nGh[b] * nGh[b];
       in.sum_nI += nIh[b];
       in.sum_nG += nGh[b];
+      in.sum_nGnC += (int64_t)nGh[b] * nCh[b];
       in.flops_local_chol += (nI + nG) * (nI + nG) * (nI + nG) / 3.0 + nI * nI * nI / 3.0;
     }
     in.max_local_dofs = ml;
@@ -1075,6 +1121,9 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     tot.sum_nG2 += in.sum_nG2;
     tot.sum_nI += in.sum_nI;
     tot.sum_nG += in.sum_nG;
+    tot.sum_nGnC += in.sum_nGnC;
+    in.n_nodes = (int64_t)(h.N + 1) * (h.N + 1) * (h.N + 1);
+    tot.n_nodes += in.n_nodes;
     tot.flops_local_chol += in.flops_local_chol;
   }
   tot.max_local_dofs = maxl;
@@ -1382,6 +1431,9 @@ int cb_host_indexing(const cb_problem* p, const int32_t* cell_count, cb_info* in
   if (N < 1 || s < 1 || N % s != 0) return fail(CB_ERR_ARG, "n_cells must be >= 1 and divisible by sub_cells");
   if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
     return fail(CB_ERR_ARG, "invalid ball arrays");
+  if (p->coarse_variant < 0 || p->coarse_variant > 1)
+    return fail(CB_ERR_ARG, "host indexing supports the standard objects and variant 1 (variant 2 needs the "
+                            "integrated cut cells of cb_setup)");
   Geometry geo;
   geo.N = N;
   geo.s = s;

@@ -55,16 +55,32 @@ int64_t index_scan_blocks(int64_t n);
 void launch_index_cells(hipStream_t st, const BatchDev& b, int64_t n_cells_total, const int32_t* count,
                         int store_cut, const IndexWork& w, int32_t* cellinfo, int64_t* cut_cells);
 
+// Inputs of the variant-2 split (Sect. 4.5): the cell data and integrated
+// cut-cell matrices, and the diagonal of the uncut reference stiffness
+// (device, 8 values); stiffness = 0 (topological weights, constant on every
+// object) leaves the standard objects.
+struct V2Inputs {
+  int stiffness;
+  const int32_t* cellinfo;
+  const double* kappa;
+  const double* Kc;
+  const double* kdiag;
+};
+// "The same weighting coefficient, up to machine precision" (Sect. 4.5):
+// coefficients lie in [0, 1].
+constexpr double V2_TOL = 1e-12;
+
 // Node passes up to the per-subdomain counts: DOFs, S sets, the floating
 // check, objects, variant 1 (variant = 1; problems without balls have no
-// cut FE edges), coarse
-// selection (objects = 0: every object; 1: corners and edges).  Writes
+// cut FE edges) or variant 2 (variant = 2: the cell info and cut-cell
+// matrices of v2 must be complete), coarse selection (objects = 0: every
+// object; 1: corners and edges).  Writes
 // dofmask [nn], dof_node [n_dof] (global node ids; sized nn), and per
 // subdomain nI, nG, nC.
 void launch_index_nodes(hipStream_t st, const BatchDev& b, int64_t n_cells_total, int64_t nn, int ns,
                         const int32_t* sub_off, const int32_t* count, const double* balls, int variant, int objects,
-                        const IndexWork& w, uint8_t* dofmask, int64_t* dof_node, int32_t* nI, int32_t* nG,
-                        int32_t* nC);
+                        const V2Inputs& v2, const IndexWork& w, uint8_t* dofmask, int64_t* dof_node, int32_t* nI,
+                        int32_t* nG, int32_t* nC);
 
 // Per-subdomain index maps with padded sizes NIp, NGp, NCp (see SubDev) and
 // the interface / coarse lists:

@@ -645,6 +645,77 @@ __global__ __launch_bounds__(IT) void v1_classify_kernel(BatchDev b, int64_t nn,
   if (add) link[n] = (uint8_t)(L | add);
 }
 
+// ---- variant 2 (Sect. 4.5) -------------------------------------------------
+// Weighting coefficients of the interface node (I, J, K) with S-mask mask:
+// W[t] = A^w_xixi / sum_{w' in S} A^w'_xixi for the t-th subdomain w of S
+// (eq. alge-weighting), A^w_xixi = sum of kappa_e h K_e[a, a] over the active
+// cells e of w around the node in ascending cell order; returns |S|.
+__device__ inline int v2_coefficients(const ProbDev& d, uint32_t mask, int I, int J, int K,
+                                      const int32_t* __restrict__ cellinfo, const double* __restrict__ kappa,
+                                      const double* __restrict__ Kc, const double* __restrict__ kdiag,
+                                      double W[8]) {
+  const int N = d.N, s = d.s;
+  const int bx0 = (I - 1) / s, by0 = (J - 1) / s, bz0 = (K - 1) / s;
+  const int card = __popc(mask);
+  double D[8];
+  for (int t = 0; t < 8; ++t) D[t] = 0.0;
+  for (int w = 0; w < 2; ++w)
+    for (int v = 0; v < 2; ++v)
+      for (int u = 0; u < 2; ++u) {
+        const int ci = I - 1 + u, cj = J - 1 + v, ck = K - 1 + w;
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= N || cj >= N || ck >= N) continue;
+        const int64_t c = d.cell_off + ci + (int64_t)N * (cj + (int64_t)N * ck);
+        const int32_t info = cellinfo[c];
+        if (info == CELL_INACTIVE) continue;
+        const int a = (1 - u) + 2 * (1 - v) + 4 * (1 - w);   // the node's corner in the cell
+        const int bit = (ci / s - bx0) + 2 * (cj / s - by0) + 4 * (ck / s - bz0);
+        const int t = __popc(mask & ((1u << bit) - 1u));
+        const double kd = info == CELL_UNCUT ? kdiag[a] : Kc[(int64_t)info * PACK36 + pack_index(a, a)];
+        D[t] += kappa[c] * d.h * kd;
+      }
+  double tot = 0.0;
+  for (int t = 0; t < card; ++t) tot += D[t];
+  for (int t = 0; t < card; ++t) W[t] = D[t] / tot;
+  return card;
+}
+
+// Variant 2: a link of a pass-1 edge object whose two DOFs have different
+// weighting coefficients (some component differs by more than V2_TOL) is
+// marked cut, so that the second join aggregates only equal neighbours.
+__global__ __launch_bounds__(IT) void v2_classify_kernel(BatchDev b, int64_t nn, const int32_t* __restrict__ cellinfo,
+                                                         const double* __restrict__ kappa,
+                                                         const double* __restrict__ Kc,
+                                                         const double* __restrict__ kdiag,
+                                                         const uint8_t* __restrict__ smask,
+                                                         const int32_t* __restrict__ par1,
+                                                         const int32_t* __restrict__ size1,
+                                                         const uint8_t* __restrict__ face, uint8_t* link) {
+  const int64_t n = (int64_t)blockIdx.x * IT + threadIdx.x;
+  if (n >= nn) return;
+  const uint32_t L = link[n];
+  if (!(L & 7u)) return;
+  const int32_t r = par1[n];
+  if (size1[r] < 2 || face[r]) return;   // not an edge object
+  NodePos q;
+  if (!node_pos(b, n, q)) return;
+  const ProbDev& d = b.prob[q.p];
+  const int64_t N1 = q.N + 1;
+  double Wa[8], Wb[8];
+  const int card = v2_coefficients(d, smask[n], q.I, q.J, q.K, cellinfo, kappa, Kc, kdiag, Wa);
+  uint32_t add = 0;
+  for (int axis = 0; axis < 3; ++axis) {
+    if (!(L >> axis & 1u)) continue;
+    const int64_t m = n + axis_step(axis, N1);
+    (void)v2_coefficients(d, smask[m], q.I + (axis == 0), q.J + (axis == 1), q.K + (axis == 2), cellinfo, kappa,
+                          Kc, kdiag, Wb);
+    bool same = true;
+    for (int t = 0; t < card; ++t)
+      if (!(fabs(Wa[t] - Wb[t]) <= V2_TOL)) same = false;
+    if (!same) add |= 8u << axis;
+  }
+  if (add) link[n] = (uint8_t)(L | add);
+}
+
 // Object kind at a final root r (pass-1 root r1 = par1[r]).
 __device__ inline int object_kind(int32_t r, const int32_t* size2, const int32_t* par1, const uint8_t* face) {
   if (size2[r] == 1) return KIND_CORNER;
@@ -853,8 +924,8 @@ void launch_index_cells(hipStream_t st, const BatchDev& b, int64_t n_cells_total
 
 void launch_index_nodes(hipStream_t st, const BatchDev& b, int64_t n_cells_total, int64_t nn, int ns,
                         const int32_t* sub_off, const int32_t* count, const double* balls, int variant, int objects,
-                        const IndexWork& w, uint8_t* dofmask, int64_t* dof_node, int32_t* nI, int32_t* nG,
-                        int32_t* nC) {
+                        const V2Inputs& v2, const IndexWork& w, uint8_t* dofmask, int64_t* dof_node, int32_t* nI,
+                        int32_t* nG, int32_t* nC) {
   const dim3 gn(grid_of(nn)), gc(grid_of(n_cells_total)), blk(IT);
   // DOFs and subdomain sets
   hipLaunchKernelGGL(smask_kernel, gn, blk, 0, st, b, nn, count, w.smask, dofmask);
@@ -876,11 +947,15 @@ void launch_index_nodes(hipStream_t st, const BatchDev& b, int64_t n_cells_total
   hipLaunchKernelGGL(compress_kernel, gn, blk, 0, st, nn, w.par1);
   hipLaunchKernelGGL(face_kernel, gc, blk, 0, st, b, n_cells_total, count, w.smask, w.par1, w.face);
   hipLaunchKernelGGL(object_size_kernel, gn, blk, 0, st, nn, w.smask, w.par1, w.size1);
-  // variant 1: cut FE edges of edge objects; then the final objects (without
-  // a split, the same links join the same sets)
+  // variant 1: cut FE edges of edge objects; variant 2 (stiffness weights
+  // only): links between DOFs of unequal weighting coefficients; then the
+  // final objects (without a split, the same links join the same sets)
   if (variant == 1)
     hipLaunchKernelGGL(v1_classify_kernel, gn, blk, 0, st, b, nn, balls, w.par1, w.size1, w.face, w.link,
                        w.cutdof);
+  if (variant == 2 && v2.stiffness)
+    hipLaunchKernelGGL(v2_classify_kernel, gn, blk, 0, st, b, nn, v2.cellinfo, v2.kappa, v2.Kc, v2.kdiag, w.smask,
+                       w.par1, w.size1, w.face, w.link);
   hipLaunchKernelGGL(iota_kernel, gn, blk, 0, st, nn, w.par2);
   hipLaunchKernelGGL(link_join_kernel, gn, blk, 0, st, b, nn, w.link, (const uint8_t*)w.cutdof, w.par2);
   hipLaunchKernelGGL(compress_kernel, gn, blk, 0, st, nn, w.par2);

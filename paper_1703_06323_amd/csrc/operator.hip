@@ -92,35 +92,134 @@ __device__ inline double wg_sum_range(const double* __restrict__ part, int64_t b
   return wg_sum_all(acc, sh);
 }
 
-// Node-space kernels run in blocks of SEG_ALIGN threads, so every block lies
-// inside one problem's node segment and finds it from its first node.
-__global__ __launch_bounds__(256) void apply_A_kernel(BatchDev bd, int64_t nn,
-                                                      const int32_t* __restrict__ cellinfo,
-                                                      const double* __restrict__ kappa,
-                                                      const double* __restrict__ Kc,
-                                                      const uint8_t* __restrict__ dofmask,
-                                                      const double* __restrict__ x,
-                                                      double* __restrict__ y, double* __restrict__ dpart) {
+// Workgroup b runs on XCD b % 8: renumber so that each XCD runs a
+// contiguous range of the G items (neighbouring blocks share their halo in
+// that XCD's L2).
+__device__ inline int32_t xcd_item(int32_t b, int32_t G) {
+  const int32_t xcd = b & 7, k = b >> 3, base = G >> 3, rem = G & 7;
+  return (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + k;
+}
+
+// Matrix-free A-bar x.  A workgroup takes a block of SEG_ALIGN consecutive
+// nodes of one problem (its problem read from op_prob, no search) and first
+// stages in LDS, with independent coalesced loads:
+//  * x on the three node ranges that hold the blocks' neighbours in the
+//    planes K-1, K, K+1: [l0 - N1 - 1, l1 + N1 + 1] + dz (N+1)^2;
+//  * cell info and kappa h of the cells around the block's nodes, on two
+//    ranges of the cell anchor a(l) = (I-1) + N (J-1) + N^2 (K-1) of a node:
+//    [amin, amin + op_lc) + w N^2 for the layers w = 0, 1.  Along l the
+//    anchor grows by one per node, stays at a row change and drops by N at
+//    a plane change, so it spans at most 255 + N (256 / (N+1)^2 + 1) <=
+//    511 + N over a block; amin is the smaller of a(l0) and the anchors of
+//    the plane starts inside the block.
+// Then each thread sums over the (up to 8) active cells around its node
+// kappa_e h (row a of the cell matrix) . x_e from LDS, in the same order as
+// the load's node gather; a cut cell's row comes from its full row-major
+// copy Kf (one 64-byte segment per row).  DOF nodes are the interior nodes next to an
+// active cell; every other node of the block gets 0.  Staged entries outside
+// the problem, and cells whose coordinates leave the grid, are never used.
+__global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t n_items,
+                                                            const int32_t* __restrict__ cellinfo,
+                                                            const double* __restrict__ kappa,
+                                                            const double* __restrict__ Kf,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y, double* __restrict__ dpart) {
+  extern __shared__ double op_lds[];
   __shared__ double sh[SEG_ALIGN / 64];
-  const int64_t base = (int64_t)blockIdx.x * SEG_ALIGN;
-  const int64_t n = base + threadIdx.x;
-  if (base >= nn) return;
-  const int p = find_segment(bd.node_off, bd.P, base);
+  const int32_t item = xcd_item((int32_t)blockIdx.x, n_items);
+  const int p = bd.op_prob[item];
   if (bd.active && !bd.active[p]) return;
-  double v = 0.0;
-  if (n < nn && dofmask[n]) {
-    const ProbDev pr = bd.prob[p];
-    const int N1 = pr.N + 1;
-    const int l = (int)(n - pr.node_off);
-    const int I = l % N1, J = (l / N1) % N1, K = l / (N1 * N1);
-    v = node_gather<false>(pr.N, I, J, K, cellinfo + pr.cell_off, kappa + pr.cell_off, Kc, x + pr.node_off,
-                           pr.h);
+  const ProbDev pr = bd.prob[p];
+  const int N = pr.N, N1 = N + 1, LX = bd.op_lx, LC = bd.op_lc;
+  const int64_t plane1 = (int64_t)N1 * N1, nodes = plane1 * N1, ncells = (int64_t)N * N * N;
+  const int64_t l0 = (int64_t)item * SEG_ALIGN - pr.node_off;          // first local node of the block
+  const int64_t l1 = min(l0 + SEG_ALIGN, nodes) - 1;                     // last node of the problem in it
+  double* xs = op_lds;                                                   // [3][LX]
+  double* ks = xs + 3 * LX;                                              // [2][LC] kappa h
+  int32_t* cs = reinterpret_cast<int32_t*>(ks + 2 * LC);                 // [2][LC] cell info
+  const double* xp = x + pr.node_off;
+  const int32_t* cip = cellinfo + pr.cell_off;
+  const double* kp = kappa + pr.cell_off;
+  const int64_t xb = l0 - N1 - 1;                                        // node of xs[1][0]
+  auto anchor = [&](int64_t l) {
+    const int I = (int)(l % N1), J = (int)((l / N1) % N1), K = (int)(l / plane1);
+    return (int64_t)(I - 1) + (int64_t)N * ((J - 1) + (int64_t)N * (K - 1));
+  };
+  int64_t cb = l0 < nodes ? anchor(l0) : 0;                              // cell of cs[0][0]
+  for (int64_t ps = (l0 / plane1 + 1) * plane1; ps <= l1; ps += plane1) cb = min(cb, anchor(ps));
+  if (l0 < nodes) {
+    for (int t = threadIdx.x; t < 3 * LX; t += SEG_ALIGN) {
+      const int dz = t / LX;
+      const int64_t g = xb + (t - dz * LX) + (int64_t)(dz - 1) * plane1;
+      xs[t] = (g >= 0 && g < nodes) ? xp[g] : 0.0;
+    }
+    for (int t = threadIdx.x; t < 2 * LC; t += SEG_ALIGN) {
+      const int w = t / LC;
+      const int64_t c = cb + (t - w * LC) + (int64_t)w * N * N;
+      const bool ok = c >= 0 && c < ncells;
+      cs[t] = ok ? cip[c] : CELL_INACTIVE;
+      ks[t] = ok ? kp[c] * pr.h : 0.0;
+    }
   }
-  if (n < nn) y[n] = v;
+  __syncthreads();
+  const int64_t l = l0 + threadIdx.x;
+  double v = 0.0, xv0 = 0.0;
+  if (l < nodes) {
+    const int I = (int)(l % N1), J = (int)((l / N1) % N1), K = (int)(l / plane1);
+    const int64_t xo = l - xb;                          // offset of the node itself in each x range
+    const int64_t co = anchor(l) - cb;                  // offset of its anchor cell in each cell range
+    xv0 = xs[LX + xo];
+    double acc = 0.0;
+    bool touched = false;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      if (K - 1 + w < 0 || K - 1 + w >= N) continue;
+#pragma unroll
+      for (int vv = 0; vv < 2; ++vv) {
+        if (J - 1 + vv < 0 || J - 1 + vv >= N) continue;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (I - 1 + u < 0 || I - 1 + u >= N) continue;
+          const int64_t cc = w * LC + co + u + (int64_t)N * vv;
+          const int32_t info = cs[cc];
+          if (info == CELL_INACTIVE) continue;
+          touched = true;
+          const int a = (1 - u) + 2 * (1 - vv) + 4 * (1 - w);   // the node's corner in the cell
+          double row = 0.0;
+          if (info == CELL_UNCUT) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+              const int dz = w + ((b >> 2) & 1), dy = vv + ((b >> 1) & 1), dx = u + (b & 1);
+              row += c_Kref[a * 8 + b] * xs[dz * LX + xo + (dx - 1) + (int64_t)N1 * (dy - 1)];
+            }
+          } else {
+            // row a of the cell's full matrix: 64 contiguous bytes
+            const double2* R = reinterpret_cast<const double2*>(Kf + (int64_t)info * 64 + a * 8);
+            double r8[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double2 v2 = R[q];
+              r8[2 * q] = v2.x;
+              r8[2 * q + 1] = v2.y;
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+              const int dz = w + ((b >> 2) & 1), dy = vv + ((b >> 1) & 1), dx = u + (b & 1);
+              row += r8[b] * xs[dz * LX + xo + (dx - 1) + (int64_t)N1 * (dy - 1)];
+            }
+          }
+          acc += ks[cc] * row;
+        }
+      }
+    }
+    const bool interior = I >= 1 && I < N && J >= 1 && J < N && K >= 1 && K < N;
+    v = (interior && touched) ? acc : 0.0;
+  }
+  // every node of the block, the alignment padding after the problem included
+  y[(int64_t)item * SEG_ALIGN + threadIdx.x] = v;
   if (dpart) {
-    // this block's part of x.y
-    const double t = wg_sum_all(n < nn ? x[n] * v : 0.0, sh);
-    if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+    const double t = wg_sum_all(xv0 * v, sh);
+    if (threadIdx.x == 0) dpart[item] = t;
   }
 }
 
@@ -213,7 +312,7 @@ __global__ void copy_kernel(int64_t n, const double* __restrict__ src, double* _
 
 // x += alpha p, r -= alpha q with alpha = rho / p.q of the node's problem
 // (rho = r.z of the latest preconditioned residual, slot 3; p.q from the
-// block parts of the operator kernel, also stored in slot 1); the block
+// work-item parts of the operator kernel, also stored in slot 1); the block
 // parts of the new r.r go to rr_part.  zero1 and zero2 (may be null) are
 // cleared on the same nodes (the preconditioner's scratch vectors, so that
 // they need no fill of their own).
@@ -229,9 +328,8 @@ __global__ __launch_bounds__(256) void cg_update_xr_kernel(BatchDev bd, int64_t 
   if (base >= nn) return;
   const int pb = find_segment(bd.node_off, bd.P, base);
   if (bd.active && !bd.active[pb]) return;
-  const int64_t b0 = bd.node_off[pb] / SEG_ALIGN, b1 = (bd.node_off[pb + 1] + SEG_ALIGN - 1) / SEG_ALIGN;
-  const double pq = wg_sum_range(pq_part, b0, b1, sh);
-  if ((int64_t)blockIdx.x == b0 && threadIdx.x == 0) S[CG_S * pb + 1] = pq;
+  const double pq = wg_sum_range(pq_part, bd.op_off[pb], bd.op_off[pb + 1], sh);
+  if (base == bd.node_off[pb] && threadIdx.x == 0) S[CG_S * pb + 1] = pq;
   const double alpha = S[CG_S * pb + 3] / pq;
   double rn = 0.0;
   if (i < nn) {
@@ -436,12 +534,34 @@ void set_reference_matrices(const double* Kref, const double* Mref) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_Mref), Mref, 64 * sizeof(double));
 }
 
-void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,
-                    const double* kappa, const double* Kc, const uint8_t* dofmask, const double* x, double* y,
+int prepare_apply_A() {
+  // 128 KB covers N up to 1024 (116 KB); the kernel's static LDS comes on top
+  static const hipError_t e = hipFuncSetAttribute((const void*)apply_A_kernel,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+  return e == hipSuccess ? 0 : -1;
+}
+
+__global__ void expand_rows_kernel(int64_t n, const double* __restrict__ Kc, double* __restrict__ Kf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * 64) return;
+  const int64_t e = i >> 6;
+  const int a = (int)((i >> 3) & 7), b = (int)(i & 7);
+  Kf[i] = Kc[e * PACK36 + pack_index(a, b)];
+}
+
+void launch_expand_rows(hipStream_t st, int64_t n_cut, const double* Kc, double* Kf) {
+  if (n_cut <= 0) return;
+  hipLaunchKernelGGL(expand_rows_kernel, dim3(nblocks(n_cut * 64, 256)), dim3(256), 0, st, n_cut, Kc, Kf);
+}
+
+void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, int32_t n_items, const int32_t* cellinfo,
+                    const double* kappa, const double* Kf, const uint8_t* dofmask, const double* x, double* y,
                     double* dpart) {
-  if (nn <= 0) return;
-  hipLaunchKernelGGL(apply_A_kernel, dim3(nblocks(nn, SEG_ALIGN)), dim3(SEG_ALIGN), 0, st, b, nn, cellinfo,
-                     kappa, Kc, dofmask, x, y, dpart);
+  (void)dofmask;
+  if (nn <= 0 || n_items <= 0) return;
+  const size_t sh = (size_t)(3 * b.op_lx + 2 * b.op_lc) * sizeof(double) + (size_t)2 * b.op_lc * sizeof(int32_t);
+  hipLaunchKernelGGL(apply_A_kernel, dim3((unsigned)n_items), dim3(SEG_ALIGN), sh, st, b, n_items, cellinfo, kappa,
+                     Kf, x, y, dpart);
 }
 
 void launch_load(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,

@@ -53,7 +53,7 @@ class cb_info(C.Structure):
                 ("sum_nI", C.c_int64), ("sum_nG", C.c_int64), ("flops_local_chol", C.c_double),
                 ("t_integrate_ms", C.c_double),
                 ("t_topology_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("sum_nGnC", C.c_int64), ("n_nodes", C.c_int64)]
 
 
 _lib = None
@@ -247,13 +247,7 @@ class Solver:
 
     def profile_launches(self, name: str) -> np.ndarray:
         """Durations (ms) of every bracketed launch of one kernel group."""
-        n = C.c_int64(0)
-        _check(_lib.cb_profile_launches(self.ctx, name.encode(), None, 0, C.byref(n)))
-        out = np.zeros(n.value, np.float64)
-        if n.value:
-            _check(_lib.cb_profile_launches(self.ctx, name.encode(), out.ctypes.data_as(C.c_void_p), n.value,
-                                            C.byref(n)))
-        return out
+        return _profile_launches(self.ctx, name)
 
     # -- host exports --------------------------------------------------------
     def export_indexing(self) -> dict:
@@ -340,6 +334,12 @@ class BatchSolver:
     def export_indexing(self, k: int) -> dict:
         return _export_indexing(self.ctx, int(k), self.ns[k], self.problem_info(k))
 
+    def profile(self, enable=True):
+        _check(_lib.cb_profile(self.ctx, 1 if enable else 0))
+
+    def profile_launches(self, name: str) -> np.ndarray:
+        return _profile_launches(self.ctx, name)
+
     def export_subdomains(self, k: int):
         return _export_subdomains(self.ctx, int(k), int(self.problem_info(k)["n_sub"]))
 
@@ -366,6 +366,15 @@ class BatchSolver:
                                  rel.ctypes.data_as(C.POINTER(C.c_double)))
         _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
         return outputs, it, rel
+
+
+def _profile_launches(ctx, name):
+    n = C.c_int64(0)
+    _check(_lib.cb_profile_launches(ctx, name.encode(), None, 0, C.byref(n)))
+    out = np.zeros(n.value, np.float64)
+    if n.value:
+        _check(_lib.cb_profile_launches(ctx, name.encode(), out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+    return out
 
 
 _INDEX_KEYS = ("cell_status", "cell_count", "dof_node", "card", "obj_ptr", "obj_dofs", "obj_type",

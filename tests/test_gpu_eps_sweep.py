@@ -1,7 +1,8 @@
 """The eps sweep of the single-ball problem (51 ball positions across one
 cell, Sect. 5.2) on the GPU, one batch of 51 problems per (weighting,
-coarse variant): FP64 iteration counts equal to the oracle's and solutions
-within 1e-10; the stiffness-weighted counts stay within one iteration."""
+coarse variant: standard, variant 1, variant 2): FP64 iteration counts
+equal to the oracle's and solutions within 1e-10; the stiffness-weighted
+counts stay within one iteration."""
 import numpy as np
 import pytest
 
@@ -17,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("weighting", [W.W_CARDINALITY, W.W_STIFFNESS])
-@pytest.mark.parametrize("variant", [W.CV_STANDARD, W.CV_V1])
+@pytest.mark.parametrize("variant", [W.CV_STANDARD, W.CV_V1, W.CV_V2])
 def test_eps_sweep_matches_oracle(weighting, variant):
     from paper_1703_06323_amd import BatchSolver
     probs = [W.single_ball(shift_x=float(e)).with_options(weighting=weighting, coarse_variant=variant)

@@ -24,6 +24,16 @@ from oracle import OracleSolver, topology
 
 pytestmark = pytest.mark.gpu
 
+def _kappa_layer0():
+    """kappa 10 in the bottom cell layer of subdomain 0 of an 8^3 mesh with
+    4^3-cell subdomains (variant 2 then splits one coarse edge)."""
+    k = np.ones(512)
+    for j in range(4):
+        for i in range(4):
+            k[i + 8 * j] = 10.0
+    return k
+
+
 CASES = {
     "single_ball_standard_cardinality": lambda: W.single_ball().with_options(weighting=0, coarse_variant=0),
     "single_ball_standard_stiffness": lambda: W.single_ball().with_options(coarse_variant=0),
@@ -34,6 +44,11 @@ CASES = {
     "uncut16_s4": lambda: W.uncut(16, 4),
     "one_subdomain": lambda: W.random_balls(8, 8, 3, 5),
     "full_elements": lambda: W.random_balls(16, 8, 5, 6).with_options(full_elements=1),
+    "single_ball_v2_stiffness": lambda: W.single_ball().with_options(coarse_variant=2),
+    "balls16_s4_v2": lambda: W.random_balls(16, 4, 6, 3).with_options(coarse_variant=2),
+    "balls24_s8_lognormal_v2": lambda: W.random_balls(24, 8, 8, 4, lognormal_kappa=True).with_options(
+        coarse_variant=2),
+    "uncut8_kappa_layer_v2": lambda: W.uncut(8, 4).with_options(coarse_variant=2, kappa=_kappa_layer0()),
 }
 
 _oracles = {}

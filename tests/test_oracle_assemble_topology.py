@@ -334,3 +334,139 @@ def test_load_on_cut_mesh_by_global_hats():
         fq = phi @ f
         expect += (h ** 3 / 512.0) * (phi * fq[:, None]).sum(axis=0)
     np.testing.assert_allclose(b, expect[d.dof_node], rtol=1e-13, atol=1e-16)
+
+
+# ---- variant 2 (Sect. 4.5): edges split where the weighting coefficient changes ----
+#
+# On an uncut 8^3 mesh with 2 x 2 x 2 blocks of 4^3 cells, every uncut cell
+# has the same diagonal stiffness entries, so a node's stiffness weight on
+# subdomain w is proportional to the sum of kappa over the cells of w that
+# contain it.  The nodes (4, 4, K), K = 1..3, form the coarse edge shared by
+# the four lower subdomains 0..3; node (4, 4, K) lies in the cell layers K-1
+# and K.  Raising kappa in one layer of subdomain 0's cells changes the
+# coefficients of the edge nodes that touch that layer and no others: the
+# expected objects below are the standard ones with that edge re-split by
+# hand.  No other edge node touches layers 0-2 of subdomain 0.
+
+def _kappa_layer(n, s, layer, value):
+    kap = np.ones(n ** 3)
+    for j in range(s):
+        for i in range(s):
+            kap[i + n * (j + n * layer)] = value
+    return kap
+
+
+def _objects_of(p):
+    d = assemble.discretise(p)
+    t = topology.build(p, d)
+    n1 = p.n + 1
+    got = {}
+    for o, dofs in enumerate(t.objects()):
+        nodes = d.dof_node[dofs]
+        key = frozenset((int(g % n1), int((g // n1) % n1), int(g // (n1 * n1))) for g in nodes)
+        got[key] = int(t.obj_type[o])
+    return d, t, got
+
+
+@pytest.mark.parametrize("layer,corners,edge", [
+    (0, [1], [2, 3]),     # (4,4,1) sees kappa 10 + 1, the others 1 + 1
+    (1, [3], [1, 2]),     # (4,4,1) and (4,4,2) both see 1 + 10; (4,4,3) sees 1 + 1
+    (2, [1], [2, 3]),     # (4,4,2) and (4,4,3) both see 10 + 1; (4,4,1) sees 1 + 1
+])
+def test_variant2_splits_edge_at_coefficient_changes(layer, corners, edge):
+    n, s = 8, 4
+    p = W.uncut(n, s).with_options(kappa=_kappa_layer(n, s, layer, 10.0), coarse_variant=2)
+    expect = _uncut_two_block_objects(n, s)
+    assert expect.pop(frozenset((4, 4, K) for K in (1, 2, 3))) == topology.EDGE
+    for K in corners:
+        expect[frozenset({(4, 4, K)})] = topology.CORNER
+    expect[frozenset((4, 4, K) for K in edge)] = topology.EDGE
+    d, t, got = _objects_of(p)
+    assert got == expect
+    assert t.n_coarse == len(expect)
+    # the standard objects of the same problem are the uncut two-block ones
+    _, _, got0 = _objects_of(p.with_options(coarse_variant=0))
+    assert got0 == _uncut_two_block_objects(n, s)
+
+
+def test_variant2_three_distinct_coefficients_give_three_corners():
+    """kappa 10 in layer 0 and 100 in layer 1 of subdomain 0: the nodes
+    (4,4,1), (4,4,2), (4,4,3) see 10 + 100, 100 + 1 and 1 + 1: all three
+    coefficients differ, so the edge becomes three corners."""
+    n, s = 8, 4
+    kap = _kappa_layer(n, s, 0, 10.0) * _kappa_layer(n, s, 1, 100.0)
+    p = W.uncut(n, s).with_options(kappa=kap, coarse_variant=2)
+    expect = _uncut_two_block_objects(n, s)
+    expect.pop(frozenset((4, 4, K) for K in (1, 2, 3)))
+    for K in (1, 2, 3):
+        expect[frozenset({(4, 4, K)})] = topology.CORNER
+    assert _objects_of(p)[2] == expect
+
+
+def test_variant2_is_standard_with_constant_coefficients():
+    """Topological weights are 1/|S| on every object, and on an uncut mesh
+    with constant kappa every edge node has two equal cells per subdomain:
+    in both cases variant 2 keeps the standard objects."""
+    cut = W.random_balls(16, 4, 6, 3)
+    for p in (cut.with_options(weighting=0), W.uncut(12, 4)):
+        _, t0, got0 = _objects_of(p.with_options(coarse_variant=0))
+        _, t2, got2 = _objects_of(p.with_options(coarse_variant=2))
+        assert got2 == got0
+
+
+def test_variant2_refines_the_standard_edges():
+    """On cut meshes with stiffness weights variant 2 only splits edges:
+    faces and corners are the standard ones, every new object lies in one
+    standard edge, and the objects still partition the interface."""
+    for p in (W.random_balls(16, 4, 6, 3), W.single_ball(), W.random_balls(24, 8, 10, 4)):
+        d, t0, got0 = _objects_of(p.with_options(coarse_variant=0))
+        _, t2, got2 = _objects_of(p.with_options(coarse_variant=2))
+        std_edges = [k for k, v in got0.items() if v == topology.EDGE]
+        for k, v in got2.items():
+            if k in got0 and got0[k] == v:
+                continue
+            assert v in (topology.CORNER, topology.EDGE)
+            assert sum(k <= e for e in std_edges) == 1
+        for k, v in got0.items():
+            if v != topology.EDGE:
+                assert got2.get(k) == v
+        assert np.array_equal(np.sort(t2.obj_dofs), np.flatnonzero(t2.card() >= 2))
+
+
+def test_variant2_counts_only_active_cells_of_each_subdomain():
+    """Cell (3, 3, 0) of subdomain 0 removed (hand-made cell data): node
+    (4, 4, 1) then lies in one active cell of subdomain 0 and two of each of
+    subdomains 1-3, (4, 4, 2) and (4, 4, 3) in two of each.  The standard
+    edge {(4,4,K)} stays whole (its links still lie in active cells of all
+    four subdomains); variant 2 makes (4, 4, 1) a corner."""
+    n, s = 8, 4
+    count = _counts(n, [(3, 3, 0)])
+    p = W.uncut(n, s).with_options(coarse_variant=2)
+    _, _, got0 = _oracle_objects(p.with_options(coarse_variant=0), count)
+    assert got0 == _uncut_two_block_objects(n, s)
+    _, _, got2 = _oracle_objects(p, count)
+    expect = _uncut_two_block_objects(n, s)
+    expect.pop(frozenset((4, 4, K) for K in (1, 2, 3)))
+    expect[frozenset({(4, 4, 1)})] = topology.CORNER
+    expect[frozenset({(4, 4, 2), (4, 4, 3)})] = topology.EDGE
+    assert got2 == expect
+
+
+@pytest.mark.parametrize("corner,splits", [(7, True), (0, False), (6, False)])
+def test_variant2_uses_the_nodes_own_diagonal_entry(corner, splits):
+    """Uncut 8^3 mesh; the diagonal entry K_e[corner, corner] of cell
+    (3, 3, 0) (subdomain 0) is tripled by hand in the discretisation.  Node
+    (4, 4, 1) is corner 7 of that cell (local node a = ix + 2 iy + 4 iz with
+    offsets (1, 1, 1)), so only corner 7 changes its coefficient and splits
+    the edge; corner 0 is node (3, 3, 0) on the cube face (not a DOF) and
+    corner 6 is node (3, 4, 1) of a face object (faces are never split)."""
+    n, s = 8, 4
+    p = W.uncut(n, s).with_options(coarse_variant=2)
+    d = assemble.discretise(p)
+    pos = int(np.searchsorted(d.active, 3 + n * (3 + n * 0)))
+    d.Kunit[pos, corner, corner] *= 3.0
+    t = topology.build(p, d)
+    n1 = n + 1
+    node1 = d.dof_of_node[4 + n1 * (4 + n1 * 1)]
+    o = [k for k, dofs in enumerate(t.objects()) if node1 in dofs][0]
+    assert (t.obj_type[o] == topology.CORNER) == splits

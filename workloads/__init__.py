@@ -27,6 +27,9 @@ OBJ_CEF = 0
 OBJ_CE = 1
 CV_STANDARD = 0
 CV_V1 = 1
+CV_V2 = 2
+CUT_NEUMANN = 0
+CUT_NITSCHE = 1
 FP64 = 0
 FP32_LOCAL = 1
 
@@ -47,6 +50,7 @@ class Problem:
     coarse_variant: int = CV_V1
     local_precision: int = FP64
     full_elements: int = 0      # test flag: every active cell integrated as uncut
+    cut_boundary: int = 0       # ball surfaces: 0 homogeneous Neumann, 1 homogeneous Dirichlet (Nitsche)
     name: str = ""
 
     def with_options(self, **kw) -> "Problem":
