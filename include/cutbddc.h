@@ -68,6 +68,9 @@ typedef struct {
   int32_t coarse_variant;      /* cb_variant                                              */
   int32_t local_precision;     /* cb_precision: subdomain factor/solves in FP64 or FP32   */
   int32_t full_elements;       /* test flag: integrate every active cell as uncut         */
+  int32_t cut_boundary;        /* ball surfaces: 0 homogeneous Neumann; 1 homogeneous     */
+                               /* Dirichlet imposed by Nitsche's method with beta_e =     */
+                               /* 2 lambda_max (Sect. 2.2, eq. local-eigenvals)           */
 } cb_problem;
 
 typedef struct {
@@ -135,6 +138,25 @@ int cb_grad(cb_ctx* c, const double* u_dev, const double* lam_dev,
 int cb_apply_operator(cb_ctx* c, const double* x_dev, double* y_dev);       /* y = A-bar x  */
 int cb_apply_preconditioner(cb_ctx* c, const double* r_dev, double* z_dev); /* z = M r      */
 int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev);           /* b = M_cut f  */
+
+/* Manufactured-solution accuracy (Sect. 5.1): the exact solution
+ * u = sin(k |x - x0|) (the paper takes k = 5 pi, x0 = the origin), with
+ * strong Dirichlet data u on the cube faces and, on the ball surfaces,
+ * Neumann data grad u . n (cut_boundary 0) or Dirichlet data u by Nitsche's
+ * method (cut_boundary 1).  Single-problem contexts whose kappa is 1.
+ * x0: host double[3].  Volume integrals use the kept points of the volume
+ * rule, surface integrals the sphere rule of the Nitsche terms.
+ * cb_manufactured_load: b_dev [n_dof] (device) = the load of f = -Lap u
+ *   plus the surface data, minus A-bar applied to the Dirichlet lift; solve
+ *   with cb_solve_rhs.
+ * cb_manufactured_errors: *l2, *h1 (host) = the L2 and H1-seminorm errors
+ *   of u_h = u_dev [n_dof] (device) plus the lift, over the kept points.
+ * Errors: CB_ERR_ARG (null pointer, non-finite x0 or k, a given kappa),
+ * CB_ERR_STATE (a batch context), CB_ERR_DEVICE / CB_ERR_OOM.  Both calls
+ * allocate work buffers and synchronise the stream. */
+int cb_manufactured_load(cb_ctx* c, const double* x0, double k, double* b_dev);
+int cb_manufactured_errors(cb_ctx* c, const double* x0, double k, const double* u_dev,
+                           double* l2, double* h1);
 
 /* Totals over every problem of the context (one problem for cb_setup). */
 int cb_query(const cb_ctx* c, cb_info* out);

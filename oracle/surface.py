@@ -29,11 +29,17 @@ Readings taken (the paper omits its integration section):
     summed over the cell's points in the order (ball, j, k).  With
     D_e = h K_unit (the volume form), B_e = U (the surface form of eq.
     local-eigenvals in physical units), beta_e = 2 lambda_max / h where
-    lambda_max is the largest eigenvalue of U x = lambda K_unit x on the
-    complement of the constants (both forms vanish on constants).  Where
-    the kept-point rule leaves K_unit singular on that complement (cells
-    with very few kept points), 1e-10 of its mean eigenvalue is added to
-    it, which bounds lambda_max.
+    lambda_max is the largest eigenvalue of U x = lambda (K_unit + alpha
+    K_ref) x on the complement of the constants (both forms vanish on
+    constants), K_ref the unit stiffness of a whole cell and alpha =
+    BETA_REG.  The kept-point rule leaves K_unit singular on that
+    complement in cells with one or two kept points, where the paper's
+    exactly integrated form is not; the shift counts the cell's void part
+    with stiffness alpha, as the fictitious domain of the finite cell
+    method, and bounds lambda_max there.  It is small enough that the
+    coercivity bound x^T A_e x >= x^T K_e x / 2 - alpha x^T K_ref x / 2
+    keeps every local matrix positive definite on our workloads (1e-4
+    does not).
   * The Nitsche element form with homogeneous Dirichlet data, kappa_e
     times the paper's form, is then kappa_e h (K_unit + 2 lambda_max S - T
     - T^T): the stored unit stiffness of a cut cell becomes
@@ -47,8 +53,9 @@ import numpy as np
 
 from .integrate import LOCAL_NODE_OFFSETS
 
-# relative shift of the volume form on the complement of the constants
-BETA_REG = 1e-10
+# stiffness of a cut cell's void part in the eigenproblem (relative to a
+# whole cell's)
+BETA_REG = 1e-6
 
 
 def sphere_rule(r: float, h: float):
@@ -146,20 +153,26 @@ def _complement_basis():
     return vecs[:, vals > 0.5]
 
 
+def reference_stiffness():
+    """Unit stiffness of a whole cell (every point of the volume rule kept)."""
+    from .integrate import unit_stiffness
+    return unit_stiffness(np.ones((1, 512), dtype=bool))[0]
+
+
 def beta_unit(K, U):
-    """2 lambda_max of U x = lambda K x on the complement of the constants
-    (eq. local-eigenvals, beta_e = 2 lambda_max; the physical beta_e is this
-    value over h), per cell; 0 where U vanishes."""
+    """2 lambda_max of U x = lambda (K + BETA_REG K_ref) x on the complement
+    of the constants (eq. local-eigenvals, beta_e = 2 lambda_max; the
+    physical beta_e is this value over h), per cell; 0 where U vanishes."""
     import scipy.linalg
     Q = _complement_basis()
+    Kr = Q.T @ reference_stiffness() @ Q
     out = np.zeros(K.shape[0])
     for e in range(K.shape[0]):
         K7 = Q.T @ K[e] @ Q
         U7 = Q.T @ U[e] @ Q
         if not np.any(U7):
             continue
-        K7 = K7 + BETA_REG * (np.trace(K7) / 7.0) * np.eye(7)
-        lam = scipy.linalg.eigh(U7, K7, eigvals_only=True)
+        lam = scipy.linalg.eigh(U7, K7 + BETA_REG * Kr, eigvals_only=True)
         out[e] = 2.0 * lam[-1]
     return out
 

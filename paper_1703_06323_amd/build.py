@@ -23,7 +23,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-I{CSRC}",
           "-I/opt/rocm/include"]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HIP_SOURCES = ["integrate.hip", "indexing.hip", "operator.hip", "dense.hip", "bddc.hip", "noalloc.hip"]
+HIP_SOURCES = ["integrate.hip", "indexing.hip", "operator.hip", "dense.hip", "bddc.hip", "noalloc.hip", "nitsche.hip",
+               "manufactured.hip"]
 HOST_SOURCES = ["topology.cpp", "cutbddc.cpp"]
 
 

@@ -23,6 +23,8 @@
 #include "common.h"
 #include "dense.h"
 #include "indexing.h"
+#include "manufactured.h"
+#include "nitsche.h"
 #include "topology.hpp"
 
 using namespace cutbddc;
@@ -265,6 +267,14 @@ struct cb_ctx {
   std::vector<ProbHost> pb;
   int s = 0;
   int weighting = 1, objects = 0, variant = 1, precision = 0, full_elements = 0;
+  bool nitsche = false;       // Nitsche's weak Dirichlet condition on the ball surfaces
+  bool kappa_given = false;   // some problem brought its own kappa
+  std::vector<double> radii_h;   // ball radii, in the order of the ball array
+  // sphere rules of the balls (built on first use) and beta_e of every
+  // stored cut cell (Nitsche only)
+  DevBuf sr_ball, sr_t, sr_w, sr_c, sr_s, sr_d, sr_k, beta_d;
+  bool sr_ready = false;
+  NitscheRule sr{};
   int64_t n_cells_tot = 0, nn = 0, n_dof_tot = 0, n_iface_tot = 0, n_cut_tot = 0;
   int ns = 0, nc_tot = 0;
   int32_t n_chunks = 0;
@@ -625,7 +635,8 @@ int validate_problem(const cb_problem* p) {
   if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_centres || !p->ball_radii)))
     return fail(CB_ERR_ARG, "invalid ball arrays");
   if (p->weighting < 0 || p->weighting > 1 || p->objects < 0 || p->objects > 1 || p->coarse_variant < 0 ||
-      p->coarse_variant > 2 || p->local_precision < 0 || p->local_precision > 1)
+      p->coarse_variant > 2 || p->local_precision < 0 || p->local_precision > 1 || p->cut_boundary < 0 ||
+      p->cut_boundary > 1)
     return fail(CB_ERR_ARG, "invalid option value");
   for (int i = 0; i < p->n_balls; ++i) {
     if (!(p->ball_radii[i] > 0.0) || !std::isfinite(p->ball_radii[i]))
@@ -654,6 +665,74 @@ int validate_problem(const cb_problem* p) {
 
 inline int64_t align_seg(int64_t x) { return ((x + SEG_ALIGN - 1) / SEG_ALIGN) * SEG_ALIGN; }
 
+// Tensor rules of every ball's sphere (Gauss-Legendre in cos theta,
+// midpoint in phi, n_t = max(8, ceil(4 pi r / h)) from the problem's h),
+// uploaded once per context.
+int build_sphere_rules(cb_ctx* c) {
+  if (c->sr_ready) return CB_OK;
+  hipStream_t st = c->st;
+  std::vector<NitscheBall> rb;
+  std::vector<double> t, w, cph, sph, dph;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k = 0; k < c->P; ++k) {
+    const ProbHost& h = c->pb[k];
+    for (int i = 0; i < h.nb; ++i) {
+      const double r = c->radii_h[h.ball_off + i];
+      const int nt = std::max(8, (int)std::ceil(4.0 * 3.14159265358979323846 * r / h.h));
+      const int nphi = 2 * nt;
+      NitscheBall b{r, nt, nphi, (int32_t)t.size(), (int32_t)cph.size()};
+      rb.push_back(b);
+      t.resize(t.size() + nt);
+      w.resize(w.size() + nt);
+      gauss_legendre(nt, t.data() + b.off_t, w.data() + b.off_t);
+      for (int q = 0; q < nphi; ++q) {
+        const double phi = two_pi * (q + 0.5) / nphi;
+        cph.push_back(std::cos(phi));
+        sph.push_back(std::sin(phi));
+      }
+      dph.push_back(two_pi / nphi);
+    }
+  }
+  if (rb.empty()) rb.push_back(NitscheBall{});   // keeps every table non-empty
+  for (std::vector<double>* v : {&t, &w, &cph, &sph, &dph})
+    if (v->empty()) v->push_back(0.0);
+  CHK(dalloc(c->sr_ball, rb.size() * sizeof(NitscheBall)));
+  HIPCHK(hipMemcpyAsync(c->sr_ball.p, rb.data(), rb.size() * sizeof(NitscheBall), hipMemcpyHostToDevice, st));
+  CHK(upload(c->sr_t, t, st));
+  CHK(upload(c->sr_w, w, st));
+  CHK(upload(c->sr_c, cph, st));
+  CHK(upload(c->sr_s, sph, st));
+  CHK(upload(c->sr_d, dph, st));
+  CHK(upload(c->sr_k, std::vector<double>(c->Kref, c->Kref + 64), st));
+  // the host tables must outlive the copies
+  HIPCHK(hipStreamSynchronize(st));
+  c->sr = NitscheRule{c->sr_ball.as<NitscheBall>(), c->sr_t.as<double>(), c->sr_w.as<double>(),
+                      c->sr_c.as<double>(),        c->sr_s.as<double>(), c->sr_d.as<double>(),
+                      c->sr_k.as<double>()};
+  c->sr_ready = true;
+  return CB_OK;
+}
+
+// Nitsche's surface terms (homogeneous Dirichlet data on the ball surfaces)
+// added to the unit stiffness of the n_cut stored cut cells, and beta_e of
+// each kept for the surface load of given data.
+int add_nitsche_terms(cb_ctx* c, int64_t n_cut) {
+  hipStream_t st = c->st;
+  CHK(build_sphere_rules(c));
+  CHK(dalloc(c->beta_d, std::max<int64_t>(1, n_cut) * sizeof(double)));
+  if (n_cut <= 0) return CB_OK;
+  DevBuf d_status;
+  CHK(upload(d_status, std::vector<int>(1, 0), st));
+  launch_nitsche(st, c->batch(false), c->sr, c->balls.as<double>(), c->cut_d.as<int64_t>(), n_cut, c->Kc.as<double>(),
+                 c->beta_d.as<double>(), d_status.as<int>());
+  HIPCHK(hipGetLastError());
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(CB_ERR_NOT_SPD, std::to_string(bad) + " cut cells: the Nitsche eigenproblem broke down");
+  return CB_OK;
+}
+
 // Setup of P problems: cell classification, indexing and cut-cell
 // integration on the GPU, with one readback of the per-problem counts (the
 // host sizes the index maps and groups the coarse problems).
@@ -667,7 +746,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     const cb_problem& b = ps[0];
     if (a.sub_cells != b.sub_cells || a.weighting != b.weighting || a.objects != b.objects ||
         a.coarse_variant != b.coarse_variant || a.local_precision != b.local_precision ||
-        (a.full_elements != 0) != (b.full_elements != 0))
+        (a.full_elements != 0) != (b.full_elements != 0) || a.cut_boundary != b.cut_boundary)
       return fail(CB_ERR_ARG, "problems of a batch must share sub_cells and every option");
   }
   std::unique_ptr<cb_ctx> c(new cb_ctx());
@@ -680,6 +759,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   c->variant = ps[0].coarse_variant;
   c->precision = ps[0].local_precision;
   c->full_elements = ps[0].full_elements ? 1 : 0;
+  c->nitsche = ps[0].cut_boundary == 1 && !c->full_elements;
   hipStream_t st = c->st;
   const int s = c->s;
 
@@ -737,6 +817,10 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     }
   }
   CHK(upload(c->balls, balls, st));
+  c->radii_h.assign((size_t)std::max(1, ball_off), 0.0);
+  for (int k = 0; k < P; ++k)
+    for (int i = 0; i < c->pb[k].nb; ++i) c->radii_h[c->pb[k].ball_off + i] = ps[k].ball_radii[i];
+  for (int k = 0; k < P; ++k) c->kappa_given = c->kappa_given || ps[k].kappa != nullptr;
   // kappa: 1 on the device, then the given per-cell values
   CHK(dalloc(c->kappa, c->n_cells_tot * sizeof(double)));
   launch_fill(st, c->n_cells_tot, 1.0, c->kappa.as<double>());
@@ -842,7 +926,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   // Variant 2 compares weighting coefficients built from the cut-cell
   // matrices, so those are integrated before the node passes (one extra
   // readback: the number of stored cut cells); otherwise after them.
-  const bool integrate_first = c->variant == 2;
+  const bool integrate_first = c->variant == 2 || c->nitsche;
   auto integrate = [&](int64_t n_cut) -> int {
     CHK(dalloc(c->Kc, std::max<int64_t>(1, n_cut) * PACK36 * sizeof(double)));
     CHK(dalloc(c->Mc, std::max<int64_t>(1, n_cut) * PACK36 * sizeof(double)));
@@ -856,6 +940,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
     HIPCHK(hipMemcpyAsync(&tot, c->iw.seg_cells + P, sizeof(Count4), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     CHK(integrate(tot.z));
+    if (c->nitsche) CHK(add_nitsche_terms(c.get(), tot.z));
     std::vector<double> kd(8);
     for (int a = 0; a < 8; ++a) kd[a] = c->Kref[a * 8 + a];
     CHK(upload(c->kdiag_d, kd, st));
@@ -1698,6 +1783,66 @@ int cb_load(cb_ctx* c, const double* f_nodes_dev, double* b_dev) {
   launch_gather_dofs(c->st, c->n_dof_tot, c->dof_node.as<int64_t>(), c->bgrid.as<double>(), b_dev);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
+  return CB_OK;
+}
+
+static int mms_check(cb_ctx* c, const double* x0, double k, MmsParams* m) {
+  if (!c || !x0) return fail(CB_ERR_ARG, "null argument");
+  CHK(need_single(c));
+  if (!std::isfinite(x0[0]) || !std::isfinite(x0[1]) || !std::isfinite(x0[2]) || !std::isfinite(k))
+    return fail(CB_ERR_ARG, "x0 and k must be finite");
+  if (c->kappa_given) return fail(CB_ERR_ARG, "the manufactured solution solves -Lap u = f: kappa must be 1");
+  *m = MmsParams{{x0[0], x0[1], x0[2]}, k};
+  return CB_OK;
+}
+
+int cb_manufactured_load(cb_ctx* c, const double* x0, double k, double* b_dev) {
+  MmsParams m;
+  CHK(mms_check(c, x0, k, &m));
+  if (!b_dev && c->n_dof_tot > 0) return fail(CB_ERR_ARG, "null argument");
+  hipStream_t st = c->st;
+  DevBuf be;
+  CHK(dalloc(be, std::max<int64_t>(1, c->n_cells_tot) * 8 * sizeof(double)));
+  launch_mms_volume(st, c->batch(false), m, c->xi_d.as<double>(), c->balls.as<double>(), c->cellinfo.as<int32_t>(),
+                    c->n_cells_tot, be.as<double>());
+  if (!c->full_elements) {
+    CHK(build_sphere_rules(c));
+    launch_surface_load(st, c->batch(false), c->sr, c->balls.as<double>(), c->n_cells_tot, c->cut_d.as<int64_t>(),
+                        c->n_cut_tot, c->nitsche ? 1 : 0, c->beta_d.as<double>(), m, be.as<double>());
+  }
+  double* bg = c->bgrid.as<double>();
+  double* ud = c->t1.as<double>();
+  double* y = c->t2.as<double>();
+  launch_mms_gather(st, c->batch(false), c->nn, m, c->cellinfo.as<int32_t>(), c->dofmask.as<uint8_t>(),
+                    be.as<double>(), bg, ud);
+  CHK(apply_A_grid(c, ud, y, false));
+  launch_mms_finish(st, c->n_dof_tot, c->dof_node.as<int64_t>(), bg, y, b_dev);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));   // be is released on return
+  return CB_OK;
+}
+
+int cb_manufactured_errors(cb_ctx* c, const double* x0, double k, const double* u_dev, double* l2, double* h1) {
+  MmsParams m;
+  CHK(mms_check(c, x0, k, &m));
+  if ((!u_dev && c->n_dof_tot > 0) || !l2 || !h1) return fail(CB_ERR_ARG, "null argument");
+  hipStream_t st = c->st;
+  DevBuf err, out;
+  CHK(dalloc(err, std::max<int64_t>(1, c->n_cells_tot) * 2 * sizeof(double)));
+  CHK(dalloc(out, 2 * sizeof(double)));
+  double* ug = c->t1.as<double>();
+  // the lift at the cube-face nodes, then the DOF values
+  launch_mms_gather(st, c->batch(false), c->nn, m, c->cellinfo.as<int32_t>(), c->dofmask.as<uint8_t>(), nullptr,
+                    c->t2.as<double>(), ug);
+  launch_scatter_dofs(st, c->n_dof_tot, c->dof_node.as<int64_t>(), u_dev, ug);
+  launch_mms_errors(st, c->batch(false), m, c->xi_d.as<double>(), c->balls.as<double>(), c->cellinfo.as<int32_t>(),
+                    c->n_cells_tot, ug, err.as<double>(), out.as<double>());
+  HIPCHK(hipGetLastError());
+  double e2[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(e2, out.p, sizeof(e2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *l2 = std::sqrt(e2[0]);
+  *h1 = std::sqrt(e2[1]);
   return CB_OK;
 }
 

@@ -148,17 +148,44 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
   int64_t cb = l0 < nodes ? anchor(l0) : 0;                              // cell of cs[0][0]
   for (int64_t ps = (l0 / plane1 + 1) * plane1; ps <= l1; ps += plane1) cb = min(cb, anchor(ps));
   if (l0 < nodes) {
-    for (int t = threadIdx.x; t < 3 * LX; t += SEG_ALIGN) {
-      const int dz = t / LX;
-      const int64_t g = xb + (t - dz * LX) + (int64_t)(dz - 1) * plane1;
-      xs[t] = (g >= 0 && g < nodes) ? xp[g] : 0.0;
+    // every load of a pass is issued before the first LDS store, so that a
+    // thread waits for memory once per pass (one pass for N <= 120)
+    constexpr int SV = 8;
+    for (int base = 0; base < 3 * LX; base += SV * SEG_ALIGN) {
+      double v[SV];
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
+        const int dz = t / LX;
+        const int64_t g = xb + (t - dz * LX) + (int64_t)(dz - 1) * plane1;
+        v[q] = (t < 3 * LX && g >= 0 && g < nodes) ? xp[g] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
+        if (t < 3 * LX) xs[t] = v[q];
+      }
     }
-    for (int t = threadIdx.x; t < 2 * LC; t += SEG_ALIGN) {
-      const int w = t / LC;
-      const int64_t c = cb + (t - w * LC) + (int64_t)w * N * N;
-      const bool ok = c >= 0 && c < ncells;
-      cs[t] = ok ? cip[c] : CELL_INACTIVE;
-      ks[t] = ok ? kp[c] * pr.h : 0.0;
+    for (int base = 0; base < 2 * LC; base += SV * SEG_ALIGN) {
+      int32_t ci[SV];
+      double kv[SV];
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
+        const int w = t / LC;
+        const int64_t c = cb + (t - w * LC) + (int64_t)w * N * N;
+        const bool ok = t < 2 * LC && c >= 0 && c < ncells;
+        ci[q] = ok ? cip[c] : CELL_INACTIVE;
+        kv[q] = ok ? kp[c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
+        if (t < 2 * LC) {
+          cs[t] = ci[q];
+          ks[t] = kv[q] * pr.h;
+        }
+      }
     }
   }
   __syncthreads();

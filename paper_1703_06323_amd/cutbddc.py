@@ -40,7 +40,7 @@ class cb_problem(C.Structure):
                 ("ball_centres", C.POINTER(C.c_double)), ("ball_radii", C.POINTER(C.c_double)),
                 ("kappa", C.POINTER(C.c_double)), ("weighting", C.c_int32), ("objects", C.c_int32),
                 ("coarse_variant", C.c_int32), ("local_precision", C.c_int32),
-                ("full_elements", C.c_int32)]
+                ("full_elements", C.c_int32), ("cut_boundary", C.c_int32)]
 
 
 class cb_info(C.Structure):
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.cb_apply_preconditioner.argtypes = [vp, vp, vp]
     lib.cb_load.argtypes = [vp, vp, vp]
     lib.cb_query.argtypes = [vp, C.POINTER(cb_info)]
+    lib.cb_manufactured_load.argtypes = [vp, dp, C.c_double, vp]
+    lib.cb_manufactured_errors.argtypes = [vp, dp, C.c_double, vp, dp, dp]
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
     lib.cb_export_problem_indexing.argtypes = [vp, C.c_int32] + [vp] * 8
     lib.cb_export_subdomains.argtypes = [vp, C.c_int32, vp, vp]
@@ -139,7 +141,8 @@ class Solver:
                        centres.ctypes.data_as(P), radii.ctypes.data_as(P),
                        kappa.ctypes.data_as(P) if kappa is not None else None,
                        int(problem.weighting), int(problem.objects), int(problem.coarse_variant),
-                       int(problem.local_precision), int(problem.full_elements))
+                       int(problem.local_precision), int(problem.full_elements),
+                       int(getattr(problem, "cut_boundary", 0)))
         st = torch.cuda.current_stream() if stream is None else stream
         self.stream = st
         ctx = C.c_void_p()
@@ -220,6 +223,22 @@ class Solver:
         _check(_lib.cb_load(self.ctx, _dptr(fv), b.data_ptr()))
         return b
 
+    def manufactured_load(self, x0=(0.0, 0.0, 0.0), k=5.0 * np.pi):
+        """Load [n_dof] of the exact solution sin(k |x - x0|) (volume, surface
+        data and the Dirichlet lift moved to the right)."""
+        b = self._vec(self.n_dof)
+        xv = (C.c_double * 3)(*[float(v) for v in x0])
+        _check(_lib.cb_manufactured_load(self.ctx, xv, float(k), b.data_ptr()))
+        return b
+
+    def manufactured_errors(self, u, x0=(0.0, 0.0, 0.0), k=5.0 * np.pi):
+        """(L2 error, H1-seminorm error) of u [n_dof] plus the lift."""
+        xv = (C.c_double * 3)(*[float(v) for v in x0])
+        l2 = C.c_double(0.0)
+        h1 = C.c_double(0.0)
+        _check(_lib.cb_manufactured_errors(self.ctx, xv, float(k), self._f64(u).data_ptr(), C.byref(l2), C.byref(h1)))
+        return float(l2.value), float(h1.value)
+
     PROFILE_GROUPS = ("apply_interior", "apply_neumann", "apply_A", "coarse_gemv",
                       "local_cholesky", "local_inverse", "coarse_factor")
 
@@ -298,7 +317,8 @@ class BatchSolver:
             arr[k] = cb_problem(int(problem.n), int(problem.s), int(radii.size), centres.ctypes.data_as(Pd),
                                 radii.ctypes.data_as(Pd), kappa.ctypes.data_as(Pd) if kappa is not None else None,
                                 int(problem.weighting), int(problem.objects), int(problem.coarse_variant),
-                                int(problem.local_precision), int(problem.full_elements))
+                                int(problem.local_precision), int(problem.full_elements),
+                                int(getattr(problem, "cut_boundary", 0)))
         st = torch.cuda.current_stream() if stream is None else stream
         self.stream = st
         ctx = C.c_void_p()
@@ -418,7 +438,7 @@ def _problem_struct(problem):
     p = cb_problem(int(problem.n), int(problem.s), int(radii.size), centres.ctypes.data_as(P),
                    radii.ctypes.data_as(P), None, int(problem.weighting), int(problem.objects),
                    int(problem.coarse_variant), int(problem.local_precision),
-                   int(problem.full_elements))
+                   int(problem.full_elements), int(getattr(problem, "cut_boundary", 0)))
     return p, (centres, radii)
 
 

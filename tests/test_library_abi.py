@@ -71,6 +71,7 @@ def test_setup_argument_errors():
     assert _setup_status(W.uncut(10, 4))[0] == cutbddc.CB_ERR_ARG                 # s does not divide N
     assert _setup_status(W.uncut(8, 4).with_options(weighting=3))[0] == cutbddc.CB_ERR_ARG
     assert _setup_status(W.uncut(8, 4).with_options(coarse_variant=7))[0] == cutbddc.CB_ERR_ARG
+    assert _setup_status(W.uncut(8, 4).with_options(cut_boundary=2))[0] == cutbddc.CB_ERR_ARG
     bad = W.Problem(n=8, s=4, centres=np.array([[0.5, 0.5, 0.5]]), radii=np.array([-0.1]))
     assert _setup_status(bad)[0] == cutbddc.CB_ERR_ARG
 
@@ -81,3 +82,6 @@ def test_null_context_errors():
     lib = cutbddc.load_library()
     assert lib.cb_factor(None) == cutbddc.CB_ERR_ARG
     assert lib.cb_query(None, None) == cutbddc.CB_ERR_ARG
+    x0 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib.cb_manufactured_load(None, x0, 1.0, None) == cutbddc.CB_ERR_ARG
+    assert lib.cb_manufactured_errors(None, x0, 1.0, None, None, None) == cutbddc.CB_ERR_ARG

@@ -125,8 +125,8 @@ def test_beta_makes_the_nitsche_form_coercive(seed):
     """beta_e = 2 lambda_max gives x^T A_e x >= x^T K_e x / 2 on the
     complement of the constants (Young's inequality with the bound
     x^T U x <= lambda_max x^T K x), up to the shift that bounds lambda_max
-    on cells where K is singular there; with beta = lambda_max / 4 the bound
-    fails on some cell."""
+    on cells where K is singular there (alpha x^T K_ref x / 2); with an
+    eighth of beta the bound fails on some cell."""
     p = W.random_balls(16, 4, 8, seed)
     d = assemble.discretise(p)
     pos = np.searchsorted(d.active, d.cut)
@@ -135,6 +135,7 @@ def test_beta_makes_the_nitsche_form_coercive(seed):
     beta = surface.beta_unit(K, U)
     assert np.all(beta >= 0) and np.any(beta > 0)
     Q = surface._complement_basis()
+    Kref = surface.reference_stiffness()
 
     def worst(b):
         m = np.inf
@@ -143,8 +144,7 @@ def test_beta_makes_the_nitsche_form_coercive(seed):
                 continue
             A = K[e] + b[e] * S[e] - T[e] - T[e].T
             K7 = Q.T @ K[e] @ Q
-            shift = surface.BETA_REG * np.trace(K7) / 7.0
-            E = Q.T @ (A - 0.5 * K[e]) @ Q + 0.5 * shift * np.eye(7)
+            E = Q.T @ (A - 0.5 * K[e] + 0.5 * surface.BETA_REG * Kref) @ Q
             scale = max(np.abs(Q.T @ A @ Q).max(), np.trace(K7), 1e-300)   # rounding of the largest term
             m = min(m, np.linalg.eigvalsh(E).min() / scale)
         return m
