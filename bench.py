@@ -10,9 +10,21 @@ timed region; ball data are passed from the host (80 doubles).
 
 Prints one JSON line.  `value` is the FP64 path; the FP32-local path (local
 factorisations and solves in FP32, outer PCG and coarse solve in FP64) is
-reported alongside with its speedup, and so is the batch of 256 independent
-problems (sizes 16^3..48^3, FP32 local) set up, factored and solved as one
-context (sum of their DOFs over the wall time of the whole batch).
+reported alongside with its speedup.  Also reported:
+  * the 96^3 workload (40 balls, log-normal kappa, 12^3 subdomains) in FP64
+    and FP32-local, each with its error against the FP64 oracle's stored
+    solution sample and its iteration count against the oracle's, and the
+    coarse factorisation's share of the step;
+  * the batch of 256 independent problems (sizes 16^3..48^3, FP32 local)
+    set up, factored and solved as one context (sum of their DOFs over the
+    wall time of the whole batch), with the HBM rate of its three streaming
+    kernels on first-sweep launches (every problem still iterating) and the
+    MFMA rate of its local factorisation.
+
+Kernel rates come from one more (untimed, profiled) cycle on the same
+workload: the library brackets every launch of a kernel group with two HIP
+events on the context stream (HIP graphs are off while profiling), so each
+duration is that of a launch inside the solve.
 """
 from __future__ import annotations
 
@@ -48,14 +60,19 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 256-problem batch (for profiling) and print its object")
+    ap.add_argument("--no-96", action="store_true", help="skip the 96^3 workload")
+    ap.add_argument("--steps-96", type=int, default=2)
     return ap.parse_args()
 
 
-def run_steps(problem, f_dev, steps, warmup, rtol, profile):
+def run_steps(problem, f_dev, steps, warmup, rtol, profile, check=None):
     """Times `steps` setup + factor + solve cycles on the production path.
     With profile, one more (untimed) cycle follows with the library's
-    per-group event timing, and the dominant kernel's average launch
-    duration is taken from back-to-back launches on that context."""
+    per-launch event timing: kt holds the group totals, the in-solve launch
+    durations of apply_interior (`apply_interior_launches_ms`) and, for
+    comparison, its average over 20 back-to-back launches on the factored
+    context.  check(u) (untimed, on that cycle) adds its result as
+    kt["check"]."""
     import torch
     from paper_1703_06323_amd import Solver
 
@@ -66,9 +83,13 @@ def run_steps(problem, f_dev, steps, warmup, rtol, profile):
         s.factor()
         u, it, rel = s.solve(f_dev, rtol=rtol)
         info = s.info()
-        kt = s.profile_times() if prof else {}
+        kt = {}
         if prof:
-            kt["apply_interior_avg_ms"] = s.time_kernel("apply_interior", 20)
+            kt = s.profile_times()
+            kt["apply_interior_launches_ms"] = s.profile_launches("apply_interior")
+            kt["apply_interior_b2b_ms"] = s.time_kernel("apply_interior", 20)
+            if check is not None:
+                kt["check"] = check(u)
         s.close()
         return it, rel, info, kt
 
@@ -83,9 +104,46 @@ def run_steps(problem, f_dev, steps, warmup, rtol, profile):
     return dt, res, kt
 
 
+def apply_bytes(info, probs, s_bytes):
+    """Algorithmic HBM bytes of one launch of each streaming kernel, summed
+    over the problems of a context (all of them active):
+      apply_A: x read and y written once per node (16 B), the cell code of
+        every cell (4 B), kappa of every active cell (8 B) and the packed
+        unit stiffness of every stored cut cell (36 x 8 B);
+      apply_interior: the unique entries of every subdomain's symmetric
+        Dirichlet inverse (s_bytes each) plus 2.5 gathered / scattered
+        vectors of n_I doubles on average (2 on the first launch of an
+        apply, 3 on the second);
+      apply_neumann: the unique entries of Kt (s_bytes each), Phi (n_G n_c
+        doubles) and four vectors of n_G doubles (two inputs, the weights,
+        the output)."""
+    nodes = sum((p.n + 1) ** 3 for p in probs)
+    cells = sum(p.n ** 3 for p in probs)
+    a = 16.0 * nodes + 4.0 * cells + 8.0 * info["n_active"] + 288.0 * info["n_cut_stored"]
+    i = s_bytes * (info["sum_nI2"] + info["sum_nI"]) / 2.0 + 8.0 * 2.5 * info["sum_nI"]
+    g = s_bytes * (info["sum_nG2"] + info["sum_nG"]) / 2.0 + 8.0 * info["sum_nGnC"] + 32.0 * info["sum_nG"]
+    return {"apply_A": a, "apply_interior": i, "apply_neumann": g}
+
+
+def hbm_rate(name, kernel, alg_bytes, launches_ms):
+    import numpy as np
+    d = np.asarray(launches_ms, dtype=np.float64)
+    if d.size == 0:
+        return None
+    avg_s = float(d.mean()) * 1e-3
+    achieved = alg_bytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "launches": int(d.size), "avg_launch_us": avg_s * 1e6,
+            "alg_bytes_per_launch": alg_bytes}
+
+
 def run_batch(steps, warmup, rtol):
     """The 256-problem batch: per step, setup + factor + solve of every
-    problem in one context, then release.  Sources resident in HBM."""
+    problem in one context, then release.  Sources resident in HBM.  One
+    more (untimed) cycle is profiled for the kernel rates: first-sweep
+    launches are those of the initial preconditioner apply and the first
+    PCG iteration (apply_A 5, apply_interior 4, apply_neumann 2), when every
+    problem still iterates."""
     import numpy as np
     import torch
 
@@ -95,13 +153,20 @@ def run_batch(steps, warmup, rtol):
     probs = W.batch_256()
     fs = [torch.tensor(p.f, dtype=torch.float64, device="cuda") for p in probs]
 
-    def one():
+    def one(prof=False):
         b = BatchSolver(probs)
+        if prof:
+            b.profile(True)
         b.factor()
         us, its, rels = b.solve(fs, rtol=rtol)
         info = b.info()
+        kt = {}
+        if prof:
+            kt = b.profile_times()
+            for g in ("apply_A", "apply_interior", "apply_neumann"):
+                kt[g + "_launches_ms"] = b.profile_launches(g)
         b.close()
-        return its, rels, info
+        return its, rels, info, kt
 
     for _ in range(warmup):
         one()
@@ -110,11 +175,20 @@ def run_batch(steps, warmup, rtol):
     res = [one() for _ in range(steps)]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    its, rels, info = res[-1]
+    its, rels, info, _ = res[-1]
+    _, _, pinfo, kt = one(True)
     n_dof = int(info["n_dof"])
     sizes = {}
     for p in probs:
         sizes[f"{p.n}^3"] = sizes.get(f"{p.n}^3", 0) + 1
+    rates = {}
+    if int(np.min(its)) >= 2:
+        by = apply_bytes(pinfo, probs, 4.0)
+        first = {"apply_A": 5, "apply_interior": 4, "apply_neumann": 2}
+        names = {"apply_A": "apply_A_kernel", "apply_interior": "apply_interior_kernel<float>",
+                 "apply_neumann": "apply_neumann_kernel<float>"}
+        for g, k in first.items():
+            rates[g] = hbm_rate(g, names[g], by[g], kt[g + "_launches_ms"][:k])
     return {
         "value": n_dof / dt, "unit": "DOF/s", "ms_per_batch": dt * 1e3, "steps": steps, "warmup": warmup,
         "dtype": "f32 local factor/solves, f64 PCG and coarse",
@@ -127,15 +201,82 @@ def run_batch(steps, warmup, rtol):
         "phase_ms": {k: round(float(info[k]), 3) for k in
                      ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},
         "flops_local_chol": float(info["flops_local_chol"]),
+        "first_sweep_hbm": rates,
+        "mfma": mfma_util(kt, pinfo, fp32=True),
     }
 
 
+def run_96(args, fp32):
+    """The 96^3 workload (40 balls, log-normal kappa) with its error against
+    the FP64 oracle's stored solution sample (16384 DOFs, written by
+    tests/golden/make_golden.py from the oracle alone) and the oracle's
+    iteration count."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    meta = json.load(open(os.path.join(ROOT, "tests", "golden", "cut_cube_96.json")))
+    smp = np.load(os.path.join(ROOT, "tests", "golden", "cut_cube_96_sample.npz"))
+    idx = torch.as_tensor(smp["idx"], device="cuda")
+    ref = smp["u"]
+
+    def check(u):
+        v = u[idx].cpu().numpy()
+        return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+
+    p = W.cut_cube_96_lognormal().with_options(local_precision=1 if fp32 else 0)
+    f = torch.tensor(p.f, dtype=torch.float64, device="cuda")
+    dt, res, kt = run_steps(p, f, args.steps_96, 1, args.rtol, profile=True, check=check)
+    it, rel, info, _ = res[-1]
+    n_dof = int(info["n_dof"])
+    coarse = kt.get("coarse_factor", (0.0, 0))[0]
+    return {
+        "value": n_dof / dt, "unit": "DOF/s", "ms_per_step": dt * 1e3, "steps": args.steps_96, "warmup": 1,
+        "dtype": "f32 local factor/solves, f64 PCG and coarse" if fp32 else "f64",
+        "workload": "cut_cube_96_balls40_lognormal: unit cube minus 40 seeded balls, 96^3 Q1 cells, "
+                    "12^3 subdomains of 8^3 cells, kappa = exp(N(0,1)) per cell, f ~ U(0,1)",
+        "n_dof": n_dof, "n_coarse": int(info["n_coarse"]), "iterations": it, "relres": rel,
+        "oracle_iterations": int(meta["iterations_rtol_1e-8"]),
+        "iteration_change": it - int(meta["iterations_rtol_1e-8"]),
+        "rel_error_vs_fp64_oracle": kt.get("check"),
+        "phase_ms": {k: round(float(info[k]), 3) for k in
+                     ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},
+        "coarse_factor_ms": coarse,
+        "coarse_factor_share_of_step": coarse / (dt * 1e3),
+        "mfma": mfma_util(kt, info, fp32=fp32),
+    }
+
+
+def cpu_info():
+    """CPU model and the BLAS library the oracle's NumPy / SciPy call."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        for d in threadpool_info():
+            if d.get("user_api") == "blas":
+                blas.append(f"{d.get('internal_api')} {d.get('version')} ({os.path.basename(d.get('filepath', ''))})")
+    except Exception:  # noqa: BLE001  (reporting only)
+        pass
+    return model, ", ".join(sorted(set(blas))) or "unknown"
+
+
 def cpu_baseline():
-    """The oracle, as it stands, on one BLAS thread.  It first runs the
-    octant [0, 0.5]^3 of the same 20-ball geometry at the same cell size
-    (32^3 cells, 4^3 subdomains of 8^3 cells, mapped onto the unit cube);
-    when eight times that time fits the budget (45 s) it then runs the whole
-    workload and reports that, else it reports the octant.  Full path:
+    """The oracle, as it stands, with as many BLAS threads as the host
+    gives this process (at most 16, the host share of one GPU).  It first
+    runs the octant [0, 0.5]^3 of the same 20-ball geometry at the same cell
+    size (32^3 cells, 4^3 subdomains of 8^3 cells, mapped onto the unit
+    cube); when eight times that time fits the budget (45 s) it then runs the
+    whole workload and reports that, else it reports the octant.  Full path:
     integrate, indexing, factor, PCG to rtol 1e-8."""
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -143,6 +284,8 @@ def cpu_baseline():
     import workloads as W
     from oracle import OracleSolver
 
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    model, blas = cpu_info()
     base = W.cut_cube_64()
     n = 32
     keep = np.ones(base.radii.size, dtype=bool)
@@ -154,7 +297,9 @@ def cpu_baseline():
     # the workload's nodal source restricted to the octant (same h)
     N1 = 65
     p.f = base.f[I + N1 * (J + N1 * K)]
-    with threadpool_limits(limits=1):
+    common = {"unit": "DOF/s", "cores": threads, "kind": "oracle", "cpu_model": model, "blas": blas,
+              "host_cpus_visible": len(os.sched_getaffinity(0))}
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
         s = OracleSolver(p)
         x, it, rel = s.solve(rtol=1e-8)
@@ -164,14 +309,14 @@ def cpu_baseline():
             sf = OracleSolver(base)
             xf, itf, relf = sf.solve(rtol=1e-8)
             dtf = time.perf_counter() - t0
-            return {"value": sf.n_dof / dtf, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-                    "sample": (f"whole workload (64^3 cells, 512 subdomains, {sf.n_dof} DOFs, {itf} PCG "
-                               f"iterations), full oracle path in {dtf:.1f} s on 1 BLAS thread; "
-                               f"octant probe {s.n_dof} DOFs in {dt:.1f} s")}
-    return {"value": s.n_dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"octant [0,0.5]^3 of the workload at the same h: {n}^3 cells, "
-                       f"{(n // 8) ** 3} subdomains of 8^3, {s.n_dof} DOFs, {it} PCG iterations, "
-                       f"full oracle path in {dt:.1f} s on 1 BLAS thread")}
+            return dict(common, value=sf.n_dof / dtf,
+                        sample=(f"whole workload (64^3 cells, 512 subdomains, {sf.n_dof} DOFs, {itf} PCG "
+                                f"iterations), full oracle path in {dtf:.1f} s with {threads} BLAS threads; "
+                                f"octant probe {s.n_dof} DOFs in {dt:.1f} s"))
+    return dict(common, value=s.n_dof / dt,
+                sample=(f"octant [0,0.5]^3 of the workload at the same h: {n}^3 cells, "
+                        f"{(n // 8) ** 3} subdomains of 8^3, {s.n_dof} DOFs, {it} PCG iterations, "
+                        f"full oracle path in {dt:.1f} s with {threads} BLAS threads"))
 
 
 def main():
@@ -235,12 +380,18 @@ def main():
                          ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},
             "mfma": mfma_util(kt32, info32, fp32=True),
         }
+    if not args.no_96:
+        out["cut_cube_96"] = {"fp64": run_96(args, False)}
+        if not args.no_fp32:
+            out["cut_cube_96"]["fp32_local"] = run_96(args, True)
+            out["cut_cube_96"]["fp32_speedup_vs_fp64"] = (out["cut_cube_96"]["fp32_local"]["value"] /
+                                                          out["cut_cube_96"]["fp64"]["value"])
     if not args.no_batch:
         out["batch_256"] = run_batch(args.batch_steps, 1, args.rtol)
     out["roofline"] = roofline(kt64, info64)
     out["mfma"] = mfma_util(kt64, info64)
     out["kernel_ms"] = {k: {"total_ms": round(v[0], 4), "launches": v[1]} for k, v in kt64.items()
-                        if k != "apply_interior_avg_ms"}
+                        if isinstance(v, tuple)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
@@ -248,22 +399,24 @@ def main():
 
 def roofline(kt, info):
     """Dominant kernel's achieved rate: algorithmic bytes per launch over
-    the average launch duration that the library measures with two HIP
-    events around 20 back-to-back launches on the context stream."""
-    avg_ms = kt.get("apply_interior_avg_ms")
-    if not avg_ms:
+    the mean duration of its launches inside the profiled solve (two HIP
+    events on the context stream around each launch).  The average over 20
+    back-to-back launches on the factored context is reported beside it."""
+    d = kt.get("apply_interior_launches_ms")
+    if d is None or len(d) == 0:
         return None
     # per launch: the unique entries of every subdomain's symmetric
     # Dirichlet inverse (lower triangle with diagonal, 8 B each) plus the
     # gathered input(s) and the scattered output (2 vectors on the first
     # launch of an apply, 3 on the second: 2.5 on average)
     alg_bytes = 8.0 * (info["sum_nI2"] + info["sum_nI"]) / 2.0 + 8.0 * 2.5 * info["sum_nI"]
-    avg_s = avg_ms * 1e-3
-    achieved = alg_bytes / avg_s / 1e9
-    return {"bound": "hbm", "kernel": "apply_interior_kernel<double>", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": APPLY_INTERIOR_TRAFFIC_BYTES, "avg_launch_us": avg_s * 1e6,
-            "alg_bytes_per_launch": alg_bytes}
+    out = hbm_rate("apply_interior", "apply_interior_kernel<double>", alg_bytes, d)
+    out["traffic"] = APPLY_INTERIOR_TRAFFIC_BYTES
+    out["timing"] = "mean of the in-solve launches of the profiled cycle"
+    b2b = kt.get("apply_interior_b2b_ms")
+    if b2b:
+        out["back_to_back_us"] = b2b * 1e3
+    return out
 
 
 def mfma_util(kt, info, fp32=False):

@@ -97,6 +97,9 @@ typedef struct {
   double t_solve_ms;
   int64_t sum_nGnC;            /* sum over subdomains of n_G * (coarse DOFs touching it)  */
   int64_t n_nodes;             /* grid nodes (N+1)^3, summed over problems                */
+  double lanczos_lmin;         /* extreme eigenvalue estimates of M A-bar from the last   */
+  double lanczos_lmax;         /* solve's PCG coefficients (cb_pcg_history); 0 before one,
+                                  and in cb_query of a batch context                      */
 } cb_info;
 
 typedef struct cb_ctx cb_ctx;
@@ -194,6 +197,27 @@ int cb_solve_batch(cb_ctx* c, const double* const* f_nodes_dev, double* const* u
 /* Counts of problem k of the context (fields as cb_info; times are 0). */
 int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out);
 
+/* Record of the last solve of problem k (0 for cb_setup contexts), kept on
+ * the device by the convergence check of every PCG iteration (Sect. 5.1):
+ * *n = iterations recorded (the first 1024 at most); alpha[j] and relres[j]
+ * (|r_j| / |b| of the recursive residual) for j < n; beta[j] = rho_{j+1} /
+ * rho_j, rho = r.z, for j < n - 1.  *lambda_min, *lambda_max = the extreme
+ * eigenvalues of the Lanczos matrix of those n steps, estimates of the
+ * spectrum of M A-bar (their quotient estimates its condition number; NaN
+ * when the coefficients are not those of an SPD system).  Host outputs;
+ * arrays hold cap entries, any output but n may be null.  Synchronises the
+ * context stream.  Errors: CB_ERR_ARG, CB_ERR_STATE (no solve yet). */
+int cb_pcg_history(const cb_ctx* c, int32_t k, int32_t cap, double* alpha, double* beta, double* relres,
+                   int32_t* n, double* lambda_min, double* lambda_max);
+
+/* The same estimates from given CG coefficients: n alphas (> 0) and n - 1
+ * betas (>= 0), host arrays; the tridiagonal matrix has diagonal
+ * 1/alpha_j + beta_{j-1}/alpha_{j-1} and off-diagonal sqrt(beta_j)/alpha_j,
+ * and its extreme eigenvalues come from bisection on Sturm counts.  n = 0
+ * gives (1, 1).  No GPU needed.  Errors: CB_ERR_ARG. */
+int cb_lanczos_extremes(int32_t n, const double* alpha, const double* beta, double* lambda_min,
+                        double* lambda_max);
+
 /* Measurement hooks.  With profiling enabled the library brackets every
  * launch of the named kernel groups with HIP events on the context stream:
  * "apply_interior" (Dirichlet inverse products), "apply_neumann" (interface
@@ -250,7 +274,9 @@ int cb_export_subdomains(const cb_ctx* c, int32_t k, int64_t* sub_ptr, int64_t* 
  * K [n_cut_stored*36], M [n_cut_stored*36], cut_cells [n_cut_stored]. */
 int cb_export_cut_matrices(const cb_ctx* c, double* K, double* M, int64_t* cut_cells);
 
-/* Dense coarse matrix A_c [n_coarse^2] (row-major, host) after cb_factor. */
+/* Dense coarse matrix A_c [n_coarse^2] (row-major, host) after cb_factor.
+ * Kept for single-problem contexts whose padded coarse matrix fits 1 GiB
+ * (n_coarse up to about 11 500); CB_ERR_STATE beyond. */
 int cb_export_coarse(const cb_ctx* c, double* Ac);
 
 /* Host-only indexing (no device work): DOF numbering, subdomain sets,

@@ -132,9 +132,12 @@ void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int3
 // the block parts rr_part (blocks of SEG_ALIGN nodes; node_off [P+1]) into
 // slot 2; moves slot 3 to slot 0; writes the count of running problems to
 // n_active and to host memory nact_host (may be null).
+// hist (may be null): per problem p and iteration k <= hcap, the triple
+// (alpha_k, beta that formed p_k (0 for k = 1), |r_k| / |b|) at
+// hist[(p hcap + k - 1) 3].
 void launch_cg_check(hipStream_t st, int P, const int64_t* node_off, const double* rr_part, const double* params,
                      double* S, int32_t* active, int32_t* it, int32_t* status, double* relres, int32_t* n_active,
-                     int32_t* nact_host);
+                     int32_t* nact_host, double* hist, int32_t hcap);
 // x, r update (alpha = S[3] / p.q, p.q = sum of the problem's work-item
 // parts pq_part of the operator, stored in slot 1); the block parts of the new r.r go to rr_part;
 // zero1 and zero2 (may be null) are cleared on the same nodes.

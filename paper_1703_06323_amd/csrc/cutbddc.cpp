@@ -7,9 +7,11 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <memory>
@@ -85,6 +87,7 @@ BlockCache& block_cache() {
   return *c;
 }
 constexpr size_t CACHE_LIMIT = (size_t)48 << 30;   // bytes kept for reuse
+constexpr int32_t HIST_CAP = 1024;                   // PCG iterations recorded per problem
 
 void* cache_get(size_t bytes, hipStream_t st, hipError_t* err) {
   BlockCache& c = block_cache();
@@ -146,6 +149,18 @@ struct DevBuf {
 
 thread_local hipStream_t g_alloc_stream = nullptr;   // stream of the context being served
 
+// Opt-in poison mode (environment CUTBDDC_POISON=1): every buffer handed
+// out is filled with 0xFF bytes first (NaN in every float, -1 in every
+// signed integer), so a read of data that nothing wrote shows up in the
+// results instead of reusing what an earlier owner of the block left.
+bool poison_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("CUTBDDC_POISON");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
 int dalloc(DevBuf& b, size_t bytes) {
   b.release();
   if (bytes == 0) bytes = 8;
@@ -158,6 +173,11 @@ int dalloc(DevBuf& b, size_t bytes) {
   }
   b.bytes = bytes;
   b.st = g_alloc_stream;
+  if (poison_enabled()) {
+    // finished before the call returns, whichever stream then uses the block
+    HIPCHK(hipMemsetAsync(b.p, 0xFF, bytes, g_alloc_stream));
+    HIPCHK(hipStreamSynchronize(g_alloc_stream));
+  }
   return CB_OK;
 }
 
@@ -306,6 +326,8 @@ struct cb_ctx {
   // work vectors and PCG state
   DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, tcvec, ucvec, partial, scal, bgrid;
   DevBuf pq_part, rr_part;   // per node block (SEG_ALIGN nodes): parts of p.q and r.r
+  DevBuf hist;               // PCG coefficients per problem and iteration (launch_cg_check)
+  bool solved = false;
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
   void* pin = nullptr;
@@ -505,7 +527,7 @@ int pcg_body(cb_ctx* c) {
                       c->rr_part.as<double>());
   launch_cg_check(st, c->P, c->node_off_d.as<int64_t>(), c->rr_part.as<double>(), c->params.as<double>(), S,
                   c->active.as<int32_t>(), c->itc.as<int32_t>(), c->status.as<int32_t>(), c->relres_d.as<double>(),
-                  c->nact_d.as<int32_t>(), c->pin_nact_dev);
+                  c->nact_d.as<int32_t>(), c->pin_nact_dev, c->hist.as<double>(), HIST_CAP);
   CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true, true));
   launch_dot_chunks(st, bm, c->chunk_ptr_d.as<int32_t>(), c->n_chunks, c->r.as<double>(), c->z.as<double>(),
                     c->partial.as<double>());
@@ -1139,6 +1161,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   const size_t n_blk = std::max<size_t>(1, (size_t)((c->nn + SEG_ALIGN - 1) / SEG_ALIGN));
   CHK(dalloc(c->pq_part, (size_t)std::max(1, c->op_items) * sizeof(double)));
   CHK(dalloc(c->rr_part, n_blk * sizeof(double)));
+  CHK(dalloc(c->hist, (size_t)P * HIST_CAP * 3 * sizeof(double)));
   CHK(dalloc(c->scal, (size_t)P * CG_S * sizeof(double)));
   CHK(dalloc(c->params, 2 * sizeof(double)));
   CHK(dalloc(c->active, (size_t)P * sizeof(int32_t)));
@@ -1436,22 +1459,42 @@ int factor_impl(cb_ctx* c) {
     DevBuf Ac;
     CHK(dalloc(Ac, (size_t)c->ac_total * sizeof(double)));
     CHK(dalloc(c->Acinv, (size_t)c->ac_total * sizeof(double)));
-    size_t maxL = 0, maxLL = 0, maxD = 0;
+    size_t maxL = 0, maxD = 0;
     for (const CoarseGroup& gr : c->groups) {
       maxL = std::max(maxL, (size_t)gr.ldc);
-      maxLL = std::max(maxLL, (size_t)gr.ldc * gr.ldc * gr.probs.size());
       maxD = std::max(maxD, gr.probs.size() * (size_t)diag_blocks(gr.ldc, 0) * DB * DB);
     }
     // a single problem keeps its coarse matrix for export
-    if (c->P == 1) CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
+    // (up to 1 GiB: larger coarse problems are for solving, not inspection)
+    const bool keep = c->P == 1 && c->ac_total <= ((int64_t)1 << 27);
+    if (keep) CHK(dalloc(c->AcKeep, (size_t)c->ac_total * sizeof(double)));
+    else c->AcKeep.release();
     launch_coarse_assemble(st, c->batch(false), c->prow_off_d.as<int64_t>(), c->n_prows, (int)maxL,
                            c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(), c->sub(0),
-                           AcLoc.as<double>(), Ac.as<double>(), c->P == 1 ? c->AcKeep.as<double>() : nullptr);
+                           AcLoc.as<double>(), Ac.as<double>(), keep ? c->AcKeep.as<double>() : nullptr);
     HIPCHK(hipGetLastError());
-    DevBuf Lc, Yc, ones;
+    // Envelope of each coarse matrix: A_c couples two coarse DOFs only
+    // when a subdomain holds both, so row i's first nonzero column is the
+    // smallest coarse id among the subdomains that hold i.
+    std::vector<int32_t> cids((size_t)ns * NCp), ncs(ns);
+    HIPCHK(hipMemcpyAsync(cids.data(), c->Cids.p, cids.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ncs.data(), c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int32_t> first(c->nc_tot);   // problem-local
+    for (int k = 0; k < c->P; ++k)
+      for (int i = 0; i < c->pb[k].n_coarse; ++i) first[c->pb[k].coarse_off + i] = i;
+    for (int k = 0; k < c->P; ++k) {
+      const ProbHost& h = c->pb[k];
+      for (int w = h.sub_off; w < h.sub_off + h.ns; ++w) {
+        const int32_t* ids = &cids[(size_t)w * NCp];
+        int32_t lo = INT32_MAX;
+        for (int t = 0; t < ncs[w]; ++t) lo = std::min(lo, ids[t] - h.coarse_off);
+        for (int t = 0; t < ncs[w]; ++t) first[ids[t]] = std::min(first[ids[t]], lo);
+      }
+    }
+    DevBuf Lc, ones;
     const std::vector<double> onesv(maxL, 1.0);
     CHK(dalloc(Lc, maxD * sizeof(double)));
-    CHK(dalloc(Yc, maxLL * sizeof(double)));
     CHK(upload(ones, onesv, st));
     ProfScope cps(c, "coarse_factor");
     int slot = 0;
@@ -1463,13 +1506,32 @@ int factor_impl(cb_ctx* c) {
       // the triangular inverse and the far trailing updates run beside the
       // factorisation on two more streams
       const AuxStreams ax{c->aux_st, c->aux_st3, c->aux_ev, c->aux_ev3};
+      // envelope end per column block, over the problems of the group
+      // (padding rows carry only their diagonal)
+      std::vector<int32_t> last(L);
+      for (int i = 0; i < L; ++i) last[i] = i;
+      for (int q = 0; q < nb; ++q) {
+        const ProbHost& h = c->pb[gr.probs[q]];
+        for (int i = 0; i < h.n_coarse; ++i) {
+          const int f = first[h.coarse_off + i];
+          last[f] = std::max(last[f], i);
+        }
+      }
+      std::vector<int> env(diag_blocks(L, 0));
+      int32_t run = 0, col = 0;
+      for (size_t kb = 0; kb < env.size(); ++kb) {
+        const int cend = std::min(L, (int)(kb + 1) * DB);
+        for (; col < cend; ++col) run = std::max(run, last[col]);
+        env[kb] = run + 1;
+      }
+      double* Y = c->Acinv.as<double>() + gr.ac_off;
       if (cholesky_inverse<double>(st, ax, A, L, sA, L, nb, Lc.as<double>(), sLc,
-                                   c->info_d.as<int>() + ns + 1 + slot, Yc.as<double>(), sA) != 0)
+                                   c->info_d.as<int>() + ns + 1 + slot, Y, sA, env.data()) != 0)
         return fail(CB_ERR_DEVICE, "event record or wait failed in the coarse factorisation");
       // the solve applies Y^T (Y x): keep Y in the lower triangle and its
-      // transpose in the upper one
-      symmetrize_scale<double, double>(st, Yc.as<double>(), L, sA, c->Acinv.as<double>() + gr.ac_off, L, sA,
-                                       ones.as<double>(), 0, L, nb);
+      // transpose in the upper one (in place: every 32 x 32 lower tile is
+      // read into LDS by the one workgroup that writes it and its mirror)
+      symmetrize_scale<double, double>(st, Y, L, sA, Y, L, sA, ones.as<double>(), 0, L, nb);
       HIPCHK(hipGetLastError());
       slot += nb;
     }
@@ -1671,7 +1733,97 @@ int solve_common(cb_ctx* c, double* u_dev, double* const* u_ptrs_dev, double rto
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   c->info.t_solve_ms = ms;
+  c->solved = true;
   return CB_OK;
+}
+
+// Extreme eigenvalues of the Lanczos tridiagonal matrix of n CG steps
+// (diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal
+// sqrt(beta_j)/alpha_j): bisection on Sturm counts within the Gershgorin
+// interval.  n = 0 gives (1, 1).
+int lanczos_extremes_impl(int n, const double* alpha, const double* beta, double* lmin, double* lmax) {
+  if (n <= 0) {
+    *lmin = *lmax = 1.0;
+    return CB_OK;
+  }
+  for (int j = 0; j < n; ++j)
+    if (!(alpha[j] > 0.0) || !std::isfinite(alpha[j]) || (j + 1 < n && (!(beta[j] >= 0.0) || !std::isfinite(beta[j]))))
+      return fail(CB_ERR_ARG, "CG coefficients must have alpha > 0 and beta >= 0, finite");
+  std::vector<double> d(n), e2(n, 0.0);
+  double lo = 0.0, hi = 0.0;
+  for (int j = 0; j < n; ++j) {
+    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < n) {
+      const double e = std::sqrt(beta[j]) / alpha[j];
+      e2[j] = e * e;
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    const double r = (j > 0 ? std::sqrt(e2[j - 1]) : 0.0) + (j + 1 < n ? std::sqrt(e2[j]) : 0.0);
+    lo = j ? std::min(lo, d[j] - r) : d[j] - r;
+    hi = j ? std::max(hi, d[j] + r) : d[j] + r;
+  }
+  // number of eigenvalues below x (signs of the pivots of T - x I)
+  auto below = [&](double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int j = 0; j < n; ++j) {
+      q = d[j] - x - (j > 0 ? e2[j - 1] / q : 0.0);
+      if (q == 0.0) q = -std::numeric_limits<double>::min();
+      if (q < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int k) {   // k-th smallest eigenvalue, 1-based
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double m = 0.5 * (a + b);
+      if (below(m) >= k)
+        b = m;
+      else
+        a = m;
+    }
+    return 0.5 * (a + b);
+  };
+  *lmin = kth(1);
+  *lmax = kth(n);
+  return CB_OK;
+}
+
+// The last solve's recorded PCG coefficients of problem k (alpha, the
+// betas between iterations, relative residuals), n = iterations kept.
+int read_history(const cb_ctx* c, int k, std::vector<double>* alpha, std::vector<double>* beta,
+                 std::vector<double>* relres) {
+  if (!c->solved) return fail(CB_ERR_STATE, "no solve has run on this context");
+  const int n = std::min<int32_t>(c->pin_it()[k], HIST_CAP);
+  std::vector<double> h((size_t)std::max(n, 1) * 3);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(h.data(), c->hist.as<double>() + (size_t)k * HIST_CAP * 3, (size_t)n * 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  }
+  alpha->resize(n);
+  beta->resize(n > 0 ? n - 1 : 0);
+  relres->resize(n);
+  for (int j = 0; j < n; ++j) {
+    (*alpha)[j] = h[3 * j];
+    (*relres)[j] = h[3 * j + 2];
+    if (j > 0) (*beta)[j - 1] = h[3 * j + 1];
+  }
+  return CB_OK;
+}
+
+// Lanczos estimates of the last solve of problem k, or zeros (no solve,
+// no iteration, or coefficients that are not those of an SPD system).
+void fill_lanczos(const cb_ctx* c, int k, cb_info* out) {
+  out->lanczos_lmin = out->lanczos_lmax = 0.0;
+  if (!c->solved) return;
+  std::vector<double> a, b, r;
+  if (read_history(c, k, &a, &b, &r) != CB_OK || a.empty()) return;
+  double lo = 0.0, hi = 0.0;
+  if (lanczos_extremes_impl((int)a.size(), a.data(), b.data(), &lo, &hi) != CB_OK) return;
+  out->lanczos_lmin = lo;
+  out->lanczos_lmax = hi;
 }
 
 int single_result(cb_ctx* c, int32_t* iters, double* relres) {
@@ -1874,6 +2026,8 @@ int cb_query(const cb_ctx* c, cb_info* out) {
   *out = c->info;
   out->n_fp64_fallbacks = c->n_fallbacks;
   out->factored = c->factored ? 1 : 0;
+  out->lanczos_lmin = out->lanczos_lmax = 0.0;
+  if (c->P == 1) fill_lanczos(c, 0, out);
   return CB_OK;
 }
 
@@ -1882,7 +2036,38 @@ int cb_query_problem(const cb_ctx* c, int32_t k, cb_info* out) {
   if (k < 0 || k >= c->P) return fail(CB_ERR_ARG, "problem index out of range");
   *out = c->pb[k].info;
   out->factored = c->factored ? 1 : 0;
+  fill_lanczos(c, k, out);
   return CB_OK;
+}
+
+int cb_pcg_history(const cb_ctx* c, int32_t k, int32_t cap, double* alpha, double* beta, double* relres, int32_t* n,
+                   double* lambda_min, double* lambda_max) {
+  if (!c || !n) return fail(CB_ERR_ARG, "null argument");
+  if (k < 0 || k >= c->P) return fail(CB_ERR_ARG, "problem index out of range");
+  if (cap < 0) return fail(CB_ERR_ARG, "cap must be >= 0");
+  std::vector<double> a, b, r;
+  CHK(read_history(c, k, &a, &b, &r));
+  *n = (int32_t)a.size();
+  for (int j = 0; j < (int)a.size() && j < cap; ++j) {
+    if (alpha) alpha[j] = a[j];
+    if (relres) relres[j] = r[j];
+    if (beta && j < (int)b.size()) beta[j] = b[j];
+  }
+  if (lambda_min || lambda_max) {
+    double lo = std::numeric_limits<double>::quiet_NaN(), hi = lo;
+    if (lanczos_extremes_impl((int)a.size(), a.data(), b.data(), &lo, &hi) != CB_OK)
+      lo = hi = std::numeric_limits<double>::quiet_NaN();
+    if (lambda_min) *lambda_min = lo;
+    if (lambda_max) *lambda_max = hi;
+  }
+  return CB_OK;
+}
+
+int cb_lanczos_extremes(int32_t n, const double* alpha, const double* beta, double* lambda_min,
+                        double* lambda_max) {
+  if (n < 0 || !lambda_min || !lambda_max || (n > 0 && !alpha) || (n > 1 && !beta))
+    return fail(CB_ERR_ARG, "null argument or n < 0");
+  return lanczos_extremes_impl(n, alpha, beta, lambda_min, lambda_max);
 }
 
 }  // extern "C"
@@ -2049,6 +2234,7 @@ int cb_export_coarse(const cb_ctx* c, double* Ac) {
   const ProbHost& h = c->pb[0];
   const int nc = h.n_coarse, ldc = h.ldc;
   if (nc == 0) return CB_OK;
+  if (!c->AcKeep.p) return fail(CB_ERR_STATE, "the coarse matrix is kept only up to 1 GiB");
   HIPCHK(hipMemcpy2D(Ac, nc * sizeof(double), c->AcKeep.as<double>() + h.ac_off, ldc * sizeof(double),
                      nc * sizeof(double), nc, hipMemcpyDeviceToHost));
   return CB_OK;

@@ -79,9 +79,14 @@ struct AuxStreams {
 // trailing matrix; the triangular-inverse step of block k runs on st2.  st
 // waits for st2 and st3 before returning.  Returns -1 if an event record or
 // wait fails.
+// env (host, optional): per DB-wide column block k, the end (exclusive) of
+// the rows of every matrix of the batch that can be nonzero in that column
+// block of L: one past the last row i whose first nonzero column in A lies
+// at or before the block's last column (fill stays inside this envelope).
+// Rows at or past it take only zero updates, which are skipped.
 template <typename T>
 int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
-                     int64_t sL, int* info, T* Y, int64_t sY);
+                     int64_t sL, int* info, T* Y, int64_t sY, const int* env = nullptr);
 
 // out = D sym(lower(in)) D, full storage.
 template <typename T, typename TO>

@@ -1128,8 +1128,10 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
 // below it, both final once the Cholesky sweep has passed that block.
 template <typename T>
 void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, int S0, int h) {
+                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, int S0, int h, int row_end = -1) {
   const int send = S0 + h;
+  // rows at or past row_end have L[row, S] = 0: their update is exactly zero
+  const int rend = row_end < 0 ? nb : std::min(nb, row_end);
   const int blk = diag_block_index(off + S0, split);
   const T* li = Linv + (int64_t)blk * DB * DB;
   // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0] (in place: a single tile row reads
@@ -1141,7 +1143,7 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
             sY, batch, 0);
   hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, li, DB, sLi,
                      Y + (int64_t)S0 * ldy + S0, ldy, sY, h);
-  const int rest = nb - send;
+  const int rest = rend - send;
   if (rest > 0) {
     const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
     gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
@@ -1169,13 +1171,15 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
 
 template <typename T>
 int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, int64_t sA, int n, int batch, T* Linv,
-                     int64_t sL, int* info, T* Y, int64_t sY) {
+                     int64_t sL, int* info, T* Y, int64_t sY, const int* env) {
   // Block step k on st: diagonal block, panel, then the update of column
   // block k+1 only (after the far update of step k-1, which also covered
   // it).  The far update of step k (rows and columns right of block k+1)
   // runs on st3 beside the factorisation of block k+1: the two touch
   // disjoint parts of A and read only the panel of block k.  Step k of the
   // triangular inverse reads the final column block k and runs on st2.
+  // With env, every step works only on rows below the block's envelope end
+  // (the factor is zero beyond it, so the skipped updates are exact zeros).
   hipLaunchKernelGGL(eye_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
   bool far_pending = false;
   int K0 = 0;
@@ -1183,14 +1187,15 @@ int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, in
     const int b = std::min(DB, n - K0);
     const int K1 = K0 + b;
     diag_step<T>(st, A, lda, sA, K0, b, Linv, sL, diag_block_index(K0, 0), batch, info);
-    const int rest = n - K1;
+    const int rend = env ? std::max(K1, std::min(n, env[K0 / DB])) : n;
+    const int rest = rend - K1;
     T* panel = A + (int64_t)K1 * lda + K0;
     if (rest > 0) {
       const T* li = Linv + (int64_t)diag_block_index(K0, 0) * DB * DB;
       gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
     }
     if (hipEventRecord(ax.ev2, st) != hipSuccess || hipStreamWaitEvent(ax.st2, ax.ev2, 0) != hipSuccess) return -1;
-    tri_inverse_step<T>(ax.st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, K0, b);
+    tri_inverse_step<T>(ax.st2, A, lda, sA, 0, n, 0, batch, Linv, sL, Y, lda, sY, K0, b, rend);
     if (rest > 0) {
       const int b2 = std::min(DB, rest);
       if (far_pending && hipStreamWaitEvent(st, ax.ev3, 0) != hipSuccess) return -1;
@@ -1234,7 +1239,7 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
                                int64_t, T*, int64_t, int64_t);                                      \
   template int cholesky_inverse<T>(hipStream_t, const AuxStreams&, T*, int64_t, int64_t, int, int, T*,  \
-                                   int64_t, int*, T*, int64_t);
+                                   int64_t, int*, T*, int64_t, const int*);
 INST(double)
 INST(float)
 #undef INST

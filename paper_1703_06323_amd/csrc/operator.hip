@@ -100,6 +100,45 @@ __device__ inline int32_t xcd_item(int32_t b, int32_t G) {
   return (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + k;
 }
 
+// Cell C = u + 2 vv + 4 w around node (I, J, K) of the operator kernel,
+// without branches except around a cut cell's row load: a cell outside the
+// grid counts as inactive (its staged code belongs to another cell), and an
+// inactive one adds nothing.  cc stays inside the staged cell ranges for
+// every node of the block.
+template <int C>
+__device__ __forceinline__ void op_cell(int I, int J, int K, int N, int LC, int co, const int32_t* cs,
+                                        const double* ks, const double* __restrict__ Kf,
+                                        const double (&xn)[3][3][3], double& acc, bool& touched) {
+  constexpr int u = C & 1, vv = (C >> 1) & 1, w = C >> 2;
+  constexpr int a = 7 - C;                               // the node's corner in the cell
+  const bool in = (unsigned)(I - 1 + u) < (unsigned)N && (unsigned)(J - 1 + vv) < (unsigned)N &&
+                  (unsigned)(K - 1 + w) < (unsigned)N;
+  const int cc = w * LC + co + u + N * vv;
+  const int32_t info = in ? cs[cc] : CELL_INACTIVE;
+  const bool act = info != CELL_INACTIVE;
+  touched = touched || act;
+  // row a of the cell matrix times x: the reference row (constant
+  // operands), replaced for a cut cell by its row from the full row-major
+  // copy (64 contiguous bytes)
+  double row = 0.0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+    row = fma(c_Kref[a * 8 + b], xn[w + ((b >> 2) & 1)][vv + ((b >> 1) & 1)][u + (b & 1)], row);
+  if (info >= 0) {
+    const double2* R = reinterpret_cast<const double2*>(Kf + (int64_t)info * 64 + a * 8);
+    double rc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v2 = R[q];
+      rc = fma(v2.x, xn[w + (((2 * q) >> 2) & 1)][vv + (((2 * q) >> 1) & 1)][u + ((2 * q) & 1)], rc);
+      rc = fma(v2.y, xn[w + (((2 * q + 1) >> 2) & 1)][vv + (((2 * q + 1) >> 1) & 1)][u + ((2 * q + 1) & 1)], rc);
+    }
+    row = rc;
+  }
+  const double t = fma(ks[cc], row, acc);
+  acc = act ? t : acc;
+}
+
 // Matrix-free A-bar x.  A workgroup takes a block of SEG_ALIGN consecutive
 // nodes of one problem (its problem read from op_prob, no search) and first
 // stages in LDS, with independent coalesced loads:
@@ -130,23 +169,25 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
   const int p = bd.op_prob[item];
   if (bd.active && !bd.active[p]) return;
   const ProbDev pr = bd.prob[p];
+  // local node and cell numbers fit 32 bits: N <= 1024 (setup checks it)
   const int N = pr.N, N1 = N + 1, LX = bd.op_lx, LC = bd.op_lc;
-  const int64_t plane1 = (int64_t)N1 * N1, nodes = plane1 * N1, ncells = (int64_t)N * N * N;
-  const int64_t l0 = (int64_t)item * SEG_ALIGN - pr.node_off;          // first local node of the block
-  const int64_t l1 = min(l0 + SEG_ALIGN, nodes) - 1;                     // last node of the problem in it
+  const int plane1 = N1 * N1, nodes = plane1 * N1, ncells = N * N * N;
+  const int l0 = (int)((int64_t)item * SEG_ALIGN - pr.node_off);       // first local node of the block
+  const int l1 = min(l0 + SEG_ALIGN, nodes) - 1;                         // last node of the problem in it
   double* xs = op_lds;                                                   // [3][LX]
   double* ks = xs + 3 * LX;                                              // [2][LC] kappa h
   int32_t* cs = reinterpret_cast<int32_t*>(ks + 2 * LC);                 // [2][LC] cell info
   const double* xp = x + pr.node_off;
   const int32_t* cip = cellinfo + pr.cell_off;
   const double* kp = kappa + pr.cell_off;
-  const int64_t xb = l0 - N1 - 1;                                        // node of xs[1][0]
-  auto anchor = [&](int64_t l) {
-    const int I = (int)(l % N1), J = (int)((l / N1) % N1), K = (int)(l / plane1);
-    return (int64_t)(I - 1) + (int64_t)N * ((J - 1) + (int64_t)N * (K - 1));
+  const int xb = l0 - N1 - 1;                                            // node of xs[1][0]
+  auto anchor = [&](int l) {
+    const int K = l / plane1, r = l - K * plane1;
+    const int J = r / N1, I = r - J * N1;
+    return (I - 1) + N * ((J - 1) + N * (K - 1));
   };
-  int64_t cb = l0 < nodes ? anchor(l0) : 0;                              // cell of cs[0][0]
-  for (int64_t ps = (l0 / plane1 + 1) * plane1; ps <= l1; ps += plane1) cb = min(cb, anchor(ps));
+  int cb = l0 < nodes ? anchor(l0) : 0;                                  // cell of cs[0][0]
+  for (int ps = (l0 / plane1 + 1) * plane1; ps <= l1; ps += plane1) cb = min(cb, anchor(ps));
   if (l0 < nodes) {
     // every load of a pass is issued before the first LDS store, so that a
     // thread waits for memory once per pass (one pass for N <= 120)
@@ -157,7 +198,7 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
       for (int q = 0; q < SV; ++q) {
         const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
         const int dz = t / LX;
-        const int64_t g = xb + (t - dz * LX) + (int64_t)(dz - 1) * plane1;
+        const int g = xb + (t - dz * LX) + (dz - 1) * plane1;
         v[q] = (t < 3 * LX && g >= 0 && g < nodes) ? xp[g] : 0.0;
       }
 #pragma unroll
@@ -173,7 +214,7 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
       for (int q = 0; q < SV; ++q) {
         const int t = base + q * SEG_ALIGN + (int)threadIdx.x;
         const int w = t / LC;
-        const int64_t c = cb + (t - w * LC) + (int64_t)w * N * N;
+        const int c = cb + (t - w * LC) + w * N * N;
         const bool ok = t < 2 * LC && c >= 0 && c < ncells;
         ci[q] = ok ? cip[c] : CELL_INACTIVE;
         kv[q] = ok ? kp[c] : 0.0;
@@ -189,56 +230,35 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
     }
   }
   __syncthreads();
-  const int64_t l = l0 + threadIdx.x;
+  const int l = l0 + (int)threadIdx.x;
   double v = 0.0, xv0 = 0.0;
   if (l < nodes) {
-    const int I = (int)(l % N1), J = (int)((l / N1) % N1), K = (int)(l / plane1);
-    const int64_t xo = l - xb;                          // offset of the node itself in each x range
-    const int64_t co = anchor(l) - cb;                  // offset of its anchor cell in each cell range
-    xv0 = xs[LX + xo];
+    const int K = l / plane1, rr = l - K * plane1;
+    const int J = rr / N1, I = rr - J * N1;
+    const int xo = l - xb;                              // offset of the node itself in each x range
+    const int co = anchor(l) - cb;                      // offset of its anchor cell in each cell range
+    // the node's 27 neighbours (in-range LDS reads also where a neighbour
+    // leaves the grid: those values only meet cells that are skipped)
+    double xn[3][3][3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) xn[dz][dy][dx] = xs[dz * LX + xo + (dx - 1) + N1 * (dy - 1)];
+    xv0 = xn[1][1][1];
+    // The 8 cells around the node, in the load's order (op_cell<C> below,
+    // one instantiation per cell so that every index is a constant)
     double acc = 0.0;
     bool touched = false;
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      if (K - 1 + w < 0 || K - 1 + w >= N) continue;
-#pragma unroll
-      for (int vv = 0; vv < 2; ++vv) {
-        if (J - 1 + vv < 0 || J - 1 + vv >= N) continue;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (I - 1 + u < 0 || I - 1 + u >= N) continue;
-          const int64_t cc = w * LC + co + u + (int64_t)N * vv;
-          const int32_t info = cs[cc];
-          if (info == CELL_INACTIVE) continue;
-          touched = true;
-          const int a = (1 - u) + 2 * (1 - vv) + 4 * (1 - w);   // the node's corner in the cell
-          double row = 0.0;
-          if (info == CELL_UNCUT) {
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-              const int dz = w + ((b >> 2) & 1), dy = vv + ((b >> 1) & 1), dx = u + (b & 1);
-              row += c_Kref[a * 8 + b] * xs[dz * LX + xo + (dx - 1) + (int64_t)N1 * (dy - 1)];
-            }
-          } else {
-            // row a of the cell's full matrix: 64 contiguous bytes
-            const double2* R = reinterpret_cast<const double2*>(Kf + (int64_t)info * 64 + a * 8);
-            double r8[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double2 v2 = R[q];
-              r8[2 * q] = v2.x;
-              r8[2 * q + 1] = v2.y;
-            }
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-              const int dz = w + ((b >> 2) & 1), dy = vv + ((b >> 1) & 1), dx = u + (b & 1);
-              row += r8[b] * xs[dz * LX + xo + (dx - 1) + (int64_t)N1 * (dy - 1)];
-            }
-          }
-          acc += ks[cc] * row;
-        }
-      }
-    }
+    op_cell<0>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<1>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<2>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<3>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<4>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<5>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<6>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell<7>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
     const bool interior = I >= 1 && I < N && J >= 1 && J < N && K >= 1 && K < N;
     v = (interior && touched) ? acc : 0.0;
   }
@@ -454,7 +474,8 @@ __global__ __launch_bounds__(256) void cg_check_kernel(int P, const int64_t* __r
                                                        const double* __restrict__ params, double* __restrict__ S,
                                                        int32_t* __restrict__ active, int32_t* __restrict__ it,
                                                        int32_t* __restrict__ status, double* __restrict__ relres,
-                                                       int32_t* __restrict__ n_active, int32_t* nact_host) {
+                                                       int32_t* __restrict__ n_active, int32_t* nact_host,
+                                                       double* __restrict__ hist, int32_t hcap) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int p = wv; p < P; p += 4) {
     if (!active[p]) continue;
@@ -469,8 +490,16 @@ __global__ __launch_bounds__(256) void cg_check_kernel(int P, const int64_t* __r
   const int32_t max_iter = (int32_t)params[1];
   for (int p = threadIdx.x; p < P; p += 256) {
     if (!active[p]) continue;
-    S[CG_S * p + 0] = S[CG_S * p + 3];
     const int32_t k = it[p] + 1;
+    if (hist && k <= hcap) {
+      // alpha of this iteration (the x, r update's own quotient) and the
+      // beta that formed its search direction (none for the first)
+      double* hrow = hist + ((int64_t)p * hcap + (k - 1)) * 3;
+      hrow[0] = S[CG_S * p + 3] / S[CG_S * p + 1];
+      hrow[1] = k >= 2 ? S[CG_S * p + 3] / S[CG_S * p + 0] : 0.0;
+      hrow[2] = sqrt(S[CG_S * p + 2]) / sqrt(S[CG_S * p + 4]);
+    }
+    S[CG_S * p + 0] = S[CG_S * p + 3];
     it[p] = k;
     const double rr = S[CG_S * p + 2];
     if (!isfinite(rr)) {
@@ -655,9 +684,9 @@ void launch_cg_init(hipStream_t st, int P, const double* params, double* S, int3
 
 void launch_cg_check(hipStream_t st, int P, const int64_t* node_off, const double* rr_part, const double* params,
                      double* S, int32_t* active, int32_t* it, int32_t* status, double* relres, int32_t* n_active,
-                     int32_t* nact_host) {
+                     int32_t* nact_host, double* hist, int32_t hcap) {
   hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(256), 0, st, P, node_off, rr_part, params, S, active, it,
-                     status, relres, n_active, nact_host);
+                     status, relres, n_active, nact_host, hist, hcap);
 }
 
 void launch_gather_dofs_batch(hipStream_t st, int P, int64_t n_dof_total, const int64_t* dof_off,

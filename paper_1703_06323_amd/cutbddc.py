@@ -53,7 +53,8 @@ class cb_info(C.Structure):
                 ("sum_nI", C.c_int64), ("sum_nG", C.c_int64), ("flops_local_chol", C.c_double),
                 ("t_integrate_ms", C.c_double),
                 ("t_topology_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_solve_ms", C.c_double), ("sum_nGnC", C.c_int64), ("n_nodes", C.c_int64)]
+                ("t_solve_ms", C.c_double), ("sum_nGnC", C.c_int64), ("n_nodes", C.c_int64),
+                ("lanczos_lmin", C.c_double), ("lanczos_lmax", C.c_double)]
 
 
 _lib = None
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.cb_apply_preconditioner.argtypes = [vp, vp, vp]
     lib.cb_load.argtypes = [vp, vp, vp]
     lib.cb_query.argtypes = [vp, C.POINTER(cb_info)]
+    lib.cb_pcg_history.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, ip, dp, dp]
+    lib.cb_lanczos_extremes.argtypes = [C.c_int32, vp, vp, dp, dp]
     lib.cb_manufactured_load.argtypes = [vp, dp, C.c_double, vp]
     lib.cb_manufactured_errors.argtypes = [vp, dp, C.c_double, vp, dp, dp]
     lib.cb_export_indexing.argtypes = [vp] + [vp] * 8
@@ -223,6 +226,10 @@ class Solver:
         _check(_lib.cb_load(self.ctx, _dptr(fv), b.data_ptr()))
         return b
 
+    def pcg_history(self) -> dict:
+        """The last solve's PCG record (cb_pcg_history)."""
+        return _pcg_history(self.ctx, 0)
+
     def manufactured_load(self, x0=(0.0, 0.0, 0.0), k=5.0 * np.pi):
         """Load [n_dof] of the exact solution sin(k |x - x0|) (volume, surface
         data and the Dirichlet lift moved to the right)."""
@@ -247,14 +254,7 @@ class Solver:
 
     def profile_times(self) -> dict:
         """{group: (total_ms, launches)} of the bracketed kernel groups."""
-        out = {}
-        for name in self.PROFILE_GROUPS:
-            t = C.c_double(0.0)
-            n = C.c_int64(0)
-            _check(_lib.cb_profile_time(self.ctx, name.encode(), C.byref(t), C.byref(n)))
-            if n.value:
-                out[name] = (float(t.value), int(n.value))
-        return out
+        return _profile_times(self.ctx, self.PROFILE_GROUPS)
 
     def time_kernel(self, which: str, reps: int = 20) -> float:
         """Average launch duration (ms) of "apply_interior" or "apply_neumann"
@@ -360,6 +360,14 @@ class BatchSolver:
     def profile_launches(self, name: str) -> np.ndarray:
         return _profile_launches(self.ctx, name)
 
+    def profile_times(self) -> dict:
+        """{group: (total_ms, launches)} of the bracketed kernel groups."""
+        return _profile_times(self.ctx, Solver.PROFILE_GROUPS)
+
+    def pcg_history(self, k: int) -> dict:
+        """The last solve's PCG record of problem k (cb_pcg_history)."""
+        return _pcg_history(self.ctx, int(k))
+
     def export_subdomains(self, k: int):
         return _export_subdomains(self.ctx, int(k), int(self.problem_info(k)["n_sub"]))
 
@@ -386,6 +394,42 @@ class BatchSolver:
                                  rel.ctypes.data_as(C.POINTER(C.c_double)))
         _check(rc, allow=(CB_ERR_NO_CONVERGENCE,) if allow_no_convergence else ())
         return outputs, it, rel
+
+
+def _pcg_history(ctx, k):
+    n = C.c_int32(0)
+    _check(_lib.cb_pcg_history(ctx, k, 0, None, None, None, C.byref(n), None, None))
+    m = max(n.value, 1)
+    a, b, r = np.zeros(m), np.zeros(m), np.zeros(m)
+    lo, hi = C.c_double(0.0), C.c_double(0.0)
+    _check(_lib.cb_pcg_history(ctx, k, m, a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                               r.ctypes.data_as(C.c_void_p), C.byref(n), C.byref(lo), C.byref(hi)))
+    k_ = n.value
+    return {"alpha": a[:k_], "beta": b[:max(k_ - 1, 0)], "relres": r[:k_],
+            "lambda_min": lo.value, "lambda_max": hi.value}
+
+
+def lanczos_extremes(alpha, beta):
+    """(lambda_min, lambda_max) of the Lanczos matrix of CG coefficients
+    (cb_lanczos_extremes; host only)."""
+    lib = load_library()
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    lo, hi = C.c_double(0.0), C.c_double(0.0)
+    _check(lib.cb_lanczos_extremes(int(a.size), a.ctypes.data_as(C.c_void_p) if a.size else None,
+                                   b.ctypes.data_as(C.c_void_p) if b.size else None, C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def _profile_times(ctx, groups):
+    out = {}
+    for name in groups:
+        t = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(_lib.cb_profile_time(ctx, name.encode(), C.byref(t), C.byref(n)))
+        if n.value:
+            out[name] = (float(t.value), int(n.value))
+    return out
 
 
 def _profile_launches(ctx, name):

@@ -85,3 +85,6 @@ def test_null_context_errors():
     x0 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     assert lib.cb_manufactured_load(None, x0, 1.0, None) == cutbddc.CB_ERR_ARG
     assert lib.cb_manufactured_errors(None, x0, 1.0, None, None, None) == cutbddc.CB_ERR_ARG
+    n = ctypes.c_int32(0)
+    assert lib.cb_pcg_history(None, 0, 0, None, None, None, ctypes.byref(n), None, None) == cutbddc.CB_ERR_ARG
+    assert lib.cb_lanczos_extremes(-1, None, None, None, None) == cutbddc.CB_ERR_ARG
