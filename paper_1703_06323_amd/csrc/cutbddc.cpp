@@ -1252,11 +1252,12 @@ size_t factor_work_budget() {
 template <typename T>
 struct FactorWork {
   int chunk = 0;
-  DevBuf K, Linv, Y, PS, Pd64, KSw, G, Sc, PhiF, V, StV, StC;
+  DevBuf K, Linv, Y, PS, YI, PSI, Pd64, KSw, G, Sc, PhiF, V, StV, StC;
   static size_t per_sub(const cb_ctx* c) {
     const int nt = c->nt, NIp = c->NIp, NGp = c->NGp, NCp = c->NCp, nbig = std::max(NIp, NGp);
     return (size_t)nt * nt * sizeof(T) + (size_t)diag_blocks(nt, NIp) * DB * DB * sizeof(T) +
-           2 * (size_t)nbig * nbig * sizeof(T) + (size_t)NIp * NIp * 8 + (size_t)NGp * NGp * 8 +
+           2 * (size_t)nbig * nbig * sizeof(T) + 2 * (size_t)NIp * NIp * sizeof(T) + (size_t)NIp * NIp * 8 +
+           (size_t)NGp * NGp * 8 +
            (size_t)(NGp * NCp + NCp * NCp + 2 * nt * NCp) * sizeof(double) +
            (size_t)nt * STENCIL * (sizeof(double) + sizeof(int32_t));
   }
@@ -1268,6 +1269,8 @@ struct FactorWork {
     CHK(dalloc(Linv, (size_t)n * diag_blocks(nt, NIp) * DB * DB * sizeof(T)));
     CHK(dalloc(Y, (size_t)n * nbig * nbig * sizeof(T)));
     CHK(dalloc(PS, (size_t)n * nbig * nbig * sizeof(T)));
+    CHK(dalloc(YI, (size_t)n * NIp * NIp * sizeof(T)));
+    CHK(dalloc(PSI, (size_t)n * NIp * NIp * sizeof(T)));
     CHK(dalloc(Pd64, (size_t)n * NIp * NIp * sizeof(double)));
     CHK(dalloc(KSw, (size_t)n * NGp * NGp * sizeof(double)));
     CHK(dalloc(G, (size_t)n * NGp * NCp * sizeof(double)));
@@ -1279,7 +1282,7 @@ struct FactorWork {
     return CB_OK;
   }
   void release() {
-    for (DevBuf* b : {&K, &Linv, &Y, &PS, &Pd64, &KSw, &G, &Sc, &PhiF, &V, &StV, &StC}) b->release();
+    for (DevBuf* b : {&K, &Linv, &Y, &PS, &YI, &PSI, &Pd64, &KSw, &G, &Sc, &PhiF, &V, &StV, &StC}) b->release();
   }
 };
 
@@ -1300,8 +1303,9 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
   const int64_t sP = (int64_t)NIp * NIp, sKS = (int64_t)NGp * NGp;
   const int64_t pkI = packed_elems(NIp), pkG = packed_elems(NGp);
   const int ns = c->ns;
-  DevBuf &K = fw.K, &Linv = fw.Linv, &Y = fw.Y, &PS = fw.PS, &Pd64 = fw.Pd64, &KSw = fw.KSw, &G = fw.G,
-         &Sc = fw.Sc, &PhiF = fw.PhiF, &V = fw.V, &StV = fw.StV, &StC = fw.StC;
+  DevBuf &K = fw.K, &Linv = fw.Linv, &Y = fw.Y, &PS = fw.PS, &YI = fw.YI, &PSI = fw.PSI, &Pd64 = fw.Pd64,
+         &KSw = fw.KSw, &G = fw.G, &Sc = fw.Sc, &PhiF = fw.PhiF, &V = fw.V, &StV = fw.StV, &StC = fw.StC;
+  const int64_t sI2 = (int64_t)NIp * NIp;
   {
     const SubDev sd = c->sub(w0);
     const double* Dsw = c->Ds.as<double>() + (int64_t)w0 * nt;
@@ -1310,18 +1314,32 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     launch_assemble_local<T>(st, sd, g, nc, K.as<T>(), c->diagAG.as<double>() + (int64_t)w0 * NGp,
                              c->Ds.as<double>() + (int64_t)w0 * nt, StV.as<double>(), StC.as<int32_t>());
     HIPCHK(hipGetLastError());
-    timed(c, "local_cholesky",
-          [&] { cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0); });
+    int chol_rc = 0;
+    timed(c, "local_cholesky", [&] {
+      const AuxStreams ax{c->aux_st, c->aux_st3, c->aux_ev, c->aux_ev3};
+      chol_rc = cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0, &ax);
+    });
+    if (chol_rc != 0) return fail(CB_ERR_DEVICE, "event record or wait failed in the local factorisation");
     HIPCHK(hipGetLastError());
+    // The interior and interface inverses only read the factor: the
+    // interior one runs on the second stream beside the interface one
+    // (in line on st while profiling, so that the group timers see it).
+    const bool overlap = !c->prof;
+    hipStream_t sti = overlap ? c->aux_st : st;
+    if (overlap) {
+      HIPCHK(hipEventRecord(c->aux_ev, st));
+      HIPCHK(hipStreamWaitEvent(sti, c->aux_ev, 0));
+    }
     // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NIp, sY);
-      gemm<T>(st, 1, 0, NIp, NIp, NIp, T(1), Y.as<T>(), NIp, sY, Y.as<T>(), NIp, sY, T(0), PS.as<T>(), NIp, sY, nc,
-              GEMM_LOWER | GEMM_KFROM_DIAG);
+      tri_inverse<T>(sti, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, YI.as<T>(), NIp, sI2);
+      gemm<T>(sti, 1, 0, NIp, NIp, NIp, T(1), YI.as<T>(), NIp, sI2, YI.as<T>(), NIp, sI2, T(0), PSI.as<T>(), NIp,
+              sI2, nc, GEMM_LOWER | GEMM_KFROM_DIAG);
     });
-    launch_pack_lower<T, TS>(st, NIp, nc, PS.as<T>(), NIp, sY, Dsw, nt, c->P_.as<TS>() + (int64_t)w0 * pkI);
+    launch_pack_lower<T, TS>(sti, NIp, nc, PSI.as<T>(), NIp, sI2, Dsw, nt, c->P_.as<TS>() + (int64_t)w0 * pkI);
     // full FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
-    symmetrize_scale<T, double>(st, PS.as<T>(), NIp, sY, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
+    symmetrize_scale<T, double>(sti, PSI.as<T>(), NIp, sI2, Pd64.as<double>(), NIp, sP, Dsw, nt, NIp, nc);
+    if (overlap) HIPCHK(hipEventRecord(c->aux_ev, sti));
     const double* Pd = Pd64.as<double>();
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
@@ -1349,6 +1367,8 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
                             (size_t)sG * sizeof(double), (size_t)sG * sizeof(double), nc, hipMemcpyDeviceToDevice,
                             st));
     launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), 0, NIp);
+    // A_II^{-1} (and P) from the second stream
+    if (overlap) HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
     gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, sP, V.as<double>(), NCp, sF, 0.0, PhiF.as<double>(), NCp,
                  sF, nc, 0);
     launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), NIp,

@@ -53,9 +53,15 @@ inline int diag_block_index(int p, int split) {
 // the diagonal): sL >= diag_blocks(n, split) * DB * DB.  info[b] is set to
 // (first row with a non-positive pivot) + 1 for matrix b; the pivot is then
 // replaced by 1 so that the factorisation finishes without NaNs.
+// With ax (streams and events lent by the caller, see AuxStreams), one
+// block of lookahead: after the panel of block k, st updates only column
+// block k+1 and goes on to factor it, while ax->st3 updates the rest of the
+// trailing matrix; st waits for st3 before returning.  Returns -1 if an
+// event record or wait fails.
+struct AuxStreams;
 template <typename T>
-void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
-              int* info);
+int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
+             int* info, const AuxStreams* ax = nullptr);
 
 // Y = inverse of the lower-triangular diagonal range [off, off+nb) of L
 // (off and off+nb block starts of the same split), from the diagonal-block

@@ -1097,13 +1097,15 @@ void diag_step(hipStream_t st, T* A, int64_t lda, int64_t sA, int K0, int b, T* 
 }
 
 template <typename T>
-void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
-              int* info) {
+int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
+             int* info, const AuxStreams* ax) {
   // Right-looking blocked Cholesky over DB-wide diagonal blocks: the block
   // is factored and inverted in LDS, the panel below becomes
   // A_panel L_kk^{-T} (one GEMM, in place: a single 128-wide column tile
-  // reads only its own rows), and the trailing matrix gets one rank-b update.
+  // reads only its own rows), and the trailing matrix gets one rank-b update
+  // (with ax: the next column block on st, the rest on st3, see dense.h).
   if (split <= 0 || split >= n) split = 0;
+  bool far_pending = false;
   int K0 = 0;
   while (K0 < n) {
     const int lim = (split > 0 && K0 < split) ? split : n;
@@ -1115,11 +1117,33 @@ void cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, i
       T* panel = A + (int64_t)K1 * lda + K0;
       const T* li = Linv + (int64_t)diag_block_index(K0, split) * DB * DB;
       gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
-      gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
-              lda, sA, batch, GEMM_LOWER);
+      if (!ax) {
+        gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
+                lda, sA, batch, GEMM_LOWER);
+      } else {
+        // the next step's block width (blocks end at the split)
+        const int lim2 = (split > 0 && K1 < split) ? split : n;
+        const int b2 = std::min(DB, lim2 - K1);
+        if (hipEventRecord(ax->ev2, st) != hipSuccess) return -1;
+        // column block k+1 also received the far update of step k-1
+        if (far_pending && hipStreamWaitEvent(st, ax->ev3, 0) != hipSuccess) return -1;
+        gemm<T>(st, 0, 1, rest, b2, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1, lda,
+                sA, batch, GEMM_LOWER);
+        far_pending = rest > b2;
+        if (far_pending) {
+          const int K2 = K1 + b2;
+          T* pf = panel + (int64_t)b2 * lda;
+          if (hipStreamWaitEvent(ax->st3, ax->ev2, 0) != hipSuccess) return -1;
+          gemm<T>(ax->st3, 0, 1, rest - b2, rest - b2, b, T(-1), pf, lda, sA, pf, lda, sA, T(1),
+                  A + (int64_t)K2 * lda + K2, lda, sA, batch, GEMM_LOWER);
+          if (hipEventRecord(ax->ev3, ax->st3) != hipSuccess) return -1;
+        }
+      }
     }
     K0 = K1;
   }
+  if (ax && far_pending && hipStreamWaitEvent(st, ax->ev3, 0) != hipSuccess) return -1;
+  return 0;
 }
 
 // One block step of the triangular inverse (see tri_inverse): block row S
@@ -1235,7 +1259,8 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template void gemm<T>(hipStream_t, int, int, int, int, int, T, const T*, int64_t, int64_t,    \
                         const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int);         \
   template int gemm_autotune<T>(int, int, int, int, int, int, int);                              \
-  template void cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*); \
+  template int cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*,   \
+                           const AuxStreams*);                                                   \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
                                int64_t, T*, int64_t, int64_t);                                      \
   template int cholesky_inverse<T>(hipStream_t, const AuxStreams&, T*, int64_t, int64_t, int, int, T*,  \
