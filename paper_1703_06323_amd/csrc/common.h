@@ -43,15 +43,42 @@ struct BatchDev {
   const int64_t* cell_off;   // [P+1]
   const int64_t* node_off;   // [P+1]
   const int32_t* active;     // [P] problems whose PCG still runs, or null (all)
-  // Work items of the matrix-free operator: the blocks of SEG_ALIGN nodes;
-  // problem p owns items [op_off[p], op_off[p+1]) = node_off / SEG_ALIGN,
-  // op_prob[item] = p.  op_lx, op_lc: lengths of the LDS ranges of x and of
-  // the cell data per block (SEG_ALIGN + 2 (N+1) + 2 and 2 SEG_ALIGN + 2 N +
-  // 2 for the largest N of the context).
+  // Work items of the matrix-free operator, problem p owning items
+  // [op_off[p], op_off[p+1]), op_prob[item] = p, in one of two forms:
+  //  * op_box = 0, node blocks: the blocks of SEG_ALIGN consecutive nodes
+  //    (op_off = node_off / SEG_ALIGN); op_lx, op_lc: lengths of the LDS
+  //    ranges of x and of the cell data per block (SEG_ALIGN + 2 (N+1) + 2
+  //    and 2 SEG_ALIGN + 2 N + 2 for the largest N of the context);
+  //  * op_box = 1, node boxes: SW along x, TY along y, ZC along z (SW TY <=
+  //    SEG_ALIGN threads, one node each per plane, marching over the ZC
+  //    planes); op_geom[8 p ..] = {nseg, SW, TY, ngy, ZC, nzc}: nseg
+  //    x-segments, ngy y-groups and nzc z-chunks, the item's local number
+  //    being (seg ngy + gy) nzc + zc; op_xp, op_cp: the largest tile plane
+  //    of x with its halo, (SW + 2)(TY + 2), and of cells, (SW + 1)(TY + 1).
   const int32_t* op_off;     // [P+1]
   const int32_t* op_prob;    // [items]
-  int32_t op_lx, op_lc;
+  const int32_t* op_geom;    // [8 P] (boxes)
+  int32_t op_box;
+  int32_t op_lx, op_lc;      // (blocks)
+  int32_t op_xp, op_cp;      // (boxes)
 };
+
+// Operator node-box geometry of a problem with N1 = N + 1 nodes per axis
+// (host): x-segments and y-groups whose (SW + 2)(TY + 2) / (SW TY) halo
+// ratio is smallest with at least half a workgroup of nodes per plane, and
+// ZC planes per item so that an item holds about nodes_per_item nodes.
+// Boxes stage each x value about 1.3 times against about 4 (9 for a
+// 256-node block inside one row) for node blocks, but keep fewer threads
+// busy on small meshes; contexts whose meshes all have at least
+// OP_BOX_MIN_N cells per axis use them (environment CUTBDDC_OPERATOR =
+// box or block forces one form).
+struct OpGeom {
+  int32_t nseg, SW, TY, ngy, ZC, nzc;
+};
+OpGeom op_geometry(int N1, int64_t nodes_per_item);
+constexpr int OP_BOX_MIN_N = 128;
+constexpr int OP_XP_MAX = 4 * SEG_ALIGN;   // staging registers per thread: 4 x values
+constexpr int OP_CP_MAX = 3 * SEG_ALIGN;   // and 3 cells
 
 
 // Largest p in [0, P) with off[p] <= i (off ascending, off[0] = 0).

@@ -307,8 +307,8 @@ struct cb_ctx {
 
   // per-problem device tables
   DevBuf kdiag_d;            // diagonal of the uncut reference stiffness (variant 2)
-  DevBuf op_off_d, op_prob_d;   // operator work items (BatchDev::op_off, op_prob)
-  int32_t op_items = 0, op_lx = 0, op_lc = 0;
+  DevBuf op_off_d, op_prob_d, op_geom_d;   // operator work items (BatchDev::op_off, op_prob, op_geom)
+  int32_t op_items = 0, op_box = 0, op_lx = 0, op_lc = 0, op_xp = 0, op_cp = 0;
   DevBuf prob_d, cell_off_d, node_off_d, sub_off_d, dof_off_d, chunk_ptr_d, prow_off_d, coarse_prob_d, sub_prob_d,
       sub_blk_d;
   // device indexing work arrays (kept for the index export)
@@ -379,8 +379,12 @@ struct cb_ctx {
     b.active = masked ? active.as<int32_t>() : nullptr;
     b.op_off = op_off_d.as<int32_t>();
     b.op_prob = op_prob_d.as<int32_t>();
+    b.op_geom = op_geom_d.as<int32_t>();
+    b.op_box = op_box;
     b.op_lx = op_lx;
     b.op_lc = op_lc;
+    b.op_xp = op_xp;
+    b.op_cp = op_cp;
     return b;
   }
   GridDev grid() const {
@@ -891,21 +895,56 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   for (int k = 0; k < P; ++k) sub_offs[k] = c->pb[k].sub_off;
   sub_offs[P] = c->ns;
   CHK(upload(c->sub_off_d, sub_offs, st));
-  // operator work items: the node blocks of every problem
+  // operator work items: node boxes (every mesh large) or node blocks
   {
-    std::vector<int32_t> op_offs(P + 1, 0), op_prob((size_t)(c->nn / SEG_ALIGN));
-    int maxN = 1;
+    int minN = 1 << 30, maxN = 1;
+    int64_t all_nodes = 0;
     for (int k = 0; k < P; ++k) {
-      op_offs[k + 1] = (int32_t)(node_offs[k + 1] / SEG_ALIGN);
-      for (int32_t it = op_offs[k]; it < op_offs[k + 1]; ++it) op_prob[it] = k;
+      minN = std::min(minN, c->pb[k].N);
       maxN = std::max(maxN, c->pb[k].N);
+      all_nodes += (int64_t)(c->pb[k].N + 1) * (c->pb[k].N + 1) * (c->pb[k].N + 1);
     }
-    c->op_items = op_offs[P];
+    // CUTBDDC_OPERATOR = block, box or box:<nodes per box> overrides the choice
+    const char* mode = std::getenv("CUTBDDC_OPERATOR");
+    int64_t per_item_forced = 0;
+    if (mode && std::strncmp(mode, "box", 3) == 0) {
+      c->op_box = 1;
+      if (mode[3] == ':') per_item_forced = std::max<long long>(1, std::atoll(mode + 4));
+    } else {
+      c->op_box = mode && std::strcmp(mode, "block") == 0 ? 0 : (minN >= OP_BOX_MIN_N ? 1 : 0);
+    }
+    std::vector<int32_t> op_offs(P + 1, 0), op_prob, geom((size_t)8 * P, 0);
     c->op_lx = SEG_ALIGN + 2 * (maxN + 1) + 2;
     c->op_lc = 2 * SEG_ALIGN + 2 * maxN + 2;
+    c->op_xp = c->op_cp = 1;
+    if (c->op_box) {
+      // about 2048 boxes in the context, of at most 2048 nodes each
+      const int64_t per_item = per_item_forced ? per_item_forced
+                                               : std::min<int64_t>(2048, std::max<int64_t>(1, all_nodes / 2048));
+      for (int k = 0; k < P; ++k) {
+        const OpGeom g = op_geometry(c->pb[k].N + 1, per_item);
+        int32_t* gk = &geom[(size_t)8 * k];
+        gk[0] = g.nseg, gk[1] = g.SW, gk[2] = g.TY, gk[3] = g.ngy, gk[4] = g.ZC, gk[5] = g.nzc;
+        const int32_t items = g.nseg * g.ngy * g.nzc;
+        op_offs[k + 1] = op_offs[k] + items;
+        op_prob.insert(op_prob.end(), (size_t)items, k);
+        c->op_xp = std::max(c->op_xp, (g.SW + 2) * (g.TY + 2));
+        c->op_cp = std::max(c->op_cp, (g.SW + 1) * (g.TY + 1));
+      }
+      if (c->op_xp > OP_XP_MAX || c->op_cp > OP_CP_MAX)
+        return fail(CB_ERR_ARG, "operator node box exceeds its staging registers");
+    } else {
+      op_prob.resize((size_t)(c->nn / SEG_ALIGN));
+      for (int k = 0; k < P; ++k) {
+        op_offs[k + 1] = (int32_t)(node_offs[k + 1] / SEG_ALIGN);
+        for (int32_t it = op_offs[k]; it < op_offs[k + 1]; ++it) op_prob[it] = k;
+      }
+    }
+    c->op_items = op_offs[P];
     CHK(upload(c->op_off_d, op_offs, st));
     CHK(upload(c->op_prob_d, op_prob, st));
-    if (prepare_apply_A() != 0) return fail(CB_ERR_DEVICE, "setting the operator kernel's LDS limit failed");
+    CHK(upload(c->op_geom_d, geom, st));
+    if (prepare_apply_A() != 0) return fail(CB_ERR_DEVICE, "setting the operator kernels' LDS limits failed");
   }
   const int64_t nn = c->nn, ncell = c->n_cells_tot;
   const int ns = c->ns;

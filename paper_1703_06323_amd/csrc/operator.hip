@@ -7,6 +7,8 @@
 // active cells around it; no atomics, fixed summation order.
 #include "common.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace cutbddc {
@@ -100,13 +102,13 @@ __device__ inline int32_t xcd_item(int32_t b, int32_t G) {
   return (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + k;
 }
 
-// Cell C = u + 2 vv + 4 w around node (I, J, K) of the operator kernel,
+// Cell C = u + 2 vv + 4 w around node (I, J, K) of the node-block operator kernel,
 // without branches except around a cut cell's row load: a cell outside the
 // grid counts as inactive (its staged code belongs to another cell), and an
 // inactive one adds nothing.  cc stays inside the staged cell ranges for
 // every node of the block.
 template <int C>
-__device__ __forceinline__ void op_cell(int I, int J, int K, int N, int LC, int co, const int32_t* cs,
+__device__ __forceinline__ void op_cell_lin(int I, int J, int K, int N, int LC, int co, const int32_t* cs,
                                         const double* ks, const double* __restrict__ Kf,
                                         const double (&xn)[3][3][3], double& acc, bool& touched) {
   constexpr int u = C & 1, vv = (C >> 1) & 1, w = C >> 2;
@@ -139,7 +141,8 @@ __device__ __forceinline__ void op_cell(int I, int J, int K, int N, int LC, int 
   acc = act ? t : acc;
 }
 
-// Matrix-free A-bar x.  A workgroup takes a block of SEG_ALIGN consecutive
+// Matrix-free A-bar x, node-block form (contexts whose meshes are all small
+// enough: see op_use_boxes).  A workgroup takes a block of SEG_ALIGN consecutive
 // nodes of one problem (its problem read from op_prob, no search) and first
 // stages in LDS, with independent coalesced loads:
 //  * x on the three node ranges that hold the blocks' neighbours in the
@@ -157,7 +160,7 @@ __device__ __forceinline__ void op_cell(int I, int J, int K, int N, int LC, int 
 // copy Kf (one 64-byte segment per row).  DOF nodes are the interior nodes next to an
 // active cell; every other node of the block gets 0.  Staged entries outside
 // the problem, and cells whose coordinates leave the grid, are never used.
-__global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t n_items,
+__global__ __launch_bounds__(SEG_ALIGN) void apply_A_lin_kernel(BatchDev bd, int32_t n_items,
                                                             const int32_t* __restrict__ cellinfo,
                                                             const double* __restrict__ kappa,
                                                             const double* __restrict__ Kf,
@@ -247,18 +250,18 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) xn[dz][dy][dx] = xs[dz * LX + xo + (dx - 1) + N1 * (dy - 1)];
     xv0 = xn[1][1][1];
-    // The 8 cells around the node, in the load's order (op_cell<C> below,
+    // The 8 cells around the node, in the load's order (op_cell_lin<C> below,
     // one instantiation per cell so that every index is a constant)
     double acc = 0.0;
     bool touched = false;
-    op_cell<0>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<1>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<2>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<3>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<4>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<5>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<6>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
-    op_cell<7>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<0>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<1>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<2>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<3>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<4>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<5>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<6>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
+    op_cell_lin<7>(I, J, K, N, LC, co, cs, ks, Kf, xn, acc, touched);
     const bool interior = I >= 1 && I < N && J >= 1 && J < N && K >= 1 && K < N;
     v = (interior && touched) ? acc : 0.0;
   }
@@ -267,6 +270,201 @@ __global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t
   if (dpart) {
     const double t = wg_sum_all(xv0 * v, sh);
     if (threadIdx.x == 0) dpart[item] = t;
+  }
+}
+
+// Cell C = u + 2 vv + 4 w around a node of the operator kernel, without
+// branches except around a cut cell's row load.  cs / ks: the staged cell
+// codes and kappa h of the two cell layers below (w = 0) and above (w = 1)
+// the node's plane, at c0 + w cstride + vv CX + u (cells outside the grid
+// are staged as inactive); an inactive cell adds nothing.
+template <int C>
+__device__ __forceinline__ void op_cell(const int32_t* cs, const double* ks, int c0, int cstride, int CX,
+                                        const double* __restrict__ Kf, const double (&xn)[3][3][3], double& acc,
+                                        bool& touched) {
+  constexpr int u = C & 1, vv = (C >> 1) & 1, w = C >> 2;
+  constexpr int a = 7 - C;                               // the node's corner in the cell
+  const int cc = c0 + w * cstride + vv * CX + u;
+  const int32_t info = cs[cc];
+  const bool act = info != CELL_INACTIVE;
+  touched = touched || act;
+  // row a of the cell matrix times x: the reference row (constant
+  // operands), replaced for a cut cell by its row from the full row-major
+  // copy (64 contiguous bytes)
+  double row = 0.0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+    row = fma(c_Kref[a * 8 + b], xn[w + ((b >> 2) & 1)][vv + ((b >> 1) & 1)][u + (b & 1)], row);
+  if (info >= 0) {
+    const double2* R = reinterpret_cast<const double2*>(Kf + (int64_t)info * 64 + a * 8);
+    double rc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v2 = R[q];
+      rc = fma(v2.x, xn[w + (((2 * q) >> 2) & 1)][vv + (((2 * q) >> 1) & 1)][u + ((2 * q) & 1)], rc);
+      rc = fma(v2.y, xn[w + (((2 * q + 1) >> 2) & 1)][vv + (((2 * q + 1) >> 1) & 1)][u + ((2 * q + 1) & 1)], rc);
+    }
+    row = rc;
+  }
+  const double t = fma(ks[cc], row, acc);
+  acc = act ? t : acc;
+}
+
+// Matrix-free A-bar x, node-box form (contexts with large meshes).  A
+// workgroup takes one node box of one problem: nx
+// <= SW nodes along x, ny <= TY along y (one thread per (x, y) column) and
+// nz <= ZC planes, which it marches through.  It keeps in LDS, as rings,
+// three planes of x over the box's columns and their one-node halo
+// ((nx + 2)(ny + 2) values each) and two layers of cell codes and kappa h
+// over the (nx + 1)(ny + 1) cells around them; at each plane the loads of
+// the next plane and cell layer are issued before the arithmetic, so their
+// latency overlaps it.  Each thread sums over the (up to 8) active cells
+// around its node kappa_e h (row a of the cell matrix) . x_e, in the same
+// order as the load's node gather.  DOF nodes are the interior nodes next
+// to an active cell; every other node gets 0, and the first item of a
+// problem also clears the alignment padding after its nodes.
+__global__ __launch_bounds__(SEG_ALIGN) void apply_A_kernel(BatchDev bd, int32_t n_items,
+                                                            const int32_t* __restrict__ cellinfo,
+                                                            const double* __restrict__ kappa,
+                                                            const double* __restrict__ Kf,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y, double* __restrict__ dpart) {
+  extern __shared__ double op_lds[];
+  __shared__ double sh[SEG_ALIGN / 64];
+  const int32_t item = xcd_item((int32_t)blockIdx.x, n_items);
+  const int p = bd.op_prob[item];
+  if (bd.active && !bd.active[p]) return;
+  const ProbDev pr = bd.prob[p];
+  const int32_t* gm = bd.op_geom + 8 * p;
+  const int SW = gm[1], TY = gm[2], ngy = gm[3], ZC = gm[4], nzc = gm[5];
+  // local node and cell numbers fit 32 bits: N <= 1024 (setup checks it)
+  const int N = pr.N, N1 = N + 1;
+  const int li = item - bd.op_off[p];
+  const int zc = li % nzc, rest = li / nzc, gy = rest % ngy, seg = rest / ngy;
+  const int x0 = seg * SW, nx = min(SW, N1 - x0);
+  const int y0 = gy * TY, ny = min(TY, N1 - y0);
+  const int z0 = zc * ZC, nz = min(ZC, N1 - z0);
+  const int PX = nx + 2, XPL = PX * (ny + 2);            // x tile plane with its halo
+  const int CX = nx + 1, CPL = CX * (ny + 1);            // cell tile layer
+  const int XS = bd.op_xp, CS = bd.op_cp;                // ring slot strides
+  double* xs = op_lds;                                   // [3][XS]
+  double* ks = xs + 3 * XS;                              // [2][CS] kappa h
+  int32_t* cs = reinterpret_cast<int32_t*>(ks + 2 * CS); // [2][CS] cell code
+  const double* xp = x + pr.node_off;
+  const int32_t* cip = cellinfo + pr.cell_off;
+  const double* kp = kappa + pr.cell_off;
+  const int t = threadIdx.x;
+  const double h = pr.h;
+  // staging of node plane K (x over the tile and halo) and of cell layer
+  // Kc (codes and kappa h), through registers
+  constexpr int RX = OP_XP_MAX / SEG_ALIGN, RC = OP_CP_MAX / SEG_ALIGN;
+  double xr[RX], kr[RC];
+  int32_t cr[RC];
+  auto load_plane = [&](int K) {
+#pragma unroll
+    for (int q = 0; q < RX; ++q) {
+      const int idx = t + q * SEG_ALIGN;
+      const int ix = idx % PX, iy = idx / PX;
+      const int gx = x0 - 1 + ix, gyy = y0 - 1 + iy;
+      const bool ok = idx < XPL && (unsigned)gx < (unsigned)N1 && (unsigned)gyy < (unsigned)N1 &&
+                      (unsigned)K < (unsigned)N1;
+      xr[q] = ok ? xp[gx + N1 * (gyy + N1 * K)] : 0.0;
+    }
+  };
+  auto store_plane = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < RX; ++q) {
+      const int idx = t + q * SEG_ALIGN;
+      if (idx < XPL) xs[slot * XS + idx] = xr[q];
+    }
+  };
+  auto load_layer = [&](int Kc) {
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+      const int idx = t + q * SEG_ALIGN;
+      const int ix = idx % CX, iy = idx / CX;
+      const int gx = x0 - 1 + ix, gyy = y0 - 1 + iy;
+      const bool ok = idx < CPL && (unsigned)gx < (unsigned)N && (unsigned)gyy < (unsigned)N &&
+                      (unsigned)Kc < (unsigned)N;
+      const int c = ok ? gx + N * (gyy + N * Kc) : 0;
+      cr[q] = ok ? cip[c] : CELL_INACTIVE;
+      kr[q] = ok ? kp[c] : 0.0;
+    }
+  };
+  auto store_layer = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+      const int idx = t + q * SEG_ALIGN;
+      if (idx < CPL) {
+        cs[slot * CS + idx] = cr[q];
+        ks[slot * CS + idx] = kr[q] * h;
+      }
+    }
+  };
+  // planes z0 - 1 and z0 (slots 0, 1), cell layer z0 - 1 (slot 0); then the
+  // loads of plane z0 + 1 and layer z0
+  load_plane(z0 - 1);
+  store_plane(0);
+  load_plane(z0);
+  store_plane(1);
+  load_layer(z0 - 1);
+  store_layer(0);
+  load_plane(z0 + 1);
+  load_layer(z0);
+  const bool mine = t < nx * ny;
+  const int tx = mine ? t % nx : 0, ty = mine ? t / nx : 0;
+  const int I = x0 + tx, J = y0 + ty;
+  double dot = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const int z = z0 + k;
+    // plane z + 1 into slot (k + 2) % 3 (plane z - 2 held it), layer z into
+    // slot (k + 1) % 2 (layer z - 2 held it)
+    store_plane((k + 2) % 3);
+    store_layer((k + 1) % 2);
+    __syncthreads();
+    if (k + 1 < nz) {
+      load_plane(z + 2);
+      load_layer(z + 1);
+    }
+    if (mine) {
+      double xn[3][3][3];
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        const double* pl = xs + ((k + dz) % 3) * XS;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) xn[dz][dy][dx] = pl[(ty + dy) * PX + tx + dx];
+      }
+      // cell layers z - 1 (slot k % 2) and z (slot (k + 1) % 2)
+      const int s0 = k & 1;
+      const int c0 = s0 * CS + ty * CX + tx;
+      const int cstride = s0 ? -CS : CS;
+      double acc = 0.0;
+      bool touched = false;
+      op_cell<0>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<1>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<2>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<3>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<4>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<5>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<6>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      op_cell<7>(cs, ks, c0, cstride, CX, Kf, xn, acc, touched);
+      const bool interior = I >= 1 && I < N && J >= 1 && J < N && z >= 1 && z < N;
+      const double v = (interior && touched) ? acc : 0.0;
+      y[pr.node_off + I + (int64_t)N1 * (J + (int64_t)N1 * z)] = v;
+      dot = fma(xn[1][1][1], v, dot);
+    }
+    __syncthreads();
+  }
+  if (li == 0) {
+    // the alignment padding after the problem's nodes
+    const int64_t e0 = pr.node_off + (int64_t)N1 * N1 * N1, e1 = bd.node_off[p + 1];
+    for (int64_t i = e0 + t; i < e1; i += SEG_ALIGN) y[i] = 0.0;
+  }
+  if (dpart) {
+    const double tsum = wg_sum_all(dot, sh);
+    if (t == 0) dpart[item] = tsum;
   }
 }
 
@@ -591,10 +789,39 @@ void set_reference_matrices(const double* Kref, const double* Mref) {
 }
 
 int prepare_apply_A() {
-  // 128 KB covers N up to 1024 (116 KB); the kernel's static LDS comes on top
-  static const hipError_t e = hipFuncSetAttribute((const void*)apply_A_kernel,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-  return e == hipSuccess ? 0 : -1;
+  // node blocks: 128 KB covers N up to 1024 (116 KB); node boxes: the rings
+  // need at most 3 OP_XP_MAX + 2 OP_CP_MAX doubles and 2 OP_CP_MAX codes
+  // (42 KB); the kernels' static LDS comes on top
+  static const hipError_t e1 = hipFuncSetAttribute((const void*)apply_A_lin_kernel,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+  static const hipError_t e2 = hipFuncSetAttribute((const void*)apply_A_kernel,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+  return e1 == hipSuccess && e2 == hipSuccess ? 0 : -1;
+}
+
+OpGeom op_geometry(int N1, int64_t nodes_per_item) {
+  OpGeom best{1, N1, 1, N1, 1, N1};
+  double best_ratio = 1e300;
+  for (int nseg = 1; nseg <= 64; ++nseg) {
+    const int SW = (N1 + nseg - 1) / nseg;
+    if (SW > SEG_ALIGN) continue;
+    const int tymax = SEG_ALIGN / SW;
+    const int ngy = (N1 + tymax - 1) / tymax;
+    const int TY = (N1 + ngy - 1) / ngy;
+    // at least half a workgroup of nodes per plane, when the mesh allows it
+    if (2 * SW * TY < SEG_ALIGN && N1 * std::min(N1, tymax) >= SEG_ALIGN / 2) continue;
+    const double ratio = (double)(SW + 2) * (TY + 2) / ((double)SW * TY);
+    if (ratio < best_ratio - 1e-12) {
+      best_ratio = ratio;
+      best = OpGeom{(N1 + SW - 1) / SW, SW, TY, ngy, 1, N1};
+    }
+    if (SW <= 8) break;
+  }
+  const int64_t per_plane = (int64_t)best.SW * best.TY;
+  const int zc = (int)std::max<int64_t>(1, std::min<int64_t>(32, (nodes_per_item + per_plane / 2) / per_plane));
+  best.nzc = (N1 + zc - 1) / zc;
+  best.ZC = (N1 + best.nzc - 1) / best.nzc;
+  return best;
 }
 
 __global__ void expand_rows_kernel(int64_t n, const double* __restrict__ Kc, double* __restrict__ Kf) {
@@ -615,9 +842,15 @@ void launch_apply_A(hipStream_t st, const BatchDev& b, int64_t nn, int32_t n_ite
                     double* dpart) {
   (void)dofmask;
   if (nn <= 0 || n_items <= 0) return;
-  const size_t sh = (size_t)(3 * b.op_lx + 2 * b.op_lc) * sizeof(double) + (size_t)2 * b.op_lc * sizeof(int32_t);
-  hipLaunchKernelGGL(apply_A_kernel, dim3((unsigned)n_items), dim3(SEG_ALIGN), sh, st, b, n_items, cellinfo, kappa,
-                     Kf, x, y, dpart);
+  if (b.op_box) {
+    const size_t sh = (size_t)(3 * b.op_xp + 2 * b.op_cp) * sizeof(double) + (size_t)2 * b.op_cp * sizeof(int32_t);
+    hipLaunchKernelGGL(apply_A_kernel, dim3((unsigned)n_items), dim3(SEG_ALIGN), sh, st, b, n_items, cellinfo, kappa,
+                       Kf, x, y, dpart);
+  } else {
+    const size_t sh = (size_t)(3 * b.op_lx + 2 * b.op_lc) * sizeof(double) + (size_t)2 * b.op_lc * sizeof(int32_t);
+    hipLaunchKernelGGL(apply_A_lin_kernel, dim3((unsigned)n_items), dim3(SEG_ALIGN), sh, st, b, n_items, cellinfo,
+                       kappa, Kf, x, y, dpart);
+  }
 }
 
 void launch_load(hipStream_t st, const BatchDev& b, int64_t nn, const int32_t* cellinfo,

@@ -299,3 +299,51 @@ def test_fp32_breakdown_refactored_in_fp64(monkeypatch):
     r = np.random.default_rng(3).standard_normal(s.n_dof)
     z, z0 = s.apply_preconditioner(r).cpu().numpy(), s0.apply_preconditioner(r).cpu().numpy()
     assert rel(z, z0) < 1e-5
+
+
+BOX_CASES = ["single_ball_v1_stiffness", "balls16_s4", "balls24_s8_lognormal", "balls32_s8_ce", "uncut16_s4",
+             "one_subdomain", "full_elements"]
+
+
+@pytest.mark.parametrize("per_box", [1, 2048])
+@pytest.mark.parametrize("name", BOX_CASES)
+def test_operator_node_boxes(name, per_box, monkeypatch):
+    """The node-box form of the operator (chosen by setup for large meshes),
+    forced on the small cases: one plane per box, and boxes marching over up
+    to 32 planes."""
+    from paper_1703_06323_amd import Solver
+    monkeypatch.setenv("CUTBDDC_OPERATOR", f"box:{per_box}")
+    o = oracle(name)
+    say(f"[gpu] node-box operator {name} {per_box}")
+    s = Solver(CASES[name]())
+    x = np.random.default_rng(43).standard_normal(o.n_dof)
+    y = s.apply_operator(x).cpu().numpy()
+    yo = o.d.A @ x
+    assert elementwise(y, yo) < 1e-13
+    s.close()
+
+
+def test_node_box_solves_match_node_block_solves(monkeypatch):
+    """PCG (whose p.q parts come from the operator kernel) with node boxes,
+    one problem and a batch of three, against the node-block form."""
+    from paper_1703_06323_amd import BatchSolver, Solver
+    probs = [W.random_balls(16, 4, 6, 3), W.random_balls(24, 4, 8, 4, lognormal_kappa=True), W.single_ball()]
+    res = {}
+    for mode in ("block", "box:2048"):
+        monkeypatch.setenv("CUTBDDC_OPERATOR", mode)
+        say(f"[gpu] solves with operator {mode}")
+        s = Solver(probs[0])
+        s.factor()
+        u, it, _ = s.solve(probs[0].f, rtol=1e-8)
+        b = BatchSolver(probs)
+        b.factor()
+        us, its, _ = b.solve([p.f for p in probs], rtol=1e-8)
+        res[mode] = (u.cpu().numpy(), it, [v.cpu().numpy() for v in us], list(its))
+        s.close()
+        b.close()
+    ub, itb, usb, itsb = res["block"]
+    ux, itx, usx, itsx = res["box:2048"]
+    assert itx == itb and itsx == itsb
+    assert elementwise(ux, ub) < 1e-10
+    for a, c in zip(usx, usb):
+        assert elementwise(a, c) < 1e-10

@@ -114,6 +114,18 @@ def cut_cube_96_lognormal(seed: int = 2) -> Problem:
     return p.with_options(local_precision=FP32_LOCAL)
 
 
+def operator_256(seed: int = 5) -> Problem:
+    """256^3 cells, 32^3 subdomains of 8^3 cells, 200 balls with centres
+    U(0.1,0.9)^3 then radii U(0.02,0.05), kappa = 1: the mesh whose operator
+    working set (x, y, cell data: about 470 MB) exceeds the 256 MB MALL.
+    Used for the operator apply only (its dense coarse problem would not
+    fit)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.1, 0.9, size=(200, 3))
+    r = rng.uniform(0.02, 0.05, size=(200,))
+    return Problem(n=256, s=8, centres=c, radii=r, name="operator_256_balls200")
+
+
 def batch_256(seed: int = 3, count: int = 256) -> List[Problem]:
     """`count` independent problems.  Per problem k, in order: N_k uniform from
     {16, 24, 32, 48}; n_b,k integer in [5, 30]; centres; radii; f.  kappa = 1,
