@@ -1354,9 +1354,16 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
                              c->Ds.as<double>() + (int64_t)w0 * nt, StV.as<double>(), StC.as<int32_t>());
     HIPCHK(hipGetLastError());
     int chol_rc = 0;
+    // rows [nI, NIp) and [NIp + nG, nt) of K are identity padding: the
+    // dense products skip the tiles and k stages that only meet them
+    GemmRows act;
+    act.na = sd.nI;
+    act.nb = sd.nG;
+    act.split = NIp;
     timed(c, "local_cholesky", [&] {
       const AuxStreams ax{c->aux_st, c->aux_st3, c->aux_ev, c->aux_ev3};
-      chol_rc = cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0, &ax);
+      chol_rc = cholesky<T>(st, K.as<T>(), nt, sK, nt, NIp, nc, Linv.as<T>(), sL, c->info_d.as<int>() + w0, &ax,
+                            &act);
     });
     if (chol_rc != 0) return fail(CB_ERR_DEVICE, "event record or wait failed in the local factorisation");
     HIPCHK(hipGetLastError());
@@ -1369,11 +1376,12 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
       HIPCHK(hipEventRecord(c->aux_ev, st));
       HIPCHK(hipStreamWaitEvent(sti, c->aux_ev, 0));
     }
-    // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I
+    // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I (zero on the padding, which no
+    // later step reads)
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(sti, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, YI.as<T>(), NIp, sI2);
+      tri_inverse<T>(sti, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, YI.as<T>(), NIp, sI2, &act);
       gemm<T>(sti, 1, 0, NIp, NIp, NIp, T(1), YI.as<T>(), NIp, sI2, YI.as<T>(), NIp, sI2, T(0), PSI.as<T>(), NIp,
-              sI2, nc, GEMM_LOWER | GEMM_KFROM_DIAG);
+              sI2, nc, GEMM_LOWER | GEMM_KFROM_DIAG, act);
     });
     launch_pack_lower<T, TS>(sti, NIp, nc, PSI.as<T>(), NIp, sI2, Dsw, nt, c->P_.as<TS>() + (int64_t)w0 * pkI);
     // full FP64 copy of A_II^{-1} for the harmonic extension of the coarse basis
@@ -1382,10 +1390,11 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     const double* Pd = Pd64.as<double>();
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
+    // (zero on the padding)
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, &act);
       gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, nc,
-              GEMM_LOWER | GEMM_KFROM_DIAG);
+              GEMM_LOWER | GEMM_KFROM_DIAG, act.at(NIp, NIp, NIp));
     });
     symmetrize_scale<T, double>(st, PS.as<T>(), NGp, sY, KS, NGp, sKS, Dsw + NIp, nt, NGp, nc);
     HIPCHK(hipGetLastError());

@@ -17,11 +17,36 @@ enum GemmMode {
 
 constexpr int CHOL_BLOCK = 32;
 
+// Padded batches: matrix b of a batch is nonzero only on the index set
+// [0, na[b]) u [split, split + nb[b]) of a common index space (rows, columns
+// and the k of a product may be offset into it by r_off, c_off and k_off);
+// outside it only the diagonal may be nonzero, and no product reads it.
+// Given to gemm(), every output tile whose rows or columns miss the set, or
+// whose k range does, takes no product (its C is left as is when beta = 1,
+// else becomes beta C), and the k loop of the other tiles covers only the
+// hull of the set's k (rounded down to a stage).  The result is exact when
+// A and B vanish outside the set; an output entry with both indices outside
+// it then gets beta C instead of the product of the padding diagonals.
+// nb may be null (one range).  Device pointers, indexed by the batch entry.
+struct GemmRows {
+  const int32_t* na = nullptr;
+  const int32_t* nb = nullptr;
+  int32_t split = 0;
+  int32_t r_off = 0, c_off = 0, k_off = 0;
+  GemmRows at(int r, int c, int k) const {
+    GemmRows g = *this;
+    g.r_off = r;
+    g.c_off = c;
+    g.k_off = k;
+    return g;
+  }
+};
+
 // C = alpha op(A) op(B) + beta C; TA/TB = 0 plain, 1 transposed storage.
 template <typename T>
 void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
           int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
-          int batch, int mode);
+          int batch, int mode, const GemmRows& rows = GemmRows{});
 
 // Times every GEMM tile shape on scratch matrices of the bucket of
 // (TA, TB, M, N, K, batch, mode) and records the fastest for later calls of
@@ -58,17 +83,22 @@ inline int diag_block_index(int p, int split) {
 // block k+1 and goes on to factor it, while ax->st3 updates the rest of the
 // trailing matrix; st waits for st3 before returning.  Returns -1 if an
 // event record or wait fails.
+// rows (optional): the nonzero index sets of the matrices (GemmRows with
+// offsets 0; the padding outside them holds the identity): the panel and
+// trailing updates skip the tiles and k stages that only meet padding.
 struct AuxStreams;
 template <typename T>
 int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
-             int* info, const AuxStreams* ax = nullptr);
+             int* info, const AuxStreams* ax = nullptr, const GemmRows* rows = nullptr);
 
 // Y = inverse of the lower-triangular diagonal range [off, off+nb) of L
 // (off and off+nb block starts of the same split), from the diagonal-block
-// inverses written by cholesky().
+// inverses written by cholesky().  rows (optional, as for cholesky(), in
+// the index space of L): the updates skip padding tiles; Y is still the
+// identity on the padding.
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY);
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows = nullptr);
 
 // Streams and events lent to cholesky_inverse by the caller (default
 // priority, non-blocking).  The events are recorded and waited on at every

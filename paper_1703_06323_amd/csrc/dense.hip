@@ -81,7 +81,7 @@ template <typename T, int TA, int TB, int BM, int BN, int DEPTH = 1, int KB = 12
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M, int N, int K, T alpha, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA, const T* __restrict__ B,
                                                    int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
-                                                   int64_t sC, int mode, int vec, int swz) {
+                                                   int64_t sC, int mode, int vec, int swz, GemmRows rows) {
   typedef typename Vec16<T>::type V;
   constexpr int VW = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int KT = KB / (int)sizeof(T);       // k per stage
@@ -137,6 +137,31 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   int kbeg = 0, kend = K;
   if (mode & GEMM_KFROM_DIAG) kbeg = (max(row0, col0) / KT) * KT;
   if (mode & GEMM_KTO_DIAG) kend = min(K, row0 + BM);
+  if (rows.na) {
+    // padded batch (GemmRows): the nonzero index set of matrix bz is
+    // [0, na) u [sp, sp + nb)
+    const int na = rows.na[bz], nb = rows.nb ? rows.nb[bz] : 0, sp = rows.split;
+    auto meets = [&](int lo, int hi) { return (lo < na && hi > 0) || (nb > 0 && lo < sp + nb && hi > sp); };
+    const int g0 = kbeg + rows.k_off, g1 = kend + rows.k_off;
+    int lo = g1, hi = g0;   // hull of the set within [g0, g1)
+    if (g0 < na && g1 > 0) {
+      lo = max(g0, 0);
+      hi = min(g1, na);
+    }
+    if (nb > 0 && g0 < sp + nb && g1 > sp) {
+      lo = min(lo, max(g0, sp));
+      hi = max(hi, min(g1, sp + nb));
+    }
+    const bool live = lo < hi && meets(rows.r_off + row0, rows.r_off + row0 + BM) &&
+                      meets(rows.c_off + col0, rows.c_off + col0 + BN);
+    if (!live) {
+      if (beta == T(1)) return;
+      kend = kbeg;   // no product: the epilogue writes beta C
+    } else {
+      kbeg = max(kbeg, ((lo - rows.k_off) / KT) * KT);
+      kend = hi - rows.k_off;
+    }
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int wr = wv / WGN, wc = wv % WGN;
@@ -946,7 +971,7 @@ bool gemm_xcd_swizzle() {
 template <typename T>
 void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A,
                  int64_t lda, int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc,
-                 int64_t sC, int batch, int mode) {
+                 int64_t sC, int batch, int mode, const GemmRows& rows = GemmRows{}) {
   // shapes: 0-3 = 64x64, 128x64, 64x128, 128x128 (128-byte k stages);
   // 4 = 64x64 and 5 = 32x64 with 512-byte stages; 6 = 64x128 and 7 = 128x64
   // with 256-byte stages
@@ -960,7 +985,7 @@ void gemm_launch(int shape, hipStream_t st, int TA, int TB, int M, int N, int K,
 #define GEMM_CASE(a, b, sh, bm, bn, kb)                                                                   \
   if (TA == a && TB == b && shape == sh) {                                                                 \
     hipLaunchKernelGGL((gemm_kernel<T, a, b, bm, bn, 1, kb>), grid, dim3(64 * (bm / 32) * (bn / 32)), 0, st, M, \
-                       N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz);             \
+                       N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, mode, vec, swz, rows);       \
     return;                                                                                                \
   }
 #define GEMM_SHAPES(a, b)                                                                              \
@@ -984,7 +1009,7 @@ void gemm_set_thread_tuning(bool on) { t_tuning = on; }
 template <typename T>
 void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T* A, int64_t lda,
           int64_t sA, const T* B, int64_t ldb, int64_t sB, T beta, T* C, int64_t ldc, int64_t sC,
-          int batch, int mode) {
+          int batch, int mode, const GemmRows& rows) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   // C == A: one tile column, whose tiles read only their own rows of A;
   // C == B: one tile row, whose tiles read only their own columns of B
@@ -1002,7 +1027,7 @@ void gemm(hipStream_t st, int TA, int TB, int M, int N, int K, T alpha, const T*
     if (inplace == IN_PLACE_A) shape = N > 64 ? 2 : 0;
     if (inplace == IN_PLACE_B) shape = M > 64 ? 1 : 0;
   }
-  gemm_launch<T>(shape, st, TA, TB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, mode);
+  gemm_launch<T>(shape, st, TA, TB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, mode, rows);
 }
 
 template <typename T>
@@ -1098,7 +1123,9 @@ void diag_step(hipStream_t st, T* A, int64_t lda, int64_t sA, int K0, int b, T* 
 
 template <typename T>
 int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, int batch, T* Linv, int64_t sL,
-             int* info, const AuxStreams* ax) {
+             int* info, const AuxStreams* ax, const GemmRows* rows) {
+  const GemmRows none{};
+  const GemmRows& rs = rows ? *rows : none;
   // Right-looking blocked Cholesky over DB-wide diagonal blocks: the block
   // is factored and inverted in LDS, the panel below becomes
   // A_panel L_kk^{-T} (one GEMM, in place: a single 128-wide column tile
@@ -1116,10 +1143,11 @@ int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, in
     if (rest > 0) {
       T* panel = A + (int64_t)K1 * lda + K0;
       const T* li = Linv + (int64_t)diag_block_index(K0, split) * DB * DB;
-      gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0);
+      gemm<T>(st, 0, 1, rest, b, b, T(1), panel, lda, sA, li, DB, sL, T(0), panel, lda, sA, batch, 0,
+              rs.at(K1, K0, K0));
       if (!ax) {
         gemm<T>(st, 0, 1, rest, rest, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1,
-                lda, sA, batch, GEMM_LOWER);
+                lda, sA, batch, GEMM_LOWER, rs.at(K1, K1, K0));
       } else {
         // the next step's block width (blocks end at the split)
         const int lim2 = (split > 0 && K1 < split) ? split : n;
@@ -1128,14 +1156,14 @@ int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, in
         // column block k+1 also received the far update of step k-1
         if (far_pending && hipStreamWaitEvent(st, ax->ev3, 0) != hipSuccess) return -1;
         gemm<T>(st, 0, 1, rest, b2, b, T(-1), panel, lda, sA, panel, lda, sA, T(1), A + (int64_t)K1 * lda + K1, lda,
-                sA, batch, GEMM_LOWER);
+                sA, batch, GEMM_LOWER, rs.at(K1, K1, K0));
         far_pending = rest > b2;
         if (far_pending) {
           const int K2 = K1 + b2;
           T* pf = panel + (int64_t)b2 * lda;
           if (hipStreamWaitEvent(ax->st3, ax->ev2, 0) != hipSuccess) return -1;
           gemm<T>(ax->st3, 0, 1, rest - b2, rest - b2, b, T(-1), pf, lda, sA, pf, lda, sA, T(1),
-                  A + (int64_t)K2 * lda + K2, lda, sA, batch, GEMM_LOWER);
+                  A + (int64_t)K2 * lda + K2, lda, sA, batch, GEMM_LOWER, rs.at(K2, K2, K0));
           if (hipEventRecord(ax->ev3, ax->st3) != hipSuccess) return -1;
         }
       }
@@ -1152,7 +1180,8 @@ int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, in
 // below it, both final once the Cholesky sweep has passed that block.
 template <typename T>
 void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, int S0, int h, int row_end = -1) {
+                      const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, int S0, int h, int row_end = -1,
+                      const GemmRows& rs = GemmRows{}) {
   const int send = S0 + h;
   // rows at or past row_end have L[row, S] = 0: their update is exactly zero
   const int rend = row_end < 0 ? nb : std::min(nb, row_end);
@@ -1164,20 +1193,20 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
   // same values exactly).
   if (S0 > 0)
     gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
-            sY, batch, 0);
+            sY, batch, 0, rs.at(off + S0, off, off + S0));
   hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, li, DB, sLi,
                      Y + (int64_t)S0 * ldy + S0, ldy, sY, h);
   const int rest = rend - send;
   if (rest > 0) {
     const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
     gemm<T>(st, 0, 0, rest, send, h, T(-1), LlS, ldl, sL, Y + (int64_t)S0 * ldy, ldy, sY, T(1),
-            Y + (int64_t)send * ldy, ldy, sY, batch, 0);
+            Y + (int64_t)send * ldy, ldy, sY, batch, 0, rs.at(off + send, off, off + S0));
   }
 }
 
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY) {
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows) {
   // Y = L_block^{-1} for the diagonal range [off, off+nb) of L (lower) by
   // block forward substitution on L Y = I over the factor's diagonal blocks
   // S: Y holds the running right-hand side R (initially I); Y[S, 0:send] =
@@ -1188,7 +1217,8 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
     const int p = off + S0;
     const int lim = (split > 0 && p < split) ? std::min(split - off, nb) : nb;
     const int h = std::min(DB, lim - S0);
-    tri_inverse_step<T>(st, L, ldl, sL, off, nb, split, batch, Linv, sLi, Y, ldy, sY, S0, h);
+    tri_inverse_step<T>(st, L, ldl, sL, off, nb, split, batch, Linv, sLi, Y, ldy, sY, S0, h, -1,
+                        rows ? *rows : GemmRows{});
     S0 += h;
   }
 }
@@ -1257,12 +1287,13 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
 
 #define INST(T)                                                                                 \
   template void gemm<T>(hipStream_t, int, int, int, int, int, T, const T*, int64_t, int64_t,    \
-                        const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int);         \
+                        const T*, int64_t, int64_t, T, T*, int64_t, int64_t, int, int,          \
+                        const GemmRows&);                                                      \
   template int gemm_autotune<T>(int, int, int, int, int, int, int);                              \
   template int cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*,   \
-                           const AuxStreams*);                                                   \
+                           const AuxStreams*, const GemmRows*);                                  \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
-                               int64_t, T*, int64_t, int64_t);                                      \
+                               int64_t, T*, int64_t, int64_t, const GemmRows*);                     \
   template int cholesky_inverse<T>(hipStream_t, const AuxStreams&, T*, int64_t, int64_t, int, int, T*,  \
                                    int64_t, int*, T*, int64_t, const int*);
 INST(double)
