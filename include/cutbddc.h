@@ -100,6 +100,11 @@ typedef struct {
   double lanczos_lmin;         /* extreme eigenvalue estimates of M A-bar from the last   */
   double lanczos_lmax;         /* solve's PCG coefficients (cb_pcg_history); 0 before one,
                                   and in cb_query of a batch context                      */
+  int32_t coarse_separator;    /* cb_query after cb_factor: separator size when the coarse */
+  int32_t coarse_octant_max;   /* problem is solved by nested dissection (one problem,     */
+                               /* m >= 4 and n_coarse >= 1024, or CUTBDDC_COARSE=nd; the  */
+                               /* largest octant block in the second field); 0 and 0 when */
+                               /* it is a dense Cholesky of the whole coarse matrix        */
 } cb_info;
 
 typedef struct cb_ctx cb_ctx;

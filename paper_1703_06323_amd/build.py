@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-
           "-I/opt/rocm/include"]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HIP_SOURCES = ["integrate.hip", "indexing.hip", "operator.hip", "dense.hip", "bddc.hip", "noalloc.hip", "nitsche.hip",
-               "manufactured.hip"]
+               "manufactured.hip", "coarse_nd.hip"]
 HOST_SOURCES = ["topology.cpp", "cutbddc.cpp"]
 
 

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "bddc.h"
+#include "coarse_nd.h"
 #include "common.h"
 #include "dense.h"
 #include "indexing.h"
@@ -322,6 +323,25 @@ struct cb_ctx {
       cs_row;
   // factor results
   DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
+  // coarse problem by one level of nested dissection (coarse_nd.h), chosen
+  // at each cb_factor for single-problem contexts; Acinv is then unused
+  struct {
+    bool on = false;
+    int Lo = 0, Lso = 0, Ls = 0, n_s = 0, n_o_max = 0;
+    DevBuf oid, sid, sep, pos, Yo, W, WT, Ys, to, rs, us, xs, info;
+    NDDev dev() const {
+      NDDev d;
+      d.Lo = Lo;
+      d.Lso = Lso;
+      d.Ls = Ls;
+      d.n_s = n_s;
+      d.oid = oid.as<int32_t>();
+      d.sid = sid.as<int32_t>();
+      d.sep = sep.as<int32_t>();
+      d.pos = pos.as<int32_t>();
+      return d;
+    }
+  } nd;
   DevBuf optr_d, omem_d;   // object member lists per subdomain (built at factorisation)
   // work vectors and PCG state
   DevBuf x, r, z, p, q, t1, t2, t3, zbuf, cloc, cvec, tcvec, ucvec, partial, scal, bgrid;
@@ -491,8 +511,14 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked, bool cleare
     launch_coarse_rhs(st, c->nc_tot, c->cs_ptr.as<int64_t>(), c->cs_sub.as<int32_t>(), c->cs_row.as<int32_t>(),
                       c->NCp, c->cloc.as<double>(), c->cvec.as<double>());
     timed(c, "coarse_gemv", [&] {
-      launch_coarse_gemv(st, c->batch(masked), c->nc_tot, c->coarse_prob_d.as<int32_t>(), c->Acinv.as<double>(),
-                         c->cvec.as<double>(), c->tcvec.as<double>(), c->ucvec.as<double>());
+      if (c->nd.on)
+        launch_nd_solve(st, c->batch(masked), c->nd.dev(), c->nd.Yo.as<double>(), c->nd.W.as<double>(),
+                        c->nd.WT.as<double>(), c->nd.Ys.as<double>(), c->cvec.as<double>(), c->nd.to.as<double>(),
+                        c->nd.rs.as<double>(), c->nd.us.as<double>(), c->nd.xs.as<double>(),
+                        c->ucvec.as<double>());
+      else
+        launch_coarse_gemv(st, c->batch(masked), c->nc_tot, c->coarse_prob_d.as<int32_t>(), c->Acinv.as<double>(),
+                           c->cvec.as<double>(), c->tcvec.as<double>(), c->ucvec.as<double>());
     });
     launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
@@ -1461,6 +1487,195 @@ int fp64_refactor(cb_ctx* c, double* AcLoc, int* n_redo) {
   return CB_OK;
 }
 
+// Nested dissection of the coarse problem (coarse_nd.h): chosen for a
+// context of one problem with at least 4 subdomains per axis and at least
+// ND_MIN_COARSE coarse DOFs.  CUTBDDC_COARSE=dense or =nd (read at every
+// cb_factor) overrides the rule; nd still needs one problem, 2 subdomains
+// per axis and a nonempty separator.
+constexpr int ND_MIN_COARSE = 1024;
+bool coarse_nd_wanted(const cb_ctx* c) {
+  if (c->P != 1 || c->pb[0].m < 2 || c->pb[0].n_coarse == 0) return false;
+  const char* e = std::getenv("CUTBDDC_COARSE");
+  if (e && std::strcmp(e, "dense") == 0) return false;
+  if (e && std::strcmp(e, "nd") == 0) return true;
+  return c->pb[0].m >= 4 && c->pb[0].n_coarse >= ND_MIN_COARSE;
+}
+
+// Envelope end per DB-wide column block (the env of cholesky_inverse) from
+// last[f] = the largest row whose first nonzero column is f (at least f).
+std::vector<int> envelope_ends(const std::vector<int32_t>& last) {
+  const int L = (int)last.size();
+  std::vector<int> env(diag_blocks(L, 0));
+  int32_t run = 0, col = 0;
+  for (size_t kb = 0; kb < env.size(); ++kb) {
+    const int cend = std::min(L, (int)(kb + 1) * DB);
+    for (; col < cend; ++col) run = std::max(run, last[col]);
+    env[kb] = run + 1;
+  }
+  return env;
+}
+
+struct NDPlan {
+  int Lo = 0, Lso = 0, Ls = 0, n_s = 0, n_o_max = 0;
+  std::vector<int32_t> oid, sid, sep, pos;
+  std::vector<int> env;   // envelope of the octant blocks (over the batch of 8)
+};
+
+// Octant partition of the coarse DOFs of the single problem from the coarse
+// ids of every subdomain (cids: NCp slots per subdomain, ncs[w] used) and
+// the block of every subdomain.  Octant of block (bx, by, bz): bit 0 for
+// bx >= m/2, bit 1 for by >= m/2, bit 2 for bz >= m/2.  Within an octant
+// and within the separator the DOFs keep their coarse order.  Returns false
+// when there is no separator.
+bool plan_nd(const cb_ctx* c, const std::vector<int32_t>& cids, const std::vector<int32_t>& ncs,
+             const std::vector<int32_t>& blk, NDPlan& pl) {
+  const ProbHost& h = c->pb[0];
+  const int m = h.m, half = m / 2, nc = h.n_coarse, NCp = c->NCp;
+  auto octant = [&](int b) {
+    const int bx = b % m, by = (b / m) % m, bz = b / (m * m);
+    return (bx >= half ? 1 : 0) + (by >= half ? 2 : 0) + (bz >= half ? 4 : 0);
+  };
+  auto ids_of = [&](int w) { return &cids[(size_t)w * NCp]; };
+  // -2: held by no subdomain yet; 0..7: interior to that octant; -1: separator
+  std::vector<int> oct(nc, -2);
+  for (int w = h.sub_off; w < h.sub_off + h.ns; ++w) {
+    const int o = octant(blk[w]);
+    for (int t = 0; t < ncs[w]; ++t) {
+      int& x = oct[ids_of(w)[t] - h.coarse_off];
+      x = (x == -2 || x == o) ? o : -1;
+    }
+  }
+  std::vector<int> loc(nc, -1);
+  std::vector<std::vector<int32_t>> inner(8);
+  std::vector<int32_t> sid;
+  for (int i = 0; i < nc; ++i) {
+    if (oct[i] == -2) return false;
+    if (oct[i] >= 0) {
+      loc[i] = (int)inner[oct[i]].size();
+      inner[oct[i]].push_back(i);
+    } else {
+      loc[i] = (int)sid.size();
+      sid.push_back(i);
+    }
+  }
+  const int n_s = (int)sid.size();
+  if (n_s == 0) return false;
+  // separator DOFs held by a subdomain of each octant (the only separator
+  // columns of A_os that can be nonzero), and the first interior column of
+  // every interior row (its subdomains' smallest interior DOF)
+  std::vector<std::vector<char>> cpl(8, std::vector<char>(n_s, 0));
+  std::vector<std::vector<int32_t>> firstl(8);
+  for (int o = 0; o < 8; ++o) {
+    firstl[o].resize(inner[o].size());
+    for (size_t i = 0; i < inner[o].size(); ++i) firstl[o][i] = (int32_t)i;
+  }
+  for (int w = h.sub_off; w < h.sub_off + h.ns; ++w) {
+    const int o = octant(blk[w]);
+    int32_t lo = INT32_MAX;
+    for (int t = 0; t < ncs[w]; ++t) {
+      const int i = ids_of(w)[t] - h.coarse_off;
+      if (oct[i] == -1) cpl[o][loc[i]] = 1;
+      else lo = std::min(lo, (int32_t)loc[i]);
+    }
+    for (int t = 0; t < ncs[w]; ++t) {
+      const int i = ids_of(w)[t] - h.coarse_off;
+      if (oct[i] >= 0) firstl[o][loc[i]] = std::min(firstl[o][loc[i]], lo);
+    }
+  }
+  std::vector<std::vector<int32_t>> sep(8);
+  int n_o_max = 0, n_so_max = 0;
+  for (int o = 0; o < 8; ++o) {
+    for (int t = 0; t < n_s; ++t)
+      if (cpl[o][t]) sep[o].push_back(t);
+    n_o_max = std::max(n_o_max, (int)inner[o].size());
+    n_so_max = std::max(n_so_max, (int)sep[o].size());
+  }
+  pl.n_s = n_s;
+  pl.n_o_max = n_o_max;
+  pl.Lo = round_up(std::max(1, n_o_max), CHOL_BLOCK);
+  pl.Lso = round_up(std::max(1, n_so_max), 32);
+  pl.Ls = round_up(n_s, CHOL_BLOCK);
+  pl.oid.assign((size_t)8 * pl.Lo, -1);
+  pl.sep.assign((size_t)8 * pl.Lso, -1);
+  pl.pos.assign((size_t)8 * n_s, -1);
+  std::vector<int32_t> last(pl.Lo);
+  for (int i = 0; i < pl.Lo; ++i) last[i] = i;
+  for (int o = 0; o < 8; ++o) {
+    for (size_t i = 0; i < inner[o].size(); ++i) {
+      pl.oid[(size_t)o * pl.Lo + i] = inner[o][i];
+      last[firstl[o][i]] = std::max(last[firstl[o][i]], (int32_t)i);
+    }
+    for (size_t a = 0; a < sep[o].size(); ++a) {
+      pl.sep[(size_t)o * pl.Lso + a] = sep[o][a];
+      pl.pos[(size_t)o * n_s + sep[o][a]] = (int32_t)a;
+    }
+  }
+  pl.sid = std::move(sid);
+  pl.env = envelope_ends(last);
+  return true;
+}
+
+// Nested-dissection factorisation of the coarse problem (coarse_nd.h) from
+// its full ldc x ldc matrix Ac (problem-local coarse ids; the single
+// problem's ids start at 0).
+int factor_coarse_nd(cb_ctx* c, const double* Ac, int ldc, const NDPlan& pl) {
+  hipStream_t st = c->st;
+  auto& nd = c->nd;
+  const int Lo = pl.Lo, Lso = pl.Lso, Ls = pl.Ls;
+  nd.Lo = Lo;
+  nd.Lso = Lso;
+  nd.Ls = Ls;
+  nd.n_s = pl.n_s;
+  nd.n_o_max = pl.n_o_max;
+  CHK(upload(nd.oid, pl.oid, st));
+  CHK(upload(nd.sid, pl.sid, st));
+  CHK(upload(nd.sep, pl.sep, st));
+  CHK(upload(nd.pos, pl.pos, st));
+  const int64_t sO = (int64_t)Lo * Lo, sW = (int64_t)Lo * Lso, sS = (int64_t)Lso * Lso, sY = (int64_t)Ls * Ls;
+  const int64_t sLo = (int64_t)diag_blocks(Lo, 0) * DB * DB, sLs = (int64_t)diag_blocks(Ls, 0) * DB * DB;
+  CHK(dalloc(nd.Yo, (size_t)(8 * sO) * sizeof(double)));
+  CHK(dalloc(nd.W, (size_t)(8 * sW) * sizeof(double)));
+  CHK(dalloc(nd.WT, (size_t)(8 * sW) * sizeof(double)));
+  CHK(dalloc(nd.Ys, (size_t)sY * sizeof(double)));
+  CHK(dalloc(nd.to, (size_t)8 * Lo * sizeof(double)));
+  for (DevBuf* b : {&nd.rs, &nd.us, &nd.xs}) CHK(dalloc(*b, (size_t)Ls * sizeof(double)));
+  CHK(dalloc(nd.info, 9 * sizeof(int)));
+  HIPCHK(hipMemsetAsync(nd.info.p, 0, 9 * sizeof(int), st));
+  DevBuf Aoo, Aos, So, S, Lc, ones;
+  CHK(dalloc(Aoo, (size_t)(8 * sO) * sizeof(double)));
+  CHK(dalloc(Aos, (size_t)(8 * sW) * sizeof(double)));
+  CHK(dalloc(So, (size_t)(8 * sS) * sizeof(double)));
+  CHK(dalloc(S, (size_t)sY * sizeof(double)));
+  CHK(dalloc(Lc, (size_t)std::max(8 * sLo, sLs) * sizeof(double)));
+  CHK(upload(ones, std::vector<double>(std::max(Lo, Ls), 1.0), st));
+  const NDDev d = nd.dev();
+  const AuxStreams ax{c->aux_st, c->aux_st3, c->aux_ev, c->aux_ev3};
+  int* info = nd.info.as<int>();
+  launch_nd_gather(st, d, Ac, ldc, Aoo.as<double>(), Aos.as<double>());
+  // the 8 octant blocks as one batch, then W_o = Y_o A_os (Y_o lower
+  // triangular: a row tile's k loop ends at its last row)
+  if (cholesky_inverse<double>(st, ax, Aoo.as<double>(), Lo, sO, Lo, 8, Lc.as<double>(), sLo, info,
+                               nd.Yo.as<double>(), sO, pl.env.data()) != 0)
+    return fail(CB_ERR_DEVICE, "event record or wait failed in the coarse factorisation");
+  gemm<double>(st, 0, 0, Lo, Lso, Lo, 1.0, nd.Yo.as<double>(), Lo, sO, Aos.as<double>(), Lso, sW, 0.0,
+               nd.W.as<double>(), Lso, sW, 8, GEMM_KTO_DIAG);
+  symmetrize_scale<double, double>(st, nd.Yo.as<double>(), Lo, sO, nd.Yo.as<double>(), Lo, sO,
+                                   ones.as<double>(), 0, Lo, 8);
+  launch_nd_transpose(st, d, nd.W.as<double>(), nd.WT.as<double>());
+  // S = A_ss - sum_o W_o^T W_o, then its factor and inverse
+  gemm<double>(st, 1, 0, Lso, Lso, Lo, 1.0, nd.W.as<double>(), Lso, sW, nd.W.as<double>(), Lso, sW, 0.0,
+               So.as<double>(), Lso, sS, 8, GEMM_LOWER);
+  launch_nd_schur(st, d, Ac, ldc, So.as<double>(), S.as<double>());
+  if (cholesky_inverse<double>(st, ax, S.as<double>(), Ls, sY, Ls, 1, Lc.as<double>(), sLs, info + 8,
+                               nd.Ys.as<double>(), sY, nullptr) != 0)
+    return fail(CB_ERR_DEVICE, "event record or wait failed in the coarse factorisation");
+  symmetrize_scale<double, double>(st, nd.Ys.as<double>(), Ls, sY, nd.Ys.as<double>(), Ls, sY, ones.as<double>(),
+                                   0, Ls, 1);
+  HIPCHK(hipGetLastError());
+  nd.on = true;
+  return CB_OK;
+}
+
 template <typename T>
 int factor_impl(cb_ctx* c) {
   hipStream_t st = c->st;
@@ -1523,10 +1738,24 @@ int factor_impl(cb_ctx* c) {
   // coarse matrices (one block per problem) and their inverses, in FP64;
   // the blocks of a group share their order and are factored as a batch
   std::vector<int> coarse_slot(c->P, -1);   // index into info_d after ns + 1
+  c->nd.on = false;
   if (c->ac_total > 0) {
+    // coarse ids of every subdomain (fixed since setup)
+    std::vector<int32_t> cids((size_t)ns * NCp), ncs(ns);
+    HIPCHK(hipMemcpyAsync(cids.data(), c->Cids.p, cids.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ncs.data(), c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    NDPlan plan;
+    bool use_nd = false;
+    if (coarse_nd_wanted(c)) {
+      std::vector<int32_t> blk(ns);
+      HIPCHK(hipMemcpyAsync(blk.data(), c->sub_blk_d.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      use_nd = plan_nd(c, cids, ncs, blk, plan);
+    }
     DevBuf Ac;
     CHK(dalloc(Ac, (size_t)c->ac_total * sizeof(double)));
-    CHK(dalloc(c->Acinv, (size_t)c->ac_total * sizeof(double)));
+    if (use_nd) c->Acinv.release();
+    else CHK(dalloc(c->Acinv, (size_t)c->ac_total * sizeof(double)));
     size_t maxL = 0, maxD = 0;
     for (const CoarseGroup& gr : c->groups) {
       maxL = std::max(maxL, (size_t)gr.ldc);
@@ -1544,9 +1773,6 @@ int factor_impl(cb_ctx* c) {
     // Envelope of each coarse matrix: A_c couples two coarse DOFs only
     // when a subdomain holds both, so row i's first nonzero column is the
     // smallest coarse id among the subdomains that hold i.
-    std::vector<int32_t> cids((size_t)ns * NCp), ncs(ns);
-    HIPCHK(hipMemcpyAsync(cids.data(), c->Cids.p, cids.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ncs.data(), c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<int32_t> first(c->nc_tot);   // problem-local
     for (int k = 0; k < c->P; ++k)
@@ -1565,8 +1791,10 @@ int factor_impl(cb_ctx* c) {
     CHK(dalloc(Lc, maxD * sizeof(double)));
     CHK(upload(ones, onesv, st));
     ProfScope cps(c, "coarse_factor");
+    if (use_nd) CHK(factor_coarse_nd(c, Ac.as<double>() + c->pb[0].ac_off, c->pb[0].ldc, plan));
     int slot = 0;
     for (const CoarseGroup& gr : c->groups) {
+      if (use_nd) break;
       const int L = gr.ldc, nb = (int)gr.probs.size();
       const int64_t sA = (int64_t)L * L, sLc = (int64_t)diag_blocks(L, 0) * DB * DB;
       for (int q = 0; q < nb; ++q) coarse_slot[gr.probs[q]] = slot + q;
@@ -1585,13 +1813,7 @@ int factor_impl(cb_ctx* c) {
           last[f] = std::max(last[f], i);
         }
       }
-      std::vector<int> env(diag_blocks(L, 0));
-      int32_t run = 0, col = 0;
-      for (size_t kb = 0; kb < env.size(); ++kb) {
-        const int cend = std::min(L, (int)(kb + 1) * DB);
-        for (; col < cend; ++col) run = std::max(run, last[col]);
-        env[kb] = run + 1;
-      }
+      const std::vector<int> env = envelope_ends(last);
       double* Y = c->Acinv.as<double>() + gr.ac_off;
       if (cholesky_inverse<double>(st, ax, A, L, sA, L, nb, Lc.as<double>(), sLc,
                                    c->info_d.as<int>() + ns + 1 + slot, Y, sA, env.data()) != 0)
@@ -1604,12 +1826,17 @@ int factor_impl(cb_ctx* c) {
       slot += nb;
     }
   }
+  if (!c->nd.on)
+    for (DevBuf* b : {&c->nd.oid, &c->nd.sid, &c->nd.sep, &c->nd.pos, &c->nd.Yo, &c->nd.W, &c->nd.WT, &c->nd.Ys,
+                      &c->nd.to, &c->nd.rs, &c->nd.us, &c->nd.xs, &c->nd.info})
+      b->release();
   // join the second stream before the chunk buffers go back to the cache
   HIPCHK(hipEventRecord(c->aux_ev, c->aux_st));
   HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
   fw.release();
-  std::vector<int> info(n_info);
+  std::vector<int> info(n_info), nd_info(9, 0);
   HIPCHK(hipMemcpyAsync(info.data(), c->info_d.p, n_info * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (c->nd.on) HIPCHK(hipMemcpyAsync(nd_info.data(), c->nd.info.p, 9 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<int32_t> sub_prob(ns);
   for (int k = 0; k < c->P; ++k)
@@ -1625,6 +1852,10 @@ int factor_impl(cb_ctx* c) {
   for (int k = 0; k < c->P; ++k)
     if (coarse_slot[k] >= 0 && info[ns + 1 + coarse_slot[k]] != 0)
       return fail(CB_ERR_NOT_SPD, "coarse Cholesky failed" + where(k));
+  for (int o = 0; o < 9; ++o)
+    if (nd_info[o] != 0)
+      return fail(CB_ERR_NOT_SPD, o < 8 ? "coarse Cholesky failed in the block of octant " + std::to_string(o)
+                                        : std::string("coarse Cholesky failed in the separator's Schur complement"));
   return CB_OK;
 }
 
@@ -2096,6 +2327,8 @@ int cb_query(const cb_ctx* c, cb_info* out) {
   out->factored = c->factored ? 1 : 0;
   out->lanczos_lmin = out->lanczos_lmax = 0.0;
   if (c->P == 1) fill_lanczos(c, 0, out);
+  out->coarse_separator = c->nd.on ? c->nd.n_s : 0;
+  out->coarse_octant_max = c->nd.on ? c->nd.n_o_max : 0;
   return CB_OK;
 }
 

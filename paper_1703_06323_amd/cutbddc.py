@@ -54,7 +54,8 @@ class cb_info(C.Structure):
                 ("t_integrate_ms", C.c_double),
                 ("t_topology_ms", C.c_double), ("t_factor_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("sum_nGnC", C.c_int64), ("n_nodes", C.c_int64),
-                ("lanczos_lmin", C.c_double), ("lanczos_lmax", C.c_double)]
+                ("lanczos_lmin", C.c_double), ("lanczos_lmax", C.c_double),
+                ("coarse_separator", C.c_int32), ("coarse_octant_max", C.c_int32)]
 
 
 _lib = None

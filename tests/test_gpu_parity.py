@@ -347,3 +347,67 @@ def test_node_box_solves_match_node_block_solves(monkeypatch):
     assert elementwise(ux, ub) < 1e-10
     for a, c in zip(usx, usb):
         assert elementwise(a, c) < 1e-10
+
+
+ND_CASES = ["single_ball_v1_stiffness", "balls16_s4", "balls24_s8_lognormal", "balls32_s8_ce", "uncut16_s4",
+            "full_elements", "balls16_s4_v2", "balls24_s8_lognormal_v2", "uncut8_kappa_layer_v2"]
+
+
+@pytest.mark.parametrize("name", ND_CASES)
+def test_nested_dissection_coarse_solve(name, monkeypatch):
+    """The coarse problem by nested dissection (octant blocks and the Schur
+    complement of the separator; chosen by the size rule for large single
+    meshes), forced on the small cases: the preconditioner and the PCG
+    solution against the oracle's dense coarse solve."""
+    from paper_1703_06323_amd import Solver
+    monkeypatch.setenv("CUTBDDC_COARSE", "nd")
+    o = oracle(name)
+    say(f"[gpu] nested-dissection coarse solve {name}")
+    s = Solver(CASES[name]())
+    s.factor()
+    inf = s.info()
+    assert 0 < inf["coarse_separator"] <= inf["n_coarse"]
+    assert inf["coarse_separator"] + inf["coarse_octant_max"] <= inf["n_coarse"]
+    r = np.random.default_rng(7).standard_normal(o.n_dof)
+    z = s.apply_preconditioner(r).cpu().numpy()
+    zo = o.M.apply(r)
+    assert elementwise(z, zo) < 1e-10
+    p = CASES[name]()
+    u, it, relres = s.solve(p.f, rtol=1e-8)
+    x, it_o, _ = o.solve(rtol=1e-8)
+    assert relres < 1e-8 and abs(it - it_o) <= 1, (it, it_o)
+    assert elementwise(u.cpu().numpy(), x) < 1e-10
+    s.close()
+
+
+def test_nested_dissection_is_the_default_for_large_coarse_problems(monkeypatch):
+    """48^3 cells in 4^3-cell subdomains (12^3 subdomains, about 5 000 coarse
+    DOFs): the size rule picks nested dissection; its preconditioner and
+    solution agree with the dense coarse Cholesky's."""
+    from paper_1703_06323_amd import Solver
+    p = W.random_balls(48, 4, 30, 11)
+    r = None
+    out = {}
+    for mode in ("", "dense"):
+        if mode:
+            monkeypatch.setenv("CUTBDDC_COARSE", mode)
+        else:
+            monkeypatch.delenv("CUTBDDC_COARSE", raising=False)
+        say(f"[gpu] 48^3 coarse {mode or 'default'}")
+        s = Solver(p)
+        s.factor()
+        inf = s.info()
+        if r is None:
+            r = np.random.default_rng(3).standard_normal(s.n_dof)
+        z = s.apply_preconditioner(r).cpu().numpy()
+        u, it, relres = s.solve(p.f, rtol=1e-8)
+        out[mode] = (inf, z, u.cpu().numpy(), it)
+        s.close()
+    inf, z, u, it = out[""]
+    assert inf["coarse_separator"] > 0 and inf["n_coarse"] >= 1024
+    assert out["dense"][0]["coarse_separator"] == 0
+    say(f"  n_coarse {inf['n_coarse']}, separator {inf['coarse_separator']}, "
+        f"largest octant {inf['coarse_octant_max']}, iterations {it} / {out['dense'][3]}")
+    assert elementwise(z, out["dense"][1]) < 1e-10
+    assert abs(it - out["dense"][3]) <= 1
+    assert elementwise(u, out["dense"][2]) < 1e-9
