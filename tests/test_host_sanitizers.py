@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1703_06323_amd", "csrc")
 BUILD = os.path.join(ROOT, "_build")
 DEVICE_OBJS = [os.path.join(BUILD, f + ".hip.o") for f in ("integrate", "indexing", "operator", "dense", "bddc",
-                                                            "nitsche", "manufactured")]
+                                                            "nitsche", "manufactured", "coarse_nd")]
 GXX = shutil.which("g++")
 
 pytestmark = pytest.mark.skipif(
