@@ -266,7 +266,9 @@ def run_96(args, fp32):
         "dtype": "f32 local factor/solves, f64 PCG and coarse" if fp32 else "f64",
         "workload": "cut_cube_96_balls40_lognormal: unit cube minus 40 seeded balls, 96^3 Q1 cells, "
                     "12^3 subdomains of 8^3 cells, kappa = exp(N(0,1)) per cell, f ~ U(0,1)",
-        "n_dof": n_dof, "n_coarse": int(info["n_coarse"]), "iterations": it, "relres": rel,
+        "n_dof": n_dof, "n_coarse": int(info["n_coarse"]),
+        "coarse_separator": int(info["coarse_separator"]), "coarse_octant_max": int(info["coarse_octant_max"]),
+        "iterations": it, "relres": rel,
         "oracle_iterations": int(meta["iterations_rtol_1e-8"]),
         "iteration_change": it - int(meta["iterations_rtol_1e-8"]),
         "rel_error_vs_fp64_oracle": kt.get("check"),
@@ -388,6 +390,8 @@ def main():
                         "8^3 subdomains of 8^3 cells, BDDC(cef) variant 1, stiffness weighting, "
                         "PCG rtol 1e-8, FP64",
             "n_dof": n_dof, "n_cut": int(info64["n_cut"]), "n_coarse": int(info64["n_coarse"]),
+            "coarse_separator": int(info64["coarse_separator"]),
+            "coarse_octant_max": int(info64["coarse_octant_max"]),
             "iterations": it64, "relres": rel64,
             "phase_ms": {k: round(float(info64[k]), 3) for k in
                          ("t_integrate_ms", "t_topology_ms", "t_factor_ms", "t_solve_ms")},

@@ -480,26 +480,54 @@ __device__ inline int packed_offset(int r, int c, int vw) {
 }
 
 // out (packed) = D sym(in) D where sym(in)[i][j] = in[max(i,j)][min(i,j)]
-// (only the lower triangle of in is read); D may be null (identity).
+// (only the lower triangle of in is read); D may be null (identity).  One
+// block per lower SB x SB block: the block is read into LDS (16-byte loads
+// with veci) and leaves in the packed order, one 16-byte vector per store.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void pack_lower_kernel(const TI* __restrict__ in, int64_t ldi, int64_t sI,
                                                          const double* __restrict__ D, int64_t sD,
-                                                         TO* __restrict__ out, int nbk) {
-  constexpr int VW = 16 / sizeof(TO);
+                                                         TO* __restrict__ out, int nbk, int veci) {
+  typedef TI __attribute__((ext_vector_type(16 / sizeof(TI)))) VI;
+  typedef TO __attribute__((ext_vector_type(16 / sizeof(TO)))) VO;
+  constexpr int VW = 16 / sizeof(TO), WI = 16 / sizeof(TI);
+  __shared__ double tile[SB][SB + 1];
+  __shared__ double dI[SB], dJ[SB];
   const int64_t w = blockIdx.y;
-  const int q = blockIdx.x;
+  const int q = blockIdx.x, tid = threadIdx.x;
   int I = 0;
   while ((I + 1) * (I + 2) / 2 <= q) ++I;
   const int J = q - I * (I + 1) / 2;
-  const TI* x = in + w * sI;
+  const TI* x = in + w * sI + (int64_t)(SB * I) * ldi + SB * J;
   const double* d = D ? D + w * sD : nullptr;
+  if (tid < SB) dI[tid] = d ? d[SB * I + tid] : 1.0;
+  else if (tid < 2 * SB) dJ[tid - SB] = d ? d[SB * J + tid - SB] : 1.0;
+  if (veci) {
+    for (int e = tid; e < SB * SB / WI; e += 256) {
+      const int r = e / (SB / WI), c = (e - r * (SB / WI)) * WI;
+      const VI v = *reinterpret_cast<const VI*>(x + (int64_t)r * ldi + c);
+#pragma unroll
+      for (int l = 0; l < WI; ++l) tile[r][c + l] = (double)v[l];
+    }
+  } else {
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int r = e / SB, c = e % SB;
+      tile[r][c] = (double)x[(int64_t)r * ldi + c];
+    }
+  }
+  __syncthreads();
+  // vector p = k * 64 + r + 32 h of the block holds row r, columns
+  // 16 h + k VW + [0, VW) (packed_offset)
   TO* o = out + (w * nbk + q) * (int64_t)(SB * SB);
-  for (int e = threadIdx.x; e < SB * SB; e += 256) {
-    const int r = e / SB, c = e % SB;
-    const int i = SB * I + r, j = SB * J + c;
-    const TI v = i >= j ? x[(int64_t)i * ldi + j] : x[(int64_t)j * ldi + i];
-    const double sc = d ? d[i] * d[j] : 1.0;
-    o[packed_offset(r, c, VW)] = (TO)((double)v * sc);
+  for (int p = tid; p < SB * SB / VW; p += 256) {
+    const int k = p >> 6, r = p & 31, h = (p >> 5) & 1;
+    VO a;
+#pragma unroll
+    for (int l = 0; l < VW; ++l) {
+      const int c = 16 * h + k * VW + l;
+      const double v = (I != J || c <= r) ? tile[r][c] : tile[c][r];
+      a[l] = (TO)(v * dI[r] * dJ[c]);
+    }
+    *reinterpret_cast<VO*>(o + (int64_t)p * VW) = a;
   }
 }
 
@@ -892,8 +920,10 @@ template <typename TI, typename TO>
 void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi, int64_t sI, const double* D,
                        int64_t sD, TO* out) {
   if (ns <= 0 || n <= 0) return;
+  constexpr int WI = 16 / sizeof(TI);
+  const int veci = (reinterpret_cast<uintptr_t>(in) & 15) == 0 && ldi % WI == 0 && sI % WI == 0;
   hipLaunchKernelGGL((pack_lower_kernel<TI, TO>), dim3(packed_blocks(n), ns), dim3(256), 0, st, in, ldi, sI, D, sD,
-                     out, packed_blocks(n));
+                     out, packed_blocks(n), veci);
 }
 template void launch_pack_lower<float, float>(hipStream_t, int, int, const float*, int64_t, int64_t, const double*,
                                               int64_t, float*);

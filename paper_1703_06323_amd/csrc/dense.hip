@@ -816,21 +816,75 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
 }
 
 // Y (nb x nb per matrix) = identity.
+// Element-wise helpers of the factorisation.  With vec (leading
+// dimensions, batch strides, widths and base addresses multiples of 16
+// bytes) every thread moves 16-byte vectors; the grid's x dimension strides
+// over one matrix, y is the batch entry.
 template <typename T>
-__global__ __launch_bounds__(256) void eye_kernel(T* Y, int64_t ldy, int64_t sY, int nb) {
-  const int r = blockIdx.x;
-  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)r * ldy;
-  for (int c = threadIdx.x; c < nb; c += 256) y[c] = c == r ? T(1) : T(0);
+bool vec16_ok(const void* p, int64_t ld, int64_t stride, int width) {
+  constexpr int VW = 16 / sizeof(T);
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && ld % VW == 0 && stride % VW == 0 && width % VW == 0;
+}
+// workgroups per matrix: about 4 items per thread, at most 8192 in all
+inline int helper_blocks(int64_t items, int batch) {
+  const int64_t cap = std::max<int64_t>(4, 8192 / std::max(1, batch));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (items + 1023) / 1024));
 }
 
-// Y[r][c] = L[r][c] for r, c < h (one row per block; batch along y).
+// Y[r][c] = (r == c) for r, c < nb.
+template <typename T>
+__global__ __launch_bounds__(256) void eye_kernel(T* Y, int64_t ldy, int64_t sY, int nb, int vec) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = 16 / sizeof(T);
+  T* y = Y + (int64_t)blockIdx.y * sY;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  if (vec) {
+    const int vpr = nb / VW;
+    const int64_t tot = (int64_t)nb * vpr;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += step) {
+      const int r = (int)(e / vpr), c = (int)(e - (int64_t)r * vpr) * VW;
+      V x;
+#pragma unroll
+      for (int l = 0; l < VW; ++l) x[l] = c + l == r ? T(1) : T(0);
+      *reinterpret_cast<V*>(y + (int64_t)r * ldy + c) = x;
+    }
+  } else {
+    const int64_t tot = (int64_t)nb * nb;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += step) {
+      const int r = (int)(e / nb), c = (int)(e - (int64_t)r * nb);
+      y[(int64_t)r * ldy + c] = c == r ? T(1) : T(0);
+    }
+  }
+}
+
+template <typename T>
+void launch_eye(hipStream_t st, T* Y, int64_t ldy, int64_t sY, int nb, int batch) {
+  const int vec = vec16_ok<T>(Y, ldy, sY, nb);
+  const int64_t items = (int64_t)nb * nb / (vec ? 16 / sizeof(T) : 1);
+  hipLaunchKernelGGL(eye_kernel<T>, dim3(helper_blocks(items, batch), batch), dim3(256), 0, st, Y, ldy, sY, nb, vec);
+}
+
+// Y[r][c] = L[r][c] for r, c < h.
 template <typename T>
 __global__ __launch_bounds__(256) void copy_block_kernel(const T* __restrict__ L, int64_t ldl, int64_t sL, T* Y,
-                                                          int64_t ldy, int64_t sY, int h) {
-  const int r = blockIdx.x;
-  const T* l = L + (int64_t)blockIdx.y * sL + (int64_t)r * ldl;
-  T* y = Y + (int64_t)blockIdx.y * sY + (int64_t)r * ldy;
-  for (int c = threadIdx.x; c < h; c += 256) y[c] = l[c];
+                                                          int64_t ldy, int64_t sY, int h, int vec) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = 16 / sizeof(T);
+  const T* l = L + (int64_t)blockIdx.y * sL;
+  T* y = Y + (int64_t)blockIdx.y * sY;
+  const int step = gridDim.x * 256;
+  if (vec) {
+    const int vpr = h / VW, tot = h * vpr;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < tot; e += step) {
+      const int r = e / vpr, c = (e - r * vpr) * VW;
+      *reinterpret_cast<V*>(y + (int64_t)r * ldy + c) = *reinterpret_cast<const V*>(l + (int64_t)r * ldl + c);
+    }
+  } else {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < h * h; e += step) {
+      const int r = e / h, c = e - r * h;
+      y[(int64_t)r * ldy + c] = l[(int64_t)r * ldl + c];
+    }
+  }
 }
 
 // out (full symmetric, row-major nb x nb) = D * sym(lower(in)) * D
@@ -851,34 +905,65 @@ __global__ __launch_bounds__(256) void symmetrize_scale_kernel(const T* in, int6
 
 // The same for nb a multiple of 32, by 32 x 32 tiles: the lower tile (I, J)
 // is read once (coalesced) into LDS and written to (I, J) and, transposed,
-// to (J, I), both coalesced.  One block per lower tile.
+// to (J, I), both coalesced, with 16-byte loads (veci) and stores (veco)
+// where the layouts allow them.  One block per lower tile.
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void symmetrize_scale_tiled_kernel(const T* in, int64_t ldi, int64_t sI,
                                                                      TO* out, int64_t ldo, int64_t sO,
-                                                                     const double* D, int64_t sD) {
+                                                                     const double* D, int64_t sD, int veci,
+                                                                     int veco) {
+  typedef typename Vec16<T>::type VI;
+  typedef typename Vec16<TO>::type VO;
+  constexpr int WI = 16 / sizeof(T), WO = 16 / sizeof(TO);
   __shared__ double tile[32][33];
+  __shared__ double dI[32], dJ[32];
   const int64_t bz = blockIdx.y;
-  const int q = blockIdx.x;
+  const int q = blockIdx.x, tid = threadIdx.x;
   int I = 0;
   while ((I + 1) * (I + 2) / 2 <= q) ++I;
   const int J = q - I * (I + 1) / 2;
-  const T* x = in + bz * sI;
+  const T* x = in + bz * sI + (int64_t)(32 * I) * ldi + 32 * J;
   TO* o = out + bz * sO;
   const double* d = D + bz * sD;
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    tile[r][c] = (double)x[(int64_t)(32 * I + r) * ldi + 32 * J + c];
+  if (tid < 32) dI[tid] = d[32 * I + tid];
+  else if (tid < 64) dJ[tid - 32] = d[32 * J + tid - 32];
+  if (veci) {
+    for (int e = tid; e < 32 * 32 / WI; e += 256) {
+      const int r = e / (32 / WI), c = (e - r * (32 / WI)) * WI;
+      const VI v = *reinterpret_cast<const VI*>(x + (int64_t)r * ldi + c);
+#pragma unroll
+      for (int l = 0; l < WI; ++l) tile[r][c + l] = (double)v[l];
+    }
+  } else {
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int r = e >> 5, c = e & 31;
+      tile[r][c] = (double)x[(int64_t)r * ldi + c];
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    const int i = 32 * I + r, j = 32 * J + c;
-    const double v = (I != J || c <= r) ? tile[r][c] : tile[c][r];
-    o[(int64_t)i * ldo + j] = (TO)(v * d[i] * d[j]);
-    if (I != J) {
-      // element (32 J + r, 32 I + c) of the upper tile = tile[c][r]
-      const int i2 = 32 * J + r, j2 = 32 * I + c;
-      o[(int64_t)i2 * ldo + j2] = (TO)(tile[c][r] * d[i2] * d[j2]);
+  // element (r, c) of tile (I, J) of D sym D, and of its mirror tile (J, I)
+  auto low = [&](int r, int c) { return (I != J || c <= r ? tile[r][c] : tile[c][r]) * dI[r] * dJ[c]; };
+  auto mir = [&](int r, int c) { return tile[c][r] * dJ[r] * dI[c]; };
+  TO* oL = o + (int64_t)(32 * I) * ldo + 32 * J;
+  TO* oU = o + (int64_t)(32 * J) * ldo + 32 * I;
+  if (veco) {
+    for (int e = tid; e < 32 * 32 / WO; e += 256) {
+      const int r = e / (32 / WO), c = (e - r * (32 / WO)) * WO;
+      VO a;
+#pragma unroll
+      for (int l = 0; l < WO; ++l) a[l] = (TO)low(r, c + l);
+      *reinterpret_cast<VO*>(oL + (int64_t)r * ldo + c) = a;
+      if (I != J) {
+#pragma unroll
+        for (int l = 0; l < WO; ++l) a[l] = (TO)mir(r, c + l);
+        *reinterpret_cast<VO*>(oU + (int64_t)r * ldo + c) = a;
+      }
+    }
+  } else {
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int r = e >> 5, c = e & 31;
+      oL[(int64_t)r * ldo + c] = (TO)low(r, c);
+      if (I != J) oU[(int64_t)r * ldo + c] = (TO)mir(r, c);
     }
   }
 }
@@ -1194,8 +1279,12 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
   if (S0 > 0)
     gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
             sY, batch, 0, rs.at(off + S0, off, off + S0));
-  hipLaunchKernelGGL(copy_block_kernel<T>, dim3(h, batch), dim3(256), 0, st, li, DB, sLi,
-                     Y + (int64_t)S0 * ldy + S0, ldy, sY, h);
+  {
+    T* yb = Y + (int64_t)S0 * ldy + S0;
+    const int vec = vec16_ok<T>(li, DB, sLi, h) && vec16_ok<T>(yb, ldy, sY, h);
+    hipLaunchKernelGGL(copy_block_kernel<T>, dim3(helper_blocks((int64_t)h * h / (vec ? 16 / sizeof(T) : 1), batch), batch),
+                       dim3(256), 0, st, li, DB, sLi, yb, ldy, sY, h, vec);
+  }
   const int rest = rend - send;
   if (rest > 0) {
     const T* LlS = L + (int64_t)(off + send) * ldl + (off + S0);
@@ -1211,7 +1300,7 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
   // block forward substitution on L Y = I over the factor's diagonal blocks
   // S: Y holds the running right-hand side R (initially I); Y[S, 0:send] =
   // inv(L_SS) R_S[:, 0:send], and the rows below get one rank-|S| update.
-  hipLaunchKernelGGL(eye_kernel<T>, dim3(nb, batch), dim3(256), 0, st, Y, ldy, sY, nb);
+  launch_eye<T>(st, Y, ldy, sY, nb, batch);
   int S0 = 0;
   while (S0 < nb) {
     const int p = off + S0;
@@ -1234,7 +1323,7 @@ int cholesky_inverse(hipStream_t st, const AuxStreams& ax, T* A, int64_t lda, in
   // triangular inverse reads the final column block k and runs on st2.
   // With env, every step works only on rows below the block's envelope end
   // (the factor is zero beyond it, so the skipped updates are exact zeros).
-  hipLaunchKernelGGL(eye_kernel<T>, dim3(n, batch), dim3(256), 0, st, Y, lda, sY, n);
+  launch_eye<T>(st, Y, lda, sY, n, batch);
   bool far_pending = false;
   int K0 = 0;
   while (K0 < n) {
@@ -1277,8 +1366,9 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
                       int64_t sO, const double* D, int64_t sD, int nb, int batch) {
   if (nb % 32 == 0) {
     const int nt = nb / 32;
+    const int veci = vec16_ok<T>(in, ldi, sI, 32), veco = vec16_ok<TO>(out, ldo, sO, 32);
     hipLaunchKernelGGL((symmetrize_scale_tiled_kernel<T, TO>), dim3(nt * (nt + 1) / 2, batch), dim3(256), 0, st, in,
-                       ldi, sI, out, ldo, sO, D, sD);
+                       ldi, sI, out, ldo, sO, D, sD, veci, veco);
     return;
   }
   hipLaunchKernelGGL((symmetrize_scale_kernel<T, TO>), dim3(nb, batch), dim3(256), 0, st, in, ldi,
