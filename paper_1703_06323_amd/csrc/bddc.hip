@@ -63,24 +63,28 @@ template <> struct RowVec<double> {
 // rows in LDS: 27 lanes each sum one neighbour of the row's node over the
 // cells around it (fixed order), lanes over the object's slots add the
 // C^T R C term, and the row is written out with coalesced stores.
+// Large subdomains (BIG: the padded row buffers and vectors would not fit
+// in LDS) keep the diagonal and the scaling in Dscale, where the scaling
+// ends up anyway, and build only row_waves rows at a time.
 constexpr int ASM_WAVES = 8;   // rows in flight per subdomain (one per wave)
-template <typename T>
+template <typename T, bool BIG>
 __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev sd, GridDev g, T* Kmat,
                                                                        double* diagA_G, double* Dscale,
                                                                        double* __restrict__ st_val,
-                                                                       int32_t* __restrict__ st_col) {
+                                                                       int32_t* __restrict__ st_col,
+                                                                       int row_waves) {
   extern __shared__ double smem[];
   const int w = blockIdx.x;
   const int NIp = sd.NIp, NGp = sd.NGp, NCp = sd.NCp, nt = NIp + NGp;
   const int s = g.s, s3 = s * s * s;
-  double* diag = smem;              // [nt]
-  double* Ds = diag + nt;           // [nt]
-  double* rho = Ds + nt;            // [NCp]: rho_t / |t|^2
+  double* diag = BIG ? Dscale + (int64_t)w * nt : smem;   // [nt]
+  double* Ds = BIG ? diag : diag + nt;                     // [nt] (in place of diag when BIG)
+  double* rho = BIG ? smem : Ds + nt;                      // [NCp]: rho_t / |t|^2
   double* ckh = rho + NCp;          // [s^3]: kappa h per block cell
   int* optr = reinterpret_cast<int*>(ckh + s3);    // [NCp + 1]
   int* omem = optr + NCp + 1;                      // [NGp]
   int* cinfo = omem + NGp;                         // [s^3]
-  T* rows = reinterpret_cast<T*>(ckh + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4));   // [ASM_WAVES][nt]
+  T* rows = reinterpret_cast<T*>(ckh + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4));   // [row_waves][nt]
   const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
   const ProbDev pr = g.prob[sd.sub_prob[w]];
   const int m = pr.m, N1 = pr.N + 1;
@@ -146,16 +150,17 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void assemble_local_kernel(SubDev s
       const int t = gobj[r - NIp];
       if (t >= 0) dk += rho[t];
     }
-    Ds[r] = real ? 1.0 / sqrt(dk) : 1.0;
-    Dscale[(int64_t)w * nt + r] = Ds[r];
+    const double dr = real ? 1.0 / sqrt(dk) : 1.0;
+    Ds[r] = dr;
+    if (!BIG) Dscale[(int64_t)w * nt + r] = dr;
   }
   __syncthreads();
-  // phase 2: rows, one wave per row
+  // phase 2: rows, one wave per row (the first row_waves waves)
   const int lane = tid & 63, wv = tid >> 6;
   T* rb = rows + wv * nt;
   typedef typename RowVec<T>::type V;
   constexpr int VW = 16 / sizeof(T);
-  for (int r = wv; r < nt; r += ASM_WAVES) {
+  for (int r = wv; wv < row_waves && r < nt; r += row_waves) {
     for (int c = lane * VW; c < nt; c += 64 * VW) *reinterpret_cast<V*>(rb + c) = V{};
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -266,8 +271,15 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, const doubl
   __syncthreads();
   const double* x = X + (int64_t)w * nt * NCp;
   double* y = Y + (int64_t)w * nt * NCp;
+  const int nI = sd.nI[w], nG = sd.nG[w], nC = sd.nC[w];
   for (int e = tid; e < R * NCp; e += 256) {
     const int rr = e / NCp, t = e - rr * NCp;
+    // padding rows (empty stencils) and padding columns of X (zero) give 0
+    const int r = rb + rr;
+    if (t >= nC || r >= NIp + nG || (r >= nI && r < NIp)) {
+      y[(int64_t)r * NCp + t] = 0.0;
+      continue;
+    }
     // An empty slot holds the value 0 (and column -1): its load goes to
     // column 0 and adds 0, so all 27 loads issue together, unconditionally.
     double xv[STENCIL];
@@ -395,7 +407,8 @@ __global__ __launch_bounds__(256) void small_spd_inverse_kernel(SubDev sd, doubl
   }
   __syncthreads();
   __shared__ double piv;
-  for (int k = 0; k < NCp; ++k) {
+  // the padding rows and columns are an identity block that no step changes
+  for (int k = 0; k < nC; ++k) {
     if (tid == 0) {
       const double p = S[k * NCp + k];
       if (!(p > 0.0) && info) atomicMax(info, 1);
@@ -626,6 +639,119 @@ __device__ inline void symv_packed(const TM* __restrict__ Pk, int nbu, Gather&& 
   __syncthreads();
 }
 
+// Block-row form of the packed symmetric products, for operators whose
+// per-block partial sums would not fit in LDS: one workgroup of SYMV_ROWS_T
+// threads per (block row I, subdomain) forms
+//   y_I = sum_{J <= I} P_IJ x_J + sum_{K > I} P_KI^T x_K
+// (every block is read twice, once for its row and once for its column).
+// Thread (r, p) (r = t % 32, p = t / 32) sums the columns c = p + 8 k of
+// every block in block order; the 8 partial sums of row r are then added
+// in order of p.  Returns y_I[r] in threads r < 32.
+constexpr int SYMV_ROWS_T = 256;
+template <typename TM>
+__device__ inline double symv_block_row(const TM* __restrict__ Pk, int nbu, int I, const double* xs, double* red) {
+  constexpr int VW = 16 / sizeof(TM);
+  const int t = threadIdx.x, r = t & 31, p = t >> 5;
+  double acc = 0.0;
+  for (int J = 0; J <= I; ++J) {
+    const TM* B = Pk + (int64_t)(I * (I + 1) / 2 + J) * SB * SB;
+#pragma unroll
+    for (int k = 0; k < SB / 8; ++k) {
+      const int c = p + 8 * k;
+      acc += (double)B[packed_offset(r, c, VW)] * xs[J * SB + c];
+    }
+  }
+  for (int K = I + 1; K < nbu; ++K) {
+    const TM* B = Pk + (int64_t)(K * (K + 1) / 2 + I) * SB * SB;
+#pragma unroll
+    for (int k = 0; k < SB / 8; ++k) {
+      const int c = p + 8 * k;
+      acc += (double)B[packed_offset(c, r, VW)] * xs[K * SB + c];
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  double y = 0.0;
+  if (t < SB)
+    for (int q = 0; q < SYMV_ROWS_T / SB; ++q) y += red[q * SB + t];
+  return y;
+}
+
+// apply_interior_kernel in block-row form: grid (NIp / SB, ns).
+template <typename TM>
+__global__ __launch_bounds__(SYMV_ROWS_T) void apply_interior_rows_kernel(SubDev sd, const TM* __restrict__ P,
+                                                                      const double* __restrict__ a,
+                                                                      const double* __restrict__ b,
+                                                                      double* __restrict__ out) {
+  extern __shared__ double lds[];
+  const int I = blockIdx.x, w = blockIdx.y;
+  if (sd.active && !sd.active[sd.sub_prob[w]]) return;
+  const int NIp = sd.NIp, nbk = (NIp / SB) * (NIp / SB + 1) / 2;
+  const int nI = sd.nI[w], nbu = (nI + SB - 1) / SB;
+  if (I >= nbu) return;
+  double* xs = lds;                 // [NIp]
+  double* red = xs + NIp;           // [SYMV_ROWS_T]
+  const int64_t* idx = sd.I_idx + (int64_t)w * NIp;
+  for (int j = threadIdx.x; j < NIp; j += blockDim.x) {
+    double v = 0.0;
+    if (j < nI) {
+      const int64_t n = idx[j];
+      v = a[n] - (b ? b[n] : 0.0);
+    }
+    xs[j] = v;
+  }
+  __syncthreads();
+  const double y = symv_block_row<TM>(P + (int64_t)w * nbk * SB * SB, nbu, I, xs, red);
+  const int j = I * SB + threadIdx.x;
+  if (threadIdx.x < SB && j < nI) out[idx[j]] = y;
+}
+
+// apply_neumann_kernel in block-row form: grid (NGp / SB, ns); block row 0
+// also forms the coarse restriction cloc_w = Phi_w^T g_w.
+template <typename TM>
+__global__ __launch_bounds__(SYMV_ROWS_T) void apply_neumann_rows_kernel(SubDev sd, const TM* __restrict__ Kt,
+                                                                     const double* __restrict__ Phi,
+                                                                     const double* __restrict__ Dw,
+                                                                     const double* __restrict__ r,
+                                                                     const double* __restrict__ t,
+                                                                     double* __restrict__ z,
+                                                                     double* __restrict__ cloc) {
+  extern __shared__ double lds[];
+  const int I = blockIdx.x, w = blockIdx.y;
+  if (sd.active && !sd.active[sd.sub_prob[w]]) return;
+  const int NGp = sd.NGp, NCp = sd.NCp, nbk = (NGp / SB) * (NGp / SB + 1) / 2;
+  const int nG = sd.nG[w], nC = sd.nC[w], nbu = (nG + SB - 1) / SB;
+  const int tid = threadIdx.x;
+  if (I >= nbu) {
+    if (tid < SB) z[(int64_t)w * NGp + I * SB + tid] = 0.0;
+    return;
+  }
+  double* gs = lds;                 // [NGp]
+  double* red = gs + NGp;           // [SYMV_ROWS_T]
+  const int64_t* idx = sd.G_idx + (int64_t)w * NGp;
+  for (int j = tid; j < NGp; j += blockDim.x) {
+    double v = 0.0;
+    if (j < nG) {
+      const int64_t n = idx[j];
+      v = Dw[(int64_t)w * NGp + j] * (r[n] - t[n]);
+    }
+    gs[j] = v;
+  }
+  __syncthreads();
+  if (I == 0) {
+    const double* ph = Phi + (int64_t)w * NGp * NCp;
+    for (int u = tid; u < NCp; u += blockDim.x) {
+      double acc = 0.0;
+      if (u < nC)
+        for (int j = 0; j < nG; ++j) acc += ph[(int64_t)j * NCp + u] * gs[j];
+      cloc[(int64_t)w * NCp + u] = acc;
+    }
+  }
+  const double y = symv_block_row<TM>(Kt + (int64_t)w * nbk * SB * SB, nbu, I, gs, red);
+  const int j = I * SB + tid;
+  if (tid < SB) z[(int64_t)w * NGp + j] = j < nG ? y : 0.0;
+}
+
 // Threads per workgroup of the packed apply kernels: with two subdomains
 // per CU, 512 threads keep 4 waves per SIMD streaming operator blocks.
 constexpr int APPLY_T = 512;
@@ -820,33 +946,68 @@ void bddc_set_reference(const double* Kref) {
 inline int packed_blocks(int n) { return (n / SB) * (n / SB + 1) / 2; }
 
 // Dynamic LDS bytes of the per-subdomain kernels, from the padded sizes.
+// The assembly keeps its diagonal and scaling vectors in LDS and builds
+// ASM_WAVES rows at a time when that fits; otherwise (big) it keeps them in
+// global memory and builds as many rows at a time as fit (asm_row_waves).
+size_t lds_assemble_fixed(int NGp, int NCp, int s) {
+  const int s3 = s * s * s;
+  return (size_t)(NCp + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4)) * sizeof(double);
+}
 size_t lds_assemble_local(int NIp, int NGp, int NCp, int s, size_t elem) {
   const int nt = NIp + NGp;
-  const int s3 = s * s * s;
-  return (size_t)(2 * nt + NCp + s3 + 2 * ((NCp + 1 + NGp + s3 + 3) / 4)) * sizeof(double) +
-         (size_t)ASM_WAVES * nt * elem;
+  return lds_assemble_fixed(NGp, NCp, s) + (size_t)2 * nt * sizeof(double) + (size_t)ASM_WAVES * nt * elem;
 }
+// rows in flight of the big assembly (0: even one row does not fit)
+int asm_row_waves(int NIp, int NGp, int NCp, int s, size_t elem) {
+  const size_t fixed = lds_assemble_fixed(NGp, NCp, s), row = (size_t)(NIp + NGp) * elem;
+  if (fixed + row > LDS_BYTES) return 0;
+  return (int)std::min<size_t>(ASM_WAVES, (LDS_BYTES - fixed) / row);
+}
+bool asm_big(int NIp, int NGp, int NCp, int s, size_t elem) {
+  return lds_assemble_local(NIp, NGp, NCp, s, elem) > LDS_BYTES;
+}
+// The packed applies hold the vectors and the partial sums of every block in
+// LDS; larger operators take the block-row form (x and one partial per
+// thread in LDS).
 size_t lds_apply_interior(int NIp) { return (size_t)(2 * NIp + 2 * packed_blocks(NIp) * SB) * sizeof(double); }
 size_t lds_apply_neumann(int NGp) {
   return (size_t)(2 * NGp + 2 * packed_blocks(NGp) * SB + APPLY_T) * sizeof(double);
 }
+size_t lds_apply_rows(int n) { return (size_t)(n + SYMV_ROWS_T) * sizeof(double); }
 size_t lds_small_spd_inverse(int NCp) { return (size_t)NCp * NCp * sizeof(double); }
 
 size_t bddc_lds_need(int NIp, int NGp, int NCp, int s, int fp32_local) {
   const size_t elem = fp32_local ? sizeof(float) : sizeof(double);
-  return std::max(std::max(lds_assemble_local(NIp, NGp, NCp, s, elem), lds_apply_interior(NIp)),
-                  std::max(lds_apply_neumann(NGp), lds_small_spd_inverse(NCp)));
+  const size_t as = asm_big(NIp, NGp, NCp, s, elem)
+                        ? (asm_row_waves(NIp, NGp, NCp, s, elem) > 0 ? lds_assemble_fixed(NGp, NCp, s) +
+                                                                             (size_t)(NIp + NGp) * elem
+                                                                       : (size_t)-1)
+                        : lds_assemble_local(NIp, NGp, NCp, s, elem);
+  const size_t ai = lds_apply_interior(NIp) <= LDS_BYTES ? lds_apply_interior(NIp) : lds_apply_rows(NIp);
+  const size_t an = lds_apply_neumann(NGp) <= LDS_BYTES ? lds_apply_neumann(NGp) : lds_apply_rows(NGp);
+  return std::max(std::max(as, ai), std::max(an, lds_small_spd_inverse(NCp)));
 }
 
 template <typename T>
 void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, int ns, T* K,
                            double* diagA_G, double* Dscale, double* st_val, int32_t* st_col) {
-  const size_t sh = lds_assemble_local(sd.NIp, sd.NGp, sd.NCp, g.s, sizeof(T));
-  static const bool attr = hipFuncSetAttribute((const void*)assemble_local_kernel<T>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+  static const bool attr =
+      hipFuncSetAttribute((const void*)assemble_local_kernel<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)LDS_BYTES) == hipSuccess &&
+      hipFuncSetAttribute((const void*)assemble_local_kernel<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)LDS_BYTES) == hipSuccess;
   (void)attr;
-  hipLaunchKernelGGL(assemble_local_kernel<T>, dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G, Dscale,
-                     st_val, st_col);
+  if (!asm_big(sd.NIp, sd.NGp, sd.NCp, g.s, sizeof(T))) {
+    const size_t sh = lds_assemble_local(sd.NIp, sd.NGp, sd.NCp, g.s, sizeof(T));
+    hipLaunchKernelGGL((assemble_local_kernel<T, false>), dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G,
+                       Dscale, st_val, st_col, ASM_WAVES);
+  } else {
+    // setup has checked that one row fits (bddc_lds_need)
+    const int rw = asm_row_waves(sd.NIp, sd.NGp, sd.NCp, g.s, sizeof(T));
+    const size_t sh = lds_assemble_fixed(sd.NGp, sd.NCp, g.s) + (size_t)rw * (sd.NIp + sd.NGp) * sizeof(T);
+    hipLaunchKernelGGL((assemble_local_kernel<T, true>), dim3(ns), dim3(64 * ASM_WAVES), sh, st, sd, g, K, diagA_G,
+                       Dscale, st_val, st_col, rw);
+  }
 }
 template void launch_assemble_local<double>(hipStream_t, const SubDev&, const GridDev&, int, double*,
                                             double*, double*, double*, int32_t*);
@@ -936,6 +1097,15 @@ template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out) {
   const size_t sh = lds_apply_interior(sd.NIp);
+  if (sh > LDS_BYTES) {
+    static const bool attr_rows = hipFuncSetAttribute((const void*)apply_interior_rows_kernel<TM>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      (int)LDS_BYTES) == hipSuccess;
+    (void)attr_rows;
+    hipLaunchKernelGGL(apply_interior_rows_kernel<TM>, dim3(sd.NIp / SB, ns), dim3(SYMV_ROWS_T),
+                       lds_apply_rows(sd.NIp), st, sd, P, a, b, out);
+    return;
+  }
   static bool attr = (hipFuncSetAttribute((const void*)apply_interior_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
@@ -950,6 +1120,15 @@ template <typename TM>
 void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc) {
   const size_t sh = lds_apply_neumann(sd.NGp);
+  if (sh > LDS_BYTES) {
+    static const bool attr_rows = hipFuncSetAttribute((const void*)apply_neumann_rows_kernel<TM>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      (int)LDS_BYTES) == hipSuccess;
+    (void)attr_rows;
+    hipLaunchKernelGGL(apply_neumann_rows_kernel<TM>, dim3(sd.NGp / SB, ns), dim3(SYMV_ROWS_T),
+                       lds_apply_rows(sd.NGp), st, sd, Kt, Phi, Dw, r, t, z, cloc);
+    return;
+  }
   static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;

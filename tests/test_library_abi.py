@@ -50,11 +50,12 @@ def _setup_status(problem):
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-@pytest.mark.parametrize("s", [12, 16])
+@pytest.mark.parametrize("s", [24, 32])
 def test_setup_rejects_blocks_too_large_for_lds(s):
-    """Subdomain blocks whose padded local vectors and partial sums exceed
-    the 160 KB of LDS of a workgroup are an argument error at setup, not a
-    launch failure inside factor or solve."""
+    """Subdomain blocks whose cell tables and one assembly row exceed the
+    160 KB of LDS of a workgroup are an argument error at setup, not a
+    launch failure inside factor or solve (blocks up to 16 cells per side
+    take the large-subdomain kernels)."""
     import workloads as W
     from paper_1703_06323_amd import cutbddc
     rc, msg, ctx = _setup_status(W.uncut(2 * s, s))
