@@ -1120,6 +1120,25 @@ int gemm_autotune(int TA, int TB, int M, int N, int K, int batch, int mode) {
   return gemm_autotune_impl<T>(TA, TB, M, N, K, batch, mode, 0);
 }
 
+// Operands of the tuning runs: values in [-0.5, 0.5) from a hash of the
+// index (the MFMA units and the memory system see data like the real
+// operands', not zeros).
+template <typename T>
+__global__ __launch_bounds__(256) void tune_fill_kernel(T* p, int64_t n, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = T((double)(h & 0xffffu) / 65536.0 - 0.5);
+  }
+}
+template <typename T>
+void tune_fill(T* p, int64_t n, uint32_t seed) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256));
+  hipLaunchKernelGGL(tune_fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, nullptr, p, n, seed);
+}
+
 template <typename T>
 int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode, int inplace) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
@@ -1146,9 +1165,9 @@ int gemm_autotune_impl(int TA, int TB, int M, int N, int K, int batch, int mode,
     (void)hipFree(C);
     return best;
   }
-  (void)hipMemset(A, 0, sA * batch * sizeof(T));
-  (void)hipMemset(B, 0, sB * batch * sizeof(T));
-  (void)hipMemset(C, 0, sC * batch * sizeof(T));
+  tune_fill<T>(A, sA * batch, 1u);
+  tune_fill<T>(B, sB * batch, 2u);
+  tune_fill<T>(C, sC * batch, 3u);
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
