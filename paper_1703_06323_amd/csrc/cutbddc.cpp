@@ -55,14 +55,80 @@ int fail(int code, const std::string& msg) {
     if (rc_ != CB_OK) return rc_; \
   } while (0)
 
-// Two timing events owned by one call, destroyed on every exit (error
+// Streams, events and pinned staging blocks of finished calls and destroyed
+// contexts, kept for later ones: creating and destroying them costs about
+// 0.2 ms per context, as much as a small solver step.  Kept per device;
+// whatever comes back is idle (a context synchronises its streams before it
+// hands them back, a call's timing events have completed or are re-recorded
+// before any read).  The pool lives until the process ends.
+struct HandlePool {
+  std::mutex mu;
+  std::map<int, std::vector<hipStream_t>> streams;      // non-blocking, default priority
+  std::map<int, std::vector<hipEvent_t>> sync_events;   // timing disabled
+  std::map<int, std::vector<hipEvent_t>> time_events;   // timing enabled
+  std::map<int, std::vector<std::pair<size_t, void*>>> pinned;
+};
+HandlePool& handle_pool() {
+  static HandlePool* p = new HandlePool;
+  return *p;
+}
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+template <typename H>
+bool pool_take(std::map<int, std::vector<H>>& m, int dev, H* out) {
+  std::lock_guard<std::mutex> g(handle_pool().mu);
+  auto& v = m[dev];
+  if (v.empty()) return false;
+  *out = v.back();
+  v.pop_back();
+  return true;
+}
+template <typename H>
+void pool_put(std::map<int, std::vector<H>>& m, int dev, H h) {
+  std::lock_guard<std::mutex> g(handle_pool().mu);
+  m[dev].push_back(h);
+}
+hipError_t pooled_stream(hipStream_t* s) {
+  if (pool_take(handle_pool().streams, current_device(), s)) return hipSuccess;
+  return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+hipError_t pooled_sync_event(hipEvent_t* e) {
+  if (pool_take(handle_pool().sync_events, current_device(), e)) return hipSuccess;
+  return hipEventCreateWithFlags(e, hipEventDisableTiming);
+}
+hipError_t pooled_time_event(hipEvent_t* e) {
+  if (pool_take(handle_pool().time_events, current_device(), e)) return hipSuccess;
+  return hipEventCreate(e);
+}
+// pinned block of at least `bytes` (its capacity in *cap)
+hipError_t pooled_pinned(void** p, size_t bytes, size_t* cap) {
+  {
+    std::lock_guard<std::mutex> g(handle_pool().mu);
+    auto& v = handle_pool().pinned[current_device()];
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i].first >= bytes) {
+        *cap = v[i].first;
+        *p = v[i].second;
+        v.erase(v.begin() + (std::ptrdiff_t)i);
+        return hipSuccess;
+      }
+  }
+  *cap = std::max<size_t>(bytes, 4096);
+  return hipHostMalloc(p, *cap, hipHostMallocDefault);
+}
+
+// Two timing events owned by one call, handed back on every exit (error
 // returns included).
 struct EventPair {
   hipEvent_t* a;
   hipEvent_t* b;
   ~EventPair() {
-    if (*a) (void)hipEventDestroy(*a);
-    if (*b) (void)hipEventDestroy(*b);
+    const int dev = current_device();
+    if (*a) pool_put(handle_pool().time_events, dev, *a);
+    if (*b) pool_put(handle_pool().time_events, dev, *b);
   }
 };
 
@@ -351,6 +417,8 @@ struct cb_ctx {
   DevBuf params, active, itc, status, relres_d, nact_d, fptrs, uptrs;
   // pinned host staging: [0] n_active, then P iterations, P statuses, P relres, 2P pointers
   void* pin = nullptr;
+  size_t pin_cap = 0;
+  int dev = 0;                       // device of the context's streams, events and pinned block
   int32_t* pin_nact_dev = nullptr;   // device address of pin_nact()
   // second and third streams for work that overlaps the coarse factorisation
   hipStream_t aux_st = nullptr, aux_st3 = nullptr;
@@ -364,13 +432,14 @@ struct cb_ctx {
 
   ~cb_ctx() {
     if (graph) (void)hipGraphExecDestroy(graph);
-    if (cap_st) (void)hipStreamDestroy(cap_st);
-    if (aux_st) (void)hipStreamDestroy(aux_st);
-    if (aux_st3) (void)hipStreamDestroy(aux_st3);
-    if (aux_ev) (void)hipEventDestroy(aux_ev);
-    if (aux_ev3) (void)hipEventDestroy(aux_ev3);
-    if (nact_ev) (void)hipEventDestroy(nact_ev);
-    if (pin) (void)hipHostFree(pin);
+    // streams, events and the pinned block go back to the handle pool, idle
+    HandlePool& hp = handle_pool();
+    for (hipStream_t s : {cap_st, aux_st, aux_st3})
+      if (s && hipStreamSynchronize(s) == hipSuccess) pool_put(hp.streams, dev, s);
+      else if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : {aux_ev, aux_ev3, nact_ev})
+      if (e) pool_put(hp.sync_events, dev, e);
+    if (pin) pool_put(hp.pinned, dev, std::make_pair(pin_cap, pin));
     for (auto& kv : prof_ev)
       for (auto& e : kv.second.ev) {
         (void)hipEventDestroy(e.first);
@@ -575,7 +644,7 @@ bool graphs_enabled() {
 // capture runs on a private stream; replays go to the context's stream.
 int capture_body(cb_ctx* c) {
   if (c->graph || c->graph_failed) return CB_OK;
-  if (!c->cap_st) HIPCHK(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  if (!c->cap_st) HIPCHK(pooled_stream(&c->cap_st));
   hipStream_t user = c->st;
   c->st = c->cap_st;
   hipGraph_t g = nullptr;
@@ -633,7 +702,7 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
     HIPCHK(hipGetLastError());
     const bool use_graph = graphs_enabled() && !c->prof;
     if (use_graph) CHK(capture_body(c));
-    if (!c->nact_ev) HIPCHK(hipEventCreateWithFlags(&c->nact_ev, hipEventDisableTiming));
+    if (!c->nact_ev) HIPCHK(pooled_sync_event(&c->nact_ev));
     auto issue = [&]() -> int {
       if (use_graph && c->graph) HIPCHK(hipGraphLaunch(c->graph, st));
       else CHK(pcg_body(c));
@@ -802,6 +871,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
       return fail(CB_ERR_ARG, "problems of a batch must share sub_cells and every option");
   }
   std::unique_ptr<cb_ctx> c(new cb_ctx());
+  c->dev = current_device();
   c->st = static_cast<hipStream_t>(stream);
   g_alloc_stream = c->st;
   c->P = P;
@@ -817,8 +887,8 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EventPair ev01{&e0, &e1};
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(pooled_time_event(&e0));
+  HIPCHK(pooled_time_event(&e1));
   HIPCHK(hipEventRecord(e0, st));
 
   // problem segments
@@ -980,8 +1050,8 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   HIPCHK(hipGetLastError());
   hipEvent_t ea = nullptr, eb = nullptr;
   EventPair ev_ab{&ea, &eb};
-  HIPCHK(hipEventCreate(&ea));
-  HIPCHK(hipEventCreate(&eb));
+  HIPCHK(pooled_time_event(&ea));
+  HIPCHK(pooled_time_event(&eb));
   HIPCHK(hipEventRecord(ea, st));
 
   // ---- device indexing (one readback of the counts) ----------------------
@@ -1236,7 +1306,7 @@ int setup_impl(const cb_problem* ps, int P, void* stream, cb_ctx** out) {
   CHK(dalloc(c->nact_d, sizeof(int32_t)));
   CHK(dalloc(c->fptrs, (size_t)P * sizeof(double*)));
   CHK(dalloc(c->uptrs, (size_t)P * sizeof(double*)));
-  HIPCHK(hipHostMalloc(&c->pin, c->pin_bytes(), hipHostMallocDefault));
+  HIPCHK(pooled_pinned(&c->pin, c->pin_bytes(), &c->pin_cap));
   {
     void* dp = nullptr;
     HIPCHK(hipHostGetDevicePointer(&dp, c->pin, 0));
@@ -1691,14 +1761,27 @@ int factor_impl(cb_ctx* c) {
   CHK(dalloc(c->diagAG, (size_t)ns * NGp * sizeof(double)));
   CHK(dalloc(c->Ds, (size_t)ns * nt * sizeof(double)));
   CHK(dalloc(c->Dw, (size_t)ns * NGp * sizeof(double)));
-  if (!c->aux_st) HIPCHK(hipStreamCreateWithFlags(&c->aux_st, hipStreamNonBlocking));
-  if (!c->aux_st3) HIPCHK(hipStreamCreateWithFlags(&c->aux_st3, hipStreamNonBlocking));
-  if (!c->aux_ev) HIPCHK(hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
-  if (!c->aux_ev3) HIPCHK(hipEventCreateWithFlags(&c->aux_ev3, hipEventDisableTiming));
+  if (!c->aux_st) HIPCHK(pooled_stream(&c->aux_st));
+  if (!c->aux_st3) HIPCHK(pooled_stream(&c->aux_st3));
+  if (!c->aux_ev) HIPCHK(pooled_sync_event(&c->aux_ev));
+  if (!c->aux_ev3) HIPCHK(pooled_sync_event(&c->aux_ev3));
   const int n_info = ns + 1 + c->P;
   CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
   HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));
   HIPCHK(hipMemsetAsync(c->Dw.p, 0, (size_t)ns * NGp * sizeof(double), st));
+  // coarse ids and blocks of every subdomain (fixed since setup), for the
+  // host side of the coarse factorisation; read now, while only the fills
+  // above are queued, so that the coarse section needs no synchronisation
+  std::vector<int32_t> cids, ncs, blk;
+  if (c->ac_total > 0) {
+    cids.resize((size_t)ns * NCp);
+    ncs.resize(ns);
+    blk.resize(ns);
+    HIPCHK(hipMemcpyAsync(cids.data(), c->Cids.p, cids.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ncs.data(), c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(blk.data(), c->sub_blk_d.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   DevBuf AcLoc;
   CHK(dalloc(AcLoc, (size_t)ns * sC * sizeof(double)));
   // object member lists, once for all subdomains (sub() hands them out below)
@@ -1740,18 +1823,10 @@ int factor_impl(cb_ctx* c) {
   std::vector<int> coarse_slot(c->P, -1);   // index into info_d after ns + 1
   c->nd.on = false;
   if (c->ac_total > 0) {
-    // coarse ids of every subdomain (fixed since setup)
-    std::vector<int32_t> cids((size_t)ns * NCp), ncs(ns);
-    HIPCHK(hipMemcpyAsync(cids.data(), c->Cids.p, cids.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ncs.data(), c->nC.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    // (the coarse ids and blocks of every subdomain were read back before
+    // the local factorisation: the host work below runs while it does)
     NDPlan plan;
-    bool use_nd = false;
-    if (coarse_nd_wanted(c)) {
-      std::vector<int32_t> blk(ns);
-      HIPCHK(hipMemcpyAsync(blk.data(), c->sub_blk_d.p, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      use_nd = plan_nd(c, cids, ncs, blk, plan);
-    }
+    const bool use_nd = coarse_nd_wanted(c) && plan_nd(c, cids, ncs, blk, plan);
     DevBuf Ac;
     CHK(dalloc(Ac, (size_t)c->ac_total * sizeof(double)));
     if (use_nd) c->Acinv.release();
@@ -1773,7 +1848,6 @@ int factor_impl(cb_ctx* c) {
     // Envelope of each coarse matrix: A_c couples two coarse DOFs only
     // when a subdomain holds both, so row i's first nonzero column is the
     // smallest coarse id among the subdomains that hold i.
-    HIPCHK(hipStreamSynchronize(st));
     std::vector<int32_t> first(c->nc_tot);   // problem-local
     for (int k = 0; k < c->P; ++k)
       for (int i = 0; i < c->pb[k].n_coarse; ++i) first[c->pb[k].coarse_off + i] = i;
@@ -1985,8 +2059,8 @@ int cb_factor(cb_ctx* c) {
   if (!c) return fail(CB_ERR_ARG, "null context");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EventPair ev01{&e0, &e1};
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(pooled_time_event(&e0));
+  HIPCHK(pooled_time_event(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
   c->factored = false;
   if (c->graph) {
@@ -2016,8 +2090,8 @@ namespace {
 int solve_common(cb_ctx* c, double* u_dev, double* const* u_ptrs_dev, double rtol, int32_t max_iter) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EventPair ev01{&e0, &e1};
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(pooled_time_event(&e0));
+  HIPCHK(pooled_time_event(&e1));
   HIPCHK(hipEventRecord(e0, c->st));
   int sweeps = 0;
   CHK(pcg(c, rtol, max_iter, &sweeps));
@@ -2606,8 +2680,8 @@ int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms) {
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EventPair ev01{&e0, &e1};
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(pooled_time_event(&e0));
+  HIPCHK(pooled_time_event(&e1));
   launch();   // warm
   HIPCHK(hipEventRecord(e0, st));
   for (int i = 0; i < reps; ++i) launch();
