@@ -153,6 +153,7 @@ class Solver:
         _check(lib.cb_setup(C.byref(p), C.c_void_p(st.cuda_stream), C.byref(ctx)))
         self.ctx = ctx
         self.n = int(problem.n)
+        self._n_dof = None
 
     def __del__(self):
         if getattr(self, "ctx", None) and _lib is not None:
@@ -173,7 +174,10 @@ class Solver:
 
     @property
     def n_dof(self) -> int:
-        return int(self.info()["n_dof"])
+        # fixed at setup
+        if self._n_dof is None:
+            self._n_dof = int(self.info()["n_dof"])
+        return self._n_dof
 
     def _vec(self, n):
         return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
