@@ -115,14 +115,15 @@ def apply_bytes(info, probs, s_bytes):
         Dirichlet inverse (s_bytes each) plus 2.5 gathered / scattered
         vectors of n_I doubles on average (2 on the first launch of an
         apply, 3 on the second);
-      apply_neumann: the unique entries of Kt (s_bytes each), Phi (n_G n_c
-        doubles) and four vectors of n_G doubles (two inputs, the weights,
+      apply_neumann: the unique entries of Kt and the n_G n_c entries of
+        Phi (s_bytes each: Phi is kept in the local precision for these
+        products) and four vectors of n_G doubles (two inputs, the weights,
         the output)."""
     nodes = sum((p.n + 1) ** 3 for p in probs)
     cells = sum(p.n ** 3 for p in probs)
     a = 16.0 * nodes + 4.0 * cells + 8.0 * info["n_active"] + 288.0 * info["n_cut_stored"]
     i = s_bytes * (info["sum_nI2"] + info["sum_nI"]) / 2.0 + 8.0 * 2.5 * info["sum_nI"]
-    g = s_bytes * (info["sum_nG2"] + info["sum_nG"]) / 2.0 + 8.0 * info["sum_nGnC"] + 32.0 * info["sum_nG"]
+    g = s_bytes * (info["sum_nG2"] + info["sum_nG"]) / 2.0 + s_bytes * info["sum_nGnC"] + 32.0 * info["sum_nG"]
     return {"apply_A": a, "apply_interior": i, "apply_neumann": g}
 
 

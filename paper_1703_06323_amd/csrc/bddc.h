@@ -83,8 +83,9 @@ void launch_pack_lower(hipStream_t st, int n, int ns, const TI* in, int64_t ldi,
 template <typename TM>
 void launch_apply_interior(hipStream_t st, const SubDev& sd, int ns, const TM* P, const double* a,
                            const double* b, double* out);
-template <typename TM>
-void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
+// Phi in the storage type TP (FP64; FP32 on the FP32-local path).
+template <typename TM, typename TP>
+void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const TP* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc);
 // Largest dynamic LDS request in bytes of the per-subdomain kernels (local
 // assembly, packed applies, coarse-basis Gram inverse) for padded orders
@@ -100,8 +101,8 @@ void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int3
 // (p = coarse_prob[c]).  t has nc_total entries.
 void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const int32_t* coarse_prob,
                         const double* M, const double* x, double* t, double* y);
-void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,
-                       double* z);
+template <typename TP>
+void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const TP* Phi, const double* uc, double* z);
 void launch_iface_average(hipStream_t st, int64_t n_iface, const int64_t* iface_node, const int64_t* if_ptr,
                           const int32_t* if_sub, const int32_t* if_slot, int NGp, const double* Dw,
                           const double* z, double* out);

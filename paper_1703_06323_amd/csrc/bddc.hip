@@ -708,9 +708,9 @@ __global__ __launch_bounds__(SYMV_ROWS_T) void apply_interior_rows_kernel(SubDev
 
 // apply_neumann_kernel in block-row form: grid (NGp / SB, ns); block row 0
 // also forms the coarse restriction cloc_w = Phi_w^T g_w.
-template <typename TM>
+template <typename TM, typename TP>
 __global__ __launch_bounds__(SYMV_ROWS_T) void apply_neumann_rows_kernel(SubDev sd, const TM* __restrict__ Kt,
-                                                                     const double* __restrict__ Phi,
+                                                                     const TP* __restrict__ Phi,
                                                                      const double* __restrict__ Dw,
                                                                      const double* __restrict__ r,
                                                                      const double* __restrict__ t,
@@ -739,11 +739,11 @@ __global__ __launch_bounds__(SYMV_ROWS_T) void apply_neumann_rows_kernel(SubDev 
   }
   __syncthreads();
   if (I == 0) {
-    const double* ph = Phi + (int64_t)w * NGp * NCp;
+    const TP* ph = Phi + (int64_t)w * NGp * NCp;
     for (int u = tid; u < NCp; u += blockDim.x) {
       double acc = 0.0;
       if (u < nC)
-        for (int j = 0; j < nG; ++j) acc += ph[(int64_t)j * NCp + u] * gs[j];
+        for (int j = 0; j < nG; ++j) acc += (double)ph[(int64_t)j * NCp + u] * gs[j];
       cloc[(int64_t)w * NCp + u] = acc;
     }
   }
@@ -790,9 +790,9 @@ __global__ __launch_bounds__(APPLY_T) void apply_interior_kernel(SubDev sd, cons
 
 // z_w = Kt_w g_w with g_w[j] = Dw[j] (r - t)[G_idx[j]] (Kt_w packed);
 // cloc_w = Phi_w^T g_w.
-template <typename TM>
+template <typename TM, typename TP>
 __global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const TM* __restrict__ Kt,
-                                                            const double* __restrict__ Phi,
+                                                            const TP* __restrict__ Phi,
                                                             const double* __restrict__ Dw,
                                                             const double* __restrict__ r,
                                                             const double* __restrict__ t,
@@ -825,14 +825,14 @@ __global__ __launch_bounds__(APPLY_T) void apply_neumann_kernel(SubDev sd, const
     // so that consecutive threads read consecutive entries of a row; the G
     // partial sums of a column are added in a fixed order
     double* part = colp + nbk * SB;   // [blockDim]
-    const double* ph = Phi + (int64_t)w * NGp * NCp;
+    const TP* ph = Phi + (int64_t)w * NGp * NCp;
     const int tid = threadIdx.x;
     for (int u0 = 0; u0 < NCp; u0 += blockDim.x) {
       const int nu = min(NCp - u0, (int)blockDim.x), G = blockDim.x / nu;
       const int u = u0 + tid % nu, gq = tid / nu;
       double acc = 0.0;
       if (gq < G && u < nC)
-        for (int j = gq; j < nG; j += G) acc += ph[(int64_t)j * NCp + u] * gs[j];
+        for (int j = gq; j < nG; j += G) acc += (double)ph[(int64_t)j * NCp + u] * gs[j];
       part[tid] = acc;
       __syncthreads();
       if (tid < nu) {
@@ -904,7 +904,8 @@ __global__ __launch_bounds__(CT_T) void coarse_tri_kernel(BatchDev bd, const int
 }
 
 // u~_w[j] = z_w[j] + sum_t Phi_w[j][t] u_c[C_ids[t]]  (in place in z)
-__global__ __launch_bounds__(256) void add_coarse_kernel(SubDev sd, const double* __restrict__ Phi,
+template <typename TP>
+__global__ __launch_bounds__(256) void add_coarse_kernel(SubDev sd, const TP* __restrict__ Phi,
                                                          const double* __restrict__ uc, double* __restrict__ z) {
   extern __shared__ double ul[];
   const int w = blockIdx.x;
@@ -913,10 +914,10 @@ __global__ __launch_bounds__(256) void add_coarse_kernel(SubDev sd, const double
   const int nG = sd.nG[w], nC = sd.nC[w];
   for (int t = threadIdx.x; t < NCp; t += 256) ul[t] = t < nC ? uc[sd.C_ids[(int64_t)w * NCp + t]] : 0.0;
   __syncthreads();
-  const double* ph = Phi + (int64_t)w * NGp * NCp;
+  const TP* ph = Phi + (int64_t)w * NGp * NCp;
   for (int j = threadIdx.x; j < nG; j += 256) {
     double acc = z[(int64_t)w * NGp + j];
-    for (int t = 0; t < nC; ++t) acc += ph[(int64_t)j * NCp + t] * ul[t];
+    for (int t = 0; t < nC; ++t) acc += (double)ph[(int64_t)j * NCp + t] * ul[t];
     z[(int64_t)w * NGp + j] = acc;
   }
 }
@@ -1116,28 +1117,29 @@ template void launch_apply_interior<double>(hipStream_t, const SubDev&, int, con
 template void launch_apply_interior<float>(hipStream_t, const SubDev&, int, const float*, const double*,
                                            const double*, double*);
 
-template <typename TM>
-void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const double* Phi,
+template <typename TM, typename TP>
+void launch_apply_neumann(hipStream_t st, const SubDev& sd, int ns, const TM* Kt, const TP* Phi,
                           const double* Dw, const double* r, const double* t, double* z, double* cloc) {
   const size_t sh = lds_apply_neumann(sd.NGp);
   if (sh > LDS_BYTES) {
-    static const bool attr_rows = hipFuncSetAttribute((const void*)apply_neumann_rows_kernel<TM>,
+    static const bool attr_rows = hipFuncSetAttribute((const void*)apply_neumann_rows_kernel<TM, TP>,
                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
                                                       (int)LDS_BYTES) == hipSuccess;
     (void)attr_rows;
-    hipLaunchKernelGGL(apply_neumann_rows_kernel<TM>, dim3(sd.NGp / SB, ns), dim3(SYMV_ROWS_T),
+    hipLaunchKernelGGL((apply_neumann_rows_kernel<TM, TP>), dim3(sd.NGp / SB, ns), dim3(SYMV_ROWS_T),
                        lds_apply_rows(sd.NGp), st, sd, Kt, Phi, Dw, r, t, z, cloc);
     return;
   }
-  static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM>,
+  static bool attr = (hipFuncSetAttribute((const void*)apply_neumann_kernel<TM, TP>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess);
   (void)attr;
-  hipLaunchKernelGGL(apply_neumann_kernel<TM>, dim3(ns), dim3(APPLY_T), sh, st, sd, Kt, Phi, Dw, r, t, z, cloc);
+  hipLaunchKernelGGL((apply_neumann_kernel<TM, TP>), dim3(ns), dim3(APPLY_T), sh, st, sd, Kt, Phi, Dw, r, t, z,
+                     cloc);
 }
-template void launch_apply_neumann<double>(hipStream_t, const SubDev&, int, const double*, const double*,
-                                           const double*, const double*, const double*, double*, double*);
-template void launch_apply_neumann<float>(hipStream_t, const SubDev&, int, const float*, const double*,
-                                          const double*, const double*, const double*, double*, double*);
+template void launch_apply_neumann<double, double>(hipStream_t, const SubDev&, int, const double*, const double*,
+                                                   const double*, const double*, const double*, double*, double*);
+template void launch_apply_neumann<float, float>(hipStream_t, const SubDev&, int, const float*, const float*,
+                                                 const double*, const double*, const double*, double*, double*);
 
 void launch_coarse_rhs(hipStream_t st, int nc, const int64_t* cs_ptr, const int32_t* cs_sub,
                        const int32_t* cs_row, int NCp, const double* cloc, double* c) {
@@ -1153,10 +1155,12 @@ void launch_coarse_gemv(hipStream_t st, const BatchDev& b, int nc_total, const i
   hipLaunchKernelGGL(coarse_tri_kernel, dim3(nc_total), dim3(CT_T), 0, st, b, coarse_prob, M, t, y, 1);
 }
 
-void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const double* Phi, const double* uc,
-                       double* z) {
-  hipLaunchKernelGGL(add_coarse_kernel, dim3(ns), dim3(256), sd.NCp * sizeof(double), st, sd, Phi, uc, z);
+template <typename TP>
+void launch_add_coarse(hipStream_t st, const SubDev& sd, int ns, const TP* Phi, const double* uc, double* z) {
+  hipLaunchKernelGGL(add_coarse_kernel<TP>, dim3(ns), dim3(256), sd.NCp * sizeof(double), st, sd, Phi, uc, z);
 }
+template void launch_add_coarse<double>(hipStream_t, const SubDev&, int, const double*, const double*, double*);
+template void launch_add_coarse<float>(hipStream_t, const SubDev&, int, const float*, const double*, double*);
 
 void launch_iface_average(hipStream_t st, int64_t n_iface, const int64_t* iface_node, const int64_t* if_ptr,
                           const int32_t* if_sub, const int32_t* if_slot, int NGp, const double* Dw,

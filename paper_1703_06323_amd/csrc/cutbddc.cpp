@@ -389,6 +389,7 @@ struct cb_ctx {
       cs_row;
   // factor results
   DevBuf P_, Kt, Phi, Dw, diagAG, Ds, Acinv, AcKeep, info_d;
+  DevBuf Phi32;   // FP32 copy of Phi for the products of the FP32-local path
   // coarse problem by one level of nested dissection (coarse_nd.h), chosen
   // at each cb_factor for single-problem contexts; Acinv is then unused
   struct {
@@ -569,10 +570,10 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked, bool cleare
   // (3)-(4) weighted restriction, constrained Neumann solves, coarse rhs
   timed(c, "apply_neumann", [&] {
     if (c->precision == CB_FP32_LOCAL)
-      launch_apply_neumann<float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi.as<double>(), c->Dw.as<double>(),
+      launch_apply_neumann<float, float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi32.as<float>(), c->Dw.as<double>(),
                                   r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
     else
-      launch_apply_neumann<double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
+      launch_apply_neumann<double, double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
                                    c->Dw.as<double>(), r, t2, c->zbuf.as<double>(), c->cloc.as<double>());
   });
   // (5) coarse correction
@@ -589,7 +590,10 @@ int apply_M_grid(cb_ctx* c, const double* r, double* z, bool masked, bool cleare
         launch_coarse_gemv(st, c->batch(masked), c->nc_tot, c->coarse_prob_d.as<int32_t>(), c->Acinv.as<double>(),
                            c->cvec.as<double>(), c->tcvec.as<double>(), c->ucvec.as<double>());
     });
-    launch_add_coarse(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
+    if (c->precision == CB_FP32_LOCAL)
+      launch_add_coarse<float>(st, sd, c->ns, c->Phi32.as<float>(), c->ucvec.as<double>(), c->zbuf.as<double>());
+    else
+      launch_add_coarse<double>(st, sd, c->ns, c->Phi.as<double>(), c->ucvec.as<double>(), c->zbuf.as<double>());
   }
   // (6) weighted average on the interface
   if (!cleared) launch_fill(st, nn, 0.0, z);
@@ -1813,6 +1817,13 @@ int factor_impl(cb_ctx* c) {
   if (std::is_same<T, float>::value) {
     fw.release();
     CHK(fp64_refactor(c, AcLoc.as<double>(), &c->n_fallbacks));
+    // the coarse restriction and prolongation of the FP32-local path read
+    // Phi in FP32 (both with the same rounded copy, so that the coarse
+    // correction stays symmetric); the coarse matrix is formed from Phi in FP64
+    CHK(dalloc(c->Phi32, (size_t)ns * sG * sizeof(float)));
+    convert_to_float(st, (int64_t)ns * sG, c->Phi.as<double>(), c->Phi32.as<float>());
+  } else {
+    c->Phi32.release();
   }
   launch_weights(st, c->n_iface_tot, c->if_ptr.as<int64_t>(), c->if_sub.as<int32_t>(), c->if_slot.as<int32_t>(),
                  NGp, c->diagAG.as<double>(), c->weighting == CB_W_STIFFNESS, c->Dw.as<double>());
@@ -2670,10 +2681,10 @@ int cb_time_kernel(cb_ctx* c, int32_t which, int32_t reps, double* avg_ms) {
       else launch_apply_interior<double>(st, sd, c->ns, c->P_.as<double>(), c->r.as<double>(), nullptr,
                                          c->t1.as<double>());
     } else {
-      if (f32) launch_apply_neumann<float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi.as<double>(),
+      if (f32) launch_apply_neumann<float, float>(st, sd, c->ns, c->Kt.as<float>(), c->Phi32.as<float>(),
                                            c->Dw.as<double>(), c->r.as<double>(), c->t2.as<double>(),
                                            c->zbuf.as<double>(), c->cloc.as<double>());
-      else launch_apply_neumann<double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
+      else launch_apply_neumann<double, double>(st, sd, c->ns, c->Kt.as<double>(), c->Phi.as<double>(),
                                         c->Dw.as<double>(), c->r.as<double>(), c->t2.as<double>(),
                                         c->zbuf.as<double>(), c->cloc.as<double>());
     }
