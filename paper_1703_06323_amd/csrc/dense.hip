@@ -535,17 +535,24 @@ __global__ __launch_bounds__(DF_THREADS) void diag_factor_kernel(T* A, int64_t l
 // of 16 (b <= DB): the same outputs as diag_factor_kernel (L in place with
 // the upper part of the block zeroed, X = L^{-1} into block `blk` of Linv,
 // info for a bad pivot), with far fewer workgroup barriers.  The block lives
-// in LDS as 16 x 16 tiles (lower tiles of L and of X, element (r, c) of a
-// tile at r * 16 + (c ^ r) so that reading a tile column is free of bank
-// conflicts).  For each tile column p:
+// in LDS as one array of 16 x 16 lower tiles (element (r, c) of a tile at
+// r * 16 + (c ^ r) so that reading a tile column is free of bank
+// conflicts); a tile holds A, then L, then M = X_ii L_ij, then X, so that
+// the block takes 74 KB in FP64 and two workgroups share a CU.  L leaves for
+// global memory as its tiles become final.  For each tile column p:
 //   1. wave 0 factors the diagonal tile and inverts it in registers,
 //      column by column, exchanging values with lane shuffles (no
-//      barriers);
-//   2. every wave takes one tile: a panel tile L_ip = A_ip X_pp^T (i > p) or
-//      a tile of row p of X, X_pj = -X_pp (sum_{j<=k<p} L_pk X_kj);
-//   3. the trailing tiles A_ij -= L_ip L_jp^T (p < j <= i) are shared out.
+//      barriers); L_pp goes to global memory, X_pp to the tile;
+//   2. panel phase, one tile per item: L_ip = A_ip X_pp^T (i > p; to the tile
+//      and to global memory) and M_pk = X_pp L_pk (k < p, in place: L row p
+//      has no other use left);
+//   3. wave 0 updates and factors the next diagonal tile, the others form
+//      row p of X, X_pj = -sum_{j<=k<p} M_pk X_kj, held in registers until
+//      every wave has read row p's M tiles, and share out the trailing tiles
+//      A_ij -= L_ip L_jp^T (p < j <= i).
 // Tile products run on the 16x16x4 MFMAs.
 constexpr int DK_THREADS = 512;
+constexpr int NW_DK = DK_THREADS / 64;   // waves
 constexpr int DK_TILES = (DB / 16) * (DB / 16 + 1) / 2;
 static_assert(DB == 128, "the tile-row lookup of the diagonal kernel assumes 8 x 8 tiles");
 __device__ inline int dk_tile(int I, int J) { return I * (I + 1) / 2 + J; }
@@ -609,15 +616,16 @@ template <typename T>
 __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t lda, int64_t sA, int k0, int b,
                                                                 T* Linv, int64_t sL, int blk, int* info) {
   extern __shared__ __align__(16) unsigned char dk_lds[];
-  T* Ls = reinterpret_cast<T*>(dk_lds);
-  T* Xs = Ls + DK_TILES * 256;
+  // one array of lower tiles: tile (i, j) holds A, then L once its panel
+  // step is done, then (row i's inverse step) M = X_ii L_ij, and finally X
+  T* Ts = reinterpret_cast<T*>(dk_lds);
   const int64_t bz = blockIdx.x;
   T* a = A + bz * sA + (int64_t)k0 * lda + k0;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = b >> 4;
   typedef typename Acc<T>::type AccT;
-  // load the lower tiles (upper part of diagonal tiles as zero); X = 0.
-  // Every load is issued before the first LDS write.
+  // load the lower tiles (upper part of diagonal tiles as zero).  Every
+  // load is issued before the first LDS write.
   constexpr int LD_IT = DK_TILES * 256 / DK_THREADS;
   static_assert(LD_IT * DK_THREADS == DK_TILES * 256, "load split");
   T ld[LD_IT];
@@ -633,8 +641,7 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
   for (int it = 0; it < LD_IT; ++it) {
     const int e = tid + it * DK_THREADS;
     const int q = e >> 8, rc = e & 255, r = rc >> 4, c = rc & 15;
-    Ls[q * 256 + dk_at(r, c)] = ld[it];
-    Xs[q * 256 + dk_at(r, c)] = T(0);
+    Ts[q * 256 + dk_at(r, c)] = ld[it];
   }
   __syncthreads();
   int bad = 0;   // wave 0: first failing row + 1
@@ -642,16 +649,16 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
   // holds columns g + 4t of row r of the whole symmetric tile (both
   // triangles, updated alike, so they stay exactly equal): row j of A and X
   // reaches every lane by a row broadcast from lane j of its own group, and
-  // only column j of A (one value per lane) needs a lane shuffle.
+  // only column j of A (one value per lane) needs a lane shuffle.  L_pp
+  // goes to global memory (upper triangle zero), X_pp to tile (p, p).
   auto factor_diag = [&](int p) {
-    T* Lp = Ls + dk_tile(p, p) * 256;
-    T* Xp = Xs + dk_tile(p, p) * 256;
+    T* Tp = Ts + dk_tile(p, p) * 256;
     const int r = lane & 15, g = lane >> 4;
     T av[4], xv[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = g + 4 * t;
-      av[t] = c <= r ? Lp[dk_at(r, c)] : Lp[dk_at(c, r)];
+      av[t] = c <= r ? Tp[dk_at(r, c)] : Tp[dk_at(c, r)];
       xv[t] = c == r ? T(1) : T(0);
     }
     auto step = [&](auto jc) {
@@ -704,63 +711,81 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
     step(std::integral_constant<int, 13>{});
     step(std::integral_constant<int, 14>{});
     step(std::integral_constant<int, 15>{});
+    // every lane has read the tile (before the first step): it now takes X_pp
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = g + 4 * t;
-      Lp[dk_at(r, c)] = c <= r ? av[t] : T(0);
-      Xp[dk_at(r, c)] = xv[t];
+      a[(int64_t)(16 * p + r) * lda + 16 * p + c] = c <= r ? av[t] : T(0);
+      Tp[dk_at(r, c)] = xv[t];
+    }
+  };
+  // the tile of an MFMA accumulator (lane layout of Acc) to tile slot S and,
+  // if g is given, to global memory at g (leading dimension lda)
+  auto put_tile = [&](const AccT& acc, T* S, T* gm, T sign) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = Acc<T>::row(lane, v), c = lane & 15;
+      const T x = sign * acc[v];
+      S[dk_at(r, c)] = x;
+      if (gm) gm[(int64_t)r * lda + c] = x;
     }
   };
   // A_ij -= L_ip L_jp^T by the calling wave
   auto trail = [&](int p, int i, int j) {
     AccT acc = {0, 0, 0, 0};
-    dk_mma<T>(acc, Ls + dk_tile(i, p) * 256, Ls + dk_tile(j, p) * 256, 1, lane);
-    T* Aij = Ls + dk_tile(i, j) * 256;
+    dk_mma<T>(acc, Ts + dk_tile(i, p) * 256, Ts + dk_tile(j, p) * 256, 1, lane);
+    T* Aij = Ts + dk_tile(i, j) * 256;
 #pragma unroll
     for (int v = 0; v < 4; ++v) Aij[dk_at(Acc<T>::row(lane, v), lane & 15)] -= acc[v];
   };
-  // tile X_pj (j < p) of row p of X = L^{-1}: -X_pp sum_{j<=k<p} L_pk X_kj,
-  // by the calling wave
+  // X_pj (j < p) of row p of X = L^{-1}: -sum_{j<=k<p} M_pk X_kj with
+  // M_pk = X_pp L_pk (tiles (p, k) hold M by then), into registers
   auto xrow_tile = [&](int p, int j) {
     AccT acc = {0, 0, 0, 0};
-    T* Xpj = Xs + dk_tile(p, j) * 256;
-    for (int k = j; k < p; ++k) dk_mma<T>(acc, Ls + dk_tile(p, k) * 256, Xs + dk_tile(k, j) * 256, 0, lane);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
-    __builtin_amdgcn_wave_barrier();
-    AccT acc2 = {0, 0, 0, 0};
-    dk_mma<T>(acc2, Xs + dk_tile(p, p) * 256, Xpj, 0, lane);
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Xpj[dk_at(Acc<T>::row(lane, v), lane & 15)] = -acc2[v];
+    for (int k = j; k < p; ++k) dk_mma<T>(acc, Ts + dk_tile(p, k) * 256, Ts + dk_tile(k, j) * 256, 0, lane);
+    return acc;
   };
-  constexpr int NW = DK_THREADS / 64;
+  // panel phase of step p: L_ip = A_ip X_pp^T (i > p; to the tile and to
+  // global memory) and M_pk = X_pp L_pk (k < p; in place), one tile per item
+  auto panel = [&](int p) {
+    const int nl = nt - 1 - p;
+    for (int item = wv; item < nl + p; item += NW_DK) {
+      AccT acc = {0, 0, 0, 0};
+      if (item < nl) {
+        const int i = p + 1 + item;
+        T* Tip = Ts + dk_tile(i, p) * 256;
+        dk_mma<T>(acc, Tip, Ts + dk_tile(p, p) * 256, 1, lane);
+        put_tile(acc, Tip, a + (int64_t)(16 * i) * lda + 16 * p, T(1));
+      } else {
+        const int k = item - nl;
+        T* Tpk = Ts + dk_tile(p, k) * 256;
+        dk_mma<T>(acc, Ts + dk_tile(p, p) * 256, Tpk, 0, lane);
+        put_tile(acc, Tpk, nullptr, T(1));
+      }
+    }
+  };
   if (wv == 0) factor_diag(0);
   __syncthreads();
   for (int p = 0; p < nt; ++p) {
-    // 2. panel tiles L_ip = A_ip X_pp^T (i > p), one per wave
-    for (int i = p + 1 + wv; i < nt; i += NW) {
-      AccT acc = {0, 0, 0, 0};
-      T* Lip = Ls + dk_tile(i, p) * 256;
-      dk_mma<T>(acc, Lip, Xs + dk_tile(p, p) * 256, 1, lane);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Lip[dk_at(Acc<T>::row(lane, v), lane & 15)] = acc[v];
-    }
+    panel(p);
     __syncthreads();
     if (p + 1 == nt) break;
-    // 3. wave 0: the next diagonal tile's update and factorisation
-    // (lookahead); the other waves: row p of X (its inputs are final: L row
-    // p, X rows above, X_pp), heaviest tile first, then the remaining
-    // trailing tiles
+    // wave 0: the next diagonal tile's update and factorisation
+    // (lookahead); the other waves: row p of X (inputs final: M row p, X
+    // rows above), heaviest tile first, held in registers until every wave
+    // has read row p's M tiles, then the trailing tiles
     const int m = nt - 1 - p, ntr = m * (m + 1) / 2;
+    AccT xacc = {0, 0, 0, 0};
+    int xj = -1;
     if (wv == 0) {
       trail(p, p + 1, p + 1);
       __builtin_amdgcn_wave_barrier();
       factor_diag(p + 1);
     } else {
-      for (int item = wv - 1; item < p + ntr - 1; item += NW - 1) {
+      for (int item = wv - 1; item < p + ntr - 1; item += NW_DK - 1) {
         if (item < p) {
-          xrow_tile(p, item);
+          xacc = xrow_tile(p, item);
+          xj = item;
         } else {
           const int q = item - p + 1;
           int ii = 0;
@@ -771,13 +796,25 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
       }
     }
     __syncthreads();
+    if (xj >= 0) put_tile(xacc, Ts + dk_tile(p, xj) * 256, nullptr, T(-1));
+    // the next panel phase reads neither row p nor the tiles written here
   }
-  // row nt - 1 of X
-  for (int j = wv; j < nt - 1; j += NW) xrow_tile(nt - 1, j);
-  __syncthreads();
-  // write L (upper part of the block zero) and X (zero above the diagonal
-  // and outside the b x b block), VW consecutive columns per thread (b and
-  // the tile edges are multiples of 16, so a group never straddles them)
+  // row nt - 1 of X (its M tiles were formed by the last panel phase)
+  {
+    AccT xacc = {0, 0, 0, 0};
+    int xj = -1;
+    for (int j = wv; j < nt - 1; j += NW_DK) {
+      xacc = xrow_tile(nt - 1, j);
+      xj = j;
+    }
+    __syncthreads();
+    if (xj >= 0) put_tile(xacc, Ts + dk_tile(nt - 1, xj) * 256, nullptr, T(-1));
+    __syncthreads();
+  }
+  // write X (zero above the diagonal and outside the b x b block) and the
+  // zero upper tiles of the L block (its lower tiles left on the way), VW
+  // consecutive columns per thread (b and the tile edges are multiples of
+  // 16, so a group never straddles them)
   typedef typename Vec16<T>::type V;
   constexpr int VW = 16 / sizeof(T);
   T* li = Linv + bz * sL + (int64_t)blk * DB * DB;
@@ -787,14 +824,12 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
     const int row = e / (DB / VW), col = (e - row * (DB / VW)) * VW;
     const int I = row >> 4, J = col >> 4, r = row & 15;
     const bool tile = row < b && col < b && J <= I;
-    V xo, lo;
+    V xo;
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       const int c = (col + k) & 15;
       const bool in = tile && col + k <= row;
-      const int at = tile ? dk_tile(I, J) * 256 + dk_at(r, c) : 0;
-      xo[k] = in ? Xs[at] : T(0);
-      lo[k] = in ? Ls[at] : T(0);
+      xo[k] = in ? Ts[dk_tile(I, J) * 256 + dk_at(r, c)] : T(0);
     }
     if (vecl) {
       *reinterpret_cast<V*>(li + e * VW) = xo;
@@ -802,13 +837,13 @@ __global__ __launch_bounds__(DK_THREADS) void diag_block_kernel(T* A, int64_t ld
 #pragma unroll
       for (int k = 0; k < VW; ++k) li[e * VW + k] = xo[k];
     }
-    if (row < b && col < b) {
+    if (row < b && col < b && J > I) {
       T* dst = a + (int64_t)row * lda + col;
       if (vec) {
-        *reinterpret_cast<V*>(dst) = lo;
+        *reinterpret_cast<V*>(dst) = V{};
       } else {
 #pragma unroll
-        for (int k = 0; k < VW; ++k) dst[k] = lo[k];
+        for (int k = 0; k < VW; ++k) dst[k] = T(0);
       }
     }
   }
@@ -1215,9 +1250,9 @@ void diag_step(hipStream_t st, T* A, int64_t lda, int64_t sA, int K0, int b, T* 
   if (b % 16 == 0 && diag_blocked_enabled()) {
     static const bool attr =
         hipFuncSetAttribute((const void*)diag_block_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(2 * DK_TILES * 256 * sizeof(T))) == hipSuccess;
+                            (int)(DK_TILES * 256 * sizeof(T))) == hipSuccess;
     (void)attr;
-    hipLaunchKernelGGL(diag_block_kernel<T>, dim3(batch), dim3(DK_THREADS), 2 * DK_TILES * 256 * sizeof(T), st, A,
+    hipLaunchKernelGGL(diag_block_kernel<T>, dim3(batch), dim3(DK_THREADS), DK_TILES * 256 * sizeof(T), st, A,
                        lda, sA, K0, b, Linv, sL, blk, info);
   } else {
     hipLaunchKernelGGL(diag_factor_kernel<T>, dim3(batch), dim3(DF_THREADS), 0, st, A, lda, sA, K0, b, Linv, sL, blk,
