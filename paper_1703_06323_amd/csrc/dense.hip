@@ -284,7 +284,12 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   };
 
   const int ks = 4 * (lane >> 4);
+  // a wave whose 32 x 32 outputs all lie above the diagonal of a
+  // lower-triangle product has nothing to store: it only helps stage the
+  // operands and keeps the barriers
+  const bool idle = (mode & GEMM_LOWER) && col0 + wc * WN > row0 + wr * WM + WM - 1;
   auto compute = [&](int buf) {
+    if (idle) return;
 #pragma unroll
     for (int kb = 0; kb < KT; kb += 16) {
       T av[FM][4], bv[FN][4];
