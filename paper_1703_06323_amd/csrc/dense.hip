@@ -1332,12 +1332,13 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
   const int blk = diag_block_index(off + S0, split);
   const T* li = Linv + (int64_t)blk * DB * DB;
   // Y[S, 0:S0] = inv(L_SS) R_S[:, 0:S0] (in place: a single tile row reads
-  // only its own columns of R_S before writing them).  R_S[:, S] is still the
-  // identity, so Y[S, S] = inv(L_SS) is a copy (the product would give the
-  // same values exactly).
+  // only its own columns of R_S before writing them; inv(L_SS) is lower
+  // triangular, so a row tile's k loop ends at its last row).  R_S[:, S] is
+  // still the identity, so Y[S, S] = inv(L_SS) is a copy (the product would
+  // give the same values exactly).
   if (S0 > 0)
     gemm<T>(st, 0, 0, h, S0, h, T(1), li, DB, sLi, Y + (int64_t)S0 * ldy, ldy, sY, T(0), Y + (int64_t)S0 * ldy, ldy,
-            sY, batch, 0, rs.at(off + S0, off, off + S0));
+            sY, batch, GEMM_KTO_DIAG, rs.at(off + S0, off, off + S0));
   {
     T* yb = Y + (int64_t)S0 * ldy + S0;
     const int vec = vec16_ok<T>(li, DB, sLi, h) && vec16_ok<T>(yb, ldy, sY, h);
