@@ -137,11 +137,14 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   int kbeg = 0, kend = K;
   if (mode & GEMM_KFROM_DIAG) kbeg = (max(row0, col0) / KT) * KT;
   if (mode & GEMM_KTO_DIAG) kend = min(K, row0 + BM);
+  // padded batch (GemmRows): the nonzero index set of matrix bz is
+  // [0, na) u [sp, sp + nb)
+  int na = 0, nb = 0;
+  const int sp = rows.split;
+  auto meets = [&](int lo, int hi) { return (lo < na && hi > 0) || (nb > 0 && lo < sp + nb && hi > sp); };
   if (rows.na) {
-    // padded batch (GemmRows): the nonzero index set of matrix bz is
-    // [0, na) u [sp, sp + nb)
-    const int na = rows.na[bz], nb = rows.nb ? rows.nb[bz] : 0, sp = rows.split;
-    auto meets = [&](int lo, int hi) { return (lo < na && hi > 0) || (nb > 0 && lo < sp + nb && hi > sp); };
+    na = rows.na[bz];
+    nb = rows.nb ? rows.nb[bz] : 0;
     const int g0 = kbeg + rows.k_off, g1 = kend + rows.k_off;
     int lo = g1, hi = g0;   // hull of the set within [g0, g1)
     if (g0 < na && g1 > 0) {
@@ -287,7 +290,11 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32)) void gemm_kernel(int M,
   // a wave whose 32 x 32 outputs all lie above the diagonal of a
   // lower-triangle product has nothing to store: it only helps stage the
   // operands and keeps the barriers
-  const bool idle = (mode & GEMM_LOWER) && col0 + wc * WN > row0 + wr * WM + WM - 1;
+  // (likewise a wave whose rows or columns are padding only: its products
+  // are exact zeros, and its outputs become beta C)
+  const bool idle = ((mode & GEMM_LOWER) && col0 + wc * WN > row0 + wr * WM + WM - 1) ||
+                    (rows.na && !(meets(rows.r_off + row0 + wr * WM, rows.r_off + row0 + wr * WM + WM) &&
+                                  meets(rows.c_off + col0 + wc * WN, rows.c_off + col0 + wc * WN + WN)));
   auto compute = [&](int buf) {
     if (idle) return;
 #pragma unroll
