@@ -51,9 +51,10 @@ void launch_assemble_local(hipStream_t st, const SubDev& sd, const GridDev& g, i
 void launch_weights(hipStream_t st, int64_t n_iface, const int64_t* if_ptr, const int32_t* if_sub,
                     const int32_t* if_slot, int NGp, const double* diagA_G, int stiffness, double* Dw);
 // Rows [r0, r0 + nrows) of Y = A_omega X (FP64, nt x NCp blocks), from the
-// stencil rows written by launch_assemble_local.
+// stencil rows written by launch_assemble_local.  The caller states that
+// rows [0, xfrom) of X are zero: their terms are not loaded.
 void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* st_val, const int32_t* st_col,
-                        const double* X, double* Y, int r0, int nrows);
+                        const double* X, double* Y, int r0, int nrows, int xfrom = 0);
 // Gt = (K_S^{-1} C^T)^T (NCp x NGp) and S_c = C G with C the object-mean
 // constraints.
 void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt);

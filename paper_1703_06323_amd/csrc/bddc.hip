@@ -252,10 +252,11 @@ __global__ void weights_kernel(int64_t n_iface, const int64_t* __restrict__ if_p
 // per (LA_ROWS-row chunk, subdomain): the chunk's stencil rows go to LDS,
 // then all threads stream X along its rows (entries summed in slot order).
 constexpr int LA_ROWS = 64;
+template <bool SKIP>
 __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, const double* __restrict__ st_val,
                                                           const int32_t* __restrict__ st_col,
                                                           const double* __restrict__ X, double* __restrict__ Y,
-                                                          int r0, int nrows) {
+                                                          int r0, int nrows, int xfrom) {
   __shared__ double sval[LA_ROWS * STENCIL];
   __shared__ int scol[LA_ROWS * STENCIL];
   const int w = blockIdx.y;
@@ -281,10 +282,14 @@ __global__ __launch_bounds__(256) void local_apply_kernel(SubDev sd, const doubl
       continue;
     }
     // An empty slot holds the value 0 (and column -1): its load goes to
-    // column 0 and adds 0, so all 27 loads issue together, unconditionally.
+    // column 0 and adds 0, so all 27 loads issue together.  Columns below
+    // xfrom hold zeros in X: those lanes skip the load and add 0 as well.
     double xv[STENCIL];
 #pragma unroll
-    for (int k = 0; k < STENCIL; ++k) xv[k] = x[(int64_t)max(scol[rr * STENCIL + k], 0) * NCp + t];
+    for (int k = 0; k < STENCIL; ++k) {
+      const int c = max(scol[rr * STENCIL + k], 0);
+      xv[k] = (!SKIP || c >= xfrom) ? x[(int64_t)c * NCp + t] : 0.0;
+    }
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < STENCIL; ++k) acc += sval[rr * STENCIL + k] * xv[k];
@@ -349,8 +354,10 @@ __global__ __launch_bounds__(256) void object_lists_kernel(SubDev sd, int32_t* _
 // Kernel 3c: Gt = (K_S^{-1} C^T)^T without forming C: since K_S^{-1} is
 // symmetric, row t of Gt is the mean of the rows of K_S^{-1} over the slots
 // of object t, so every row of K_S^{-1} is read once and coalesced.  One
-// block per (CC_COLS-column chunk, subdomain); Gt is NCp x NGp.
-constexpr int CC_COLS = 256;
+// block per (CC_COLS-column chunk, subdomain): lane l of wave v owns column
+// chunk + l and the objects t = v, v + 4, ...; four partial sums keep four
+// row loads in flight per wave.  Gt is NCp x NGp.
+constexpr int CC_COLS = 64;
 __device__ inline int packed_offset(int r, int c, int vw);
 __global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const double* __restrict__ KS,
                                                               double* __restrict__ Gt) {
@@ -362,13 +369,20 @@ __global__ __launch_bounds__(256) void constraint_cols_kernel(SubDev sd, const d
   object_members_get(sd, w, ptr, mem);
   const double* ks = KS + (int64_t)w * NGp * NGp;
   double* gt = Gt + (int64_t)w * NCp * NGp;
-  const int i = blockIdx.x * CC_COLS + threadIdx.x;
+  const int i = blockIdx.x * CC_COLS + (threadIdx.x & 63);
   if (i >= NGp) return;
-  for (int t = 0; t < NCp; ++t) {
+  for (int t = threadIdx.x >> 6; t < NCp; t += 4) {
     const int b = ptr[t], en = ptr[t + 1];
-    double acc = 0.0;
-    for (int q = b; q < en; ++q) acc += ks[(int64_t)mem[q] * NGp + i];
-    gt[(int64_t)t * NGp + i] = en > b ? acc / (double)(en - b) : 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = b;
+    for (; q + 4 <= en; q += 4) {
+      a0 += ks[(int64_t)mem[q] * NGp + i];
+      a1 += ks[(int64_t)mem[q + 1] * NGp + i];
+      a2 += ks[(int64_t)mem[q + 2] * NGp + i];
+      a3 += ks[(int64_t)mem[q + 3] * NGp + i];
+    }
+    for (; q < en; ++q) a0 += ks[(int64_t)mem[q] * NGp + i];
+    gt[(int64_t)t * NGp + i] = en > b ? ((a0 + a1) + (a2 + a3)) / (double)(en - b) : 0.0;
   }
 }
 
@@ -390,6 +404,36 @@ __global__ __launch_bounds__(256) void constraint_rows_kernel(SubDev sd, const d
     double acc = 0.0;
     for (int q = b; q < en; ++q) acc += gt[(int64_t)u * NGp + mem[q]];
     sc[e] = en > b ? acc / (double)(en - b) : 0.0;
+  }
+}
+
+// The same with one row u of Gt per wave, staged in LDS by coalesced loads;
+// lane t then averages the staged row over the slots of object t (the same
+// terms in the same order as above).  Block (CR_W waves) rows blockIdx.x *
+// CR_W + wave; LDS: the member lists, then one row buffer per wave.
+__global__ __launch_bounds__(256) void constraint_rows_staged_kernel(SubDev sd, const double* __restrict__ Gt,
+                                                                     double* __restrict__ Sc) {
+  extern __shared__ int smem_i[];
+  const int w = blockIdx.y;
+  const int NGp = sd.NGp, NCp = sd.NCp;
+  int* ptr = smem_i;
+  int* mem = smem_i + NCp + 1;
+  double* buf = reinterpret_cast<double*>(smem_i + ((NCp + 1 + NGp + 1) & ~1));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int u = blockIdx.x * (blockDim.x >> 6) + wave;
+  double* row = buf + (int64_t)wave * NGp;
+  if (u < NCp) {
+    const double* gt = Gt + ((int64_t)w * NCp + u) * NGp;
+    for (int j = lane; j < NGp; j += 64) row[j] = gt[j];
+  }
+  object_members_get(sd, w, ptr, mem);   // ends with a barrier
+  if (u >= NCp) return;
+  double* sc = Sc + (int64_t)w * NCp * NCp;
+  for (int t = lane; t < NCp; t += 64) {
+    const int b = ptr[t], en = ptr[t + 1];
+    double acc = 0.0;
+    for (int q = b; q < en; ++q) acc += row[mem[q]];
+    sc[(int64_t)t * NCp + u] = en > b ? acc / (double)(en - b) : 0.0;
   }
 }
 
@@ -1029,10 +1073,13 @@ void launch_object_lists(hipStream_t st, const SubDev& sd, int ns, int32_t* optr
 }
 
 void launch_local_apply(hipStream_t st, const SubDev& sd, int ns, const double* st_val, const int32_t* st_col,
-                        const double* X, double* Y, int r0, int nrows) {
+                        const double* X, double* Y, int r0, int nrows, int xfrom) {
   if (nrows <= 0 || ns <= 0) return;
   dim3 grid((nrows + LA_ROWS - 1) / LA_ROWS, ns);
-  hipLaunchKernelGGL(local_apply_kernel, grid, dim3(256), 0, st, sd, st_val, st_col, X, Y, r0, nrows);
+  if (xfrom > 0)
+    hipLaunchKernelGGL(local_apply_kernel<true>, grid, dim3(256), 0, st, sd, st_val, st_col, X, Y, r0, nrows, xfrom);
+  else
+    hipLaunchKernelGGL(local_apply_kernel<false>, grid, dim3(256), 0, st, sd, st_val, st_col, X, Y, r0, nrows, 0);
 }
 
 void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const double* KS, double* Gt) {
@@ -1044,6 +1091,15 @@ void launch_constraint_cols(hipStream_t st, const SubDev& sd, int ns, const doub
 
 void launch_constraint_rows(hipStream_t st, const SubDev& sd, int ns, const double* Gt, double* Sc) {
   if (ns <= 0) return;
+  // staged form while the member lists and four row buffers fit in 64 KB
+  const size_t ints = (size_t)((sd.NCp + 1 + sd.NGp + 1) & ~1) * sizeof(int);
+  const size_t rowb = (size_t)sd.NGp * sizeof(double);
+  constexpr int CR_W = 4;
+  if (ints + CR_W * rowb <= 65536) {
+    hipLaunchKernelGGL(constraint_rows_staged_kernel, dim3((sd.NCp + CR_W - 1) / CR_W, ns), dim3(64 * CR_W),
+                       ints + CR_W * rowb, st, sd, Gt, Sc);
+    return;
+  }
   hipLaunchKernelGGL(constraint_rows_kernel, dim3(ns), dim3(256), (size_t)(sd.NCp + 1 + sd.NGp) * sizeof(int), st,
                      sd, Gt, Sc);
 }

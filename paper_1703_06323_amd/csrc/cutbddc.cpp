@@ -424,6 +424,7 @@ struct cb_ctx {
   // second and third streams for work that overlaps the coarse factorisation
   hipStream_t aux_st = nullptr, aux_st3 = nullptr;
   hipEvent_t aux_ev = nullptr, aux_ev3 = nullptr;
+  hipEvent_t fill_ev = nullptr;   // identity fills of the local inverses done
   hipEvent_t nact_ev = nullptr;   // readback of the running-problem count
   // captured PCG iteration
   hipStream_t cap_st = nullptr;
@@ -438,7 +439,7 @@ struct cb_ctx {
     for (hipStream_t s : {cap_st, aux_st, aux_st3})
       if (s && hipStreamSynchronize(s) == hipSuccess) pool_put(hp.streams, dev, s);
       else if (s) (void)hipStreamDestroy(s);
-    for (hipEvent_t e : {aux_ev, aux_ev3, nact_ev})
+    for (hipEvent_t e : {aux_ev, aux_ev3, fill_ev, nact_ev})
       if (e) pool_put(hp.sync_events, dev, e);
     if (pin) pool_put(hp.pinned, dev, std::make_pair(pin_cap, pin));
     for (auto& kv : prof_ev)
@@ -674,13 +675,6 @@ int capture_body(cb_ctx* c) {
   return CB_OK;
 }
 
-int read_active(cb_ctx* c, int32_t* n) {
-  HIPCHK(hipMemcpyAsync(c->pin_nact(), c->nact_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  *n = *c->pin_nact();
-  return CB_OK;
-}
-
 // PCG on grid vectors for all problems at once: b in c->bgrid, x in c->x.
 // Per-problem results land in the pinned staging arrays.  A problem whose
 // residual meets the tolerance stops; the others continue.  Returns the
@@ -696,17 +690,30 @@ int pcg(cb_ctx* c, double rtol, int32_t max_iter, int* sweeps) {
   launch_cg_init(st, c->P, c->params.as<double>(), S, c->active.as<int32_t>(), c->itc.as<int32_t>(),
                  c->status.as<int32_t>(), c->relres_d.as<double>(), c->nact_d.as<int32_t>());
   HIPCHK(hipGetLastError());
-  int32_t n_active = 0;
-  CHK(read_active(c, &n_active));
-  int k = 0;
-  if (n_active > 0) {
+  // The count of running problems after the initial check is read back
+  // through an event while the first preconditioner apply is queued and the
+  // iteration graph captured: with no running problem that apply is masked
+  // by the device's active flags and the loop is skipped.  Without any DOF
+  // (where some grids would be empty) the apply waits for the count.
+  if (!c->nact_ev) HIPCHK(pooled_sync_event(&c->nact_ev));
+  HIPCHK(hipMemcpyAsync(c->pin_nact(), c->nact_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(c->nact_ev, st));
+  const bool use_graph = graphs_enabled() && !c->prof;
+  auto first_apply = [&]() -> int {
     CHK(apply_M_grid(c, c->r.as<double>(), c->z.as<double>(), true));
     launch_copy(st, nn, c->z.as<double>(), c->p.as<double>());
     dot(c, c->r.as<double>(), c->z.as<double>(), 3, true);
     HIPCHK(hipGetLastError());
-    const bool use_graph = graphs_enabled() && !c->prof;
     if (use_graph) CHK(capture_body(c));
-    if (!c->nact_ev) HIPCHK(pooled_sync_event(&c->nact_ev));
+    return CB_OK;
+  };
+  const bool early = c->n_dof_tot > 0;
+  if (early) CHK(first_apply());
+  HIPCHK(hipEventSynchronize(c->nact_ev));
+  int32_t n_active = *static_cast<volatile int32_t*>(c->pin_nact());
+  int k = 0;
+  if (n_active > 0) {
+    if (!early) CHK(first_apply());
     auto issue = [&]() -> int {
       if (use_graph && c->graph) HIPCHK(hipGraphLaunch(c->graph, st));
       else CHK(pcg_body(c));
@@ -1450,6 +1457,20 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     const double* Dsw = c->Ds.as<double>() + (int64_t)w0 * nt;
     double* Phiw = c->Phi.as<double>() + (int64_t)w0 * sG;
     double* KS = KSw.as<double>();
+    // The identity right-hand sides of the two triangular inverses touch
+    // neither K nor the factor: they are written on the second stream
+    // beside the assembly and the Cholesky, which leave it idle (in line on
+    // st while profiling).  That stream first waits for st, whose previous
+    // chunk still read Y.
+    const bool overlap = !c->prof;
+    hipStream_t sti = overlap ? c->aux_st : st;
+    if (overlap) {
+      HIPCHK(hipEventRecord(c->fill_ev, st));
+      HIPCHK(hipStreamWaitEvent(sti, c->fill_ev, 0));
+    }
+    fill_identity<T>(sti, YI.as<T>(), NIp, sI2, NIp, nc);
+    fill_identity<T>(sti, Y.as<T>(), NGp, sY, NGp, nc);
+    if (overlap) HIPCHK(hipEventRecord(c->fill_ev, sti));
     launch_assemble_local<T>(st, sd, g, nc, K.as<T>(), c->diagAG.as<double>() + (int64_t)w0 * NGp,
                              c->Ds.as<double>() + (int64_t)w0 * nt, StV.as<double>(), StC.as<int32_t>());
     HIPCHK(hipGetLastError());
@@ -1470,8 +1491,6 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     // The interior and interface inverses only read the factor: the
     // interior one runs on the second stream beside the interface one
     // (in line on st while profiling, so that the group timers see it).
-    const bool overlap = !c->prof;
-    hipStream_t sti = overlap ? c->aux_st : st;
     if (overlap) {
       HIPCHK(hipEventRecord(c->aux_ev, st));
       HIPCHK(hipStreamWaitEvent(sti, c->aux_ev, 0));
@@ -1479,7 +1498,8 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     // P = A_II^{-1} = D_I (Y_I^T Y_I) D_I (zero on the padding, which no
     // later step reads)
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(sti, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, YI.as<T>(), NIp, sI2, &act);
+      tri_inverse<T>(sti, K.as<T>(), nt, sK, 0, NIp, NIp, nc, Linv.as<T>(), sL, YI.as<T>(), NIp, sI2, &act,
+                     false);
       gemm<T>(sti, 1, 0, NIp, NIp, NIp, T(1), YI.as<T>(), NIp, sI2, YI.as<T>(), NIp, sI2, T(0), PSI.as<T>(), NIp,
               sI2, nc, GEMM_LOWER | GEMM_KFROM_DIAG, act);
     });
@@ -1491,8 +1511,9 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     HIPCHK(hipGetLastError());
     // K_S^{-1} = D_G (Y_G^T Y_G) D_G, kept in FP64 for the coarse basis
     // (zero on the padding)
+    if (overlap) HIPCHK(hipStreamWaitEvent(st, c->fill_ev, 0));
     timed(c, "local_inverse", [&] {
-      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, &act);
+      tri_inverse<T>(st, K.as<T>(), nt, sK, NIp, NGp, NIp, nc, Linv.as<T>(), sL, Y.as<T>(), NGp, sY, &act, false);
       gemm<T>(st, 1, 0, NGp, NGp, NGp, T(1), Y.as<T>(), NGp, sY, Y.as<T>(), NGp, sY, T(0), PS.as<T>(), NGp, sY, nc,
               GEMM_LOWER | GEMM_KFROM_DIAG, act.at(NIp, NIp, NIp));
     });
@@ -1510,11 +1531,14 @@ int factor_chunk(cb_ctx* c, FactorWork<T>& fw, int w0, int nc, double* AcLoc) {
     // and the local coarse matrix as the FP64 Gram matrix Phi^T A_omega Phi.
     // A_omega Phi vanishes on the interior rows, so the Gram matrix is
     // Phi_G^T (A_omega Phi)_G; only the needed rows of A_omega X are formed.
-    launch_fill(st, (int64_t)nc * sF, 0.0, PhiF.as<double>());
+    // The first product reads only the interface rows of PhiF (its interior
+    // rows are zero in [0; Phi_G]); the interior rows are then written, all
+    // of them, by the GEMM that forms Phi_I.
     HIPCHK(hipMemcpy2DAsync(PhiF.as<double>() + (int64_t)NIp * NCp, sF * sizeof(double), Phiw,
                             (size_t)sG * sizeof(double), (size_t)sG * sizeof(double), nc, hipMemcpyDeviceToDevice,
                             st));
-    launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), 0, NIp);
+    launch_local_apply(st, sd, nc, StV.as<double>(), StC.as<int32_t>(), PhiF.as<double>(), V.as<double>(), 0, NIp,
+                       NIp);
     // A_II^{-1} (and P) from the second stream
     if (overlap) HIPCHK(hipStreamWaitEvent(st, c->aux_ev, 0));
     gemm<double>(st, 0, 0, NIp, NCp, NIp, -1.0, Pd, NIp, sP, V.as<double>(), NCp, sF, 0.0, PhiF.as<double>(), NCp,
@@ -1769,6 +1793,7 @@ int factor_impl(cb_ctx* c) {
   if (!c->aux_st3) HIPCHK(pooled_stream(&c->aux_st3));
   if (!c->aux_ev) HIPCHK(pooled_sync_event(&c->aux_ev));
   if (!c->aux_ev3) HIPCHK(pooled_sync_event(&c->aux_ev3));
+  if (!c->fill_ev) HIPCHK(pooled_sync_event(&c->fill_ev));
   const int n_info = ns + 1 + c->P;
   CHK(dalloc(c->info_d, (size_t)n_info * sizeof(int)));
   HIPCHK(hipMemsetAsync(c->info_d.p, 0, (size_t)n_info * sizeof(int), st));

@@ -95,10 +95,15 @@ int cholesky(hipStream_t st, T* A, int64_t lda, int64_t sA, int n, int split, in
 // (off and off+nb block starts of the same split), from the diagonal-block
 // inverses written by cholesky().  rows (optional, as for cholesky(), in
 // the index space of L): the updates skip padding tiles; Y is still the
-// identity on the padding.
+// identity on the padding.  fill = false: Y already holds the identity
+// (written by fill_identity on st, or on a stream that st waits for).
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows = nullptr);
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows = nullptr,
+                 bool fill = true);
+// Y[b] = I (nb x nb, leading dimension ldy, matrix stride sY) for b < batch.
+template <typename T>
+void fill_identity(hipStream_t st, T* Y, int64_t ldy, int64_t sY, int nb, int batch);
 
 // Streams and events lent to cholesky_inverse by the caller (default
 // priority, non-blocking).  The events are recorded and waited on at every

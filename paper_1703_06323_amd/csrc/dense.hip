@@ -1362,12 +1362,12 @@ void tri_inverse_step(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int o
 
 template <typename T>
 void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, int nb, int split, int batch,
-                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows) {
+                 const T* Linv, int64_t sLi, T* Y, int64_t ldy, int64_t sY, const GemmRows* rows, bool fill) {
   // Y = L_block^{-1} for the diagonal range [off, off+nb) of L (lower) by
   // block forward substitution on L Y = I over the factor's diagonal blocks
   // S: Y holds the running right-hand side R (initially I); Y[S, 0:send] =
   // inv(L_SS) R_S[:, 0:send], and the rows below get one rank-|S| update.
-  launch_eye<T>(st, Y, ldy, sY, nb, batch);
+  if (fill) launch_eye<T>(st, Y, ldy, sY, nb, batch);
   int S0 = 0;
   while (S0 < nb) {
     const int p = off + S0;
@@ -1377,6 +1377,11 @@ void tri_inverse(hipStream_t st, const T* L, int64_t ldl, int64_t sL, int off, i
                         rows ? *rows : GemmRows{});
     S0 += h;
   }
+}
+
+template <typename T>
+void fill_identity(hipStream_t st, T* Y, int64_t ldy, int64_t sY, int nb, int batch) {
+  launch_eye<T>(st, Y, ldy, sY, nb, batch);
 }
 
 template <typename T>
@@ -1450,7 +1455,8 @@ void symmetrize_scale(hipStream_t st, const T* in, int64_t ldi, int64_t sI, TO* 
   template int cholesky<T>(hipStream_t, T*, int64_t, int64_t, int, int, int, T*, int64_t, int*,   \
                            const AuxStreams*, const GemmRows*);                                  \
   template void tri_inverse<T>(hipStream_t, const T*, int64_t, int64_t, int, int, int, int, const T*, \
-                               int64_t, T*, int64_t, int64_t, const GemmRows*);                     \
+                               int64_t, T*, int64_t, int64_t, const GemmRows*, bool);               \
+  template void fill_identity<T>(hipStream_t, T*, int64_t, int64_t, int, int);                   \
   template int cholesky_inverse<T>(hipStream_t, const AuxStreams&, T*, int64_t, int64_t, int, int, T*,  \
                                    int64_t, int*, T*, int64_t, const int*);
 INST(double)
